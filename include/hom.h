@@ -1,0 +1,182 @@
+/*
+ * hom.h -- C ABI of libhom: guaranteed upper/lower bounds on homogenized
+ * coefficients by the FFT-based Galerkin method (Vondrejc, Zeman, Marek,
+ * "Guaranteed upper-lower bounds on homogenized properties by FFT-based
+ * Galerkin method"), hot path on AMD MI355X (gfx950).
+ *
+ * What is computed.  For a Y-periodic SPD coefficient field A (Sec. 3, eq. A)
+ * and an odd grid N (eq. N_odd), the library solves the Galerkin problems of
+ * Def. homog_problem restricted to trigonometric polynomials of degree N:
+ *   primal  min_{e in E_N} a(E + e, E + e),     a(u,v)    = (A u, v)_{L2}
+ *   dual    min_{j in J_N} a^-1(J + j, J + j),  a^-1(u,v) = (A^-1 u, v)_{L2}
+ * by conjugate gradients (Sec. 7.1), where the bilinear forms are integrated
+ * exactly by the double-grid quadrature (Lemma integral_eval_double_grid):
+ * every operator application goes to the doubled grid M = 2N - 1, applies the
+ * coefficient there (eq. MBA_GA) and comes back.  The energies of the
+ * minimisers are the guaranteed bounds of Def. upper_lower_bounds and
+ * Lemma bounds:  Bbar^-1 <= A_H <= Abar.
+ *
+ * Conventions shared by all entry points
+ *  - Every pointer documented as "device" is a HIP device pointer owned by
+ *    the caller; the library never frees caller memory.  "host" pointers are
+ *    read or written synchronously.
+ *  - All device work is ordered on the hipStream_t given at setup (passed as
+ *    void*; NULL means the default stream).  Entry points that return host
+ *    results (solves, bounds) synchronise that stream before returning.
+ *  - No exception crosses the ABI; every entry point returns hom_status.
+ *    Arguments are validated before anything is launched.
+ *  - Grid sizes N_a must be odd and M_a = 2 N_a - 1 must be of the form
+ *    3^p 5^q (the FFT radices implemented), else HOM_E_UNSUPPORTED_SIZE.
+ *
+ * Spectral layout of a solution ("field") vector.
+ *   A field x in E_N (primal) or J_N (dual) is stored by its Fourier
+ *   coefficients on the half index set k0 in [0, (N0-1)/2], k1 in Z_N1,
+ *   (k2 in Z_N2), frequencies k_a < 0 stored at index k_a + N_a; the other
+ *   half follows from x_hat(-k) = conj(x_hat(k)) (real fields).  At each k
+ *   the coefficient is expanded in an orthonormal basis T(k) of the range of
+ *   the projection G^E(k) (primal: T = xi/|xi|, xi_a = k_a/Y_a) or G^J(k)
+ *   (dual, d = 2: T = (-n_2, n_1); d = 3: t1 = normalised e_a - n_a n with a
+ *   the axis of smallest |n_a| (first on ties), t2 = n x t1), so
+ *   x_hat(k) = T(k) c(k).  The vector holds c as complex double (re, im
+ *   interleaved), m components (primal 1, dual d - 1) outermost:
+ *     index = ((c * H0 + k0) * N1 + (k1 mod N1)) [* N2 + (k2 mod N2)],
+ *   H0 = (N0 + 1)/2.  The entry k = 0 is zero.  hom_field_len() returns the
+ *   number of complex entries.
+ */
+#ifndef HOM_H
+#define HOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HOM_OK = 0,
+  HOM_NOT_CONVERGED = 1,        /* warning: maxit reached; outputs are valid, the bounds still guaranteed */
+  HOM_E_INVALID = -1,           /* bad argument (null pointer, d, tolerance, ...) */
+  HOM_E_UNSUPPORTED_SIZE = -2,  /* even N, or M = 2N-1 not of the form 3^p 5^q, or a size class not built */
+  HOM_E_NOT_SPD = -3,           /* CG met <p, C p> <= 0: the coefficient is not SPD */
+  HOM_E_DEVICE = -4,            /* a HIP call failed */
+  HOM_E_WORKSPACE = -5          /* workspace too small or misaligned */
+} hom_status;
+
+enum { HOM_FP64 = 0, HOM_MIXED = 1 };   /* hom_desc.precision */
+
+typedef struct {
+  int32_t d;          /* 2 or 3 */
+  int32_t N[3];       /* odd grid sizes per axis (N[2] ignored for d = 2) */
+  double  Y[3];       /* cell side lengths Y_a > 0 (cell = prod (-Y_a/2, Y_a/2)) */
+  int32_t precision;  /* HOM_FP64: everything FP64.  HOM_MIXED: FFTs and the coefficient
+                         apply in FP32; CG vectors, inner products, residual recurrence,
+                         right-hand side and the bound quadrature in FP64 */
+  int32_t ncoef;      /* 1: isotropic a(x) I.  d(d+1)/2: symmetric matrix, components
+                         ordered xx, yy, (zz), xy, (xz, yz) */
+} hom_desc;
+
+typedef struct {
+  int32_t iters;          /* CG iterations performed */
+  int32_t status;         /* hom_status of this load */
+  double  rel_res_recur;  /* ||r|| / ||E|| from the CG recurrence at exit */
+  double  rel_res_true;   /* ||b - C x|| / ||E|| recomputed at exit (FP64 path of the precision mode) */
+} hom_info;
+
+typedef struct {
+  double A_up[9];    /* Abar (upper bound), row-major d x d */
+  double B_up[9];    /* Bbar (dual energies) */
+  double A_low[9];   /* Bbar^{-1} (lower bound) */
+  double A_mean[9];  /* (Abar + Bbar^{-1}) / 2 */
+  double D[9];       /* (Abar - Bbar^{-1}) / 2, the guaranteed error */
+} hom_result;
+
+typedef struct hom_problem hom_problem;
+
+/* Human-readable name of a status code (static string). */
+const char* hom_status_str(int32_t status);
+
+/* Number of complex entries of one solution vector (layout above) for the
+ * primal (dual = 0) or the dual (dual = 1) problem. */
+hom_status hom_field_len(const hom_desc* desc, int32_t dual, size_t* n_complex);
+
+/* Bytes of device workspace hom_setup needs for up to max_loads simultaneous
+ * loads (1 <= max_loads <= 3).  Alignment required: 256 bytes. */
+hom_status hom_workspace_bytes(const hom_desc* desc, int32_t max_loads, size_t* bytes);
+
+/* Build a problem (Sec. 6, Lemma integral_eval_double_grid, Lemma
+ * bounds_for_matrix-inclusion).  Ahat, Bhat: device, complex double
+ * (re, im interleaved), ncoef x M0 x M1 (x M2), the Fourier coefficients of A
+ * and of A^{-1} on Z_M (M = 2N - 1), frequency n_a stored at n_a mod M_a.
+ * The library evaluates the coefficient on the doubled grid,
+ * A_M(x^k) = sum_n omega_M^{kn} A_hat(n), in FP64 on the device (plus an
+ * FP32 copy for HOM_MIXED), and keeps the Z_N part of A_hat for the
+ * right-hand side.  Ahat/Bhat may be freed after the call returns.
+ * ws: device workspace of at least hom_workspace_bytes(); it must stay
+ * allocated until hom_destroy.  stream: hipStream_t or NULL.
+ * On success *out receives a handle (host memory owned by the library). */
+hom_status hom_setup(const hom_desc* desc, int32_t max_loads, const void* Ahat, const void* Bhat,
+                     void* ws, size_t ws_bytes, void* stream, hom_problem** out);
+
+/* Primal solves (Sec. 7.1, eq. linear_system_primal with the exact form):
+ * for each of nload loads E (host, nload x d doubles) find x in E_N with
+ * G^E K x = -G^E K E by CG, K the exact Galerkin operator on the doubled
+ * grid.  x0: host array of nload device pointers (field layout) or NULL for
+ * x0 = 0; an initial guess is symmetrised on the k0 = 0 plane (real field)
+ * and is admissible by construction of the layout.  Stopping rule
+ * (Convergence-criteria remark, Sec. 7.2): ||r_i|| <= tol ||E||, r the
+ * residual in the L2 norm (Parseval).  x_out: host array of nload device
+ * pointers, each hom_field_len(primal) complex doubles; may alias x0.
+ * info: host array of nload entries.  Returns HOM_NOT_CONVERGED if any load
+ * hit maxit (its iterate is still returned), HOM_E_NOT_SPD on breakdown. */
+hom_status hom_solve_primal(hom_problem* pb, int32_t nload, const double* E, const double* const* x0,
+                            double tol, int32_t maxit, double* const* x_out, hom_info* info);
+
+/* Dual solves (eq. linear_system_dual): G^J K' j = -G^J K' J with K' the
+ * exact Galerkin operator of the series of A^{-1}; arguments as above,
+ * fields in the dual layout. */
+hom_status hom_solve_dual(hom_problem* pb, int32_t nload, const double* J, const double* const* x0,
+                          double tol, int32_t maxit, double* const* x_out, hom_info* info);
+
+/* Guaranteed bounds (Def. upper_lower_bounds, eq. approx_homog_with_error):
+ * Abar_ab = a(e_b + x^(b), e_a + x^(a)), Bbar_ab = a^-1(e_b + j^(b), e_a + j^(a)),
+ * each by the FP64 double-grid quadrature; A_low = Bbar^-1, A_mean, D.
+ * primal, dual: host arrays of d device pointers to fields for the unit loads
+ * e_1..e_d (any admissible fields give guaranteed bounds).  Either array may
+ * be NULL, in which case the corresponding outputs are NaN. */
+hom_status hom_bounds(hom_problem* pb, const double* const* primal, const double* const* dual,
+                      hom_result* out);
+
+/* Apply the Galerkin operator once: y = T^T G K (T x) (primal, dual = 0) or
+ * the dual analogue, in the precision mode of the problem.  x, y: device
+ * field vectors.  Used to check the operator against a reference. */
+hom_status hom_apply(hom_problem* pb, int32_t dual, const double* x, double* y);
+
+/* Device-side Fourier coefficients of a matrix-inclusion medium (eq.
+ * A_with_inclusions, Remark inclusion): A_hat(n) = A0 delta_n0 +
+ * sum_j (A_j - A0) f_hat_j(n) phi_{-n}(x_j) on Z_M, written in the Ahat layout of
+ * hom_setup (ncoef components).  inverse = 1 gives the series of A^{-1}
+ * (valid for non-overlapping inclusions: A0^{-1} and A_j^{-1} - A0^{-1}).
+ * Host inputs: A0 (d x d), n_incl inclusions with kind[j] (0 box, 1 ball (d = 3)),
+ * center[j*d + a], size[j*d + a] (box sides; ball radius in size[j*d]),
+ * A_in[j*d*d ...] (coefficient inside, d x d row-major).  out: device. */
+hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
+                               const double* center, const double* size, const double* A_in,
+                               int32_t inverse, void* out, void* stream);
+
+/* Device-side Fourier coefficients of a pixel/voxel image (Remark inclusion
+ * summed over pixels): pixel i_a along axis a covers
+ * [-Y_a/2 + i_a Y_a/P_a, -Y_a/2 + (i_a+1) Y_a/P_a); P_a must be of the form 3^p 5^q.
+ * phase: host int32 array (P0 x P1 (x P2), row-major) of phase ids;
+ * phase_A: host nphase x d x d.  inverse = 1 uses the inverse phase matrices.
+ * out: device, Ahat layout of hom_setup. */
+hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t* phase, int32_t nphase,
+                           const double* phase_A, int32_t inverse, void* out, void* stream);
+
+/* Release the handle (host memory only; the workspace stays with the caller). */
+void hom_destroy(hom_problem* pb);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HOM_H */

@@ -1,0 +1,11 @@
+"""MI355X (gfx950) implementation of the FFT-based Galerkin method with
+guaranteed upper-lower bounds on homogenized coefficients.
+
+The compute path is the HIP library libhom.so (include/hom.h); this package
+only marshals arguments and provides PyTorch-owned device memory and streams.
+"""
+from .api import (Problem, coef_inclusions, coef_pixels, coef_from_cell, problem_from_cell, field_len,
+                  workspace_bytes, spectrum_from_field, field_from_spectrum, HomError)
+
+__all__ = ["Problem", "coef_inclusions", "coef_pixels", "coef_from_cell", "problem_from_cell", "field_len",
+           "workspace_bytes", "spectrum_from_field", "field_from_spectrum", "HomError"]

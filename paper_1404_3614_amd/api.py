@@ -1,0 +1,267 @@
+"""Python binding of libhom: device memory and streams from PyTorch, every
+computation in the HIP library.  Names follow the C ABI (include/hom.h)."""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+__all__ = ["Problem", "coef_inclusions", "coef_pixels", "coef_from_cell", "problem_from_cell",
+           "field_len", "workspace_bytes", "spectrum_from_field", "HomError"]
+
+HomError = L.HomError
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        raise RuntimeError("libhom needs a ROCm GPU (torch.cuda.is_available() is False)")
+    return torch.device("cuda", torch.cuda.current_device())
+
+
+def _desc(d, N, Y, precision, ncoef):
+    ds = L.Desc()
+    ds.d = d
+    for a in range(3):
+        ds.N[a] = int(N[a]) if a < d else 1
+        ds.Y[a] = float(Y[a]) if a < d else 1.0
+    ds.precision = {"fp64": L.HOM_FP64, "mixed": L.HOM_MIXED}.get(precision, precision)
+    ds.ncoef = ncoef
+    return ds
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptrs(tensors):
+    arr = (C.c_void_p * len(tensors))()
+    for i, t in enumerate(tensors):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def field_len(d, N, dual, Y=(1, 1, 1)):
+    n = C.c_size_t()
+    ds = _desc(d, N, Y, "fp64", 1)
+    L.check(L.load().hom_field_len(C.byref(ds), int(dual), C.byref(n)), "hom_field_len")
+    return n.value
+
+
+def workspace_bytes(d, N, Y, precision, ncoef, max_loads):
+    n = C.c_size_t()
+    ds = _desc(d, N, Y, precision, ncoef)
+    L.check(L.load().hom_workspace_bytes(C.byref(ds), int(max_loads), C.byref(n)), "hom_workspace_bytes")
+    return n.value
+
+
+def _is_iso(A):
+    A = np.asarray(A, float)
+    return np.allclose(A, A[0, 0] * np.eye(A.shape[0]), rtol=0, atol=0)
+
+
+def cell_ncoef(cell):
+    """1 when every phase is a multiple of I, else d(d+1)/2."""
+    d = cell.d
+    mats = list(cell.phase_A) if hasattr(cell, "phase") else [cell.A0] + list(cell.A)
+    return 1 if all(_is_iso(A) for A in mats) else d * (d + 1) // 2
+
+
+def coef_inclusions(cell, N, ncoef, inverse=False, stream=None):
+    """Fourier coefficients on Z_{2N-1} of a matrix-inclusion cell, on the device."""
+    d = cell.d
+    ds = _desc(d, N, cell.Y, "fp64", ncoef)
+    M = [2 * n - 1 for n in N[:d]]
+    out = torch.empty((ncoef,) + tuple(M), dtype=torch.complex128, device=_dev())
+    n = cell.n
+    kind = (C.c_int32 * max(n, 1))(*[0 if k == "rect" else 1 for k in cell.kind])
+    cen = np.ascontiguousarray(np.array(cell.center, float).reshape(-1) if n else np.zeros(1))
+    siz = np.zeros((max(n, 1), d))
+    for j, (k, s) in enumerate(zip(cell.kind, cell.size)):
+        siz[j, :len(s)] = s
+    Ain = np.ascontiguousarray(np.array(cell.A, float).reshape(-1) if n else np.zeros(1))
+    A0 = np.ascontiguousarray(np.asarray(cell.A0, float).reshape(-1))
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    siz = np.ascontiguousarray(siz.reshape(-1))
+    st = L.load().hom_coef_inclusions(C.byref(ds), dp(A0), n, kind, dp(cen), dp(siz), dp(Ain), int(inverse),
+                                      C.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    L.check(st, "hom_coef_inclusions")
+    return out
+
+
+def coef_pixels(cell, N, ncoef, inverse=False, stream=None):
+    """Fourier coefficients on Z_{2N-1} of a pixel/voxel image, on the device."""
+    d = cell.d
+    ds = _desc(d, N, cell.Y, "fp64", ncoef)
+    M = [2 * n - 1 for n in N[:d]]
+    out = torch.empty((ncoef,) + tuple(M), dtype=torch.complex128, device=_dev())
+    P = (C.c_int32 * 3)(*(list(cell.phase.shape) + [1] * (3 - d)))
+    ph = np.ascontiguousarray(cell.phase.astype(np.int32).reshape(-1))
+    pA = np.ascontiguousarray(np.asarray(cell.phase_A, float).reshape(-1))
+    st = L.load().hom_coef_pixels(C.byref(ds), P, ph.ctypes.data_as(C.POINTER(C.c_int32)), len(cell.phase_A),
+                                  pA.ctypes.data_as(C.POINTER(C.c_double)), int(inverse),
+                                  C.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    L.check(st, "hom_coef_pixels")
+    return out
+
+
+def coef_from_cell(cell, N, ncoef=None, stream=None):
+    ncoef = cell_ncoef(cell) if ncoef is None else ncoef
+    f = coef_pixels if hasattr(cell, "phase") else coef_inclusions
+    return f(cell, N, ncoef, False, stream), f(cell, N, ncoef, True, stream), ncoef
+
+
+class Problem:
+    """One periodic cell on an odd grid N: the doubled-grid coefficients of A
+    and A^{-1} live in a workspace tensor; solves return spectral fields."""
+
+    def __init__(self, d, N, Y, Ahat, Bhat, precision="mixed", ncoef=1, max_loads=None, stream=None):
+        lib = L.load()
+        self.d = d
+        self.N = tuple(int(n) for n in N[:d])
+        self.Y = tuple(float(y) for y in Y[:d])
+        self.precision = precision
+        self.ncoef = ncoef
+        self.max_loads = d if max_loads is None else max_loads
+        # a dedicated stream (not the legacy default stream) so that the CG chunks are graph-captured
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        self.desc = _desc(d, self.N, self.Y, precision, ncoef)
+        nbytes = workspace_bytes(d, self.N, self.Y, precision, ncoef, self.max_loads)
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=_dev())
+        off = (-self.ws.data_ptr()) % 256
+        self._ws_ptr = self.ws.data_ptr() + off
+        h = C.c_void_p()
+        st = lib.hom_setup(C.byref(self.desc), self.max_loads, C.c_void_p(Ahat.data_ptr()),
+                           C.c_void_p(Bhat.data_ptr()), C.c_void_p(self._ws_ptr), nbytes,
+                           C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        L.check(st, "hom_setup")
+        self.h = h
+        self.flen = [field_len(d, self.N, 0, self.Y), field_len(d, self.N, 1, self.Y)]
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                L.load().hom_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def new_field(self, dual=False):
+        t = torch.zeros(self.flen[int(dual)], dtype=torch.complex128, device=_dev())
+        self.stream.wait_stream(torch.cuda.current_stream())
+        return t
+
+    def solve(self, dual=False, E=None, x0=None, tol=1e-6, maxit=10000, out=None, allow_not_converged=False):
+        """Solve for loads E (nload x d; default the unit loads).  Returns
+        (fields, infos) with fields a list of complex128 device tensors."""
+        d = self.d
+        E = np.eye(d) if E is None else np.atleast_2d(np.asarray(E, float))
+        n = E.shape[0]
+        fields = out if out is not None else [self.new_field(dual) for _ in range(n)]
+        infos = (L.Info * n)()
+        Ec = np.ascontiguousarray(E.reshape(-1))
+        self.stream.wait_stream(torch.cuda.current_stream())
+        x0p = _dptrs(x0) if x0 is not None else None
+        f = L.load().hom_solve_dual if dual else L.load().hom_solve_primal
+        st = f(self.h, n, Ec.ctypes.data_as(C.POINTER(C.c_double)), x0p, float(tol), int(maxit),
+               _dptrs(fields), infos)
+        L.check(st, "hom_solve_dual" if dual else "hom_solve_primal", allow_not_converged)
+        info = [dict(iters=i.iters, status=i.status, rel_res_recur=i.rel_res_recur,
+                     rel_res_true=i.rel_res_true) for i in infos]
+        return fields, info
+
+    def bounds(self, primal=None, dual=None):
+        res = L.Result()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        st = L.load().hom_bounds(self.h, _dptrs(primal) if primal is not None else None,
+                                 _dptrs(dual) if dual is not None else None, C.byref(res))
+        L.check(st, "hom_bounds")
+        d = self.d
+        g = lambda a: np.array(a[:d * d]).reshape(d, d)
+        return dict(A_up=g(res.A_up), B_up=g(res.B_up), A_low=g(res.A_low), A_mean=g(res.A_mean), D=g(res.D))
+
+    def apply(self, x, dual=False):
+        y = self.new_field(dual)
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_apply(self.h, int(dual), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())),
+                "hom_apply")
+        return y
+
+    def solve_bounds(self, tol=1e-6, maxit=10000, allow_not_converged=False):
+        xp, ip = self.solve(False, tol=tol, maxit=maxit, allow_not_converged=allow_not_converged)
+        xd, idl = self.solve(True, tol=tol, maxit=maxit, allow_not_converged=allow_not_converged)
+        b = self.bounds(xp, xd)
+        b.update(info_primal=ip, info_dual=idl, fields_primal=xp, fields_dual=xd)
+        return b
+
+
+def problem_from_cell(cell, N, precision="mixed", max_loads=None, stream=None):
+    N = tuple(int(n) for n in (N if np.iterable(N) else [N] * cell.d))
+    Ah, Bh, nc = coef_from_cell(cell, N, stream=stream)
+    pb = Problem(cell.d, N, cell.Y, Ah, Bh, precision=precision, ncoef=nc, max_loads=max_loads, stream=stream)
+    return pb
+
+
+# ---------------------------------------------------------------- layout helpers
+def _freqs(n):
+    return np.rint(np.fft.fftfreq(n, 1.0 / n)).astype(np.int64)
+
+
+def basis_np(d, N, Y, dual):
+    """T(k) of the field layout (include/hom.h) on the stored half, as an
+    array (m, d, H0, N1[, N2]); zero at k = 0."""
+    H0 = (N[0] + 1) // 2
+    axes = [np.arange(H0)] + [_freqs(n) for n in N[1:d]]
+    ks = np.meshgrid(*axes, indexing="ij")
+    xi = np.stack([k / Y[a] for a, k in enumerate(ks)])
+    nrm = np.sqrt(np.sum(xi * xi, axis=0))
+    safe = np.where(nrm == 0, 1.0, nrm)
+    n = xi / safe
+    n[:, nrm == 0] = 0.0
+    if not dual:
+        return n[None]
+    if d == 2:
+        return np.stack([np.stack([-n[1], n[0]])])
+    a = np.argmin(np.abs(n), axis=0)
+    t1 = -np.take_along_axis(n, a[None], 0) * n
+    for ax in range(3):
+        t1[ax] += (a == ax)
+    t1 /= np.where(np.linalg.norm(t1, axis=0) == 0, 1, np.linalg.norm(t1, axis=0))
+    t2 = np.cross(n, t1, axis=0)
+    T = np.stack([t1, t2])
+    T[:, :, nrm == 0] = 0.0
+    return T
+
+
+def spectrum_from_field(c, d, N, Y, dual):
+    """Full Fourier coefficients x_hat (d, *N) in FFT order from a field vector
+    in the library layout (numpy, host)."""
+    c = np.asarray(c)
+    m = 1 if not dual else d - 1
+    H0 = (N[0] + 1) // 2
+    c = c.reshape((m, H0) + tuple(N[1:d]))
+    T = basis_np(d, N, Y, dual)
+    half = np.einsum("mg...,m...->g...", T, c)
+    full = np.zeros((d,) + tuple(N), dtype=np.complex128)
+    full[:, :H0] = half
+    # k0 < 0 from x_hat(-k) = conj(x_hat(k))
+    for i0 in range(H0, N[0]):
+        src = N[0] - i0
+        sl = half[:, src]
+        idx = [np.mod(-_freqs(n), n) for n in N[1:d]]
+        full[:, i0] = np.conj(sl[(slice(None),) + np.ix_(*idx)]) if idx else np.conj(sl)
+    return full
+
+
+def field_from_spectrum(xhat, d, N, Y, dual):
+    """Library layout from full Fourier coefficients (d, *N): c = T^T x_hat on the stored half."""
+    H0 = (N[0] + 1) // 2
+    T = basis_np(d, N, Y, dual)
+    half = np.asarray(xhat)[:, :H0]
+    return np.einsum("mg...,g...->m...", T, half).reshape(-1)

@@ -1,0 +1,852 @@
+// C ABI of libhom (declared in include/hom.h): validation, workspace carving,
+// coefficient setup on the device, and the host loop that enqueues CG
+// iterations (captured into a HIP graph per chunk of iterations).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "../../include/hom.h"
+#include "hom_internal.hpp"
+
+using namespace hom;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+bool smooth35(int M, Plan* pl) {
+  int n = 0;
+  int v = M;
+  while (v % 5 == 0 && n < kMaxStages) {
+    pl->r[n++] = 5;
+    v /= 5;
+  }
+  while (v % 3 == 0 && n < kMaxStages) {
+    pl->r[n++] = 3;
+    v /= 3;
+  }
+  pl->n = n;
+  return v == 1;
+}
+
+int env_int(const char* name, int def) {
+  const char* s = std::getenv(name);
+  return s ? std::atoi(s) : def;
+}
+
+struct SlotBufs {
+  Cx<double>* r[kMaxLoads] = {};
+  Cx<double>* p[kMaxLoads] = {};
+  Cx<double>* s[kMaxLoads] = {};
+  Cx<double>* b[kMaxLoads] = {};
+  Cx<double>* tmp[kMaxLoads] = {};
+  void* bufA = nullptr;
+  void* bufB = nullptr;
+  double* part_g = nullptr;
+  double* part_d = nullptr;
+  double* part_q = nullptr;
+  CgScal* sc = nullptr;
+  UnitDev* unit = nullptr;
+  int* iter_base = nullptr;
+  int* active = nullptr;
+};
+
+// Byte sizes of everything carved from the workspace.
+struct Sizes {
+  int d, nc, L;
+  int N[3], M[3];
+  int H0, S, Q;
+  size_t Mt;
+};
+
+}  // namespace
+
+struct hom_problem {
+  hom_desc desc;
+  int max_loads;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  Sizes z;
+  Plan plan[3];
+  double* coef64[2];
+  float* coef32[2];
+  Cx<double>* ahat_half[2];
+  Cx<double>* tw64[3];
+  Cx<float>* tw32[3];
+  Cx<double>* scratch;  // setup: nc * Mt complex
+  SlotBufs slot[2];     // primal, dual
+  // bounds (FP64, L = d)
+  void* bbufA;
+  void* bbufB;
+  double* bpart_q[2];
+  UnitDev* bunit[2];
+  UnitDev host_unit[2];
+  UnitDev host_bunit[2];
+  int* pinned_active;
+  hipGraphExec_t graph[2][kMaxLoads + 1];
+  int graph_chunk;
+};
+
+namespace {
+
+bool fill_sizes(const hom_desc* desc, int max_loads, Sizes* z, Plan* plan) {
+  if (!desc) return false;
+  const int d = desc->d;
+  if (d != 2 && d != 3) return false;
+  z->d = d;
+  z->nc = desc->ncoef;
+  z->L = max_loads;
+  int Nphys[3] = {desc->N[0], desc->N[1], d == 3 ? desc->N[2] : 1};
+  if (d == 2) {
+    z->N[0] = Nphys[0];
+    z->N[1] = 1;
+    z->N[2] = Nphys[1];
+  } else {
+    for (int a = 0; a < 3; ++a) z->N[a] = Nphys[a];
+  }
+  for (int a = 0; a < 3; ++a) z->M[a] = 2 * z->N[a] - 1;
+  for (int a = 0; a < 3; ++a) {
+    if (a == 1 && d == 2) {
+      plan[a].n = 0;
+      continue;
+    }
+    if (!smooth35(z->M[a], &plan[a])) return false;
+  }
+  z->H0 = (z->N[0] + 1) / 2;
+  z->S = z->H0 * z->N[1] * z->N[2];
+  z->Q = (z->N[1] + 1) / 2 + (z->H0 - 1) * z->N[1];
+  z->Mt = (size_t)z->M[0] * z->M[1] * z->M[2];
+  return true;
+}
+
+hom_status validate_desc(const hom_desc* desc, int max_loads) {
+  if (!desc) return HOM_E_INVALID;
+  if (desc->d != 2 && desc->d != 3) return HOM_E_INVALID;
+  if (max_loads < 1 || max_loads > kMaxLoads) return HOM_E_INVALID;
+  if (desc->precision != HOM_FP64 && desc->precision != HOM_MIXED) return HOM_E_INVALID;
+  const int d = desc->d;
+  if (desc->ncoef != 1 && desc->ncoef != d * (d + 1) / 2) return HOM_E_INVALID;
+  for (int a = 0; a < d; ++a) {
+    if (!(desc->Y[a] > 0.0) || !std::isfinite(desc->Y[a])) return HOM_E_INVALID;
+    if (desc->N[a] < 3 || desc->N[a] % 2 == 0) return HOM_E_UNSUPPORTED_SIZE;
+    if (desc->N[a] > 4097) return HOM_E_UNSUPPORTED_SIZE;
+    Plan pl;
+    if (!smooth35(2 * desc->N[a] - 1, &pl)) return HOM_E_UNSUPPORTED_SIZE;
+  }
+  return HOM_OK;
+}
+
+int packs(int L, int d) { return (L * d + 1) / 2; }
+
+// Points per apply-pass block: largest count with LDS within budget and the
+// per-thread butterfly registers within 16 sets.
+int choose_tileA(int M0, int npts, int P, size_t csize, int min_radix) {
+  const size_t budget = (size_t)env_int("HOM_LDS_BUDGET", 80 * 1024);
+  int best = 1;
+  for (int t = 1; t <= 64 && t <= npts; ++t) {
+    const size_t lds = (size_t)M0 * t * P * csize;
+    const int bf = (M0 / min_radix) * t * P;
+    if (lds <= budget && (bf + kBlock - 1) / kBlock <= 16) best = t;
+  }
+  return best;
+}
+
+int choose_tileM(int M1, int inner, size_t csize, int min_radix) {
+  int best = 1;
+  for (int t = 1; t <= 256 && t <= inner; ++t) {
+    const size_t lds = (size_t)M1 * t * csize;
+    const int bf = (M1 / min_radix) * t;
+    if (lds <= 48 * 1024 && (bf + kBlock - 1) / kBlock <= 8) best = t;
+  }
+  return best;
+}
+
+int min_radix(const Plan& p) {
+  int r = 5;
+  for (int i = 0; i < p.n; ++i) r = std::min(r, p.r[i]);
+  return p.n ? r : 5;
+}
+
+// Layout of the workspace; with pb == nullptr only the total is computed.
+size_t carve(const hom_desc* desc, int max_loads, const Sizes& z, hom_problem* pb) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> size_t {
+    const size_t o = off;
+    off = up(off + bytes);
+    return o;
+  };
+  char* base = pb ? pb->ws : nullptr;
+  auto ptr = [&](size_t o) -> char* { return base ? base + o : nullptr; };
+  const int d = z.d, nc = z.nc, L = max_loads;
+  const bool mixed = desc->precision == HOM_MIXED;
+  const size_t cs = mixed ? sizeof(Cx<float>) : sizeof(Cx<double>);
+  for (int k = 0; k < 2; ++k) {
+    size_t o = take(nc * z.Mt * sizeof(double));
+    if (pb) pb->coef64[k] = (double*)ptr(o);
+    if (mixed) {
+      o = take(nc * z.Mt * sizeof(float));
+      if (pb) pb->coef32[k] = (float*)ptr(o);
+    } else if (pb) {
+      pb->coef32[k] = nullptr;
+    }
+    o = take(nc * (size_t)z.S * sizeof(Cx<double>));
+    if (pb) pb->ahat_half[k] = (Cx<double>*)ptr(o);
+  }
+  for (int a = 0; a < 3; ++a) {
+    size_t o = take(z.M[a] * sizeof(Cx<double>));
+    if (pb) pb->tw64[a] = (Cx<double>*)ptr(o);
+    o = take(z.M[a] * sizeof(Cx<float>));
+    if (pb) pb->tw32[a] = (Cx<float>*)ptr(o);
+  }
+  {
+    size_t o = take(nc * z.Mt * sizeof(Cx<double>));
+    if (pb) pb->scratch = (Cx<double>*)ptr(o);
+  }
+  const size_t npts = (size_t)z.M[1] * z.M[2];
+  for (int k = 0; k < 2; ++k) {
+    const int m = k == 0 ? 1 : d - 1;
+    const int P = packs(L, d);
+    SlotBufs sb;
+    const size_t vec = (size_t)m * z.S * sizeof(Cx<double>);
+    for (int l = 0; l < L; ++l) {
+      sb.r[l] = (Cx<double>*)ptr(take(vec));
+      sb.p[l] = (Cx<double>*)ptr(take(vec));
+      sb.s[l] = (Cx<double>*)ptr(take(vec));
+      sb.b[l] = (Cx<double>*)ptr(take(vec));
+      sb.tmp[l] = (Cx<double>*)ptr(take(vec));
+    }
+    sb.bufA = ptr(take((size_t)z.N[0] * z.N[1] * z.M[2] * P * cs));
+    if (d == 3) sb.bufB = ptr(take((size_t)z.N[0] * z.M[1] * z.M[2] * P * cs));
+    sb.part_g = (double*)ptr(take((size_t)L * z.Q * sizeof(double)));
+    sb.part_d = (double*)ptr(take((size_t)L * z.Q * sizeof(double)));
+    sb.part_q = (double*)ptr(take(npts * 9 * sizeof(double)));
+    sb.sc = (CgScal*)ptr(take(L * sizeof(CgScal)));
+    sb.unit = (UnitDev*)ptr(take(sizeof(UnitDev)));
+    sb.iter_base = (int*)ptr(take(sizeof(int)));
+    sb.active = (int*)ptr(take(sizeof(int)));
+    if (pb) pb->slot[k] = sb;
+  }
+  {
+    const int P = packs(d, d);
+    void* a = ptr(take((size_t)z.N[0] * z.N[1] * z.M[2] * P * sizeof(Cx<double>)));
+    void* b = d == 3 ? ptr(take((size_t)z.N[0] * z.M[1] * z.M[2] * P * sizeof(Cx<double>))) : nullptr;
+    double* q0 = (double*)ptr(take(npts * 9 * sizeof(double)));
+    double* q1 = (double*)ptr(take(npts * 9 * sizeof(double)));
+    UnitDev* u0 = (UnitDev*)ptr(take(sizeof(UnitDev)));
+    UnitDev* u1 = (UnitDev*)ptr(take(sizeof(UnitDev)));
+    if (pb) {
+      pb->bbufA = a;
+      pb->bbufB = b;
+      pb->bpart_q[0] = q0;
+      pb->bpart_q[1] = q1;
+      pb->bunit[0] = u0;
+      pb->bunit[1] = u1;
+    }
+  }
+  return off;
+}
+
+Geo make_geo(const hom_problem* pb, int dual, int L, bool fp32, int P_override = 0) {
+  const Sizes& z = pb->z;
+  Geo g;
+  std::memset(&g, 0, sizeof(g));
+  g.d = z.d;
+  for (int a = 0; a < 3; ++a) {
+    g.N[a] = z.N[a];
+    g.M[a] = z.M[a];
+    g.pl[a] = pb->plan[a];
+    g.tw[a] = fp32 ? (const void*)pb->tw32[a] : (const void*)pb->tw64[a];
+  }
+  g.H0 = z.H0;
+  g.S = z.S;
+  g.m = dual ? z.d - 1 : 1;
+  g.L = L;
+  g.P = P_override ? P_override : packs(L, z.d);
+  g.nc = z.nc;
+  g.dual = dual;
+  g.Q = z.Q;
+  g.nbF = z.Q;
+  g.nbL = z.Q;
+  const size_t cs = fp32 ? sizeof(Cx<float>) : sizeof(Cx<double>);
+  const int npts = z.M[1] * z.M[2];
+  g.tileA = choose_tileA(z.M[0], npts, g.P, cs, min_radix(pb->plan[0]));
+  g.nbA = (npts + g.tileA - 1) / g.tileA;
+  g.tileM = z.d == 3 ? choose_tileM(z.M[1], z.M[2] * g.P, cs, min_radix(pb->plan[1])) : 1;
+  if (z.d == 2) {
+    g.phys_axis[0] = 0;
+    g.phys_axis[1] = 2;
+    g.phys_axis[2] = 1;
+    g.iY[0] = 1.0 / pb->desc.Y[0];
+    g.iY[1] = 1.0;
+    g.iY[2] = 1.0 / pb->desc.Y[1];
+  } else {
+    for (int a = 0; a < 3; ++a) {
+      g.phys_axis[a] = a;
+      g.iY[a] = 1.0 / pb->desc.Y[a];
+    }
+  }
+  g.invM = 1.0 / (double)z.Mt;
+  return g;
+}
+
+#define HIPCHK(x)                      \
+  do {                                 \
+    if ((x) != hipSuccess) return HOM_E_DEVICE; \
+  } while (0)
+
+template <typename R>
+hipError_t enqueue_matvec_passes(const Geo& g, const UnitDev* u, int first_mode, int last_mode, int jstep,
+                                 const int* iter_base, hipStream_t st) {
+  hipError_t e = launch_first<R>(g, u, 1, first_mode, jstep, iter_base, st);
+  if (e != hipSuccess) return e;
+  if (g.d == 3) {
+    e = launch_mid<R>(g, u, 1, 1, st);
+    if (e != hipSuccess) return e;
+  }
+  e = launch_apply<R>(g, u, 1, APPLY_COEF, st);
+  if (e != hipSuccess) return e;
+  if (g.d == 3) {
+    e = launch_mid<R>(g, u, 1, 0, st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_last<R>(g, u, 1, last_mode, jstep, iter_base, st);
+}
+
+hipError_t enqueue_passes(bool fp32, const Geo& g, const UnitDev* u, int fm, int lm, int j, const int* ib,
+                          hipStream_t st) {
+  return fp32 ? enqueue_matvec_passes<float>(g, u, fm, lm, j, ib, st)
+              : enqueue_matvec_passes<double>(g, u, fm, lm, j, ib, st);
+}
+
+void fill_unit(hom_problem* pb, int k, int L, const double* E, double* const* x, UnitDev* hu) {
+  std::memset(hu, 0, sizeof(*hu));
+  SlotBufs& sb = pb->slot[k];
+  const bool mixed = pb->desc.precision == HOM_MIXED;
+  hu->coef = mixed ? (const void*)pb->coef32[k] : (const void*)pb->coef64[k];
+  hu->ahat = pb->ahat_half[k];
+  for (int l = 0; l < L; ++l) {
+    hu->x[l] = x ? reinterpret_cast<Cx<double>*>(x[l]) : sb.tmp[l];
+    hu->r[l] = sb.r[l];
+    hu->p[l] = sb.p[l];
+    hu->s[l] = sb.s[l];
+    hu->b[l] = sb.b[l];
+    for (int c = 0; c < 3; ++c) hu->E[l][c] = (E && c < pb->desc.d) ? E[l * pb->desc.d + c] : 0.0;
+  }
+  hu->bufA = sb.bufA;
+  hu->bufB = sb.bufB;
+  hu->part_g = sb.part_g;
+  hu->part_d = sb.part_d;
+  hu->part_q = sb.part_q;
+  hu->sc = sb.sc;
+}
+
+hom_status solve_impl(hom_problem* pb, int k, int nload, const double* E, const double* const* x0, double tol,
+                      int maxit, double* const* x_out, hom_info* info) {
+  if (!pb || !E || !x_out || !info) return HOM_E_INVALID;
+  if (nload < 1 || nload > pb->max_loads) return HOM_E_INVALID;
+  if (!(tol > 0.0) || maxit < 0) return HOM_E_INVALID;
+  for (int l = 0; l < nload; ++l) {
+    if (!x_out[l]) return HOM_E_INVALID;
+    double e2 = 0.0;
+    for (int c = 0; c < pb->desc.d; ++c) {
+      if (!std::isfinite(E[l * pb->desc.d + c])) return HOM_E_INVALID;
+      e2 += E[l * pb->desc.d + c] * E[l * pb->desc.d + c];
+    }
+    if (e2 == 0.0) return HOM_E_INVALID;
+  }
+  hipStream_t st = pb->stream;
+  const bool fp32 = pb->desc.precision == HOM_MIXED;
+  Geo g = make_geo(pb, k, nload, fp32);
+  SlotBufs& sb = pb->slot[k];
+  UnitDev* hu = &pb->host_unit[k];
+  fill_unit(pb, k, nload, E, x_out, hu);
+  HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+
+  bool have_x0 = false;
+  const size_t vbytes = (size_t)g.m * g.S * sizeof(Cx<double>);
+  for (int l = 0; l < nload; ++l) {
+    const double* src = x0 ? x0[l] : nullptr;
+    if (src) {
+      have_x0 = true;
+      const Cx<double>* s = reinterpret_cast<const Cx<double>*>(src);
+      if (src == x_out[l]) {
+        HIPCHK(hipMemcpyAsync(sb.tmp[l], src, vbytes, hipMemcpyDeviceToDevice, st));
+        s = sb.tmp[l];
+      }
+      HIPCHK(launch_symmetrize(g, s, reinterpret_cast<Cx<double>*>(x_out[l]), g.m, st));
+    }
+  }
+  if (have_x0) {
+    for (int l = 0; l < nload; ++l)
+      if (!x0[l]) HIPCHK(hipMemsetAsync(x_out[l], 0, vbytes, st));
+  }
+  HIPCHK(launch_init_scal(g, sb.unit, 1, sb.iter_base, tol, maxit, st));
+  HIPCHK(launch_rhs(g, sb.unit, 1, st));
+  HIPCHK(launch_start_vectors(g, sb.unit, 1, have_x0 ? 1 : 0, st));
+  if (have_x0) HIPCHK(enqueue_passes(fp32, g, sb.unit, FIRST_FIELD, LAST_RESID, 0, nullptr, st));
+
+  const int chunk = std::max(1, pb->graph_chunk);
+  const bool use_graph = st != nullptr && env_int("HOM_NO_GRAPH", 0) == 0;
+  auto enqueue_chunk = [&]() -> hipError_t {
+    for (int j = 0; j < chunk; ++j) {
+      hipError_t e = enqueue_passes(fp32, g, sb.unit, FIRST_CG, LAST_CG, j, sb.iter_base, st);
+      if (e != hipSuccess) return e;
+    }
+    hipError_t e = launch_advance(g, sb.unit, 1, sb.iter_base, chunk, sb.active, st);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(pb->pinned_active, sb.active, sizeof(int), hipMemcpyDeviceToHost, st);
+  };
+  hipGraphExec_t& gx = pb->graph[k][nload];
+  if (use_graph && !gx) {
+    hipGraph_t graph;
+    HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t e = enqueue_chunk();
+    hipError_t e2 = hipStreamEndCapture(st, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) return HOM_E_DEVICE;
+    HIPCHK(hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0));
+    HIPCHK(hipGraphDestroy(graph));
+  }
+  int done_iters = 0;
+  while (true) {
+    if (use_graph)
+      HIPCHK(hipGraphLaunch(gx, st));
+    else
+      HIPCHK(enqueue_chunk());
+    HIPCHK(hipStreamSynchronize(st));
+    done_iters += chunk;
+    if (*pb->pinned_active == 0) break;
+    if (done_iters > maxit + chunk) break;
+  }
+  // true residual b - C x of the returned iterate, in the precision mode of the solve
+  HIPCHK(enqueue_passes(fp32, g, sb.unit, FIRST_FIELD, LAST_RESID, 0, nullptr, st));
+  std::vector<double> part((size_t)nload * g.Q);
+  std::vector<CgScal> sc(nload);
+  HIPCHK(hipMemcpyAsync(part.data(), sb.part_d, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(sc.data(), sb.sc, nload * sizeof(CgScal), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  hom_status worst = HOM_OK;
+  for (int l = 0; l < nload; ++l) {
+    double s = 0.0;
+    for (int q = 0; q < g.Q; ++q) s += part[(size_t)l * g.Q + q];
+    hom_info& in = info[l];
+    in.iters = sc[l].iters;
+    in.rel_res_recur = std::sqrt(std::max(sc[l].gamma_last, 0.0)) / sc[l].normE;
+    in.rel_res_true = std::sqrt(std::max(s, 0.0)) / sc[l].normE;
+    int stt = sc[l].status;
+    hom_status h;
+    if (stt == 1) h = HOM_OK;
+    else if (stt == 2 || stt == 0) h = HOM_NOT_CONVERGED;
+    else if (stt == -3) h = HOM_E_NOT_SPD;
+    else h = HOM_E_INVALID;
+    if (stt == 0) in.iters = maxit;
+    in.status = h;
+    if (h < 0 && (worst >= 0 || h < worst)) worst = h;
+    else if (h == HOM_NOT_CONVERGED && worst == HOM_OK) worst = h;
+  }
+  return worst;
+}
+
+void inv_small(int d, const double* A, double* X) {
+  if (d == 2) {
+    const double det = A[0] * A[3] - A[1] * A[2];
+    X[0] = A[3] / det;
+    X[1] = -A[1] / det;
+    X[2] = -A[2] / det;
+    X[3] = A[0] / det;
+  } else {
+    const double a = A[0], b = A[1], c = A[2], dd = A[3], e = A[4], f = A[5], g = A[6], h = A[7], i = A[8];
+    const double C00 = e * i - f * h, C01 = -(dd * i - f * g), C02 = dd * h - e * g;
+    const double det = a * C00 + b * C01 + c * C02;
+    X[0] = C00 / det;
+    X[1] = -(b * i - c * h) / det;
+    X[2] = (b * f - c * e) / det;
+    X[3] = C01 / det;
+    X[4] = (a * i - c * g) / det;
+    X[5] = -(a * f - c * dd) / det;
+    X[6] = C02 / det;
+    X[7] = -(a * h - b * g) / det;
+    X[8] = (a * e - b * dd) / det;
+  }
+}
+
+void coef_components(int d, int nc, const double* A, double* out) {
+  if (nc == 1) {
+    out[0] = A[0];
+  } else if (d == 2) {
+    out[0] = A[0];
+    out[1] = A[3];
+    out[2] = A[1];
+  } else {
+    out[0] = A[0];
+    out[1] = A[4];
+    out[2] = A[8];
+    out[3] = A[1];
+    out[4] = A[2];
+    out[5] = A[5];
+  }
+}
+
+void twiddles(int M, std::vector<Cx<double>>& t64, std::vector<Cx<float>>& t32) {
+  t64.resize(M);
+  t32.resize(M);
+  for (int t = 0; t < M; ++t) {
+    // exp(-2 pi i t / M) from the DFT definition, evaluated in double
+    const double a = -2.0 * M_PI * (double)t / (double)M;
+    t64[t].x = std::cos(a);
+    t64[t].y = std::sin(a);
+    t32[t].x = (float)t64[t].x;
+    t32[t].y = (float)t64[t].y;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hom_status_str(int32_t s) {
+  switch (s) {
+    case HOM_OK: return "HOM_OK";
+    case HOM_NOT_CONVERGED: return "HOM_NOT_CONVERGED";
+    case HOM_E_INVALID: return "HOM_E_INVALID";
+    case HOM_E_UNSUPPORTED_SIZE: return "HOM_E_UNSUPPORTED_SIZE";
+    case HOM_E_NOT_SPD: return "HOM_E_NOT_SPD";
+    case HOM_E_DEVICE: return "HOM_E_DEVICE";
+    case HOM_E_WORKSPACE: return "HOM_E_WORKSPACE";
+    default: return "HOM_UNKNOWN";
+  }
+}
+
+hom_status hom_field_len(const hom_desc* desc, int32_t dual, size_t* n) {
+  hom_status s = validate_desc(desc, 1);
+  if (s != HOM_OK) return s;
+  if (!n) return HOM_E_INVALID;
+  Sizes z;
+  Plan pl[3];
+  fill_sizes(desc, 1, &z, pl);
+  *n = (size_t)(dual ? desc->d - 1 : 1) * z.S;
+  return HOM_OK;
+}
+
+hom_status hom_workspace_bytes(const hom_desc* desc, int32_t max_loads, size_t* bytes) {
+  hom_status s = validate_desc(desc, max_loads);
+  if (s != HOM_OK) return s;
+  if (!bytes) return HOM_E_INVALID;
+  Sizes z;
+  Plan pl[3];
+  fill_sizes(desc, max_loads, &z, pl);
+  *bytes = carve(desc, max_loads, z, nullptr);
+  return HOM_OK;
+}
+
+hom_status hom_setup(const hom_desc* desc, int32_t max_loads, const void* Ahat, const void* Bhat, void* ws,
+                     size_t ws_bytes, void* stream, hom_problem** out) {
+  hom_status s = validate_desc(desc, max_loads);
+  if (s != HOM_OK) return s;
+  if (!Ahat || !Bhat || !ws || !out) return HOM_E_INVALID;
+  if (((uintptr_t)ws) % kAlign) return HOM_E_WORKSPACE;
+  Sizes z;
+  Plan pl[3];
+  fill_sizes(desc, max_loads, &z, pl);
+  const size_t need = carve(desc, max_loads, z, nullptr);
+  if (ws_bytes < need) return HOM_E_WORKSPACE;
+  hom_problem* pb = new hom_problem();
+  std::memset((void*)pb, 0, sizeof(*pb));
+  pb->desc = *desc;
+  pb->max_loads = max_loads;
+  pb->stream = reinterpret_cast<hipStream_t>(stream);
+  pb->ws = (char*)ws;
+  pb->ws_bytes = ws_bytes;
+  pb->z = z;
+  for (int a = 0; a < 3; ++a) pb->plan[a] = pl[a];
+  pb->graph_chunk = env_int("HOM_CHUNK", 8);
+  carve(desc, max_loads, z, pb);
+  if (hipHostMalloc((void**)&pb->pinned_active, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    delete pb;
+    return HOM_E_DEVICE;
+  }
+  hipStream_t st = pb->stream;
+  std::vector<Cx<double>> t64[3];
+  std::vector<Cx<float>> t32[3];
+  hom_status rc = HOM_OK;
+  auto fail = [&](hom_status e) {
+    hipStreamSynchronize(st);
+    hipHostFree(pb->pinned_active);
+    delete pb;
+    return e;
+  };
+  for (int a = 0; a < 3; ++a) {
+    twiddles(z.M[a], t64[a], t32[a]);
+    if (hipMemcpyAsync(pb->tw64[a], t64[a].data(), z.M[a] * sizeof(Cx<double>), hipMemcpyHostToDevice, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(pb->tw32[a], t32[a].data(), z.M[a] * sizeof(Cx<float>), hipMemcpyHostToDevice, st) !=
+            hipSuccess)
+      return fail(HOM_E_DEVICE);
+  }
+  // coefficient on the doubled grid: A_M(x^k) = sum_n omega^{kn} A_hat(n) (eq. MBA_GA), FP64
+  Geo g = make_geo(pb, 0, 1, false);
+  const int nc = z.nc;
+  for (int k = 0; k < 2; ++k) {
+    const void* src = k == 0 ? Ahat : Bhat;
+    if (hipMemcpyAsync(pb->scratch, src, nc * z.Mt * sizeof(Cx<double>), hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return fail(HOM_E_DEVICE);
+    if (launch_extract_half(g, pb->scratch, pb->ahat_half[k], nc, st) != hipSuccess) return fail(HOM_E_DEVICE);
+    hipError_t e = launch_line_fft<double>(pb->scratch, nc, z.M[0], z.M[1] * z.M[2], pl[0], pb->tw64[0], 1, st);
+    if (e == hipSuccess && z.M[1] > 1)
+      e = launch_line_fft<double>(pb->scratch, nc * z.M[0], z.M[1], z.M[2], pl[1], pb->tw64[1], 1, st);
+    if (e == hipSuccess)
+      e = launch_line_fft<double>(pb->scratch, nc * z.M[0] * z.M[1], z.M[2], 1, pl[2], pb->tw64[2], 1, st);
+    if (e == hipSuccess) e = launch_coef_real(pb->scratch, pb->coef64[k], pb->coef32[k], (long)(nc * z.Mt), st);
+    if (e != hipSuccess) return fail(HOM_E_DEVICE);
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(HOM_E_DEVICE);
+  (void)rc;
+  *out = pb;
+  return HOM_OK;
+}
+
+hom_status hom_solve_primal(hom_problem* pb, int32_t nload, const double* E, const double* const* x0, double tol,
+                            int32_t maxit, double* const* x_out, hom_info* info) {
+  return solve_impl(pb, 0, nload, E, x0, tol, maxit, x_out, info);
+}
+
+hom_status hom_solve_dual(hom_problem* pb, int32_t nload, const double* J, const double* const* x0, double tol,
+                          int32_t maxit, double* const* x_out, hom_info* info) {
+  return solve_impl(pb, 1, nload, J, x0, tol, maxit, x_out, info);
+}
+
+hom_status hom_apply(hom_problem* pb, int32_t dual, const double* x, double* y) {
+  if (!pb || !x || !y || (dual != 0 && dual != 1)) return HOM_E_INVALID;
+  const int k = dual;
+  hipStream_t st = pb->stream;
+  const bool fp32 = pb->desc.precision == HOM_MIXED;
+  Geo g = make_geo(pb, k, 1, fp32);
+  SlotBufs& sb = pb->slot[k];
+  UnitDev* hu = &pb->host_unit[k];
+  fill_unit(pb, k, 1, nullptr, nullptr, hu);
+  hu->x[0] = reinterpret_cast<Cx<double>*>(const_cast<double*>(x));
+  hu->s[0] = reinterpret_cast<Cx<double>*>(y);
+  HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
+  HIPCHK(enqueue_passes(fp32, g, sb.unit, FIRST_FIELD, LAST_MATVEC, 0, nullptr, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return HOM_OK;
+}
+
+hom_status hom_bounds(hom_problem* pb, const double* const* primal, const double* const* dual, hom_result* out) {
+  if (!pb || !out) return HOM_E_INVALID;
+  const int d = pb->desc.d;
+  for (int k = 0; k < 2; ++k) {
+    const double* const* f = k == 0 ? primal : dual;
+    if (f)
+      for (int a = 0; a < d; ++a)
+        if (!f[a]) return HOM_E_INVALID;
+  }
+  hipStream_t st = pb->stream;
+  const int P = packs(d, d);
+  double Ebar[2][9];
+  bool have[2] = {primal != nullptr, dual != nullptr};
+  std::vector<double> part[2];
+  Geo g[2];
+  for (int k = 0; k < 2; ++k) {
+    if (!have[k]) continue;
+    const double* const* f = k == 0 ? primal : dual;
+    g[k] = make_geo(pb, k, d, false, P);
+    UnitDev* hu = &pb->host_bunit[k];
+    std::memset(hu, 0, sizeof(*hu));
+    hu->coef = pb->coef64[k];
+    hu->ahat = pb->ahat_half[k];
+    for (int l = 0; l < d; ++l) {
+      hu->x[l] = reinterpret_cast<Cx<double>*>(const_cast<double*>(f[l]));
+      hu->E[l][l] = 1.0;
+    }
+    hu->bufA = pb->bbufA;
+    hu->bufB = pb->bbufB;
+    hu->part_q = pb->bpart_q[k];
+    HIPCHK(hipMemcpyAsync(pb->bunit[k], hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_first<double>(g[k], pb->bunit[k], 1, FIRST_BOUNDS, 0, nullptr, st));
+    if (d == 3) HIPCHK(launch_mid<double>(g[k], pb->bunit[k], 1, 1, st));
+    HIPCHK(launch_apply<double>(g[k], pb->bunit[k], 1, APPLY_QUAD, st));
+    part[k].resize((size_t)g[k].nbA * 9);
+    HIPCHK(hipMemcpyAsync(part[k].data(), pb->bpart_q[k], part[k].size() * sizeof(double), hipMemcpyDeviceToHost,
+                          st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < 2; ++k) {
+    for (int i = 0; i < 9; ++i) Ebar[k][i] = NAN;
+    if (!have[k]) continue;
+    for (int a = 0; a < d; ++a)
+      for (int b = 0; b < d; ++b) {
+        double s = 0.0;
+        for (int q = 0; q < g[k].nbA; ++q) s += part[k][(size_t)q * 9 + a * kMaxLoads + b];
+        Ebar[k][a * d + b] = s * g[k].invM;
+      }
+  }
+  std::memset(out, 0, sizeof(*out));
+  for (int i = 0; i < 9; ++i) {
+    out->A_up[i] = out->B_up[i] = out->A_low[i] = out->A_mean[i] = out->D[i] = (i < d * d) ? NAN : 0.0;
+  }
+  for (int i = 0; i < d * d; ++i) {
+    out->A_up[i] = Ebar[0][i];
+    out->B_up[i] = Ebar[1][i];
+  }
+  if (have[1]) inv_small(d, Ebar[1], out->A_low);
+  for (int i = 0; i < d * d; ++i) {
+    out->A_mean[i] = 0.5 * (out->A_up[i] + out->A_low[i]);
+    out->D[i] = 0.5 * (out->A_up[i] - out->A_low[i]);
+  }
+  return HOM_OK;
+}
+
+hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
+                               const double* center, const double* size, const double* A_in, int32_t inverse,
+                               void* out, void* stream) {
+  hom_status s = validate_desc(desc, 1);
+  if (s != HOM_OK) return s;
+  if (!A0 || !out || n_incl < 0 || (n_incl > 0 && (!kind || !center || !size || !A_in))) return HOM_E_INVALID;
+  const int d = desc->d, nc = desc->ncoef;
+  Sizes z;
+  Plan pl[3];
+  fill_sizes(desc, 1, &z, pl);
+  double A0m[9], A0i[9];
+  std::memcpy(A0m, A0, sizeof(double) * d * d);
+  inv_small(d, A0m, A0i);
+  const double* base0 = inverse ? A0i : A0m;
+  struct InclHost {
+    int kind;
+    double c[3];
+    double h[3];
+    double A[6];
+  };
+  static_assert(sizeof(InclHost) > 0, "");
+  if (incl_dev_size() != sizeof(InclHost)) return HOM_E_INVALID;
+  std::vector<InclHost> inc(n_incl);
+  for (int j = 0; j < n_incl; ++j) {
+    InclHost& I = inc[j];
+    std::memset(&I, 0, sizeof(I));
+    I.kind = kind[j];
+    if (I.kind == 1 && d != 3) return HOM_E_INVALID;
+    if (I.kind != 0 && I.kind != 1) return HOM_E_INVALID;
+    const double* c = center + (size_t)j * d;
+    const double* h = size + (size_t)j * d;
+    if (d == 2) {
+      I.c[0] = c[0];
+      I.c[1] = 0.0;
+      I.c[2] = c[1];
+      I.h[0] = h[0];
+      I.h[1] = 1.0;
+      I.h[2] = h[1];
+    } else {
+      for (int a = 0; a < 3; ++a) {
+        I.c[a] = c[a];
+        I.h[a] = h[a];
+      }
+    }
+    double Am[9], Ai[9], Dm[9];
+    std::memcpy(Am, A_in + (size_t)j * d * d, sizeof(double) * d * d);
+    if (inverse) inv_small(d, Am, Ai);
+    for (int i = 0; i < d * d; ++i) Dm[i] = (inverse ? Ai[i] : Am[i]) - base0[i];
+    coef_components(d, nc, Dm, I.A);
+  }
+  double A0c[6];
+  coef_components(d, nc, base0, A0c);
+  double iY[3] = {1.0 / desc->Y[0], 1.0, 1.0 / desc->Y[1]};
+  if (d == 3) iY[1] = 1.0 / desc->Y[1], iY[2] = 1.0 / desc->Y[2];
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  void* dev = nullptr;
+  const size_t bytes = sizeof(InclHost) * std::max(n_incl, 1) + 64;
+  if (hipMalloc(&dev, bytes) != hipSuccess) return HOM_E_DEVICE;
+  hom_status rc = HOM_OK;
+  if (hipMemcpyAsync(dev, A0c, sizeof(A0c), hipMemcpyHostToDevice, st) != hipSuccess ||
+      (n_incl > 0 && hipMemcpyAsync((char*)dev + 64, inc.data(), sizeof(InclHost) * n_incl, hipMemcpyHostToDevice,
+                                    st) != hipSuccess) ||
+      launch_coef_incl(d, z.M, iY, nc, (const double*)dev, n_incl, (char*)dev + 64,
+                       reinterpret_cast<Cx<double>*>(out), st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    rc = HOM_E_DEVICE;
+  hipFree(dev);
+  return rc;
+}
+
+hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t* phase, int32_t nphase,
+                           const double* phase_A, int32_t inverse, void* out, void* stream) {
+  hom_status s = validate_desc(desc, 1);
+  if (s != HOM_OK) return s;
+  if (!P || !phase || nphase < 1 || !phase_A || !out) return HOM_E_INVALID;
+  const int d = desc->d, nc = desc->ncoef;
+  Sizes z;
+  Plan pl[3];
+  fill_sizes(desc, 1, &z, pl);
+  int Pint[3] = {P[0], 1, P[1]};
+  if (d == 3) Pint[1] = P[1], Pint[2] = P[2];
+  Plan pp[3];
+  for (int a = 0; a < 3; ++a) {
+    if (Pint[a] < 1) return HOM_E_INVALID;
+    if (Pint[a] == 1) {
+      pp[a].n = 0;
+      continue;
+    }
+    if (!smooth35(Pint[a], &pp[a])) return HOM_E_UNSUPPORTED_SIZE;
+  }
+  const size_t Pt = (size_t)Pint[0] * Pint[1] * Pint[2];
+  std::vector<double> comp((size_t)nphase * 6);
+  for (int q = 0; q < nphase; ++q) {
+    double Am[9], Ai[9];
+    std::memcpy(Am, phase_A + (size_t)q * d * d, sizeof(double) * d * d);
+    if (inverse) inv_small(d, Am, Ai);
+    coef_components(d, nc, inverse ? Ai : Am, &comp[(size_t)q * 6]);
+  }
+  std::vector<Cx<double>> img(nc * Pt);
+  for (size_t t = 0; t < Pt; ++t) {
+    const int q = phase[t];
+    if (q < 0 || q >= nphase) return HOM_E_INVALID;
+    for (int c = 0; c < nc; ++c) {
+      img[c * Pt + t].x = comp[(size_t)q * 6 + c];
+      img[c * Pt + t].y = 0.0;
+    }
+  }
+  std::vector<Cx<double>> tw[3];
+  std::vector<Cx<float>> tw32;
+  size_t twoff[3], off = up(nc * Pt * sizeof(Cx<double>));
+  for (int a = 0; a < 3; ++a) {
+    twiddles(Pint[a], tw[a], tw32);
+    twoff[a] = off;
+    off = up(off + Pint[a] * sizeof(Cx<double>));
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* dev = nullptr;
+  if (hipMalloc((void**)&dev, off) != hipSuccess) return HOM_E_DEVICE;
+  Cx<double>* D = reinterpret_cast<Cx<double>*>(dev);
+  hipError_t e = hipMemcpyAsync(D, img.data(), img.size() * sizeof(Cx<double>), hipMemcpyHostToDevice, st);
+  for (int a = 0; a < 3 && e == hipSuccess; ++a)
+    e = hipMemcpyAsync(dev + twoff[a], tw[a].data(), Pint[a] * sizeof(Cx<double>), hipMemcpyHostToDevice, st);
+  // unnormalised forward DFT of the image along each axis
+  if (e == hipSuccess && Pint[0] > 1)
+    e = launch_line_fft<double>(D, nc, Pint[0], Pint[1] * Pint[2], pp[0], (const Cx<double>*)(dev + twoff[0]), 0, st);
+  if (e == hipSuccess && Pint[1] > 1)
+    e = launch_line_fft<double>(D, nc * Pint[0], Pint[1], Pint[2], pp[1], (const Cx<double>*)(dev + twoff[1]), 0, st);
+  if (e == hipSuccess && Pint[2] > 1)
+    e = launch_line_fft<double>(D, nc * Pint[0] * Pint[1], Pint[2], 1, pp[2], (const Cx<double>*)(dev + twoff[2]), 0,
+                                st);
+  if (e == hipSuccess) e = launch_pixel_factor(d, z.M, Pint, nc, D, reinterpret_cast<Cx<double>*>(out), st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  hipFree(dev);
+  return e == hipSuccess ? HOM_OK : HOM_E_DEVICE;
+}
+
+void hom_destroy(hom_problem* pb) {
+  if (!pb) return;
+  for (int k = 0; k < 2; ++k)
+    for (int l = 0; l <= kMaxLoads; ++l)
+      if (pb->graph[k][l]) hipGraphExecDestroy(pb->graph[k][l]);
+  if (pb->pinned_active) hipHostFree(pb->pinned_active);
+  delete pb;
+}
+
+}  // extern "C"

@@ -1,0 +1,120 @@
+// Internal types shared by the kernels and the C ABI layer of libhom.
+//
+// Internal geometry always has three axes.  A 2D problem (N0, N1) is
+// embedded as (N0, 1, N1): the middle axis has one point, so its FFT pass is
+// skipped and every kernel is written once.  Physical axis g of the problem
+// is internal axis phys_axis[g].
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hom {
+
+constexpr int kMaxLoads = 3;      // loads solved together per coefficient field
+constexpr int kMaxPacks = 5;      // ceil(3 loads * 3 components / 2)
+constexpr int kMaxStages = 12;    // radix-3/5 stages per FFT length
+constexpr int kBlock = 256;       // threads per block of every pipeline kernel
+
+template <typename R>
+struct __align__(2 * sizeof(R)) Cx {
+  R x, y;
+};
+
+// Radix schedule of one FFT length (product of r[0..n-1]).
+struct Plan {
+  int n;
+  int r[kMaxStages];
+};
+
+// Per-load CG scalars (Chronopoulos-Gear recurrence), double-buffered by iteration parity.
+struct CgScal {
+  double gamma[2];   // <r_i, r_i>
+  double beta[2];    // gamma_i / gamma_{i-1}
+  double alpha[2];   // step length alpha_i
+  double normE;      // ||E||
+  double gamma0;     // <r_0, r_0>
+  double gamma_last; // <r, r> at exit
+  int32_t status;    // 0 active, 1 converged, 2 maxit, -3 not SPD, -1 invalid (NaN)
+  int32_t iters;     // iteration index at exit
+  double tol;
+  int32_t maxit;
+  int32_t pad_;
+};
+
+// One coefficient field with L loads: device-resident pointers.
+struct UnitDev {
+  const void* coef;                  // R-typed [nc][M0*M1*M2] on the doubled grid
+  const Cx<double>* ahat;            // [nc][S] Fourier coefficients on the stored half of Z_N
+  Cx<double>* x[kMaxLoads];
+  Cx<double>* r[kMaxLoads];
+  Cx<double>* p[kMaxLoads];
+  Cx<double>* s[kMaxLoads];
+  Cx<double>* b[kMaxLoads];
+  void* bufA;                        // [N0][N1][M2][P]
+  void* bufB;                        // [N0][M1][M2][P] (3D only)
+  double* part_g;                    // [L][nbF]
+  double* part_d;                    // [L][nbL]
+  double* part_q;                    // [nbApply][9]
+  CgScal* sc;                        // [L]
+  double E[kMaxLoads][3];            // loads (physical components)
+};
+
+// Shape information shared by every unit of a launch (passed by value).
+struct Geo {
+  int d;               // physical dimension
+  int N[3], M[3];      // internal sizes (N[1] = M[1] = 1 for d = 2)
+  int H0;              // (N0 + 1) / 2 stored k0 values
+  int S;               // H0 * N1 * N2 stored frequencies per component
+  int m;               // components of the unknown per load (1 primal, d - 1 dual)
+  int L;               // loads per unit
+  int P;               // complex packs = ceil(L * d / 2)
+  int nc;              // coefficient components
+  int dual;            // 0 primal (G^E), 1 dual (G^J)
+  int Q;               // stored row pairs handled by the first/last pass
+  int nbF, nbL, nbA;   // blocks per unit of first / last / apply pass
+  int tileA;           // points per apply-pass block
+  int tileM;           // complex elements per middle-pass block
+  int phys_axis[3];
+  double iY[3];        // 1 / Y_a (internal axes)
+  double invM;         // 1 / (M0 M1 M2)
+  Plan pl[3];
+  const void* tw[3];   // R-typed twiddles exp(-2 pi i t / M_a), t < M_a
+};
+
+enum FirstMode { FIRST_CG = 0, FIRST_FIELD = 1, FIRST_BOUNDS = 2 };
+enum LastMode { LAST_CG = 0, LAST_RESID = 1, LAST_MATVEC = 2 };
+enum ApplyMode { APPLY_COEF = 0, APPLY_QUAD = 1 };
+
+// Launch wrappers (hom_kernels.hip).  All return hipError_t of the launch.
+template <typename R>
+hipError_t launch_first(const Geo& g, const UnitDev* units, int nunits, int mode, int jstep,
+                        const int* iter_base, hipStream_t st);
+template <typename R>
+hipError_t launch_last(const Geo& g, const UnitDev* units, int nunits, int mode, int jstep,
+                       const int* iter_base, hipStream_t st);
+template <typename R>
+hipError_t launch_apply(const Geo& g, const UnitDev* units, int nunits, int mode, hipStream_t st);
+template <typename R>
+hipError_t launch_mid(const Geo& g, const UnitDev* units, int nunits, int inverse, hipStream_t st);
+
+// Generic strided complex FFT pass over [outer][L][inner] arrays, full length (setup).
+template <typename R>
+hipError_t launch_line_fft(Cx<R>* data, int outer, int Lm, int inner, const Plan& pl, const Cx<R>* tw,
+                           int inverse, hipStream_t st);
+
+hipError_t launch_rhs(const Geo& g, const UnitDev* units, int nunits, hipStream_t st);
+hipError_t launch_init_scal(const Geo& g, const UnitDev* units, int nunits, int* iter_base, double tol, int maxit,
+                            hipStream_t st);
+hipError_t launch_start_vectors(const Geo& g, const UnitDev* units, int nunits, int have_x0, hipStream_t st);
+hipError_t launch_symmetrize(const Geo& g, const Cx<double>* src, Cx<double>* dst, int m, hipStream_t st);
+hipError_t launch_advance(const Geo& g, const UnitDev* units, int nunits, int* iter_base, int step,
+                          int* active_out, hipStream_t st);
+hipError_t launch_coef_real(const Cx<double>* full, double* c64, float* c32, long n, hipStream_t st);
+hipError_t launch_extract_half(const Geo& g, const Cx<double>* full, Cx<double>* half, int nc, hipStream_t st);
+hipError_t launch_coef_incl(int d, const int* Mint, const double* iY, int nc, const double* A0c, int n_incl,
+                            const void* dev_incl, Cx<double>* out, hipStream_t st);
+hipError_t launch_pixel_factor(int d, const int* Mint, const int* Pint, int nc, const Cx<double>* dft,
+                               Cx<double>* out, hipStream_t st);
+size_t incl_dev_size();
+
+}  // namespace hom

@@ -1,0 +1,1057 @@
+// HIP kernels of libhom for gfx950 (CDNA4, wave64).
+//
+// One CG iteration of the Galerkin method without numerical integration
+// (Sec. 6-7) is a chain of line-FFT passes over the doubled grid M = 2N - 1:
+//
+//   k_first  (rows, last axis)  CG update x += a p, r -= a s; <r,r> partial;
+//                               r_hat(k) -> x_hat(k) = T(k) r(k) packed two real
+//                               fields per complex line; inverse FFT (zero-padded N -> M)
+//   k_mid    (3D, axis 1)       inverse FFT of the middle axis (N1 -> M1)
+//   k_apply  (columns, axis 0)  inverse FFT (N0 -> M0), coefficient apply
+//                               w = A_M(x) u(x) on the doubled grid (eq. MBA_GA),
+//                               forward FFT, truncation to Z_N0 (operator P_N)
+//   k_mid    (3D, axis 1)       forward FFT with truncation (M1 -> N1)
+//   k_last   (rows, last axis)  forward FFT with truncation, unpacking, projection
+//                               onto range G^E / G^J by T(k)^T, CG direction update,
+//                               <r, C r> partial
+//
+// FFTs are self-sorting (Stockham) radix-3/5 passes on lines staged in LDS,
+// in place with register staging: every stage loads its butterfly inputs into
+// registers, synchronises, then stores the outputs.  The doubled-grid field
+// never goes to HBM: only the intermediates with one pruned axis do.
+#include "hom_internal.hpp"
+
+namespace hom {
+
+// ------------------------------------------------------------------ complex
+template <typename R>
+__device__ __forceinline__ Cx<R> cx(R a, R b) {
+  Cx<R> c;
+  c.x = a;
+  c.y = b;
+  return c;
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return cx(a.x + b.x, a.y + b.y); }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return cx(a.x - b.x, a.y - b.y); }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator*(Cx<R> a, R s) { return cx(a.x * s, a.y * s); }
+template <typename R>
+__device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
+  return cx(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// i * s * a
+template <typename R>
+__device__ __forceinline__ Cx<R> imul(Cx<R> a, R s) { return cx(-a.y * s, a.x * s); }
+
+// ------------------------------------------------------------------ indices
+// FFT-order index <-> signed frequency for an odd length n.
+__device__ __forceinline__ int fr(int i, int n) { return i <= (n - 1) / 2 ? i : i - n; }
+__device__ __forceinline__ int ixn(int k, int n) { return k >= 0 ? k : k + n; }
+// Position on the length-M axis of frequency index i of a length-N axis (zero padding).
+__device__ __forceinline__ int padpos(int i, int N, int M) { return i <= (N - 1) / 2 ? i : i + (M - N); }
+// Index on the length-N axis kept by truncation of position j of a length-M axis, or -1.
+__device__ __forceinline__ int truncidx(int j, int N, int M) {
+  const int h = (N - 1) / 2;
+  if (j <= h) return j;
+  if (j >= M - h) return j - (M - N);
+  return -1;
+}
+
+// ------------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum_arr(const double* __restrict__ p, int n) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int i = lane; i < n; i += 64) s += p[i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  return __shfl(s, 0, 64);
+}
+
+// Sum over the block in a fixed order; every thread must call it.
+__device__ __forceinline__ double block_sum(double v, double* sred) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sred[w] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) r += sred[i];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------------ FFT
+template <typename R>
+__device__ __forceinline__ void bfly3(Cx<R>* v, R sgn) {
+  const R s3 = (R)0.86602540378443864676;
+  Cx<R> t = v[1] + v[2];
+  Cx<R> dl = v[1] - v[2];
+  Cx<R> m = v[0] - t * (R)0.5;
+  Cx<R> j = imul(dl, sgn * s3);
+  v[0] = v[0] + t;
+  v[1] = m + j;
+  v[2] = m - j;
+}
+
+template <typename R>
+__device__ __forceinline__ void bfly5(Cx<R>* v, R sgn) {
+  const R c1 = (R)0.30901699437494742410, c2 = (R)-0.80901699437494742410;
+  const R s1 = (R)0.95105651629515357212, s2 = (R)0.58778525229247312917;
+  Cx<R> t1 = v[1] + v[4], t2 = v[2] + v[3], t3 = v[1] - v[4], t4 = v[2] - v[3];
+  Cx<R> a1 = v[0] + t1 * c1 + t2 * c2;
+  Cx<R> a2 = v[0] + t1 * c2 + t2 * c1;
+  Cx<R> b1 = t3 * s1 + t4 * s2;
+  Cx<R> b2 = t3 * s2 - t4 * s1;
+  v[0] = v[0] + t1 + t2;
+  Cx<R> ib1 = imul(b1, sgn), ib2 = imul(b2, sgn);
+  v[1] = a1 + ib1;
+  v[4] = a1 - ib1;
+  v[2] = a2 + ib2;
+  v[3] = a2 - ib2;
+}
+
+// In-place Stockham FFT of nl interleaved lines of length M held in LDS as
+// buf[j * nl + l] (element j of line l).  The whole block participates.
+// Stage with radix R after Ns points done: butterfly j reads elements
+// j + r M/R, twiddles by w^(r (j mod Ns) M/(Ns R)) and writes
+// (j / Ns) Ns R + (j mod Ns) + r Ns.
+template <typename R, int MAXB>
+__device__ void lds_fft(Cx<R>* buf, int nl, int M, const Plan& pl, const Cx<R>* __restrict__ tw, bool inv) {
+  const int tid = threadIdx.x;
+  const R sgn = inv ? (R)1 : (R)-1;
+  int Ns = 1;
+  for (int s = 0; s < pl.n; ++s) {
+    const int Rr = pl.r[s];
+    const int nb = M / Rr;
+    const int total = nb * nl;
+    const int tstride = M / (Ns * Rr);
+    Cx<R> v[MAXB][5];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+      const int t = tid + i * kBlock;
+      if (t < total) {
+        const int l = t % nl, j = t / nl;
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+          if (r < Rr) v[i][r] = buf[(j + r * nb) * nl + l];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+      const int t = tid + i * kBlock;
+      if (t < total) {
+        const int l = t % nl, j = t / nl;
+        const int k = j % Ns;
+        if (k) {
+#pragma unroll
+          for (int r = 1; r < 5; ++r)
+            if (r < Rr) {
+              Cx<R> w = tw[r * k * tstride];
+              if (inv) w.y = -w.y;
+              v[i][r] = cmul(v[i][r], w);
+            }
+        }
+        if (Rr == 5)
+          bfly5(v[i], sgn);
+        else
+          bfly3(v[i], sgn);
+        const int base = (j / Ns) * Ns * Rr + k;
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+          if (r < Rr) buf[(base + r * Ns) * nl + l] = v[i][r];
+      }
+    }
+    __syncthreads();
+    Ns *= Rr;
+  }
+}
+
+// ------------------------------------------------------------------ basis T(k)
+// Orthonormal basis of the range of G^E(k) (primal, one column xi/|xi|) or of
+// G^J(k) (dual: d = 2 the rotated normal, d = 3 two tangents), Def. projection.
+__device__ __forceinline__ void basis(const Geo& g, int k0, int k1, int k2, double T[3][2]) {
+  const int kk[3] = {k0, k1, k2};
+  double n[3] = {0.0, 0.0, 0.0};
+  double n2 = 0.0;
+  for (int c = 0; c < g.d; ++c) {
+    const int a = g.phys_axis[c];
+    n[c] = kk[a] * g.iY[a];
+    n2 += n[c] * n[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) T[c][0] = T[c][1] = 0.0;
+  if (n2 == 0.0) return;
+  const double inv = 1.0 / sqrt(n2);
+  for (int c = 0; c < g.d; ++c) n[c] *= inv;
+  if (!g.dual) {
+    for (int c = 0; c < g.d; ++c) T[c][0] = n[c];
+  } else if (g.d == 2) {
+    T[0][0] = -n[1];
+    T[1][0] = n[0];
+  } else {
+    int a = 0;
+    if (fabs(n[1]) < fabs(n[a])) a = 1;
+    if (fabs(n[2]) < fabs(n[a])) a = 2;
+    double t1[3] = {-n[a] * n[0], -n[a] * n[1], -n[a] * n[2]};
+    t1[a] += 1.0;
+    const double in1 = 1.0 / sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+    t1[0] *= in1;
+    t1[1] *= in1;
+    t1[2] *= in1;
+    const double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+    for (int c = 0; c < 3; ++c) {
+      T[c][0] = t1[c];
+      T[c][1] = t2[c];
+    }
+  }
+}
+
+// Symmetric coefficient times vector: w = A u, A given by nc components.
+template <typename R>
+__device__ __forceinline__ void coef_mul(int d, int nc, const R* a, const R* u, R* w) {
+  if (nc == 1) {
+    for (int c = 0; c < d; ++c) w[c] = a[0] * u[c];
+  } else if (d == 2) {  // xx, yy, xy
+    w[0] = a[0] * u[0] + a[2] * u[1];
+    w[1] = a[2] * u[0] + a[1] * u[1];
+  } else {  // xx, yy, zz, xy, xz, yz
+    w[0] = a[0] * u[0] + a[3] * u[1] + a[4] * u[2];
+    w[1] = a[3] * u[0] + a[1] * u[1] + a[5] * u[2];
+    w[2] = a[4] * u[0] + a[5] * u[1] + a[2] * u[2];
+  }
+}
+
+__device__ __forceinline__ void decode_pair(const Geo& g, int q, int& h0, int& k1) {
+  const int half1 = (g.N[1] + 1) / 2;
+  if (q < half1) {
+    h0 = 0;
+    k1 = q;
+  } else {
+    const int q2 = q - half1;
+    h0 = 1 + q2 / g.N[1];
+    k1 = fr(q2 % g.N[1], g.N[1]);
+  }
+}
+
+__host__ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+// ============================================================== first pass
+template <typename R, int MAXB>
+__global__ __launch_bounds__(kBlock) void k_first(Geo g, const UnitDev* __restrict__ units, int mode, int jstep,
+                                                  const int* __restrict__ iter_base) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double s_alpha[kMaxLoads];
+  __shared__ int s_act[kMaxLoads];
+  __shared__ double s_red[kBlock / 64];
+  const UnitDev& U = units[blockIdx.z];
+  const int tid = threadIdx.x;
+  const int N0 = g.N[0], N1 = g.N[1], N2 = g.N[2], M2 = g.M[2];
+  const int L = g.L, m = g.m, P = g.P, d = g.d;
+  int h0, k1;
+  decode_pair(g, blockIdx.x, h0, k1);
+  const bool self = (h0 == 0 && k1 == 0);
+  const bool rowB = (h0 == 0 && k1 != 0);
+  const int i1A = ixn(k1, N1), i1B = ixn(-k1, N1);
+  const int it = iter_base ? (*iter_base + jstep) : 0;
+  const int nl = (self ? 1 : 2) * P;
+
+  Cx<double>* rA = reinterpret_cast<Cx<double>*>(smem);
+  Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem + align16((size_t)L * m * N2 * sizeof(Cx<double>)));
+
+  // ---- scalars of the step: alpha_{it-1} from <r, C r> partials of the last pass
+  if (tid < kMaxLoads * 64) {
+    const int w = tid >> 6, lane = tid & 63;
+    if (w < L) {
+      int act = 1;
+      double alpha = 0.0;
+      if (mode == FIRST_CG) {
+        CgScal* sc = U.sc + w;
+        act = (sc->status == 0);
+        if (act && it > 0) {
+          const double delta = wave_sum_arr(U.part_d + (size_t)w * g.nbL, g.nbL);
+          const double gam = sc->gamma[(it - 1) & 1];
+          double den = delta;
+          if (it > 1) den = delta - sc->beta[(it - 1) & 1] * gam / sc->alpha[(it - 2) & 1];
+          if (!(den > 0.0)) {
+            act = 0;
+            if (blockIdx.x == 0 && lane == 0) {
+              sc->status = -3;
+              sc->iters = it - 1;
+              sc->gamma_last = gam;
+            }
+          } else {
+            alpha = gam / den;
+            if (blockIdx.x == 0 && lane == 0) sc->alpha[(it - 1) & 1] = alpha;
+          }
+        }
+      }
+      if (lane == 0) {
+        s_alpha[w] = alpha;
+        s_act[w] = act;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 1: CG update of the stored rows, stage row A in LDS
+  double gp0 = 0.0, gp1 = 0.0, gp2 = 0.0;
+  const int per_row = L * m * N2;
+  const int nrows = rowB ? 2 : 1;
+  const double wt = (h0 == 0) ? 1.0 : 2.0;
+  for (int t = tid; t < nrows * per_row; t += kBlock) {
+    const int row = t / per_row, rem = t - row * per_row;
+    const int l = rem / (m * N2), c = (rem / N2) % m, i2 = rem % N2;
+    const int i1 = row ? i1B : i1A;
+    const size_t idx = ((size_t)(c * g.H0 + h0) * N1 + i1) * N2 + i2;
+    Cx<double> val = cx(0.0, 0.0);
+    if (mode == FIRST_CG) {
+      if (s_act[l]) {
+        Cx<double> rv = U.r[l][idx];
+        if (it > 0) {
+          const double a = s_alpha[l];
+          Cx<double> xv = U.x[l][idx];
+          const Cx<double> pv = U.p[l][idx], sv = U.s[l][idx];
+          xv = xv + pv * a;
+          rv = rv - sv * a;
+          U.x[l][idx] = xv;
+          U.r[l][idx] = rv;
+        }
+        const double e = wt * (rv.x * rv.x + rv.y * rv.y);
+        if (l == 0) gp0 += e;
+        else if (l == 1) gp1 += e;
+        else gp2 += e;
+        val = rv;
+      }
+    } else {
+      val = U.x[l][idx];
+    }
+    if (row == 0) rA[(l * m + c) * N2 + i2] = val;
+  }
+  if (mode == FIRST_CG) {
+    for (int l = 0; l < L; ++l) {
+      const double s = block_sum(l == 0 ? gp0 : (l == 1 ? gp1 : gp2), s_red);
+      if (tid == 0) U.part_g[(size_t)l * g.nbF + blockIdx.x] = s;
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 2: fields of both lines, two real fields per complex pack
+  const int hN2 = (N2 - 1) / 2;
+  for (int t = tid; t < M2 * nl; t += kBlock) {
+    const int j = t / nl, l = t - (t / nl) * nl;
+    const int line = l / P, pk = l - line * P;
+    Cx<R> o = cx((R)0, (R)0);
+    int k2 = 0;
+    bool has = true;
+    if (j <= hN2) k2 = j;
+    else if (j >= M2 - hN2) k2 = j - M2;
+    else has = false;
+    if (has) {
+      const int sk2 = line ? -k2 : k2;     // line B at k2 is conj of row A at -k2
+      const int src = ixn(sk2, N2);
+      double T[3][2];
+      basis(g, h0, k1, sk2, T);
+      Cx<double> X[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int f = 2 * pk + s;
+        X[s] = cx(0.0, 0.0);
+        if (f < L * d) {
+          const int lf = f / d, gam = f - (f / d) * d;
+          Cx<double> xv = cx(0.0, 0.0);
+          for (int c = 0; c < m; ++c) xv = xv + rA[(lf * m + c) * N2 + src] * T[gam][c];
+          if (line) xv.y = -xv.y;
+          if (mode == FIRST_BOUNDS && self && k2 == 0) xv.x += U.E[lf][gam];
+          X[s] = xv;
+        }
+      }
+      o = cx((R)(X[0].x - X[1].y), (R)(X[0].y + X[1].x));
+    }
+    buf[j * nl + l] = o;
+  }
+  __syncthreads();
+  lds_fft<R, MAXB>(buf, nl, M2, g.pl[2], reinterpret_cast<const Cx<R>*>(g.tw[2]), true);
+
+  Cx<R>* out = reinterpret_cast<Cx<R>*>(U.bufA);
+  const int i0A = h0, i0B = ixn(-h0, N0);
+  for (int t = tid; t < M2 * nl; t += kBlock) {
+    const int j = t / nl, l = t - (t / nl) * nl;
+    const int line = l / P, pk = l - line * P;
+    const int i0 = line ? i0B : i0A, i1 = line ? i1B : i1A;
+    out[(((size_t)i0 * N1 + i1) * M2 + j) * P + pk] = buf[j * nl + l];
+  }
+}
+
+// ============================================================== last pass
+template <typename R, int MAXB>
+__global__ __launch_bounds__(kBlock) void k_last(Geo g, const UnitDev* __restrict__ units, int mode, int jstep,
+                                                 const int* __restrict__ iter_base) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double s_beta[kMaxLoads];
+  __shared__ int s_act[kMaxLoads];
+  __shared__ double s_red[kBlock / 64];
+  const UnitDev& U = units[blockIdx.z];
+  const int tid = threadIdx.x;
+  const int N0 = g.N[0], N1 = g.N[1], N2 = g.N[2], M2 = g.M[2];
+  const int L = g.L, m = g.m, P = g.P, d = g.d;
+  int h0, k1;
+  decode_pair(g, blockIdx.x, h0, k1);
+  const bool self = (h0 == 0 && k1 == 0);
+  const bool rowB = (h0 == 0 && k1 != 0);
+  const int i1A = ixn(k1, N1), i1B = ixn(-k1, N1);
+  const int it = iter_base ? (*iter_base + jstep) : 0;
+  const int nl = (self ? 1 : 2) * P;
+  Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem);
+
+  // ---- scalars: gamma_it from the first-pass partials, convergence, beta_it
+  if (tid < kMaxLoads * 64) {
+    const int w = tid >> 6, lane = tid & 63;
+    if (w < L) {
+      int act = 1;
+      double beta = 0.0;
+      if (mode == LAST_CG) {
+        CgScal* sc = U.sc + w;
+        act = (sc->status == 0);
+        if (act) {
+          const double gam = wave_sum_arr(U.part_g + (size_t)w * g.nbF, g.nbF);
+          const bool bad = !(gam == gam) || gam > 1e300;
+          const bool conv = sqrt(gam) <= sc->tol * sc->normE;
+          if (bad || conv || it >= sc->maxit) {
+            act = 0;
+            if (blockIdx.x == 0 && lane == 0) {
+              sc->status = bad ? -1 : (conv ? 1 : 2);
+              sc->iters = it;
+              sc->gamma_last = gam;
+              if (it == 0) sc->gamma0 = gam;
+            }
+          } else {
+            beta = (it == 0) ? 0.0 : gam / sc->gamma[(it - 1) & 1];
+            if (blockIdx.x == 0 && lane == 0) {
+              sc->gamma[it & 1] = gam;
+              sc->beta[it & 1] = beta;
+              if (it == 0) sc->gamma0 = gam;
+            }
+          }
+        }
+      }
+      if (lane == 0) {
+        s_beta[w] = beta;
+        s_act[w] = act;
+      }
+    }
+  }
+  __syncthreads();
+  int any = 0;
+  for (int l = 0; l < L; ++l) any |= s_act[l];
+  if (!any) return;  // uniform over the block
+
+  // ---- load both lines and transform forward
+  const Cx<R>* in = reinterpret_cast<const Cx<R>*>(U.bufA);
+  const int i0A = h0, i0B = ixn(-h0, N0);
+  for (int t = tid; t < M2 * nl; t += kBlock) {
+    const int j = t / nl, l = t - (t / nl) * nl;
+    const int line = l / P, pk = l - line * P;
+    const int i0 = line ? i0B : i0A, i1 = line ? i1B : i1A;
+    buf[j * nl + l] = in[(((size_t)i0 * N1 + i1) * M2 + j) * P + pk];
+  }
+  __syncthreads();
+  lds_fft<R, MAXB>(buf, nl, M2, g.pl[2], reinterpret_cast<const Cx<R>*>(g.tw[2]), false);
+
+  // ---- epilogue on the stored entries of row A (and of row B when it is stored)
+  double dp0 = 0.0, dp1 = 0.0, dp2 = 0.0;
+  const int nrows = rowB ? 2 : 1;
+  const double wt = (h0 == 0) ? 1.0 : 2.0;
+  const double sc_m = g.invM * 0.5;
+  for (int t = tid; t < nrows * N2; t += kBlock) {
+    const int row = t / N2, i2 = t - row * N2;
+    const int k2 = fr(i2, N2);
+    const int lineK = self ? 0 : row, lineM = self ? 0 : 1 - row;
+    const int posK = padpos(i2, N2, M2), posM = padpos(ixn(-k2, N2), N2, M2);
+    const int kk0 = row ? 0 : h0, kk1 = row ? -k1 : k1;
+    const int i1 = row ? i1B : i1A;
+    double T[3][2];
+    basis(g, kk0, kk1, k2, T);
+    for (int l = 0; l < L; ++l) {
+      if (mode == LAST_CG && !s_act[l]) continue;
+      Cx<double> wv[3];
+      for (int gam = 0; gam < d; ++gam) {
+        const int f = l * d + gam, pk = f >> 1;
+        const Cx<R> za = buf[posK * nl + lineK * P + pk];
+        const Cx<R> zb = buf[posM * nl + lineM * P + pk];
+        if ((f & 1) == 0)
+          wv[gam] = cx(((double)za.x + (double)zb.x) * sc_m, ((double)za.y - (double)zb.y) * sc_m);
+        else
+          wv[gam] = cx(((double)za.y + (double)zb.y) * sc_m, -((double)za.x - (double)zb.x) * sc_m);
+      }
+      for (int c = 0; c < m; ++c) {
+        Cx<double> w = cx(0.0, 0.0);
+        for (int gam = 0; gam < d; ++gam) w = w + wv[gam] * T[gam][c];
+        const size_t idx = ((size_t)(c * g.H0 + kk0) * N1 + i1) * N2 + i2;
+        double e;
+        if (mode == LAST_CG) {
+          const Cx<double> rv = U.r[l][idx];
+          const double b = s_beta[l];
+          if (it == 0) {
+            U.p[l][idx] = rv;
+            U.s[l][idx] = w;
+          } else {
+            U.p[l][idx] = rv + U.p[l][idx] * b;
+            U.s[l][idx] = w + U.s[l][idx] * b;
+          }
+          e = wt * (rv.x * w.x + rv.y * w.y);
+        } else if (mode == LAST_RESID) {
+          const Cx<double> rn = U.b[l][idx] - w;
+          U.r[l][idx] = rn;
+          e = wt * (rn.x * rn.x + rn.y * rn.y);
+        } else {
+          U.s[l][idx] = w;
+          e = wt * (w.x * w.x + w.y * w.y);
+        }
+        if (l == 0) dp0 += e;
+        else if (l == 1) dp1 += e;
+        else dp2 += e;
+      }
+    }
+  }
+  for (int l = 0; l < L; ++l) {
+    const double s = block_sum(l == 0 ? dp0 : (l == 1 ? dp1 : dp2), s_red);
+    if (tid == 0) U.part_d[(size_t)l * g.nbL + blockIdx.x] = s;
+  }
+}
+
+// ============================================================== middle axis (3D)
+template <typename R, int MAXB>
+__global__ __launch_bounds__(kBlock) void k_mid(Geo g, const UnitDev* __restrict__ units, int inverse) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem);
+  const UnitDev& U = units[blockIdx.z];
+  const int tid = threadIdx.x;
+  const int N1 = g.N[1], M1 = g.M[1];
+  const int inner = g.M[2] * g.P;
+  const int tile = g.tileM;
+  const int e0 = blockIdx.x * tile;
+  const int te = min(tile, inner - e0);
+  const int i0 = blockIdx.y;
+  const Cx<R>* in = reinterpret_cast<const Cx<R>*>(inverse ? U.bufA : U.bufB);
+  Cx<R>* out = reinterpret_cast<Cx<R>*>(inverse ? U.bufB : U.bufA);
+  const int Lin = inverse ? N1 : M1, Lout = inverse ? M1 : N1;
+  for (int t = tid; t < M1 * tile; t += kBlock) {
+    const int j = t / tile, e = t - (t / tile) * tile;
+    Cx<R> v = cx((R)0, (R)0);
+    if (e < te) {
+      int src = j;
+      if (inverse) src = truncidx(j, N1, M1);
+      if (src >= 0) v = in[((size_t)i0 * Lin + src) * inner + e0 + e];
+    }
+    buf[j * tile + e] = v;
+  }
+  __syncthreads();
+  lds_fft<R, MAXB>(buf, tile, M1, g.pl[1], reinterpret_cast<const Cx<R>*>(g.tw[1]), inverse != 0);
+  for (int t = tid; t < Lout * tile; t += kBlock) {
+    const int j = t / tile, e = t - (t / tile) * tile;
+    if (e < te) {
+      const int pos = inverse ? j : padpos(j, N1, M1);
+      out[((size_t)i0 * Lout + j) * inner + e0 + e] = buf[pos * tile + e];
+    }
+  }
+}
+
+// ============================================================== axis 0 + coefficient
+template <typename R, int MAXB>
+__global__ __launch_bounds__(kBlock) void k_apply(Geo g, const UnitDev* __restrict__ units, int mode) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double s_red[kBlock / 64];
+  Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem);
+  const UnitDev& U = units[blockIdx.z];
+  const int tid = threadIdx.x;
+  const int N0 = g.N[0], M0 = g.M[0], P = g.P, d = g.d, L = g.L, nc = g.nc;
+  const int npts = g.M[1] * g.M[2];
+  const size_t Mtot = (size_t)M0 * npts;
+  const int tileA = g.tileA;
+  const int p0 = blockIdx.x * tileA;
+  const int tp = min(tileA, npts - p0);
+  const int nl = tileA * P;
+  Cx<R>* data = reinterpret_cast<Cx<R>*>(g.N[1] > 1 ? U.bufB : U.bufA);
+  const R* coef = reinterpret_cast<const R*>(U.coef);
+
+  for (int t = tid; t < M0 * nl; t += kBlock) {
+    const int j = t / nl, l = t - (t / nl) * nl;
+    const int i0 = truncidx(j, N0, M0);
+    Cx<R> v = cx((R)0, (R)0);
+    if (i0 >= 0 && l < tp * P) v = data[((size_t)i0 * npts + p0) * P + l];
+    buf[j * nl + l] = v;
+  }
+  __syncthreads();
+  lds_fft<R, MAXB>(buf, nl, M0, g.pl[0], reinterpret_cast<const Cx<R>*>(g.tw[0]), true);
+
+  if (mode == APPLY_COEF) {
+    for (int t = tid; t < M0 * tileA; t += kBlock) {
+      const int j = t / tileA, pt = t - (t / tileA) * tileA;
+      if (pt >= tp) continue;
+      const size_t ci = (size_t)j * npts + p0 + pt;
+      R a[6];
+      for (int c = 0; c < nc; ++c) a[c] = coef[c * Mtot + ci];
+      R u[2 * kMaxPacks], w[2 * kMaxPacks];
+      for (int pk = 0; pk < P; ++pk) {
+        const Cx<R> z = buf[j * nl + pt * P + pk];
+        u[2 * pk] = z.x;
+        u[2 * pk + 1] = z.y;
+      }
+      for (int l = 0; l < L; ++l) coef_mul<R>(d, nc, a, u + l * d, w + l * d);
+      for (int f = L * d; f < 2 * P; ++f) w[f] = (R)0;
+      for (int pk = 0; pk < P; ++pk) buf[j * nl + pt * P + pk] = cx(w[2 * pk], w[2 * pk + 1]);
+    }
+    __syncthreads();
+    lds_fft<R, MAXB>(buf, nl, M0, g.pl[0], reinterpret_cast<const Cx<R>*>(g.tw[0]), false);
+    for (int t = tid; t < N0 * nl; t += kBlock) {
+      const int i0 = t / nl, l = t - (t / nl) * nl;
+      if (l < tp * P) data[((size_t)i0 * npts + p0) * P + l] = buf[padpos(i0, N0, M0) * nl + l];
+    }
+  } else {
+    // FP64 quadrature of the bilinear forms: sum_x v_b(x) . A(x) v_a(x)
+    double acc[kMaxLoads * kMaxLoads];
+    for (int i = 0; i < kMaxLoads * kMaxLoads; ++i) acc[i] = 0.0;
+    for (int t = tid; t < M0 * tileA; t += kBlock) {
+      const int j = t / tileA, pt = t - (t / tileA) * tileA;
+      if (pt >= tp) continue;
+      const size_t ci = (size_t)j * npts + p0 + pt;
+      R a[6];
+      for (int c = 0; c < nc; ++c) a[c] = coef[c * Mtot + ci];
+      R u[2 * kMaxPacks], w[2 * kMaxPacks];
+      for (int pk = 0; pk < P; ++pk) {
+        const Cx<R> z = buf[j * nl + pt * P + pk];
+        u[2 * pk] = z.x;
+        u[2 * pk + 1] = z.y;
+      }
+      for (int la = 0; la < L; ++la) {
+        coef_mul<R>(d, nc, a, u + la * d, w);
+        for (int lb = 0; lb < L; ++lb) {
+          double s = 0.0;
+          for (int c = 0; c < d; ++c) s += (double)u[lb * d + c] * (double)w[c];
+          acc[la * kMaxLoads + lb] += s;
+        }
+      }
+    }
+    for (int i = 0; i < L * kMaxLoads; ++i) {
+      if ((i % kMaxLoads) >= L) continue;
+      const double s = block_sum(acc[i], s_red);
+      if (tid == 0) U.part_q[(size_t)blockIdx.x * 9 + i] = s;
+    }
+  }
+}
+
+// ============================================================== setup FFT
+template <typename R, int MAXB>
+__global__ __launch_bounds__(kBlock) void k_line_fft(Cx<R>* data, int outer, int Lm, int inner, int tile, Plan pl,
+                                                     const Cx<R>* tw, int inverse) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem);
+  const int tid = threadIdx.x;
+  const int e0 = blockIdx.x * tile;
+  const int te = min(tile, inner - e0);
+  const size_t base = (size_t)blockIdx.y * Lm * inner;
+  for (int t = tid; t < Lm * tile; t += kBlock) {
+    const int j = t / tile, e = t - (t / tile) * tile;
+    buf[j * tile + e] = (e < te) ? data[base + (size_t)j * inner + e0 + e] : cx((R)0, (R)0);
+  }
+  __syncthreads();
+  lds_fft<R, MAXB>(buf, tile, Lm, pl, tw, inverse != 0);
+  for (int t = tid; t < Lm * tile; t += kBlock) {
+    const int j = t / tile, e = t - (t / tile) * tile;
+    if (e < te) data[base + (size_t)j * inner + e0 + e] = buf[j * tile + e];
+  }
+}
+
+// ============================================================== small kernels
+// Right-hand side b(k) = -T(k)^T A_hat(k) E on the stored half of Z_N
+// (the Z_N part of A_M E is exactly A_hat(k) E since E is constant).
+__global__ void k_rhs(Geo g, const UnitDev* __restrict__ units) {
+  const UnitDev& U = units[blockIdx.z];
+  const int d = g.d, nc = g.nc;
+  const int S = g.S;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S; t += gridDim.x * blockDim.x) {
+    const int i2 = t % g.N[2], i1 = (t / g.N[2]) % g.N[1], h0 = t / (g.N[2] * g.N[1]);
+    const int k1 = fr(i1, g.N[1]), k2 = fr(i2, g.N[2]);
+    double T[3][2];
+    basis(g, h0, k1, k2, T);
+    Cx<double> a[6];
+    for (int c = 0; c < nc; ++c) a[c] = U.ahat[(size_t)c * S + t];
+    for (int l = 0; l < g.L; ++l) {
+      Cx<double> v[3];
+      for (int gam = 0; gam < d; ++gam) {
+        Cx<double> s = cx(0.0, 0.0);
+        for (int dl = 0; dl < d; ++dl) {
+          Cx<double> A;
+          if (nc == 1) A = (gam == dl) ? a[0] : cx(0.0, 0.0);
+          else if (d == 2) A = (gam == dl) ? a[gam] : a[2];
+          else {
+            if (gam == dl) A = a[gam];
+            else {
+              const int lo = min(gam, dl), hi = max(gam, dl);
+              A = (lo == 0 && hi == 1) ? a[3] : ((lo == 0 && hi == 2) ? a[4] : a[5]);
+            }
+          }
+          s = s + A * U.E[l][dl];
+        }
+        v[gam] = s;
+      }
+      for (int c = 0; c < g.m; ++c) {
+        Cx<double> s = cx(0.0, 0.0);
+        for (int gam = 0; gam < d; ++gam) s = s + v[gam] * T[gam][c];
+        U.b[l][(size_t)c * S + t] = cx(-s.x, -s.y);
+      }
+    }
+  }
+}
+
+// x = 0 or untouched (given x0), r = b (x0 = 0).
+__global__ void k_start(Geo g, const UnitDev* __restrict__ units, int have_x0) {
+  const UnitDev& U = units[blockIdx.z];
+  const size_t n = (size_t)g.m * g.S;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    for (int l = 0; l < g.L; ++l) {
+      if (!have_x0) {
+        U.x[l][t] = cx(0.0, 0.0);
+        U.r[l][t] = U.b[l][t];
+      }
+      U.p[l][t] = cx(0.0, 0.0);
+      U.s[l][t] = cx(0.0, 0.0);
+    }
+  }
+}
+
+__global__ void k_init_scal(Geo g, const UnitDev* __restrict__ units, int nunits, int* iter_base, double tol,
+                            int maxit) {
+  const int u = blockIdx.x * blockDim.x + threadIdx.x;
+  if (u == 0 && iter_base) *iter_base = 0;
+  if (u >= nunits) return;
+  const UnitDev& U = units[u];
+  for (int l = 0; l < g.L; ++l) {
+    CgScal* sc = U.sc + l;
+    double e2 = 0.0;
+    for (int c = 0; c < g.d; ++c) e2 += U.E[l][c] * U.E[l][c];
+    sc->normE = sqrt(e2);
+    sc->status = 0;
+    sc->iters = 0;
+    sc->gamma[0] = sc->gamma[1] = 0.0;
+    sc->beta[0] = sc->beta[1] = 0.0;
+    sc->alpha[0] = sc->alpha[1] = 1.0;
+    sc->gamma0 = sc->gamma_last = 0.0;
+    sc->tol = tol;
+    sc->maxit = maxit;
+  }
+}
+
+// Symmetrise a field on the k0 = 0 plane so that it is the spectrum of a real
+// field: x_hat(k) <- (x_hat(k) + conj(x_hat(-k))) / 2, and zero the mean.
+__global__ void k_symmetrize(Geo g, const Cx<double>* __restrict__ src, Cx<double>* __restrict__ dst, int m) {
+  const int S = g.S;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S; t += gridDim.x * blockDim.x) {
+    const int i2 = t % g.N[2], i1 = (t / g.N[2]) % g.N[1], h0 = t / (g.N[2] * g.N[1]);
+    if (h0 > 0) {
+      for (int c = 0; c < m; ++c) dst[(size_t)c * S + t] = src[(size_t)c * S + t];
+      continue;
+    }
+    const int k1 = fr(i1, g.N[1]), k2 = fr(i2, g.N[2]);
+    const int tm = (ixn(-k1, g.N[1])) * g.N[2] + ixn(-k2, g.N[2]);
+    double Tk[3][2], Tm[3][2];
+    basis(g, 0, k1, k2, Tk);
+    basis(g, 0, -k1, -k2, Tm);
+    Cx<double> xs[3];
+    for (int gam = 0; gam < g.d; ++gam) {
+      Cx<double> a = cx(0.0, 0.0), b = cx(0.0, 0.0);
+      for (int c = 0; c < m; ++c) {
+        a = a + src[(size_t)c * S + t] * Tk[gam][c];
+        b = b + src[(size_t)c * S + tm] * Tm[gam][c];
+      }
+      xs[gam] = cx(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+    }
+    for (int c = 0; c < m; ++c) {
+      Cx<double> s = cx(0.0, 0.0);
+      for (int gam = 0; gam < g.d; ++gam) s = s + xs[gam] * Tk[gam][c];
+      dst[(size_t)c * S + t] = s;
+    }
+  }
+}
+
+// After a chunk of iterations: advance the iteration base and count active loads.
+__global__ void k_advance(Geo g, const UnitDev* __restrict__ units, int nunits, int* iter_base, int step,
+                          int* active_out) {
+  __shared__ int cnt[kBlock];
+  int c = 0;
+  for (int u = threadIdx.x; u < nunits; u += blockDim.x)
+    for (int l = 0; l < g.L; ++l) c += (units[u].sc[l].status == 0);
+  cnt[threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int i = 0; i < (int)blockDim.x; ++i) s += cnt[i];
+    *active_out = s;
+    *iter_base += step;
+  }
+}
+
+__global__ void k_coef_real(const Cx<double>* __restrict__ full, double* __restrict__ c64, float* __restrict__ c32,
+                            long n) {
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const double v = full[t].x;
+    c64[t] = v;
+    if (c32) c32[t] = (float)v;
+  }
+}
+
+// Z_N part of a Z_M array (stored half), component-major.
+__global__ void k_extract_half(Geo g, const Cx<double>* __restrict__ full, Cx<double>* __restrict__ half, int nc) {
+  const int S = g.S;
+  const size_t Mt = (size_t)g.M[0] * g.M[1] * g.M[2];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S * nc; t += gridDim.x * blockDim.x) {
+    const int c = t / S, s = t - c * S;
+    const int i2 = s % g.N[2], i1 = (s / g.N[2]) % g.N[1], h0 = s / (g.N[2] * g.N[1]);
+    const int j0 = h0, j1 = padpos(i1, g.N[1], g.M[1]), j2 = padpos(i2, g.N[2], g.M[2]);
+    half[t] = full[c * Mt + ((size_t)j0 * g.M[1] + j1) * g.M[2] + j2];
+  }
+}
+
+struct InclDev {
+  int kind;         // 0 box, 1 ball
+  double c[3];      // centre (internal axes)
+  double h[3];      // box sides (internal axes) or radius in h[0]
+  double A[6];      // coefficient difference in nc components
+};
+
+// A_hat(n) = A0 delta_n0 + sum_j A_j f_hat_j(n) exp(-2 pi i sum n_a x_a / Y_a) on Z_M
+// (eq. A_with_inclusions, Remark inclusion; ball: textbook transform of a ball).
+__global__ void k_coef_incl(int d, int M0, int M1, int M2, double iY0, double iY1, double iY2, int nc,
+                            const double* __restrict__ A0c, int n_incl, const InclDev* __restrict__ inc,
+                            Cx<double>* __restrict__ out) {
+  const size_t Mt = (size_t)M0 * M1 * M2;
+  const double iY[3] = {iY0, iY1, iY2};
+  const double vol_inv = iY0 * iY1 * iY2;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < Mt; t += (size_t)gridDim.x * blockDim.x) {
+    const int j2 = t % M2, j1 = (t / M2) % M1, j0 = t / ((size_t)M1 * M2);
+    const int n[3] = {fr(j0, M0), fr(j1, M1), fr(j2, M2)};
+    double acc_re[6] = {0, 0, 0, 0, 0, 0}, acc_im[6] = {0, 0, 0, 0, 0, 0};
+    if (n[0] == 0 && n[1] == 0 && n[2] == 0)
+      for (int c = 0; c < nc; ++c) acc_re[c] = A0c[c];
+    for (int j = 0; j < n_incl; ++j) {
+      const InclDev& I = inc[j];
+      double f;
+      if (I.kind == 0) {
+        f = 1.0;
+        for (int a = 0; a < 3; ++a) {
+          const double hy = I.h[a] * iY[a];
+          const double x = hy * n[a];
+          f *= hy * (x == 0.0 ? 1.0 : sinpi(x) / (M_PI * x));
+        }
+      } else {
+        double xi2 = 0.0;
+        for (int a = 0; a < 3; ++a) xi2 += (n[a] * iY[a]) * (n[a] * iY[a]);
+        const double kap = 2.0 * M_PI * sqrt(xi2);
+        const double R = I.h[0];
+        const double tt = kap * R;
+        if (tt < 1e-2)
+          f = (4.0 / 3.0) * M_PI * R * R * R * (1.0 - tt * tt / 10.0 + tt * tt * tt * tt / 280.0);
+        else
+          f = 4.0 * M_PI * (sin(tt) - tt * cos(tt)) / (kap * kap * kap);
+        f *= vol_inv;
+      }
+      double ph = 0.0;
+      for (int a = 0; a < 3; ++a) ph += n[a] * I.c[a] * iY[a];
+      double sn, cs;
+      sincospi(-2.0 * ph, &sn, &cs);
+      for (int c = 0; c < nc; ++c) {
+        acc_re[c] += I.A[c] * f * cs;
+        acc_im[c] += I.A[c] * f * sn;
+      }
+    }
+    for (int c = 0; c < nc; ++c) out[c * Mt + t] = cx(acc_re[c], acc_im[c]);
+  }
+}
+
+// Pixel images: A_hat(n) = prod_a [sinc(n_a/P_a)/P_a exp(-2 pi i n_a (1/(2P_a) - 1/2))] * D(n mod P),
+// D the unnormalised forward DFT of the image.
+__global__ void k_pixel_factor(int M0, int M1, int M2, int P0, int P1, int P2, int nc, const Cx<double>* __restrict__ D,
+                               Cx<double>* __restrict__ out) {
+  const size_t Mt = (size_t)M0 * M1 * M2, Pt = (size_t)P0 * P1 * P2;
+  const int Mv[3] = {M0, M1, M2}, Pv[3] = {P0, P1, P2};
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < Mt; t += (size_t)gridDim.x * blockDim.x) {
+    const int j[3] = {(int)(t / ((size_t)M1 * M2)), (int)((t / M2) % M1), (int)(t % M2)};
+    Cx<double> fac = cx(1.0, 0.0);
+    size_t di = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int n = fr(j[a], Mv[a]);
+      const double x = (double)n / Pv[a];
+      const double sc = (n == 0 ? 1.0 : sinpi(x) / (M_PI * x)) / Pv[a];
+      double sn, cs;
+      sincospi(-2.0 * n * (0.5 / Pv[a] - 0.5), &sn, &cs);
+      fac = cmul(fac, cx(sc * cs, sc * sn));
+      int nm = n % Pv[a];
+      if (nm < 0) nm += Pv[a];
+      di = di * Pv[a] + nm;
+    }
+    for (int c = 0; c < nc; ++c) out[c * Mt + t] = cmul(fac, D[c * Pt + di]);
+  }
+}
+
+// ============================================================== launchers
+static int pow2_at_least(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+
+static int max_butterflies(const Plan& pl, int M, int nl) {
+  int mx = 0;
+  for (int s = 0; s < pl.n; ++s) mx = max(mx, (M / pl.r[s]) * nl);
+  return mx;
+}
+
+#define HOM_DISPATCH(KERN, MAXB_NEEDED, LDS, GRID, ...)                                               \
+  do {                                                                                               \
+    const int mb_ = pow2_at_least((MAXB_NEEDED + kBlock - 1) / kBlock);                              \
+    const void* fn_ = nullptr;                                                                       \
+    switch (mb_) {                                                                                   \
+      case 1: fn_ = (const void*)KERN<R, 1>; break;                                                  \
+      case 2: fn_ = (const void*)KERN<R, 2>; break;                                                  \
+      case 4: fn_ = (const void*)KERN<R, 4>; break;                                                  \
+      case 8: fn_ = (const void*)KERN<R, 8>; break;                                                  \
+      case 16: fn_ = (const void*)KERN<R, 16>; break;                                                \
+      default: return hipErrorInvalidValue;                                                          \
+    }                                                                                                \
+    if ((LDS) > 160 * 1024) return hipErrorInvalidValue;                                             \
+    hipError_t e_ = hipFuncSetAttribute(fn_, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(LDS)); \
+    if (e_ != hipSuccess) return e_;                                                                 \
+    switch (mb_) {                                                                                   \
+      case 1: hipLaunchKernelGGL((KERN<R, 1>), GRID, dim3(kBlock), LDS, st, __VA_ARGS__); break;      \
+      case 2: hipLaunchKernelGGL((KERN<R, 2>), GRID, dim3(kBlock), LDS, st, __VA_ARGS__); break;      \
+      case 4: hipLaunchKernelGGL((KERN<R, 4>), GRID, dim3(kBlock), LDS, st, __VA_ARGS__); break;      \
+      case 8: hipLaunchKernelGGL((KERN<R, 8>), GRID, dim3(kBlock), LDS, st, __VA_ARGS__); break;      \
+      case 16: hipLaunchKernelGGL((KERN<R, 16>), GRID, dim3(kBlock), LDS, st, __VA_ARGS__); break;    \
+    }                                                                                                \
+    return hipGetLastError();                                                                        \
+  } while (0)
+
+template <typename R>
+hipError_t launch_first(const Geo& g, const UnitDev* units, int nunits, int mode, int jstep, const int* iter_base,
+                        hipStream_t st) {
+  const int nl = 2 * g.P;
+  const size_t lds = align16((size_t)g.L * g.m * g.N[2] * sizeof(Cx<double>)) + (size_t)g.M[2] * nl * sizeof(Cx<R>);
+  HOM_DISPATCH(k_first, max_butterflies(g.pl[2], g.M[2], nl), lds, dim3(g.Q, 1, nunits), g, units, mode, jstep,
+               iter_base);
+}
+
+template <typename R>
+hipError_t launch_last(const Geo& g, const UnitDev* units, int nunits, int mode, int jstep, const int* iter_base,
+                       hipStream_t st) {
+  const int nl = 2 * g.P;
+  const size_t lds = (size_t)g.M[2] * nl * sizeof(Cx<R>);
+  HOM_DISPATCH(k_last, max_butterflies(g.pl[2], g.M[2], nl), lds, dim3(g.Q, 1, nunits), g, units, mode, jstep,
+               iter_base);
+}
+
+template <typename R>
+hipError_t launch_apply(const Geo& g, const UnitDev* units, int nunits, int mode, hipStream_t st) {
+  const int nl = g.tileA * g.P;
+  const size_t lds = (size_t)g.M[0] * nl * sizeof(Cx<R>);
+  HOM_DISPATCH(k_apply, max_butterflies(g.pl[0], g.M[0], nl), lds, dim3(g.nbA, 1, nunits), g, units, mode);
+}
+
+template <typename R>
+hipError_t launch_mid(const Geo& g, const UnitDev* units, int nunits, int inverse, hipStream_t st) {
+  const int inner = g.M[2] * g.P;
+  const int nb = (inner + g.tileM - 1) / g.tileM;
+  const size_t lds = (size_t)g.M[1] * g.tileM * sizeof(Cx<R>);
+  HOM_DISPATCH(k_mid, max_butterflies(g.pl[1], g.M[1], g.tileM), lds, dim3(nb, g.N[0], nunits), g, units, inverse);
+}
+
+template <typename R>
+hipError_t launch_line_fft(Cx<R>* data, int outer, int Lm, int inner, const Plan& pl, const Cx<R>* tw, int inverse,
+                           hipStream_t st) {
+  int tile = 1;
+  while (tile * 2 <= inner && (size_t)Lm * tile * 2 * sizeof(Cx<R>) <= 48 * 1024 && tile < 64) tile *= 2;
+  const int nb = (inner + tile - 1) / tile;
+  const size_t lds = (size_t)Lm * tile * sizeof(Cx<R>);
+  HOM_DISPATCH(k_line_fft, max_butterflies(pl, Lm, tile), lds, dim3(nb, outer, 1), data, outer, Lm, inner, tile, pl,
+               tw, inverse);
+}
+
+template hipError_t launch_first<float>(const Geo&, const UnitDev*, int, int, int, const int*, hipStream_t);
+template hipError_t launch_first<double>(const Geo&, const UnitDev*, int, int, int, const int*, hipStream_t);
+template hipError_t launch_last<float>(const Geo&, const UnitDev*, int, int, int, const int*, hipStream_t);
+template hipError_t launch_last<double>(const Geo&, const UnitDev*, int, int, int, const int*, hipStream_t);
+template hipError_t launch_apply<float>(const Geo&, const UnitDev*, int, int, hipStream_t);
+template hipError_t launch_apply<double>(const Geo&, const UnitDev*, int, int, hipStream_t);
+template hipError_t launch_mid<float>(const Geo&, const UnitDev*, int, int, hipStream_t);
+template hipError_t launch_mid<double>(const Geo&, const UnitDev*, int, int, hipStream_t);
+template hipError_t launch_line_fft<double>(Cx<double>*, int, int, int, const Plan&, const Cx<double>*, int,
+                                            hipStream_t);
+
+static int grid_for(size_t n) {
+  size_t b = (n + kBlock - 1) / kBlock;
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  return (int)b;
+}
+
+hipError_t launch_rhs(const Geo& g, const UnitDev* units, int nunits, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs, dim3(grid_for(g.S), 1, nunits), dim3(kBlock), 0, st, g, units);
+  return hipGetLastError();
+}
+
+hipError_t launch_start_vectors(const Geo& g, const UnitDev* units, int nunits, int have_x0, hipStream_t st) {
+  hipLaunchKernelGGL(k_start, dim3(grid_for((size_t)g.m * g.S), 1, nunits), dim3(kBlock), 0, st, g, units, have_x0);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_scal(const Geo& g, const UnitDev* units, int nunits, int* iter_base, double tol, int maxit,
+                            hipStream_t st) {
+  hipLaunchKernelGGL(k_init_scal, dim3((nunits + kBlock - 1) / kBlock), dim3(kBlock), 0, st, g, units, nunits,
+                     iter_base, tol, maxit);
+  return hipGetLastError();
+}
+
+hipError_t launch_symmetrize(const Geo& g, const Cx<double>* src, Cx<double>* dst, int m, hipStream_t st) {
+  hipLaunchKernelGGL(k_symmetrize, dim3(grid_for(g.S)), dim3(kBlock), 0, st, g, src, dst, m);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance(const Geo& g, const UnitDev* units, int nunits, int* iter_base, int step, int* active_out,
+                          hipStream_t st) {
+  hipLaunchKernelGGL(k_advance, dim3(1), dim3(kBlock), 0, st, g, units, nunits, iter_base, step, active_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_real(const Cx<double>* full, double* c64, float* c32, long n, hipStream_t st) {
+  hipLaunchKernelGGL(k_coef_real, dim3(grid_for(n)), dim3(kBlock), 0, st, full, c64, c32, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_half(const Geo& g, const Cx<double>* full, Cx<double>* half, int nc, hipStream_t st) {
+  hipLaunchKernelGGL(k_extract_half, dim3(grid_for((size_t)g.S * nc)), dim3(kBlock), 0, st, g, full, half, nc);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_incl(int d, const int* Mint, const double* iY, int nc, const double* A0c, int n_incl,
+                            const void* dev_incl, Cx<double>* out, hipStream_t st) {
+  const size_t Mt = (size_t)Mint[0] * Mint[1] * Mint[2];
+  hipLaunchKernelGGL(k_coef_incl, dim3(grid_for(Mt)), dim3(kBlock), 0, st, d, Mint[0], Mint[1], Mint[2], iY[0], iY[1],
+                     iY[2], nc, A0c, n_incl, reinterpret_cast<const InclDev*>(dev_incl), out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pixel_factor(int d, const int* Mint, const int* Pint, int nc, const Cx<double>* dft, Cx<double>* out,
+                               hipStream_t st) {
+  (void)d;
+  const size_t Mt = (size_t)Mint[0] * Mint[1] * Mint[2];
+  hipLaunchKernelGGL(k_pixel_factor, dim3(grid_for(Mt)), dim3(kBlock), 0, st, Mint[0], Mint[1], Mint[2], Pint[0],
+                     Pint[1], Pint[2], nc, dft, out);
+  return hipGetLastError();
+}
+
+size_t incl_dev_size() { return sizeof(InclDev); }
+
+}  // namespace hom
