@@ -173,6 +173,16 @@ hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n
 hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t* phase, int32_t nphase,
                            const double* phase_A, int32_t inverse, void* out, void* stream);
 
+/* Per-kernel timing of one operator application (measurement support).
+ * Enqueues `reps` launches of each pass of the operator of the primal
+ * (dual = 0) or dual problem with nload loads, in the launch configuration of
+ * the solver, bracketing each batch of launches with HIP events on the
+ * problem's stream.  ms_out (host, 5 doubles) receives the average duration
+ * per launch in milliseconds of: row inverse pass, middle inverse pass (3D,
+ * else 0), column pass with the coefficient, middle forward pass (3D, else 0),
+ * row forward pass.  The slot's scratch vectors are overwritten. */
+hom_status hom_profile_passes(hom_problem* pb, int32_t dual, int32_t nload, int32_t reps, double* ms_out);
+
 /* Release the handle (host memory only; the workspace stays with the caller). */
 void hom_destroy(hom_problem* pb);
 

@@ -50,6 +50,7 @@ EXPORTS = {
                                         C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p]),
     "hom_coef_pixels": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
                                     C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p]),
+    "hom_profile_passes": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "hom_destroy": (None, [C.c_void_p]),
 }
 

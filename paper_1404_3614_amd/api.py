@@ -193,6 +193,13 @@ class Problem:
                 "hom_apply")
         return y
 
+    def profile_passes(self, dual=False, nload=None, reps=20):
+        """Average per-launch milliseconds of the five operator passes (HIP events)."""
+        ms = (C.c_double * 5)()
+        n = self.d if nload is None else nload
+        L.check(L.load().hom_profile_passes(self.h, int(dual), int(n), int(reps), ms), "hom_profile_passes")
+        return dict(first=ms[0], mid_inv=ms[1], apply=ms[2], mid_fwd=ms[3], last=ms[4])
+
     def solve_bounds(self, tol=1e-6, maxit=10000, allow_not_converged=False):
         xp, ip = self.solve(False, tol=tol, maxit=maxit, allow_not_converged=allow_not_converged)
         xd, idl = self.solve(True, tol=tol, maxit=maxit, allow_not_converged=allow_not_converged)

@@ -577,8 +577,8 @@ hom_status hom_setup(const hom_desc* desc, int32_t max_loads, const void* Ahat, 
   std::vector<Cx<float>> t32[3];
   hom_status rc = HOM_OK;
   auto fail = [&](hom_status e) {
-    hipStreamSynchronize(st);
-    hipHostFree(pb->pinned_active);
+    (void)hipStreamSynchronize(st);
+    (void)hipHostFree(pb->pinned_active);
     delete pb;
     return e;
   };
@@ -770,7 +770,7 @@ hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n
                        reinterpret_cast<Cx<double>*>(out), st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     rc = HOM_E_DEVICE;
-  hipFree(dev);
+  (void)hipFree(dev);
   return rc;
 }
 
@@ -836,16 +836,66 @@ hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t
                                 st);
   if (e == hipSuccess) e = launch_pixel_factor(d, z.M, Pint, nc, D, reinterpret_cast<Cx<double>*>(out), st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  hipFree(dev);
+  (void)hipFree(dev);
   return e == hipSuccess ? HOM_OK : HOM_E_DEVICE;
+}
+
+hom_status hom_profile_passes(hom_problem* pb, int32_t dual, int32_t nload, int32_t reps, double* ms_out) {
+  if (!pb || !ms_out || (dual != 0 && dual != 1) || nload < 1 || nload > pb->max_loads || reps < 1)
+    return HOM_E_INVALID;
+  const int k = dual;
+  hipStream_t st = pb->stream;
+  const bool fp32 = pb->desc.precision == HOM_MIXED;
+  Geo g = make_geo(pb, k, nload, fp32);
+  SlotBufs& sb = pb->slot[k];
+  UnitDev* hu = &pb->host_unit[k];
+  fill_unit(pb, k, nload, nullptr, nullptr, hu);
+  for (int l = 0; l < nload; ++l) hu->s[l] = sb.p[l];  // matvec output goes to scratch
+  HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
+  const size_t vbytes = (size_t)g.m * g.S * sizeof(Cx<double>);
+  for (int l = 0; l < nload; ++l) HIPCHK(hipMemsetAsync(sb.tmp[l], 0, vbytes, st));
+  hipEvent_t ev[6];
+  for (int i = 0; i < 6; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  hom_status rc = HOM_OK;
+  auto run = [&](int which) -> hipError_t {
+    for (int r = 0; r < reps; ++r) {
+      hipError_t e = hipSuccess;
+      if (which == 0) e = fp32 ? launch_first<float>(g, sb.unit, 1, FIRST_FIELD, 0, nullptr, st)
+                               : launch_first<double>(g, sb.unit, 1, FIRST_FIELD, 0, nullptr, st);
+      if (which == 1 && g.d == 3) e = fp32 ? launch_mid<float>(g, sb.unit, 1, 1, st) : launch_mid<double>(g, sb.unit, 1, 1, st);
+      if (which == 2) e = fp32 ? launch_apply<float>(g, sb.unit, 1, APPLY_COEF, st)
+                               : launch_apply<double>(g, sb.unit, 1, APPLY_COEF, st);
+      if (which == 3 && g.d == 3) e = fp32 ? launch_mid<float>(g, sb.unit, 1, 0, st) : launch_mid<double>(g, sb.unit, 1, 0, st);
+      if (which == 4) e = fp32 ? launch_last<float>(g, sb.unit, 1, LAST_MATVEC, 0, nullptr, st)
+                               : launch_last<double>(g, sb.unit, 1, LAST_MATVEC, 0, nullptr, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  // one untimed round so that first-launch costs are excluded
+  for (int w = 0; w < 5 && rc == HOM_OK; ++w)
+    if (run(w) != hipSuccess) rc = HOM_E_DEVICE;
+  for (int w = 0; w < 5 && rc == HOM_OK; ++w) {
+    if (hipEventRecord(ev[w], st) != hipSuccess || run(w) != hipSuccess || hipEventRecord(ev[w + 1], st) != hipSuccess)
+      rc = HOM_E_DEVICE;
+  }
+  if (rc == HOM_OK && hipEventSynchronize(ev[5]) != hipSuccess) rc = HOM_E_DEVICE;
+  for (int w = 0; w < 5 && rc == HOM_OK; ++w) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev[w], ev[w + 1]) != hipSuccess) rc = HOM_E_DEVICE;
+    const bool skipped = (w == 1 || w == 3) && g.d != 3;
+    ms_out[w] = skipped ? 0.0 : (double)ms / reps;
+  }
+  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
+  return rc;
 }
 
 void hom_destroy(hom_problem* pb) {
   if (!pb) return;
   for (int k = 0; k < 2; ++k)
     for (int l = 0; l <= kMaxLoads; ++l)
-      if (pb->graph[k][l]) hipGraphExecDestroy(pb->graph[k][l]);
-  if (pb->pinned_active) hipHostFree(pb->pinned_active);
+      if (pb->graph[k][l]) (void)hipGraphExecDestroy(pb->graph[k][l]);
+  if (pb->pinned_active) (void)hipHostFree(pb->pinned_active);
   delete pb;
 }
 

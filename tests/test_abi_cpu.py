@@ -1,0 +1,101 @@
+"""CPU checks of the C ABI: the library loads, exports every function that
+include/hom.h declares, and validates arguments before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hom.h")
+
+
+def _lib():
+    from paper_1404_3614_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        from paper_1404_3614_amd import build
+        build.build(verbose=False)
+    return L, L.load()
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(hom_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["hom_setup", "hom_solve_primal", "hom_solve_dual", "hom_bounds", "hom_workspace_bytes",
+              "hom_field_len", "hom_coef_inclusions", "hom_coef_pixels", "hom_apply", "hom_destroy"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    L, lib = _lib()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+        assert n in L.EXPORTS, f"{n} has no ctypes declaration"
+
+
+def _desc(L, d=2, N=(13, 13, 1), prec=0, nc=1, Y=(1.0, 1.0, 1.0)):
+    ds = L.Desc()
+    ds.d = d
+    for a in range(3):
+        ds.N[a] = N[a]
+        ds.Y[a] = Y[a]
+    ds.precision = prec
+    ds.ncoef = nc
+    return ds
+
+
+@pytest.mark.parametrize("N,expect", [((13, 13, 1), 0), ((12, 13, 1), -2), ((7, 13, 1), -2),
+                                      ((313, 313, 1), 0), ((1, 13, 1), -2), ((63, 41, 1), 0)])
+def test_size_validation(N, expect):
+    # N even -> unsupported; N = 7 gives M = 13, not of the form 3^p 5^q
+    L, lib = _lib()
+    n = C.c_size_t()
+    assert lib.hom_workspace_bytes(C.byref(_desc(L, N=N)), 2, C.byref(n)) == expect
+
+
+def test_argument_validation_without_device():
+    L, lib = _lib()
+    n = C.c_size_t()
+    assert lib.hom_workspace_bytes(C.byref(_desc(L, d=4)), 1, C.byref(n)) == L.HOM_E_INVALID
+    assert lib.hom_workspace_bytes(C.byref(_desc(L, nc=2)), 1, C.byref(n)) == L.HOM_E_INVALID
+    assert lib.hom_workspace_bytes(C.byref(_desc(L, prec=7)), 1, C.byref(n)) == L.HOM_E_INVALID
+    assert lib.hom_workspace_bytes(C.byref(_desc(L)), 0, C.byref(n)) == L.HOM_E_INVALID
+    assert lib.hom_workspace_bytes(C.byref(_desc(L)), 4, C.byref(n)) == L.HOM_E_INVALID
+    assert lib.hom_workspace_bytes(C.byref(_desc(L, Y=(1.0, -1.0, 1.0))), 1, C.byref(n)) == L.HOM_E_INVALID
+    assert lib.hom_workspace_bytes(None, 1, C.byref(n)) == L.HOM_E_INVALID
+    h = C.c_void_p()
+    # null coefficient pointers are rejected before any device call
+    assert lib.hom_setup(C.byref(_desc(L)), 1, None, None, None, 0, None, C.byref(h)) == L.HOM_E_INVALID
+    assert lib.hom_bounds(None, None, None, None) == L.HOM_E_INVALID
+    assert lib.hom_status_str(-3) == b"HOM_E_NOT_SPD"
+    lib.hom_destroy(None)
+
+
+def test_field_len_matches_layout():
+    L, lib = _lib()
+    n = C.c_size_t()
+    assert lib.hom_field_len(C.byref(_desc(L, N=(13, 13, 1))), 0, C.byref(n)) == 0
+    assert n.value == 7 * 13
+    assert lib.hom_field_len(C.byref(_desc(L, d=3, N=(5, 13, 41))), 1, C.byref(n)) == 0
+    assert n.value == 2 * 3 * 13 * 41
+    # N1 = 9 gives M1 = 17: unsupported
+    assert lib.hom_field_len(C.byref(_desc(L, d=3, N=(5, 9, 13))), 1, C.byref(n)) == L.HOM_E_UNSUPPORTED_SIZE
+
+
+def test_workspace_grows_with_loads_and_precision():
+    L, lib = _lib()
+    sizes = {}
+    for prec in (0, 1):
+        for loads in (1, 2):
+            n = C.c_size_t()
+            assert lib.hom_workspace_bytes(C.byref(_desc(L, N=(41, 41, 1), prec=prec)), loads, C.byref(n)) == 0
+            sizes[(prec, loads)] = n.value
+            assert n.value % 256 == 0
+    assert sizes[(0, 2)] > sizes[(0, 1)]
+    assert sizes[(1, 1)] != sizes[(0, 1)]
