@@ -111,12 +111,19 @@ hom_status hom_workspace_bytes(const hom_desc* desc, int32_t max_loads, size_t* 
  * The library evaluates the coefficient on the doubled grid,
  * A_M(x^k) = sum_n omega_M^{kn} A_hat(n), in FP64 on the device (plus an
  * FP32 copy for HOM_MIXED), and keeps the Z_N part of A_hat for the
- * right-hand side.  Ahat/Bhat may be freed after the call returns.
+ * right-hand side.  The work is enqueued on the stream without host
+ * synchronisation: Ahat/Bhat must stay valid until the stream has passed it
+ * (every solve and bounds call synchronises the stream).
  * ws: device workspace of at least hom_workspace_bytes(); it must stay
  * allocated until hom_destroy.  stream: hipStream_t or NULL.
  * On success *out receives a handle (host memory owned by the library). */
 hom_status hom_setup(const hom_desc* desc, int32_t max_loads, const void* Ahat, const void* Bhat,
                      void* ws, size_t ws_bytes, void* stream, hom_problem** out);
+
+/* Replace the coefficient of an existing problem (same desc) by new Fourier
+ * data, as hom_setup does; keeps the handle, its workspace and any batch or
+ * captured graph built on it.  Same lifetime rule for Ahat/Bhat. */
+hom_status hom_update_coefficients(hom_problem* pb, const void* Ahat, const void* Bhat);
 
 /* Primal solves (Sec. 7.1, eq. linear_system_primal with the exact form):
  * for each of nload loads E (host, nload x d doubles) find x in E_N with
@@ -185,6 +192,53 @@ hom_status hom_profile_passes(hom_problem* pb, int32_t dual, int32_t nload, int3
 
 /* Release the handle (host memory only; the workspace stays with the caller). */
 void hom_destroy(hom_problem* pb);
+
+/* ---- Batched solves.  A batch groups n problems with identical hom_desc and
+ * max_loads that were set up on the same stream; every kernel launch of a CG
+ * iteration then covers all n problems (one grid slice per problem), and
+ * chunks of iterations are replayed from one captured HIP graph.  Each
+ * problem keeps its own CG scalars and stopping decision; converged problems
+ * skip their work.  The bounds are still computed per problem exactly as in
+ * hom_bounds. */
+typedef struct hom_batch hom_batch;
+
+/* Device workspace bytes for a batch of n problems (alignment 256). */
+hom_status hom_batch_workspace_bytes(int32_t n, size_t* bytes);
+
+/* pbs: host array of n handles (n >= 1), all with the same desc, max_loads
+ * and stream, else HOM_E_INVALID.  ws: device workspace of
+ * hom_batch_workspace_bytes(n) bytes, kept until hom_batch_destroy.  The
+ * problems must outlive the batch. */
+hom_status hom_batch_create(hom_problem* const* pbs, int32_t n, void* ws, size_t ws_bytes, hom_batch** out);
+
+/* Lockstep primal (dual = 0) or dual (dual = 1) solves of all problems for
+ * the same nload loads E (host, nload x d).  x0: NULL or host array of
+ * n * nload device pointers (entries may be NULL); x_out: host array of
+ * n * nload device pointers, problem-major; info: host array of n * nload.
+ * Same return convention as hom_solve_primal (worst status over the batch). */
+hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const double* E, const double* const* x0,
+                           double tol, int32_t maxit, double* const* x_out, hom_info* info);
+
+/* Bounds of every problem (as hom_bounds): primal, dual: host arrays of
+ * n * d device pointers (problem-major, unit loads e_1..e_d), either may be
+ * NULL; out: host array of n results. */
+hom_status hom_batch_bounds(hom_batch* b, const double* const* primal, const double* const* dual, hom_result* out);
+
+/* As hom_profile_passes, for the launch configuration of the batch (every
+ * launch covers all n problems). */
+hom_status hom_batch_profile_passes(hom_batch* b, int32_t dual, int32_t nload, int32_t reps, double* ms_out);
+
+/* Per-kernel timing of the CG iterations of later hom_batch_solve calls
+ * (measurement support): with on = 1 the iterations are launched directly
+ * (not from the captured graph, whose event records cannot be timed) with a
+ * HIP event recorded around every kernel on the problem stream, and the
+ * elapsed times are accumulated per pass type (same five types as
+ * hom_profile_passes).  Turning it on or off resets the accumulators. */
+hom_status hom_batch_set_timing(hom_batch* b, int32_t on);
+/* ms_sum[5]: accumulated milliseconds; launches[5]: number of launches. */
+hom_status hom_batch_get_timing(hom_batch* b, double* ms_sum, int64_t* launches);
+
+void hom_batch_destroy(hom_batch* b);
 
 #ifdef __cplusplus
 }

@@ -4,8 +4,8 @@ guaranteed upper-lower bounds on homogenized coefficients.
 The compute path is the HIP library libhom.so (include/hom.h); this package
 only marshals arguments and provides PyTorch-owned device memory and streams.
 """
-from .api import (Problem, coef_inclusions, coef_pixels, coef_from_cell, problem_from_cell, field_len,
+from .api import (Problem, Batch, coef_inclusions, coef_pixels, coef_from_cell, problem_from_cell, field_len,
                   workspace_bytes, spectrum_from_field, field_from_spectrum, HomError)
 
-__all__ = ["Problem", "coef_inclusions", "coef_pixels", "coef_from_cell", "problem_from_cell", "field_len",
+__all__ = ["Problem", "Batch", "coef_inclusions", "coef_pixels", "coef_from_cell", "problem_from_cell", "field_len",
            "workspace_bytes", "spectrum_from_field", "field_from_spectrum", "HomError"]

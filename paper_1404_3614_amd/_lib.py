@@ -39,6 +39,7 @@ EXPORTS = {
     "hom_workspace_bytes": (C.c_int32, [C.POINTER(Desc), C.c_int32, C.POINTER(C.c_size_t)]),
     "hom_setup": (C.c_int32, [C.POINTER(Desc), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                               C.c_void_p, C.POINTER(C.c_void_p)]),
+    "hom_update_coefficients": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "hom_solve_primal": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_void_p),
                                      C.c_double, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(Info)]),
     "hom_solve_dual": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_void_p),
@@ -52,6 +53,19 @@ EXPORTS = {
                                     C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p]),
     "hom_profile_passes": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "hom_destroy": (None, [C.c_void_p]),
+    "hom_batch_workspace_bytes": (C.c_int32, [C.c_int32, C.POINTER(C.c_size_t)]),
+    "hom_batch_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_size_t,
+                                     C.POINTER(C.c_void_p)]),
+    "hom_batch_solve": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_void_p), C.c_double, C.c_int32, C.POINTER(C.c_void_p),
+                                    C.POINTER(Info)]),
+    "hom_batch_bounds": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                     C.POINTER(Result)]),
+    "hom_batch_profile_passes": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                             C.POINTER(C.c_double)]),
+    "hom_batch_set_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "hom_batch_get_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "hom_batch_destroy": (None, [C.c_void_p]),
 }
 
 _lib = None

@@ -10,7 +10,7 @@ import torch
 
 from . import _lib as L
 
-__all__ = ["Problem", "coef_inclusions", "coef_pixels", "coef_from_cell", "problem_from_cell",
+__all__ = ["Problem", "Batch", "coef_inclusions", "coef_pixels", "coef_from_cell", "problem_from_cell",
            "field_len", "workspace_bytes", "spectrum_from_field", "HomError"]
 
 HomError = L.HomError
@@ -141,6 +141,7 @@ class Problem:
                            C.c_void_p(self.stream.cuda_stream), C.byref(h))
         L.check(st, "hom_setup")
         self.h = h
+        self._coef_refs = (Ahat, Bhat)   # the setup reads them asynchronously on self.stream
         self.flen = [field_len(d, self.N, 0, self.Y), field_len(d, self.N, 1, self.Y)]
 
     def __del__(self):
@@ -151,6 +152,13 @@ class Problem:
             except Exception:
                 pass
             self.h = None
+
+    def update_coefficients(self, Ahat, Bhat):
+        """New coefficient (same grid and layout) for this problem, keeping its workspace."""
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_update_coefficients(self.h, C.c_void_p(Ahat.data_ptr()), C.c_void_p(Bhat.data_ptr())),
+                "hom_update_coefficients")
+        self._coef_refs = (Ahat, Bhat)
 
     def new_field(self, dual=False):
         t = torch.zeros(self.flen[int(dual)], dtype=torch.complex128, device=_dev())
@@ -206,6 +214,94 @@ class Problem:
         b = self.bounds(xp, xd)
         b.update(info_primal=ip, info_dual=idl, fields_primal=xp, fields_dual=xd)
         return b
+
+
+def _result_dict(res, d):
+    g = lambda a: np.array(a[:d * d]).reshape(d, d)
+    return dict(A_up=g(res.A_up), B_up=g(res.B_up), A_low=g(res.A_low), A_mean=g(res.A_mean), D=g(res.D))
+
+
+class Batch:
+    """Problems of one size class (same d, N, Y, precision, ncoef, max_loads,
+    stream) solved in lockstep: each CG kernel launch covers all of them."""
+
+    def __init__(self, problems):
+        lib = L.load()
+        self.problems = list(problems)
+        n = len(self.problems)
+        p0 = self.problems[0]
+        self.d, self.N, self.stream = p0.d, p0.N, p0.stream
+        nb = C.c_size_t()
+        L.check(lib.hom_batch_workspace_bytes(n, C.byref(nb)), "hom_batch_workspace_bytes")
+        self.ws = torch.empty(nb.value + 256, dtype=torch.uint8, device=_dev())
+        ptr = self.ws.data_ptr() + ((-self.ws.data_ptr()) % 256)
+        hs = (C.c_void_p * n)(*[p.h.value for p in self.problems])
+        h = C.c_void_p()
+        L.check(lib.hom_batch_create(hs, n, C.c_void_p(ptr), nb.value, C.byref(h)), "hom_batch_create")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                L.load().hom_batch_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def solve(self, dual=False, E=None, x0=None, tol=1e-6, maxit=10000, out=None, allow_not_converged=False):
+        d, n = self.d, len(self.problems)
+        E = np.eye(d) if E is None else np.atleast_2d(np.asarray(E, float))
+        nl = E.shape[0]
+        fields = out if out is not None else [[p.new_field(dual) for _ in range(nl)] for p in self.problems]
+        flat = [f for fs in fields for f in fs]
+        infos = (L.Info * (n * nl))()
+        Ec = np.ascontiguousarray(E.reshape(-1))
+        self.stream.wait_stream(torch.cuda.current_stream())
+        x0p = _dptrs([t for ts in x0 for t in ts]) if x0 is not None else None
+        st = L.load().hom_batch_solve(self.h, int(dual), nl, Ec.ctypes.data_as(C.POINTER(C.c_double)), x0p,
+                                      float(tol), int(maxit), _dptrs(flat), infos)
+        L.check(st, "hom_batch_solve", allow_not_converged)
+        info = [[dict(iters=infos[i * nl + l].iters, status=infos[i * nl + l].status,
+                      rel_res_recur=infos[i * nl + l].rel_res_recur, rel_res_true=infos[i * nl + l].rel_res_true)
+                 for l in range(nl)] for i in range(n)]
+        return fields, info
+
+    def bounds(self, primal=None, dual=None):
+        n, d = len(self.problems), self.d
+        res = (L.Result * n)()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        pp = _dptrs([t for ts in primal for t in ts]) if primal is not None else None
+        dp = _dptrs([t for ts in dual for t in ts]) if dual is not None else None
+        L.check(L.load().hom_batch_bounds(self.h, pp, dp, res), "hom_batch_bounds")
+        return [_result_dict(res[i], d) for i in range(n)]
+
+    def set_timing(self, on=True):
+        L.check(L.load().hom_batch_set_timing(self.h, int(bool(on))), "hom_batch_set_timing")
+
+    def get_timing(self):
+        """Average milliseconds per launch of each pass over the timed solves, and launch counts."""
+        ms = (C.c_double * 5)()
+        cnt = (C.c_int64 * 5)()
+        L.check(L.load().hom_batch_get_timing(self.h, ms, cnt), "hom_batch_get_timing")
+        names = ["first", "mid_inv", "apply", "mid_fwd", "last"]
+        return {n: (ms[i] / cnt[i] if cnt[i] else 0.0) for i, n in enumerate(names)}, \
+            {n: int(cnt[i]) for i, n in enumerate(names)}
+
+    def profile_passes(self, dual=False, nload=None, reps=20):
+        ms = (C.c_double * 5)()
+        n = self.d if nload is None else nload
+        L.check(L.load().hom_batch_profile_passes(self.h, int(dual), int(n), int(reps), ms),
+                "hom_batch_profile_passes")
+        return dict(first=ms[0], mid_inv=ms[1], apply=ms[2], mid_fwd=ms[3], last=ms[4])
+
+    def solve_bounds(self, tol=1e-6, maxit=10000, allow_not_converged=False):
+        xp, ip = self.solve(False, tol=tol, maxit=maxit, allow_not_converged=allow_not_converged)
+        xd, idl = self.solve(True, tol=tol, maxit=maxit, allow_not_converged=allow_not_converged)
+        out = self.bounds(xp, xd)
+        for i, b in enumerate(out):
+            b.update(info_primal=ip[i], info_dual=idl[i])
+        return out
 
 
 def problem_from_cell(cell, N, precision="mixed", max_loads=None, stream=None):

@@ -274,6 +274,10 @@ Geo make_geo(const hom_problem* pb, int dual, int L, bool fp32, int P_override =
   g.Q = z.Q;
   g.nbF = z.Q;
   g.nbL = z.Q;
+  if (fp32) {
+    const int G = fast_row_pairs(z.M[2], g.P);
+    if (G > 0) g.nbF = g.nbL = (z.Q + G - 1) / G;
+  }
   const size_t cs = fp32 ? sizeof(Cx<float>) : sizeof(Cx<double>);
   const int npts = z.M[1] * z.M[2];
   g.tileA = choose_tileA(z.M[0], npts, g.P, cs, min_radix(pb->plan[0]));
@@ -302,27 +306,28 @@ Geo make_geo(const hom_problem* pb, int dual, int L, bool fp32, int P_override =
   } while (0)
 
 template <typename R>
-hipError_t enqueue_matvec_passes(const Geo& g, const UnitDev* u, int first_mode, int last_mode, int jstep,
+hipError_t enqueue_matvec_passes(const Geo& g, const UnitDev* u, int nu, int first_mode, int last_mode, int jstep,
                                  const int* iter_base, hipStream_t st) {
-  hipError_t e = launch_first<R>(g, u, 1, first_mode, jstep, iter_base, st);
+  const bool cg = first_mode == FIRST_CG;
+  hipError_t e = launch_first<R>(g, u, nu, first_mode, jstep, iter_base, st);
   if (e != hipSuccess) return e;
   if (g.d == 3) {
-    e = launch_mid<R>(g, u, 1, 1, st);
+    e = launch_mid<R>(g, u, nu, 1 | (cg ? MID_CG : 0), st);
     if (e != hipSuccess) return e;
   }
-  e = launch_apply<R>(g, u, 1, APPLY_COEF, st);
+  e = launch_apply<R>(g, u, nu, cg ? APPLY_COEF_CG : APPLY_COEF, st);
   if (e != hipSuccess) return e;
   if (g.d == 3) {
-    e = launch_mid<R>(g, u, 1, 0, st);
+    e = launch_mid<R>(g, u, nu, cg ? MID_CG : 0, st);
     if (e != hipSuccess) return e;
   }
-  return launch_last<R>(g, u, 1, last_mode, jstep, iter_base, st);
+  return launch_last<R>(g, u, nu, last_mode, jstep, iter_base, st);
 }
 
 hipError_t enqueue_passes(bool fp32, const Geo& g, const UnitDev* u, int fm, int lm, int j, const int* ib,
-                          hipStream_t st) {
-  return fp32 ? enqueue_matvec_passes<float>(g, u, fm, lm, j, ib, st)
-              : enqueue_matvec_passes<double>(g, u, fm, lm, j, ib, st);
+                          hipStream_t st, int nu = 1) {
+  return fp32 ? enqueue_matvec_passes<float>(g, u, nu, fm, lm, j, ib, st)
+              : enqueue_matvec_passes<double>(g, u, nu, fm, lm, j, ib, st);
 }
 
 void fill_unit(hom_problem* pb, int k, int L, const double* E, double* const* x, UnitDev* hu) {
@@ -347,9 +352,10 @@ void fill_unit(hom_problem* pb, int k, int L, const double* E, double* const* x,
   hu->sc = sb.sc;
 }
 
-hom_status solve_impl(hom_problem* pb, int k, int nload, const double* E, const double* const* x0, double tol,
-                      int maxit, double* const* x_out, hom_info* info) {
-  if (!pb || !E || !x_out || !info) return HOM_E_INVALID;
+// Validate loads and output pointers of one problem.
+hom_status check_solve_args(const hom_problem* pb, int nload, const double* E, double* const* x_out, double tol,
+                            int maxit) {
+  if (!pb || !E || !x_out) return HOM_E_INVALID;
   if (nload < 1 || nload > pb->max_loads) return HOM_E_INVALID;
   if (!(tol > 0.0) || maxit < 0) return HOM_E_INVALID;
   for (int l = 0; l < nload; ++l) {
@@ -361,50 +367,139 @@ hom_status solve_impl(hom_problem* pb, int k, int nload, const double* E, const 
     }
     if (e2 == 0.0) return HOM_E_INVALID;
   }
-  hipStream_t st = pb->stream;
-  const bool fp32 = pb->desc.precision == HOM_MIXED;
-  Geo g = make_geo(pb, k, nload, fp32);
-  SlotBufs& sb = pb->slot[k];
-  UnitDev* hu = &pb->host_unit[k];
-  fill_unit(pb, k, nload, E, x_out, hu);
-  HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));
+  return HOM_OK;
+}
 
-  bool have_x0 = false;
+// Copy/symmetrise initial guesses into the outputs of one problem; returns whether any was given.
+hom_status prepare_x0(hom_problem* pb, int k, int nload, const Geo& g, const double* const* x0,
+                      double* const* x_out, bool* have) {
+  hipStream_t st = pb->stream;
+  SlotBufs& sb = pb->slot[k];
+  *have = false;
   const size_t vbytes = (size_t)g.m * g.S * sizeof(Cx<double>);
   for (int l = 0; l < nload; ++l) {
     const double* src = x0 ? x0[l] : nullptr;
-    if (src) {
-      have_x0 = true;
-      const Cx<double>* s = reinterpret_cast<const Cx<double>*>(src);
-      if (src == x_out[l]) {
-        HIPCHK(hipMemcpyAsync(sb.tmp[l], src, vbytes, hipMemcpyDeviceToDevice, st));
-        s = sb.tmp[l];
-      }
-      HIPCHK(launch_symmetrize(g, s, reinterpret_cast<Cx<double>*>(x_out[l]), g.m, st));
+    if (!src) continue;
+    *have = true;
+    const Cx<double>* s = reinterpret_cast<const Cx<double>*>(src);
+    if (src == x_out[l]) {
+      HIPCHK(hipMemcpyAsync(sb.tmp[l], src, vbytes, hipMemcpyDeviceToDevice, st));
+      s = sb.tmp[l];
     }
+    HIPCHK(launch_symmetrize(g, s, reinterpret_cast<Cx<double>*>(x_out[l]), g.m, st));
   }
-  if (have_x0) {
-    for (int l = 0; l < nload; ++l)
-      if (!x0[l]) HIPCHK(hipMemsetAsync(x_out[l], 0, vbytes, st));
-  }
-  HIPCHK(launch_init_scal(g, sb.unit, 1, sb.iter_base, tol, maxit, st));
-  HIPCHK(launch_rhs(g, sb.unit, 1, st));
-  HIPCHK(launch_start_vectors(g, sb.unit, 1, have_x0 ? 1 : 0, st));
-  if (have_x0) HIPCHK(enqueue_passes(fp32, g, sb.unit, FIRST_FIELD, LAST_RESID, 0, nullptr, st));
+  return HOM_OK;
+}
 
-  const int chunk = std::max(1, pb->graph_chunk);
-  const bool use_graph = st != nullptr && env_int("HOM_NO_GRAPH", 0) == 0;
+hom_status zero_missing_x0(hom_problem* pb, int k, int nload, const Geo& g, const double* const* x0,
+                           double* const* x_out) {
+  const size_t vbytes = (size_t)g.m * g.S * sizeof(Cx<double>);
+  for (int l = 0; l < nload; ++l)
+    if (!x0 || !x0[l]) HIPCHK(hipMemsetAsync(x_out[l], 0, vbytes, pb->stream));
+  (void)k;
+  return HOM_OK;
+}
+
+// CG over n units in lockstep (one unit = one problem's coefficient with nload loads).
+struct SolveRun {
+  hipStream_t st;
+  Geo g;
+  bool fp32;
+  const UnitDev* units;       // device array of n units
+  int n;
+  int* iter_base;             // device
+  int* active;                // device
+  int* pinned_active;         // host, pinned
+  hipGraphExec_t* graph;      // cache slot
+  int chunk;
+  std::vector<const double*> part_d;   // per unit, device
+  std::vector<const CgScal*> sc;       // per unit, device
+  // optional per-kernel timing: events recorded around every launch of the chunk
+  std::vector<hipEvent_t>* events = nullptr;
+  double* tsum = nullptr;              // [5] accumulated ms per pass type
+  long long* tcnt = nullptr;           // [5] launches per pass type
+};
+
+// Pass types in launch order within one operator application.
+static int pass_types(int d, int* types) {
+  int n = 0;
+  types[n++] = 0;
+  if (d == 3) types[n++] = 1;
+  types[n++] = 2;
+  if (d == 3) types[n++] = 3;
+  types[n++] = 4;
+  return n;
+}
+
+// One CG iteration with every kernel timed by its own start/stop event pair
+// (hipExtLaunchKernelGGL); ev holds 2 events per pass.
+template <typename R>
+static hipError_t enqueue_timed_passes(const Geo& g, const UnitDev* u, int nu, int jstep, const int* iter_base,
+                                       hipStream_t st, hipEvent_t* ev) {
+  int k = 0;
+  auto arm = [&]() {
+    g_ext_timing.on = true;
+    g_ext_timing.start = ev[2 * k];
+    g_ext_timing.stop = ev[2 * k + 1];
+    ++k;
+  };
+  hipError_t e;
+  arm();
+  e = launch_first<R>(g, u, nu, FIRST_CG, jstep, iter_base, st);
+  if (e == hipSuccess && g.d == 3) {
+    arm();
+    e = launch_mid<R>(g, u, nu, 1 | MID_CG, st);
+  }
+  if (e == hipSuccess) {
+    arm();
+    e = launch_apply<R>(g, u, nu, APPLY_COEF_CG, st);
+  }
+  if (e == hipSuccess && g.d == 3) {
+    arm();
+    e = launch_mid<R>(g, u, nu, MID_CG, st);
+  }
+  if (e == hipSuccess) {
+    arm();
+    e = launch_last<R>(g, u, nu, LAST_CG, jstep, iter_base, st);
+  }
+  g_ext_timing.on = false;
+  return e;
+}
+
+hom_status solve_units(SolveRun& R, int nload, double tol, int maxit, bool have_x0, hom_info* info) {
+  hipStream_t st = R.st;
+  const Geo& g = R.g;
+  HIPCHK(launch_init_scal(g, R.units, R.n, R.iter_base, tol, maxit, st));
+  HIPCHK(launch_rhs(g, R.units, R.n, st));
+  HIPCHK(launch_start_vectors(g, R.units, R.n, have_x0 ? 1 : 0, st));
+  if (have_x0) HIPCHK(enqueue_passes(R.fp32, g, R.units, FIRST_FIELD, LAST_RESID, 0, nullptr, st, R.n));
+  const int chunk = std::max(1, R.chunk);
+  // events recorded inside a captured graph cannot be timed, so timing runs launch directly
+  const bool use_graph = st != nullptr && env_int("HOM_NO_GRAPH", 0) == 0 && R.events == nullptr;
+  int types[5];
+  const int npass = pass_types(g.d, types);
+  const bool timing = R.events != nullptr;
+  if (timing && R.events->empty()) {
+    R.events->resize((size_t)chunk * 2 * npass);
+    for (auto& ev : *R.events) HIPCHK(hipEventCreate(&ev));
+  }
   auto enqueue_chunk = [&]() -> hipError_t {
     for (int j = 0; j < chunk; ++j) {
-      hipError_t e = enqueue_passes(fp32, g, sb.unit, FIRST_CG, LAST_CG, j, sb.iter_base, st);
+      hipError_t e;
+      if (timing) {
+        hipEvent_t* ev = R.events->data() + (size_t)j * 2 * npass;
+        e = R.fp32 ? enqueue_timed_passes<float>(g, R.units, R.n, j, R.iter_base, st, ev)
+                   : enqueue_timed_passes<double>(g, R.units, R.n, j, R.iter_base, st, ev);
+      } else {
+        e = enqueue_passes(R.fp32, g, R.units, FIRST_CG, LAST_CG, j, R.iter_base, st, R.n);
+      }
       if (e != hipSuccess) return e;
     }
-    hipError_t e = launch_advance(g, sb.unit, 1, sb.iter_base, chunk, sb.active, st);
+    hipError_t e = launch_advance(g, R.units, R.n, R.iter_base, chunk, R.active, st);
     if (e != hipSuccess) return e;
-    return hipMemcpyAsync(pb->pinned_active, sb.active, sizeof(int), hipMemcpyDeviceToHost, st);
+    return hipMemcpyAsync(R.pinned_active, R.active, sizeof(int), hipMemcpyDeviceToHost, st);
   };
-  hipGraphExec_t& gx = pb->graph[k][nload];
+  hipGraphExec_t& gx = *R.graph;
   if (use_graph && !gx) {
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -421,37 +516,89 @@ hom_status solve_impl(hom_problem* pb, int k, int nload, const double* E, const 
     else
       HIPCHK(enqueue_chunk());
     HIPCHK(hipStreamSynchronize(st));
+    if (timing) {
+      for (int j = 0; j < chunk; ++j) {
+        hipEvent_t* ev = R.events->data() + (size_t)j * 2 * npass;
+        for (int p = 0; p < npass; ++p) {
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]));
+          R.tsum[types[p]] += ms;
+          R.tcnt[types[p]] += 1;
+        }
+      }
+    }
     done_iters += chunk;
-    if (*pb->pinned_active == 0) break;
+    if (*R.pinned_active == 0) break;
     if (done_iters > maxit + chunk) break;
   }
-  // true residual b - C x of the returned iterate, in the precision mode of the solve
-  HIPCHK(enqueue_passes(fp32, g, sb.unit, FIRST_FIELD, LAST_RESID, 0, nullptr, st));
-  std::vector<double> part((size_t)nload * g.Q);
-  std::vector<CgScal> sc(nload);
-  HIPCHK(hipMemcpyAsync(part.data(), sb.part_d, part.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(sc.data(), sb.sc, nload * sizeof(CgScal), hipMemcpyDeviceToHost, st));
+  // true residual b - C x of the returned iterates, in the precision mode of the solve
+  HIPCHK(enqueue_passes(R.fp32, g, R.units, FIRST_FIELD, LAST_RESID, 0, nullptr, st, R.n));
+  std::vector<double> part((size_t)R.n * nload * g.Q);
+  std::vector<CgScal> sc((size_t)R.n * nload);
+  for (int u = 0; u < R.n; ++u) {
+    HIPCHK(hipMemcpyAsync(part.data() + (size_t)u * nload * g.Q, R.part_d[u], (size_t)nload * g.Q * sizeof(double),
+                          hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(sc.data() + (size_t)u * nload, R.sc[u], nload * sizeof(CgScal), hipMemcpyDeviceToHost, st));
+  }
   HIPCHK(hipStreamSynchronize(st));
   hom_status worst = HOM_OK;
-  for (int l = 0; l < nload; ++l) {
-    double s = 0.0;
-    for (int q = 0; q < g.Q; ++q) s += part[(size_t)l * g.Q + q];
-    hom_info& in = info[l];
-    in.iters = sc[l].iters;
-    in.rel_res_recur = std::sqrt(std::max(sc[l].gamma_last, 0.0)) / sc[l].normE;
-    in.rel_res_true = std::sqrt(std::max(s, 0.0)) / sc[l].normE;
-    int stt = sc[l].status;
-    hom_status h;
-    if (stt == 1) h = HOM_OK;
-    else if (stt == 2 || stt == 0) h = HOM_NOT_CONVERGED;
-    else if (stt == -3) h = HOM_E_NOT_SPD;
-    else h = HOM_E_INVALID;
-    if (stt == 0) in.iters = maxit;
-    in.status = h;
-    if (h < 0 && (worst >= 0 || h < worst)) worst = h;
-    else if (h == HOM_NOT_CONVERGED && worst == HOM_OK) worst = h;
-  }
+  for (int u = 0; u < R.n; ++u)
+    for (int l = 0; l < nload; ++l) {
+      const size_t ul = (size_t)u * nload + l;
+      double s = 0.0;
+      for (int q = 0; q < g.Q; ++q) s += part[ul * g.Q + q];
+      hom_info& in = info[ul];
+      in.iters = sc[ul].iters;
+      in.rel_res_recur = std::sqrt(std::max(sc[ul].gamma_last, 0.0)) / sc[ul].normE;
+      in.rel_res_true = std::sqrt(std::max(s, 0.0)) / sc[ul].normE;
+      const int stt = sc[ul].status;
+      hom_status h;
+      if (stt == 1) h = HOM_OK;
+      else if (stt == 2 || stt == 0) h = HOM_NOT_CONVERGED;
+      else if (stt == -3) h = HOM_E_NOT_SPD;
+      else h = HOM_E_INVALID;
+      if (stt == 0) in.iters = maxit;
+      in.status = h;
+      if (h < 0 && (worst >= 0 || h < worst)) worst = h;
+      else if (h == HOM_NOT_CONVERGED && worst == HOM_OK) worst = h;
+    }
   return worst;
+}
+
+hom_status solve_impl(hom_problem* pb, int k, int nload, const double* E, const double* const* x0, double tol,
+                      int maxit, double* const* x_out, hom_info* info) {
+  hom_status s = check_solve_args(pb, nload, E, x_out, tol, maxit);
+  if (s != HOM_OK) return s;
+  if (!info) return HOM_E_INVALID;
+  hipStream_t st = pb->stream;
+  const bool fp32 = pb->desc.precision == HOM_MIXED;
+  Geo g = make_geo(pb, k, nload, fp32);
+  SlotBufs& sb = pb->slot[k];
+  UnitDev* hu = &pb->host_unit[k];
+  fill_unit(pb, k, nload, E, x_out, hu);
+  HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  bool have_x0 = false;
+  s = prepare_x0(pb, k, nload, g, x0, x_out, &have_x0);
+  if (s != HOM_OK) return s;
+  if (have_x0) {
+    s = zero_missing_x0(pb, k, nload, g, x0, x_out);
+    if (s != HOM_OK) return s;
+  }
+  SolveRun R;
+  R.st = st;
+  R.g = g;
+  R.fp32 = fp32;
+  R.units = sb.unit;
+  R.n = 1;
+  R.iter_base = sb.iter_base;
+  R.active = sb.active;
+  R.pinned_active = pb->pinned_active;
+  R.graph = &pb->graph[k][nload];
+  R.chunk = pb->graph_chunk;
+  R.part_d.push_back(sb.part_d);
+  R.sc.push_back(sb.sc);
+  return solve_units(R, nload, tol, maxit, have_x0, info);
 }
 
 void inv_small(int d, const double* A, double* X) {
@@ -474,6 +621,21 @@ void inv_small(int d, const double* A, double* X) {
     X[6] = C02 / det;
     X[7] = -(a * h - b * g) / det;
     X[8] = (a * e - b * dd) / det;
+  }
+}
+
+void fill_result(int d, const double Ebar[2][9], const bool have[2], hom_result* out) {
+  std::memset(out, 0, sizeof(*out));
+  for (int i = 0; i < 9; ++i)
+    out->A_up[i] = out->B_up[i] = out->A_low[i] = out->A_mean[i] = out->D[i] = (i < d * d) ? NAN : 0.0;
+  for (int i = 0; i < d * d; ++i) {
+    out->A_up[i] = Ebar[0][i];
+    out->B_up[i] = Ebar[1][i];
+  }
+  if (have[1]) inv_small(d, Ebar[1], out->A_low);
+  for (int i = 0; i < d * d; ++i) {
+    out->A_mean[i] = 0.5 * (out->A_up[i] + out->A_low[i]);
+    out->D[i] = 0.5 * (out->A_up[i] - out->A_low[i]);
   }
 }
 
@@ -505,6 +667,26 @@ void twiddles(int M, std::vector<Cx<double>>& t64, std::vector<Cx<float>>& t32) 
     t32[t].x = (float)t64[t].x;
     t32[t].y = (float)t64[t].y;
   }
+}
+
+// Coefficient on the doubled grid, A_M(x^k) = sum_n omega^{kn} A_hat(n) (eq. MBA_GA), in FP64 on the
+// device, its FP32 copy, and the Z_N part of A_hat; stream-ordered, no host synchronisation.
+hom_status setup_coefficients(hom_problem* pb, const void* Ahat, const void* Bhat) {
+  const Sizes& z = pb->z;
+  hipStream_t st = pb->stream;
+  Geo g = make_geo(pb, 0, 1, false);
+  const int nc = z.nc;
+  for (int k = 0; k < 2; ++k) {
+    const void* src = k == 0 ? Ahat : Bhat;
+    HIPCHK(hipMemcpyAsync(pb->scratch, src, nc * z.Mt * sizeof(Cx<double>), hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_extract_half(g, pb->scratch, pb->ahat_half[k], nc, st));
+    HIPCHK(launch_line_fft<double>(pb->scratch, nc, z.M[0], z.M[1] * z.M[2], pb->plan[0], pb->tw64[0], 1, st));
+    if (z.M[1] > 1)
+      HIPCHK(launch_line_fft<double>(pb->scratch, nc * z.M[0], z.M[1], z.M[2], pb->plan[1], pb->tw64[1], 1, st));
+    HIPCHK(launch_line_fft<double>(pb->scratch, nc * z.M[0] * z.M[1], z.M[2], 1, pb->plan[2], pb->tw64[2], 1, st));
+    HIPCHK(launch_coef_real(pb->scratch, pb->coef64[k], pb->coef32[k], (long)(nc * z.Mt), st));
+  }
+  return HOM_OK;
 }
 
 }  // namespace
@@ -573,43 +755,26 @@ hom_status hom_setup(const hom_desc* desc, int32_t max_loads, const void* Ahat, 
     return HOM_E_DEVICE;
   }
   hipStream_t st = pb->stream;
-  std::vector<Cx<double>> t64[3];
-  std::vector<Cx<float>> t32[3];
-  hom_status rc = HOM_OK;
-  auto fail = [&](hom_status e) {
+  for (int a = 0; a < 3; ++a)
+    if (launch_twiddles(pb->tw64[a], pb->tw32[a], z.M[a], st) != hipSuccess) {
+      (void)hipHostFree(pb->pinned_active);
+      delete pb;
+      return HOM_E_DEVICE;
+    }
+  hom_status rc = setup_coefficients(pb, Ahat, Bhat);
+  if (rc != HOM_OK) {
     (void)hipStreamSynchronize(st);
     (void)hipHostFree(pb->pinned_active);
     delete pb;
-    return e;
-  };
-  for (int a = 0; a < 3; ++a) {
-    twiddles(z.M[a], t64[a], t32[a]);
-    if (hipMemcpyAsync(pb->tw64[a], t64[a].data(), z.M[a] * sizeof(Cx<double>), hipMemcpyHostToDevice, st) !=
-            hipSuccess ||
-        hipMemcpyAsync(pb->tw32[a], t32[a].data(), z.M[a] * sizeof(Cx<float>), hipMemcpyHostToDevice, st) !=
-            hipSuccess)
-      return fail(HOM_E_DEVICE);
+    return rc;
   }
-  // coefficient on the doubled grid: A_M(x^k) = sum_n omega^{kn} A_hat(n) (eq. MBA_GA), FP64
-  Geo g = make_geo(pb, 0, 1, false);
-  const int nc = z.nc;
-  for (int k = 0; k < 2; ++k) {
-    const void* src = k == 0 ? Ahat : Bhat;
-    if (hipMemcpyAsync(pb->scratch, src, nc * z.Mt * sizeof(Cx<double>), hipMemcpyDeviceToDevice, st) != hipSuccess)
-      return fail(HOM_E_DEVICE);
-    if (launch_extract_half(g, pb->scratch, pb->ahat_half[k], nc, st) != hipSuccess) return fail(HOM_E_DEVICE);
-    hipError_t e = launch_line_fft<double>(pb->scratch, nc, z.M[0], z.M[1] * z.M[2], pl[0], pb->tw64[0], 1, st);
-    if (e == hipSuccess && z.M[1] > 1)
-      e = launch_line_fft<double>(pb->scratch, nc * z.M[0], z.M[1], z.M[2], pl[1], pb->tw64[1], 1, st);
-    if (e == hipSuccess)
-      e = launch_line_fft<double>(pb->scratch, nc * z.M[0] * z.M[1], z.M[2], 1, pl[2], pb->tw64[2], 1, st);
-    if (e == hipSuccess) e = launch_coef_real(pb->scratch, pb->coef64[k], pb->coef32[k], (long)(nc * z.Mt), st);
-    if (e != hipSuccess) return fail(HOM_E_DEVICE);
-  }
-  if (hipStreamSynchronize(st) != hipSuccess) return fail(HOM_E_DEVICE);
-  (void)rc;
   *out = pb;
   return HOM_OK;
+}
+
+hom_status hom_update_coefficients(hom_problem* pb, const void* Ahat, const void* Bhat) {
+  if (!pb || !Ahat || !Bhat) return HOM_E_INVALID;
+  return setup_coefficients(pb, Ahat, Bhat);
 }
 
 hom_status hom_solve_primal(hom_problem* pb, int32_t nload, const double* E, const double* const* x0, double tol,
@@ -688,19 +853,7 @@ hom_status hom_bounds(hom_problem* pb, const double* const* primal, const double
         Ebar[k][a * d + b] = s * g[k].invM;
       }
   }
-  std::memset(out, 0, sizeof(*out));
-  for (int i = 0; i < 9; ++i) {
-    out->A_up[i] = out->B_up[i] = out->A_low[i] = out->A_mean[i] = out->D[i] = (i < d * d) ? NAN : 0.0;
-  }
-  for (int i = 0; i < d * d; ++i) {
-    out->A_up[i] = Ebar[0][i];
-    out->B_up[i] = Ebar[1][i];
-  }
-  if (have[1]) inv_small(d, Ebar[1], out->A_low);
-  for (int i = 0; i < d * d; ++i) {
-    out->A_mean[i] = 0.5 * (out->A_up[i] + out->A_low[i]);
-    out->D[i] = 0.5 * (out->A_up[i] - out->A_low[i]);
-  }
+  fill_result(d, Ebar, have, out);
   return HOM_OK;
 }
 
@@ -840,45 +993,34 @@ hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t
   return e == hipSuccess ? HOM_OK : HOM_E_DEVICE;
 }
 
-hom_status hom_profile_passes(hom_problem* pb, int32_t dual, int32_t nload, int32_t reps, double* ms_out) {
-  if (!pb || !ms_out || (dual != 0 && dual != 1) || nload < 1 || nload > pb->max_loads || reps < 1)
-    return HOM_E_INVALID;
-  const int k = dual;
-  hipStream_t st = pb->stream;
-  const bool fp32 = pb->desc.precision == HOM_MIXED;
-  Geo g = make_geo(pb, k, nload, fp32);
-  SlotBufs& sb = pb->slot[k];
-  UnitDev* hu = &pb->host_unit[k];
-  fill_unit(pb, k, nload, nullptr, nullptr, hu);
-  for (int l = 0; l < nload; ++l) hu->s[l] = sb.p[l];  // matvec output goes to scratch
-  HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
-  const size_t vbytes = (size_t)g.m * g.S * sizeof(Cx<double>);
-  for (int l = 0; l < nload; ++l) HIPCHK(hipMemsetAsync(sb.tmp[l], 0, vbytes, st));
+// Average per-launch time of each operator pass over n units (HIP events on the stream).
+static hom_status profile_units(const Geo& g, const UnitDev* units, int n, bool fp32, hipStream_t st, int reps,
+                                double* ms_out) {
   hipEvent_t ev[6];
   for (int i = 0; i < 6; ++i) HIPCHK(hipEventCreate(&ev[i]));
   hom_status rc = HOM_OK;
   auto run = [&](int which) -> hipError_t {
     for (int r = 0; r < reps; ++r) {
       hipError_t e = hipSuccess;
-      if (which == 0) e = fp32 ? launch_first<float>(g, sb.unit, 1, FIRST_FIELD, 0, nullptr, st)
-                               : launch_first<double>(g, sb.unit, 1, FIRST_FIELD, 0, nullptr, st);
-      if (which == 1 && g.d == 3) e = fp32 ? launch_mid<float>(g, sb.unit, 1, 1, st) : launch_mid<double>(g, sb.unit, 1, 1, st);
-      if (which == 2) e = fp32 ? launch_apply<float>(g, sb.unit, 1, APPLY_COEF, st)
-                               : launch_apply<double>(g, sb.unit, 1, APPLY_COEF, st);
-      if (which == 3 && g.d == 3) e = fp32 ? launch_mid<float>(g, sb.unit, 1, 0, st) : launch_mid<double>(g, sb.unit, 1, 0, st);
-      if (which == 4) e = fp32 ? launch_last<float>(g, sb.unit, 1, LAST_MATVEC, 0, nullptr, st)
-                               : launch_last<double>(g, sb.unit, 1, LAST_MATVEC, 0, nullptr, st);
+      if (which == 0)
+        e = fp32 ? launch_first<float>(g, units, n, FIRST_FIELD, 0, nullptr, st)
+                 : launch_first<double>(g, units, n, FIRST_FIELD, 0, nullptr, st);
+      if (which == 1 && g.d == 3) e = fp32 ? launch_mid<float>(g, units, n, 1, st) : launch_mid<double>(g, units, n, 1, st);
+      if (which == 2)
+        e = fp32 ? launch_apply<float>(g, units, n, APPLY_COEF, st) : launch_apply<double>(g, units, n, APPLY_COEF, st);
+      if (which == 3 && g.d == 3) e = fp32 ? launch_mid<float>(g, units, n, 0, st) : launch_mid<double>(g, units, n, 0, st);
+      if (which == 4)
+        e = fp32 ? launch_last<float>(g, units, n, LAST_MATVEC, 0, nullptr, st)
+                 : launch_last<double>(g, units, n, LAST_MATVEC, 0, nullptr, st);
       if (e != hipSuccess) return e;
     }
     return hipSuccess;
   };
-  // one untimed round so that first-launch costs are excluded
   for (int w = 0; w < 5 && rc == HOM_OK; ++w)
-    if (run(w) != hipSuccess) rc = HOM_E_DEVICE;
-  for (int w = 0; w < 5 && rc == HOM_OK; ++w) {
+    if (run(w) != hipSuccess) rc = HOM_E_DEVICE;  // untimed round: first-launch costs excluded
+  for (int w = 0; w < 5 && rc == HOM_OK; ++w)
     if (hipEventRecord(ev[w], st) != hipSuccess || run(w) != hipSuccess || hipEventRecord(ev[w + 1], st) != hipSuccess)
       rc = HOM_E_DEVICE;
-  }
   if (rc == HOM_OK && hipEventSynchronize(ev[5]) != hipSuccess) rc = HOM_E_DEVICE;
   for (int w = 0; w < 5 && rc == HOM_OK; ++w) {
     float ms = 0.f;
@@ -888,6 +1030,266 @@ hom_status hom_profile_passes(hom_problem* pb, int32_t dual, int32_t nload, int3
   }
   for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
   return rc;
+}
+
+// Point a unit at scratch vectors for a timing run (input tmp = 0, output p).
+static hom_status profile_unit_setup(hom_problem* pb, int k, int nload, const Geo& g, UnitDev* hu) {
+  SlotBufs& sb = pb->slot[k];
+  fill_unit(pb, k, nload, nullptr, nullptr, hu);
+  for (int l = 0; l < nload; ++l) hu->s[l] = sb.p[l];
+  const size_t vbytes = (size_t)g.m * g.S * sizeof(Cx<double>);
+  for (int l = 0; l < nload; ++l) HIPCHK(hipMemsetAsync(sb.tmp[l], 0, vbytes, pb->stream));
+  return HOM_OK;
+}
+
+hom_status hom_profile_passes(hom_problem* pb, int32_t dual, int32_t nload, int32_t reps, double* ms_out) {
+  if (!pb || !ms_out || (dual != 0 && dual != 1) || nload < 1 || nload > pb->max_loads || reps < 1)
+    return HOM_E_INVALID;
+  const int k = dual;
+  hipStream_t st = pb->stream;
+  const bool fp32 = pb->desc.precision == HOM_MIXED;
+  Geo g = make_geo(pb, k, nload, fp32);
+  SlotBufs& sb = pb->slot[k];
+  UnitDev* hu = &pb->host_unit[k];
+  hom_status s = profile_unit_setup(pb, k, nload, g, hu);
+  if (s != HOM_OK) return s;
+  HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
+  return profile_units(g, sb.unit, 1, fp32, st, reps, ms_out);
+}
+
+struct hom_batch {
+  int n;
+  std::vector<hom_problem*> pbs;
+  hipStream_t stream;
+  UnitDev* units[2];
+  UnitDev* bunits[2];
+  int* iter_base[2];
+  int* active[2];
+  std::vector<UnitDev> host_units[2];
+  std::vector<UnitDev> host_bunits[2];
+  hipGraphExec_t graph[2][kMaxLoads + 1];
+  hipGraphExec_t tgraph[2][kMaxLoads + 1];      // variants with event records
+  std::vector<hipEvent_t> tevents[2][kMaxLoads + 1];
+  int timing = 0;
+  double tsum[5] = {0, 0, 0, 0, 0};
+  long long tcnt[5] = {0, 0, 0, 0, 0};
+};
+
+static size_t batch_layout(int n, char* base, hom_batch* b) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> char* {
+    char* p = base ? base + off : nullptr;
+    off = up(off + bytes);
+    return p;
+  };
+  for (int k = 0; k < 2; ++k) {
+    char* u = take((size_t)n * sizeof(UnitDev));
+    char* bu = take((size_t)n * sizeof(UnitDev));
+    char* ib = take(sizeof(int));
+    char* ac = take(sizeof(int));
+    if (b) {
+      b->units[k] = (UnitDev*)u;
+      b->bunits[k] = (UnitDev*)bu;
+      b->iter_base[k] = (int*)ib;
+      b->active[k] = (int*)ac;
+    }
+  }
+  return off;
+}
+
+hom_status hom_batch_workspace_bytes(int32_t n, size_t* bytes) {
+  if (n < 1 || !bytes) return HOM_E_INVALID;
+  *bytes = batch_layout(n, nullptr, nullptr);
+  return HOM_OK;
+}
+
+hom_status hom_batch_create(hom_problem* const* pbs, int32_t n, void* ws, size_t ws_bytes, hom_batch** out) {
+  if (!pbs || n < 1 || !ws || !out) return HOM_E_INVALID;
+  if (((uintptr_t)ws) % kAlign) return HOM_E_WORKSPACE;
+  if (ws_bytes < batch_layout(n, nullptr, nullptr)) return HOM_E_WORKSPACE;
+  for (int i = 0; i < n; ++i) {
+    if (!pbs[i]) return HOM_E_INVALID;
+    const hom_desc& a = pbs[0]->desc;
+    const hom_desc& c = pbs[i]->desc;
+    if (std::memcmp(&a, &c, sizeof(hom_desc)) != 0 || pbs[i]->max_loads != pbs[0]->max_loads ||
+        pbs[i]->stream != pbs[0]->stream)
+      return HOM_E_INVALID;
+  }
+  hom_batch* b = new hom_batch();
+  b->n = n;
+  b->pbs.assign(pbs, pbs + n);
+  b->stream = pbs[0]->stream;
+  std::memset(b->graph, 0, sizeof(b->graph));
+  std::memset(b->tgraph, 0, sizeof(b->tgraph));
+  batch_layout(n, (char*)ws, b);
+  for (int k = 0; k < 2; ++k) {
+    b->host_units[k].resize(n);
+    b->host_bunits[k].resize(n);
+  }
+  *out = b;
+  return HOM_OK;
+}
+
+hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const double* E, const double* const* x0,
+                           double tol, int32_t maxit, double* const* x_out, hom_info* info) {
+  if (!b || !info || (dual != 0 && dual != 1)) return HOM_E_INVALID;
+  const int k = dual, n = b->n;
+  for (int i = 0; i < n; ++i) {
+    hom_status s = check_solve_args(b->pbs[i], nload, E, x_out + (size_t)i * nload, tol, maxit);
+    if (s != HOM_OK) return s;
+  }
+  hom_problem* p0 = b->pbs[0];
+  hipStream_t st = b->stream;
+  const bool fp32 = p0->desc.precision == HOM_MIXED;
+  Geo g = make_geo(p0, k, nload, fp32);
+  bool have_x0 = false;
+  for (int i = 0; i < n; ++i) {
+    fill_unit(b->pbs[i], k, nload, E, x_out + (size_t)i * nload, &b->host_units[k][i]);
+    if (x0) {
+      bool h = false;
+      hom_status s = prepare_x0(b->pbs[i], k, nload, g, x0 + (size_t)i * nload, x_out + (size_t)i * nload, &h);
+      if (s != HOM_OK) return s;
+      have_x0 = have_x0 || h;
+    }
+  }
+  if (have_x0)
+    for (int i = 0; i < n; ++i) {
+      hom_status s = zero_missing_x0(b->pbs[i], k, nload, g, x0 + (size_t)i * nload, x_out + (size_t)i * nload);
+      if (s != HOM_OK) return s;
+    }
+  HIPCHK(hipMemcpyAsync(b->units[k], b->host_units[k].data(), (size_t)n * sizeof(UnitDev), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  SolveRun R;
+  R.st = st;
+  R.g = g;
+  R.fp32 = fp32;
+  R.units = b->units[k];
+  R.n = n;
+  R.iter_base = b->iter_base[k];
+  R.active = b->active[k];
+  R.pinned_active = p0->pinned_active;
+  R.graph = &b->graph[k][nload];
+  R.chunk = p0->graph_chunk;
+  if (b->timing) {
+    R.events = &b->tevents[k][nload];
+    R.tsum = b->tsum;
+    R.tcnt = b->tcnt;
+  }
+  for (int i = 0; i < n; ++i) {
+    R.part_d.push_back(b->pbs[i]->slot[k].part_d);
+    R.sc.push_back(b->pbs[i]->slot[k].sc);
+  }
+  return solve_units(R, nload, tol, maxit, have_x0, info);
+}
+
+hom_status hom_batch_bounds(hom_batch* b, const double* const* primal, const double* const* dual, hom_result* out) {
+  if (!b || !out) return HOM_E_INVALID;
+  const int n = b->n;
+  hom_problem* p0 = b->pbs[0];
+  const int d = p0->desc.d;
+  for (int k = 0; k < 2; ++k) {
+    const double* const* f = k == 0 ? primal : dual;
+    if (f)
+      for (int i = 0; i < n * d; ++i)
+        if (!f[i]) return HOM_E_INVALID;
+  }
+  hipStream_t st = b->stream;
+  const int P = packs(d, d);
+  bool have[2] = {primal != nullptr, dual != nullptr};
+  std::vector<double> part[2];
+  Geo g[2];
+  for (int k = 0; k < 2; ++k) {
+    if (!have[k]) continue;
+    const double* const* f = k == 0 ? primal : dual;
+    g[k] = make_geo(p0, k, d, false, P);
+    for (int i = 0; i < n; ++i) {
+      hom_problem* pb = b->pbs[i];
+      UnitDev* hu = &b->host_bunits[k][i];
+      std::memset(hu, 0, sizeof(*hu));
+      hu->coef = pb->coef64[k];
+      hu->ahat = pb->ahat_half[k];
+      for (int l = 0; l < d; ++l) {
+        hu->x[l] = reinterpret_cast<Cx<double>*>(const_cast<double*>(f[(size_t)i * d + l]));
+        hu->E[l][l] = 1.0;
+      }
+      hu->bufA = pb->bbufA;
+      hu->bufB = pb->bbufB;
+      hu->part_q = pb->bpart_q[k];
+    }
+    HIPCHK(hipMemcpyAsync(b->bunits[k], b->host_bunits[k].data(), (size_t)n * sizeof(UnitDev), hipMemcpyHostToDevice,
+                          st));
+    HIPCHK(launch_first<double>(g[k], b->bunits[k], n, FIRST_BOUNDS, 0, nullptr, st));
+    if (d == 3) HIPCHK(launch_mid<double>(g[k], b->bunits[k], n, 1, st));
+    HIPCHK(launch_apply<double>(g[k], b->bunits[k], n, APPLY_QUAD, st));
+    const size_t per = (size_t)g[k].nbA * 9;
+    part[k].resize(per * n);
+    for (int i = 0; i < n; ++i)
+      HIPCHK(hipMemcpyAsync(part[k].data() + per * i, b->pbs[i]->bpart_q[k], per * sizeof(double),
+                            hipMemcpyDeviceToHost, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  for (int i = 0; i < n; ++i) {
+    double Ebar[2][9];
+    for (int k = 0; k < 2; ++k) {
+      for (int j = 0; j < 9; ++j) Ebar[k][j] = NAN;
+      if (!have[k]) continue;
+      const size_t per = (size_t)g[k].nbA * 9;
+      for (int a = 0; a < d; ++a)
+        for (int c = 0; c < d; ++c) {
+          double s = 0.0;
+          for (int q = 0; q < g[k].nbA; ++q) s += part[k][per * i + (size_t)q * 9 + a * kMaxLoads + c];
+          Ebar[k][a * d + c] = s * g[k].invM;
+        }
+    }
+    fill_result(d, Ebar, have, &out[i]);
+  }
+  return HOM_OK;
+}
+
+hom_status hom_batch_profile_passes(hom_batch* b, int32_t dual, int32_t nload, int32_t reps, double* ms_out) {
+  if (!b || !ms_out || (dual != 0 && dual != 1) || reps < 1) return HOM_E_INVALID;
+  hom_problem* p0 = b->pbs[0];
+  if (nload < 1 || nload > p0->max_loads) return HOM_E_INVALID;
+  const int k = dual, n = b->n;
+  const bool fp32 = p0->desc.precision == HOM_MIXED;
+  Geo g = make_geo(p0, k, nload, fp32);
+  for (int i = 0; i < n; ++i) {
+    hom_status s = profile_unit_setup(b->pbs[i], k, nload, g, &b->host_units[k][i]);
+    if (s != HOM_OK) return s;
+  }
+  HIPCHK(hipMemcpyAsync(b->units[k], b->host_units[k].data(), (size_t)n * sizeof(UnitDev), hipMemcpyHostToDevice,
+                        b->stream));
+  return profile_units(g, b->units[k], n, fp32, b->stream, reps, ms_out);
+}
+
+hom_status hom_batch_set_timing(hom_batch* b, int32_t on) {
+  if (!b) return HOM_E_INVALID;
+  b->timing = on ? 1 : 0;
+  for (int i = 0; i < 5; ++i) {
+    b->tsum[i] = 0.0;
+    b->tcnt[i] = 0;
+  }
+  return HOM_OK;
+}
+
+hom_status hom_batch_get_timing(hom_batch* b, double* ms_sum, int64_t* launches) {
+  if (!b || !ms_sum || !launches) return HOM_E_INVALID;
+  for (int i = 0; i < 5; ++i) {
+    ms_sum[i] = b->tsum[i];
+    launches[i] = b->tcnt[i];
+  }
+  return HOM_OK;
+}
+
+void hom_batch_destroy(hom_batch* b) {
+  if (!b) return;
+  for (int k = 0; k < 2; ++k)
+    for (int l = 0; l <= kMaxLoads; ++l) {
+      if (b->graph[k][l]) (void)hipGraphExecDestroy(b->graph[k][l]);
+      if (b->tgraph[k][l]) (void)hipGraphExecDestroy(b->tgraph[k][l]);
+      for (auto ev : b->tevents[k][l]) (void)hipEventDestroy(ev);
+    }
+  delete b;
 }
 
 void hom_destroy(hom_problem* pb) {

@@ -1,0 +1,138 @@
+// Device helpers shared by the pipeline kernels: complex arithmetic, index
+// maps between Z_N and the doubled grid, fixed-order reductions, the basis
+// T(k) of the projected spaces and the symmetric coefficient product.
+#pragma once
+#include "hom_internal.hpp"
+
+namespace hom {
+
+// ------------------------------------------------------------------ complex
+template <typename R>
+__device__ __forceinline__ Cx<R> cx(R a, R b) {
+  Cx<R> c;
+  c.x = a;
+  c.y = b;
+  return c;
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return cx(a.x + b.x, a.y + b.y); }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return cx(a.x - b.x, a.y - b.y); }
+template <typename R>
+__device__ __forceinline__ Cx<R> operator*(Cx<R> a, R s) { return cx(a.x * s, a.y * s); }
+template <typename R>
+__device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
+  return cx(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+// i * s * a
+template <typename R>
+__device__ __forceinline__ Cx<R> imul(Cx<R> a, R s) { return cx(-a.y * s, a.x * s); }
+
+// ------------------------------------------------------------------ indices
+// FFT-order index <-> signed frequency for an odd length n.
+__device__ __forceinline__ int fr(int i, int n) { return i <= (n - 1) / 2 ? i : i - n; }
+__device__ __forceinline__ int ixn(int k, int n) { return k >= 0 ? k : k + n; }
+// Position on the length-M axis of frequency index i of a length-N axis (zero padding).
+__device__ __forceinline__ int padpos(int i, int N, int M) { return i <= (N - 1) / 2 ? i : i + (M - N); }
+// Index on the length-N axis kept by truncation of position j of a length-M axis, or -1.
+__device__ __forceinline__ int truncidx(int j, int N, int M) {
+  const int h = (N - 1) / 2;
+  if (j <= h) return j;
+  if (j >= M - h) return j - (M - N);
+  return -1;
+}
+
+// ------------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum_arr(const double* __restrict__ p, int n) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+  for (int i = lane; i < n; i += 64) s += p[i];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  return __shfl(s, 0, 64);
+}
+
+// Sum over the block in a fixed order; every thread must call it.
+__device__ __forceinline__ double block_sum(double v, double* sred) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) sred[w] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) r += sred[i];
+  __syncthreads();
+  return r;
+}
+
+// ------------------------------------------------------------------ basis T(k)
+// Orthonormal basis of the range of G^E(k) (primal, one column xi/|xi|) or of
+// G^J(k) (dual: d = 2 the rotated normal, d = 3 two tangents), Def. projection.
+__device__ __forceinline__ void basis(const Geo& g, int k0, int k1, int k2, double T[3][2]) {
+  const int kk[3] = {k0, k1, k2};
+  double n[3] = {0.0, 0.0, 0.0};
+  double n2 = 0.0;
+  for (int c = 0; c < g.d; ++c) {
+    const int a = g.phys_axis[c];
+    n[c] = kk[a] * g.iY[a];
+    n2 += n[c] * n[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) T[c][0] = T[c][1] = 0.0;
+  if (n2 == 0.0) return;
+  const double inv = 1.0 / sqrt(n2);
+  for (int c = 0; c < g.d; ++c) n[c] *= inv;
+  if (!g.dual) {
+    for (int c = 0; c < g.d; ++c) T[c][0] = n[c];
+  } else if (g.d == 2) {
+    T[0][0] = -n[1];
+    T[1][0] = n[0];
+  } else {
+    int a = 0;
+    if (fabs(n[1]) < fabs(n[a])) a = 1;
+    if (fabs(n[2]) < fabs(n[a])) a = 2;
+    double t1[3] = {-n[a] * n[0], -n[a] * n[1], -n[a] * n[2]};
+    t1[a] += 1.0;
+    const double in1 = 1.0 / sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+    t1[0] *= in1;
+    t1[1] *= in1;
+    t1[2] *= in1;
+    const double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+    for (int c = 0; c < 3; ++c) {
+      T[c][0] = t1[c];
+      T[c][1] = t2[c];
+    }
+  }
+}
+
+// Symmetric coefficient times vector: w = A u, A given by nc components.
+template <typename R>
+__device__ __forceinline__ void coef_mul(int d, int nc, const R* a, const R* u, R* w) {
+  if (nc == 1) {
+    for (int c = 0; c < d; ++c) w[c] = a[0] * u[c];
+  } else if (d == 2) {  // xx, yy, xy
+    w[0] = a[0] * u[0] + a[2] * u[1];
+    w[1] = a[2] * u[0] + a[1] * u[1];
+  } else {  // xx, yy, zz, xy, xz, yz
+    w[0] = a[0] * u[0] + a[3] * u[1] + a[4] * u[2];
+    w[1] = a[3] * u[0] + a[1] * u[1] + a[5] * u[2];
+    w[2] = a[4] * u[0] + a[5] * u[1] + a[2] * u[2];
+  }
+}
+
+__device__ __forceinline__ void decode_pair(const Geo& g, int q, int& h0, int& k1) {
+  const int half1 = (g.N[1] + 1) / 2;
+  if (q < half1) {
+    h0 = 0;
+    k1 = q;
+  } else {
+    const int q2 = q - half1;
+    h0 = 1 + q2 / g.N[1];
+    k1 = fr(q2 % g.N[1], g.N[1]);
+  }
+}
+
+__host__ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
+
+}  // namespace hom

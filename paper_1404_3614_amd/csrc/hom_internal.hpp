@@ -83,7 +83,17 @@ struct Geo {
 
 enum FirstMode { FIRST_CG = 0, FIRST_FIELD = 1, FIRST_BOUNDS = 2 };
 enum LastMode { LAST_CG = 0, LAST_RESID = 1, LAST_MATVEC = 2 };
-enum ApplyMode { APPLY_COEF = 0, APPLY_QUAD = 1 };
+enum ApplyMode { APPLY_COEF = 0, APPLY_QUAD = 1, APPLY_COEF_CG = 2 };
+constexpr int MID_CG = 2;  // flag or-ed into the inverse argument of launch_mid
+
+// Host-side switch: when `on`, the next pipeline kernel launch is issued with
+// hipExtLaunchKernelGGL and these start/stop events (kernel-execution
+// timestamps), used by the timing mode of batched solves.
+struct ExtTiming {
+  bool on = false;
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+extern ExtTiming g_ext_timing;
 
 // Launch wrappers (hom_kernels.hip).  All return hipError_t of the launch.
 template <typename R>
@@ -109,6 +119,7 @@ hipError_t launch_start_vectors(const Geo& g, const UnitDev* units, int nunits, 
 hipError_t launch_symmetrize(const Geo& g, const Cx<double>* src, Cx<double>* dst, int m, hipStream_t st);
 hipError_t launch_advance(const Geo& g, const UnitDev* units, int nunits, int* iter_base, int step,
                           int* active_out, hipStream_t st);
+hipError_t launch_twiddles(Cx<double>* t64, Cx<float>* t32, int M, hipStream_t st);
 hipError_t launch_coef_real(const Cx<double>* full, double* c64, float* c32, long n, hipStream_t st);
 hipError_t launch_extract_half(const Geo& g, const Cx<double>* full, Cx<double>* half, int nc, hipStream_t st);
 hipError_t launch_coef_incl(int d, const int* Mint, const double* iY, int nc, const double* A0c, int n_incl,
@@ -116,5 +127,11 @@ hipError_t launch_coef_incl(int d, const int* Mint, const double* iY, int nc, co
 hipError_t launch_pixel_factor(int d, const int* Mint, const int* Pint, int nc, const Cx<double>* dft,
                                Cx<double>* out, hipStream_t st);
 size_t incl_dev_size();
+
+// Specialised FP32 passes (hom_fast.hip); false/0 when no specialisation exists.
+bool fast_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st, hipError_t* err);
+bool fast_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, int jstep, const int* iter_base,
+              hipStream_t st, hipError_t* err);
+int fast_row_pairs(int M, int P);
 
 }  // namespace hom

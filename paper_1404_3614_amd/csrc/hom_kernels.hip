@@ -19,69 +19,13 @@
 // in place with register staging: every stage loads its butterfly inputs into
 // registers, synchronises, then stores the outputs.  The doubled-grid field
 // never goes to HBM: only the intermediates with one pruned axis do.
-#include "hom_internal.hpp"
+#include "hom_device.hpp"
+
+#include <hip/hip_ext.h>
 
 namespace hom {
 
-// ------------------------------------------------------------------ complex
-template <typename R>
-__device__ __forceinline__ Cx<R> cx(R a, R b) {
-  Cx<R> c;
-  c.x = a;
-  c.y = b;
-  return c;
-}
-template <typename R>
-__device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return cx(a.x + b.x, a.y + b.y); }
-template <typename R>
-__device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return cx(a.x - b.x, a.y - b.y); }
-template <typename R>
-__device__ __forceinline__ Cx<R> operator*(Cx<R> a, R s) { return cx(a.x * s, a.y * s); }
-template <typename R>
-__device__ __forceinline__ Cx<R> cmul(Cx<R> a, Cx<R> b) {
-  return cx(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
-}
-// i * s * a
-template <typename R>
-__device__ __forceinline__ Cx<R> imul(Cx<R> a, R s) { return cx(-a.y * s, a.x * s); }
-
-// ------------------------------------------------------------------ indices
-// FFT-order index <-> signed frequency for an odd length n.
-__device__ __forceinline__ int fr(int i, int n) { return i <= (n - 1) / 2 ? i : i - n; }
-__device__ __forceinline__ int ixn(int k, int n) { return k >= 0 ? k : k + n; }
-// Position on the length-M axis of frequency index i of a length-N axis (zero padding).
-__device__ __forceinline__ int padpos(int i, int N, int M) { return i <= (N - 1) / 2 ? i : i + (M - N); }
-// Index on the length-N axis kept by truncation of position j of a length-M axis, or -1.
-__device__ __forceinline__ int truncidx(int j, int N, int M) {
-  const int h = (N - 1) / 2;
-  if (j <= h) return j;
-  if (j >= M - h) return j - (M - N);
-  return -1;
-}
-
-// ------------------------------------------------------------------ reductions
-__device__ __forceinline__ double wave_sum_arr(const double* __restrict__ p, int n) {
-  const int lane = threadIdx.x & 63;
-  double s = 0.0;
-  for (int i = lane; i < n; i += 64) s += p[i];
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  return __shfl(s, 0, 64);
-}
-
-// Sum over the block in a fixed order; every thread must call it.
-__device__ __forceinline__ double block_sum(double v, double* sred) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) sred[w] = v;
-  __syncthreads();
-  double r = 0.0;
-#pragma unroll
-  for (int i = 0; i < kBlock / 64; ++i) r += sred[i];
-  __syncthreads();
-  return r;
-}
+ExtTiming g_ext_timing;
 
 // ------------------------------------------------------------------ FFT
 template <typename R>
@@ -170,74 +114,6 @@ __device__ void lds_fft(Cx<R>* buf, int nl, int M, const Plan& pl, const Cx<R>* 
   }
 }
 
-// ------------------------------------------------------------------ basis T(k)
-// Orthonormal basis of the range of G^E(k) (primal, one column xi/|xi|) or of
-// G^J(k) (dual: d = 2 the rotated normal, d = 3 two tangents), Def. projection.
-__device__ __forceinline__ void basis(const Geo& g, int k0, int k1, int k2, double T[3][2]) {
-  const int kk[3] = {k0, k1, k2};
-  double n[3] = {0.0, 0.0, 0.0};
-  double n2 = 0.0;
-  for (int c = 0; c < g.d; ++c) {
-    const int a = g.phys_axis[c];
-    n[c] = kk[a] * g.iY[a];
-    n2 += n[c] * n[c];
-  }
-#pragma unroll
-  for (int c = 0; c < 3; ++c) T[c][0] = T[c][1] = 0.0;
-  if (n2 == 0.0) return;
-  const double inv = 1.0 / sqrt(n2);
-  for (int c = 0; c < g.d; ++c) n[c] *= inv;
-  if (!g.dual) {
-    for (int c = 0; c < g.d; ++c) T[c][0] = n[c];
-  } else if (g.d == 2) {
-    T[0][0] = -n[1];
-    T[1][0] = n[0];
-  } else {
-    int a = 0;
-    if (fabs(n[1]) < fabs(n[a])) a = 1;
-    if (fabs(n[2]) < fabs(n[a])) a = 2;
-    double t1[3] = {-n[a] * n[0], -n[a] * n[1], -n[a] * n[2]};
-    t1[a] += 1.0;
-    const double in1 = 1.0 / sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
-    t1[0] *= in1;
-    t1[1] *= in1;
-    t1[2] *= in1;
-    const double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
-    for (int c = 0; c < 3; ++c) {
-      T[c][0] = t1[c];
-      T[c][1] = t2[c];
-    }
-  }
-}
-
-// Symmetric coefficient times vector: w = A u, A given by nc components.
-template <typename R>
-__device__ __forceinline__ void coef_mul(int d, int nc, const R* a, const R* u, R* w) {
-  if (nc == 1) {
-    for (int c = 0; c < d; ++c) w[c] = a[0] * u[c];
-  } else if (d == 2) {  // xx, yy, xy
-    w[0] = a[0] * u[0] + a[2] * u[1];
-    w[1] = a[2] * u[0] + a[1] * u[1];
-  } else {  // xx, yy, zz, xy, xz, yz
-    w[0] = a[0] * u[0] + a[3] * u[1] + a[4] * u[2];
-    w[1] = a[3] * u[0] + a[1] * u[1] + a[5] * u[2];
-    w[2] = a[4] * u[0] + a[5] * u[1] + a[2] * u[2];
-  }
-}
-
-__device__ __forceinline__ void decode_pair(const Geo& g, int q, int& h0, int& k1) {
-  const int half1 = (g.N[1] + 1) / 2;
-  if (q < half1) {
-    h0 = 0;
-    k1 = q;
-  } else {
-    const int q2 = q - half1;
-    h0 = 1 + q2 / g.N[1];
-    k1 = fr(q2 % g.N[1], g.N[1]);
-  }
-}
-
-__host__ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
 // ============================================================== first pass
 template <typename R, int MAXB>
@@ -296,6 +172,11 @@ __global__ __launch_bounds__(kBlock) void k_first(Geo g, const UnitDev* __restri
     }
   }
   __syncthreads();
+  if (mode == FIRST_CG) {
+    int any = 0;
+    for (int l = 0; l < L; ++l) any |= s_act[l];
+    if (!any) return;  // uniform over the block
+  }
 
   // ---- phase 1: CG update of the stored rows, stage row A in LDS
   double gp0 = 0.0, gp1 = 0.0, gp2 = 0.0;
@@ -525,10 +406,16 @@ __global__ __launch_bounds__(kBlock) void k_last(Geo g, const UnitDev* __restric
 
 // ============================================================== middle axis (3D)
 template <typename R, int MAXB>
-__global__ __launch_bounds__(kBlock) void k_mid(Geo g, const UnitDev* __restrict__ units, int inverse) {
+__global__ __launch_bounds__(kBlock) void k_mid(Geo g, const UnitDev* __restrict__ units, int flags) {
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem);
   const UnitDev& U = units[blockIdx.z];
+  const int inverse = flags & 1;
+  if (flags & MID_CG) {
+    bool any = false;
+    for (int l = 0; l < g.L; ++l) any |= (U.sc[l].status == 0);
+    if (!any) return;
+  }
   const int tid = threadIdx.x;
   const int N1 = g.N[1], M1 = g.M[1];
   const int inner = g.M[2] * g.P;
@@ -577,6 +464,12 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo g, const UnitDev* __restri
   const int nl = tileA * P;
   Cx<R>* data = reinterpret_cast<Cx<R>*>(g.N[1] > 1 ? U.bufB : U.bufA);
   const R* coef = reinterpret_cast<const R*>(U.coef);
+  if (mode == APPLY_COEF_CG) {
+    bool any = false;
+    for (int l = 0; l < L; ++l) any |= (U.sc[l].status == 0);
+    if (!any) return;
+    mode = APPLY_COEF;
+  }
 
   for (int t = tid; t < M0 * nl; t += kBlock) {
     const int j = t / nl, l = t - (t / nl) * nl;
@@ -795,6 +688,16 @@ __global__ void k_advance(Geo g, const UnitDev* __restrict__ units, int nunits, 
   }
 }
 
+// Twiddle tables exp(-2 pi i t / M), t < M, from sincospi in FP64.
+__global__ void k_twiddles(Cx<double>* t64, Cx<float>* t32, int M) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < M; t += gridDim.x * blockDim.x) {
+    double s, c;
+    sincospi(-2.0 * (double)t / (double)M, &s, &c);
+    t64[t] = cx(c, s);
+    if (t32) t32[t] = cx((float)c, (float)s);
+  }
+}
+
 __global__ void k_coef_real(const Cx<double>* __restrict__ full, double* __restrict__ c64, float* __restrict__ c32,
                             long n) {
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
@@ -910,6 +813,15 @@ static int max_butterflies(const Plan& pl, int M, int nl) {
   return mx;
 }
 
+#define HOM_LAUNCH1(K, GRID, LDS, ...)                                                                   \
+  do {                                                                                                 \
+    if (g_ext_timing.on)                                                                               \
+      hipExtLaunchKernelGGL(K, GRID, dim3(kBlock), LDS, st, g_ext_timing.start, g_ext_timing.stop, 0,  \
+                            __VA_ARGS__);                                                             \
+    else                                                                                               \
+      hipLaunchKernelGGL(K, GRID, dim3(kBlock), LDS, st, __VA_ARGS__);                                 \
+  } while (0)
+
 #define HOM_DISPATCH(KERN, MAXB_NEEDED, LDS, GRID, ...)                                               \
   do {                                                                                               \
     const int mb_ = pow2_at_least((MAXB_NEEDED + kBlock - 1) / kBlock);                              \
@@ -926,11 +838,11 @@ static int max_butterflies(const Plan& pl, int M, int nl) {
     hipError_t e_ = hipFuncSetAttribute(fn_, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(LDS)); \
     if (e_ != hipSuccess) return e_;                                                                 \
     switch (mb_) {                                                                                   \
-      case 1: hipLaunchKernelGGL((KERN<R, 1>), GRID, dim3(kBlock), LDS, st, __VA_ARGS__); break;      \
-      case 2: hipLaunchKernelGGL((KERN<R, 2>), GRID, dim3(kBlock), LDS, st, __VA_ARGS__); break;      \
-      case 4: hipLaunchKernelGGL((KERN<R, 4>), GRID, dim3(kBlock), LDS, st, __VA_ARGS__); break;      \
-      case 8: hipLaunchKernelGGL((KERN<R, 8>), GRID, dim3(kBlock), LDS, st, __VA_ARGS__); break;      \
-      case 16: hipLaunchKernelGGL((KERN<R, 16>), GRID, dim3(kBlock), LDS, st, __VA_ARGS__); break;    \
+      case 1: HOM_LAUNCH1((KERN<R, 1>), GRID, LDS, __VA_ARGS__); break;                              \
+      case 2: HOM_LAUNCH1((KERN<R, 2>), GRID, LDS, __VA_ARGS__); break;                              \
+      case 4: HOM_LAUNCH1((KERN<R, 4>), GRID, LDS, __VA_ARGS__); break;                              \
+      case 8: HOM_LAUNCH1((KERN<R, 8>), GRID, LDS, __VA_ARGS__); break;                              \
+      case 16: HOM_LAUNCH1((KERN<R, 16>), GRID, LDS, __VA_ARGS__); break;                            \
     }                                                                                                \
     return hipGetLastError();                                                                        \
   } while (0)
@@ -938,6 +850,10 @@ static int max_butterflies(const Plan& pl, int M, int nl) {
 template <typename R>
 hipError_t launch_first(const Geo& g, const UnitDev* units, int nunits, int mode, int jstep, const int* iter_base,
                         hipStream_t st) {
+  if constexpr (sizeof(R) == 4) {
+    hipError_t e;
+    if (fast_row(true, g, units, nunits, mode, jstep, iter_base, st, &e)) return e;
+  }
   const int nl = 2 * g.P;
   const size_t lds = align16((size_t)g.L * g.m * g.N[2] * sizeof(Cx<double>)) + (size_t)g.M[2] * nl * sizeof(Cx<R>);
   HOM_DISPATCH(k_first, max_butterflies(g.pl[2], g.M[2], nl), lds, dim3(g.Q, 1, nunits), g, units, mode, jstep,
@@ -947,6 +863,10 @@ hipError_t launch_first(const Geo& g, const UnitDev* units, int nunits, int mode
 template <typename R>
 hipError_t launch_last(const Geo& g, const UnitDev* units, int nunits, int mode, int jstep, const int* iter_base,
                        hipStream_t st) {
+  if constexpr (sizeof(R) == 4) {
+    hipError_t e;
+    if (fast_row(false, g, units, nunits, mode, jstep, iter_base, st, &e)) return e;
+  }
   const int nl = 2 * g.P;
   const size_t lds = (size_t)g.M[2] * nl * sizeof(Cx<R>);
   HOM_DISPATCH(k_last, max_butterflies(g.pl[2], g.M[2], nl), lds, dim3(g.Q, 1, nunits), g, units, mode, jstep,
@@ -955,6 +875,10 @@ hipError_t launch_last(const Geo& g, const UnitDev* units, int nunits, int mode,
 
 template <typename R>
 hipError_t launch_apply(const Geo& g, const UnitDev* units, int nunits, int mode, hipStream_t st) {
+  if constexpr (sizeof(R) == 4) {
+    hipError_t e;
+    if (mode != APPLY_QUAD && fast_apply(g, units, nunits, mode == APPLY_COEF_CG ? 1 : 0, st, &e)) return e;
+  }
   const int nl = g.tileA * g.P;
   const size_t lds = (size_t)g.M[0] * nl * sizeof(Cx<R>);
   HOM_DISPATCH(k_apply, max_butterflies(g.pl[0], g.M[0], nl), lds, dim3(g.nbA, 1, nunits), g, units, mode);
@@ -1022,6 +946,11 @@ hipError_t launch_symmetrize(const Geo& g, const Cx<double>* src, Cx<double>* ds
 hipError_t launch_advance(const Geo& g, const UnitDev* units, int nunits, int* iter_base, int step, int* active_out,
                           hipStream_t st) {
   hipLaunchKernelGGL(k_advance, dim3(1), dim3(kBlock), 0, st, g, units, nunits, iter_base, step, active_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_twiddles(Cx<double>* t64, Cx<float>* t32, int M, hipStream_t st) {
+  hipLaunchKernelGGL(k_twiddles, dim3(grid_for(M)), dim3(kBlock), 0, st, t64, t32, M);
   return hipGetLastError();
 }
 

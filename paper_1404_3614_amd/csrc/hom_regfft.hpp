@@ -1,0 +1,191 @@
+// Register-resident DFTs of small 3/5-smooth lengths and the four-step
+// decomposition used by the fused passes.
+//
+// A length M = A * B transform of one line is split over threads:
+//   step 1: thread n2 (< B) holds x[B n1 + n2], n1 < A, and computes the
+//           A-point DFT over n1 in registers, then multiplies by w_M^(n2 k1);
+//   exchange through LDS (one write, one read per element);
+//   step 2: thread k1 (< A) holds the B values of column k1 and computes the
+//           B-point DFT, giving X[k1 + A k2] in register k2.
+// Register DFTs of composite length are themselves four-step products of
+// radix-3/5 butterflies with compile-time twiddles, so every index is a
+// constant after unrolling.
+#pragma once
+#include "hom_internal.hpp"
+
+namespace hom {
+namespace rf {
+
+// cos(2 pi p / q) and sin(2 pi p / q) at compile time (Taylor series after
+// reduction to [-pi, pi]; |error| < 1e-16 for the small q used here).
+constexpr double kPi = 3.14159265358979323846264338327950288;
+constexpr double reduce(int p, int q) {
+  int r = p % q;
+  if (r < 0) r += q;
+  double x = 2.0 * kPi * (double)r / (double)q;
+  if (x > kPi) x -= 2.0 * kPi;
+  return x;
+}
+constexpr double ccos(int p, int q) {
+  const double x = reduce(p, q);
+  double term = 1.0, sum = 1.0;
+  for (int k = 1; k < 30; ++k) {
+    term *= -x * x / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double csin(int p, int q) {
+  const double x = reduce(p, q);
+  double term = x, sum = x;
+  for (int k = 1; k < 30; ++k) {
+    term *= -x * x / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+
+template <typename R>
+__device__ __forceinline__ Cx<R> mk(R a, R b) {
+  Cx<R> c;
+  c.x = a;
+  c.y = b;
+  return c;
+}
+template <typename R>
+__device__ __forceinline__ Cx<R> add(Cx<R> a, Cx<R> b) { return mk(a.x + b.x, a.y + b.y); }
+template <typename R>
+__device__ __forceinline__ Cx<R> sub(Cx<R> a, Cx<R> b) { return mk(a.x - b.x, a.y - b.y); }
+template <typename R>
+__device__ __forceinline__ Cx<R> scl(Cx<R> a, R s) { return mk(a.x * s, a.y * s); }
+template <typename R>
+__device__ __forceinline__ Cx<R> mul(Cx<R> a, Cx<R> b) { return mk(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+// multiply by exp(S 2 pi i p / q) with compile-time p, q
+template <typename R, int S, int p, int q>
+__device__ __forceinline__ Cx<R> rot(Cx<R> a) {
+  if constexpr (p % q == 0) {
+    return a;
+  } else {
+    constexpr double c = ccos(p, q), s = S * csin(p, q);
+    return mk((R)(a.x * (R)c - a.y * (R)s), (R)(a.x * (R)s + a.y * (R)c));
+  }
+}
+
+// ---- prime radices, in place, natural order; S = -1 forward, +1 inverse
+template <typename R, int S>
+__device__ __forceinline__ void dft3(Cx<R>& a0, Cx<R>& a1, Cx<R>& a2) {
+  const R s3 = (R)(S * 0.86602540378443864676);
+  Cx<R> t = add(a1, a2), d = sub(a1, a2);
+  Cx<R> m = sub(a0, scl(t, (R)0.5));
+  Cx<R> j = mk(-d.y * s3, d.x * s3);
+  a0 = add(a0, t);
+  a1 = add(m, j);
+  a2 = sub(m, j);
+}
+
+template <typename R, int S>
+__device__ __forceinline__ void dft5(Cx<R>& a0, Cx<R>& a1, Cx<R>& a2, Cx<R>& a3, Cx<R>& a4) {
+  const R c1 = (R)0.30901699437494742410, c2 = (R)-0.80901699437494742410;
+  const R s1 = (R)(S * 0.95105651629515357212), s2 = (R)(S * 0.58778525229247312917);
+  Cx<R> t1 = add(a1, a4), t2 = add(a2, a3), t3 = sub(a1, a4), t4 = sub(a2, a3);
+  Cx<R> b1 = add(a0, add(scl(t1, c1), scl(t2, c2)));
+  Cx<R> b2 = add(a0, add(scl(t1, c2), scl(t2, c1)));
+  Cx<R> e1 = add(scl(t3, s1), scl(t4, s2));
+  Cx<R> e2 = sub(scl(t3, s2), scl(t4, s1));
+  a0 = add(a0, add(t1, t2));
+  Cx<R> j1 = mk(-e1.y, e1.x), j2 = mk(-e2.y, e2.x);
+  a1 = add(b1, j1);
+  a4 = sub(b1, j1);
+  a2 = add(b2, j2);
+  a3 = sub(b2, j2);
+}
+
+template <typename R, int N, int S>
+struct Dft;
+
+template <typename R, int S>
+struct Dft<R, 1, S> {
+  static __device__ __forceinline__ void run(Cx<R>* v) { (void)v; }
+};
+template <typename R, int S>
+struct Dft<R, 3, S> {
+  static __device__ __forceinline__ void run(Cx<R>* v) { dft3<R, S>(v[0], v[1], v[2]); }
+};
+template <typename R, int S>
+struct Dft<R, 5, S> {
+  static __device__ __forceinline__ void run(Cx<R>* v) { dft5<R, S>(v[0], v[1], v[2], v[3], v[4]); }
+};
+
+// composite N = N1 * N2: n = N2 n1 + n2, k = k1 + N1 k2
+template <typename R, int N1, int N2, int S>
+struct DftComp {
+  template <int n2, int k1>
+  static __device__ __forceinline__ void twid(Cx<R>* a) {
+    a[k1] = rot<R, S, n2 * k1, N1 * N2>(a[k1]);
+    if constexpr (k1 + 1 < N1) twid<n2, k1 + 1>(a);
+  }
+  template <int n2>
+  static __device__ __forceinline__ void step1(const Cx<R>* v, Cx<R>* t) {
+    Cx<R> a[N1];
+#pragma unroll
+    for (int n1 = 0; n1 < N1; ++n1) a[n1] = v[N2 * n1 + n2];
+    Dft<R, N1, S>::run(a);
+    twid<n2, 0>(a);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) t[n2 * N1 + k1] = a[k1];
+    if constexpr (n2 + 1 < N2) step1<n2 + 1>(v, t);
+  }
+  static __device__ __forceinline__ void run(Cx<R>* v) {
+    Cx<R> t[N1 * N2];
+    step1<0>(v, t);
+#pragma unroll
+    for (int k1 = 0; k1 < N1; ++k1) {
+      Cx<R> b[N2];
+#pragma unroll
+      for (int n2 = 0; n2 < N2; ++n2) b[n2] = t[n2 * N1 + k1];
+      Dft<R, N2, S>::run(b);
+#pragma unroll
+      for (int k2 = 0; k2 < N2; ++k2) v[k1 + N1 * k2] = b[k2];
+    }
+  }
+};
+
+template <typename R, int S>
+struct Dft<R, 9, S> : DftComp<R, 3, 3, S> {};
+template <typename R, int S>
+struct Dft<R, 15, S> : DftComp<R, 3, 5, S> {};
+template <typename R, int S>
+struct Dft<R, 25, S> : DftComp<R, 5, 5, S> {};
+template <typename R, int S>
+struct Dft<R, 27, S> : DftComp<R, 3, 9, S> {};
+
+// Factorisation M = A * B used by the fused passes (A: registers in step 1).
+template <int M>
+struct Split;
+template <>
+struct Split<9> { static constexpr int A = 3, B = 3; };
+template <>
+struct Split<25> { static constexpr int A = 5, B = 5; };
+template <>
+struct Split<27> { static constexpr int A = 9, B = 3; };
+template <>
+struct Split<45> { static constexpr int A = 9, B = 5; };
+template <>
+struct Split<75> { static constexpr int A = 15, B = 5; };
+template <>
+struct Split<81> { static constexpr int A = 9, B = 9; };
+template <>
+struct Split<125> { static constexpr int A = 25, B = 5; };
+template <>
+struct Split<225> { static constexpr int A = 15, B = 15; };
+template <>
+struct Split<243> { static constexpr int A = 27, B = 9; };
+template <>
+struct Split<375> { static constexpr int A = 25, B = 15; };
+template <>
+struct Split<625> { static constexpr int A = 25, B = 25; };
+template <>
+struct Split<675> { static constexpr int A = 27, B = 25; };
+
+}  // namespace rf
+}  // namespace hom

@@ -234,3 +234,61 @@ def test_setup_coefficients_match_oracle():
         for c, (i, j) in enumerate(comp):
             assert np.abs(Ah[c].cpu().numpy() - ref[i, j]).max() < 1e-13 * max(1, np.abs(ref).max())
             assert np.abs(Bh[c].cpu().numpy() - refB[i, j]).max() < 1e-13 * max(1, np.abs(refB).max())
+
+
+def test_batch_equals_single_problem_solves():
+    # lockstep batching runs the same per-problem arithmetic: results are bitwise equal
+    H = _H()
+    import torch
+    cells = [homgen.pixel_cell(seed=30 + i, P=25, values=(1.0, 20.0 + 30 * i)) for i in range(3)]
+    st = torch.cuda.Stream()
+    probs = []
+    for c in cells:
+        Ah, Bh, nc = H.coef_from_cell(c, (41, 41))
+        probs.append(H.Problem(2, (41, 41), (1.0, 1.0), Ah, Bh, precision="mixed", ncoef=nc, max_loads=2, stream=st))
+    batch = H.Batch(probs)
+    out = batch.solve_bounds(tol=1e-8)
+    for p, c, b in zip(probs, cells, out):
+        single = p.solve_bounds(tol=1e-8)
+        assert np.array_equal(single["A_up"], b["A_up"]) and np.array_equal(single["A_low"], b["A_low"])
+        assert [i["iters"] for i in single["info_primal"]] == [i["iters"] for i in b["info_primal"]]
+        ob = ga.bounds(ga.make_problem(c, 41), tol=1e-11)
+        assert relerr(b["A_up"], ob["A_up"]) < 1e-6 and relerr(b["A_low"], ob["A_low"]) < 1e-6
+
+
+def test_batch_3d_mixed_contrast():
+    H = _H()
+    import torch
+    st = torch.cuda.Stream()
+    cells = [homgen.sphere_cell(seed=40 + i, n=4 + i, anisotropic=(i == 1)) for i in range(3)]
+    nc = 6
+    probs = []
+    for c in cells:
+        Ah, Bh, _ = H.coef_from_cell(c, (13, 13, 13), ncoef=nc)
+        probs.append(H.Problem(3, (13, 13, 13), (1.0, 1.0, 1.0), Ah, Bh, precision="fp64", ncoef=nc, stream=st))
+    out = H.Batch(probs).solve_bounds(tol=1e-10)
+    for c, b in zip(cells, out):
+        ob = ga.bounds(ga.make_problem(c, 13), tol=1e-11)
+        assert relerr(b["A_up"], ob["A_up"]) < 1e-9 and relerr(b["A_low"], ob["A_low"]) < 1e-9
+
+
+def test_update_coefficients_matches_fresh_setup_and_timing_counts():
+    H = _H()
+    import torch
+    st = torch.cuda.Stream()
+    cells = [homgen.pixel_cell(seed=50 + i, P=25, values=(1.0, 10.0 + 40 * i)) for i in range(2)]
+    coefs = [H.coef_from_cell(c, (41, 41)) for c in cells]
+    probs = [H.Problem(2, (41, 41), (1.0, 1.0), *coefs[i][:2], precision="mixed", ncoef=1, max_loads=2, stream=st)
+             for i in range(2)]
+    batch = H.Batch(probs)
+    batch.set_timing(True)
+    first = batch.solve_bounds(tol=1e-8)
+    ms, cnt = batch.get_timing()
+    assert cnt["first"] == cnt["apply"] == cnt["last"] > 0 and ms["apply"] > 0
+    batch.set_timing(False)
+    # swap the coefficients between the two problems and solve again with the same batch
+    probs[0].update_coefficients(*coefs[1][:2])
+    probs[1].update_coefficients(*coefs[0][:2])
+    swapped = batch.solve_bounds(tol=1e-8)
+    assert np.array_equal(swapped[0]["A_up"], first[1]["A_up"])
+    assert np.array_equal(swapped[1]["A_low"], first[0]["A_low"])
