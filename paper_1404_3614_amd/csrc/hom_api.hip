@@ -275,7 +275,7 @@ Geo make_geo(const hom_problem* pb, int dual, int L, bool fp32, int P_override =
   g.nbF = z.Q;
   g.nbL = z.Q;
   if (fp32) {
-    const int G = fast_row_pairs(z.M[2], g.P);
+    const int G = fast_row_pairs(z.M[2], z.d, L);
     if (G > 0) g.nbF = g.nbL = (z.Q + G - 1) / G;
   }
   const size_t cs = fp32 ? sizeof(Cx<float>) : sizeof(Cx<double>);

@@ -145,26 +145,88 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply_fast(Geo g, const Unit
 }
 
 // ============================================================== row passes
-// G row pairs per block; a (pair, line) group of T threads transforms all P
-// packs of its line.  Line A = (h0, k1, .), line B = (-h0, -k1, .).
-template <typename R, int M, int P, int G>
-__global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_first_fast(Geo g, const UnitDev* __restrict__ units, int mode,
-                                                                  int jstep, const int* __restrict__ iter_base) {
+// G row pairs per block; line A = (h0, k1, .), line B = (-h0, -k1, .).  The
+// packed fields of both lines are staged in LDS in natural position order
+// ([2G lines][P packs][M]); the four-step FFT runs one pack at a time and
+// reuses the staging area for its exchange.
+// T(k) of the field layout with compile-time dimension and problem type.
+template <int D, int DUAL>
+__device__ __forceinline__ void basis_t(const Geo& g, int k0, int k1, int k2, double T[3][2]) {
+  const int kk[3] = {k0, k1, k2};
+  double n[3] = {0.0, 0.0, 0.0};
+  double n2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < D; ++c) {
+    const int a = (D == 2) ? (c == 0 ? 0 : 2) : c;
+    n[c] = kk[a] * g.iY[a];
+    n2 += n[c] * n[c];
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c) T[c][0] = T[c][1] = 0.0;
+  if (n2 == 0.0) return;
+  const double inv = 1.0 / sqrt(n2);
+#pragma unroll
+  for (int c = 0; c < D; ++c) n[c] *= inv;
+  if constexpr (!DUAL) {
+#pragma unroll
+    for (int c = 0; c < D; ++c) T[c][0] = n[c];
+  } else if constexpr (D == 2) {
+    T[0][0] = -n[1];
+    T[1][0] = n[0];
+  } else {
+    const double a0 = fabs(n[0]), a1 = fabs(n[1]), a2 = fabs(n[2]);
+    const int a = (a1 < a0) ? ((a2 < a1) ? 2 : 1) : ((a2 < a0) ? 2 : 0);
+    double t1[3] = {-n[a] * n[0], -n[a] * n[1], -n[a] * n[2]};
+    t1[0] += (a == 0);
+    t1[1] += (a == 1);
+    t1[2] += (a == 2);
+    const double in1 = 1.0 / sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
+    t1[0] *= in1;
+    t1[1] *= in1;
+    t1[2] *= in1;
+    T[0][0] = t1[0];
+    T[1][0] = t1[1];
+    T[2][0] = t1[2];
+    T[0][1] = n[1] * t1[2] - n[2] * t1[1];
+    T[1][1] = n[2] * t1[0] - n[0] * t1[2];
+    T[2][1] = n[0] * t1[1] - n[1] * t1[0];
+  }
+}
+
+struct RowInfo {
+  int valid, h0, k1, rowB, self, i1A, i1B, i0B;
+};
+
+__device__ __forceinline__ void row_info(const Geo& g, int qpair, RowInfo& ri) {
+  ri.valid = qpair < g.Q;
+  int h0 = 0, k1 = 0;
+  if (ri.valid) decode_pair(g, qpair, h0, k1);
+  ri.h0 = h0;
+  ri.k1 = k1;
+  ri.self = (h0 == 0 && k1 == 0);
+  ri.rowB = (h0 == 0 && k1 != 0);
+  ri.i1A = ixn(k1, g.N[1]);
+  ri.i1B = ixn(-k1, g.N[1]);
+  ri.i0B = ixn(-h0, g.N[0]);
+}
+
+template <typename R, int M, int D, int L, int DUAL, int G>
+__global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_first_fast(Geo g, const UnitDev* __restrict__ units,
+                                                                         int mode, int jstep,
+                                                                         const int* __restrict__ iter_base) {
   constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T, N2 = Cfg<M>::N, H2 = Cfg<M>::H;
+  constexpr int P = (L * D + 1) / 2, m = DUAL ? D - 1 : 1, d = D;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_alpha[kMaxLoads];
   __shared__ int s_act[kMaxLoads];
   __shared__ double s_red[16];
+  __shared__ RowInfo s_row[G];
   const UnitDev& U = units[blockIdx.z];
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int N0 = g.N[0], N1 = g.N[1];
-  const int L = g.L, m = g.m, d = g.d;
+  const int N1 = g.N[1];
   const int it = iter_base ? (*iter_base + jstep) : 0;
-
-  Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem);                                        // [M]
-  Cx<double>* rA = reinterpret_cast<Cx<double>*>(smem + align16(M * sizeof(Cx<R>)));  // [G][L][m][N2]
-  Cx<R>* ex = reinterpret_cast<Cx<R>*>(smem + align16(M * sizeof(Cx<R>)) +
-                                       align16((size_t)G * L * m * N2 * sizeof(Cx<double>)));  // [2G][M]
+  Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem);                          // [M]
+  Cx<R>* stage = reinterpret_cast<Cx<R>*>(smem + align16(M * sizeof(Cx<R>)));  // [2G][P][M]
 
   if (tid < 64) {
     const int lane = tid;
@@ -198,8 +260,10 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_first_fast(Geo g
       }
     }
   }
+  if (tid < G) row_info(g, blockIdx.x * G + tid, s_row[tid]);
   const Cx<R>* twg = reinterpret_cast<const Cx<R>*>(g.tw[2]);
   for (int i = tid; i < M; i += nthr) tw[i] = twg[i];
+  for (int i = tid; i < 2 * G * P * M; i += nthr) stage[i] = rf::mk<R>(0, 0);
   __syncthreads();
   if (mode == FIRST_CG) {
     int any = 0;
@@ -207,44 +271,66 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_first_fast(Geo g
     if (!any) return;
   }
 
-  // ---- CG update of the stored rows of every pair of the block; stage row A
+  // ---- CG update of the stored entries; packed fields of row A into the staging area
   double gp0 = 0.0, gp1 = 0.0, gp2 = 0.0;
-  const int per_row = L * m * N2;
-  for (int t = tid; t < G * 2 * per_row; t += nthr) {
-    const int gp = t / (2 * per_row), rem0 = t - gp * 2 * per_row;
-    const int row = rem0 / per_row, rem = rem0 - row * per_row;
-    const int qpair = blockIdx.x * G + gp;
-    if (qpair >= g.Q) continue;
-    int h0, k1;
-    decode_pair(g, qpair, h0, k1);
-    const bool rowB = (h0 == 0 && k1 != 0);
-    if (row == 1 && !rowB) continue;
-    const int l = rem / (m * N2), c = (rem / N2) % m, i2 = rem % N2;
-    const int i1 = row ? ixn(-k1, N1) : ixn(k1, N1);
-    const size_t idx = ((size_t)(c * g.H0 + h0) * N1 + i1) * N2 + i2;
-    Cx<double> val = cx(0.0, 0.0);
-    if (mode == FIRST_CG) {
-      if (s_act[l]) {
-        Cx<double> rv = U.r[l][idx];
-        if (it > 0) {
-          const double a = s_alpha[l];
-          Cx<double> xv = U.x[l][idx];
-          const Cx<double> pv = U.p[l][idx], sv = U.s[l][idx];
-          xv = xv + pv * a;
-          rv = rv - sv * a;
-          U.x[l][idx] = xv;
-          U.r[l][idx] = rv;
+  for (int t = tid; t < G * 2 * N2; t += nthr) {
+    const int gp = t / (2 * N2), rem = t - gp * 2 * N2;
+    const int row = rem / N2, i2 = rem - row * N2;
+    const RowInfo& ri = s_row[gp];
+    if (!ri.valid || (row == 1 && !ri.rowB)) continue;
+    const int h0 = ri.h0;
+    const int i1 = row ? ri.i1B : ri.i1A;
+    const double wt = h0 == 0 ? 1.0 : 2.0;
+    Cx<double> rv[L][m];
+#pragma unroll
+    for (int l = 0; l < L; ++l)
+#pragma unroll
+      for (int c = 0; c < m; ++c) {
+        const size_t idx = ((size_t)(c * g.H0 + h0) * N1 + i1) * N2 + i2;
+        Cx<double> v = cx(0.0, 0.0);
+        if (mode != FIRST_CG) {
+          v = U.x[l][idx];
+        } else if (s_act[l]) {
+          v = U.r[l][idx];
+          if (it > 0) {
+            const double a = s_alpha[l];
+            const Cx<double> xv = U.x[l][idx], pv = U.p[l][idx], sv = U.s[l][idx];
+            v = v - sv * a;
+            U.x[l][idx] = xv + pv * a;
+            U.r[l][idx] = v;
+          }
+          const double e = wt * (v.x * v.x + v.y * v.y);
+          if (l == 0) gp0 += e;
+          else if (l == 1) gp1 += e;
+          else gp2 += e;
         }
-        const double e = (h0 == 0 ? 1.0 : 2.0) * (rv.x * rv.x + rv.y * rv.y);
-        if (l == 0) gp0 += e;
-        else if (l == 1) gp1 += e;
-        else gp2 += e;
-        val = rv;
+        rv[l][c] = v;
       }
-    } else {
-      val = U.x[l][idx];
+    if (row == 1) continue;
+    // fields x_hat_{l,gam}(k) = sum_c T_{gam c}(k) r_{l,c}(k) on line A at k2 and their conjugates on line B at -k2
+    const int k2 = fr(i2, N2);
+    double Tb[3][2];
+    basis_t<D, DUAL>(g, h0, ri.k1, k2, Tb);
+    const int posA = padpos(i2, N2, M), posB = padpos(ixn(-k2, N2), N2, M);
+    Cx<R>* sA = stage + (size_t)(2 * gp) * P * M;
+    Cx<R>* sB = stage + (size_t)(2 * gp + 1) * P * M;
+#pragma unroll
+    for (int pk = 0; pk < P; ++pk) {
+      Cx<double> X[2];
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        const int f = 2 * pk + s;
+        X[s] = cx(0.0, 0.0);
+        if (f < L * d) {
+          const int lf = f / d, gam = f - (f / d) * d;
+#pragma unroll
+          for (int c = 0; c < m; ++c) X[s] = X[s] + rv[lf][c] * Tb[gam][c];
+          if (mode == FIRST_BOUNDS && ri.self && k2 == 0) X[s].x += U.E[lf][gam];
+        }
+      }
+      sA[pk * M + posA] = rf::mk<R>((R)(X[0].x - X[1].y), (R)(X[0].y + X[1].x));
+      if (!ri.self) sB[pk * M + posB] = rf::mk<R>((R)(X[0].x + X[1].y), (R)(-X[0].y + X[1].x));
     }
-    if (row == 0) rA[((gp * L + l) * m + c) * N2 + i2] = val;
   }
   if (mode == FIRST_CG) {
     for (int l = 0; l < L; ++l) {
@@ -263,92 +349,65 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_first_fast(Geo g
   }
   __syncthreads();
 
-  // ---- group (pair, line): fields at x_hat(k), packed, inverse four-step FFT
+  // ---- inverse four-step FFT of every (line, pack), one pack at a time
   const int grp = tid / T, q = tid - (tid / T) * T;
   const int gp = grp >> 1, line = grp & 1;
-  const int qpair = blockIdx.x * G + gp;
-  int h0 = 0, k1 = 0;
-  bool live = grp < 2 * G && qpair < g.Q;
+  bool live = grp < 2 * G;
+  RowInfo ri;
   if (live) {
-    decode_pair(g, qpair, h0, k1);
-    if (line == 1 && h0 == 0 && k1 == 0) live = false;  // self-paired row: one line
-  }
-  Cx<R> v[P][T];
-#pragma unroll
-  for (int n1 = 0; n1 < A; ++n1) {
-    const int pos = B * n1 + q;
-    int k2 = 0;
-    bool has = live && q < B;
-    if (pos <= H2) k2 = pos;
-    else if (pos >= M - H2) k2 = pos - M;
-    else has = false;
-    Cx<double> X[2 * P];
-#pragma unroll
-    for (int f = 0; f < 2 * P; ++f) X[f] = cx(0.0, 0.0);
-    if (has) {
-      const int sk2 = line ? -k2 : k2;
-      const int src = ixn(sk2, N2);
-      double Tb[3][2];
-      basis(g, h0, k1, sk2, Tb);
-#pragma unroll
-      for (int f = 0; f < 2 * P; ++f) {
-        if (f < L * d) {
-          const int lf = f / d, gam = f - (f / d) * d;
-          Cx<double> xv = cx(0.0, 0.0);
-          for (int c = 0; c < m; ++c) xv = xv + rA[((gp * L + lf) * m + c) * N2 + src] * Tb[gam][c];
-          if (line) xv.y = -xv.y;
-          if (mode == FIRST_BOUNDS && h0 == 0 && k1 == 0 && k2 == 0) xv.x += U.E[lf][gam];
-          X[f] = xv;
-        }
-      }
-    }
-#pragma unroll
-    for (int pk = 0; pk < P; ++pk)
-      v[pk][n1] = rf::mk<R>((R)(X[2 * pk].x - X[2 * pk + 1].y), (R)(X[2 * pk].y + X[2 * pk + 1].x));
+    ri = s_row[gp];
+    live = ri.valid && !(line == 1 && ri.self);
   }
   Cx<R>* out = reinterpret_cast<Cx<R>*>(U.bufA);
-  const int i0 = line ? ixn(-h0, N0) : h0;
-  const int i1 = line ? ixn(-k1, N1) : ixn(k1, N1);
-  Cx<R>* ebuf = ex + (size_t)grp * M;
+  const int i0 = live ? (line ? ri.i0B : ri.h0) : 0;
+  const int i1 = live ? (line ? ri.i1B : ri.i1A) : 0;
+  Cx<R> v[T];
 #pragma unroll
   for (int pk = 0; pk < P; ++pk) {
-    if (q < B && grp < 2 * G) {
-      rf::Dft<R, A, 1>::run(v[pk]);
+    Cx<R>* sp = stage + ((size_t)grp * P + pk) * M;
+    if (live && q < B) {
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) v[n1] = sp[B * n1 + q];
+    }
+    __syncthreads();
+    if (live && q < B) {
+      rf::Dft<R, A, 1>::run(v);
 #pragma unroll
       for (int k1r = 0; k1r < A; ++k1r) {
         Cx<R> w = tw[q * k1r];
         w.y = -w.y;
-        ebuf[q * A + k1r] = rf::mul(v[pk][k1r], w);
+        sp[q * A + k1r] = rf::mul(v[k1r], w);
       }
     }
     __syncthreads();
-    if (q < A && live) {
+    if (live && q < A) {
 #pragma unroll
-      for (int n2 = 0; n2 < B; ++n2) v[pk][n2] = ebuf[n2 * A + q];
-      rf::Dft<R, B, 1>::run(v[pk]);
+      for (int n2 = 0; n2 < B; ++n2) v[n2] = sp[n2 * A + q];
+      rf::Dft<R, B, 1>::run(v);
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) out[(((size_t)i0 * N1 + i1) * M + (q + A * k2)) * P + pk] = v[pk][k2];
+      for (int k2 = 0; k2 < B; ++k2) out[(((size_t)i0 * N1 + i1) * M + (q + A * k2)) * P + pk] = v[k2];
     }
-    __syncthreads();
   }
+  (void)H2;
 }
 
-template <typename R, int M, int P, int G>
-__global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_last_fast(Geo g, const UnitDev* __restrict__ units, int mode,
-                                                                 int jstep, const int* __restrict__ iter_base) {
+template <typename R, int M, int D, int L, int DUAL, int G>
+__global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_last_fast(Geo g, const UnitDev* __restrict__ units,
+                                                                        int mode, int jstep,
+                                                                        const int* __restrict__ iter_base) {
   constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T, N2 = Cfg<M>::N;
+  constexpr int P = (L * D + 1) / 2, m = DUAL ? D - 1 : 1, d = D;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_beta[kMaxLoads];
   __shared__ int s_act[kMaxLoads];
   __shared__ double s_red[16];
+  __shared__ RowInfo s_row[G];
   const UnitDev& U = units[blockIdx.z];
   const int tid = threadIdx.x, nthr = blockDim.x;
-  const int N0 = g.N[0], N1 = g.N[1];
-  const int L = g.L, m = g.m, d = g.d;
+  const int N1 = g.N[1];
   const int it = iter_base ? (*iter_base + jstep) : 0;
   Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem);                                   // [M]
-  Cx<R>* ex = reinterpret_cast<Cx<R>*>(smem + align16(M * sizeof(Cx<R>)));       // [2G][M]
-  Cx<R>* zk = ex + (size_t)2 * G * M;                                            // [2G][P][N2]
+  Cx<R>* stage = reinterpret_cast<Cx<R>*>(smem + align16(M * sizeof(Cx<R>)));  // [2G][P][M]
 
   if (tid < 64) {
     const int lane = tid;
@@ -386,6 +445,7 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_last_fast(Geo g,
       }
     }
   }
+  if (tid < G) row_info(g, blockIdx.x * G + tid, s_row[tid]);
   const Cx<R>* twg = reinterpret_cast<const Cx<R>*>(g.tw[2]);
   for (int i = tid; i < M; i += nthr) tw[i] = twg[i];
   __syncthreads();
@@ -395,48 +455,46 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_last_fast(Geo g,
     if (!any) return;
   }
 
-  // ---- forward four-step FFT of every line of the block, Z_N2 part to LDS
+  // ---- forward four-step FFT of every (line, pack); natural-order result in the staging area
   const int grp = tid / T, q = tid - (tid / T) * T;
   const int gp = grp >> 1, line = grp & 1;
-  const int qpair = blockIdx.x * G + gp;
-  int h0 = 0, k1 = 0;
-  bool live = grp < 2 * G && qpair < g.Q;
+  bool live = grp < 2 * G;
+  RowInfo ri;
   if (live) {
-    decode_pair(g, qpair, h0, k1);
-    if (line == 1 && h0 == 0 && k1 == 0) live = false;
+    ri = s_row[gp];
+    live = ri.valid && !(line == 1 && ri.self);
   }
   const Cx<R>* in = reinterpret_cast<const Cx<R>*>(U.bufA);
-  const int i0 = line ? ixn(-h0, N0) : h0;
-  const int i1 = line ? ixn(-k1, N1) : ixn(k1, N1);
+  const int i0 = live ? (line ? ri.i0B : ri.h0) : 0;
+  const int i1 = live ? (line ? ri.i1B : ri.i1A) : 0;
   Cx<R> v[P][T];
+  if (live && q < A) {
 #pragma unroll
-  for (int n2 = 0; n2 < B; ++n2) {
-    const int pos = q + A * n2;
+    for (int n2 = 0; n2 < B; ++n2)
 #pragma unroll
-    for (int pk = 0; pk < P; ++pk)
-      v[pk][n2] = (live && q < A) ? in[(((size_t)i0 * N1 + i1) * M + pos) * P + pk] : rf::mk<R>(0, 0);
+      for (int pk = 0; pk < P; ++pk) v[pk][n2] = in[(((size_t)i0 * N1 + i1) * M + (q + A * n2)) * P + pk];
   }
-  Cx<R>* ebuf = ex + (size_t)grp * M;
 #pragma unroll
   for (int pk = 0; pk < P; ++pk) {
-    if (q < A && grp < 2 * G) {
+    Cx<R>* sp = stage + ((size_t)grp * P + pk) * M;
+    if (live && q < A) {
       rf::Dft<R, B, -1>::run(v[pk]);
 #pragma unroll
-      for (int m2 = 0; m2 < B; ++m2) ebuf[q * B + m2] = rf::mul(v[pk][m2], tw[q * m2]);
+      for (int m2 = 0; m2 < B; ++m2) sp[q * B + m2] = rf::mul(v[pk][m2], tw[q * m2]);
     }
     __syncthreads();
-    if (q < B && live) {
+    if (live && q < B) {
 #pragma unroll
-      for (int n1 = 0; n1 < A; ++n1) v[pk][n1] = ebuf[n1 * B + q];
+      for (int n1 = 0; n1 < A; ++n1) v[pk][n1] = sp[n1 * B + q];
       rf::Dft<R, A, -1>::run(v[pk]);
-#pragma unroll
-      for (int m1 = 0; m1 < A; ++m1) {
-        const int i2 = kept<M>(q + B * m1);
-        if (i2 >= 0) zk[((size_t)grp * P + pk) * N2 + i2] = v[pk][m1];
-      }
     }
     __syncthreads();
+    if (live && q < B) {
+#pragma unroll
+      for (int m1 = 0; m1 < A; ++m1) sp[q + B * m1] = v[pk][m1];
+    }
   }
+  __syncthreads();
 
   // ---- epilogue: unpack, project (T^T), CG direction update, <r, C r>
   double dp0 = 0.0, dp1 = 0.0, dp2 = 0.0;
@@ -444,52 +502,65 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_last_fast(Geo g,
   for (int t = tid; t < G * 2 * N2; t += nthr) {
     const int gpe = t / (2 * N2), rem = t - gpe * 2 * N2;
     const int row = rem / N2, i2 = rem - row * N2;
-    const int qp = blockIdx.x * G + gpe;
-    if (qp >= g.Q) continue;
-    int hh, kk1;
-    decode_pair(g, qp, hh, kk1);
-    const bool self = (hh == 0 && kk1 == 0);
-    const bool rowB = (hh == 0 && kk1 != 0);
-    if (row == 1 && !rowB) continue;
+    const RowInfo& re = s_row[gpe];
+    if (!re.valid || (row == 1 && !re.rowB)) continue;
     const int k2 = fr(i2, N2);
-    const int lineK = (self ? 0 : row), lineM = (self ? 0 : 1 - row);
-    const int gK = 2 * gpe + lineK, gM = 2 * gpe + lineM;
-    const int jK = i2, jM = ixn(-k2, N2);
-    const int kk0 = row ? 0 : hh, kkk1 = row ? -kk1 : kk1;
-    const int ii1 = row ? ixn(-kk1, N1) : ixn(kk1, N1);
-    const double wt = (hh == 0) ? 1.0 : 2.0;
+    const int lineK = re.self ? 0 : row, lineM = re.self ? 0 : 1 - row;
+    const Cx<R>* zK = stage + (size_t)(2 * gpe + lineK) * P * M;
+    const Cx<R>* zM = stage + (size_t)(2 * gpe + lineM) * P * M;
+    const int jK = padpos(i2, N2, M), jM = padpos(ixn(-k2, N2), N2, M);
+    const int kk0 = row ? 0 : re.h0, kk1 = row ? -re.k1 : re.k1;
+    const int ii1 = row ? re.i1B : re.i1A;
+    const double wt = (re.h0 == 0) ? 1.0 : 2.0;
     double Tb[3][2];
-    basis(g, kk0, kkk1, k2, Tb);
+    basis_t<D, DUAL>(g, kk0, kk1, k2, Tb);
+#pragma unroll
     for (int l = 0; l < L; ++l) {
       if (mode == LAST_CG && !s_act[l]) continue;
-      Cx<double> wv[3];
+      Cx<double> rv[m], pv[m], sv[m], bv[m];
+#pragma unroll
+      for (int c = 0; c < m; ++c) {
+        const size_t idx = ((size_t)(c * g.H0 + kk0) * N1 + ii1) * N2 + i2;
+        if (mode == LAST_CG) {
+          rv[c] = U.r[l][idx];
+          if (it > 0) {
+            pv[c] = U.p[l][idx];
+            sv[c] = U.s[l][idx];
+          }
+        } else if (mode == LAST_RESID) {
+          bv[c] = U.b[l][idx];
+        }
+      }
+      Cx<double> wv[D];
+#pragma unroll
       for (int gam = 0; gam < d; ++gam) {
         const int f = l * d + gam, pk = f >> 1;
-        const Cx<R> za = zk[((size_t)gK * P + pk) * N2 + jK];
-        const Cx<R> zb = zk[((size_t)gM * P + pk) * N2 + jM];
+        const Cx<R> za = zK[pk * M + jK];
+        const Cx<R> zb = zM[pk * M + jM];
         if ((f & 1) == 0)
           wv[gam] = cx(((double)za.x + (double)zb.x) * sc_m, ((double)za.y - (double)zb.y) * sc_m);
         else
           wv[gam] = cx(((double)za.y + (double)zb.y) * sc_m, -((double)za.x - (double)zb.x) * sc_m);
       }
+#pragma unroll
       for (int c = 0; c < m; ++c) {
         Cx<double> w = cx(0.0, 0.0);
+#pragma unroll
         for (int gam = 0; gam < d; ++gam) w = w + wv[gam] * Tb[gam][c];
         const size_t idx = ((size_t)(c * g.H0 + kk0) * N1 + ii1) * N2 + i2;
         double e;
         if (mode == LAST_CG) {
-          const Cx<double> rv = U.r[l][idx];
           const double b = s_beta[l];
           if (it == 0) {
-            U.p[l][idx] = rv;
+            U.p[l][idx] = rv[c];
             U.s[l][idx] = w;
           } else {
-            U.p[l][idx] = rv + U.p[l][idx] * b;
-            U.s[l][idx] = w + U.s[l][idx] * b;
+            U.p[l][idx] = rv[c] + pv[c] * b;
+            U.s[l][idx] = w + sv[c] * b;
           }
-          e = wt * (rv.x * w.x + rv.y * w.y);
+          e = wt * (rv[c].x * w.x + rv[c].y * w.y);
         } else if (mode == LAST_RESID) {
-          const Cx<double> rn = U.b[l][idx] - w;
+          const Cx<double> rn = bv[c] - w;
           U.r[l][idx] = rn;
           e = wt * (rn.x * rn.x + rn.y * rn.y);
         } else {
@@ -567,52 +638,59 @@ bool fast_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t s
   return false;
 }
 
-template <int M, int P>
+template <int M>
 static constexpr int pairs_per_block() {
   return (M >= 625) ? 2 : ((M >= 125) ? 4 : (256 / (2 * Cfg<M>::T)));
 }
 
-// Row pairs per block of the specialised row passes for (M, P), or 0 when
-// no specialisation exists (then the generic passes run).
-int fast_row_pairs(int M, int P) {
-  if (std::getenv("HOM_NO_FAST")) return 0;
-#define HOM_RP(MM, PP) \
-  if (M == MM && P == PP) return pairs_per_block<MM, PP>();
-  HOM_RP(625, 1) HOM_RP(625, 2) HOM_RP(125, 1) HOM_RP(125, 2) HOM_RP(81, 1) HOM_RP(81, 2) HOM_RP(25, 1)
-  HOM_RP(25, 2) HOM_RP(81, 3) HOM_RP(81, 5)
-#undef HOM_RP
-  return 0;
+static bool row_supported(int M, int D, int L) {
+  if (D == 2) return (M == 625 || M == 125 || M == 81 || M == 25) && (L == 1 || L == 2);
+  return M == 81 && L >= 1 && L <= 3;
 }
 
-template <int M, int P>
+// Row pairs per block of the specialised row passes, or 0 when no
+// specialisation exists (then the generic passes run).
+int fast_row_pairs(int M, int D, int L) {
+  if (std::getenv("HOM_NO_FAST")) return 0;
+  if (!row_supported(M, D, L)) return 0;
+  if (M == 625) return pairs_per_block<625>();
+  if (M == 125) return pairs_per_block<125>();
+  if (M == 81) return pairs_per_block<81>();
+  return pairs_per_block<25>();
+}
+
+template <int M, int D, int L, int DUAL>
 static hipError_t run_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, int jstep,
                           const int* iter_base, hipStream_t st) {
-  constexpr int G = pairs_per_block<M, P>();
-  constexpr int T = Cfg<M>::T, N2 = Cfg<M>::N;
+  constexpr int G = pairs_per_block<M>();
+  constexpr int T = Cfg<M>::T, P = (L * D + 1) / 2;
   const int nb = (g.Q + G - 1) / G;
-  if (first) {
-    const size_t lds = align16(M * sizeof(Cx<float>)) + align16((size_t)G * g.L * g.m * N2 * sizeof(Cx<double>)) +
-                       (size_t)2 * G * M * sizeof(Cx<float>);
-    return launch_k(k_first_fast<float, M, P, G>, dim3(nb, 1, n), round64(2 * G * T), lds, st, g, units, mode,
-                    jstep, iter_base);
-  }
-  const size_t lds = align16(M * sizeof(Cx<float>)) + (size_t)2 * G * M * sizeof(Cx<float>) +
-                     (size_t)2 * G * P * N2 * sizeof(Cx<float>);
-  return launch_k(k_last_fast<float, M, P, G>, dim3(nb, 1, n), round64(2 * G * T), lds, st, g, units, mode, jstep,
-                  iter_base);
+  const size_t lds = align16(M * sizeof(Cx<float>)) + (size_t)2 * G * P * M * sizeof(Cx<float>);
+  if (first)
+    return launch_k(k_first_fast<float, M, D, L, DUAL, G>, dim3(nb, 1, n), round64(2 * G * T), lds, st, g, units,
+                    mode, jstep, iter_base);
+  return launch_k(k_last_fast<float, M, D, L, DUAL, G>, dim3(nb, 1, n), round64(2 * G * T), lds, st, g, units, mode,
+                  jstep, iter_base);
+}
+
+template <int M, int D, int L>
+static hipError_t run_row_d(bool first, const Geo& g, const UnitDev* units, int n, int mode, int jstep,
+                            const int* iter_base, hipStream_t st) {
+  return g.dual ? run_row<M, D, L, 1>(first, g, units, n, mode, jstep, iter_base, st)
+                : run_row<M, D, L, 0>(first, g, units, n, mode, jstep, iter_base, st);
 }
 
 bool fast_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, int jstep, const int* iter_base,
               hipStream_t st, hipError_t* err) {
-  if (!fast_row_pairs(g.M[2], g.P)) return false;
-  const int M = g.M[2], P = g.P;
-#define HOM_RW(MM, PP)                                                       \
-  if (M == MM && P == PP) {                                                 \
-    *err = run_row<MM, PP>(first, g, units, n, mode, jstep, iter_base, st); \
-    return true;                                                            \
+  if (!fast_row_pairs(g.M[2], g.d, g.L)) return false;
+  const int M = g.M[2], D = g.d, L = g.L;
+#define HOM_RW(MM, DD, LL)                                                          \
+  if (M == MM && D == DD && L == LL) {                                             \
+    *err = run_row_d<MM, DD, LL>(first, g, units, n, mode, jstep, iter_base, st);  \
+    return true;                                                                   \
   }
-  HOM_RW(625, 1) HOM_RW(625, 2) HOM_RW(125, 1) HOM_RW(125, 2) HOM_RW(81, 1) HOM_RW(81, 2) HOM_RW(25, 1)
-  HOM_RW(25, 2) HOM_RW(81, 3) HOM_RW(81, 5)
+  HOM_RW(625, 2, 1) HOM_RW(625, 2, 2) HOM_RW(125, 2, 1) HOM_RW(125, 2, 2) HOM_RW(81, 2, 1) HOM_RW(81, 2, 2)
+  HOM_RW(25, 2, 1) HOM_RW(25, 2, 2) HOM_RW(81, 3, 1) HOM_RW(81, 3, 2) HOM_RW(81, 3, 3)
 #undef HOM_RW
   return false;
 }

@@ -132,6 +132,6 @@ size_t incl_dev_size();
 bool fast_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st, hipError_t* err);
 bool fast_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, int jstep, const int* iter_base,
               hipStream_t st, hipError_t* err);
-int fast_row_pairs(int M, int P);
+int fast_row_pairs(int M, int D, int L);
 
 }  // namespace hom
