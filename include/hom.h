@@ -240,6 +240,74 @@ hom_status hom_batch_get_timing(hom_batch* b, double* ms_sum, int64_t* launches)
 
 void hom_batch_destroy(hom_batch* b);
 
+/* ---- Learned initial guess (measurement-independent helper of the solver).
+ * Fields on the doubled grid M = 2N - 1, real FP32, [nload][d][M0][M1](M2):
+ * component g of the fluctuation field of load l. */
+
+/* Values on the doubled grid of nload field vectors (primal dual = 0 or dual
+ * dual = 1 layout): u_l = F_M^-1 pad_M(T c_l) (eq. trig_connection), FP64
+ * arithmetic, written as FP32.  fields: host array of nload device pointers;
+ * out: device. */
+hom_status hom_field_to_grid(hom_problem* pb, int32_t dual, int32_t nload, const double* const* fields,
+                             float* out);
+
+/* Admissible field vectors from arbitrary real fields on the doubled grid:
+ * c_l = T(k)^T [F_M u_l](k) for k in Z_N (truncation P_N and projection on
+ * E_N or J_N, Def. projection), FP64 arithmetic.  in: device [nload][d][M^d];
+ * out: host array of nload device pointers (field layout). */
+hom_status hom_grid_to_field(hom_problem* pb, int32_t dual, int32_t nload, const float* in, double* const* out);
+
+/* Network input channels of a problem on the doubled grid, FP32 [2][M^d]:
+ * a(x)/<a> and log(max(a(x), 1e-3 <a>)/<a>), with a = trace(A_M)/d the
+ * coefficient on the doubled grid and <a> its mean.  out: device. */
+hom_status hom_net_input(hom_problem* pb, float* out);
+
+/* Pointwise energy weights on the doubled grid, FP32 [2][M^d]: channel 0
+ * max(a, 1e-3 <a>)/<a> for a = trace(A_M)/d (primal), channel 1 the same for
+ * b = trace((A^-1)_M)/d (dual): the weights of the double-grid quadrature of
+ * the energies (Lemma integral_eval_double_grid), kept positive.  out: device. */
+hom_status hom_net_weights(hom_problem* pb, float* out);
+
+/* U-Net surrogate (FP32, hand-written kernels): levels, base width, input and
+ * output channels, spatial size (2D: H, W; 3D: Z, H, W) and batch. */
+typedef struct {
+  int32_t d;
+  int32_t levels;
+  int32_t base;
+  int32_t cin;
+  int32_t cout;
+  int32_t size[3];
+  int32_t batch;
+} hom_unet_desc;
+
+typedef struct hom_unet hom_unet;
+
+/* Number of parameters and bytes of device work memory (activations,
+ * gradients, scratch) of a network. */
+hom_status hom_unet_sizes(const hom_unet_desc* desc, size_t* n_params, size_t* work_bytes);
+/* params, grads, adam_m, adam_v: device FP32 arrays of n_params each (caller
+ * owned; params initialised by the caller).  work: device, 256-byte aligned. */
+hom_status hom_unet_create(const hom_unet_desc* desc, float* params, float* grads, float* adam_m, float* adam_v,
+                           void* work, size_t work_bytes, void* stream, hom_unet** out);
+/* in: device [batch][cin][size]; out: device [batch][cout][size] or NULL. */
+hom_status hom_unet_forward(hom_unet* u, const float* in, float* out);
+/* Mean squared error of the last forward output against target (device); sets
+ * the output gradient; *loss on the host (synchronises the stream). */
+hom_status hom_unet_loss(hom_unet* u, const float* target, double* loss);
+/* Weighted mean squared error: sum_i w_i (out_i - target_i)^2 / n, output
+ * channel c taking weight channel c * wch / cout of weight [batch][wch][size]
+ * (device; cout must be a multiple of wch, 1 <= wch <= cout; NULL = unit
+ * weights).  Used with the coefficient as weight to approximate the energy
+ * norm of the field error. */
+hom_status hom_unet_loss_weighted(hom_unet* u, const float* target, const float* weight, int32_t wch,
+                                  double* loss);
+/* Parameter gradients of the last forward pass for the output gradient gout
+ * (device) or, when gout is NULL, the gradient set by hom_unet_loss. */
+hom_status hom_unet_backward(hom_unet* u, const float* gout);
+/* One Adam step (step >= 1 is the 1-based step count for bias correction). */
+hom_status hom_unet_adam(hom_unet* u, float lr, float beta1, float beta2, float eps, int32_t step);
+void hom_unet_destroy(hom_unet* u);
+
 #ifdef __cplusplus
 }
 #endif

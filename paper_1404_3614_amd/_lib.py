@@ -28,6 +28,11 @@ class Info(C.Structure):
                 ("rel_res_recur", C.c_double), ("rel_res_true", C.c_double)]
 
 
+class UNetDesc(C.Structure):
+    _fields_ = [("d", C.c_int32), ("levels", C.c_int32), ("base", C.c_int32), ("cin", C.c_int32),
+                ("cout", C.c_int32), ("size", C.c_int32 * 3), ("batch", C.c_int32)]
+
+
 class Result(C.Structure):
     _fields_ = [("A_up", C.c_double * 9), ("B_up", C.c_double * 9), ("A_low", C.c_double * 9),
                 ("A_mean", C.c_double * 9), ("D", C.c_double * 9)]
@@ -53,6 +58,19 @@ EXPORTS = {
                                     C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p]),
     "hom_profile_passes": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "hom_destroy": (None, [C.c_void_p]),
+    "hom_field_to_grid": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
+    "hom_grid_to_field": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "hom_net_input": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "hom_net_weights": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "hom_unet_sizes": (C.c_int32, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "hom_unet_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                    C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "hom_unet_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hom_unet_loss": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
+    "hom_unet_loss_weighted": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
+    "hom_unet_backward": (C.c_int32, [C.c_void_p, C.c_void_p]),
+    "hom_unet_adam": (C.c_int32, [C.c_void_p, C.c_float, C.c_float, C.c_float, C.c_float, C.c_int32]),
+    "hom_unet_destroy": (None, [C.c_void_p]),
     "hom_batch_workspace_bytes": (C.c_int32, [C.c_int32, C.POINTER(C.c_size_t)]),
     "hom_batch_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.c_void_p, C.c_size_t,
                                      C.POINTER(C.c_void_p)]),

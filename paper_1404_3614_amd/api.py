@@ -208,6 +208,45 @@ class Problem:
         L.check(L.load().hom_profile_passes(self.h, int(dual), int(n), int(reps), ms), "hom_profile_passes")
         return dict(first=ms[0], mid_inv=ms[1], apply=ms[2], mid_fwd=ms[3], last=ms[4])
 
+    @property
+    def M(self):
+        return tuple(2 * n - 1 for n in self.N)
+
+    def field_to_grid(self, fields, dual=False):
+        """Doubled-grid values (float32, [nload][d][*M]) of field vectors."""
+        n = len(fields)
+        out = torch.empty((n, self.d) + self.M, dtype=torch.float32, device=_dev())
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_field_to_grid(self.h, int(dual), n, _dptrs(fields), C.c_void_p(out.data_ptr())),
+                "hom_field_to_grid")
+        return out
+
+    def grid_to_field(self, grid, dual=False):
+        """Admissible field vectors (projected on E_N / J_N) from doubled-grid fields [nload][d][*M]."""
+        grid = grid.contiguous()
+        n = grid.shape[0]
+        out = [self.new_field(dual) for _ in range(n)]
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_grid_to_field(self.h, int(dual), n, C.c_void_p(grid.data_ptr()), _dptrs(out)),
+                "hom_grid_to_field")
+        return out
+
+    def net_input(self, out=None):
+        """Network input channels [2][*M] (float32) of the coefficient of this problem."""
+        if out is None:
+            out = torch.empty((2,) + self.M, dtype=torch.float32, device=_dev())
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_net_input(self.h, C.c_void_p(out.data_ptr())), "hom_net_input")
+        return out
+
+    def net_weights(self, out=None):
+        """Energy weights [2][*M] (float32) of the primal and dual quadratures of this problem."""
+        if out is None:
+            out = torch.empty((2,) + self.M, dtype=torch.float32, device=_dev())
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_net_weights(self.h, C.c_void_p(out.data_ptr())), "hom_net_weights")
+        return out
+
     def solve_bounds(self, tol=1e-6, maxit=10000, allow_not_converged=False):
         xp, ip = self.solve(False, tol=tol, maxit=maxit, allow_not_converged=allow_not_converged)
         xd, idl = self.solve(True, tol=tol, maxit=maxit, allow_not_converged=allow_not_converged)

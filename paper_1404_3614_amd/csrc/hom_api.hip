@@ -234,7 +234,7 @@ size_t carve(const hom_desc* desc, int max_loads, const Sizes& z, hom_problem* p
     if (pb) pb->slot[k] = sb;
   }
   {
-    const int P = packs(d, d);
+    const int P = packs(std::max(d, L), d);
     void* a = ptr(take((size_t)z.N[0] * z.N[1] * z.M[2] * P * sizeof(Cx<double>)));
     void* b = d == 3 ? ptr(take((size_t)z.N[0] * z.M[1] * z.M[2] * P * sizeof(Cx<double>))) : nullptr;
     double* q0 = (double*)ptr(take(npts * 9 * sizeof(double)));
@@ -1055,6 +1055,80 @@ hom_status hom_profile_passes(hom_problem* pb, int32_t dual, int32_t nload, int3
   if (s != HOM_OK) return s;
   HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
   return profile_units(g, sb.unit, 1, fp32, st, reps, ms_out);
+}
+
+// Unit for the FP64 grid transfers of one problem (bounds buffers, nload loads).
+static void grid_unit(hom_problem* pb, int k, int nload, UnitDev* hu) {
+  std::memset(hu, 0, sizeof(*hu));
+  SlotBufs& sb = pb->slot[k];
+  hu->coef = pb->coef64[k];
+  hu->ahat = pb->ahat_half[k];
+  for (int l = 0; l < nload; ++l) {
+    hu->r[l] = sb.r[l];
+    hu->p[l] = sb.p[l];
+    hu->s[l] = sb.s[l];
+    hu->b[l] = sb.b[l];
+    hu->x[l] = sb.tmp[l];
+  }
+  hu->bufA = pb->bbufA;
+  hu->bufB = pb->bbufB;
+  hu->part_g = sb.part_g;
+  hu->part_d = sb.part_d;
+  hu->part_q = pb->bpart_q[k];
+  hu->sc = sb.sc;
+}
+
+hom_status hom_field_to_grid(hom_problem* pb, int32_t dual, int32_t nload, const double* const* fields, float* out) {
+  if (!pb || !fields || !out || (dual != 0 && dual != 1) || nload < 1 || nload > pb->max_loads) return HOM_E_INVALID;
+  for (int l = 0; l < nload; ++l)
+    if (!fields[l]) return HOM_E_INVALID;
+  const int k = dual;
+  hipStream_t st = pb->stream;
+  Geo g = make_geo(pb, k, nload, false);
+  UnitDev* hu = &pb->host_bunit[k];
+  grid_unit(pb, k, nload, hu);
+  for (int l = 0; l < nload; ++l) hu->x[l] = reinterpret_cast<Cx<double>*>(const_cast<double*>(fields[l]));
+  hu->grid = out;
+  HIPCHK(hipMemcpyAsync(pb->bunit[k], hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_first<double>(g, pb->bunit[k], 1, FIRST_FIELD, 0, nullptr, st));
+  if (g.d == 3) HIPCHK(launch_mid<double>(g, pb->bunit[k], 1, 1, st));
+  HIPCHK(launch_apply<double>(g, pb->bunit[k], 1, APPLY_GRID, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return HOM_OK;
+}
+
+hom_status hom_grid_to_field(hom_problem* pb, int32_t dual, int32_t nload, const float* in, double* const* out) {
+  if (!pb || !in || !out || (dual != 0 && dual != 1) || nload < 1 || nload > pb->max_loads) return HOM_E_INVALID;
+  for (int l = 0; l < nload; ++l)
+    if (!out[l]) return HOM_E_INVALID;
+  const int k = dual;
+  hipStream_t st = pb->stream;
+  Geo g = make_geo(pb, k, nload, false);
+  UnitDev* hu = &pb->host_bunit[k];
+  grid_unit(pb, k, nload, hu);
+  for (int l = 0; l < nload; ++l) hu->s[l] = reinterpret_cast<Cx<double>*>(out[l]);
+  hu->grid = const_cast<float*>(in);
+  HIPCHK(hipMemcpyAsync(pb->bunit[k], hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
+  HIPCHK(launch_apply<double>(g, pb->bunit[k], 1, APPLY_FWD, st));
+  if (g.d == 3) HIPCHK(launch_mid<double>(g, pb->bunit[k], 1, 0, st));
+  HIPCHK(launch_last<double>(g, pb->bunit[k], 1, LAST_MATVEC, 0, nullptr, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return HOM_OK;
+}
+
+hom_status hom_net_input(hom_problem* pb, float* out) {
+  if (!pb || !out) return HOM_E_INVALID;
+  HIPCHK(launch_net_input(pb->coef64[0], pb->z.nc, pb->z.d, (long)pb->z.Mt, pb->ahat_half[0], (long)pb->z.S, out, 0,
+                          pb->stream));
+  return HOM_OK;
+}
+
+hom_status hom_net_weights(hom_problem* pb, float* out) {
+  if (!pb || !out) return HOM_E_INVALID;
+  for (int k = 0; k < 2; ++k)
+    HIPCHK(launch_net_input(pb->coef64[k], pb->z.nc, pb->z.d, (long)pb->z.Mt, pb->ahat_half[k], (long)pb->z.S,
+                            out + (size_t)k * pb->z.Mt, 1, pb->stream));
+  return HOM_OK;
 }
 
 struct hom_batch {

@@ -1,0 +1,821 @@
+// Surrogate network for the CG initial guess: a periodic U-Net in FP32 with
+// hand-written forward and backward kernels, sequenced by a small native
+// runtime (hom_unet_*).  The prediction only has to be cheap and close: it is
+// projected onto E_N / J_N by the solver, so any output gives an admissible
+// starting field and the bounds stay guaranteed.
+//
+// Tensors are [B][C][Z][H][W] (Z = 1 in 2D), FP32.  A "view" addresses the
+// channel slice [off, off + C) of a buffer with Ctot channels, so skip
+// connections are concatenated in place.
+//
+// Architecture (levels L, base width c, widths c_l = c 2^l, sizes s_0 = input,
+// s_{l+1} = ceil(s_l / 2)):
+//   encoder l < L-1: conv3(in_l -> c_l) relu, conv3(c_l -> c_l) relu = skip_l,
+//                    in_{l+1} = avgpool2(skip_l) (periodic, ceil)
+//   bottleneck     : conv3(in_{L-1} -> c_{L-1}) relu, conv3 relu = dec_{L-1}
+//   decoder l      : up = nearest-upsample(dec_{l+1}) to s_l, conv3(c_{l+1} -> c_l) relu,
+//                    concat [that, skip_l], conv3(2 c_l -> c_l) relu, conv3 relu = dec_l
+//   head           : conv1(c_0 -> cout)
+// Parameters: one flat FP32 array, per conv layer in this order w[cout][cin][taps]
+// then b[cout] (taps = 3^d, row-major over (z, y, x) offsets -1..1).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/hom.h"
+#include "hom_internal.hpp"
+
+namespace hom {
+namespace cnn {
+
+struct View {
+  float* p;
+  int C, Ctot, off;
+};
+
+// ------------------------------------------------------------------ convolution
+// out[b, off_o + co, q] = act( bias[co] + sum_ci sum_tap w[co, ci, tap] in[b, off_i + ci, q + tap] )
+// periodic neighbours; KS = 3 (or 1).  Block: TPX output points x COT output
+// channels; threads: each handles PPT points x CPT channels.
+constexpr int CT = 256;      // threads
+constexpr int COT = 32;      // output channels per block
+constexpr int CIC = 8;       // input channels per LDS chunk
+
+__device__ __forceinline__ int wrap(int i, int n) {
+  i %= n;
+  return i < 0 ? i + n : i;
+}
+
+// 2D tile 16 x 16 points, 3D tile 4 x 8 x 8
+template <int D>
+struct Tile {
+  static constexpr int X = D == 2 ? 16 : 8, Y = D == 2 ? 16 : 8, Z = D == 2 ? 1 : 4;
+  static constexpr int NP = X * Y * Z;
+};
+
+template <int D, int KS>
+__global__ __launch_bounds__(CT) void k_conv_fwd(const float* __restrict__ in, int Cin, int inCtot, int inOff,
+                                                 const float* __restrict__ w, const float* __restrict__ bias,
+                                                 float* __restrict__ out, int Cout, int outCtot, int outOff, int Zs,
+                                                 int Hs, int Ws, int relu, int accumulate) {
+  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z, NP = Tile<D>::NP;
+  constexpr int R = KS / 2;
+  constexpr int HX = TX + 2 * R, HY = TY + 2 * R, HZ = (D == 3) ? TZ + 2 * R : 1;
+  constexpr int TAPS = (D == 3) ? KS * KS * KS : KS * KS;
+  constexpr int PPT = NP / (CT / 8);   // points per thread (8 channel groups of 4)
+  constexpr int CPT = COT / 8;
+  __shared__ float s_in[CIC][HZ * HY * HX];
+  __shared__ float s_w[CIC][TAPS][COT];
+  const int tiles_x = (Ws + TX - 1) / TX, tiles_y = (Hs + TY - 1) / TY;
+  int tile = blockIdx.x;
+  const int tx0 = (tile % tiles_x) * TX;
+  tile /= tiles_x;
+  const int ty0 = (tile % tiles_y) * TY;
+  tile /= tiles_y;
+  const int tz0 = tile * TZ;
+  const int co0 = blockIdx.y * COT;
+  const int b = blockIdx.z;
+  const int tid = threadIdx.x;
+  const int cg = tid & 7;           // channel group: channels co0 + cg*CPT ..
+  const int pg = tid >> 3;          // point group: points pg*PPT ..
+  const size_t plane = (size_t)Zs * Hs * Ws;
+  float acc[PPT][CPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i)
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) acc[i][j] = 0.f;
+  int px[PPT], py[PPT], pz[PPT];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int pidx = pg * PPT + i;
+    px[i] = pidx % TX;
+    py[i] = (pidx / TX) % TY;
+    pz[i] = pidx / (TX * TY);
+  }
+  for (int ci0 = 0; ci0 < Cin; ci0 += CIC) {
+    __syncthreads();
+    for (int t = tid; t < CIC * HZ * HY * HX; t += CT) {
+      const int c = t / (HZ * HY * HX), r = t - c * (HZ * HY * HX);
+      const int hx = r % HX, hy = (r / HX) % HY, hz = r / (HX * HY);
+      float v = 0.f;
+      if (ci0 + c < Cin) {
+        const int gx = wrap(tx0 + hx - R, Ws), gy = wrap(ty0 + hy - R, Hs);
+        const int gz = (D == 3) ? wrap(tz0 + hz - R, Zs) : 0;
+        v = in[((size_t)b * inCtot + inOff + ci0 + c) * plane + ((size_t)gz * Hs + gy) * Ws + gx];
+      }
+      s_in[c][r] = v;
+    }
+    for (int t = tid; t < CIC * TAPS * COT; t += CT) {
+      const int co = t % COT, r = t / COT;
+      const int tap = r % TAPS, c = r / TAPS;
+      float v = 0.f;
+      if (ci0 + c < Cin && co0 + co < Cout) v = w[((size_t)(co0 + co) * Cin + ci0 + c) * TAPS + tap];
+      s_w[c][tap][co] = v;
+    }
+    __syncthreads();
+#pragma unroll 1
+    for (int c = 0; c < CIC; ++c) {
+#pragma unroll
+      for (int tap = 0; tap < TAPS; ++tap) {
+        const int kx = tap % KS, ky = (tap / KS) % KS, kz = tap / (KS * KS);
+        float wv[CPT];
+#pragma unroll
+        for (int j = 0; j < CPT; ++j) wv[j] = s_w[c][tap][cg * CPT + j];
+#pragma unroll
+        for (int i = 0; i < PPT; ++i) {
+          const float v = s_in[c][((pz[i] + kz) * HY + py[i] + ky) * HX + px[i] + kx];
+#pragma unroll
+          for (int j = 0; j < CPT; ++j) acc[i][j] = fmaf(wv[j], v, acc[i][j]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int gx = tx0 + px[i], gy = ty0 + py[i], gz = tz0 + pz[i];
+    if (gx >= Ws || gy >= Hs || gz >= Zs) continue;
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int co = co0 + cg * CPT + j;
+      if (co >= Cout) continue;
+      float v = acc[i][j] + (bias ? bias[co] : 0.f);
+      if (relu) v = fmaxf(v, 0.f);
+      float* o = out + ((size_t)b * outCtot + outOff + co) * plane + ((size_t)gz * Hs + gy) * Ws + gx;
+      if (accumulate) v += *o;
+      *o = v;
+    }
+  }
+}
+
+// Weight gradient partials: for a block of (COT output channels x CIC input
+// channels) and one chunk of points, sum over the chunk of g[co, q] in[ci, q + tap];
+// partial sums go to part[chunk][co][ci][tap] (summed in a fixed order later).
+template <int D, int KS>
+__global__ __launch_bounds__(CT) void k_conv_wgrad(const float* __restrict__ in, int Cin, int inCtot, int inOff,
+                                                   const float* __restrict__ g, int Cout, int gCtot, int gOff, int Zs,
+                                                   int Hs, int Ws, int B, int chunk, float* __restrict__ part) {
+  constexpr int TAPS = (D == 3) ? KS * KS * KS : KS * KS;
+  constexpr int R = KS / 2;
+  constexpr int PT = 64;  // points per LDS stage
+  __shared__ float s_g[PT][COT];
+  __shared__ float s_x[PT][CIC][TAPS];
+  const int co0 = blockIdx.y * COT;
+  const int ci0 = (blockIdx.z % ((Cin + CIC - 1) / CIC)) * CIC;
+  const size_t plane = (size_t)Zs * Hs * Ws;
+  const size_t total = (size_t)B * plane;
+  const size_t q0 = (size_t)blockIdx.x * chunk;
+  const size_t q1 = q0 + chunk < total ? q0 + chunk : total;
+  const int tid = threadIdx.x;
+  // thread -> (co, ci, tap) outputs: COT*CIC*TAPS outputs over CT threads
+  constexpr int NOUT = COT * CIC * TAPS;
+  constexpr int OPT = (NOUT + CT - 1) / CT;
+  float acc[OPT];
+#pragma unroll
+  for (int i = 0; i < OPT; ++i) acc[i] = 0.f;
+  for (size_t qs = q0; qs < q1; qs += PT) {
+    __syncthreads();
+    for (int t = tid; t < PT * COT; t += CT) {
+      const int p = t / COT, co = t % COT;
+      const size_t q = qs + p;
+      float v = 0.f;
+      if (q < q1 && co0 + co < Cout) {
+        const size_t bb = q / plane, r = q % plane;
+        v = g[(bb * gCtot + gOff + co0 + co) * plane + r];
+      }
+      s_g[p][co] = v;
+    }
+    for (int t = tid; t < PT * CIC * TAPS; t += CT) {
+      const int p = t / (CIC * TAPS), r = t % (CIC * TAPS);
+      const int c = r / TAPS, tap = r % TAPS;
+      const size_t q = qs + p;
+      float v = 0.f;
+      if (q < q1 && ci0 + c < Cin) {
+        const size_t bb = q / plane, rr = q % plane;
+        const int x = rr % Ws, y = (rr / Ws) % Hs, z = rr / ((size_t)Ws * Hs);
+        const int kx = tap % KS, ky = (tap / KS) % KS, kz = tap / (KS * KS);
+        const int gx = wrap(x + kx - R, Ws), gy = wrap(y + ky - R, Hs), gz = (D == 3) ? wrap(z + kz - R, Zs) : 0;
+        v = in[(bb * inCtot + inOff + ci0 + c) * plane + ((size_t)gz * Hs + gy) * Ws + gx];
+      }
+      s_x[p][c][tap] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < OPT; ++i) {
+      const int o = tid + i * CT;
+      if (o < NOUT) {
+        const int co = o / (CIC * TAPS), r = o % (CIC * TAPS);
+        const int c = r / TAPS, tap = r % TAPS;
+        float s = acc[i];
+        for (int p = 0; p < PT; ++p) s = fmaf(s_g[p][co], s_x[p][c][tap], s);
+        acc[i] = s;
+      }
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < OPT; ++i) {
+    const int o = tid + i * CT;
+    if (o < NOUT) {
+      const int co = o / (CIC * TAPS), r = o % (CIC * TAPS);
+      const int c = r / TAPS, tap = r % TAPS;
+      if (co0 + co < Cout && ci0 + c < Cin)
+        part[(((size_t)blockIdx.x * Cout + co0 + co) * Cin + ci0 + c) * TAPS + tap] = acc[i];
+    }
+  }
+}
+
+// Sum of the partials over chunks (fixed order) into the gradient (accumulate).
+__global__ void k_reduce_chunks(const float* __restrict__ part, int nchunk, size_t n, float* __restrict__ grad) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + t];
+    grad[t] += s;
+  }
+}
+
+// Bias gradient: db[co] += sum_{b, q} g[b, co, q]  (one block per channel, fixed order)
+__global__ void k_bias_grad(const float* __restrict__ g, int Cout, int gCtot, int gOff, size_t plane, int B,
+                            float* __restrict__ db) {
+  __shared__ float red[CT];
+  const int co = blockIdx.x;
+  float s = 0.f;
+  for (int b = 0; b < B; ++b) {
+    const float* p = g + ((size_t)b * gCtot + gOff + co) * plane;
+    for (size_t q = threadIdx.x; q < plane; q += CT) s += p[q];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = CT / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[co] += red[0];
+}
+
+// w'[ci][co][tap'] = w[co][ci][taps-1-tap]: the adjoint of a periodic convolution.
+__global__ void k_flip(const float* __restrict__ w, int Cout, int Cin, int taps, float* __restrict__ wf) {
+  const size_t n = (size_t)Cout * Cin * taps;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int tap = t % taps;
+    const size_t r = t / taps;
+    const int ci = r % Cin, co = r / Cin;
+    wf[((size_t)ci * Cout + co) * taps + (taps - 1 - tap)] = w[t];
+  }
+}
+
+// g <- g * (y > 0) on a view (relu derivative; y is the relu output)
+__global__ void k_relu_mask(float* g, const float* y, int C, int gCtot, int gOff, int yCtot, int yOff, size_t plane,
+                            int B) {
+  const size_t n = (size_t)B * C * plane;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const size_t q = t % plane, r = t / plane;
+    const int c = r % C, b = r / C;
+    const float yv = y[((size_t)b * yCtot + yOff + c) * plane + q];
+    float& gv = g[((size_t)b * gCtot + gOff + c) * plane + q];
+    if (!(yv > 0.f)) gv = 0.f;
+  }
+}
+
+// 2x2(x2) periodic average pooling with ceil sizes; output point j covers inputs (2j + o) mod n.
+template <int D>
+__global__ void k_pool(const float* __restrict__ in, int inCtot, int inOff, float* __restrict__ out, int outCtot,
+                       int outOff, int C, int Z, int H, int W, int Zo, int Ho, int Wo, int B) {
+  const size_t n = (size_t)B * C * Zo * Ho * Wo;
+  const float sc = D == 3 ? 0.125f : 0.25f;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int x = t % Wo, y = (t / Wo) % Ho, z = (t / ((size_t)Wo * Ho)) % Zo;
+    const size_t r = t / ((size_t)Wo * Ho * Zo);
+    const int c = r % C, b = r / C;
+    const float* src = in + ((size_t)b * inCtot + inOff + c) * ((size_t)Z * H * W);
+    float s = 0.f;
+    for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const int gz = D == 3 ? (2 * z + dz) % Z : 0;
+          s += src[((size_t)gz * H + (2 * y + dy) % H) * W + (2 * x + dx) % W];
+        }
+    out[((size_t)b * outCtot + outOff + c) * ((size_t)Zo * Ho * Wo) + ((size_t)z * Ho + y) * Wo + x] = s * sc;
+  }
+}
+
+// adjoint of k_pool, accumulated into gin: gin[q] += sc * sum over outputs covering q
+template <int D>
+__global__ void k_pool_bwd(const float* __restrict__ gout, int goCtot, int goOff, float* __restrict__ gin,
+                           int giCtot, int giOff, int C, int Z, int H, int W, int Zo, int Ho, int Wo, int B) {
+  const size_t n = (size_t)B * C * Z * H * W;
+  const float sc = D == 3 ? 0.125f : 0.25f;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int x = t % W, y = (t / W) % H, z = (t / ((size_t)W * H)) % Z;
+    const size_t r = t / ((size_t)W * H * Z);
+    const int c = r % C, b = r / C;
+    // output indices j along an axis of length n (ceil(n/2) outputs) covering input i
+    auto cands = [](int i, int nn, int no, int* js) {
+      int k = 0;
+      js[k++] = i / 2;
+      if ((nn & 1) && i == 0) js[k++] = no - 1;
+      return k;
+    };
+    int jx[2], jy[2], jz[2] = {0, 0};
+    const int nx = cands(x, W, Wo, jx), ny = cands(y, H, Ho, jy);
+    const int nz = D == 3 ? cands(z, Z, Zo, jz) : 1;
+    const float* g = gout + ((size_t)b * goCtot + goOff + c) * ((size_t)Zo * Ho * Wo);
+    float s = 0.f;
+    for (int a = 0; a < nz; ++a)
+      for (int bq = 0; bq < ny; ++bq)
+        for (int e = 0; e < nx; ++e) s += g[((size_t)jz[a] * Ho + jy[bq]) * Wo + jx[e]];
+    gin[((size_t)b * giCtot + giOff + c) * ((size_t)Z * H * W) + ((size_t)z * H + y) * W + x] += s * sc;
+  }
+}
+
+// nearest upsampling to (Z, H, W): out[q] = in[q / 2]
+template <int D>
+__global__ void k_up(const float* __restrict__ in, int inCtot, int inOff, float* __restrict__ out, int outCtot,
+                     int outOff, int C, int Zi, int Hi, int Wi, int Z, int H, int W, int B) {
+  const size_t n = (size_t)B * C * Z * H * W;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int x = t % W, y = (t / W) % H, z = (t / ((size_t)W * H)) % Z;
+    const size_t r = t / ((size_t)W * H * Z);
+    const int c = r % C, b = r / C;
+    const int zi = D == 3 ? z / 2 : 0;
+    out[((size_t)b * outCtot + outOff + c) * ((size_t)Z * H * W) + ((size_t)z * H + y) * W + x] =
+        in[((size_t)b * inCtot + inOff + c) * ((size_t)Zi * Hi * Wi) + ((size_t)zi * Hi + y / 2) * Wi + x / 2];
+  }
+}
+
+// adjoint of k_up: gin[j] = sum of gout over the (up to 2^d) outputs mapping to j
+template <int D>
+__global__ void k_up_bwd(const float* __restrict__ gout, int goCtot, int goOff, float* __restrict__ gin, int giCtot,
+                         int giOff, int C, int Zi, int Hi, int Wi, int Z, int H, int W, int B) {
+  const size_t n = (size_t)B * C * Zi * Hi * Wi;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int x = t % Wi, y = (t / Wi) % Hi, z = (t / ((size_t)Wi * Hi)) % Zi;
+    const size_t r = t / ((size_t)Wi * Hi * Zi);
+    const int c = r % C, b = r / C;
+    const float* g = gout + ((size_t)b * goCtot + goOff + c) * ((size_t)Z * H * W);
+    float s = 0.f;
+    for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+      for (int dy = 0; dy < 2; ++dy)
+        for (int dx = 0; dx < 2; ++dx) {
+          const int oz = D == 3 ? 2 * z + dz : 0, oy = 2 * y + dy, ox = 2 * x + dx;
+          if (oz < Z && oy < H && ox < W) s += g[((size_t)oz * H + oy) * W + ox];
+        }
+    gin[((size_t)b * giCtot + giOff + c) * ((size_t)Zi * Hi * Wi) + ((size_t)z * Hi + y) * Wi + x] = s;
+  }
+}
+
+// (Weighted) MSE: partial sums of w (o - t)^2 per block, gradient 2 w (o - t) / n.
+// Element i = ((b * cout + c) * plane + q) takes weight channel c * wch / cout of
+// weight[b][wch][plane]; weight == nullptr means w = 1.
+__global__ void k_mse(const float* __restrict__ o, const float* __restrict__ t, size_t n, const float* __restrict__ weight,
+                      int wch, int cout, size_t plane, float* __restrict__ grad, double* __restrict__ part) {
+  __shared__ double red[CT];
+  double s = 0.0;
+  const float sc = 2.0f / (float)n;
+  for (size_t i = blockIdx.x * (size_t)CT + threadIdx.x; i < n; i += (size_t)gridDim.x * CT) {
+    const float dv = o[i] - t[i];
+    float w = 1.f;
+    if (weight) {
+      const size_t q = i % plane, r = i / plane;
+      const int c = (int)(r % cout);
+      const size_t b = r / cout;
+      w = weight[(b * wch + (size_t)c * wch / cout) * plane + q];
+    }
+    s += (double)w * dv * dv;
+    if (grad) grad[i] = sc * w * dv;
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = CT / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m1,
+                       float* __restrict__ m2, size_t n, float lr, float b1, float b2, float eps, float c1, float c2) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float gv = g[i];
+    const float a = b1 * m1[i] + (1.f - b1) * gv;
+    const float b = b2 * m2[i] + (1.f - b2) * gv * gv;
+    m1[i] = a;
+    m2[i] = b;
+    p[i] -= lr * (a / c1) / (sqrtf(b / c2) + eps);
+  }
+}
+
+__global__ void k_fill(float* p, size_t n, float v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+static int gridn(size_t n) {
+  size_t b = (n + CT - 1) / CT;
+  return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+
+// ------------------------------------------------------------------ runtime
+struct Conv {
+  int cin, cout, ks;
+  size_t w, b;          // offsets into the parameter array
+  int lvl;              // spatial level of input and output
+  View in, out;         // activations
+  View gin, gout;       // gradients
+  bool relu;
+  bool accumulate_gin;  // gradient of the input is shared with another consumer
+};
+
+struct Net {
+  hom_unet_desc desc;
+  hipStream_t st;
+  float* params;
+  float* grads;
+  float* m1;
+  float* m2;
+  size_t nparams;
+  char* work;
+  size_t work_bytes;
+  int levels;
+  int sz[8][3];         // per level (Z, H, W)
+  std::vector<Conv> convs;
+  // buffers per level (activations and gradients)
+  float* in0;           // input copy
+  float* out;           // network output
+  float* gout;          // gradient of the output
+  float* wflip;         // flipped weights scratch
+  float* wpart;         // weight-gradient partials
+  size_t wpart_floats;
+  double* lpart;        // loss partials
+  std::vector<float*> act_bufs;
+  // views for the non-conv ops
+  struct Pool { View in, out, gin, gout; int lvl; };
+  struct Up { View in, out, gin, gout; int lvl; };
+  std::vector<Pool> pools;
+  std::vector<Up> ups;
+};
+
+static size_t plane(const Net& n, int l) { return (size_t)n.sz[l][0] * n.sz[l][1] * n.sz[l][2]; }
+
+// Build the layer list; with base == nullptr only sizes are computed.
+static size_t build_net(Net& n, char* base, size_t* nparams) {
+  const hom_unet_desc& ds = n.desc;
+  const int d = ds.d, L = ds.levels, c0 = ds.base, B = ds.batch;
+  n.levels = L;
+  n.sz[0][0] = d == 3 ? ds.size[0] : 1;
+  n.sz[0][1] = d == 3 ? ds.size[1] : ds.size[0];
+  n.sz[0][2] = d == 3 ? ds.size[2] : ds.size[1];
+  for (int l = 1; l < L; ++l)
+    for (int a = 0; a < 3; ++a) n.sz[l][a] = (a == 0 && d == 2) ? 1 : (n.sz[l - 1][a] + 1) / 2;
+  size_t off = 0;
+  auto take = [&](size_t floats) -> float* {
+    float* p = base ? reinterpret_cast<float*>(base + off) : nullptr;
+    off += ((floats * sizeof(float) + 255) / 256) * 256;
+    return p;
+  };
+  size_t poff = 0;
+  auto conv = [&](int cin, int cout, int ks, int lvl, View in, View out, View gin, View gout, bool relu, bool acc) {
+    Conv c;
+    c.cin = cin;
+    c.cout = cout;
+    c.ks = ks;
+    c.lvl = lvl;
+    c.in = in;
+    c.out = out;
+    c.gin = gin;
+    c.gout = gout;
+    c.relu = relu;
+    c.accumulate_gin = acc;
+    const int taps = ks == 3 ? (d == 3 ? 27 : 9) : 1;
+    c.w = poff;
+    poff += (size_t)cout * cin * taps;
+    c.b = poff;
+    poff += cout;
+    n.convs.push_back(c);
+  };
+  auto buf = [&](int C, int l) -> View {
+    View v;
+    v.p = take((size_t)B * C * plane(n, l));
+    v.C = C;
+    v.Ctot = C;
+    v.off = 0;
+    if (base) n.act_bufs.push_back(v.p);
+    return v;
+  };
+  auto slice = [](View v, int off, int C) {
+    v.off += off;
+    v.C = C;
+    return v;
+  };
+  n.convs.clear();
+  n.pools.clear();
+  n.ups.clear();
+  std::vector<View> skip(L), gskip(L), cat(L), gcat(L);
+  View in = buf(ds.cin, 0), gin_dummy = buf(ds.cin, 0);
+  n.in0 = in.p;
+  View cur = in, gcur = gin_dummy;
+  int cprev = ds.cin;
+  for (int l = 0; l < L; ++l) {
+    const int cl = c0 << l;
+    View a = buf(cl, l), ga = buf(cl, l);
+    conv(cprev, cl, 3, l, cur, a, gcur, ga, true, false);
+    if (l < L - 1) {
+      cat[l] = buf(2 * cl, l);
+      gcat[l] = buf(2 * cl, l);
+      skip[l] = slice(cat[l], cl, cl);
+      gskip[l] = slice(gcat[l], cl, cl);
+      conv(cl, cl, 3, l, a, skip[l], ga, gskip[l], true, false);
+      View p = buf(cl, l + 1), gp = buf(cl, l + 1);
+      Net::Pool pl;
+      pl.in = skip[l];
+      pl.out = p;
+      pl.gin = gskip[l];
+      pl.gout = gp;
+      pl.lvl = l;
+      n.pools.push_back(pl);
+      cur = p;
+      gcur = gp;
+      cprev = cl;
+    } else {
+      View bb = buf(cl, l), gbb = buf(cl, l);
+      conv(cl, cl, 3, l, a, bb, ga, gbb, true, false);
+      cur = bb;
+      gcur = gbb;
+      cprev = cl;
+    }
+  }
+  for (int l = L - 2; l >= 0; --l) {
+    const int cl = c0 << l, cu = c0 << (l + 1);
+    View u = buf(cu, l), gu = buf(cu, l);
+    Net::Up up;
+    up.in = cur;
+    up.out = u;
+    up.gin = gcur;
+    up.gout = gu;
+    up.lvl = l;
+    n.ups.push_back(up);
+    conv(cu, cl, 3, l, u, slice(cat[l], 0, cl), gu, slice(gcat[l], 0, cl), true, false);
+    View a = buf(cl, l), ga = buf(cl, l);
+    conv(2 * cl, cl, 3, l, cat[l], a, gcat[l], ga, true, false);
+    View bb = buf(cl, l), gbb = buf(cl, l);
+    conv(cl, cl, 3, l, a, bb, ga, gbb, true, false);
+    cur = bb;
+    gcur = gbb;
+  }
+  View o = buf(ds.cout, 0), go = buf(ds.cout, 0);
+  conv(c0, ds.cout, 1, 0, cur, o, gcur, go, false, false);
+  n.out = o.p;
+  n.gout = go.p;
+  // scratch: flipped weights and weight-gradient partials (largest layer), loss partials
+  size_t maxw = 0;
+  for (auto& c : n.convs) maxw = std::max(maxw, (size_t)c.cout * c.cin * (c.ks == 3 ? (d == 3 ? 27 : 9) : 1));
+  n.wflip = take(maxw);
+  const size_t nchunk = 64;
+  n.wpart_floats = nchunk * maxw;
+  n.wpart = take(n.wpart_floats);
+  n.lpart = reinterpret_cast<double*>(take(2 * 8192));
+  *nparams = poff;
+  return off;
+}
+
+template <int D>
+static hipError_t conv_fwd_launch(const Net& n, const View& in, const float* w, const float* b, const View& out,
+                                  int cin, int cout, int ks, int lvl, bool relu, bool acc) {
+  const int Z = n.sz[lvl][0], H = n.sz[lvl][1], W = n.sz[lvl][2];
+  const int tiles = ((W + Tile<D>::X - 1) / Tile<D>::X) * ((H + Tile<D>::Y - 1) / Tile<D>::Y) *
+                    ((Z + Tile<D>::Z - 1) / Tile<D>::Z);
+  dim3 grid(tiles, (cout + COT - 1) / COT, n.desc.batch);
+  if (ks == 3)
+    hipLaunchKernelGGL((k_conv_fwd<D, 3>), grid, dim3(CT), 0, n.st, in.p, cin, in.Ctot, in.off, w, b, out.p, cout,
+                       out.Ctot, out.off, Z, H, W, relu ? 1 : 0, acc ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_conv_fwd<D, 1>), grid, dim3(CT), 0, n.st, in.p, cin, in.Ctot, in.off, w, b, out.p, cout,
+                       out.Ctot, out.off, Z, H, W, relu ? 1 : 0, acc ? 1 : 0);
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t forward(Net& n) {
+  for (size_t i = 0, pi = 0, ui = 0; i < n.convs.size(); ++i) {
+    const Conv& c = n.convs[i];
+    // decoder upsampling precedes the first conv of each decoder level
+    if (ui < n.ups.size() && c.in.p == n.ups[ui].out.p) {
+      const auto& u = n.ups[ui++];
+      const int lo = u.lvl, li = lo + 1;
+      const size_t tot = (size_t)n.desc.batch * u.out.C * plane(n, lo);
+      hipLaunchKernelGGL(k_up<D>, dim3(gridn(tot)), dim3(CT), 0, n.st, u.in.p, u.in.Ctot, u.in.off, u.out.p,
+                         u.out.Ctot, u.out.off, u.out.C, n.sz[li][0], n.sz[li][1], n.sz[li][2], n.sz[lo][0],
+                         n.sz[lo][1], n.sz[lo][2], n.desc.batch);
+    }
+    hipError_t e = conv_fwd_launch<D>(n, c.in, n.params + c.w, n.params + c.b, c.out, c.cin, c.cout, c.ks, c.lvl,
+                                      c.relu, false);
+    if (e != hipSuccess) return e;
+    // pooling follows the second conv of each encoder level
+    if (pi < n.pools.size() && c.out.p == n.pools[pi].in.p && c.out.off == n.pools[pi].in.off) {
+      const auto& p = n.pools[pi++];
+      const int li = p.lvl, lo = li + 1;
+      const size_t tot = (size_t)n.desc.batch * p.out.C * plane(n, lo);
+      hipLaunchKernelGGL(k_pool<D>, dim3(gridn(tot)), dim3(CT), 0, n.st, p.in.p, p.in.Ctot, p.in.off, p.out.p,
+                         p.out.Ctot, p.out.off, p.in.C, n.sz[li][0], n.sz[li][1], n.sz[li][2], n.sz[lo][0],
+                         n.sz[lo][1], n.sz[lo][2], n.desc.batch);
+    }
+  }
+  return hipGetLastError();
+}
+
+template <int D>
+static hipError_t backward(Net& n) {
+  const int B = n.desc.batch;
+  const int d = n.desc.d;
+  for (int i = (int)n.convs.size() - 1; i >= 0; --i) {
+    const Conv& c = n.convs[i];
+    const int l = c.lvl;
+    const size_t pl = plane(n, l);
+    const int taps = c.ks == 3 ? (d == 3 ? 27 : 9) : 1;
+    if (c.relu) {
+      const size_t tot = (size_t)B * c.cout * pl;
+      hipLaunchKernelGGL(k_relu_mask, dim3(gridn(tot)), dim3(CT), 0, n.st, c.gout.p, c.out.p, c.cout, c.gout.Ctot,
+                         c.gout.off, c.out.Ctot, c.out.off, pl, B);
+    }
+    // weight gradient: partials over point chunks, then a fixed-order sum
+    const size_t total = (size_t)B * pl;
+    int nchunk = (int)std::min<size_t>(64, (total + 1023) / 1024);
+    if (nchunk < 1) nchunk = 1;
+    const int chunk = (int)((total + nchunk - 1) / nchunk);
+    const size_t nw = (size_t)c.cout * c.cin * taps;
+    dim3 gw(nchunk, (c.cout + COT - 1) / COT, (c.cin + CIC - 1) / CIC);
+    if (c.ks == 3)
+      hipLaunchKernelGGL((k_conv_wgrad<D, 3>), gw, dim3(CT), 0, n.st, c.in.p, c.cin, c.in.Ctot, c.in.off, c.gout.p,
+                         c.cout, c.gout.Ctot, c.gout.off, n.sz[l][0], n.sz[l][1], n.sz[l][2], B, chunk, n.wpart);
+    else
+      hipLaunchKernelGGL((k_conv_wgrad<D, 1>), gw, dim3(CT), 0, n.st, c.in.p, c.cin, c.in.Ctot, c.in.off, c.gout.p,
+                         c.cout, c.gout.Ctot, c.gout.off, n.sz[l][0], n.sz[l][1], n.sz[l][2], B, chunk, n.wpart);
+    hipLaunchKernelGGL(k_reduce_chunks, dim3(gridn(nw)), dim3(CT), 0, n.st, n.wpart, nchunk, nw, n.grads + c.w);
+    hipLaunchKernelGGL(k_bias_grad, dim3(c.cout), dim3(CT), 0, n.st, c.gout.p, c.cout, c.gout.Ctot, c.gout.off, pl, B,
+                       n.grads + c.b);
+    // data gradient (not needed for the input of the network)
+    if (i > 0) {
+      hipLaunchKernelGGL(k_flip, dim3(gridn(nw)), dim3(CT), 0, n.st, n.params + c.w, c.cout, c.cin, taps, n.wflip);
+      hipError_t e = conv_fwd_launch<D>(n, c.gout, n.wflip, nullptr, c.gin, c.cout, c.cin, c.ks, l, false,
+                                        c.accumulate_gin);
+      if (e != hipSuccess) return e;
+    }
+    // adjoint of the pooling / upsampling that produced this conv's input
+    for (const auto& p : n.pools)
+      if (p.out.p == c.in.p) {
+        const int li = p.lvl, lo = li + 1;
+        const size_t tot = (size_t)B * p.in.C * plane(n, li);
+        hipLaunchKernelGGL(k_pool_bwd<D>, dim3(gridn(tot)), dim3(CT), 0, n.st, p.gout.p, p.gout.Ctot, p.gout.off,
+                           p.gin.p, p.gin.Ctot, p.gin.off, p.in.C, n.sz[li][0], n.sz[li][1], n.sz[li][2],
+                           n.sz[lo][0], n.sz[lo][1], n.sz[lo][2], B);
+      }
+    for (const auto& u : n.ups)
+      if (u.out.p == c.in.p) {
+        const int lo = u.lvl, li = lo + 1;
+        const size_t tot = (size_t)B * u.in.C * plane(n, li);
+        hipLaunchKernelGGL(k_up_bwd<D>, dim3(gridn(tot)), dim3(CT), 0, n.st, u.gout.p, u.gout.Ctot, u.gout.off,
+                           u.gin.p, u.gin.Ctot, u.gin.off, u.in.C, n.sz[li][0], n.sz[li][1], n.sz[li][2],
+                           n.sz[lo][0], n.sz[lo][1], n.sz[lo][2], B);
+      }
+  }
+  return hipGetLastError();
+}
+
+}  // namespace cnn
+}  // namespace hom
+
+using hom::cnn::Net;
+
+struct hom_unet {
+  Net net;
+};
+
+namespace {
+hom_status check_udesc(const hom_unet_desc* d) {
+  if (!d) return HOM_E_INVALID;
+  if (d->d != 2 && d->d != 3) return HOM_E_INVALID;
+  if (d->levels < 1 || d->levels > 6 || d->base < 1 || d->base > 256 || d->cin < 1 || d->cout < 1 || d->batch < 1)
+    return HOM_E_INVALID;
+  for (int a = 0; a < d->d; ++a)
+    if (d->size[a] < 2) return HOM_E_INVALID;
+  return HOM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+hom_status hom_unet_sizes(const hom_unet_desc* desc, size_t* n_params, size_t* work_bytes) {
+  hom_status s = check_udesc(desc);
+  if (s != HOM_OK) return s;
+  if (!n_params || !work_bytes) return HOM_E_INVALID;
+  Net n;
+  n.desc = *desc;
+  *work_bytes = hom::cnn::build_net(n, nullptr, n_params);
+  return HOM_OK;
+}
+
+hom_status hom_unet_create(const hom_unet_desc* desc, float* params, float* grads, float* adam_m, float* adam_v,
+                           void* work, size_t work_bytes, void* stream, hom_unet** out) {
+  hom_status s = check_udesc(desc);
+  if (s != HOM_OK) return s;
+  if (!params || !grads || !adam_m || !adam_v || !work || !out) return HOM_E_INVALID;
+  if (((uintptr_t)work) % 256) return HOM_E_WORKSPACE;
+  hom_unet* u = new hom_unet();
+  u->net.desc = *desc;
+  size_t np = 0;
+  const size_t need = hom::cnn::build_net(u->net, nullptr, &np);
+  if (work_bytes < need) {
+    delete u;
+    return HOM_E_WORKSPACE;
+  }
+  u->net = Net();
+  u->net.desc = *desc;
+  hom::cnn::build_net(u->net, (char*)work, &np);
+  u->net.nparams = np;
+  u->net.params = params;
+  u->net.grads = grads;
+  u->net.m1 = adam_m;
+  u->net.m2 = adam_v;
+  u->net.work = (char*)work;
+  u->net.work_bytes = work_bytes;
+  u->net.st = reinterpret_cast<hipStream_t>(stream);
+  *out = u;
+  return HOM_OK;
+}
+
+hom_status hom_unet_forward(hom_unet* u, const float* in, float* out) {
+  if (!u || !in) return HOM_E_INVALID;
+  Net& n = u->net;
+  const size_t nin = (size_t)n.desc.batch * n.desc.cin * hom::cnn::plane(n, 0);
+  if (hipMemcpyAsync(n.in0, in, nin * sizeof(float), hipMemcpyDeviceToDevice, n.st) != hipSuccess)
+    return HOM_E_DEVICE;
+  hipError_t e = n.desc.d == 3 ? hom::cnn::forward<3>(n) : hom::cnn::forward<2>(n);
+  if (e != hipSuccess) return HOM_E_DEVICE;
+  if (out) {
+    const size_t no = (size_t)n.desc.batch * n.desc.cout * hom::cnn::plane(n, 0);
+    if (hipMemcpyAsync(out, n.out, no * sizeof(float), hipMemcpyDeviceToDevice, n.st) != hipSuccess)
+      return HOM_E_DEVICE;
+  }
+  return HOM_OK;
+}
+
+hom_status hom_unet_loss_weighted(hom_unet* u, const float* target, const float* weight, int32_t wch,
+                                  double* loss) {
+  if (!u || !target || !loss) return HOM_E_INVALID;
+  Net& n = u->net;
+  if (weight && (wch < 1 || wch > n.desc.cout || n.desc.cout % wch != 0)) return HOM_E_INVALID;
+  const size_t pl = hom::cnn::plane(n, 0);
+  const size_t no = (size_t)n.desc.batch * n.desc.cout * pl;
+  const int nb = std::min(hom::cnn::gridn(no), 1024);
+  hipLaunchKernelGGL(hom::cnn::k_mse, dim3(nb), dim3(hom::cnn::CT), 0, n.st, n.out, target, no, weight,
+                     weight ? wch : 1, n.desc.cout, pl, n.gout, n.lpart);
+  if (hipGetLastError() != hipSuccess) return HOM_E_DEVICE;
+  std::vector<double> part(nb);
+  if (hipMemcpyAsync(part.data(), n.lpart, nb * sizeof(double), hipMemcpyDeviceToHost, n.st) != hipSuccess ||
+      hipStreamSynchronize(n.st) != hipSuccess)
+    return HOM_E_DEVICE;
+  double s = 0.0;
+  for (double v : part) s += v;
+  *loss = s / (double)no;
+  return HOM_OK;
+}
+
+hom_status hom_unet_loss(hom_unet* u, const float* target, double* loss) {
+  return hom_unet_loss_weighted(u, target, nullptr, 1, loss);
+}
+
+hom_status hom_unet_backward(hom_unet* u, const float* gout) {
+  if (!u) return HOM_E_INVALID;
+  Net& n = u->net;
+  const size_t no = (size_t)n.desc.batch * n.desc.cout * hom::cnn::plane(n, 0);
+  if (gout && hipMemcpyAsync(n.gout, gout, no * sizeof(float), hipMemcpyDeviceToDevice, n.st) != hipSuccess)
+    return HOM_E_DEVICE;
+  // zero parameter gradients and every activation-gradient buffer except the output gradient
+  hipLaunchKernelGGL(hom::cnn::k_fill, dim3(hom::cnn::gridn(n.nparams)), dim3(hom::cnn::CT), 0, n.st, n.grads,
+                     n.nparams, 0.f);
+  for (const auto& c : n.convs) {
+    if (c.gin.p && c.gin.p != n.gout) {
+      const size_t tot = (size_t)n.desc.batch * c.gin.Ctot * hom::cnn::plane(n, c.lvl);
+      hipLaunchKernelGGL(hom::cnn::k_fill, dim3(hom::cnn::gridn(tot)), dim3(hom::cnn::CT), 0, n.st, c.gin.p, tot,
+                         0.f);
+    }
+  }
+  for (const auto& p : n.pools) {
+    const size_t tot = (size_t)n.desc.batch * p.gout.Ctot * hom::cnn::plane(n, p.lvl + 1);
+    hipLaunchKernelGGL(hom::cnn::k_fill, dim3(hom::cnn::gridn(tot)), dim3(hom::cnn::CT), 0, n.st, p.gout.p, tot, 0.f);
+  }
+  hipError_t e = n.desc.d == 3 ? hom::cnn::backward<3>(n) : hom::cnn::backward<2>(n);
+  return e == hipSuccess ? HOM_OK : HOM_E_DEVICE;
+}
+
+hom_status hom_unet_adam(hom_unet* u, float lr, float beta1, float beta2, float eps, int32_t step) {
+  if (!u || step < 1) return HOM_E_INVALID;
+  Net& n = u->net;
+  const float c1 = 1.f - std::pow(beta1, (float)step), c2 = 1.f - std::pow(beta2, (float)step);
+  hipLaunchKernelGGL(hom::cnn::k_adam, dim3(hom::cnn::gridn(n.nparams)), dim3(hom::cnn::CT), 0, n.st, n.params,
+                     n.grads, n.m1, n.m2, n.nparams, lr, beta1, beta2, eps, c1, c2);
+  return hipGetLastError() == hipSuccess ? HOM_OK : HOM_E_DEVICE;
+}
+
+void hom_unet_destroy(hom_unet* u) { delete u; }
+
+}  // extern "C"

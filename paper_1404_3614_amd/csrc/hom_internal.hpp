@@ -57,6 +57,7 @@ struct UnitDev {
   double* part_q;                    // [nbApply][9]
   CgScal* sc;                        // [L]
   double E[kMaxLoads][3];            // loads (physical components)
+  float* grid;                       // real fields on the doubled grid [L*d][M^d] (grid transfers)
 };
 
 // Shape information shared by every unit of a launch (passed by value).
@@ -83,7 +84,7 @@ struct Geo {
 
 enum FirstMode { FIRST_CG = 0, FIRST_FIELD = 1, FIRST_BOUNDS = 2 };
 enum LastMode { LAST_CG = 0, LAST_RESID = 1, LAST_MATVEC = 2 };
-enum ApplyMode { APPLY_COEF = 0, APPLY_QUAD = 1, APPLY_COEF_CG = 2 };
+enum ApplyMode { APPLY_COEF = 0, APPLY_QUAD = 1, APPLY_COEF_CG = 2, APPLY_GRID = 3, APPLY_FWD = 4 };
 constexpr int MID_CG = 2;  // flag or-ed into the inverse argument of launch_mid
 
 // Host-side switch: when `on`, the next pipeline kernel launch is issued with
@@ -120,6 +121,8 @@ hipError_t launch_symmetrize(const Geo& g, const Cx<double>* src, Cx<double>* ds
 hipError_t launch_advance(const Geo& g, const UnitDev* units, int nunits, int* iter_base, int step,
                           int* active_out, hipStream_t st);
 hipError_t launch_twiddles(Cx<double>* t64, Cx<float>* t32, int M, hipStream_t st);
+hipError_t launch_net_input(const double* coef64, int nc, int d, long Mt, const Cx<double>* ahat0, long S, float* out,
+                            int weight_only, hipStream_t st);
 hipError_t launch_coef_real(const Cx<double>* full, double* c64, float* c32, long n, hipStream_t st);
 hipError_t launch_extract_half(const Geo& g, const Cx<double>* full, Cx<double>* half, int nc, hipStream_t st);
 hipError_t launch_coef_incl(int d, const int* Mint, const double* iY, int nc, const double* A0c, int n_incl,

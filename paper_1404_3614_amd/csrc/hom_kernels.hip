@@ -471,18 +471,48 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo g, const UnitDev* __restri
     mode = APPLY_COEF;
   }
 
-  for (int t = tid; t < M0 * nl; t += kBlock) {
-    const int j = t / nl, l = t - (t / nl) * nl;
-    const int i0 = truncidx(j, N0, M0);
-    Cx<R> v = cx((R)0, (R)0);
-    if (i0 >= 0 && l < tp * P) v = data[((size_t)i0 * npts + p0) * P + l];
-    buf[j * nl + l] = v;
+  if (mode == APPLY_FWD) {
+    // real fields on the full doubled grid, two per complex pack
+    for (int t = tid; t < M0 * nl; t += kBlock) {
+      const int j = t / nl, l = t - (t / nl) * nl;
+      const int pt = l / P, pk = l - pt * P;
+      Cx<R> v = cx((R)0, (R)0);
+      if (pt < tp) {
+        const int f0 = 2 * pk, f1 = 2 * pk + 1;
+        const size_t gi = (size_t)j * npts + p0 + pt;
+        if (f0 < L * d) v.x = (R)U.grid[f0 * Mtot + gi];
+        if (f1 < L * d) v.y = (R)U.grid[f1 * Mtot + gi];
+      }
+      buf[j * nl + l] = v;
+    }
+    __syncthreads();
+  } else {
+    for (int t = tid; t < M0 * nl; t += kBlock) {
+      const int j = t / nl, l = t - (t / nl) * nl;
+      const int i0 = truncidx(j, N0, M0);
+      Cx<R> v = cx((R)0, (R)0);
+      if (i0 >= 0 && l < tp * P) v = data[((size_t)i0 * npts + p0) * P + l];
+      buf[j * nl + l] = v;
+    }
+    __syncthreads();
+    lds_fft<R, MAXB>(buf, nl, M0, g.pl[0], reinterpret_cast<const Cx<R>*>(g.tw[0]), true);
   }
-  __syncthreads();
-  lds_fft<R, MAXB>(buf, nl, M0, g.pl[0], reinterpret_cast<const Cx<R>*>(g.tw[0]), true);
-
-  if (mode == APPLY_COEF) {
+  if (mode == APPLY_GRID) {
     for (int t = tid; t < M0 * tileA; t += kBlock) {
+      const int j = t / tileA, pt = t - (t / tileA) * tileA;
+      if (pt >= tp) continue;
+      const size_t gi = (size_t)j * npts + p0 + pt;
+      for (int pk = 0; pk < P; ++pk) {
+        const Cx<R> z = buf[j * nl + pt * P + pk];
+        if (2 * pk < L * d) U.grid[(2 * pk) * Mtot + gi] = (float)z.x;
+        if (2 * pk + 1 < L * d) U.grid[(2 * pk + 1) * Mtot + gi] = (float)z.y;
+      }
+    }
+    return;
+  }
+
+  if (mode == APPLY_COEF || mode == APPLY_FWD) {
+    for (int t = tid; t < M0 * tileA && mode == APPLY_COEF; t += kBlock) {
       const int j = t / tileA, pt = t - (t / tileA) * tileA;
       if (pt >= tp) continue;
       const size_t ci = (size_t)j * npts + p0 + pt;
@@ -951,6 +981,36 @@ hipError_t launch_advance(const Geo& g, const UnitDev* units, int nunits, int* i
 
 hipError_t launch_twiddles(Cx<double>* t64, Cx<float>* t32, int M, hipStream_t st) {
   hipLaunchKernelGGL(k_twiddles, dim3(grid_for(M)), dim3(kBlock), 0, st, t64, t32, M);
+  return hipGetLastError();
+}
+
+// Network input: a/<a> and log(max(a, 1e-3 <a>)/<a>), a = trace(A_M)/d, <a> = trace(A_hat(0))/d.
+// weight_only: one channel max(a, 1e-3 <a>)/<a> (the pointwise weight of the
+// quadrature of the energy, kept positive where the truncated series of a
+// discontinuous coefficient overshoots below zero).
+__global__ void k_net_input(const double* __restrict__ c, int nc, int d, long Mt, const Cx<double>* __restrict__ ahat0,
+                            long S, float* __restrict__ out, int weight_only) {
+  const int nd = (nc == 1) ? 1 : d;
+  double mean = 0.0;
+  for (int k = 0; k < nd; ++k) mean += ahat0[(size_t)k * S].x;
+  mean /= nd;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < Mt; t += (long)gridDim.x * blockDim.x) {
+    double a = 0.0;
+    for (int k = 0; k < nd; ++k) a += c[(size_t)k * Mt + t];
+    a /= nd;
+    if (weight_only) {
+      out[t] = (float)(fmax(a, 1e-3 * mean) / mean);
+    } else {
+      out[t] = (float)(a / mean);
+      out[Mt + t] = (float)log(fmax(a, 1e-3 * mean) / mean);
+    }
+  }
+}
+
+hipError_t launch_net_input(const double* coef64, int nc, int d, long Mt, const Cx<double>* ahat0, long S, float* out,
+                            int weight_only, hipStream_t st) {
+  hipLaunchKernelGGL(k_net_input, dim3(grid_for(Mt)), dim3(kBlock), 0, st, coef64, nc, d, Mt, ahat0, S, out,
+                     weight_only);
   return hipGetLastError();
 }
 
