@@ -208,7 +208,8 @@ def main():
                                      "a in {1,100}, both loads, primal+dual, batched lockstep CG",
                             cells_per_step=B, tol=args.tol, precision=args.precision, cg_iters=iters,
                             batched="all cells of a step in lockstep (one launch per pass covers every cell)",
-                            plain_bound_pairs_per_s=None if plain_value is None else round(plain_value, 3)),
+                            plain_bound_pairs_per_s=None if plain_value is None else round(plain_value, 3),
+                            tile_tuning=dict(primal=batch.tuning(False, 2), dual=batch.tuning(True, 2))),
                 roofline=roofline)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_cells, args.tol)

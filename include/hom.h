@@ -240,6 +240,34 @@ hom_status hom_batch_get_timing(hom_batch* b, double* ms_sum, int64_t* launches)
 
 void hom_batch_destroy(hom_batch* b);
 
+/* ---- Tile tuning of the FP32 passes.
+ * The specialised FP32 kernels (doubled-grid lengths 25, 81, 125, 625) have
+ * several tile shapes: row pairs and threads per block of the row passes,
+ * points per block of the column pass.  With tuning on (the default; the
+ * environment variable HOM_TUNE=0 turns it off at start-up), the first
+ * mixed-precision solve of a geometry (grid, loads, primal/dual, coefficient
+ * components) in the process times every candidate on that solve's own units,
+ * with zero step lengths on scratch vectors, and keeps the fastest for every
+ * later solve of the geometry, single or batched.  The shape changes the
+ * blocking of the CG reductions, hence rounding in the last bits; within a
+ * process all solves of a geometry use one shape.  Off: fixed defaults. */
+typedef struct {
+  int32_t row_pairs;     /* row pairs per block of the row passes (0: generic passes) */
+  int32_t row_threads;   /* threads per row block (0: the smallest that covers the FFT) */
+  int32_t apply_points;  /* points per column-pass block (0: default) */
+  int32_t candidates;    /* configurations timed (0: defaults, not tuned) */
+  double row_ms;         /* measured time of one row-pass pair (first + last), ms */
+  double apply_ms;       /* measured time of one column pass, ms */
+} hom_tuning;
+
+/* mode 1: tune geometries not seen yet; 0: defaults for geometries not seen
+ * yet.  Choices already made stay in use.  HOM_E_INVALID for other modes. */
+hom_status hom_set_tuning(int32_t mode);
+/* Tile shapes the solves of (dual, nload) use; tunes now when no solve of
+ * this problem / batch has chosen them yet. */
+hom_status hom_problem_tuning(hom_problem* pb, int32_t dual, int32_t nload, hom_tuning* out);
+hom_status hom_batch_tuning(hom_batch* b, int32_t dual, int32_t nload, hom_tuning* out);
+
 /* ---- Learned initial guess (measurement-independent helper of the solver).
  * Fields on the doubled grid M = 2N - 1, real FP32, [nload][d][M0][M1](M2):
  * component g of the fluctuation field of load l. */

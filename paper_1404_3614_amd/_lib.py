@@ -33,6 +33,11 @@ class UNetDesc(C.Structure):
                 ("cout", C.c_int32), ("size", C.c_int32 * 3), ("batch", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("row_pairs", C.c_int32), ("row_threads", C.c_int32), ("apply_points", C.c_int32),
+                ("candidates", C.c_int32), ("row_ms", C.c_double), ("apply_ms", C.c_double)]
+
+
 class Result(C.Structure):
     _fields_ = [("A_up", C.c_double * 9), ("B_up", C.c_double * 9), ("A_low", C.c_double * 9),
                 ("A_mean", C.c_double * 9), ("D", C.c_double * 9)]
@@ -83,6 +88,9 @@ EXPORTS = {
                                              C.POINTER(C.c_double)]),
     "hom_batch_set_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
     "hom_batch_get_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "hom_set_tuning": (C.c_int32, [C.c_int32]),
+    "hom_problem_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
+    "hom_batch_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
     "hom_batch_destroy": (None, [C.c_void_p]),
 }
 

@@ -239,6 +239,13 @@ class Problem:
         L.check(L.load().hom_net_input(self.h, C.c_void_p(out.data_ptr())), "hom_net_input")
         return out
 
+    def tuning(self, dual=False, nload=None):
+        """Tile shapes of this problem's FP32 solves (tuned now if not chosen yet)."""
+        t = L.Tuning()
+        n = self.d if nload is None else nload
+        L.check(L.load().hom_problem_tuning(self.h, int(dual), int(n), C.byref(t)), "hom_problem_tuning")
+        return _tuning_dict(t)
+
     def net_weights(self, out=None):
         """Energy weights [2][*M] (float32) of the primal and dual quadratures of this problem."""
         if out is None:
@@ -253,6 +260,16 @@ class Problem:
         b = self.bounds(xp, xd)
         b.update(info_primal=ip, info_dual=idl, fields_primal=xp, fields_dual=xd)
         return b
+
+
+def set_tuning(on=True):
+    """Tile tuning of the FP32 passes for geometries not seen yet (hom_set_tuning)."""
+    L.check(L.load().hom_set_tuning(1 if on else 0), "hom_set_tuning")
+
+
+def _tuning_dict(t):
+    return dict(row_pairs=t.row_pairs, row_threads=t.row_threads, apply_points=t.apply_points,
+                candidates=t.candidates, row_ms=t.row_ms, apply_ms=t.apply_ms)
 
 
 def _result_dict(res, d):
@@ -314,6 +331,13 @@ class Batch:
         dp = _dptrs([t for ts in dual for t in ts]) if dual is not None else None
         L.check(L.load().hom_batch_bounds(self.h, pp, dp, res), "hom_batch_bounds")
         return [_result_dict(res[i], d) for i in range(n)]
+
+    def tuning(self, dual=False, nload=None):
+        """Tile shapes of this batch's FP32 solves (tuned now if not chosen yet)."""
+        t = L.Tuning()
+        n = self.d if nload is None else nload
+        L.check(L.load().hom_batch_tuning(self.h, int(dual), int(n), C.byref(t)), "hom_batch_tuning")
+        return _tuning_dict(t)
 
     def set_timing(self, on=True):
         L.check(L.load().hom_batch_set_timing(self.h, int(bool(on))), "hom_batch_set_timing")

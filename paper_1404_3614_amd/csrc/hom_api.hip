@@ -7,6 +7,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/hom.h"
@@ -38,6 +41,27 @@ bool smooth35(int M, Plan* pl) {
 int env_int(const char* name, int def) {
   const char* s = std::getenv(name);
   return s ? std::atoi(s) : def;
+}
+
+// ---- tile tuning of the specialised FP32 passes
+// One entry per geometry and load count, shared by every problem and batch of
+// the process: the first solve of a geometry times the candidates, later ones
+// reuse the choice, so a batch and single-cell solves of the same geometry run
+// the same kernels (and the same reduction order).
+struct TuneKey {
+  int M0, M1, M2, d, L, dual, nc, P;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(M0, M1, M2, d, L, dual, nc, P) < std::tie(o.M0, o.M1, o.M2, o.d, o.L, o.dual, o.nc, o.P);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, Tuning> g_tune_cache;
+int g_tune_mode = -1;  // -1: not read yet (HOM_TUNE, default 1)
+
+bool tuning_on() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tune_mode < 0) g_tune_mode = env_int("HOM_TUNE", 1) != 0 ? 1 : 0;
+  return g_tune_mode == 1;
 }
 
 struct SlotBufs {
@@ -92,6 +116,8 @@ struct hom_problem {
   int* pinned_active;
   hipGraphExec_t graph[2][kMaxLoads + 1];
   int graph_chunk;
+  Tuning tune[2][kMaxLoads + 1];        // tile shapes of the single-problem solves
+  bool tuned[2][kMaxLoads + 1];
 };
 
 namespace {
@@ -253,7 +279,7 @@ size_t carve(const hom_desc* desc, int max_loads, const Sizes& z, hom_problem* p
   return off;
 }
 
-Geo make_geo(const hom_problem* pb, int dual, int L, bool fp32, int P_override = 0) {
+Geo make_geo(const hom_problem* pb, int dual, int L, bool fp32, int P_override = 0, const Tuning* tune = nullptr) {
   const Sizes& z = pb->z;
   Geo g;
   std::memset(&g, 0, sizeof(g));
@@ -275,8 +301,14 @@ Geo make_geo(const hom_problem* pb, int dual, int L, bool fp32, int P_override =
   g.nbF = z.Q;
   g.nbL = z.Q;
   if (fp32) {
-    const int G = fast_row_pairs(z.M[2], z.d, L);
+    if (tune) {
+      g.rowG = tune->rowG;
+      g.rowThreads = tune->rowThreads;
+      g.apTP = tune->apTP;
+    }
+    const int G = fast_row_pairs(z.M[2], z.d, L, g.rowG);
     if (G > 0) g.nbF = g.nbL = (z.Q + G - 1) / G;
+    g.pmaj = (z.d == 2 && G > 0 && fast_apply_supported(z.M[0], z.d, g.P, z.nc)) ? 1 : 0;
   }
   const size_t cs = fp32 ? sizeof(Cx<float>) : sizeof(Cx<double>);
   const int npts = z.M[1] * z.M[2];
@@ -533,10 +565,12 @@ hom_status solve_units(SolveRun& R, int nload, double tol, int maxit, bool have_
   }
   // true residual b - C x of the returned iterates, in the precision mode of the solve
   HIPCHK(enqueue_passes(R.fp32, g, R.units, FIRST_FIELD, LAST_RESID, 0, nullptr, st, R.n));
-  std::vector<double> part((size_t)R.n * nload * g.Q);
+  // partial sums of the residual pass: [load][nbL] per unit
+  const size_t nbl = (size_t)g.nbL;
+  std::vector<double> part((size_t)R.n * nload * nbl);
   std::vector<CgScal> sc((size_t)R.n * nload);
   for (int u = 0; u < R.n; ++u) {
-    HIPCHK(hipMemcpyAsync(part.data() + (size_t)u * nload * g.Q, R.part_d[u], (size_t)nload * g.Q * sizeof(double),
+    HIPCHK(hipMemcpyAsync(part.data() + (size_t)u * nload * nbl, R.part_d[u], (size_t)nload * nbl * sizeof(double),
                           hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(sc.data() + (size_t)u * nload, R.sc[u], nload * sizeof(CgScal), hipMemcpyDeviceToHost, st));
   }
@@ -546,7 +580,7 @@ hom_status solve_units(SolveRun& R, int nload, double tol, int maxit, bool have_
     for (int l = 0; l < nload; ++l) {
       const size_t ul = (size_t)u * nload + l;
       double s = 0.0;
-      for (int q = 0; q < g.Q; ++q) s += part[ul * g.Q + q];
+      for (size_t q = 0; q < nbl; ++q) s += part[ul * nbl + q];
       hom_info& in = info[ul];
       in.iters = sc[ul].iters;
       in.rel_res_recur = std::sqrt(std::max(sc[ul].gamma_last, 0.0)) / sc[ul].normE;
@@ -565,6 +599,35 @@ hom_status solve_units(SolveRun& R, int nload, double tol, int maxit, bool have_
   return worst;
 }
 
+// Tile shapes for solves of nload loads over the problems pbs (one unit each in
+// the device array units): the process-wide choice for this geometry, timed
+// on first use with the units pointed at the problems' scratch vectors.
+hom_status solve_tuning(hom_problem* const* pbs, int n, int k, int nload, UnitDev* units, hipStream_t st,
+                        Tuning* out) {
+  hom_problem* p0 = pbs[0];
+  *out = Tuning();
+  if (p0->desc.precision != HOM_MIXED || !tuning_on()) return HOM_OK;
+  const Geo g = make_geo(p0, k, nload, true);
+  const TuneKey key{g.M[0], g.M[1], g.M[2], g.d, nload, k, g.nc, g.P};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      *out = it->second;
+      return HOM_OK;
+    }
+  }
+  std::vector<UnitDev> hu(n);
+  for (int i = 0; i < n; ++i) fill_unit(pbs[i], k, nload, nullptr, nullptr, &hu[i]);
+  HIPCHK(hipMemcpyAsync(units, hu.data(), (size_t)n * sizeof(UnitDev), hipMemcpyHostToDevice, st));
+  Tuning t;
+  HIPCHK(tune_fast(g, units, n, st, std::max(1, env_int("HOM_TUNE_REPS", 3)), &t));
+  HIPCHK(hipStreamSynchronize(st));
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  *out = g_tune_cache.emplace(key, t).first->second;
+  return HOM_OK;
+}
+
 hom_status solve_impl(hom_problem* pb, int k, int nload, const double* E, const double* const* x0, double tol,
                       int maxit, double* const* x_out, hom_info* info) {
   hom_status s = check_solve_args(pb, nload, E, x_out, tol, maxit);
@@ -572,8 +635,13 @@ hom_status solve_impl(hom_problem* pb, int k, int nload, const double* E, const 
   if (!info) return HOM_E_INVALID;
   hipStream_t st = pb->stream;
   const bool fp32 = pb->desc.precision == HOM_MIXED;
-  Geo g = make_geo(pb, k, nload, fp32);
   SlotBufs& sb = pb->slot[k];
+  if (!pb->tuned[k][nload]) {
+    s = solve_tuning(&pb, 1, k, nload, sb.unit, st, &pb->tune[k][nload]);
+    if (s != HOM_OK) return s;
+    pb->tuned[k][nload] = true;
+  }
+  Geo g = make_geo(pb, k, nload, fp32, 0, &pb->tune[k][nload]);
   UnitDev* hu = &pb->host_unit[k];
   fill_unit(pb, k, nload, E, x_out, hu);
   HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
@@ -1048,7 +1116,7 @@ hom_status hom_profile_passes(hom_problem* pb, int32_t dual, int32_t nload, int3
   const int k = dual;
   hipStream_t st = pb->stream;
   const bool fp32 = pb->desc.precision == HOM_MIXED;
-  Geo g = make_geo(pb, k, nload, fp32);
+  Geo g = make_geo(pb, k, nload, fp32, 0, pb->tuned[k][nload] ? &pb->tune[k][nload] : nullptr);
   SlotBufs& sb = pb->slot[k];
   UnitDev* hu = &pb->host_unit[k];
   hom_status s = profile_unit_setup(pb, k, nload, g, hu);
@@ -1145,6 +1213,8 @@ struct hom_batch {
   hipGraphExec_t tgraph[2][kMaxLoads + 1];      // variants with event records
   std::vector<hipEvent_t> tevents[2][kMaxLoads + 1];
   int timing = 0;
+  Tuning tune[2][kMaxLoads + 1];
+  bool tuned[2][kMaxLoads + 1] = {};
   double tsum[5] = {0, 0, 0, 0, 0};
   long long tcnt[5] = {0, 0, 0, 0, 0};
 };
@@ -1215,7 +1285,12 @@ hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const doub
   hom_problem* p0 = b->pbs[0];
   hipStream_t st = b->stream;
   const bool fp32 = p0->desc.precision == HOM_MIXED;
-  Geo g = make_geo(p0, k, nload, fp32);
+  if (!b->tuned[k][nload]) {
+    hom_status s = solve_tuning(b->pbs.data(), n, k, nload, b->units[k], st, &b->tune[k][nload]);
+    if (s != HOM_OK) return s;
+    b->tuned[k][nload] = true;
+  }
+  Geo g = make_geo(p0, k, nload, fp32, 0, &b->tune[k][nload]);
   bool have_x0 = false;
   for (int i = 0; i < n; ++i) {
     fill_unit(b->pbs[i], k, nload, E, x_out + (size_t)i * nload, &b->host_units[k][i]);
@@ -1326,7 +1401,7 @@ hom_status hom_batch_profile_passes(hom_batch* b, int32_t dual, int32_t nload, i
   if (nload < 1 || nload > p0->max_loads) return HOM_E_INVALID;
   const int k = dual, n = b->n;
   const bool fp32 = p0->desc.precision == HOM_MIXED;
-  Geo g = make_geo(p0, k, nload, fp32);
+  Geo g = make_geo(p0, k, nload, fp32, 0, b->tuned[k][nload] ? &b->tune[k][nload] : nullptr);
   for (int i = 0; i < n; ++i) {
     hom_status s = profile_unit_setup(b->pbs[i], k, nload, g, &b->host_units[k][i]);
     if (s != HOM_OK) return s;
@@ -1352,6 +1427,47 @@ hom_status hom_batch_get_timing(hom_batch* b, double* ms_sum, int64_t* launches)
     ms_sum[i] = b->tsum[i];
     launches[i] = b->tcnt[i];
   }
+  return HOM_OK;
+}
+
+static void tuning_report(const hom_problem* p0, int k, int nload, const Tuning& t, hom_tuning* out) {
+  const Geo g = make_geo(p0, k, nload, p0->desc.precision == HOM_MIXED, 0, &t);
+  out->row_pairs = p0->desc.precision == HOM_MIXED ? fast_row_pairs(g.M[2], g.d, nload, t.rowG) : 0;
+  out->row_threads = t.rowThreads;
+  out->apply_points = t.apTP;
+  out->candidates = t.candidates;
+  out->row_ms = t.row_ms;
+  out->apply_ms = t.apply_ms;
+}
+
+hom_status hom_set_tuning(int32_t mode) {
+  if (mode != 0 && mode != 1) return HOM_E_INVALID;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_mode = mode;
+  return HOM_OK;
+}
+
+hom_status hom_problem_tuning(hom_problem* pb, int32_t dual, int32_t nload, hom_tuning* out) {
+  if (!pb || !out || (dual != 0 && dual != 1) || nload < 1 || nload > pb->max_loads) return HOM_E_INVALID;
+  const int k = dual;
+  if (!pb->tuned[k][nload]) {
+    hom_status s = solve_tuning(&pb, 1, k, nload, pb->slot[k].unit, pb->stream, &pb->tune[k][nload]);
+    if (s != HOM_OK) return s;
+    pb->tuned[k][nload] = true;
+  }
+  tuning_report(pb, k, nload, pb->tune[k][nload], out);
+  return HOM_OK;
+}
+
+hom_status hom_batch_tuning(hom_batch* b, int32_t dual, int32_t nload, hom_tuning* out) {
+  if (!b || !out || (dual != 0 && dual != 1) || nload < 1 || nload > b->pbs[0]->max_loads) return HOM_E_INVALID;
+  const int k = dual;
+  if (!b->tuned[k][nload]) {
+    hom_status s = solve_tuning(b->pbs.data(), b->n, k, nload, b->units[k], b->stream, &b->tune[k][nload]);
+    if (s != HOM_OK) return s;
+    b->tuned[k][nload] = true;
+  }
+  tuning_report(b->pbs[0], k, nload, b->tune[k][nload], out);
   return HOM_OK;
 }
 

@@ -13,6 +13,7 @@
 #include <hip/hip_ext.h>
 
 #include <cstdlib>
+#include <functional>
 
 namespace hom {
 
@@ -43,10 +44,14 @@ __device__ __forceinline__ int kept(int pos) {
 }  // namespace
 
 // ============================================================== column pass
-// TP points per block, T threads per point; every thread keeps all P packs.
+// TP points per block, T threads per point.  In 2D the packs are independent
+// (pack l holds the two components of load l, and the coefficient couples only
+// those), so each block takes one pack (grid y = pack) and holds one line per
+// thread group in registers; in 3D a load straddles packs and a block holds
+// all packs of its points.
 template <typename R, int M, int D, int P, int NC, int TP>
 __global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply_fast(Geo g, const UnitDev* __restrict__ units, int cg) {
-  constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T, N = Cfg<M>::N;
+  constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem);   // [M]
   Cx<R>* ex = tw + M;                           // [M][TP]
@@ -54,7 +59,18 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply_fast(Geo g, const Unit
   if (cg && !any_active(U, g.L)) return;
   const int npts = g.M[1] * g.M[2];
   const size_t Mtot = (size_t)M * npts;
-  const int p0 = blockIdx.x * TP;
+  int p0 = blockIdx.x * TP, pk2 = 0;
+  if constexpr (D == 2) {
+    // XCD-aware order: blocks b and b + 8 run on the same XCD (round-robin
+    // dispatch), so each XCD takes a contiguous range of column blocks and,
+    // within it, the packs of one column block back to back (shared L2 lines
+    // of the coefficient and of the neighbouring columns)
+    const int nbx = (npts + TP - 1) / TP, nbx8 = (nbx + 7) / 8;
+    const int xcd = blockIdx.x % 8, w = blockIdx.x / 8, cbl = w / P, cb = xcd * nbx8 + cbl;
+    pk2 = w % P;
+    if (cbl >= nbx8 || cb >= nbx) return;
+    p0 = cb * TP;
+  }
   const int tid = threadIdx.x, pt = tid % TP, q = tid / TP;
   const bool ok = (p0 + pt) < npts;
   const Cx<R>* twg = reinterpret_cast<const Cx<R>*>(g.tw[0]);
@@ -62,86 +78,147 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply_fast(Geo g, const Unit
   Cx<R>* data = reinterpret_cast<Cx<R>*>(g.N[1] > 1 ? U.bufB : U.bufA);
   const size_t col = (size_t)(p0 + pt) * P;
   const size_t rowstride = (size_t)npts * P;
+  const R* coef = reinterpret_cast<const R*>(U.coef);
 
-  Cx<R> v[P][T];
-  // inverse, step 1: thread n2 = q holds x[B n1 + n2] (zero-padded N -> M)
+  if constexpr (D == 2) {
+    __syncthreads();
+    {
+      const int pk = pk2;  // one pack per block
+      // element (row i0, column p0 + pt, pack pk): pack-major or packs interleaved
+      const size_t rs = g.pmaj ? (size_t)npts : rowstride, ps = g.pmaj ? (size_t)g.N[0] * npts : 1;
+      const size_t cbase = g.pmaj ? (size_t)(p0 + pt) : col;
+      Cx<R> v[T];
+      // inverse, step 1: thread n2 = q holds x[B n1 + n2] (zero-padded N -> M)
 #pragma unroll
-  for (int n1 = 0; n1 < A; ++n1) {
-    const int n = B * n1 + q;
-    const int i0 = (q < B && ok) ? kept<M>(n) : -1;
+      for (int n1 = 0; n1 < A; ++n1) {
+        const int i0 = (q < B && ok) ? kept<M>(B * n1 + q) : -1;
+        v[n1] = i0 >= 0 ? data[i0 * rs + cbase + pk * ps] : rf::mk<R>(0, 0);
+      }
+      if (q < B) {
+        rf::Dft<R, A, 1>::run(v);
 #pragma unroll
-    for (int pk = 0; pk < P; ++pk) v[pk][n1] = i0 >= 0 ? data[i0 * rowstride + col + pk] : rf::mk<R>(0, 0);
-  }
-  __syncthreads();
+        for (int k1 = 0; k1 < A; ++k1) {
+          Cx<R> w = tw[q * k1];
+          w.y = -w.y;
+          ex[(q * A + k1) * TP + pt] = rf::mul(v[k1], w);
+        }
+      }
+      __syncthreads();
+      if (q < A) {
 #pragma unroll
-  for (int pk = 0; pk < P; ++pk) {
-    if (q < B) {
-      rf::Dft<R, A, 1>::run(v[pk]);
+        for (int n2 = 0; n2 < B; ++n2) v[n2] = ex[(n2 * A + q) * TP + pt];
+      }
+      __syncthreads();
+      if (q < A) {
+        rf::Dft<R, B, 1>::run(v);
+        // thread k1 = q holds u at x0 = q + A k2: the coefficient on the doubled grid
+        if (ok) {
 #pragma unroll
-      for (int k1 = 0; k1 < A; ++k1) {
-        Cx<R> w = tw[q * k1];
-        w.y = -w.y;
-        ex[(q * A + k1) * TP + pt] = rf::mul(v[pk][k1], w);
+          for (int k2 = 0; k2 < B; ++k2) {
+            const size_t ci = (size_t)(q + A * k2) * npts + p0 + pt;
+            R a[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) a[c] = coef[c * Mtot + ci];
+            const R u[2] = {v[k2].x, v[k2].y};
+            R w[2];
+            coef_mul<R>(2, NC, a, u, w);
+            v[k2] = rf::mk<R>(w[0], w[1]);
+          }
+        }
+        // forward: step over n2 in registers (thread n1 = q), exchange, step over n1
+        rf::Dft<R, B, -1>::run(v);
+#pragma unroll
+        for (int m2 = 0; m2 < B; ++m2) ex[(q * B + m2) * TP + pt] = rf::mul(v[m2], tw[q * m2]);
+      }
+      __syncthreads();
+      if (q < B) {
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) v[n1] = ex[(n1 * B + q) * TP + pt];
+        rf::Dft<R, A, -1>::run(v);
+        // thread m2 = q holds X[q + B m1]: store the Z_N0 part
+        if (ok) {
+#pragma unroll
+          for (int m1 = 0; m1 < A; ++m1) {
+            const int i0 = kept<M>(q + B * m1);
+            if (i0 >= 0) data[i0 * rs + cbase + pk * ps] = v[m1];
+          }
+        }
       }
     }
-    __syncthreads();
-    if (q < A) {
+  } else {
+    Cx<R> v[P][T];
 #pragma unroll
-      for (int n2 = 0; n2 < B; ++n2) v[pk][n2] = ex[(n2 * A + q) * TP + pt];
-      rf::Dft<R, B, 1>::run(v[pk]);
+    for (int n1 = 0; n1 < A; ++n1) {
+      const int i0 = (q < B && ok) ? kept<M>(B * n1 + q) : -1;
+#pragma unroll
+      for (int pk = 0; pk < P; ++pk) v[pk][n1] = i0 >= 0 ? data[i0 * rowstride + col + pk] : rf::mk<R>(0, 0);
     }
     __syncthreads();
-  }
-  // thread k1 = q holds u at x0 = q + A k2: apply the coefficient on the doubled grid
-  if (q < A && ok) {
-    const R* coef = reinterpret_cast<const R*>(U.coef);
 #pragma unroll
-    for (int k2 = 0; k2 < B; ++k2) {
-      const size_t ci = (size_t)(q + A * k2) * npts + p0 + pt;
-      R a[NC];
+    for (int pk = 0; pk < P; ++pk) {
+      if (q < B) {
+        rf::Dft<R, A, 1>::run(v[pk]);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) a[c] = coef[c * Mtot + ci];
-      R u[2 * P], w[2 * P];
-#pragma unroll
-      for (int pk = 0; pk < P; ++pk) {
-        u[2 * pk] = v[pk][k2].x;
-        u[2 * pk + 1] = v[pk][k2].y;
+        for (int k1 = 0; k1 < A; ++k1) {
+          Cx<R> w = tw[q * k1];
+          w.y = -w.y;
+          ex[(q * A + k1) * TP + pt] = rf::mul(v[pk][k1], w);
+        }
       }
+      __syncthreads();
+      if (q < A) {
 #pragma unroll
-      for (int f = 0; f < 2 * P; ++f) w[f] = (R)0;
+        for (int n2 = 0; n2 < B; ++n2) v[pk][n2] = ex[(n2 * A + q) * TP + pt];
+        rf::Dft<R, B, 1>::run(v[pk]);
+      }
+      __syncthreads();
+    }
+    if (q < A && ok) {
 #pragma unroll
-      for (int l = 0; l < (2 * P) / D; ++l) coef_mul<R>(D, NC, a, u + l * D, w + l * D);
+      for (int k2 = 0; k2 < B; ++k2) {
+        const size_t ci = (size_t)(q + A * k2) * npts + p0 + pt;
+        R a[NC];
 #pragma unroll
-      for (int pk = 0; pk < P; ++pk) v[pk][k2] = rf::mk<R>(w[2 * pk], w[2 * pk + 1]);
+        for (int c = 0; c < NC; ++c) a[c] = coef[c * Mtot + ci];
+        R u[2 * P], w[2 * P];
+#pragma unroll
+        for (int pk = 0; pk < P; ++pk) {
+          u[2 * pk] = v[pk][k2].x;
+          u[2 * pk + 1] = v[pk][k2].y;
+        }
+#pragma unroll
+        for (int f = 0; f < 2 * P; ++f) w[f] = (R)0;
+#pragma unroll
+        for (int l = 0; l < (2 * P) / D; ++l) coef_mul<R>(D, NC, a, u + l * D, w + l * D);
+#pragma unroll
+        for (int pk = 0; pk < P; ++pk) v[pk][k2] = rf::mk<R>(w[2 * pk], w[2 * pk + 1]);
+      }
+    }
+#pragma unroll
+    for (int pk = 0; pk < P; ++pk) {
+      if (q < A) {
+        rf::Dft<R, B, -1>::run(v[pk]);
+#pragma unroll
+        for (int m2 = 0; m2 < B; ++m2) ex[(q * B + m2) * TP + pt] = rf::mul(v[pk][m2], tw[q * m2]);
+      }
+      __syncthreads();
+      if (q < B) {
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) v[pk][n1] = ex[(n1 * B + q) * TP + pt];
+        rf::Dft<R, A, -1>::run(v[pk]);
+      }
+      __syncthreads();
+    }
+    if (q < B && ok) {
+#pragma unroll
+      for (int m1 = 0; m1 < A; ++m1) {
+        const int i0 = kept<M>(q + B * m1);
+        if (i0 >= 0)
+#pragma unroll
+          for (int pk = 0; pk < P; ++pk) data[i0 * rowstride + col + pk] = v[pk][m1];
+      }
     }
   }
-  // forward: step A over n2 in registers (thread n1 = q), exchange, step B over n1
-#pragma unroll
-  for (int pk = 0; pk < P; ++pk) {
-    if (q < A) {
-      rf::Dft<R, B, -1>::run(v[pk]);
-#pragma unroll
-      for (int m2 = 0; m2 < B; ++m2) ex[(q * B + m2) * TP + pt] = rf::mul(v[pk][m2], tw[q * m2]);
-    }
-    __syncthreads();
-    if (q < B) {
-#pragma unroll
-      for (int n1 = 0; n1 < A; ++n1) v[pk][n1] = ex[(n1 * B + q) * TP + pt];
-      rf::Dft<R, A, -1>::run(v[pk]);
-    }
-    __syncthreads();
-  }
-  // thread m2 = q holds X[q + B m1]: store the Z_N0 part
-  if (q < B && ok) {
-#pragma unroll
-    for (int m1 = 0; m1 < A; ++m1) {
-      const int i0 = kept<M>(q + B * m1);
-      if (i0 >= 0)
-#pragma unroll
-        for (int pk = 0; pk < P; ++pk) data[i0 * rowstride + col + pk] = v[pk][m1];
-    }
-  }
-  (void)N;
 }
 
 // ============================================================== row passes
@@ -210,12 +287,18 @@ __device__ __forceinline__ void row_info(const Geo& g, int qpair, RowInfo& ri) {
   ri.i0B = ixn(-h0, g.N[0]);
 }
 
+// A block handles the loads lo .. lo + L - 1 (lo = blockIdx.y * L): in 2D one
+// load per block (its pack is independent of the others), in 3D all loads.
+// P packs of the block start at pack po of the Pg packs of the field buffers.
 template <typename R, int M, int D, int L, int DUAL, int G>
-__global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_first_fast(Geo g, const UnitDev* __restrict__ units,
-                                                                         int mode, int jstep,
-                                                                         const int* __restrict__ iter_base) {
+__global__ __launch_bounds__(256) void k_first_fast(Geo g, const UnitDev* __restrict__ units, int mode, int jstep,
+                                                    const int* __restrict__ iter_base) {
   constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T, N2 = Cfg<M>::N, H2 = Cfg<M>::H;
   constexpr int P = (L * D + 1) / 2, m = DUAL ? D - 1 : 1, d = D;
+  const int lo = blockIdx.y * L, po = (lo * D) / 2, Pg = g.P;
+  const bool cgm = (mode == FIRST_CG || mode == FIRST_PROF);
+  // strides of the row-pass buffer between positions and between packs
+  const size_t lstr = g.pmaj ? 1 : (size_t)Pg, pstr = g.pmaj ? (size_t)g.N[0] * g.N[1] * M : 1;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_alpha[kMaxLoads];
   __shared__ int s_act[kMaxLoads];
@@ -224,7 +307,7 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_first_fast(Geo g
   const UnitDev& U = units[blockIdx.z];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int N1 = g.N[1];
-  const int it = iter_base ? (*iter_base + jstep) : 0;
+  const int it = (mode == FIRST_PROF) ? 1 : (iter_base ? (*iter_base + jstep) : 0);
   Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem);                          // [M]
   Cx<R>* stage = reinterpret_cast<Cx<R>*>(smem + align16(M * sizeof(Cx<R>)));  // [2G][P][M]
 
@@ -234,10 +317,10 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_first_fast(Geo g
       int act = 1;
       double alpha = 0.0;
       if (mode == FIRST_CG) {
-        CgScal* sc = U.sc + w;
+        CgScal* sc = U.sc + lo + w;
         act = (sc->status == 0);
         if (act && it > 0) {
-          const double delta = wave_sum_arr(U.part_d + (size_t)w * g.nbL, g.nbL);
+          const double delta = wave_sum_arr(U.part_d + (size_t)(lo + w) * g.nbL, g.nbL);
           const double gam = sc->gamma[(it - 1) & 1];
           double den = delta;
           if (it > 1) den = delta - sc->beta[(it - 1) & 1] * gam / sc->alpha[(it - 2) & 1];
@@ -288,16 +371,16 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_first_fast(Geo g
       for (int c = 0; c < m; ++c) {
         const size_t idx = ((size_t)(c * g.H0 + h0) * N1 + i1) * N2 + i2;
         Cx<double> v = cx(0.0, 0.0);
-        if (mode != FIRST_CG) {
-          v = U.x[l][idx];
+        if (!cgm) {
+          v = U.x[lo + l][idx];
         } else if (s_act[l]) {
-          v = U.r[l][idx];
+          v = U.r[lo + l][idx];
           if (it > 0) {
             const double a = s_alpha[l];
-            const Cx<double> xv = U.x[l][idx], pv = U.p[l][idx], sv = U.s[l][idx];
+            const Cx<double> xv = U.x[lo + l][idx], pv = U.p[lo + l][idx], sv = U.s[lo + l][idx];
             v = v - sv * a;
-            U.x[l][idx] = xv + pv * a;
-            U.r[l][idx] = v;
+            U.x[lo + l][idx] = xv + pv * a;
+            U.r[lo + l][idx] = v;
           }
           const double e = wt * (v.x * v.x + v.y * v.y);
           if (l == 0) gp0 += e;
@@ -325,14 +408,14 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_first_fast(Geo g
           const int lf = f / d, gam = f - (f / d) * d;
 #pragma unroll
           for (int c = 0; c < m; ++c) X[s] = X[s] + rv[lf][c] * Tb[gam][c];
-          if (mode == FIRST_BOUNDS && ri.self && k2 == 0) X[s].x += U.E[lf][gam];
+          if (mode == FIRST_BOUNDS && ri.self && k2 == 0) X[s].x += U.E[lo + lf][gam];
         }
       }
       sA[pk * M + posA] = rf::mk<R>((R)(X[0].x - X[1].y), (R)(X[0].y + X[1].x));
       if (!ri.self) sB[pk * M + posB] = rf::mk<R>((R)(X[0].x + X[1].y), (R)(-X[0].y + X[1].x));
     }
   }
-  if (mode == FIRST_CG) {
+  if (cgm) {
     for (int l = 0; l < L; ++l) {
       double v = l == 0 ? gp0 : (l == 1 ? gp1 : gp2);
 #pragma unroll
@@ -342,7 +425,7 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_first_fast(Geo g
       if (tid == 0) {
         double s = 0.0;
         for (int i = 0; i < (nthr + 63) / 64; ++i) s += s_red[i];
-        U.part_g[(size_t)l * g.nbF + blockIdx.x] = s;
+        U.part_g[(size_t)(lo + l) * g.nbF + blockIdx.x] = s;
       }
       __syncthreads();
     }
@@ -385,18 +468,20 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_first_fast(Geo g
       for (int n2 = 0; n2 < B; ++n2) v[n2] = sp[n2 * A + q];
       rf::Dft<R, B, 1>::run(v);
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) out[(((size_t)i0 * N1 + i1) * M + (q + A * k2)) * P + pk] = v[k2];
+      for (int k2 = 0; k2 < B; ++k2) out[(((size_t)i0 * N1 + i1) * M + (q + A * k2)) * lstr + (po + pk) * pstr] = v[k2];
     }
   }
   (void)H2;
 }
 
 template <typename R, int M, int D, int L, int DUAL, int G>
-__global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_last_fast(Geo g, const UnitDev* __restrict__ units,
-                                                                        int mode, int jstep,
-                                                                        const int* __restrict__ iter_base) {
+__global__ __launch_bounds__(256) void k_last_fast(Geo g, const UnitDev* __restrict__ units, int mode, int jstep,
+                                                   const int* __restrict__ iter_base) {
   constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T, N2 = Cfg<M>::N;
   constexpr int P = (L * D + 1) / 2, m = DUAL ? D - 1 : 1, d = D;
+  const int lo = blockIdx.y * L, po = (lo * D) / 2, Pg = g.P;
+  const bool cgm = (mode == LAST_CG || mode == LAST_PROF);
+  const size_t lstr = g.pmaj ? 1 : (size_t)Pg, pstr = g.pmaj ? (size_t)g.N[0] * g.N[1] * M : 1;
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double s_beta[kMaxLoads];
   __shared__ int s_act[kMaxLoads];
@@ -405,7 +490,7 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_last_fast(Geo g,
   const UnitDev& U = units[blockIdx.z];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int N1 = g.N[1];
-  const int it = iter_base ? (*iter_base + jstep) : 0;
+  const int it = (mode == LAST_PROF) ? 1 : (iter_base ? (*iter_base + jstep) : 0);
   Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem);                                   // [M]
   Cx<R>* stage = reinterpret_cast<Cx<R>*>(smem + align16(M * sizeof(Cx<R>)));  // [2G][P][M]
 
@@ -415,10 +500,10 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_last_fast(Geo g,
       int act = 1;
       double beta = 0.0;
       if (mode == LAST_CG) {
-        CgScal* sc = U.sc + w;
+        CgScal* sc = U.sc + lo + w;
         act = (sc->status == 0);
         if (act) {
-          const double gam = wave_sum_arr(U.part_g + (size_t)w * g.nbF, g.nbF);
+          const double gam = wave_sum_arr(U.part_g + (size_t)(lo + w) * g.nbF, g.nbF);
           const bool bad = !(gam == gam) || gam > 1e300;
           const bool conv = sqrt(gam) <= sc->tol * sc->normE;
           if (bad || conv || it >= sc->maxit) {
@@ -472,7 +557,7 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_last_fast(Geo g,
 #pragma unroll
     for (int n2 = 0; n2 < B; ++n2)
 #pragma unroll
-      for (int pk = 0; pk < P; ++pk) v[pk][n2] = in[(((size_t)i0 * N1 + i1) * M + (q + A * n2)) * P + pk];
+      for (int pk = 0; pk < P; ++pk) v[pk][n2] = in[(((size_t)i0 * N1 + i1) * M + (q + A * n2)) * lstr + (po + pk) * pstr];
   }
 #pragma unroll
   for (int pk = 0; pk < P; ++pk) {
@@ -521,14 +606,14 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_last_fast(Geo g,
 #pragma unroll
       for (int c = 0; c < m; ++c) {
         const size_t idx = ((size_t)(c * g.H0 + kk0) * N1 + ii1) * N2 + i2;
-        if (mode == LAST_CG) {
-          rv[c] = U.r[l][idx];
+        if (cgm) {
+          rv[c] = U.r[lo + l][idx];
           if (it > 0) {
-            pv[c] = U.p[l][idx];
-            sv[c] = U.s[l][idx];
+            pv[c] = U.p[lo + l][idx];
+            sv[c] = U.s[lo + l][idx];
           }
         } else if (mode == LAST_RESID) {
-          bv[c] = U.b[l][idx];
+          bv[c] = U.b[lo + l][idx];
         }
       }
       Cx<double> wv[D];
@@ -549,22 +634,22 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_last_fast(Geo g,
         for (int gam = 0; gam < d; ++gam) w = w + wv[gam] * Tb[gam][c];
         const size_t idx = ((size_t)(c * g.H0 + kk0) * N1 + ii1) * N2 + i2;
         double e;
-        if (mode == LAST_CG) {
+        if (cgm) {
           const double b = s_beta[l];
           if (it == 0) {
-            U.p[l][idx] = rv[c];
-            U.s[l][idx] = w;
+            U.p[lo + l][idx] = rv[c];
+            U.s[lo + l][idx] = w;
           } else {
-            U.p[l][idx] = rv[c] + pv[c] * b;
-            U.s[l][idx] = w + sv[c] * b;
+            U.p[lo + l][idx] = rv[c] + pv[c] * b;
+            U.s[lo + l][idx] = w + sv[c] * b;
           }
           e = wt * (rv[c].x * w.x + rv[c].y * w.y);
         } else if (mode == LAST_RESID) {
           const Cx<double> rn = bv[c] - w;
-          U.r[l][idx] = rn;
+          U.r[lo + l][idx] = rn;
           e = wt * (rn.x * rn.x + rn.y * rn.y);
         } else {
-          U.s[l][idx] = w;
+          U.s[lo + l][idx] = w;
           e = wt * (w.x * w.x + w.y * w.y);
         }
         if (l == 0) dp0 += e;
@@ -582,13 +667,59 @@ __global__ __launch_bounds__(round64(2 * G * Cfg<M>::T)) void k_last_fast(Geo g,
     if (tid == 0) {
       double s = 0.0;
       for (int i = 0; i < (nthr + 63) / 64; ++i) s += s_red[i];
-      U.part_d[(size_t)l * g.nbL + blockIdx.x] = s;
+      U.part_d[(size_t)(lo + l) * g.nbL + blockIdx.x] = s;
     }
     __syncthreads();
   }
 }
 
 // ============================================================== dispatch
+// Candidate tile shapes per FFT length (the first entry is the default).
+// Row passes: pairs per block (2 G T <= 256 threads); column pass: points per block.
+template <int M>
+struct Cands;
+template <>
+struct Cands<625> {
+  static constexpr int G[3] = {2, 1, 4};
+  static constexpr int TP[2] = {8, 4};
+};
+template <>
+struct Cands<125> {
+  static constexpr int G[3] = {4, 2, 1};
+  static constexpr int TP[2] = {10, 5};
+};
+template <>
+struct Cands<81> {
+  static constexpr int G[3] = {14, 7, 4};
+  static constexpr int TP[2] = {28, 14};
+};
+template <>
+struct Cands<25> {
+  static constexpr int G[3] = {25, 12, 6};
+  static constexpr int TP[2] = {51, 25};
+};
+
+static bool apply_supported(int M, int D, int P, int NC) {
+  if (D == 2) return (M == 625 || M == 125 || M == 81 || M == 25) && (P == 1 || P == 2) && (NC == 1 || NC == 3);
+  return M == 81 && (P == 2 || P == 3 || P == 5) && (NC == 1 || NC == 6);
+}
+
+bool fast_apply_supported(int M, int D, int P, int NC) {
+  return !std::getenv("HOM_NO_FAST") && apply_supported(M, D, P, NC);
+}
+
+static bool row_supported(int M, int D, int L) {
+  if (D == 2) return (M == 625 || M == 125 || M == 81 || M == 25) && L >= 1 && L <= kMaxLoads;
+  return M == 81 && L >= 1 && L <= 3;
+}
+
+template <int M>
+static int pick(const int* c, int n, int req) {
+  for (int i = 0; i < n; ++i)
+    if (c[i] == req) return req;
+  return c[0];
+}
+
 template <typename K>
 static hipError_t launch_k(K kern, dim3 grid, int threads, size_t lds, hipStream_t st, const Geo& g,
                            const UnitDev* units, int a, int b, const int* c) {
@@ -602,16 +733,16 @@ static hipError_t launch_k(K kern, dim3 grid, int threads, size_t lds, hipStream
   return hipGetLastError();
 }
 
-template <int M, int D, int P, int NC>
-static hipError_t run_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st) {
+template <int M, int D, int P, int NC, int TP>
+static hipError_t run_apply_tp(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st) {
   constexpr int T = Cfg<M>::T;
-  constexpr int TP = (M >= 625) ? 8 : (256 / T);
   const int npts = g.M[1] * g.M[2];
   const size_t lds = (size_t)M * sizeof(Cx<float>) * (1 + TP);
   auto kern = k_apply_fast<float, M, D, P, NC, TP>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const dim3 grid((npts + TP - 1) / TP, 1, n);
+  const int nbx = (npts + TP - 1) / TP;
+  const dim3 grid(D == 2 ? 8 * ((nbx + 7) / 8) * P : nbx, 1, n);
   if (g_ext_timing.on)
     hipExtLaunchKernelGGL(kern, grid, dim3(TP * T), lds, st, g_ext_timing.start, g_ext_timing.stop, 0, g, units, cg);
   else
@@ -619,10 +750,18 @@ static hipError_t run_apply(const Geo& g, const UnitDev* units, int n, int cg, h
   return hipGetLastError();
 }
 
+template <int M, int D, int P, int NC>
+static hipError_t run_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st) {
+  constexpr int TP0 = Cands<M>::TP[0], TP1 = Cands<M>::TP[1];
+  if (g.apTP == TP1) return run_apply_tp<M, D, P, NC, TP1>(g, units, n, cg, st);
+  return run_apply_tp<M, D, P, NC, TP0>(g, units, n, cg, st);
+}
+
 // Returns true when a specialised column pass handled the launch (*err set).
 bool fast_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st, hipError_t* err) {
   if (std::getenv("HOM_NO_FAST")) return false;
   const int M = g.M[0], D = g.d, P = g.P, NC = g.nc;
+  if (!apply_supported(M, D, P, NC)) return false;
 #define HOM_AP(MM, DD, PP, CC)                                      \
   if (M == MM && D == DD && P == PP && NC == CC) {                 \
     *err = run_apply<MM, DD, PP, CC>(g, units, n, cg, st);         \
@@ -639,38 +778,51 @@ bool fast_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t s
 }
 
 template <int M>
-static constexpr int pairs_per_block() {
-  return (M >= 625) ? 2 : ((M >= 125) ? 4 : (256 / (2 * Cfg<M>::T)));
-}
-
-static bool row_supported(int M, int D, int L) {
-  if (D == 2) return (M == 625 || M == 125 || M == 81 || M == 25) && (L == 1 || L == 2);
-  return M == 81 && L >= 1 && L <= 3;
+static int row_pairs_for(int requested) {
+  return pick<M>(Cands<M>::G, 3, requested);
 }
 
 // Row pairs per block of the specialised row passes, or 0 when no
 // specialisation exists (then the generic passes run).
-int fast_row_pairs(int M, int D, int L) {
+int fast_row_pairs(int M, int D, int L, int requested) {
   if (std::getenv("HOM_NO_FAST")) return 0;
   if (!row_supported(M, D, L)) return 0;
-  if (M == 625) return pairs_per_block<625>();
-  if (M == 125) return pairs_per_block<125>();
-  if (M == 81) return pairs_per_block<81>();
-  return pairs_per_block<25>();
+  if (M == 625) return row_pairs_for<625>(requested);
+  if (M == 125) return row_pairs_for<125>(requested);
+  if (M == 81) return row_pairs_for<81>(requested);
+  return row_pairs_for<25>(requested);
+}
+
+// Threads per block of a row pass: the requested count when it is a multiple
+// of 64 that covers the 2 G T threads of the FFT phase and is at most 256.
+static int row_threads(int G, int T, int requested) {
+  const int need = round64(2 * G * T);
+  if (requested >= need && requested <= 256 && requested % 64 == 0) return requested;
+  return need;
+}
+
+template <int M, int D, int L, int DUAL, int G>
+static hipError_t run_row_g(bool first, const Geo& g, const UnitDev* units, int n, int mode, int jstep,
+                            const int* iter_base, hipStream_t st) {
+  constexpr int T = Cfg<M>::T, P = (L * D + 1) / 2;
+  static_assert(2 * G * T <= 256, "row pass needs at most 256 threads");
+  const int nb = (g.Q + G - 1) / G;
+  const int thr = row_threads(G, T, g.rowThreads);
+  const size_t lds = align16(M * sizeof(Cx<float>)) + (size_t)2 * G * P * M * sizeof(Cx<float>);
+  const dim3 grid(nb, D == 2 ? g.L / L : 1, n);
+  if (first)
+    return launch_k(k_first_fast<float, M, D, L, DUAL, G>, grid, thr, lds, st, g, units, mode, jstep, iter_base);
+  return launch_k(k_last_fast<float, M, D, L, DUAL, G>, grid, thr, lds, st, g, units, mode, jstep, iter_base);
 }
 
 template <int M, int D, int L, int DUAL>
 static hipError_t run_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, int jstep,
                           const int* iter_base, hipStream_t st) {
-  constexpr int G = pairs_per_block<M>();
-  constexpr int T = Cfg<M>::T, P = (L * D + 1) / 2;
-  const int nb = (g.Q + G - 1) / G;
-  const size_t lds = align16(M * sizeof(Cx<float>)) + (size_t)2 * G * P * M * sizeof(Cx<float>);
-  if (first)
-    return launch_k(k_first_fast<float, M, D, L, DUAL, G>, dim3(nb, 1, n), round64(2 * G * T), lds, st, g, units,
-                    mode, jstep, iter_base);
-  return launch_k(k_last_fast<float, M, D, L, DUAL, G>, dim3(nb, 1, n), round64(2 * G * T), lds, st, g, units, mode,
-                  jstep, iter_base);
+  constexpr int G0 = Cands<M>::G[0], G1 = Cands<M>::G[1], G2 = Cands<M>::G[2];
+  const int G = row_pairs_for<M>(g.rowG);
+  if (G == G1) return run_row_g<M, D, L, DUAL, G1>(first, g, units, n, mode, jstep, iter_base, st);
+  if (G == G2) return run_row_g<M, D, L, DUAL, G2>(first, g, units, n, mode, jstep, iter_base, st);
+  return run_row_g<M, D, L, DUAL, G0>(first, g, units, n, mode, jstep, iter_base, st);
 }
 
 template <int M, int D, int L>
@@ -682,17 +834,117 @@ static hipError_t run_row_d(bool first, const Geo& g, const UnitDev* units, int 
 
 bool fast_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, int jstep, const int* iter_base,
               hipStream_t st, hipError_t* err) {
-  if (!fast_row_pairs(g.M[2], g.d, g.L)) return false;
+  if (!fast_row_pairs(g.M[2], g.d, g.L, g.rowG)) return false;
   const int M = g.M[2], D = g.d, L = g.L;
-#define HOM_RW(MM, DD, LL)                                                          \
-  if (M == MM && D == DD && L == LL) {                                             \
-    *err = run_row_d<MM, DD, LL>(first, g, units, n, mode, jstep, iter_base, st);  \
-    return true;                                                                   \
+  // 2D: one load per block (grid y = load); 3D: every load in one block
+#define HOM_RW2(MM)                                                                     \
+  if (M == MM && D == 2) {                                                             \
+    *err = run_row_d<MM, 2, 1>(first, g, units, n, mode, jstep, iter_base, st);        \
+    return true;                                                                       \
   }
-  HOM_RW(625, 2, 1) HOM_RW(625, 2, 2) HOM_RW(125, 2, 1) HOM_RW(125, 2, 2) HOM_RW(81, 2, 1) HOM_RW(81, 2, 2)
-  HOM_RW(25, 2, 1) HOM_RW(25, 2, 2) HOM_RW(81, 3, 1) HOM_RW(81, 3, 2) HOM_RW(81, 3, 3)
-#undef HOM_RW
+#define HOM_RW3(MM, LL)                                                                 \
+  if (M == MM && D == 3 && L == LL) {                                                  \
+    *err = run_row_d<MM, 3, LL>(first, g, units, n, mode, jstep, iter_base, st);       \
+    return true;                                                                       \
+  }
+  HOM_RW2(625) HOM_RW2(125) HOM_RW2(81) HOM_RW2(25)
+  HOM_RW3(81, 1) HOM_RW3(81, 2) HOM_RW3(81, 3)
+#undef HOM_RW2
+#undef HOM_RW3
   return false;
+}
+
+// ============================================================== tile tuning
+static hipError_t time_ms(hipStream_t st, int reps, float* ms, const std::function<hipError_t()>& body) {
+  hipEvent_t e0, e1;
+  hipError_t e = hipEventCreate(&e0);
+  if (e != hipSuccess) return e;
+  e = hipEventCreate(&e1);
+  if (e != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return e;
+  }
+  e = body();  // untimed: first-launch costs
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = body();
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+  if (e == hipSuccess) *ms /= (float)reps;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return e;
+}
+
+template <int M>
+static hipError_t tune_m(const Geo& g0, const UnitDev* units, int n, hipStream_t st, int reps, Tuning* best) {
+  constexpr int T = Cfg<M>::T;
+  Tuning t = *best;
+  int cand = 0;
+  hipError_t e = hipSuccess;
+  if (row_supported(M, g0.d, g0.L)) {
+    double bms = 1e30;
+    for (int gi = 0; gi < 3 && e == hipSuccess; ++gi) {
+      const int G = Cands<M>::G[gi];
+      const int base = round64(2 * G * T);
+      for (int thr = base; thr <= 256 && e == hipSuccess; thr = (thr == 256 ? 512 : 256)) {
+        Geo g = g0;
+        g.rowG = G;
+        g.rowThreads = thr;
+        g.nbF = g.nbL = (g.Q + G - 1) / G;
+        float ms = 0.f;
+        e = time_ms(st, reps, &ms, [&]() -> hipError_t {
+          hipError_t x = hipSuccess;
+          if (!fast_row(true, g, units, n, FIRST_PROF, 0, nullptr, st, &x)) return hipErrorInvalidValue;
+          if (x != hipSuccess) return x;
+          if (!fast_row(false, g, units, n, LAST_PROF, 0, nullptr, st, &x)) return hipErrorInvalidValue;
+          return x;
+        });
+        ++cand;
+        if (e == hipSuccess && ms < bms) {
+          bms = ms;
+          t.rowG = G;
+          t.rowThreads = thr;
+          t.row_ms = ms;
+        }
+      }
+    }
+  }
+  if (e == hipSuccess && apply_supported(M, g0.d, g0.P, g0.nc) && g0.M[0] == M) {
+    double bms = 1e30;
+    for (int ti = 0; ti < 2 && e == hipSuccess; ++ti) {
+      Geo g = g0;
+      g.apTP = Cands<M>::TP[ti];
+      float ms = 0.f;
+      e = time_ms(st, reps, &ms, [&]() -> hipError_t {
+        hipError_t x = hipSuccess;
+        if (!fast_apply(g, units, n, 0, st, &x)) return hipErrorInvalidValue;
+        return x;
+      });
+      ++cand;
+      if (e == hipSuccess && ms < bms) {
+        bms = ms;
+        t.apTP = g.apTP;
+        t.apply_ms = ms;
+      }
+    }
+  }
+  if (e == hipSuccess) {
+    t.candidates = cand;
+    *best = t;
+  }
+  return e;
+}
+
+hipError_t tune_fast(const Geo& g, const UnitDev* units, int n, hipStream_t st, int reps, Tuning* best) {
+  if (std::getenv("HOM_NO_FAST")) return hipSuccess;
+  const int M = g.M[2];
+  if (g.M[0] != M) return hipSuccess;  // tuned shapes cover equal row and column lengths
+  if (M == 625) return tune_m<625>(g, units, n, st, reps, best);
+  if (M == 125) return tune_m<125>(g, units, n, st, reps, best);
+  if (M == 81) return tune_m<81>(g, units, n, st, reps, best);
+  if (M == 25) return tune_m<25>(g, units, n, st, reps, best);
+  return hipSuccess;
 }
 
 }  // namespace hom

@@ -75,6 +75,11 @@ struct Geo {
   int nbF, nbL, nbA;   // blocks per unit of first / last / apply pass
   int tileA;           // points per apply-pass block
   int tileM;           // complex elements per middle-pass block
+  int rowG;            // row pairs per block of the specialised row passes (0: default)
+  int rowThreads;      // threads per block of the specialised row passes (0: default)
+  int apTP;            // points per block of the specialised column pass (0: default)
+  int pmaj;            // 2D, both specialised passes: row-pass buffer pack-major [P][N0][M2]
+                       // (otherwise [N0][N1][M2][P], packs interleaved)
   int phys_axis[3];
   double iY[3];        // 1 / Y_a (internal axes)
   double invM;         // 1 / (M0 M1 M2)
@@ -82,8 +87,10 @@ struct Geo {
   const void* tw[3];   // R-typed twiddles exp(-2 pi i t / M_a), t < M_a
 };
 
-enum FirstMode { FIRST_CG = 0, FIRST_FIELD = 1, FIRST_BOUNDS = 2 };
-enum LastMode { LAST_CG = 0, LAST_RESID = 1, LAST_MATVEC = 2 };
+// *_PROF: the memory traffic of a CG iteration with zero step lengths and no
+// scalar updates, on scratch vectors (tile tuning of the specialised passes).
+enum FirstMode { FIRST_CG = 0, FIRST_FIELD = 1, FIRST_BOUNDS = 2, FIRST_PROF = 3 };
+enum LastMode { LAST_CG = 0, LAST_RESID = 1, LAST_MATVEC = 2, LAST_PROF = 3 };
 enum ApplyMode { APPLY_COEF = 0, APPLY_QUAD = 1, APPLY_COEF_CG = 2, APPLY_GRID = 3, APPLY_FWD = 4 };
 constexpr int MID_CG = 2;  // flag or-ed into the inverse argument of launch_mid
 
@@ -135,6 +142,21 @@ size_t incl_dev_size();
 bool fast_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st, hipError_t* err);
 bool fast_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, int jstep, const int* iter_base,
               hipStream_t st, hipError_t* err);
-int fast_row_pairs(int M, int D, int L);
+// Row pairs per block for a requested value (0 or an unsupported value: the default).
+int fast_row_pairs(int M, int D, int L, int requested);
+bool fast_apply_supported(int M, int D, int P, int NC);
+
+// Tile shapes of the specialised passes: row pairs and threads per block of the
+// row passes, points per block of the column pass (0 = default).
+struct Tuning {
+  int rowG = 0, rowThreads = 0, apTP = 0;
+  double row_ms = 0.0, apply_ms = 0.0;   // measured per first+last pair and per column pass
+  int candidates = 0;                    // configurations timed
+};
+// Times every candidate tile shape of the specialised passes on the given
+// units (profile modes, scratch vectors) and returns the fastest in *best.
+// g.nbF / g.nbL need not be set.  Returns hipSuccess with best untouched when
+// no specialisation applies.
+hipError_t tune_fast(const Geo& g, const UnitDev* units, int n, hipStream_t st, int reps, Tuning* best);
 
 }  // namespace hom
