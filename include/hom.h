@@ -243,7 +243,7 @@ void hom_batch_destroy(hom_batch* b);
 /* ---- Tile tuning of the FP32 passes.
  * The specialised FP32 kernels (doubled-grid lengths 25, 81, 125, 625) have
  * several tile shapes: row pairs and threads per block of the row passes,
- * points per block of the column pass.  With tuning on (the default; the
+ * points per block and the LDS exchange width of the column pass.  With tuning on (the default; the
  * environment variable HOM_TUNE=0 turns it off at start-up), the first
  * mixed-precision solve of a geometry (grid, loads, primal/dual, coefficient
  * components) in the process times every candidate on that solve's own units,
@@ -255,6 +255,7 @@ typedef struct {
   int32_t row_pairs;     /* row pairs per block of the row passes (0: generic passes) */
   int32_t row_threads;   /* threads per row block (0: the smallest that covers the FFT) */
   int32_t apply_points;  /* points per column-pass block (0: default) */
+  int32_t apply_half_exchange; /* 1: the column pass exchanges real and imaginary parts in turn */
   int32_t candidates;    /* configurations timed (0: defaults, not tuned) */
   double row_ms;         /* measured time of one row-pass pair (first + last), ms */
   double apply_ms;       /* measured time of one column pass, ms */
@@ -267,6 +268,13 @@ hom_status hom_set_tuning(int32_t mode);
  * this problem / batch has chosen them yet. */
 hom_status hom_problem_tuning(hom_problem* pb, int32_t dual, int32_t nload, hom_tuning* out);
 hom_status hom_batch_tuning(hom_batch* b, int32_t dual, int32_t nload, hom_tuning* out);
+/* Pin the tile shape of the solves of (dual, nload): row_pairs, row_threads,
+ * apply_points and apply_half_exchange of *t (0 = default; the timing fields
+ * are ignored).  For bitwise-reproducible results across processes, or to
+ * compare shapes.  Mixed precision only; HOM_E_INVALID for a shape the
+ * specialised kernels do not have.  Synchronises the problem's stream. */
+hom_status hom_problem_set_tiles(hom_problem* pb, int32_t dual, int32_t nload, const hom_tuning* t);
+hom_status hom_batch_set_tiles(hom_batch* b, int32_t dual, int32_t nload, const hom_tuning* t);
 
 /* ---- Learned initial guess (measurement-independent helper of the solver).
  * Fields on the doubled grid M = 2N - 1, real FP32, [nload][d][M0][M1](M2):

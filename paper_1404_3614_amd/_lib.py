@@ -35,7 +35,8 @@ class UNetDesc(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("row_pairs", C.c_int32), ("row_threads", C.c_int32), ("apply_points", C.c_int32),
-                ("candidates", C.c_int32), ("row_ms", C.c_double), ("apply_ms", C.c_double)]
+                ("apply_half_exchange", C.c_int32), ("candidates", C.c_int32), ("row_ms", C.c_double),
+                ("apply_ms", C.c_double)]
 
 
 class Result(C.Structure):
@@ -91,6 +92,8 @@ EXPORTS = {
     "hom_set_tuning": (C.c_int32, [C.c_int32]),
     "hom_problem_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
     "hom_batch_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
+    "hom_problem_set_tiles": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
+    "hom_batch_set_tiles": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
     "hom_batch_destroy": (None, [C.c_void_p]),
 }
 

@@ -246,6 +246,12 @@ class Problem:
         L.check(L.load().hom_problem_tuning(self.h, int(dual), int(n), C.byref(t)), "hom_problem_tuning")
         return _tuning_dict(t)
 
+    def set_tiles(self, dual=False, nload=None, **shape):
+        """Pin the tile shape of this problem's FP32 solves (keys as returned by tuning())."""
+        n = self.d if nload is None else nload
+        t = _tiles(**shape)
+        L.check(L.load().hom_problem_set_tiles(self.h, int(dual), int(n), C.byref(t)), "hom_problem_set_tiles")
+
     def net_weights(self, out=None):
         """Energy weights [2][*M] (float32) of the primal and dual quadratures of this problem."""
         if out is None:
@@ -269,7 +275,15 @@ def set_tuning(on=True):
 
 def _tuning_dict(t):
     return dict(row_pairs=t.row_pairs, row_threads=t.row_threads, apply_points=t.apply_points,
-                candidates=t.candidates, row_ms=t.row_ms, apply_ms=t.apply_ms)
+                apply_half_exchange=t.apply_half_exchange, candidates=t.candidates, row_ms=t.row_ms,
+                apply_ms=t.apply_ms)
+
+
+def _tiles(row_pairs=0, row_threads=0, apply_points=0, apply_half_exchange=0, **_):
+    t = L.Tuning()
+    t.row_pairs, t.row_threads = int(row_pairs), int(row_threads)
+    t.apply_points, t.apply_half_exchange = int(apply_points), int(apply_half_exchange)
+    return t
 
 
 def _result_dict(res, d):
@@ -338,6 +352,12 @@ class Batch:
         n = self.d if nload is None else nload
         L.check(L.load().hom_batch_tuning(self.h, int(dual), int(n), C.byref(t)), "hom_batch_tuning")
         return _tuning_dict(t)
+
+    def set_tiles(self, dual=False, nload=None, **shape):
+        """Pin the tile shape of this batch's FP32 solves (keys as returned by tuning())."""
+        n = self.d if nload is None else nload
+        t = _tiles(**shape)
+        L.check(L.load().hom_batch_set_tiles(self.h, int(dual), int(n), C.byref(t)), "hom_batch_set_tiles")
 
     def set_timing(self, on=True):
         L.check(L.load().hom_batch_set_timing(self.h, int(bool(on))), "hom_batch_set_timing")

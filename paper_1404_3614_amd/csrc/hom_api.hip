@@ -305,6 +305,7 @@ Geo make_geo(const hom_problem* pb, int dual, int L, bool fp32, int P_override =
       g.rowG = tune->rowG;
       g.rowThreads = tune->rowThreads;
       g.apTP = tune->apTP;
+      g.apHX = tune->apHX;
     }
     const int G = fast_row_pairs(z.M[2], z.d, L, g.rowG);
     if (G > 0) g.nbF = g.nbL = (z.Q + G - 1) / G;
@@ -1435,6 +1436,7 @@ static void tuning_report(const hom_problem* p0, int k, int nload, const Tuning&
   out->row_pairs = p0->desc.precision == HOM_MIXED ? fast_row_pairs(g.M[2], g.d, nload, t.rowG) : 0;
   out->row_threads = t.rowThreads;
   out->apply_points = t.apTP;
+  out->apply_half_exchange = t.apHX;
   out->candidates = t.candidates;
   out->row_ms = t.row_ms;
   out->apply_ms = t.apply_ms;
@@ -1444,6 +1446,52 @@ hom_status hom_set_tuning(int32_t mode) {
   if (mode != 0 && mode != 1) return HOM_E_INVALID;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_mode = mode;
+  return HOM_OK;
+}
+
+// Validate a caller-chosen tile shape for solves of (dual, nload) of problem p0.
+static bool tiles_ok(const hom_problem* p0, int nload, const hom_tuning* t) {
+  if (p0->desc.precision != HOM_MIXED) return false;
+  const Sizes& z = p0->z;
+  if (t->row_pairs != 0 && fast_row_pairs(z.M[2], z.d, nload, t->row_pairs) != t->row_pairs) return false;
+  if (t->row_threads != 0 && (t->row_threads % 64 != 0 || t->row_threads > 256)) return false;
+  return fast_apply_shape_ok(z.M[0], z.d, t->apply_points, t->apply_half_exchange);
+}
+
+static Tuning tiles_from(const hom_tuning* t) {
+  Tuning u;
+  u.rowG = t->row_pairs;
+  u.rowThreads = t->row_threads;
+  u.apTP = t->apply_points;
+  u.apHX = t->apply_half_exchange;
+  return u;
+}
+
+hom_status hom_problem_set_tiles(hom_problem* pb, int32_t dual, int32_t nload, const hom_tuning* t) {
+  if (!pb || !t || (dual != 0 && dual != 1) || nload < 1 || nload > pb->max_loads) return HOM_E_INVALID;
+  if (!tiles_ok(pb, nload, t)) return HOM_E_INVALID;
+  const int k = dual;
+  HIPCHK(hipStreamSynchronize(pb->stream));
+  if (pb->graph[k][nload]) {
+    (void)hipGraphExecDestroy(pb->graph[k][nload]);
+    pb->graph[k][nload] = nullptr;
+  }
+  pb->tune[k][nload] = tiles_from(t);
+  pb->tuned[k][nload] = true;
+  return HOM_OK;
+}
+
+hom_status hom_batch_set_tiles(hom_batch* b, int32_t dual, int32_t nload, const hom_tuning* t) {
+  if (!b || !t || (dual != 0 && dual != 1) || nload < 1 || nload > b->pbs[0]->max_loads) return HOM_E_INVALID;
+  if (!tiles_ok(b->pbs[0], nload, t)) return HOM_E_INVALID;
+  const int k = dual;
+  HIPCHK(hipStreamSynchronize(b->stream));
+  if (b->graph[k][nload]) {
+    (void)hipGraphExecDestroy(b->graph[k][nload]);
+    b->graph[k][nload] = nullptr;
+  }
+  b->tune[k][nload] = tiles_from(t);
+  b->tuned[k][nload] = true;
   return HOM_OK;
 }
 

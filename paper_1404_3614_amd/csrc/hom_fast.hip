@@ -44,11 +44,138 @@ __device__ __forceinline__ int kept(int pos) {
 }  // namespace
 
 // ============================================================== column pass
-// TP points per block, T threads per point.  In 2D the packs are independent
-// (pack l holds the two components of load l, and the coefficient couples only
-// those), so each block takes one pack (grid y = pack) and holds one line per
-// thread group in registers; in 3D a load straddles packs and a block holds
-// all packs of its points.
+// Exchange of register lines between the two steps of a four-step FFT
+// through LDS: threads with `wr` store NW values at slots (wbase + j), threads
+// with `rd` load NR values from slots (rbase + j rstep); a slot holds TP
+// points.  HX = 1 moves the real parts and then the imaginary parts through a
+// real-valued buffer of half the size (more blocks per CU for the same LDS).
+template <typename R, int NW, int NR, int TP, int HX>
+__device__ __forceinline__ void xchg(Cx<R>* ex, Cx<R>* v, bool wr, int wbase, bool rd, int rbase, int rstep, int pt) {
+  if constexpr (!HX) {
+    if (wr) {
+#pragma unroll
+      for (int j = 0; j < NW; ++j) ex[(wbase + j) * TP + pt] = v[j];
+    }
+    __syncthreads();
+    if (rd) {
+#pragma unroll
+      for (int j = 0; j < NR; ++j) v[j] = ex[(rbase + j * rstep) * TP + pt];
+    }
+    __syncthreads();
+  } else {
+    R* e = reinterpret_cast<R*>(ex);
+    R t[NR];
+    if (wr) {
+#pragma unroll
+      for (int j = 0; j < NW; ++j) e[(wbase + j) * TP + pt] = v[j].x;
+    }
+    __syncthreads();
+    if (rd) {
+#pragma unroll
+      for (int j = 0; j < NR; ++j) t[j] = e[(rbase + j * rstep) * TP + pt];
+    }
+    __syncthreads();
+    if (wr) {
+#pragma unroll
+      for (int j = 0; j < NW; ++j) e[(wbase + j) * TP + pt] = v[j].y;
+    }
+    __syncthreads();
+    if (rd) {
+#pragma unroll
+      for (int j = 0; j < NR; ++j) v[j] = rf::mk<R>(t[j], e[(rbase + j * rstep) * TP + pt]);
+    }
+    __syncthreads();
+  }
+}
+
+// 2D column pass: the packs are independent (pack l holds the two components
+// of load l, and the coefficient couples only those), so a block takes one
+// pack of TP points, T threads per point, one line per thread group in
+// registers.  Block order is XCD-aware: blocks b and b + 8 run on the same
+// XCD (round-robin dispatch), so each XCD takes a contiguous range of point
+// blocks and, within it, the packs of one point block back to back (shared L2
+// lines of the coefficient and of neighbouring points).
+template <typename R, int M, int P, int NC, int TP, int HX>
+__global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply2_fast(Geo g, const UnitDev* __restrict__ units, int cg) {
+  constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem);   // [M]
+  Cx<R>* ex = tw + M;                           // exchange [M][TP]
+  const UnitDev& U = units[blockIdx.z];
+  if (cg && !any_active(U, g.L)) return;
+  const int npts = g.M[2];
+  const size_t Mtot = (size_t)M * npts;
+  const int nbx = (npts + TP - 1) / TP, nbx8 = (nbx + 7) / 8;
+  const int xcd = blockIdx.x % 8, w8 = blockIdx.x / 8, cbl = w8 / P, cb = xcd * nbx8 + cbl;
+  const int pk = w8 % P;
+  if (cbl >= nbx8 || cb >= nbx) return;
+  const int p0 = cb * TP;
+  const int tid = threadIdx.x, pt = tid % TP, q = tid / TP;
+  const bool ok = (p0 + pt) < npts;
+  const Cx<R>* twg = reinterpret_cast<const Cx<R>*>(g.tw[0]);
+  for (int i = tid; i < M; i += blockDim.x) tw[i] = twg[i];
+  Cx<R>* data = reinterpret_cast<Cx<R>*>(U.bufA);
+  // element (row i0, point p0 + pt, pack pk): pack-major [P][N0][npts] or packs interleaved
+  const size_t rs = g.pmaj ? (size_t)npts : (size_t)npts * P, ps = g.pmaj ? (size_t)g.N[0] * npts : 1;
+  const size_t cbase = g.pmaj ? (size_t)(p0 + pt) : (size_t)(p0 + pt) * P;
+  const R* coef = reinterpret_cast<const R*>(U.coef);
+  __syncthreads();
+
+  Cx<R> v[T];
+  // inverse, step 1: thread n2 = q holds x[B n1 + n2] (zero-padded N -> M)
+#pragma unroll
+  for (int n1 = 0; n1 < A; ++n1) {
+    const int i0 = (q < B && ok) ? kept<M>(B * n1 + q) : -1;
+    v[n1] = i0 >= 0 ? data[i0 * rs + cbase + pk * ps] : rf::mk<R>(0, 0);
+  }
+  if (q < B) {
+    rf::Dft<R, A, 1>::run(v);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      Cx<R> w = tw[q * k1];
+      w.y = -w.y;
+      v[k1] = rf::mul(v[k1], w);
+    }
+  }
+  xchg<R, A, B, TP, HX>(ex, v, q < B, q * A, q < A, q, A, pt);
+  if (q < A) {
+    rf::Dft<R, B, 1>::run(v);
+    // thread k1 = q holds u at x0 = q + A k2: the coefficient on the doubled grid
+    if (ok) {
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) {
+        const size_t ci = (size_t)(q + A * k2) * npts + p0 + pt;
+        R a[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) a[c] = coef[c * Mtot + ci];
+        const R u[2] = {v[k2].x, v[k2].y};
+        R w[2];
+        coef_mul<R>(2, NC, a, u, w);
+        v[k2] = rf::mk<R>(w[0], w[1]);
+      }
+    }
+    // forward: step over n2 in registers (thread n1 = q), exchange, step over n1
+    rf::Dft<R, B, -1>::run(v);
+#pragma unroll
+    for (int m2 = 0; m2 < B; ++m2) v[m2] = rf::mul(v[m2], tw[q * m2]);
+  }
+  xchg<R, B, A, TP, HX>(ex, v, q < A, q * B, q < B, q, B, pt);
+  if (q < B) {
+    rf::Dft<R, A, -1>::run(v);
+    // thread m2 = q holds X[q + B m1]: store the Z_N0 part
+    if (ok) {
+#pragma unroll
+      for (int m1 = 0; m1 < A; ++m1) {
+        const int i0 = kept<M>(q + B * m1);
+        if (i0 >= 0) data[i0 * rs + cbase + pk * ps] = v[m1];
+      }
+    }
+  }
+}
+
+// 3D column pass: TP points per block, T threads per point, all packs of a
+// point held together (a load's three components straddle packs and the
+// coefficient couples them).
 template <typename R, int M, int D, int P, int NC, int TP>
 __global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply_fast(Geo g, const UnitDev* __restrict__ units, int cg) {
   constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T;
@@ -59,18 +186,7 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply_fast(Geo g, const Unit
   if (cg && !any_active(U, g.L)) return;
   const int npts = g.M[1] * g.M[2];
   const size_t Mtot = (size_t)M * npts;
-  int p0 = blockIdx.x * TP, pk2 = 0;
-  if constexpr (D == 2) {
-    // XCD-aware order: blocks b and b + 8 run on the same XCD (round-robin
-    // dispatch), so each XCD takes a contiguous range of column blocks and,
-    // within it, the packs of one column block back to back (shared L2 lines
-    // of the coefficient and of the neighbouring columns)
-    const int nbx = (npts + TP - 1) / TP, nbx8 = (nbx + 7) / 8;
-    const int xcd = blockIdx.x % 8, w = blockIdx.x / 8, cbl = w / P, cb = xcd * nbx8 + cbl;
-    pk2 = w % P;
-    if (cbl >= nbx8 || cb >= nbx) return;
-    p0 = cb * TP;
-  }
+  const int p0 = blockIdx.x * TP;
   const int tid = threadIdx.x, pt = tid % TP, q = tid / TP;
   const bool ok = (p0 + pt) < npts;
   const Cx<R>* twg = reinterpret_cast<const Cx<R>*>(g.tw[0]);
@@ -80,143 +196,76 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply_fast(Geo g, const Unit
   const size_t rowstride = (size_t)npts * P;
   const R* coef = reinterpret_cast<const R*>(U.coef);
 
-  if constexpr (D == 2) {
-    __syncthreads();
-    {
-      const int pk = pk2;  // one pack per block
-      // element (row i0, column p0 + pt, pack pk): pack-major or packs interleaved
-      const size_t rs = g.pmaj ? (size_t)npts : rowstride, ps = g.pmaj ? (size_t)g.N[0] * npts : 1;
-      const size_t cbase = g.pmaj ? (size_t)(p0 + pt) : col;
-      Cx<R> v[T];
-      // inverse, step 1: thread n2 = q holds x[B n1 + n2] (zero-padded N -> M)
+  Cx<R> v[P][T];
 #pragma unroll
-      for (int n1 = 0; n1 < A; ++n1) {
-        const int i0 = (q < B && ok) ? kept<M>(B * n1 + q) : -1;
-        v[n1] = i0 >= 0 ? data[i0 * rs + cbase + pk * ps] : rf::mk<R>(0, 0);
+  for (int n1 = 0; n1 < A; ++n1) {
+    const int i0 = (q < B && ok) ? kept<M>(B * n1 + q) : -1;
+#pragma unroll
+    for (int pk = 0; pk < P; ++pk) v[pk][n1] = i0 >= 0 ? data[i0 * rowstride + col + pk] : rf::mk<R>(0, 0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int pk = 0; pk < P; ++pk) {
+    if (q < B) {
+      rf::Dft<R, A, 1>::run(v[pk]);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) {
+        Cx<R> w = tw[q * k1];
+        w.y = -w.y;
+        ex[(q * A + k1) * TP + pt] = rf::mul(v[pk][k1], w);
       }
-      if (q < B) {
-        rf::Dft<R, A, 1>::run(v);
-#pragma unroll
-        for (int k1 = 0; k1 < A; ++k1) {
-          Cx<R> w = tw[q * k1];
-          w.y = -w.y;
-          ex[(q * A + k1) * TP + pt] = rf::mul(v[k1], w);
-        }
-      }
-      __syncthreads();
-      if (q < A) {
-#pragma unroll
-        for (int n2 = 0; n2 < B; ++n2) v[n2] = ex[(n2 * A + q) * TP + pt];
-      }
-      __syncthreads();
-      if (q < A) {
-        rf::Dft<R, B, 1>::run(v);
-        // thread k1 = q holds u at x0 = q + A k2: the coefficient on the doubled grid
-        if (ok) {
-#pragma unroll
-          for (int k2 = 0; k2 < B; ++k2) {
-            const size_t ci = (size_t)(q + A * k2) * npts + p0 + pt;
-            R a[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) a[c] = coef[c * Mtot + ci];
-            const R u[2] = {v[k2].x, v[k2].y};
-            R w[2];
-            coef_mul<R>(2, NC, a, u, w);
-            v[k2] = rf::mk<R>(w[0], w[1]);
-          }
-        }
-        // forward: step over n2 in registers (thread n1 = q), exchange, step over n1
-        rf::Dft<R, B, -1>::run(v);
-#pragma unroll
-        for (int m2 = 0; m2 < B; ++m2) ex[(q * B + m2) * TP + pt] = rf::mul(v[m2], tw[q * m2]);
-      }
-      __syncthreads();
-      if (q < B) {
-#pragma unroll
-        for (int n1 = 0; n1 < A; ++n1) v[n1] = ex[(n1 * B + q) * TP + pt];
-        rf::Dft<R, A, -1>::run(v);
-        // thread m2 = q holds X[q + B m1]: store the Z_N0 part
-        if (ok) {
-#pragma unroll
-          for (int m1 = 0; m1 < A; ++m1) {
-            const int i0 = kept<M>(q + B * m1);
-            if (i0 >= 0) data[i0 * rs + cbase + pk * ps] = v[m1];
-          }
-        }
-      }
-    }
-  } else {
-    Cx<R> v[P][T];
-#pragma unroll
-    for (int n1 = 0; n1 < A; ++n1) {
-      const int i0 = (q < B && ok) ? kept<M>(B * n1 + q) : -1;
-#pragma unroll
-      for (int pk = 0; pk < P; ++pk) v[pk][n1] = i0 >= 0 ? data[i0 * rowstride + col + pk] : rf::mk<R>(0, 0);
     }
     __syncthreads();
+    if (q < A) {
 #pragma unroll
-    for (int pk = 0; pk < P; ++pk) {
-      if (q < B) {
-        rf::Dft<R, A, 1>::run(v[pk]);
-#pragma unroll
-        for (int k1 = 0; k1 < A; ++k1) {
-          Cx<R> w = tw[q * k1];
-          w.y = -w.y;
-          ex[(q * A + k1) * TP + pt] = rf::mul(v[pk][k1], w);
-        }
-      }
-      __syncthreads();
-      if (q < A) {
-#pragma unroll
-        for (int n2 = 0; n2 < B; ++n2) v[pk][n2] = ex[(n2 * A + q) * TP + pt];
-        rf::Dft<R, B, 1>::run(v[pk]);
-      }
-      __syncthreads();
+      for (int n2 = 0; n2 < B; ++n2) v[pk][n2] = ex[(n2 * A + q) * TP + pt];
+      rf::Dft<R, B, 1>::run(v[pk]);
     }
-    if (q < A && ok) {
+    __syncthreads();
+  }
+  if (q < A && ok) {
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) {
-        const size_t ci = (size_t)(q + A * k2) * npts + p0 + pt;
-        R a[NC];
+    for (int k2 = 0; k2 < B; ++k2) {
+      const size_t ci = (size_t)(q + A * k2) * npts + p0 + pt;
+      R a[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) a[c] = coef[c * Mtot + ci];
-        R u[2 * P], w[2 * P];
+      for (int c = 0; c < NC; ++c) a[c] = coef[c * Mtot + ci];
+      R u[2 * P], w[2 * P];
 #pragma unroll
-        for (int pk = 0; pk < P; ++pk) {
-          u[2 * pk] = v[pk][k2].x;
-          u[2 * pk + 1] = v[pk][k2].y;
-        }
-#pragma unroll
-        for (int f = 0; f < 2 * P; ++f) w[f] = (R)0;
-#pragma unroll
-        for (int l = 0; l < (2 * P) / D; ++l) coef_mul<R>(D, NC, a, u + l * D, w + l * D);
-#pragma unroll
-        for (int pk = 0; pk < P; ++pk) v[pk][k2] = rf::mk<R>(w[2 * pk], w[2 * pk + 1]);
+      for (int pk = 0; pk < P; ++pk) {
+        u[2 * pk] = v[pk][k2].x;
+        u[2 * pk + 1] = v[pk][k2].y;
       }
+#pragma unroll
+      for (int f = 0; f < 2 * P; ++f) w[f] = (R)0;
+#pragma unroll
+      for (int l = 0; l < (2 * P) / D; ++l) coef_mul<R>(D, NC, a, u + l * D, w + l * D);
+#pragma unroll
+      for (int pk = 0; pk < P; ++pk) v[pk][k2] = rf::mk<R>(w[2 * pk], w[2 * pk + 1]);
     }
+  }
 #pragma unroll
-    for (int pk = 0; pk < P; ++pk) {
-      if (q < A) {
-        rf::Dft<R, B, -1>::run(v[pk]);
+  for (int pk = 0; pk < P; ++pk) {
+    if (q < A) {
+      rf::Dft<R, B, -1>::run(v[pk]);
 #pragma unroll
-        for (int m2 = 0; m2 < B; ++m2) ex[(q * B + m2) * TP + pt] = rf::mul(v[pk][m2], tw[q * m2]);
-      }
-      __syncthreads();
-      if (q < B) {
-#pragma unroll
-        for (int n1 = 0; n1 < A; ++n1) v[pk][n1] = ex[(n1 * B + q) * TP + pt];
-        rf::Dft<R, A, -1>::run(v[pk]);
-      }
-      __syncthreads();
+      for (int m2 = 0; m2 < B; ++m2) ex[(q * B + m2) * TP + pt] = rf::mul(v[pk][m2], tw[q * m2]);
     }
-    if (q < B && ok) {
+    __syncthreads();
+    if (q < B) {
 #pragma unroll
-      for (int m1 = 0; m1 < A; ++m1) {
-        const int i0 = kept<M>(q + B * m1);
-        if (i0 >= 0)
+      for (int n1 = 0; n1 < A; ++n1) v[pk][n1] = ex[(n1 * B + q) * TP + pt];
+      rf::Dft<R, A, -1>::run(v[pk]);
+    }
+    __syncthreads();
+  }
+  if (q < B && ok) {
 #pragma unroll
-          for (int pk = 0; pk < P; ++pk) data[i0 * rowstride + col + pk] = v[pk][m1];
-      }
+    for (int m1 = 0; m1 < A; ++m1) {
+      const int i0 = kept<M>(q + B * m1);
+      if (i0 >= 0)
+#pragma unroll
+        for (int pk = 0; pk < P; ++pk) data[i0 * rowstride + col + pk] = v[pk][m1];
     }
   }
 }
@@ -676,32 +725,58 @@ __global__ __launch_bounds__(256) void k_last_fast(Geo g, const UnitDev* __restr
 // ============================================================== dispatch
 // Candidate tile shapes per FFT length (the first entry is the default).
 // Row passes: pairs per block (2 G T <= 256 threads); column pass: points per block.
+// 2D column pass: (points per block, half exchange) pairs.
+struct ApC {
+  int tp, hx;
+};
 template <int M>
 struct Cands;
 template <>
 struct Cands<625> {
   static constexpr int G[3] = {2, 1, 4};
   static constexpr int TP[2] = {8, 4};
+  static constexpr ApC AP2[4] = {{8, 0}, {10, 1}, {5, 1}, {4, 0}};
 };
 template <>
 struct Cands<125> {
   static constexpr int G[3] = {4, 2, 1};
   static constexpr int TP[2] = {10, 5};
+  static constexpr ApC AP2[4] = {{10, 0}, {5, 0}, {10, 1}, {5, 1}};
 };
 template <>
 struct Cands<81> {
   static constexpr int G[3] = {14, 7, 4};
   static constexpr int TP[2] = {28, 14};
+  static constexpr ApC AP2[4] = {{28, 0}, {14, 0}, {28, 1}, {14, 1}};
 };
 template <>
 struct Cands<25> {
   static constexpr int G[3] = {25, 12, 6};
   static constexpr int TP[2] = {51, 25};
+  static constexpr ApC AP2[4] = {{51, 0}, {25, 0}, {51, 1}, {25, 1}};
 };
 
 static bool apply_supported(int M, int D, int P, int NC) {
   if (D == 2) return (M == 625 || M == 125 || M == 81 || M == 25) && (P == 1 || P == 2) && (NC == 1 || NC == 3);
   return M == 81 && (P == 2 || P == 3 || P == 5) && (NC == 1 || NC == 6);
+}
+
+// Whether (tp, hx) is a column-pass shape of the specialised kernels (0, 0: default).
+bool fast_apply_shape_ok(int M, int D, int tp, int hx) {
+  if (tp == 0 && hx == 0) return true;
+  auto in2 = [&](const ApC* c) {
+    for (int i = 0; i < 4; ++i)
+      if (c[i].tp == tp && c[i].hx == hx) return true;
+    return false;
+  };
+  auto in3 = [&](const int* c) { return hx == 0 && (c[0] == tp || c[1] == tp); };
+  switch (M) {
+    case 625: return D == 2 ? in2(Cands<625>::AP2) : in3(Cands<625>::TP);
+    case 125: return D == 2 ? in2(Cands<125>::AP2) : in3(Cands<125>::TP);
+    case 81: return D == 2 ? in2(Cands<81>::AP2) : in3(Cands<81>::TP);
+    case 25: return D == 2 ? in2(Cands<25>::AP2) : in3(Cands<25>::TP);
+    default: return false;
+  }
 }
 
 bool fast_apply_supported(int M, int D, int P, int NC) {
@@ -741,8 +816,7 @@ static hipError_t run_apply_tp(const Geo& g, const UnitDev* units, int n, int cg
   auto kern = k_apply_fast<float, M, D, P, NC, TP>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int nbx = (npts + TP - 1) / TP;
-  const dim3 grid(D == 2 ? 8 * ((nbx + 7) / 8) * P : nbx, 1, n);
+  const dim3 grid((npts + TP - 1) / TP, 1, n);
   if (g_ext_timing.on)
     hipExtLaunchKernelGGL(kern, grid, dim3(TP * T), lds, st, g_ext_timing.start, g_ext_timing.stop, 0, g, units, cg);
   else
@@ -750,11 +824,45 @@ static hipError_t run_apply_tp(const Geo& g, const UnitDev* units, int n, int cg
   return hipGetLastError();
 }
 
+template <int M, int P, int NC, int TP, int HX>
+static hipError_t run_apply2_tp(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st) {
+  constexpr int T = Cfg<M>::T;
+  const int npts = g.M[2];
+  const size_t lds = (size_t)M * sizeof(Cx<float>) + (size_t)M * TP * (HX ? sizeof(float) : sizeof(Cx<float>));
+  auto kern = k_apply2_fast<float, M, P, NC, TP, HX>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const int nbx = (npts + TP - 1) / TP;
+  const dim3 grid(8 * ((nbx + 7) / 8) * P, 1, n);
+  if (g_ext_timing.on)
+    hipExtLaunchKernelGGL(kern, grid, dim3(TP * T), lds, st, g_ext_timing.start, g_ext_timing.stop, 0, g, units, cg);
+  else
+    hipLaunchKernelGGL(kern, grid, dim3(TP * T), lds, st, g, units, cg);
+  return hipGetLastError();
+}
+
+template <int M, int P, int NC, int I = 0>
+static hipError_t run_apply2(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st) {
+  constexpr ApC c = Cands<M>::AP2[I];
+  if constexpr (I + 1 < 4) {
+    if (!(g.apTP == c.tp && g.apHX == c.hx)) return run_apply2<M, P, NC, I + 1>(g, units, n, cg, st);
+    return run_apply2_tp<M, P, NC, c.tp, c.hx>(g, units, n, cg, st);
+  } else {
+    if (g.apTP == c.tp && g.apHX == c.hx) return run_apply2_tp<M, P, NC, c.tp, c.hx>(g, units, n, cg, st);
+    constexpr ApC c0 = Cands<M>::AP2[0];  // default
+    return run_apply2_tp<M, P, NC, c0.tp, c0.hx>(g, units, n, cg, st);
+  }
+}
+
 template <int M, int D, int P, int NC>
 static hipError_t run_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st) {
-  constexpr int TP0 = Cands<M>::TP[0], TP1 = Cands<M>::TP[1];
-  if (g.apTP == TP1) return run_apply_tp<M, D, P, NC, TP1>(g, units, n, cg, st);
-  return run_apply_tp<M, D, P, NC, TP0>(g, units, n, cg, st);
+  if constexpr (D == 2) {
+    return run_apply2<M, P, NC>(g, units, n, cg, st);
+  } else {
+    constexpr int TP0 = Cands<M>::TP[0], TP1 = Cands<M>::TP[1];
+    if (g.apTP == TP1) return run_apply_tp<M, D, P, NC, TP1>(g, units, n, cg, st);
+    return run_apply_tp<M, D, P, NC, TP0>(g, units, n, cg, st);
+  }
 }
 
 // Returns true when a specialised column pass handled the launch (*err set).
@@ -912,9 +1020,11 @@ static hipError_t tune_m(const Geo& g0, const UnitDev* units, int n, hipStream_t
   }
   if (e == hipSuccess && apply_supported(M, g0.d, g0.P, g0.nc) && g0.M[0] == M) {
     double bms = 1e30;
-    for (int ti = 0; ti < 2 && e == hipSuccess; ++ti) {
+    const int ncand = g0.d == 2 ? 4 : 2;
+    for (int ci = 0; ci < ncand && e == hipSuccess; ++ci) {
       Geo g = g0;
-      g.apTP = Cands<M>::TP[ti];
+      g.apTP = g0.d == 2 ? Cands<M>::AP2[ci].tp : Cands<M>::TP[ci];
+      g.apHX = g0.d == 2 ? Cands<M>::AP2[ci].hx : 0;
       float ms = 0.f;
       e = time_ms(st, reps, &ms, [&]() -> hipError_t {
         hipError_t x = hipSuccess;
@@ -925,6 +1035,7 @@ static hipError_t tune_m(const Geo& g0, const UnitDev* units, int n, hipStream_t
       if (e == hipSuccess && ms < bms) {
         bms = ms;
         t.apTP = g.apTP;
+        t.apHX = g.apHX;
         t.apply_ms = ms;
       }
     }

@@ -78,6 +78,7 @@ struct Geo {
   int rowG;            // row pairs per block of the specialised row passes (0: default)
   int rowThreads;      // threads per block of the specialised row passes (0: default)
   int apTP;            // points per block of the specialised column pass (0: default)
+  int apHX;            // 2D column pass: exchange real and imaginary parts separately
   int pmaj;            // 2D, both specialised passes: row-pass buffer pack-major [P][N0][M2]
                        // (otherwise [N0][N1][M2][P], packs interleaved)
   int phys_axis[3];
@@ -145,11 +146,12 @@ bool fast_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, i
 // Row pairs per block for a requested value (0 or an unsupported value: the default).
 int fast_row_pairs(int M, int D, int L, int requested);
 bool fast_apply_supported(int M, int D, int P, int NC);
+bool fast_apply_shape_ok(int M, int D, int tp, int hx);
 
 // Tile shapes of the specialised passes: row pairs and threads per block of the
 // row passes, points per block of the column pass (0 = default).
 struct Tuning {
-  int rowG = 0, rowThreads = 0, apTP = 0;
+  int rowG = 0, rowThreads = 0, apTP = 0, apHX = 0;
   double row_ms = 0.0, apply_ms = 0.0;   // measured per first+last pair and per column pass
   int candidates = 0;                    // configurations timed
 };

@@ -1,0 +1,107 @@
+"""GPU: tile shapes of the specialised FP32 passes.
+
+Every shape computes the same method: a column-pass shape changes only which
+threads transform which points, so results are bitwise equal; a row-pass
+shape changes the blocking of the CG reductions, so results agree to the
+rounding of those sums (1e-10 relative on the bounds, iteration counts within
+one).  The tuner reports a timed choice, and pinned shapes are validated."""
+import numpy as np
+import pytest
+
+import homgen
+
+pytestmark = pytest.mark.gpu
+
+# doubled-grid length -> (row shapes (pairs, threads), column shapes (points, half exchange))
+SHAPES = {
+    25: ([(25, 0), (12, 0), (6, 0), (12, 256), (6, 256)], [(51, 0), (25, 0), (51, 1), (25, 1)]),
+    81: ([(14, 0), (7, 0), (4, 0), (7, 256), (4, 256)], [(28, 0), (14, 0), (28, 1), (14, 1)]),
+    125: ([(4, 0), (2, 0), (1, 0), (2, 256), (1, 256)], [(10, 0), (5, 0), (10, 1), (5, 1)]),
+}
+
+
+def _H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1404_3614_amd as H
+    from paper_1404_3614_amd import _lib
+    _lib.load()
+    return H
+
+
+def relerr(X, R):
+    return float(np.abs(np.asarray(X) - np.asarray(R)).max() / np.linalg.norm(np.asarray(R), 2))
+
+
+def _batch(H, N, seeds):
+    import torch
+    st = torch.cuda.Stream()
+    cells = [homgen.pixel_cell(seed=s, P=25, values=(1.0, 30.0 + 20 * i)) for i, s in enumerate(seeds)]
+    probs = [H.problem_from_cell(c, N, precision="mixed", max_loads=2, stream=st) for c in cells]
+    return probs, H.Batch(probs)
+
+
+def _pin(b, **shape):
+    for dual in (False, True):
+        b.set_tiles(dual, 2, **shape)
+
+
+def _iters(out):
+    return [[i["iters"] for i in r["info_primal"] + r["info_dual"]] for r in out]
+
+
+@pytest.mark.parametrize("N", [13, 41, 63], ids=["M25", "M81", "M125"])
+def test_every_tile_shape_gives_the_same_bounds(N):
+    H = _H()
+    M = 2 * N - 1
+    rows, cols = SHAPES[M]
+    probs, b = _batch(H, (N, N), [900 + N, 901 + N])
+    _pin(b)
+    ref = b.solve_bounds(tol=1e-8)
+    print(f"[tiles] M={M} default iterations {_iters(ref)}", flush=True)
+    for tp, hx in cols:
+        _pin(b, apply_points=tp, apply_half_exchange=hx)
+        out = b.solve_bounds(tol=1e-8)
+        for r, o in zip(ref, out):
+            assert np.array_equal(r["A_up"], o["A_up"]) and np.array_equal(r["A_low"], o["A_low"]), (tp, hx)
+        assert _iters(out) == _iters(ref)
+    for G, thr in rows:
+        _pin(b, row_pairs=G, row_threads=thr)
+        out = b.solve_bounds(tol=1e-8)
+        for r, o in zip(ref, out):
+            assert relerr(o["A_up"], r["A_up"]) <= 1e-10 and relerr(o["A_low"], r["A_low"]) <= 1e-10, (G, thr)
+        for a, c in zip(_iters(out), _iters(ref)):
+            assert max(abs(x - y) for x, y in zip(a, c)) <= 1
+    with pytest.raises(H.HomError):
+        b.set_tiles(False, 2, row_pairs=3)
+    with pytest.raises(H.HomError):
+        b.set_tiles(False, 2, apply_points=7)
+    with pytest.raises(H.HomError):
+        b.set_tiles(False, 2, row_threads=96)
+
+
+def test_tuner_reports_a_timed_choice_and_batch_matches_single():
+    H = _H()
+    # N = 41 with one load: a geometry no other test of this file tunes first
+    probs, b = _batch(H, (41, 41), [1201, 1202, 1203])
+    t = b.tuning(False, 1)
+    print(f"[tiles] tuned {t}", flush=True)
+    assert t["candidates"] >= 3 and t["row_ms"] > 0 and t["apply_ms"] > 0
+    assert t["row_pairs"] in (14, 7, 4)
+    assert (t["apply_points"], t["apply_half_exchange"]) in SHAPES[81][1]
+    # every later solve of the geometry, batched or single, uses the same choice
+    E = np.array([[1.0, 0.0]])
+    xb, ib = b.solve(False, E=E, tol=1e-8)
+    for i, p in enumerate(probs):
+        assert p.tuning(False, 1)["row_pairs"] == t["row_pairs"]
+        xs, is_ = p.solve(False, E=E, tol=1e-8)
+        assert bool((xs[0] == xb[i][0]).all()) and is_[0]["iters"] == ib[i][0]["iters"]
+
+
+def test_fp64_problems_reject_pinned_tiles():
+    H = _H()
+    cell = homgen.square_inclusion_cell()
+    pb = H.problem_from_cell(cell, (13, 13), precision="fp64")
+    with pytest.raises(H.HomError):
+        pb.set_tiles(False, 2, row_pairs=25)
+    assert pb.tuning(False, 2)["candidates"] == 0
