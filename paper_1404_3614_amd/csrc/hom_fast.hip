@@ -340,7 +340,7 @@ __device__ __forceinline__ void row_info(const Geo& g, int qpair, RowInfo& ri) {
 // load per block (its pack is independent of the others), in 3D all loads.
 // P packs of the block start at pack po of the Pg packs of the field buffers.
 template <typename R, int M, int D, int L, int DUAL, int G>
-__global__ __launch_bounds__(256) void k_first_fast(Geo g, const UnitDev* __restrict__ units, int mode, int jstep,
+__global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_first_fast(Geo g, const UnitDev* __restrict__ units, int mode, int jstep,
                                                     const int* __restrict__ iter_base) {
   constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T, N2 = Cfg<M>::N, H2 = Cfg<M>::H;
   constexpr int P = (L * D + 1) / 2, m = DUAL ? D - 1 : 1, d = D;
@@ -524,7 +524,7 @@ __global__ __launch_bounds__(256) void k_first_fast(Geo g, const UnitDev* __rest
 }
 
 template <typename R, int M, int D, int L, int DUAL, int G>
-__global__ __launch_bounds__(256) void k_last_fast(Geo g, const UnitDev* __restrict__ units, int mode, int jstep,
+__global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const UnitDev* __restrict__ units, int mode, int jstep,
                                                    const int* __restrict__ iter_base) {
   constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T, N2 = Cfg<M>::N;
   constexpr int P = (L * D + 1) / 2, m = DUAL ? D - 1 : 1, d = D;
