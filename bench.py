@@ -127,10 +127,11 @@ def main():
     batch = H.Batch(probs)
     state = {"batch": batch, "probs": probs}
 
+    pairs = [(Ah, Bh) for (Ah, Bh, nc) in coefs]
+
     def step():
         # a1: doubled-grid coefficients of every cell; a2-a10: lockstep CG of the batch; a8: bounds
-        for p, (Ah, Bh, nc) in zip(probs, coefs):
-            p.update_coefficients(Ah, Bh)
+        batch.update_coefficients(pairs)
         return batch.solve_bounds(tol=args.tol)
 
     for _ in range(args.warmup):

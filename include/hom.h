@@ -219,6 +219,10 @@ hom_status hom_batch_create(hom_problem* const* pbs, int32_t n, void* ws, size_t
 hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const double* E, const double* const* x0,
                            double tol, int32_t maxit, double* const* x_out, hom_info* info);
 
+/* hom_update_coefficients for every problem of the batch (Ahat[i], Bhat[i]
+ * for problem i, same layout and ownership), enqueued in one call. */
+hom_status hom_batch_update_coefficients(hom_batch* b, const void* const* Ahat, const void* const* Bhat);
+
 /* Bounds of every problem (as hom_bounds): primal, dual: host arrays of
  * n * d device pointers (problem-major, unit loads e_1..e_d), either may be
  * NULL; out: host array of n results. */

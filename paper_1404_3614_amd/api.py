@@ -378,9 +378,33 @@ class Batch:
                 "hom_batch_profile_passes")
         return dict(first=ms[0], mid_inv=ms[1], apply=ms[2], mid_fwd=ms[3], last=ms[4])
 
+    def update_coefficients(self, coefs):
+        """New coefficients [(Ahat, Bhat)] for every problem of the batch (hom_batch_update_coefficients)."""
+        n = len(self.problems)
+        assert len(coefs) == n
+        A = (C.c_void_p * n)(*[c[0].data_ptr() for c in coefs])
+        B = (C.c_void_p * n)(*[c[1].data_ptr() for c in coefs])
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_batch_update_coefficients(self.h, A, B), "hom_batch_update_coefficients")
+        for p, c in zip(self.problems, coefs):
+            p._coef_refs = (c[0], c[1])   # the setup reads them asynchronously
+
+    def _fields(self, dual, nl):
+        """Output fields of solve_bounds, allocated once per (dual, loads) and reused."""
+        key = (bool(dual), nl)
+        cache = self.__dict__.setdefault("_field_cache", {})
+        if key not in cache:
+            cache[key] = [[p.new_field(dual) for _ in range(nl)] for p in self.problems]
+        return cache[key]
+
     def solve_bounds(self, tol=1e-6, maxit=10000, allow_not_converged=False):
-        xp, ip = self.solve(False, tol=tol, maxit=maxit, allow_not_converged=allow_not_converged)
-        xd, idl = self.solve(True, tol=tol, maxit=maxit, allow_not_converged=allow_not_converged)
+        """Primal and dual solves of the unit loads and the bounds of every problem.  The
+        fields live in buffers owned by the batch and are overwritten by the next call."""
+        d = self.d
+        xp, ip = self.solve(False, tol=tol, maxit=maxit, out=self._fields(False, d),
+                            allow_not_converged=allow_not_converged)
+        xd, idl = self.solve(True, tol=tol, maxit=maxit, out=self._fields(True, d),
+                             allow_not_converged=allow_not_converged)
         out = self.bounds(xp, xd)
         for i, b in enumerate(out):
             b.update(info_primal=ip[i], info_dual=idl[i])

@@ -447,6 +447,9 @@ struct SolveRun {
   int chunk;
   std::vector<const double*> part_d;   // per unit, device
   std::vector<const CgScal*> sc;       // per unit, device
+  // batches: end-of-solve summaries reduced on the device (n * L entries), one copy to pinned memory
+  SolveOut* collect_dev = nullptr;
+  SolveOut* collect_host = nullptr;
   // optional per-kernel timing: events recorded around every launch of the chunk
   std::vector<hipEvent_t>* events = nullptr;
   double* tsum = nullptr;              // [5] accumulated ms per pass type
@@ -543,45 +546,85 @@ hom_status solve_units(SolveRun& R, int nload, double tol, int maxit, bool have_
     HIPCHK(hipGraphDestroy(graph));
   }
   int done_iters = 0;
-  while (true) {
-    if (use_graph)
-      HIPCHK(hipGraphLaunch(gx, st));
-    else
+  if (use_graph) {
+    // one chunk stays in flight while the host reads the active count of the one before: the
+    // count is monotone and every pass of a finished unit returns at once, so a chunk enqueued
+    // after the last unit stopped changes nothing
+    hipEvent_t ev[2];
+    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
+      (void)hipEventDestroy(ev[0]);
+      return HOM_E_DEVICE;
+    }
+    hipError_t e = hipGraphLaunch(gx, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], st);
+    for (int i = 0; e == hipSuccess; ++i) {
+      e = hipGraphLaunch(gx, st);
+      if (e == hipSuccess) e = hipEventRecord(ev[(i + 1) & 1], st);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[i & 1]);
+      if (e != hipSuccess) break;
+      done_iters += chunk;
+      if (*R.pinned_active == 0 || done_iters > maxit + chunk) break;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (e != hipSuccess) return HOM_E_DEVICE;
+  } else {
+    while (true) {
       HIPCHK(enqueue_chunk());
-    HIPCHK(hipStreamSynchronize(st));
-    if (timing) {
-      for (int j = 0; j < chunk; ++j) {
-        hipEvent_t* ev = R.events->data() + (size_t)j * 2 * npass;
-        for (int p = 0; p < npass; ++p) {
-          float ms = 0.f;
-          HIPCHK(hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]));
-          R.tsum[types[p]] += ms;
-          R.tcnt[types[p]] += 1;
+      HIPCHK(hipStreamSynchronize(st));
+      if (timing) {
+        for (int j = 0; j < chunk; ++j) {
+          hipEvent_t* ev = R.events->data() + (size_t)j * 2 * npass;
+          for (int p = 0; p < npass; ++p) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]));
+            R.tsum[types[p]] += ms;
+            R.tcnt[types[p]] += 1;
+          }
         }
       }
+      done_iters += chunk;
+      if (*R.pinned_active == 0) break;
+      if (done_iters > maxit + chunk) break;
     }
-    done_iters += chunk;
-    if (*R.pinned_active == 0) break;
-    if (done_iters > maxit + chunk) break;
   }
   // true residual b - C x of the returned iterates, in the precision mode of the solve
   HIPCHK(enqueue_passes(R.fp32, g, R.units, FIRST_FIELD, LAST_RESID, 0, nullptr, st, R.n));
-  // partial sums of the residual pass: [load][nbL] per unit
+  // partial sums of the residual pass ([load][nbL] per unit) and the CG scalars
   const size_t nbl = (size_t)g.nbL;
-  std::vector<double> part((size_t)R.n * nload * nbl);
+  std::vector<double> rres((size_t)R.n * nload);
   std::vector<CgScal> sc((size_t)R.n * nload);
-  for (int u = 0; u < R.n; ++u) {
-    HIPCHK(hipMemcpyAsync(part.data() + (size_t)u * nload * nbl, R.part_d[u], (size_t)nload * nbl * sizeof(double),
+  if (R.collect_dev) {
+    HIPCHK(launch_collect_solve(R.units, R.n, nload, g.nbL, R.collect_dev, st));
+    HIPCHK(hipMemcpyAsync(R.collect_host, R.collect_dev, (size_t)R.n * nload * sizeof(SolveOut),
                           hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(sc.data() + (size_t)u * nload, R.sc[u], nload * sizeof(CgScal), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t ul = 0; ul < (size_t)R.n * nload; ++ul) {
+      rres[ul] = R.collect_host[ul].rres;
+      sc[ul] = R.collect_host[ul].sc;
+    }
+  } else {
+    std::vector<double> part((size_t)R.n * nload * nbl);
+    for (int u = 0; u < R.n; ++u) {
+      HIPCHK(hipMemcpyAsync(part.data() + (size_t)u * nload * nbl, R.part_d[u], (size_t)nload * nbl * sizeof(double),
+                            hipMemcpyDeviceToHost, st));
+      HIPCHK(hipMemcpyAsync(sc.data() + (size_t)u * nload, R.sc[u], nload * sizeof(CgScal), hipMemcpyDeviceToHost,
+                            st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    for (size_t ul = 0; ul < (size_t)R.n * nload; ++ul) {
+      double s = 0.0;
+      for (size_t q = 0; q < nbl; ++q) s += part[ul * nbl + q];
+      rres[ul] = s;
+    }
   }
-  HIPCHK(hipStreamSynchronize(st));
   hom_status worst = HOM_OK;
   for (int u = 0; u < R.n; ++u)
     for (int l = 0; l < nload; ++l) {
       const size_t ul = (size_t)u * nload + l;
-      double s = 0.0;
-      for (size_t q = 0; q < nbl; ++q) s += part[ul * nbl + q];
+      const double s = rres[ul];
       hom_info& in = info[ul];
       in.iters = sc[ul].iters;
       in.rel_res_recur = std::sqrt(std::max(sc[ul].gamma_last, 0.0)) / sc[ul].normE;
@@ -1216,6 +1259,10 @@ struct hom_batch {
   int timing = 0;
   Tuning tune[2][kMaxLoads + 1];
   bool tuned[2][kMaxLoads + 1] = {};
+  SolveOut* collect_dev = nullptr;     // [n][kMaxLoads] end-of-solve summaries (workspace)
+  double* bcollect_dev = nullptr;      // [2][n][9] bounds quadrature sums (workspace)
+  SolveOut* collect_host = nullptr;    // pinned mirrors
+  double* bcollect_host = nullptr;
   double tsum[5] = {0, 0, 0, 0, 0};
   long long tcnt[5] = {0, 0, 0, 0, 0};
 };
@@ -1238,6 +1285,12 @@ static size_t batch_layout(int n, char* base, hom_batch* b) {
       b->iter_base[k] = (int*)ib;
       b->active[k] = (int*)ac;
     }
+  }
+  char* cs = take((size_t)n * kMaxLoads * sizeof(SolveOut));
+  char* cb = take((size_t)n * 2 * 9 * sizeof(double));
+  if (b) {
+    b->collect_dev = (SolveOut*)cs;
+    b->bcollect_dev = (double*)cb;
   }
   return off;
 }
@@ -1270,6 +1323,14 @@ hom_status hom_batch_create(hom_problem* const* pbs, int32_t n, void* ws, size_t
   for (int k = 0; k < 2; ++k) {
     b->host_units[k].resize(n);
     b->host_bunits[k].resize(n);
+  }
+  if (hipHostMalloc((void**)&b->collect_host, (size_t)n * kMaxLoads * sizeof(SolveOut), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&b->bcollect_host, (size_t)n * 2 * 9 * sizeof(double), hipHostMallocDefault) !=
+          hipSuccess) {
+    if (b->collect_host) (void)hipHostFree(b->collect_host);
+    delete b;
+    return HOM_E_DEVICE;
   }
   *out = b;
   return HOM_OK;
@@ -1329,7 +1390,20 @@ hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const doub
     R.part_d.push_back(b->pbs[i]->slot[k].part_d);
     R.sc.push_back(b->pbs[i]->slot[k].sc);
   }
+  R.collect_dev = b->collect_dev;
+  R.collect_host = b->collect_host;
   return solve_units(R, nload, tol, maxit, have_x0, info);
+}
+
+hom_status hom_batch_update_coefficients(hom_batch* b, const void* const* Ahat, const void* const* Bhat) {
+  if (!b || !Ahat || !Bhat) return HOM_E_INVALID;
+  for (int i = 0; i < b->n; ++i)
+    if (!Ahat[i] || !Bhat[i]) return HOM_E_INVALID;
+  for (int i = 0; i < b->n; ++i) {
+    hom_status s = setup_coefficients(b->pbs[i], Ahat[i], Bhat[i]);
+    if (s != HOM_OK) return s;
+  }
+  return HOM_OK;
 }
 
 hom_status hom_batch_bounds(hom_batch* b, const double* const* primal, const double* const* dual, hom_result* out) {
@@ -1346,7 +1420,6 @@ hom_status hom_batch_bounds(hom_batch* b, const double* const* primal, const dou
   hipStream_t st = b->stream;
   const int P = packs(d, d);
   bool have[2] = {primal != nullptr, dual != nullptr};
-  std::vector<double> part[2];
   Geo g[2];
   for (int k = 0; k < 2; ++k) {
     if (!have[k]) continue;
@@ -1371,25 +1444,19 @@ hom_status hom_batch_bounds(hom_batch* b, const double* const* primal, const dou
     HIPCHK(launch_first<double>(g[k], b->bunits[k], n, FIRST_BOUNDS, 0, nullptr, st));
     if (d == 3) HIPCHK(launch_mid<double>(g[k], b->bunits[k], n, 1, st));
     HIPCHK(launch_apply<double>(g[k], b->bunits[k], n, APPLY_QUAD, st));
-    const size_t per = (size_t)g[k].nbA * 9;
-    part[k].resize(per * n);
-    for (int i = 0; i < n; ++i)
-      HIPCHK(hipMemcpyAsync(part[k].data() + per * i, b->pbs[i]->bpart_q[k], per * sizeof(double),
-                            hipMemcpyDeviceToHost, st));
+    HIPCHK(launch_collect_bounds(b->bunits[k], n, g[k].nbA, b->bcollect_dev + (size_t)k * n * 9, st));
   }
+  HIPCHK(hipMemcpyAsync(b->bcollect_host, b->bcollect_dev, (size_t)2 * n * 9 * sizeof(double), hipMemcpyDeviceToHost,
+                        st));
   HIPCHK(hipStreamSynchronize(st));
   for (int i = 0; i < n; ++i) {
     double Ebar[2][9];
     for (int k = 0; k < 2; ++k) {
       for (int j = 0; j < 9; ++j) Ebar[k][j] = NAN;
       if (!have[k]) continue;
-      const size_t per = (size_t)g[k].nbA * 9;
+      const double* sums = b->bcollect_host + ((size_t)k * n + i) * 9;
       for (int a = 0; a < d; ++a)
-        for (int c = 0; c < d; ++c) {
-          double s = 0.0;
-          for (int q = 0; q < g[k].nbA; ++q) s += part[k][per * i + (size_t)q * 9 + a * kMaxLoads + c];
-          Ebar[k][a * d + c] = s * g[k].invM;
-        }
+        for (int c = 0; c < d; ++c) Ebar[k][a * d + c] = sums[a * kMaxLoads + c] * g[k].invM;
     }
     fill_result(d, Ebar, have, &out[i]);
   }
@@ -1527,6 +1594,8 @@ void hom_batch_destroy(hom_batch* b) {
       if (b->tgraph[k][l]) (void)hipGraphExecDestroy(b->tgraph[k][l]);
       for (auto ev : b->tevents[k][l]) (void)hipEventDestroy(ev);
     }
+  if (b->collect_host) (void)hipHostFree(b->collect_host);
+  if (b->bcollect_host) (void)hipHostFree(b->bcollect_host);
   delete b;
 }
 

@@ -41,6 +41,12 @@ struct CgScal {
   int32_t pad_;
 };
 
+// End-of-solve summary of one (unit, load): sum of the residual partials and the CG scalars.
+struct SolveOut {
+  double rres;
+  CgScal sc;
+};
+
 // One coefficient field with L loads: device-resident pointers.
 struct UnitDev {
   const void* coef;                  // R-typed [nc][M0*M1*M2] on the doubled grid
@@ -129,6 +135,10 @@ hipError_t launch_symmetrize(const Geo& g, const Cx<double>* src, Cx<double>* ds
 hipError_t launch_advance(const Geo& g, const UnitDev* units, int nunits, int* iter_base, int step,
                           int* active_out, hipStream_t st);
 hipError_t launch_twiddles(Cx<double>* t64, Cx<float>* t32, int M, hipStream_t st);
+// Per (unit, load): residual partials summed in index order, and the CG scalars.
+hipError_t launch_collect_solve(const UnitDev* units, int n, int L, int nbL, SolveOut* out, hipStream_t st);
+// Per (unit, entry < 9): bounds quadrature partials summed in index order.
+hipError_t launch_collect_bounds(const UnitDev* units, int n, int nbA, double* out, hipStream_t st);
 hipError_t launch_net_input(const double* coef64, int nc, int d, long Mt, const Cx<double>* ahat0, long S, float* out,
                             int weight_only, hipStream_t st);
 hipError_t launch_coef_real(const Cx<double>* full, double* c64, float* c32, long n, hipStream_t st);

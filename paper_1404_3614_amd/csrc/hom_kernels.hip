@@ -979,6 +979,37 @@ hipError_t launch_advance(const Geo& g, const UnitDev* units, int nunits, int* i
   return hipGetLastError();
 }
 
+__global__ void k_collect_solve(const UnitDev* __restrict__ units, int n, int L, int nbL, SolveOut* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * L) return;
+  const int u = t / L, l = t - u * L;
+  const UnitDev& U = units[u];
+  double s = 0.0;
+  for (int q = 0; q < nbL; ++q) s += U.part_d[(size_t)l * nbL + q];
+  out[t].rres = s;
+  out[t].sc = U.sc[l];
+}
+
+__global__ void k_collect_bounds(const UnitDev* __restrict__ units, int n, int nbA, double* __restrict__ out) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n * 9) return;
+  const int u = t / 9, j = t - u * 9;
+  const double* p = units[u].part_q;
+  double s = 0.0;
+  for (int q = 0; q < nbA; ++q) s += p[(size_t)q * 9 + j];
+  out[t] = s;
+}
+
+hipError_t launch_collect_solve(const UnitDev* units, int n, int L, int nbL, SolveOut* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_collect_solve, dim3((n * L + 63) / 64), dim3(64), 0, st, units, n, L, nbL, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_collect_bounds(const UnitDev* units, int n, int nbA, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_collect_bounds, dim3((n * 9 + 63) / 64), dim3(64), 0, st, units, n, nbA, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_twiddles(Cx<double>* t64, Cx<float>* t32, int M, hipStream_t st) {
   hipLaunchKernelGGL(k_twiddles, dim3(grid_for(M)), dim3(kBlock), 0, st, t64, t32, M);
   return hipGetLastError();
