@@ -788,6 +788,18 @@ hom_status setup_coefficients(hom_problem* pb, const void* Ahat, const void* Bha
   hipStream_t st = pb->stream;
   Geo g = make_geo(pb, 0, 1, false);
   const int nc = z.nc;
+  {
+    const Cx<double>* A = reinterpret_cast<const Cx<double>*>(Ahat);
+    const Cx<double>* B = reinterpret_cast<const Cx<double>*>(Bhat);
+    hipError_t e = hipSuccess;
+    if (fast_coef_setup(z.d, z.M, nc, A, B, pb->scratch, pb->coef64[0], pb->coef32[0], pb->coef64[1], pb->coef32[1],
+                        pb->tw64[0], st, &e)) {
+      HIPCHK(e);
+      HIPCHK(launch_extract_half(g, A, pb->ahat_half[0], nc, st));
+      HIPCHK(launch_extract_half(g, B, pb->ahat_half[1], nc, st));
+      return HOM_OK;
+    }
+  }
   for (int k = 0; k < 2; ++k) {
     const void* src = k == 0 ? Ahat : Bhat;
     HIPCHK(hipMemcpyAsync(pb->scratch, src, nc * z.Mt * sizeof(Cx<double>), hipMemcpyDeviceToDevice, st));

@@ -270,6 +270,162 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply_fast(Geo g, const Unit
   }
 }
 
+// ============================================================== coefficient setup (2D, FP64)
+// A and A^-1 on the doubled grid in one complex transform: both Fourier
+// series are Hermitian, so F_M^-1 (A_hat + i s B_hat) = A_M + i s B_M with real
+// A_M, B_M.  s is the power of two nearest to <A>/<A^-1> (component 0 of the
+// zero frequency), so both parts carry similar magnitudes through the
+// rounding, and dividing by s is exact.
+__device__ __forceinline__ double coef_pair_scale(const Cx<double>* A, const Cx<double>* Bh) {
+  const double a = fabs(A[0].x), b = fabs(Bh[0].x);
+  if (!(a > 0.0) || !(b > 0.0)) return 1.0;
+  return ldexp(1.0, (int)rint(log2(a / b)));
+}
+
+// Inverse transform along axis 0 (columns of the [M][M] plane): TP columns
+// per block, T threads per column; grid (column blocks, component).
+template <int M, int TP>
+__global__ __launch_bounds__(TP * Cfg<M>::T) void k_coef_cols(const Cx<double>* __restrict__ Ah,
+                                                              const Cx<double>* __restrict__ Bh,
+                                                              Cx<double>* __restrict__ out,
+                                                              const Cx<double>* __restrict__ twg) {
+  constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<double>* tw = reinterpret_cast<Cx<double>*>(smem);  // [M]
+  Cx<double>* ex = tw + M;                               // [M][TP]
+  const int tid = threadIdx.x, pt = tid % TP, q = tid / TP;
+  const int p = blockIdx.x * TP + pt;
+  const bool ok = p < M;
+  const size_t base = (size_t)blockIdx.y * M * M;
+  const double sc = coef_pair_scale(Ah, Bh);
+  for (int i = tid; i < M; i += blockDim.x) tw[i] = twg[i];
+  Cx<double> v[T];
+#pragma unroll
+  for (int n1 = 0; n1 < A; ++n1) {
+    v[n1] = rf::mk<double>(0.0, 0.0);
+    if (q < B && ok) {
+      const size_t i = base + (size_t)(B * n1 + q) * M + p;
+      const Cx<double> a = Ah[i], b = Bh[i];
+      v[n1] = rf::mk<double>(a.x - sc * b.y, a.y + sc * b.x);
+    }
+  }
+  __syncthreads();
+  if (q < B) {
+    rf::Dft<double, A, 1>::run(v);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      Cx<double> w = tw[q * k1];
+      w.y = -w.y;
+      ex[(q * A + k1) * TP + pt] = rf::mul(v[k1], w);
+    }
+  }
+  __syncthreads();
+  if (q < A) {
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) v[n2] = ex[(n2 * A + q) * TP + pt];
+    rf::Dft<double, B, 1>::run(v);
+    if (ok) {
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) out[base + (size_t)(q + A * k2) * M + p] = v[k2];
+    }
+  }
+}
+
+// Inverse transform along axis 2 (rows), G rows per block, T threads per row,
+// then the real and imaginary parts split into A_M and B_M (FP64 and FP32).
+template <int M, int G>
+__global__ __launch_bounds__(G * Cfg<M>::T) void k_coef_rows(const Cx<double>* __restrict__ in,
+                                                             const Cx<double>* __restrict__ Ah,
+                                                             const Cx<double>* __restrict__ Bh,
+                                                             double* __restrict__ a64, float* __restrict__ a32,
+                                                             double* __restrict__ b64, float* __restrict__ b32,
+                                                             const Cx<double>* __restrict__ twg) {
+  constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<double>* tw = reinterpret_cast<Cx<double>*>(smem);  // [M]
+  Cx<double>* ex = tw + M;                               // [G][M]
+  const int tid = threadIdx.x, gr = tid / T, q = tid - gr * T;
+  const int row = blockIdx.x * G + gr;
+  const bool ok = row < M;
+  const size_t base = (size_t)blockIdx.y * M * M + (size_t)(ok ? row : 0) * M;
+  const double inv = 1.0 / coef_pair_scale(Ah, Bh);
+  for (int i = tid; i < M; i += blockDim.x) tw[i] = twg[i];
+  Cx<double>* e = ex + (size_t)gr * M;
+  Cx<double> v[T];
+#pragma unroll
+  for (int n1 = 0; n1 < A; ++n1) v[n1] = (q < B && ok) ? in[base + B * n1 + q] : rf::mk<double>(0.0, 0.0);
+  __syncthreads();
+  if (q < B && ok) {
+    rf::Dft<double, A, 1>::run(v);
+#pragma unroll
+    for (int k1 = 0; k1 < A; ++k1) {
+      Cx<double> w = tw[q * k1];
+      w.y = -w.y;
+      e[q * A + k1] = rf::mul(v[k1], w);
+    }
+  }
+  __syncthreads();
+  if (q < A && ok) {
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) v[n2] = e[n2 * A + q];
+    rf::Dft<double, B, 1>::run(v);
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) {
+      const size_t i = base + q + A * k2;
+      const double av = v[k2].x, bv = v[k2].y * inv;
+      a64[i] = av;
+      b64[i] = bv;
+      if (a32) a32[i] = (float)av;
+      if (b32) b32[i] = (float)bv;
+    }
+  }
+}
+
+template <int M>
+struct CoefTiles;
+template <>
+struct CoefTiles<625> { static constexpr int TP = 4, G = 4; };
+template <>
+struct CoefTiles<125> { static constexpr int TP = 8, G = 8; };
+template <>
+struct CoefTiles<81> { static constexpr int TP = 16, G = 16; };
+template <>
+struct CoefTiles<25> { static constexpr int TP = 32, G = 32; };
+
+template <int M>
+static hipError_t run_coef_setup(int nc, const Cx<double>* Ah, const Cx<double>* Bh, Cx<double>* scratch, double* a64,
+                                 float* a32, double* b64, float* b32, const Cx<double>* tw, hipStream_t st) {
+  constexpr int T = Cfg<M>::T, TP = CoefTiles<M>::TP, G = CoefTiles<M>::G;
+  const size_t lds1 = (size_t)M * sizeof(Cx<double>) * (1 + TP);
+  const size_t lds2 = (size_t)M * sizeof(Cx<double>) * (1 + G);
+  auto k1 = k_coef_cols<M, TP>;
+  auto k2 = k_coef_rows<M, G>;
+  hipError_t e = hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k1, dim3((M + TP - 1) / TP, nc), dim3(TP * T), lds1, st, Ah, Bh, scratch, tw);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k2, dim3((M + G - 1) / G, nc), dim3(G * T), lds2, st, scratch, Ah, Bh, a64, a32, b64, b32, tw);
+  return hipGetLastError();
+}
+
+// 2D problems with M0 = M2 in {25, 81, 125, 625}: both coefficients on the
+// doubled grid in two launches; false when no specialisation exists.
+bool fast_coef_setup(int d, const int* Mz, int nc, const Cx<double>* Ah, const Cx<double>* Bh, Cx<double>* scratch,
+                     double* a64, float* a32, double* b64, float* b32, const Cx<double>* tw, hipStream_t st,
+                     hipError_t* err) {
+  if (std::getenv("HOM_NO_FAST")) return false;
+  if (d != 2 || Mz[0] != Mz[2]) return false;
+  switch (Mz[0]) {
+    case 625: *err = run_coef_setup<625>(nc, Ah, Bh, scratch, a64, a32, b64, b32, tw, st); return true;
+    case 125: *err = run_coef_setup<125>(nc, Ah, Bh, scratch, a64, a32, b64, b32, tw, st); return true;
+    case 81: *err = run_coef_setup<81>(nc, Ah, Bh, scratch, a64, a32, b64, b32, tw, st); return true;
+    case 25: *err = run_coef_setup<25>(nc, Ah, Bh, scratch, a64, a32, b64, b32, tw, st); return true;
+    default: return false;
+  }
+}
+
 // ============================================================== row passes
 // G row pairs per block; line A = (h0, k1, .), line B = (-h0, -k1, .).  The
 // packed fields of both lines are staged in LDS in natural position order

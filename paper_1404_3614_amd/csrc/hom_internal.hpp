@@ -157,6 +157,11 @@ bool fast_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, i
 int fast_row_pairs(int M, int D, int L, int requested);
 bool fast_apply_supported(int M, int D, int P, int NC);
 bool fast_apply_shape_ok(int M, int D, int tp, int hx);
+// Both coefficients on the doubled grid (FP64 and, when given, FP32 copies) for
+// 2D problems with equal doubled-grid lengths 25, 81, 125 or 625.
+bool fast_coef_setup(int d, const int* Mz, int nc, const Cx<double>* Ah, const Cx<double>* Bh, Cx<double>* scratch,
+                     double* a64, float* a32, double* b64, float* b32, const Cx<double>* tw, hipStream_t st,
+                     hipError_t* err);
 
 // Tile shapes of the specialised passes: row pairs and threads per block of the
 // row passes, points per block of the column pass (0 = default).
