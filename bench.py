@@ -10,7 +10,17 @@ right-hand sides, 2 primal + 2 dual solves and the FP64 bound evaluation.
 Fourier data of the pixel images are computed on the device once, before the
 timed region (inputs resident in HBM).
 
-Prints one JSON line (see the design doc for the roofline and traffic method).
+Other workloads (--workload): c4, a mixed batch of 512 2D cells of uneven N
+(13, 41, 63, 313) and 64 3D cells (N = 41), random inclusions with contrast
+log-uniform in [2, 1e3], solved class by class in lockstep batches; c5, the
+learned initial guess (U-Net trained on solver fields of 2D N = 63 cells),
+plain versus learned + batched on held-out cells of contrast 1e2 - 1e3.
+
+Prints one JSON line.  The roofline object divides the algorithmic bytes per
+launch of the dominant kernel by its duration measured with HIP events; its
+traffic field is the HBM traffic per launch from the hardware counters of a
+committed profile, reported only while the kernel sources are the ones that
+profile measured.
 """
 from __future__ import annotations
 
@@ -38,7 +48,41 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-cells", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true", help="skip the one-cell-at-a-time comparison leg")
+    ap.add_argument("--tiles", default=None,
+                    help="pin the FP32 tile shape: row_pairs,row_threads,apply_points,apply_half_exchange")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"])
+    ap.add_argument("--c5-train", type=int, default=2048, help="c5: training cells")
+    ap.add_argument("--c5-steps", type=int, default=1500, help="c5: Adam steps")
+    ap.add_argument("--c5-test", type=int, default=256, help="c5: held-out cells")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c2_hbm_traffic.md")
+KERNEL_SOURCES = ["paper_1404_3614_amd/csrc/hom_fast.hip", "paper_1404_3614_amd/csrc/hom_regfft.hpp",
+                  "paper_1404_3614_amd/csrc/hom_device.hpp", "paper_1404_3614_amd/csrc/hom_internal.hpp"]
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(tiles):
+    """HBM bytes per launch of the three CG passes from the committed counter
+    profile, or None when the kernel sources or the tile shape differ from
+    the ones it measured."""
+    try:
+        txt = open(TRAFFIC_FILE).read()
+        blob = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+    except (OSError, IndexError, ValueError):
+        return None
+    if blob.get("source_sha256") != kernel_source_digest() or blob.get("tiles") != tiles:
+        return None
+    return blob.get("bytes_per_launch")
 
 
 def c2_cell(i):
@@ -115,6 +159,10 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload == "c4":
+        return run_c4(args)
+    if args.workload == "c5":
+        return run_c5(args)
     N = (313, 313)
     B = args.cells
     # inputs resident in HBM: Fourier data of A and A^-1 for every cell
@@ -125,7 +173,10 @@ def main():
     probs = [H.Problem(2, N, (1.0, 1.0), Ah, Bh, precision=args.precision, ncoef=nc, max_loads=2, stream=stream)
              for (Ah, Bh, nc) in coefs]
     batch = H.Batch(probs)
-    state = {"batch": batch, "probs": probs}
+    if args.tiles:
+        r, t, a, x = (int(v) for v in args.tiles.split(","))
+        for dual in (False, True):
+            batch.set_tiles(dual, 2, row_pairs=r, row_threads=t, apply_points=a, apply_half_exchange=x)
 
     pairs = [(Ah, Bh) for (Ah, Bh, nc) in coefs]
 
@@ -193,8 +244,15 @@ def main():
             b = unit_launches * pbytes[k] / launches[k]
             per_pass[k] = dict(ms_per_launch=round(avg_ms[k], 5), bytes_per_launch=int(b),
                                gbs=round(b / (avg_ms[k] * 1e-3) / 1e9, 1), launches=launches[k])
+    tuning = dict(primal=batch.tuning(False, 2), dual=batch.tuning(True, 2))
+    shape = [tuning["primal"][k] for k in ("row_pairs", "row_threads", "apply_points", "apply_half_exchange")]
+    same_shape = all(tuning["dual"][k] == tuning["primal"][k]
+                     for k in ("row_pairs", "row_threads", "apply_points", "apply_half_exchange"))
+    traffic_all = measured_traffic(shape) if same_shape else None
+    traffic = None if traffic_all is None else traffic_all.get(dom)
     roofline = dict(bound="hbm", kernel=names[dom], achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None, bytes_per_launch=int(nbytes),
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, traffic_unit="bytes/launch",
+                    traffic_per_pass=traffic_all, bytes_per_launch=int(nbytes),
                     ms_per_launch=round(ms, 5), per_pass=per_pass,
                     bytes_model="pass_bytes() in bench.py; units per launch = active cells of the batch",
                     timed_region="second timed pass of the same steps, kernels launched directly by "
@@ -210,10 +268,151 @@ def main():
                             cells_per_step=B, tol=args.tol, precision=args.precision, cg_iters=iters,
                             batched="all cells of a step in lockstep (one launch per pass covers every cell)",
                             plain_bound_pairs_per_s=None if plain_value is None else round(plain_value, 3),
-                            tile_tuning=dict(primal=batch.tuning(False, 2), dual=batch.tuning(True, 2))),
+                            tile_tuning=tuning),
                 roofline=roofline)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_cells, args.tol)
+    print(json.dumps(line), flush=True)
+
+
+def _line(args, value, dt, steps, workload, extra_cfg, dtype=None):
+    return dict(metric=METRIC, value=round(value, 3), unit="bound pairs/s", n_gpus=1, steps=steps,
+                warmup=args.warmup, ms_per_step=round(1e3 * dt / max(steps, 1), 3), higher_is_better=True,
+                scaling="weak", vs_baseline=None,
+                dtype=dtype or ("f32 FFT/apply + f64 CG/bounds" if args.precision == "mixed" else "f64"),
+                data="synthetic", config=dict(workload=workload, tol=args.tol, precision=args.precision,
+                                              **extra_cfg),
+                roofline=None)
+
+
+def run_c4(args):
+    """Mixed batch: 512 2D cells, N uniform in {13, 41, 63, 313}, and 64 3D cells at N = 41."""
+    import numpy as np
+    import torch
+    import homgen
+    from paper_1404_3614_amd.mixed import MixedSolver
+    specs = homgen.batch_specs()
+    ms = MixedSolver(precision=args.precision)
+    groups = ms.prepare([(N, c) for N, c, _ in specs])   # Fourier data on the device, before the timed region
+    for _ in range(args.warmup):
+        ms.solve(groups, len(specs), tol=args.tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    timings = {}
+    for _ in range(args.steps):
+        res = ms.solve(groups, len(specs), tol=args.tol, timings=timings)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    classes = []
+    for key, items in groups.items():
+        its = np.array([[i["iters"] for i in res[j]["info_primal"] + res[j]["info_dual"]] for j, _, _ in items])
+        classes.append(dict(d=key[0], N=key[1][0], cells=len(items), mean_iters=round(float(its.mean()), 1),
+                            max_iters=int(its.max()), wall_ms_last_step=round(1e3 * timings[key], 2)))
+    line = _line(args, len(specs) * args.steps / dt, dt, args.steps,
+                 "C4: 512 2D cells (random squares, N in {13,41,63,313}) + 64 3D cells (random spheres, N=41), "
+                 "contrast log-uniform in [2,1e3], d loads, primal+dual; one lockstep batch per size class, "
+                 "classes concurrent on their own streams",
+                 dict(cells_per_step=len(specs), classes=classes))
+    print(json.dumps(line), flush=True)
+
+
+def run_c5(args):
+    """Learned initial guess: a 4-level, 32-channel U-Net trained on solver fields
+    of 2D N = 63 cells; plain versus learned + batched CG on held-out cells of
+    contrast 1e2 - 1e3, inference and projection inside the timed region."""
+    import math
+    import numpy as np
+    import torch
+    import homgen
+    import paper_1404_3614_amd as H
+    from paper_1404_3614_amd import learned as LL
+    N, M = (63, 63), (125, 125)
+    logrho = (math.log10(2.0), 3.0)
+    train_cells = [homgen.random_squares_cell(5_000_000 + i, logrho=logrho)[0] for i in range(args.c5_train)]
+    t0 = time.perf_counter()
+    X, Y, W, it_train = LL.solver_samples(train_cells, N, tol=args.tol, chunk=256)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    print(f"[c5] {len(train_cells)} training fields in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    net = LL.UNet(2, M, levels=4, base=32, batch=16)
+    net.init_params(seed=1)
+    t0 = time.perf_counter()
+    hist = LL.train(net, X, Y, steps=args.c5_steps, lr=2e-3, lr_final=1e-4, seed=3,
+                    log_every=max(1, args.c5_steps // 5))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del X, Y, W
+    test = [homgen.random_squares_cell(6_000_000 + i, logrho=(2.0, 3.0))[0] for i in range(args.c5_test)]
+    st = torch.cuda.Stream()
+    probs = [H.problem_from_cell(c, N, precision=args.precision, stream=st) for c in test]
+    batch = H.Batch(probs)
+    zero = batch.bounds([[p.new_field(False) for _ in range(2)] for p in probs],
+                        [[p.new_field(True) for _ in range(2)] for p in probs])
+    for _ in range(args.warmup):
+        batch.solve_bounds(tol=args.tol)
+    torch.cuda.synchronize()
+    # plain batched CG from x0 = 0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        plain = batch.solve_bounds(tol=args.tol)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / args.steps
+    # learned + batched: inference, projection onto E_N / J_N, CG from the projected fields, bounds
+    outp = [[p.new_field(False) for _ in range(2)] for p in probs]
+    outd = [[p.new_field(True) for _ in range(2)] for p in probs]
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x0p, x0d = LL.predict_x0(net, probs)
+        fp, ip = batch.solve(False, x0=x0p, tol=args.tol, out=outp)
+        fd, idl = batch.solve(True, x0=x0d, tol=args.tol, out=outd)
+        learned = batch.bounds(fp, fd)
+    torch.cuda.synchronize()
+    t_learned = (time.perf_counter() - t0) / args.steps
+    t0 = time.perf_counter()
+    x0p, x0d = LL.predict_x0(net, probs)
+    torch.cuda.synchronize()
+    t_infer = time.perf_counter() - t0
+    start = batch.bounds(x0p, x0d)
+    # plain CG one cell at a time (no batching) on a subset
+    nsingle = min(16, len(test))
+    single = H.problem_from_cell(test[0], N, precision=args.precision)
+    single.solve_bounds(tol=args.tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in test[:nsingle]:
+        Ah, Bh, _ = H.coef_from_cell(c, N)
+        single.update_coefficients(Ah, Bh)
+        single.solve_bounds(tol=args.tol)
+    torch.cuda.synchronize()
+    t_single = (time.perf_counter() - t0) / nsingle
+    itp = np.array([[i["iters"] for i in b["info_primal"] + b["info_dual"]] for b in plain])
+    itl = np.array([[r["iters"] for r in a + b] for a, b in zip(ip, idl)])
+    err = max(float(np.abs(b1["A_up"] - b0["A_up"]).max() / np.linalg.norm(b0["A_up"], 2)) for b0, b1 in
+              zip(plain, learned))
+    ep = float(np.mean([(np.diag(s["A_up"]) - np.diag(r["A_up"])) / (np.diag(z["A_up"]) - np.diag(r["A_up"]))
+                        for s, r, z in zip(start, plain, zero)]))
+    ed = float(np.mean([(np.diag(s["B_up"]) - np.diag(r["B_up"])) / (np.diag(z["B_up"]) - np.diag(r["B_up"]))
+                        for s, r, z in zip(start, plain, zero)]))
+    n = len(test)
+    line = _line(args, n / t_learned, t_learned * args.steps, args.steps,
+                 "C5: learned + batched CG, 2D N=63 (doubled grid 125^2) random squares, contrast 1e2-1e3, "
+                 "U-Net 4 levels x 32 base channels (FP32, hand-written kernels) trained on solver fields",
+                 dict(cells_per_step=n,
+                      learned_batched_bound_pairs_per_s=round(n / t_learned, 2),
+                      plain_batched_bound_pairs_per_s=round(n / t_plain, 2),
+                      plain_unbatched_bound_pairs_per_s=round(1.0 / t_single, 2),
+                      inference_and_projection_ms=round(1e3 * t_infer, 2),
+                      iterations_plain_mean=round(float(itp.mean()), 2),
+                      iterations_plain_p95=float(np.percentile(itp, 95)),
+                      iterations_learned_mean=round(float(itl.mean()), 2),
+                      iterations_learned_p95=float(np.percentile(itl, 95)),
+                      start_energy_error_vs_zero_start=dict(primal=round(ep, 4), dual=round(ed, 4)),
+                      max_rel_bound_diff_learned_vs_plain=err,
+                      training=dict(cells=len(train_cells), field_generation_s=round(t_gen, 2),
+                                    adam_steps=args.c5_steps, batch=16, train_s=round(t_train, 2),
+                                    loss_first=round(float(np.mean(hist[:10])), 5),
+                                    loss_last=round(float(np.mean(hist[-50:])), 5))),
+                 dtype="f32 FFT/apply + f64 CG/bounds; f32 network")
     print(json.dumps(line), flush=True)
 
 

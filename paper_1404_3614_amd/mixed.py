@@ -4,11 +4,14 @@ all cells of the class, iterations replayed from a captured graph).
 
 A class keeps its problem handles, workspaces and batch between calls, so a
 stream of new cells of the same classes re-uses them through
-hom_update_coefficients.
+hom_batch_update_coefficients.  Classes run on streams of their own, driven
+by one host thread each, so small classes overlap the large ones on the GPU.
 """
 from __future__ import annotations
 
+import time
 from collections import OrderedDict
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import torch
@@ -17,22 +20,25 @@ from . import api
 
 
 class MixedSolver:
-    def __init__(self, precision="mixed", stream=None):
+    def __init__(self, precision="mixed", concurrent=True):
         self.precision = precision
-        self.stream = stream if stream is not None else torch.cuda.Stream()
+        self.concurrent = concurrent
         self.classes = {}
 
     def _class(self, key, count, coefs):
         d, N, nc, Y = key
         cls = self.classes.get(key)
         if cls is None or len(cls["probs"]) != count:
-            probs = [api.Problem(d, N, Y, Ah, Bh, precision=self.precision, ncoef=nc, stream=self.stream)
+            stream = torch.cuda.Stream()
+            probs = [api.Problem(d, N, Y, Ah, Bh, precision=self.precision, ncoef=nc, stream=stream)
                      for (Ah, Bh) in coefs]
-            cls = dict(probs=probs, batch=api.Batch(probs))
+            cls = dict(probs=probs, batch=api.Batch(probs), stream=stream)
+            # tile shapes are chosen now, on this thread, before classes run side by side
+            for dual in (False, True):
+                cls["batch"].tuning(dual, d)
             self.classes[key] = cls
         else:
-            for p, (Ah, Bh) in zip(cls["probs"], coefs):
-                p.update_coefficients(Ah, Bh)
+            cls["batch"].update_coefficients(coefs)
         return cls
 
     def prepare(self, specs):
@@ -46,12 +52,31 @@ class MixedSolver:
             groups.setdefault(key, []).append((i, Ah, Bh))
         return groups
 
-    def solve(self, groups, n_total, tol=1e-6, maxit=20000):
-        """Bounds of every cell (list in input order) with per-cell iteration counts."""
+    def solve(self, groups, n_total, tol=1e-6, maxit=20000, timings=None):
+        """Bounds of every cell (list in input order) with per-cell iteration counts.
+        timings: optional dict filled with the wall time of every class."""
         out = [None] * n_total
-        for key, items in groups.items():
-            cls = self._class(key, len(items), [(Ah, Bh) for _, Ah, Bh in items])
-            res = cls["batch"].solve_bounds(tol=tol, maxit=maxit)
+        # problem handles and batches are created here, on the calling thread
+        work = [(key, items, self._class(key, len(items), [(Ah, Bh) for _, Ah, Bh in items]))
+                for key, items in groups.items()]
+        torch.cuda.synchronize()
+
+        def run(job):
+            key, items, cls = job
+            t0 = time.perf_counter()
+            with torch.cuda.stream(cls["stream"]):
+                res = cls["batch"].solve_bounds(tol=tol, maxit=maxit)
+            cls["stream"].synchronize()
+            return key, items, res, time.perf_counter() - t0
+
+        if self.concurrent and len(work) > 1:
+            with ThreadPoolExecutor(max_workers=min(len(work), 8)) as ex:
+                done = list(ex.map(run, work))
+        else:
+            done = [run(w) for w in work]
+        for key, items, res, dt in done:
+            if timings is not None:
+                timings[key] = dt
             for (i, _, _), r in zip(items, res):
                 r["class"] = dict(d=key[0], N=key[1])
                 out[i] = r

@@ -1,6 +1,6 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
 
-Tolerances (written here, derived in the design doc):
+Tolerances (derived from the arithmetic of each mode):
   * operator, FP64 mode: 1e-12 relative (rounding of two FFT passes of length <= 625);
   * operator, mixed mode: 2e-6 relative (FP32 FFTs: ~ eps32 * log2(M^d) * a few);
   * bounds, FP64 mode, CG to 1e-10: 1e-9 relative (the bound error is quadratic in
