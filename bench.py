@@ -25,6 +25,7 @@ profile measured.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -188,11 +189,17 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # long-lived objects (modules, handles, inputs) leave the cyclic collector's
+    # generations, so a full collection cannot stall a timed step
+    gc.collect()
+    gc.freeze()
     # timed region 1 (value): CG iterations replayed from captured HIP graphs
     t0 = time.perf_counter()
-    results = []
+    results, step_ms = [], []
     for _ in range(args.steps):
+        ts = time.perf_counter()
         results.append(step())
+        step_ms.append(round(1e3 * (time.perf_counter() - ts), 2))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     # timed region 2 (kernel durations for the roofline): the same steps, iterations launched
@@ -266,6 +273,7 @@ def main():
                 config=dict(workload="C2: 2D N=313 (doubled grid 625^2), random two-phase 125x125 pixel image, "
                                      "a in {1,100}, both loads, primal+dual, batched lockstep CG",
                             cells_per_step=B, tol=args.tol, precision=args.precision, cg_iters=iters,
+                            step_ms=step_ms,
                             batched="all cells of a step in lockstep (one launch per pass covers every cell)",
                             plain_bound_pairs_per_s=None if plain_value is None else round(plain_value, 3),
                             tile_tuning=tuning),
