@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--cpu-cells", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true", help="skip the one-cell-at-a-time comparison leg")
     ap.add_argument("--tiles", default=None,
-                    help="pin the FP32 tile shape: row_pairs,row_threads,apply_points,apply_half_exchange")
+                    help="pin the FP32 tile shape: row_pairs,row_threads,apply_points,apply_half_exchange,"
+                         "apply_all_packs")
     ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"])
     ap.add_argument("--c5-train", type=int, default=2048, help="c5: training cells")
     ap.add_argument("--c5-steps", type=int, default=1500, help="c5: Adam steps")
@@ -175,9 +176,10 @@ def main():
              for (Ah, Bh, nc) in coefs]
     batch = H.Batch(probs)
     if args.tiles:
-        r, t, a, x = (int(v) for v in args.tiles.split(","))
+        r, t, a, x, al = (int(v) for v in args.tiles.split(","))
         for dual in (False, True):
-            batch.set_tiles(dual, 2, row_pairs=r, row_threads=t, apply_points=a, apply_half_exchange=x)
+            batch.set_tiles(dual, 2, row_pairs=r, row_threads=t, apply_points=a, apply_half_exchange=x,
+                            apply_all_packs=al)
 
     pairs = [(Ah, Bh) for (Ah, Bh, nc) in coefs]
 
@@ -252,9 +254,9 @@ def main():
             per_pass[k] = dict(ms_per_launch=round(avg_ms[k], 5), bytes_per_launch=int(b),
                                gbs=round(b / (avg_ms[k] * 1e-3) / 1e9, 1), launches=launches[k])
     tuning = dict(primal=batch.tuning(False, 2), dual=batch.tuning(True, 2))
-    shape = [tuning["primal"][k] for k in ("row_pairs", "row_threads", "apply_points", "apply_half_exchange")]
-    same_shape = all(tuning["dual"][k] == tuning["primal"][k]
-                     for k in ("row_pairs", "row_threads", "apply_points", "apply_half_exchange"))
+    keys = ("row_pairs", "row_threads", "apply_points", "apply_half_exchange", "apply_all_packs")
+    shape = [tuning["primal"][k] for k in keys]
+    same_shape = all(tuning["dual"][k] == tuning["primal"][k] for k in keys)
     traffic_all = measured_traffic(shape) if same_shape else None
     traffic = None if traffic_all is None else traffic_all.get(dom)
     roofline = dict(bound="hbm", kernel=names[dom], achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",

@@ -247,7 +247,8 @@ void hom_batch_destroy(hom_batch* b);
 /* ---- Tile tuning of the FP32 passes.
  * The specialised FP32 kernels (doubled-grid lengths 25, 81, 125, 625) have
  * several tile shapes: row pairs and threads per block of the row passes,
- * points per block and the LDS exchange width of the column pass.  With tuning on (the default; the
+ * points per block, the LDS exchange width and the packs per block of the
+ * column pass.  With tuning on (the default; the
  * environment variable HOM_TUNE=0 turns it off at start-up), the first
  * mixed-precision solve of a geometry (grid, loads, primal/dual, coefficient
  * components) in the process times every candidate on that solve's own units,
@@ -260,6 +261,7 @@ typedef struct {
   int32_t row_threads;   /* threads per row block (0: the smallest that covers the FFT) */
   int32_t apply_points;  /* points per column-pass block (0: default) */
   int32_t apply_half_exchange; /* 1: the column pass exchanges real and imaginary parts in turn */
+  int32_t apply_all_packs; /* 1: a column-pass block holds every pack of its points (2D) */
   int32_t candidates;    /* configurations timed (0: defaults, not tuned) */
   double row_ms;         /* measured time of one row-pass pair (first + last), ms */
   double apply_ms;       /* measured time of one column pass, ms */
@@ -273,10 +275,11 @@ hom_status hom_set_tuning(int32_t mode);
 hom_status hom_problem_tuning(hom_problem* pb, int32_t dual, int32_t nload, hom_tuning* out);
 hom_status hom_batch_tuning(hom_batch* b, int32_t dual, int32_t nload, hom_tuning* out);
 /* Pin the tile shape of the solves of (dual, nload): row_pairs, row_threads,
- * apply_points and apply_half_exchange of *t (0 = default; the timing fields
- * are ignored).  For bitwise-reproducible results across processes, or to
- * compare shapes.  Mixed precision only; HOM_E_INVALID for a shape the
- * specialised kernels do not have.  Synchronises the problem's stream. */
+ * apply_points, apply_half_exchange and apply_all_packs of *t (all 0 =
+ * default; the timing fields are ignored).  For bitwise-reproducible results
+ * across processes, or to compare shapes.  Mixed precision only;
+ * HOM_E_INVALID for a shape the specialised kernels do not have.
+ * Synchronises the problem's stream. */
 hom_status hom_problem_set_tiles(hom_problem* pb, int32_t dual, int32_t nload, const hom_tuning* t);
 hom_status hom_batch_set_tiles(hom_batch* b, int32_t dual, int32_t nload, const hom_tuning* t);
 

@@ -35,7 +35,8 @@ class UNetDesc(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("row_pairs", C.c_int32), ("row_threads", C.c_int32), ("apply_points", C.c_int32),
-                ("apply_half_exchange", C.c_int32), ("candidates", C.c_int32), ("row_ms", C.c_double),
+                ("apply_half_exchange", C.c_int32), ("apply_all_packs", C.c_int32), ("candidates", C.c_int32),
+                ("row_ms", C.c_double),
                 ("apply_ms", C.c_double)]
 
 

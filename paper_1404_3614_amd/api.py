@@ -275,14 +275,15 @@ def set_tuning(on=True):
 
 def _tuning_dict(t):
     return dict(row_pairs=t.row_pairs, row_threads=t.row_threads, apply_points=t.apply_points,
-                apply_half_exchange=t.apply_half_exchange, candidates=t.candidates, row_ms=t.row_ms,
-                apply_ms=t.apply_ms)
+                apply_half_exchange=t.apply_half_exchange, apply_all_packs=t.apply_all_packs,
+                candidates=t.candidates, row_ms=t.row_ms, apply_ms=t.apply_ms)
 
 
-def _tiles(row_pairs=0, row_threads=0, apply_points=0, apply_half_exchange=0, **_):
+def _tiles(row_pairs=0, row_threads=0, apply_points=0, apply_half_exchange=0, apply_all_packs=0, **_):
     t = L.Tuning()
     t.row_pairs, t.row_threads = int(row_pairs), int(row_threads)
     t.apply_points, t.apply_half_exchange = int(apply_points), int(apply_half_exchange)
+    t.apply_all_packs = int(apply_all_packs)
     return t
 
 

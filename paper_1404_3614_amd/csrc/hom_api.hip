@@ -306,6 +306,7 @@ Geo make_geo(const hom_problem* pb, int dual, int L, bool fp32, int P_override =
       g.rowThreads = tune->rowThreads;
       g.apTP = tune->apTP;
       g.apHX = tune->apHX;
+      g.apAll = tune->apAll;
     }
     const int G = fast_row_pairs(z.M[2], z.d, L, g.rowG);
     if (G > 0) g.nbF = g.nbL = (z.Q + G - 1) / G;
@@ -1516,6 +1517,7 @@ static void tuning_report(const hom_problem* p0, int k, int nload, const Tuning&
   out->row_threads = t.rowThreads;
   out->apply_points = t.apTP;
   out->apply_half_exchange = t.apHX;
+  out->apply_all_packs = t.apAll;
   out->candidates = t.candidates;
   out->row_ms = t.row_ms;
   out->apply_ms = t.apply_ms;
@@ -1534,7 +1536,7 @@ static bool tiles_ok(const hom_problem* p0, int nload, const hom_tuning* t) {
   const Sizes& z = p0->z;
   if (t->row_pairs != 0 && fast_row_pairs(z.M[2], z.d, nload, t->row_pairs) != t->row_pairs) return false;
   if (t->row_threads != 0 && (t->row_threads % 64 != 0 || t->row_threads > 256)) return false;
-  return fast_apply_shape_ok(z.M[0], z.d, t->apply_points, t->apply_half_exchange);
+  return fast_apply_shape_ok(z.M[0], z.d, t->apply_points, t->apply_half_exchange, t->apply_all_packs);
 }
 
 static Tuning tiles_from(const hom_tuning* t) {
@@ -1543,6 +1545,7 @@ static Tuning tiles_from(const hom_tuning* t) {
   u.rowThreads = t->row_threads;
   u.apTP = t->apply_points;
   u.apHX = t->apply_half_exchange;
+  u.apAll = t->apply_all_packs;
   return u;
 }
 

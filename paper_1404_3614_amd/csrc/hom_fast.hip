@@ -89,31 +89,39 @@ __device__ __forceinline__ void xchg(Cx<R>* ex, Cx<R>* v, bool wr, int wbase, bo
 }
 
 // 2D column pass: the packs are independent (pack l holds the two components
-// of load l, and the coefficient couples only those), so a block takes one
-// pack of TP points, T threads per point, one line per thread group in
-// registers.  Block order is XCD-aware: blocks b and b + 8 run on the same
-// XCD (round-robin dispatch), so each XCD takes a contiguous range of point
-// blocks and, within it, the packs of one point block back to back (shared L2
-// lines of the coefficient and of neighbouring points).
-template <typename R, int M, int P, int NC, int TP, int HX>
-__global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply2_fast(Geo g, const UnitDev* __restrict__ units, int cg) {
-  constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T;
+// of load l, and the coefficient couples only those), so a group of TP x T
+// threads takes one pack of TP points, T threads per point, one line per
+// thread group in registers.  PB = 1: one pack per block; PB = P: the packs of
+// the same points in one block, one thread group each, so the coefficient
+// lines fetched for one pack serve the others from the CU's cache.  Block
+// order is XCD-aware: blocks b and b + 8 run on the same XCD (round-robin
+// dispatch), so each XCD takes a contiguous range of point blocks and, within
+// it, the packs of one point block back to back.
+template <typename R, int M, int P, int NC, int TP, int HX, int PB>
+__global__ __launch_bounds__(PB * TP * Cfg<M>::T) void k_apply2_fast(Geo g, const UnitDev* __restrict__ units,
+                                                                     int cg) {
+  constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T, NT = TP * Cfg<M>::T;
+  static_assert(PB == 1 || PB == P, "a block holds one pack or all packs");
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem);   // [M]
-  Cx<R>* ex = tw + M;                           // exchange [M][TP]
   const UnitDev& U = units[blockIdx.z];
   if (cg && !any_active(U, g.L)) return;
   const int npts = g.M[2];
   const size_t Mtot = (size_t)M * npts;
   const int nbx = (npts + TP - 1) / TP, nbx8 = (nbx + 7) / 8;
-  const int xcd = blockIdx.x % 8, w8 = blockIdx.x / 8, cbl = w8 / P, cb = xcd * nbx8 + cbl;
-  const int pk = w8 % P;
+  const int xcd = blockIdx.x % 8, w8 = blockIdx.x / 8;
+  const int cbl = (PB == P) ? w8 : w8 / P, cb = xcd * nbx8 + cbl;
   if (cbl >= nbx8 || cb >= nbx) return;
+  const int grp = (PB == 1) ? 0 : (int)threadIdx.x / NT, tid = (int)threadIdx.x - grp * NT;
+  const int pk = (PB == P) ? grp : w8 % P;
+  // exchange area of this thread group: [M][TP] complex, or real with HX
+  Cx<R>* ex = reinterpret_cast<Cx<R>*>(smem + (size_t)M * sizeof(Cx<R>) +
+                                       (size_t)grp * M * TP * (HX ? sizeof(R) : sizeof(Cx<R>)));
   const int p0 = cb * TP;
-  const int tid = threadIdx.x, pt = tid % TP, q = tid / TP;
+  const int pt = tid % TP, q = tid / TP;
   const bool ok = (p0 + pt) < npts;
   const Cx<R>* twg = reinterpret_cast<const Cx<R>*>(g.tw[0]);
-  for (int i = tid; i < M; i += blockDim.x) tw[i] = twg[i];
+  for (int i = threadIdx.x; i < M; i += blockDim.x) tw[i] = twg[i];
   Cx<R>* data = reinterpret_cast<Cx<R>*>(U.bufA);
   // element (row i0, point p0 + pt, pack pk): pack-major [P][N0][npts] or packs interleaved
   const size_t rs = g.pmaj ? (size_t)npts : (size_t)npts * P, ps = g.pmaj ? (size_t)g.N[0] * npts : 1;
@@ -881,35 +889,36 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
 // ============================================================== dispatch
 // Candidate tile shapes per FFT length (the first entry is the default).
 // Row passes: pairs per block (2 G T <= 256 threads); column pass: points per block.
-// 2D column pass: (points per block, half exchange) pairs.
+// 2D column pass: (points per thread group, half exchange, all packs in one block).
 struct ApC {
-  int tp, hx;
+  int tp, hx, all;
 };
+constexpr int kAp2 = 6;  // column-pass candidates per length
 template <int M>
 struct Cands;
 template <>
 struct Cands<625> {
   static constexpr int G[3] = {2, 1, 4};
   static constexpr int TP[2] = {8, 4};
-  static constexpr ApC AP2[4] = {{8, 0}, {10, 1}, {5, 1}, {4, 0}};
+  static constexpr ApC AP2[6] = {{8, 0, 0}, {10, 1, 0}, {5, 1, 0}, {4, 0, 0}, {10, 1, 1}, {5, 1, 1}};
 };
 template <>
 struct Cands<125> {
   static constexpr int G[3] = {4, 2, 1};
   static constexpr int TP[2] = {10, 5};
-  static constexpr ApC AP2[4] = {{10, 0}, {5, 0}, {10, 1}, {5, 1}};
+  static constexpr ApC AP2[6] = {{10, 0, 0}, {5, 0, 0}, {10, 1, 0}, {5, 1, 0}, {5, 0, 1}, {5, 1, 1}};
 };
 template <>
 struct Cands<81> {
   static constexpr int G[3] = {14, 7, 4};
   static constexpr int TP[2] = {28, 14};
-  static constexpr ApC AP2[4] = {{28, 0}, {14, 0}, {28, 1}, {14, 1}};
+  static constexpr ApC AP2[6] = {{28, 0, 0}, {14, 0, 0}, {28, 1, 0}, {14, 1, 0}, {14, 0, 1}, {14, 1, 1}};
 };
 template <>
 struct Cands<25> {
   static constexpr int G[3] = {25, 12, 6};
   static constexpr int TP[2] = {51, 25};
-  static constexpr ApC AP2[4] = {{51, 0}, {25, 0}, {51, 1}, {25, 1}};
+  static constexpr ApC AP2[6] = {{51, 0, 0}, {25, 0, 0}, {51, 1, 0}, {25, 1, 0}, {25, 0, 1}, {25, 1, 1}};
 };
 
 static bool apply_supported(int M, int D, int P, int NC) {
@@ -918,14 +927,14 @@ static bool apply_supported(int M, int D, int P, int NC) {
 }
 
 // Whether (tp, hx) is a column-pass shape of the specialised kernels (0, 0: default).
-bool fast_apply_shape_ok(int M, int D, int tp, int hx) {
-  if (tp == 0 && hx == 0) return true;
+bool fast_apply_shape_ok(int M, int D, int tp, int hx, int all) {
+  if (tp == 0 && hx == 0 && all == 0) return true;
   auto in2 = [&](const ApC* c) {
-    for (int i = 0; i < 4; ++i)
-      if (c[i].tp == tp && c[i].hx == hx) return true;
+    for (int i = 0; i < kAp2; ++i)
+      if (c[i].tp == tp && c[i].hx == hx && c[i].all == all) return true;
     return false;
   };
-  auto in3 = [&](const int* c) { return hx == 0 && (c[0] == tp || c[1] == tp); };
+  auto in3 = [&](const int* c) { return hx == 0 && all == 0 && (c[0] == tp || c[1] == tp); };
   switch (M) {
     case 625: return D == 2 ? in2(Cands<625>::AP2) : in3(Cands<625>::TP);
     case 125: return D == 2 ? in2(Cands<125>::AP2) : in3(Cands<125>::TP);
@@ -980,33 +989,34 @@ static hipError_t run_apply_tp(const Geo& g, const UnitDev* units, int n, int cg
   return hipGetLastError();
 }
 
-template <int M, int P, int NC, int TP, int HX>
+template <int M, int P, int NC, int TP, int HX, int ALL>
 static hipError_t run_apply2_tp(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st) {
-  constexpr int T = Cfg<M>::T;
+  constexpr int T = Cfg<M>::T, PB = ALL ? P : 1;
   const int npts = g.M[2];
-  const size_t lds = (size_t)M * sizeof(Cx<float>) + (size_t)M * TP * (HX ? sizeof(float) : sizeof(Cx<float>));
-  auto kern = k_apply2_fast<float, M, P, NC, TP, HX>;
+  const size_t lds = (size_t)M * sizeof(Cx<float>) + (size_t)PB * M * TP * (HX ? sizeof(float) : sizeof(Cx<float>));
+  auto kern = k_apply2_fast<float, M, P, NC, TP, HX, PB>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int nbx = (npts + TP - 1) / TP;
-  const dim3 grid(8 * ((nbx + 7) / 8) * P, 1, n);
+  const dim3 grid(8 * ((nbx + 7) / 8) * (P / PB), 1, n);
   if (g_ext_timing.on)
-    hipExtLaunchKernelGGL(kern, grid, dim3(TP * T), lds, st, g_ext_timing.start, g_ext_timing.stop, 0, g, units, cg);
+    hipExtLaunchKernelGGL(kern, grid, dim3(PB * TP * T), lds, st, g_ext_timing.start, g_ext_timing.stop, 0, g, units,
+                          cg);
   else
-    hipLaunchKernelGGL(kern, grid, dim3(TP * T), lds, st, g, units, cg);
+    hipLaunchKernelGGL(kern, grid, dim3(PB * TP * T), lds, st, g, units, cg);
   return hipGetLastError();
 }
 
 template <int M, int P, int NC, int I = 0>
 static hipError_t run_apply2(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st) {
   constexpr ApC c = Cands<M>::AP2[I];
-  if constexpr (I + 1 < 4) {
-    if (!(g.apTP == c.tp && g.apHX == c.hx)) return run_apply2<M, P, NC, I + 1>(g, units, n, cg, st);
-    return run_apply2_tp<M, P, NC, c.tp, c.hx>(g, units, n, cg, st);
+  if (g.apTP == c.tp && g.apHX == c.hx && g.apAll == c.all)
+    return run_apply2_tp<M, P, NC, c.tp, c.hx, c.all>(g, units, n, cg, st);
+  if constexpr (I + 1 < kAp2) {
+    return run_apply2<M, P, NC, I + 1>(g, units, n, cg, st);
   } else {
-    if (g.apTP == c.tp && g.apHX == c.hx) return run_apply2_tp<M, P, NC, c.tp, c.hx>(g, units, n, cg, st);
     constexpr ApC c0 = Cands<M>::AP2[0];  // default
-    return run_apply2_tp<M, P, NC, c0.tp, c0.hx>(g, units, n, cg, st);
+    return run_apply2_tp<M, P, NC, c0.tp, c0.hx, c0.all>(g, units, n, cg, st);
   }
 }
 
@@ -1176,11 +1186,13 @@ static hipError_t tune_m(const Geo& g0, const UnitDev* units, int n, hipStream_t
   }
   if (e == hipSuccess && apply_supported(M, g0.d, g0.P, g0.nc) && g0.M[0] == M) {
     double bms = 1e30;
-    const int ncand = g0.d == 2 ? 4 : 2;
+    const int ncand = g0.d == 2 ? kAp2 : 2;
     for (int ci = 0; ci < ncand && e == hipSuccess; ++ci) {
       Geo g = g0;
       g.apTP = g0.d == 2 ? Cands<M>::AP2[ci].tp : Cands<M>::TP[ci];
       g.apHX = g0.d == 2 ? Cands<M>::AP2[ci].hx : 0;
+      g.apAll = g0.d == 2 ? Cands<M>::AP2[ci].all : 0;
+      if (g.apAll && g0.P == 1) continue;  // one pack: same kernel as one pack per block
       float ms = 0.f;
       e = time_ms(st, reps, &ms, [&]() -> hipError_t {
         hipError_t x = hipSuccess;
@@ -1192,6 +1204,7 @@ static hipError_t tune_m(const Geo& g0, const UnitDev* units, int n, hipStream_t
         bms = ms;
         t.apTP = g.apTP;
         t.apHX = g.apHX;
+        t.apAll = g.apAll;
         t.apply_ms = ms;
       }
     }

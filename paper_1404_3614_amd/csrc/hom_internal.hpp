@@ -85,6 +85,7 @@ struct Geo {
   int rowThreads;      // threads per block of the specialised row passes (0: default)
   int apTP;            // points per block of the specialised column pass (0: default)
   int apHX;            // 2D column pass: exchange real and imaginary parts separately
+  int apAll;           // 2D column pass: all packs of a point block in one block
   int pmaj;            // 2D, both specialised passes: row-pass buffer pack-major [P][N0][M2]
                        // (otherwise [N0][N1][M2][P], packs interleaved)
   int phys_axis[3];
@@ -156,7 +157,7 @@ bool fast_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, i
 // Row pairs per block for a requested value (0 or an unsupported value: the default).
 int fast_row_pairs(int M, int D, int L, int requested);
 bool fast_apply_supported(int M, int D, int P, int NC);
-bool fast_apply_shape_ok(int M, int D, int tp, int hx);
+bool fast_apply_shape_ok(int M, int D, int tp, int hx, int all);
 // Both coefficients on the doubled grid (FP64 and, when given, FP32 copies) for
 // 2D problems with equal doubled-grid lengths 25, 81, 125 or 625.
 bool fast_coef_setup(int d, const int* Mz, int nc, const Cx<double>* Ah, const Cx<double>* Bh, Cx<double>* scratch,
@@ -166,7 +167,7 @@ bool fast_coef_setup(int d, const int* Mz, int nc, const Cx<double>* Ah, const C
 // Tile shapes of the specialised passes: row pairs and threads per block of the
 // row passes, points per block of the column pass (0 = default).
 struct Tuning {
-  int rowG = 0, rowThreads = 0, apTP = 0, apHX = 0;
+  int rowG = 0, rowThreads = 0, apTP = 0, apHX = 0, apAll = 0;
   double row_ms = 0.0, apply_ms = 0.0;   // measured per first+last pair and per column pass
   int candidates = 0;                    // configurations timed
 };

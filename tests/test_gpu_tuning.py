@@ -1,10 +1,12 @@
 """GPU: tile shapes of the specialised FP32 passes.
 
-Every shape computes the same method: a column-pass shape changes only which
-threads transform which points, so results are bitwise equal; a row-pass
-shape changes the blocking of the CG reductions, so results agree to the
-rounding of those sums (1e-10 relative on the bounds, iteration counts within
-one).  The tuner reports a timed choice, and pinned shapes are validated."""
+Every shape computes the same method.  A column-pass shape changes only which
+threads transform which points; each instantiation may still fuse multiplies
+and adds differently, so results agree to FP32 rounding of the fields, which
+enters the FP64 bounds squared (1e-12 relative).  A row-pass shape changes the
+blocking of the CG reductions (1e-10 relative on the bounds, iteration counts
+within one).  The tuner reports a timed choice, and pinned shapes are
+validated."""
 import numpy as np
 import pytest
 
@@ -12,11 +14,14 @@ import homgen
 
 pytestmark = pytest.mark.gpu
 
-# doubled-grid length -> (row shapes (pairs, threads), column shapes (points, half exchange))
+# doubled-grid length -> (row shapes (pairs, threads), column shapes (points, half exchange, all packs))
 SHAPES = {
-    25: ([(25, 0), (12, 0), (6, 0), (12, 256), (6, 256)], [(51, 0), (25, 0), (51, 1), (25, 1)]),
-    81: ([(14, 0), (7, 0), (4, 0), (7, 256), (4, 256)], [(28, 0), (14, 0), (28, 1), (14, 1)]),
-    125: ([(4, 0), (2, 0), (1, 0), (2, 256), (1, 256)], [(10, 0), (5, 0), (10, 1), (5, 1)]),
+    25: ([(25, 0), (12, 0), (6, 0), (12, 256), (6, 256)],
+         [(51, 0, 0), (25, 0, 0), (51, 1, 0), (25, 1, 0), (25, 0, 1), (25, 1, 1)]),
+    81: ([(14, 0), (7, 0), (4, 0), (7, 256), (4, 256)],
+         [(28, 0, 0), (14, 0, 0), (28, 1, 0), (14, 1, 0), (14, 0, 1), (14, 1, 1)]),
+    125: ([(4, 0), (2, 0), (1, 0), (2, 256), (1, 256)],
+          [(10, 0, 0), (5, 0, 0), (10, 1, 0), (5, 1, 0), (5, 0, 1), (5, 1, 1)]),
 }
 
 
@@ -59,12 +64,13 @@ def test_every_tile_shape_gives_the_same_bounds(N):
     _pin(b)
     ref = b.solve_bounds(tol=1e-8)
     print(f"[tiles] M={M} default iterations {_iters(ref)}", flush=True)
-    for tp, hx in cols:
-        _pin(b, apply_points=tp, apply_half_exchange=hx)
+    for tp, hx, al in cols:
+        _pin(b, apply_points=tp, apply_half_exchange=hx, apply_all_packs=al)
         out = b.solve_bounds(tol=1e-8)
         for r, o in zip(ref, out):
-            assert np.array_equal(r["A_up"], o["A_up"]) and np.array_equal(r["A_low"], o["A_low"]), (tp, hx)
-        assert _iters(out) == _iters(ref)
+            assert relerr(o["A_up"], r["A_up"]) <= 1e-12 and relerr(o["A_low"], r["A_low"]) <= 1e-12, (tp, hx, al)
+        for a, c in zip(_iters(out), _iters(ref)):
+            assert max(abs(x - y) for x, y in zip(a, c)) <= 1
     for G, thr in rows:
         _pin(b, row_pairs=G, row_threads=thr)
         out = b.solve_bounds(tol=1e-8)
@@ -78,6 +84,8 @@ def test_every_tile_shape_gives_the_same_bounds(N):
         b.set_tiles(False, 2, apply_points=7)
     with pytest.raises(H.HomError):
         b.set_tiles(False, 2, row_threads=96)
+    with pytest.raises(H.HomError):
+        b.set_tiles(False, 2, apply_points=cols[0][0], apply_half_exchange=cols[0][1], apply_all_packs=1)
 
 
 def test_tuner_reports_a_timed_choice_and_batch_matches_single():
@@ -88,7 +96,7 @@ def test_tuner_reports_a_timed_choice_and_batch_matches_single():
     print(f"[tiles] tuned {t}", flush=True)
     assert t["candidates"] >= 3 and t["row_ms"] > 0 and t["apply_ms"] > 0
     assert t["row_pairs"] in (14, 7, 4)
-    assert (t["apply_points"], t["apply_half_exchange"]) in SHAPES[81][1]
+    assert (t["apply_points"], t["apply_half_exchange"], t["apply_all_packs"]) in SHAPES[81][1]
     # every later solve of the geometry, batched or single, uses the same choice
     E = np.array([[1.0, 0.0]])
     xb, ib = b.solve(False, E=E, tol=1e-8)
