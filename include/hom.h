@@ -219,6 +219,16 @@ hom_status hom_batch_create(hom_problem* const* pbs, int32_t n, void* ws, size_t
 hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const double* E, const double* const* x0,
                            double tol, int32_t maxit, double* const* x_out, hom_info* info);
 
+/* Primal and dual solves of the same nload loads for every problem, side by
+ * side: the dual runs on a stream of the library (default priority), so the
+ * kernels of the two solves share the GPU.  Same results as hom_batch_solve
+ * with dual = 0 and dual = 1 (no initial guesses); x_primal, x_dual and the
+ * info arrays as there.  Synchronises the caller's stream on entry and both
+ * streams on return.  With per-kernel timing on, the two solves run in turn. */
+hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, double tol, int32_t maxit,
+                                double* const* x_primal, double* const* x_dual, hom_info* info_primal,
+                                hom_info* info_dual);
+
 /* hom_update_coefficients for every problem of the batch (Ahat[i], Bhat[i]
  * for problem i, same layout and ownership), enqueued in one call. */
 hom_status hom_batch_update_coefficients(hom_batch* b, const void* const* Ahat, const void* const* Bhat);

@@ -91,6 +91,9 @@ EXPORTS = {
     "hom_batch_set_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
     "hom_batch_get_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "hom_set_tuning": (C.c_int32, [C.c_int32]),
+    "hom_batch_solve_pair": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_double, C.c_int32,
+                                         C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(Info),
+                                         C.POINTER(Info)]),
     "hom_batch_update_coefficients": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "hom_problem_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
     "hom_batch_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Tuning)]),

@@ -398,14 +398,33 @@ class Batch:
             cache[key] = [[p.new_field(dual) for _ in range(nl)] for p in self.problems]
         return cache[key]
 
+    def solve_pair(self, E=None, tol=1e-6, maxit=10000, out_primal=None, out_dual=None, allow_not_converged=False):
+        """Primal and dual solves of the same loads side by side (hom_batch_solve_pair)."""
+        d, n = self.d, len(self.problems)
+        E = np.eye(d) if E is None else np.atleast_2d(np.asarray(E, float))
+        nl = E.shape[0]
+        fp = out_primal if out_primal is not None else [[p.new_field(False) for _ in range(nl)] for p in self.problems]
+        fd = out_dual if out_dual is not None else [[p.new_field(True) for _ in range(nl)] for p in self.problems]
+        ip, idl = (L.Info * (n * nl))(), (L.Info * (n * nl))()
+        Ec = np.ascontiguousarray(E.reshape(-1))
+        self.stream.wait_stream(torch.cuda.current_stream())
+        st = L.load().hom_batch_solve_pair(self.h, nl, Ec.ctypes.data_as(C.POINTER(C.c_double)), float(tol),
+                                           int(maxit), _dptrs([t for ts in fp for t in ts]),
+                                           _dptrs([t for ts in fd for t in ts]), ip, idl)
+        L.check(st, "hom_batch_solve_pair", allow_not_converged)
+        conv = lambda infos: [[dict(iters=infos[i * nl + l].iters, status=infos[i * nl + l].status,
+                                    rel_res_recur=infos[i * nl + l].rel_res_recur,
+                                    rel_res_true=infos[i * nl + l].rel_res_true) for l in range(nl)]
+                              for i in range(n)]
+        return fp, conv(ip), fd, conv(idl)
+
     def solve_bounds(self, tol=1e-6, maxit=10000, allow_not_converged=False):
-        """Primal and dual solves of the unit loads and the bounds of every problem.  The
-        fields live in buffers owned by the batch and are overwritten by the next call."""
+        """Primal and dual solves of the unit loads (side by side) and the bounds of every
+        problem.  The fields live in buffers owned by the batch and are overwritten by the
+        next call."""
         d = self.d
-        xp, ip = self.solve(False, tol=tol, maxit=maxit, out=self._fields(False, d),
-                            allow_not_converged=allow_not_converged)
-        xd, idl = self.solve(True, tol=tol, maxit=maxit, out=self._fields(True, d),
-                             allow_not_converged=allow_not_converged)
+        xp, ip, xd, idl = self.solve_pair(tol=tol, maxit=maxit, out_primal=self._fields(False, d),
+                                          out_dual=self._fields(True, d), allow_not_converged=allow_not_converged)
         out = self.bounds(xp, xd)
         for i, b in enumerate(out):
             b.update(info_primal=ip[i], info_dual=idl[i])

@@ -453,6 +453,8 @@ struct SolveRun {
   SolveOut* collect_host = nullptr;
   // optional per-kernel timing: events recorded around every launch of the chunk
   std::vector<hipEvent_t>* events = nullptr;
+  bool use_graph = false;              // set by start_run
+  int types[5] = {0, 0, 0, 0, 0};     // pass types of one iteration
   double* tsum = nullptr;              // [5] accumulated ms per pass type
   long long* tcnt = nullptr;           // [5] launches per pass type
 };
@@ -503,95 +505,128 @@ static hipError_t enqueue_timed_passes(const Geo& g, const UnitDev* u, int nu, i
   return e;
 }
 
-hom_status solve_units(SolveRun& R, int nload, double tol, int maxit, bool have_x0, hom_info* info) {
+// One chunk of CG iterations of a run (direct launches, or the body of its graph).
+hipError_t enqueue_chunk(SolveRun& R) {
+  const Geo& g = R.g;
+  hipStream_t st = R.st;
+  const int npass = pass_types(g.d, R.types);
+  for (int j = 0; j < R.chunk; ++j) {
+    hipError_t e;
+    if (R.events) {
+      hipEvent_t* ev = R.events->data() + (size_t)j * 2 * npass;
+      e = R.fp32 ? enqueue_timed_passes<float>(g, R.units, R.n, j, R.iter_base, st, ev)
+                 : enqueue_timed_passes<double>(g, R.units, R.n, j, R.iter_base, st, ev);
+    } else {
+      e = enqueue_passes(R.fp32, g, R.units, FIRST_CG, LAST_CG, j, R.iter_base, st, R.n);
+    }
+    if (e != hipSuccess) return e;
+  }
+  hipError_t e = launch_advance(g, R.units, R.n, R.iter_base, R.chunk, R.active, st);
+  if (e != hipSuccess) return e;
+  return hipMemcpyAsync(R.pinned_active, R.active, sizeof(int), hipMemcpyDeviceToHost, st);
+}
+
+// Stage 1 of a solve: scalars, right-hand sides, start vectors (residual of a
+// given start) and, for graph runs, the captured graph of one chunk.
+hom_status start_run(SolveRun& R, int nload, double tol, int maxit, bool have_x0) {
+  (void)nload;
   hipStream_t st = R.st;
   const Geo& g = R.g;
   HIPCHK(launch_init_scal(g, R.units, R.n, R.iter_base, tol, maxit, st));
   HIPCHK(launch_rhs(g, R.units, R.n, st));
   HIPCHK(launch_start_vectors(g, R.units, R.n, have_x0 ? 1 : 0, st));
   if (have_x0) HIPCHK(enqueue_passes(R.fp32, g, R.units, FIRST_FIELD, LAST_RESID, 0, nullptr, st, R.n));
-  const int chunk = std::max(1, R.chunk);
+  R.chunk = std::max(1, R.chunk);
   // events recorded inside a captured graph cannot be timed, so timing runs launch directly
-  const bool use_graph = st != nullptr && env_int("HOM_NO_GRAPH", 0) == 0 && R.events == nullptr;
-  int types[5];
-  const int npass = pass_types(g.d, types);
-  const bool timing = R.events != nullptr;
-  if (timing && R.events->empty()) {
-    R.events->resize((size_t)chunk * 2 * npass);
+  R.use_graph = st != nullptr && env_int("HOM_NO_GRAPH", 0) == 0 && R.events == nullptr;
+  const int npass = pass_types(g.d, R.types);
+  if (R.events && R.events->empty()) {
+    R.events->resize((size_t)R.chunk * 2 * npass);
     for (auto& ev : *R.events) HIPCHK(hipEventCreate(&ev));
   }
-  auto enqueue_chunk = [&]() -> hipError_t {
-    for (int j = 0; j < chunk; ++j) {
-      hipError_t e;
-      if (timing) {
-        hipEvent_t* ev = R.events->data() + (size_t)j * 2 * npass;
-        e = R.fp32 ? enqueue_timed_passes<float>(g, R.units, R.n, j, R.iter_base, st, ev)
-                   : enqueue_timed_passes<double>(g, R.units, R.n, j, R.iter_base, st, ev);
-      } else {
-        e = enqueue_passes(R.fp32, g, R.units, FIRST_CG, LAST_CG, j, R.iter_base, st, R.n);
-      }
-      if (e != hipSuccess) return e;
-    }
-    hipError_t e = launch_advance(g, R.units, R.n, R.iter_base, chunk, R.active, st);
-    if (e != hipSuccess) return e;
-    return hipMemcpyAsync(R.pinned_active, R.active, sizeof(int), hipMemcpyDeviceToHost, st);
-  };
   hipGraphExec_t& gx = *R.graph;
-  if (use_graph && !gx) {
+  if (R.use_graph && !gx) {
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-    hipError_t e = enqueue_chunk();
+    hipError_t e = enqueue_chunk(R);
     hipError_t e2 = hipStreamEndCapture(st, &graph);
     if (e != hipSuccess || e2 != hipSuccess) return HOM_E_DEVICE;
     HIPCHK(hipGraphInstantiate(&gx, graph, nullptr, nullptr, 0));
     HIPCHK(hipGraphDestroy(graph));
   }
-  int done_iters = 0;
-  if (use_graph) {
-    // one chunk stays in flight while the host reads the active count of the one before: the
-    // count is monotone and every pass of a finished unit returns at once, so a chunk enqueued
-    // after the last unit stopped changes nothing
-    hipEvent_t ev[2];
-    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
-    if (hipEventCreateWithFlags(&ev[1], hipEventDisableTiming) != hipSuccess) {
-      (void)hipEventDestroy(ev[0]);
-      return HOM_E_DEVICE;
+  return HOM_OK;
+}
+
+// Stage 2 of graph runs: the chunk graphs of several runs (on their own
+// streams) replayed side by side until each has stopped.  One chunk per run
+// stays in flight while the host reads the active count of the one before:
+// the count is monotone and every pass of a finished unit returns at once, so
+// a chunk enqueued after the last unit stopped changes nothing.
+hom_status loop_runs(SolveRun* const* runs, int nr, int maxit) {
+  std::vector<hipEvent_t> ev((size_t)2 * nr, nullptr);
+  std::vector<int> it(nr, 0), done(nr, 0), fin(nr, 0);
+  hipError_t e = hipSuccess;
+  for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+  for (int r = 0; r < nr && e == hipSuccess; ++r) {
+    e = hipGraphLaunch(*runs[r]->graph, runs[r]->st);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * r], runs[r]->st);
+  }
+  int left = nr;
+  while (e == hipSuccess && left > 0) {
+    for (int r = 0; r < nr && e == hipSuccess; ++r) {
+      if (fin[r]) continue;
+      e = hipGraphLaunch(*runs[r]->graph, runs[r]->st);
+      if (e == hipSuccess) e = hipEventRecord(ev[2 * r + ((it[r] + 1) & 1)], runs[r]->st);
     }
-    hipError_t e = hipGraphLaunch(gx, st);
-    if (e == hipSuccess) e = hipEventRecord(ev[0], st);
-    for (int i = 0; e == hipSuccess; ++i) {
-      e = hipGraphLaunch(gx, st);
-      if (e == hipSuccess) e = hipEventRecord(ev[(i + 1) & 1], st);
-      if (e == hipSuccess) e = hipEventSynchronize(ev[i & 1]);
+    for (int r = 0; r < nr && e == hipSuccess; ++r) {
+      if (fin[r]) continue;
+      e = hipEventSynchronize(ev[2 * r + (it[r] & 1)]);
       if (e != hipSuccess) break;
-      done_iters += chunk;
-      if (*R.pinned_active == 0 || done_iters > maxit + chunk) break;
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipEventDestroy(ev[0]);
-    (void)hipEventDestroy(ev[1]);
-    if (e != hipSuccess) return HOM_E_DEVICE;
-  } else {
-    while (true) {
-      HIPCHK(enqueue_chunk());
-      HIPCHK(hipStreamSynchronize(st));
-      if (timing) {
-        for (int j = 0; j < chunk; ++j) {
-          hipEvent_t* ev = R.events->data() + (size_t)j * 2 * npass;
-          for (int p = 0; p < npass; ++p) {
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]));
-            R.tsum[types[p]] += ms;
-            R.tcnt[types[p]] += 1;
-          }
-        }
+      done[r] += runs[r]->chunk;
+      ++it[r];
+      if (*runs[r]->pinned_active == 0 || done[r] > maxit + runs[r]->chunk) {
+        fin[r] = 1;
+        --left;
       }
-      done_iters += chunk;
-      if (*R.pinned_active == 0) break;
-      if (done_iters > maxit + chunk) break;
     }
   }
-  // true residual b - C x of the returned iterates, in the precision mode of the solve
+  for (int r = 0; r < nr && e == hipSuccess; ++r) e = hipStreamSynchronize(runs[r]->st);
+  for (auto x : ev)
+    if (x) (void)hipEventDestroy(x);
+  return e == hipSuccess ? HOM_OK : HOM_E_DEVICE;
+}
+
+// Stage 2 of direct runs (no graph, optionally with per-kernel events).
+hom_status loop_direct(SolveRun& R, int maxit) {
+  hipStream_t st = R.st;
+  const int npass = pass_types(R.g.d, R.types);
+  int done_iters = 0;
+  while (true) {
+    HIPCHK(enqueue_chunk(R));
+    HIPCHK(hipStreamSynchronize(st));
+    if (R.events) {
+      for (int j = 0; j < R.chunk; ++j) {
+        hipEvent_t* ev = R.events->data() + (size_t)j * 2 * npass;
+        for (int p = 0; p < npass; ++p) {
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]));
+          R.tsum[R.types[p]] += ms;
+          R.tcnt[R.types[p]] += 1;
+        }
+      }
+    }
+    done_iters += R.chunk;
+    if (*R.pinned_active == 0) break;
+    if (done_iters > maxit + R.chunk) break;
+  }
+  return HOM_OK;
+}
+
+// Stage 3: true residual b - C x of the returned iterates (in the precision
+// mode of the solve) and the per-load summaries.
+hom_status finish_run(SolveRun& R, int nload, int maxit, hom_info* info) {
+  hipStream_t st = R.st;
+  const Geo& g = R.g;
   HIPCHK(enqueue_passes(R.fp32, g, R.units, FIRST_FIELD, LAST_RESID, 0, nullptr, st, R.n));
   // partial sums of the residual pass ([load][nbL] per unit) and the CG scalars
   const size_t nbl = (size_t)g.nbL;
@@ -642,6 +677,15 @@ hom_status solve_units(SolveRun& R, int nload, double tol, int maxit, bool have_
       else if (h == HOM_NOT_CONVERGED && worst == HOM_OK) worst = h;
     }
   return worst;
+}
+
+hom_status solve_units(SolveRun& R, int nload, double tol, int maxit, bool have_x0, hom_info* info) {
+  hom_status s = start_run(R, nload, tol, maxit, have_x0);
+  if (s != HOM_OK) return s;
+  SolveRun* one = &R;
+  s = R.use_graph ? loop_runs(&one, 1, maxit) : loop_direct(R, maxit);
+  if (s != HOM_OK) return s;
+  return finish_run(R, nload, maxit, info);
 }
 
 // Tile shapes for solves of nload loads over the problems pbs (one unit each in
@@ -1272,7 +1316,11 @@ struct hom_batch {
   int timing = 0;
   Tuning tune[2][kMaxLoads + 1];
   bool tuned[2][kMaxLoads + 1] = {};
-  SolveOut* collect_dev = nullptr;     // [n][kMaxLoads] end-of-solve summaries (workspace)
+  SolveOut* collect_dev = nullptr;     // [2][n][kMaxLoads] end-of-solve summaries (workspace)
+  hipStream_t stream2 = nullptr;       // library stream of the dual in side-by-side solves
+  int* pinned = nullptr;               // [2] active counts of the primal and dual loops (pinned; the
+                                       // captured chunk graphs copy into these)
+  hipEvent_t order_ev = nullptr;       // orders the library stream after the caller's
   double* bcollect_dev = nullptr;      // [2][n][9] bounds quadrature sums (workspace)
   SolveOut* collect_host = nullptr;    // pinned mirrors
   double* bcollect_host = nullptr;
@@ -1299,7 +1347,7 @@ static size_t batch_layout(int n, char* base, hom_batch* b) {
       b->active[k] = (int*)ac;
     }
   }
-  char* cs = take((size_t)n * kMaxLoads * sizeof(SolveOut));
+  char* cs = take((size_t)2 * n * kMaxLoads * sizeof(SolveOut));
   char* cb = take((size_t)n * 2 * 9 * sizeof(double));
   if (b) {
     b->collect_dev = (SolveOut*)cs;
@@ -1337,11 +1385,13 @@ hom_status hom_batch_create(hom_problem* const* pbs, int32_t n, void* ws, size_t
     b->host_units[k].resize(n);
     b->host_bunits[k].resize(n);
   }
-  if (hipHostMalloc((void**)&b->collect_host, (size_t)n * kMaxLoads * sizeof(SolveOut), hipHostMallocDefault) !=
+  if (hipHostMalloc((void**)&b->collect_host, (size_t)2 * n * kMaxLoads * sizeof(SolveOut), hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void**)&b->bcollect_host, (size_t)n * 2 * 9 * sizeof(double), hipHostMallocDefault) !=
-          hipSuccess) {
+          hipSuccess ||
+      hipHostMalloc((void**)&b->pinned, 2 * sizeof(int), hipHostMallocDefault) != hipSuccess) {
     if (b->collect_host) (void)hipHostFree(b->collect_host);
+    if (b->bcollect_host) (void)hipHostFree(b->bcollect_host);
     delete b;
     return HOM_E_DEVICE;
   }
@@ -1391,7 +1441,7 @@ hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const doub
   R.n = n;
   R.iter_base = b->iter_base[k];
   R.active = b->active[k];
-  R.pinned_active = p0->pinned_active;
+  R.pinned_active = b->pinned + k;
   R.graph = &b->graph[k][nload];
   R.chunk = p0->graph_chunk;
   if (b->timing) {
@@ -1403,9 +1453,91 @@ hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const doub
     R.part_d.push_back(b->pbs[i]->slot[k].part_d);
     R.sc.push_back(b->pbs[i]->slot[k].sc);
   }
-  R.collect_dev = b->collect_dev;
-  R.collect_host = b->collect_host;
+  R.collect_dev = b->collect_dev + (size_t)k * n * kMaxLoads;
+  R.collect_host = b->collect_host + (size_t)k * n * kMaxLoads;
   return solve_units(R, nload, tol, maxit, have_x0, info);
+}
+
+hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, double tol, int32_t maxit,
+                                double* const* x_primal, double* const* x_dual, hom_info* info_primal,
+                                hom_info* info_dual) {
+  if (!b || !info_primal || !info_dual || !x_primal || !x_dual) return HOM_E_INVALID;
+  const int n = b->n;
+  for (int i = 0; i < n; ++i) {
+    hom_status s = check_solve_args(b->pbs[i], nload, E, x_primal + (size_t)i * nload, tol, maxit);
+    if (s == HOM_OK) s = check_solve_args(b->pbs[i], nload, E, x_dual + (size_t)i * nload, tol, maxit);
+    if (s != HOM_OK) return s;
+  }
+  // per-kernel timing measures kernels one at a time: then the two solves run in turn
+  if (b->timing || env_int("HOM_NO_GRAPH", 0) != 0) {
+    hom_status s1 = hom_batch_solve(b, 0, nload, E, nullptr, tol, maxit, x_primal, info_primal);
+    if (s1 < 0) return s1;
+    hom_status s2 = hom_batch_solve(b, 1, nload, E, nullptr, tol, maxit, x_dual, info_dual);
+    if (s2 < 0) return s2;
+    return s1 != HOM_OK ? s1 : s2;
+  }
+  hom_problem* p0 = b->pbs[0];
+  const bool fp32 = p0->desc.precision == HOM_MIXED;
+  if (!b->stream2) {
+    if (hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess) {
+      b->stream2 = nullptr;
+      return HOM_E_DEVICE;
+    }
+  }
+  hipStream_t st[2] = {b->stream, b->stream2};
+  for (int k = 0; k < 2; ++k)
+    if (!b->tuned[k][nload]) {
+      hom_status s = solve_tuning(b->pbs.data(), n, k, nload, b->units[k], b->stream, &b->tune[k][nload]);
+      if (s != HOM_OK) return s;
+      b->tuned[k][nload] = true;
+    }
+  SolveRun R[2];
+  for (int k = 0; k < 2; ++k) {
+    double* const* xo = k == 0 ? x_primal : x_dual;
+    for (int i = 0; i < n; ++i) fill_unit(b->pbs[i], k, nload, E, xo + (size_t)i * nload, &b->host_units[k][i]);
+    HIPCHK(hipMemcpyAsync(b->units[k], b->host_units[k].data(), (size_t)n * sizeof(UnitDev), hipMemcpyHostToDevice,
+                          b->stream));
+    R[k].st = st[k];
+    R[k].g = make_geo(p0, k, nload, fp32, 0, &b->tune[k][nload]);
+    R[k].fp32 = fp32;
+    R[k].units = b->units[k];
+    R[k].n = n;
+    R[k].iter_base = b->iter_base[k];
+    R[k].active = b->active[k];
+    R[k].pinned_active = b->pinned + k;
+    R[k].graph = &b->graph[k][nload];
+    R[k].chunk = p0->graph_chunk;
+    for (int i = 0; i < n; ++i) {
+      R[k].part_d.push_back(b->pbs[i]->slot[k].part_d);
+      R[k].sc.push_back(b->pbs[i]->slot[k].sc);
+    }
+    R[k].collect_dev = b->collect_dev + (size_t)k * n * kMaxLoads;
+    R[k].collect_host = b->collect_host + (size_t)k * n * kMaxLoads;
+  }
+  // the second stream starts after everything the caller's stream holds (coefficient setup, unit tables)
+  if (!b->order_ev && hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming) != hipSuccess) {
+    b->order_ev = nullptr;
+    return HOM_E_DEVICE;
+  }
+  HIPCHK(hipEventRecord(b->order_ev, b->stream));
+  HIPCHK(hipStreamWaitEvent(b->stream2, b->order_ev, 0));
+  hom_status s = HOM_OK;
+  for (int k = 0; k < 2 && s == HOM_OK; ++k) s = start_run(R[k], nload, tol, maxit, false);
+  if (s != HOM_OK) return s;
+  SolveRun* runs[2] = {&R[0], &R[1]};
+  if (R[0].use_graph && R[1].use_graph) {
+    s = loop_runs(runs, 2, maxit);
+  } else {
+    for (int k = 0; k < 2 && s == HOM_OK; ++k) s = R[k].use_graph ? loop_runs(&runs[k], 1, maxit) : loop_direct(R[k], maxit);
+  }
+  if (s != HOM_OK) return s;
+  hom_status s0 = finish_run(R[0], nload, maxit, info_primal);
+  hom_status s1 = finish_run(R[1], nload, maxit, info_dual);
+  // later work on the caller's stream comes after the second stream's
+  HIPCHK(hipStreamSynchronize(b->stream2));
+  if (s0 < 0) return s0;
+  if (s1 < 0) return s1;
+  return s0 != HOM_OK ? s0 : s1;
 }
 
 hom_status hom_batch_update_coefficients(hom_batch* b, const void* const* Ahat, const void* const* Bhat) {
@@ -1611,6 +1743,12 @@ void hom_batch_destroy(hom_batch* b) {
     }
   if (b->collect_host) (void)hipHostFree(b->collect_host);
   if (b->bcollect_host) (void)hipHostFree(b->bcollect_host);
+  if (b->pinned) (void)hipHostFree(b->pinned);
+  if (b->order_ev) (void)hipEventDestroy(b->order_ev);
+  if (b->stream2) {
+    (void)hipStreamSynchronize(b->stream2);
+    (void)hipStreamDestroy(b->stream2);
+  }
   delete b;
 }
 

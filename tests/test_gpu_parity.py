@@ -292,3 +292,23 @@ def test_update_coefficients_matches_fresh_setup_and_timing_counts():
     swapped = batch.solve_bounds(tol=1e-8)
     assert np.array_equal(swapped[0]["A_up"], first[1]["A_up"])
     assert np.array_equal(swapped[1]["A_low"], first[0]["A_low"])
+
+
+def test_side_by_side_pair_equals_sequential_solves():
+    # the dual on the library's second stream: same kernels, same reductions, so bitwise equal;
+    # sequential solves reuse the same captured graphs afterwards
+    H = _H()
+    import torch
+    st = torch.cuda.Stream()
+    cells = [homgen.pixel_cell(seed=70 + i, P=25, values=(1.0, 15.0 + 25 * i)) for i in range(3)]
+    probs = [H.problem_from_cell(c, (41, 41), precision="mixed", max_loads=2, stream=st) for c in cells]
+    batch = H.Batch(probs)
+    for rep in range(2):
+        fp, ip, fd, idl = batch.solve_pair(tol=1e-8)
+        sp, isp = batch.solve(False, tol=1e-8)
+        sd, isd = batch.solve(True, tol=1e-8)
+        for i in range(3):
+            for l in range(2):
+                assert bool((fp[i][l] == sp[i][l]).all()) and bool((fd[i][l] == sd[i][l]).all())
+                assert ip[i][l]["iters"] == isp[i][l]["iters"] and idl[i][l]["iters"] == isd[i][l]["iters"]
+                assert ip[i][l]["status"] == 0 and idl[i][l]["status"] == 0
