@@ -133,6 +133,33 @@ def pass_bytes(pb, nload):
     return dict(first=6 * vec + rowbuf, apply=apply_bytes(pb, nload), last=rowbuf + 5 * vec)
 
 
+# FP32 flops of the register DFTs as written (a multiply-add counts 2): radix-5 and
+# radix-3 butterflies, compile-time rotations inside composite DFTs, run-time
+# twiddles between the two steps of a four-step transform
+DFT_FLOPS = {1: 0, 3: 16, 5: 48}
+SPLIT = {9: (3, 3), 25: (5, 5), 81: (9, 9), 125: (25, 5), 625: (25, 25)}
+
+
+def dft_flops(n):
+    if n in DFT_FLOPS:
+        return DFT_FLOPS[n]
+    a, b = SPLIT[n]
+    return b * dft_flops(a) + 6 * (a - 1) * (b - 1) + a * dft_flops(b)
+
+
+def apply_flops(pb, nload):
+    """Algorithmic FP32 flops per unit of the 2D column pass: per point of the
+    row axis and pack, an inverse and a forward length-M0 transform and the
+    coefficient product (2 flops per complex value, isotropic)."""
+    M = [2 * n - 1 for n in pb.N]
+    P = (nload * pb.d + 1) // 2
+    coef = 2 if pb.ncoef == 1 else 6
+    return M[-1] * P * (2 * dft_flops(M[0]) + coef * M[0])
+
+
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 256 CUs x 4 SIMD x 16 lanes x FMA at 2.4 GHz (no packed FP32)
+
+
 def cpu_baseline(ncells, tol):
     """The FP64 oracle on a bounded sample: ncells C2 bound pairs on the host."""
     import numpy as np
@@ -241,32 +268,52 @@ def main():
     pbytes = pass_bytes(probs[0], 2)
     total_ms = {k: avg_ms[k] * launches[k] for k in avg_ms}
     dom = max(total_ms, key=total_ms.get)
-    nbytes = unit_launches * pbytes[dom] / max(launches[dom], 1)
-    ms = avg_ms[dom]
-    achieved = nbytes / (ms * 1e-3) / 1e9
-    names = dict(first="k_first (row pass: CG update, fields, inverse FFT of the last axis)",
-                 apply="k_apply (column pass: inverse FFT, coefficient, forward FFT)",
-                 last="k_last (row pass: forward FFT, projection, CG direction update)")
+    names = dict(first="k_first_fast (row pass: CG update, fields, inverse FFT of the last axis)",
+                 apply="k_apply2_fast (column pass: inverse FFT, coefficient, forward FFT)",
+                 last="k_last_fast (row pass: forward FFT, projection, CG direction update)")
     per_pass = {}
     for k in ("first", "apply", "last"):
         if launches[k]:
             b = unit_launches * pbytes[k] / launches[k]
             per_pass[k] = dict(ms_per_launch=round(avg_ms[k], 5), bytes_per_launch=int(b),
                                gbs=round(b / (avg_ms[k] * 1e-3) / 1e9, 1), launches=launches[k])
+    aflops = unit_launches * apply_flops(probs[0], 2) / max(launches["apply"], 1)
+    per_pass["apply"]["flops_per_launch"] = int(aflops)
+    per_pass["apply"]["tflops"] = round(aflops / (avg_ms["apply"] * 1e-3) / 1e12, 2)
     tuning = dict(primal=batch.tuning(False, 2), dual=batch.tuning(True, 2))
     keys = ("row_pairs", "row_threads", "apply_points", "apply_half_exchange", "apply_all_packs")
     shape = [tuning["primal"][k] for k in keys]
     same_shape = all(tuning["dual"][k] == tuning["primal"][k] for k in keys)
     traffic_all = measured_traffic(shape) if same_shape else None
     traffic = None if traffic_all is None else traffic_all.get(dom)
-    roofline = dict(bound="hbm", kernel=names[dom], achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, traffic_unit="bytes/launch",
-                    traffic_per_pass=traffic_all, bytes_per_launch=int(nbytes),
-                    ms_per_launch=round(ms, 5), per_pass=per_pass,
-                    bytes_model="pass_bytes() in bench.py; units per launch = active cells of the batch",
-                    timed_region="second timed pass of the same steps, kernels launched directly by "
-                                 "hipExtLaunchKernelGGL with start/stop HIP events on the library stream",
-                    value_events_pass=round(B * args.steps / dt_events, 3))
+    nbytes = unit_launches * pbytes[dom] / max(launches[dom], 1)
+    ms = avg_ms[dom]
+    hbm = dict(achieved=round(nbytes / (ms * 1e-3) / 1e9, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+               frac=round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), bytes_per_launch=int(nbytes),
+               traffic=traffic)
+    it_bytes = sum(per_pass[k]["bytes_per_launch"] for k in per_pass)
+    it_ms = sum(per_pass[k]["ms_per_launch"] for k in per_pass)
+    matvec = dict(bytes_per_iteration=int(it_bytes), ms_per_iteration=round(it_ms, 5),
+                  gbs=round(it_bytes / (it_ms * 1e-3) / 1e9, 1),
+                  frac=round(it_bytes / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+    common = dict(kernel=names[dom], ms_per_launch=round(ms, 5), traffic=traffic, traffic_unit="bytes/launch",
+                  traffic_per_pass=traffic_all, per_pass=per_pass, matvec=matvec,
+                  bytes_model="pass_bytes() in bench.py; units per launch = active cells of the batch",
+                  timed_region="second timed pass of the same steps, kernels launched directly by "
+                               "hipExtLaunchKernelGGL with start/stop HIP events on the library stream",
+                  value_events_pass=round(B * args.steps / dt_events, 3))
+    if dom == "apply":
+        # the column pass issues vector ALU work for most of its duration (its FP32
+        # transforms): it is measured against the FP32 vector peak without packed
+        # instructions (the build emits none), with its HBM view beside it
+        tf = aflops / (ms * 1e-3) / 1e12
+        roofline = dict(bound="alu", achieved=round(tf, 2), peak=round(VALU_PEAK_TFLOPS, 1), unit="TFLOP/s",
+                        frac=round(tf / VALU_PEAK_TFLOPS, 4), peak_published_packed=157.3,
+                        frac_of_published=round(tf / 157.3, 4), flops_per_launch=int(aflops),
+                        flops_model="apply_flops() in bench.py", hbm=hbm, **common)
+    else:
+        roofline = dict(bound="hbm", achieved=hbm["achieved"], peak=HBM_PEAK_GBS, unit="GB/s", frac=hbm["frac"],
+                        bytes_per_launch=int(nbytes), **common)
 
     line = dict(metric=METRIC, value=round(value, 3), unit="bound pairs/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=round(ms_per_step, 3), higher_is_better=True, scaling="weak",
