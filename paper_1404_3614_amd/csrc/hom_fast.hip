@@ -278,6 +278,112 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply_fast(Geo g, const Unit
   }
 }
 
+// ============================================================== middle pass (3D, axis 1)
+// Lines along axis 1 of the flattened [M2][pack] elements: TP consecutive
+// elements per block (contiguous in memory), T threads per line, grid
+// (element blocks, N0 rows, units).  INV = 1: zero-padded N1 -> M1 inverse
+// transform from the row-pass buffer to the column-pass buffer; INV = 0:
+// forward transform back, keeping the Z_N1 part.
+template <int M, int TP, int INV>
+__global__ __launch_bounds__(TP * Cfg<M>::T) void k_mid_fast(Geo g, const UnitDev* __restrict__ units, int cg) {
+  constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T;
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<float>* tw = reinterpret_cast<Cx<float>*>(smem);  // [M]
+  Cx<float>* ex = tw + M;                              // [M][TP]
+  const UnitDev& U = units[blockIdx.z];
+  if (cg && !any_active(U, g.L)) return;
+  const int W = g.M[2] * g.P, N1 = g.N[1];
+  const size_t i0 = blockIdx.y;
+  const int tid = threadIdx.x, pt = tid % TP, q = tid / TP;
+  const int f = blockIdx.x * TP + pt;
+  const bool ok = f < W;
+  const Cx<float>* twg = reinterpret_cast<const Cx<float>*>(g.tw[1]);
+  for (int i = tid; i < M; i += blockDim.x) tw[i] = twg[i];
+  const Cx<float>* in = reinterpret_cast<const Cx<float>*>(INV ? U.bufA : U.bufB);
+  Cx<float>* out = reinterpret_cast<Cx<float>*>(INV ? U.bufB : U.bufA);
+  Cx<float> v[T];
+  if constexpr (INV) {
+    // thread n2 = q holds x[B n1 + n2]
+#pragma unroll
+    for (int n1 = 0; n1 < A; ++n1) {
+      const int i1 = (q < B && ok) ? kept<M>(B * n1 + q) : -1;
+      v[n1] = i1 >= 0 ? in[(i0 * N1 + i1) * W + f] : rf::mk<float>(0, 0);
+    }
+    __syncthreads();
+    if (q < B) {
+      rf::Dft<float, A, 1>::run(v);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) {
+        Cx<float> w = tw[q * k1];
+        w.y = -w.y;
+        ex[(q * A + k1) * TP + pt] = rf::mul(v[k1], w);
+      }
+    }
+    __syncthreads();
+    if (q < A) {
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) v[n2] = ex[(n2 * A + q) * TP + pt];
+      rf::Dft<float, B, 1>::run(v);
+      if (ok) {
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) out[(i0 * M + q + A * k2) * W + f] = v[k2];
+      }
+    }
+  } else {
+    // thread n1 = q holds x[q + A n2]
+#pragma unroll
+    for (int n2 = 0; n2 < B; ++n2) v[n2] = (q < A && ok) ? in[(i0 * M + q + A * n2) * W + f] : rf::mk<float>(0, 0);
+    __syncthreads();
+    if (q < A) {
+      rf::Dft<float, B, -1>::run(v);
+#pragma unroll
+      for (int m2 = 0; m2 < B; ++m2) ex[(q * B + m2) * TP + pt] = rf::mul(v[m2], tw[q * m2]);
+    }
+    __syncthreads();
+    if (q < B) {
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) v[n1] = ex[(n1 * B + q) * TP + pt];
+      rf::Dft<float, A, -1>::run(v);
+      if (ok) {
+#pragma unroll
+        for (int m1 = 0; m1 < A; ++m1) {
+          const int i1 = kept<M>(q + B * m1);
+          if (i1 >= 0) out[(i0 * N1 + i1) * W + f] = v[m1];
+        }
+      }
+    }
+  }
+}
+
+template <int M, int INV>
+static hipError_t run_mid(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st) {
+  constexpr int T = Cfg<M>::T, TP = (256 / T) > 64 ? 64 : (256 / T);
+  const int W = g.M[2] * g.P;
+  const size_t lds = (size_t)M * sizeof(Cx<float>) * (1 + TP);
+  auto kern = k_mid_fast<M, TP, INV>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const dim3 grid((W + TP - 1) / TP, g.N[0], n);
+  if (g_ext_timing.on)
+    hipExtLaunchKernelGGL(kern, grid, dim3(TP * T), lds, st, g_ext_timing.start, g_ext_timing.stop, 0, g, units, cg);
+  else
+    hipLaunchKernelGGL(kern, grid, dim3(TP * T), lds, st, g, units, cg);
+  return hipGetLastError();
+}
+
+// 3D middle pass for M1 in {25, 81, 125}; false when no specialisation exists.
+bool fast_mid(const Geo& g, const UnitDev* units, int n, int flags, hipStream_t st, hipError_t* err) {
+  if (std::getenv("HOM_NO_FAST")) return false;
+  if (g.d != 3) return false;
+  const int inv = flags & 1, cg = (flags & MID_CG) ? 1 : 0;
+  switch (g.M[1]) {
+    case 81: *err = inv ? run_mid<81, 1>(g, units, n, cg, st) : run_mid<81, 0>(g, units, n, cg, st); return true;
+    case 125: *err = inv ? run_mid<125, 1>(g, units, n, cg, st) : run_mid<125, 0>(g, units, n, cg, st); return true;
+    case 25: *err = inv ? run_mid<25, 1>(g, units, n, cg, st) : run_mid<25, 0>(g, units, n, cg, st); return true;
+    default: return false;
+  }
+}
+
 // ============================================================== coefficient setup (2D, FP64)
 // A and A^-1 on the doubled grid in one complex transform: both Fourier
 // series are Hermitian, so F_M^-1 (A_hat + i s B_hat) = A_M + i s B_M with real

@@ -157,6 +157,8 @@ bool fast_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, i
 // Row pairs per block for a requested value (0 or an unsupported value: the default).
 int fast_row_pairs(int M, int D, int L, int requested);
 bool fast_apply_supported(int M, int D, int P, int NC);
+// 3D middle pass (axis 1) for M1 in {25, 81, 125}; flags as launch_mid.
+bool fast_mid(const Geo& g, const UnitDev* units, int n, int flags, hipStream_t st, hipError_t* err);
 bool fast_apply_shape_ok(int M, int D, int tp, int hx, int all);
 // Both coefficients on the doubled grid (FP64 and, when given, FP32 copies) for
 // 2D problems with equal doubled-grid lengths 25, 81, 125 or 625.

@@ -916,6 +916,10 @@ hipError_t launch_apply(const Geo& g, const UnitDev* units, int nunits, int mode
 
 template <typename R>
 hipError_t launch_mid(const Geo& g, const UnitDev* units, int nunits, int inverse, hipStream_t st) {
+  if constexpr (sizeof(R) == 4) {
+    hipError_t e;
+    if (fast_mid(g, units, nunits, inverse, st, &e)) return e;
+  }
   const int inner = g.M[2] * g.P;
   const int nb = (inner + g.tileM - 1) / g.tileM;
   const size_t lds = (size_t)g.M[1] * g.tileM * sizeof(Cx<R>);
