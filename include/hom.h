@@ -81,6 +81,9 @@ typedef struct {
   int32_t status;         /* hom_status of this load */
   double  rel_res_recur;  /* ||r|| / ||E|| from the CG recurrence at exit */
   double  rel_res_true;   /* ||b - C x|| / ||E|| recomputed at exit (FP64 path of the precision mode) */
+  double  energy;         /* energy a(E + x, E + x) of the returned field from the CG energy
+                             decrements: primal, an upper bound on E^T A_H E; dual, J^T A_H^-1 J is
+                             bounded by it.  NaN for a solve started from a given x0. */
 } hom_info;
 
 typedef struct {
@@ -276,6 +279,20 @@ typedef struct {
   double row_ms;         /* measured time of one row-pass pair (first + last), ms */
   double apply_ms;       /* measured time of one column pass, ms */
 } hom_tuning;
+
+/* Stopping rule of later solves.  rule 0 (default): the residual rule of the
+ * paper's Convergence-criteria remark, ||r|| <= tol ||E|| with the tol of
+ * each solve call.  rule 1: that rule or, whichever holds first, an energy
+ * rule for the bounds themselves.  Each CG
+ * step lowers the energy a(E + x, E + x) of the iterate by alpha gamma; the
+ * solve stops when the remaining decrease, extrapolated from the last four
+ * decrements as a geometric tail with a factor 2 of margin, is below etol
+ * times the energy of the zero field (E^T <A> E, or E^T <A^-1> E for the
+ * dual), so the bounds are within about etol * <A> of their converged values
+ * (0 < etol < 1).  Any iterate is admissible, so the bounds stay guaranteed
+ * under either rule.  HOM_E_INVALID for other rules or tolerances. */
+hom_status hom_problem_set_stop(hom_problem* pb, int32_t rule, double etol);
+hom_status hom_batch_set_stop(hom_batch* b, int32_t rule, double etol);
 
 /* mode 1: tune geometries not seen yet; 0: defaults for geometries not seen
  * yet.  Choices already made stay in use.  HOM_E_INVALID for other modes. */

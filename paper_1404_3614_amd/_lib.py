@@ -25,7 +25,7 @@ class Desc(C.Structure):
 
 class Info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32),
-                ("rel_res_recur", C.c_double), ("rel_res_true", C.c_double)]
+                ("rel_res_recur", C.c_double), ("rel_res_true", C.c_double), ("energy", C.c_double)]
 
 
 class UNetDesc(C.Structure):
@@ -91,6 +91,8 @@ EXPORTS = {
     "hom_batch_set_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
     "hom_batch_get_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "hom_set_tuning": (C.c_int32, [C.c_int32]),
+    "hom_problem_set_stop": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double]),
+    "hom_batch_set_stop": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double]),
     "hom_batch_solve_pair": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_double, C.c_int32,
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(Info),
                                          C.POINTER(Info)]),

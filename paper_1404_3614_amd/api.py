@@ -181,7 +181,7 @@ class Problem:
                _dptrs(fields), infos)
         L.check(st, "hom_solve_dual" if dual else "hom_solve_primal", allow_not_converged)
         info = [dict(iters=i.iters, status=i.status, rel_res_recur=i.rel_res_recur,
-                     rel_res_true=i.rel_res_true) for i in infos]
+                     rel_res_true=i.rel_res_true, energy=i.energy) for i in infos]
         return fields, info
 
     def bounds(self, primal=None, dual=None):
@@ -238,6 +238,11 @@ class Problem:
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_net_input(self.h, C.c_void_p(out.data_ptr())), "hom_net_input")
         return out
+
+    def set_stop(self, rule="residual", etol=None):
+        """Stopping rule of later solves: "residual" (||r|| <= tol ||E||) or "energy" (etol)."""
+        r = {"residual": 0, "energy": 1}[rule]
+        L.check(L.load().hom_problem_set_stop(self.h, r, float(etol or 0.0)), "hom_problem_set_stop")
 
     def tuning(self, dual=False, nload=None):
         """Tile shapes of this problem's FP32 solves (tuned now if not chosen yet)."""
@@ -334,7 +339,8 @@ class Batch:
                                       float(tol), int(maxit), _dptrs(flat), infos)
         L.check(st, "hom_batch_solve", allow_not_converged)
         info = [[dict(iters=infos[i * nl + l].iters, status=infos[i * nl + l].status,
-                      rel_res_recur=infos[i * nl + l].rel_res_recur, rel_res_true=infos[i * nl + l].rel_res_true)
+                      rel_res_recur=infos[i * nl + l].rel_res_recur, rel_res_true=infos[i * nl + l].rel_res_true,
+                      energy=infos[i * nl + l].energy)
                  for l in range(nl)] for i in range(n)]
         return fields, info
 
@@ -346,6 +352,11 @@ class Batch:
         dp = _dptrs([t for ts in dual for t in ts]) if dual is not None else None
         L.check(L.load().hom_batch_bounds(self.h, pp, dp, res), "hom_batch_bounds")
         return [_result_dict(res[i], d) for i in range(n)]
+
+    def set_stop(self, rule="residual", etol=None):
+        """Stopping rule of later solves: "residual" (||r|| <= tol ||E||) or "energy" (etol)."""
+        r = {"residual": 0, "energy": 1}[rule]
+        L.check(L.load().hom_batch_set_stop(self.h, r, float(etol or 0.0)), "hom_batch_set_stop")
 
     def tuning(self, dual=False, nload=None):
         """Tile shapes of this batch's FP32 solves (tuned now if not chosen yet)."""
@@ -414,7 +425,8 @@ class Batch:
         L.check(st, "hom_batch_solve_pair", allow_not_converged)
         conv = lambda infos: [[dict(iters=infos[i * nl + l].iters, status=infos[i * nl + l].status,
                                     rel_res_recur=infos[i * nl + l].rel_res_recur,
-                                    rel_res_true=infos[i * nl + l].rel_res_true) for l in range(nl)]
+                                    rel_res_true=infos[i * nl + l].rel_res_true,
+                                    energy=infos[i * nl + l].energy) for l in range(nl)]
                               for i in range(n)]
         return fp, conv(ip), fd, conv(idl)
 

@@ -135,4 +135,28 @@ __device__ __forceinline__ void decode_pair(const Geo& g, int q, int& h0, int& k
 
 __host__ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) & ~(size_t)15; }
 
+
+// Energy rule.  A CG step x += alpha p lowers the energy a(E + x, E + x) of
+// the iterate by alpha gamma (gamma = <r, r>), so the energy of every iterate
+// (an upper bound on the primal side, on B on the dual side) is known from the
+// recurrence.  The remaining decrease is extrapolated from the last four
+// decrements as a geometric tail (ratio rho from the first and last of them),
+// with a factor 2 of margin; the rule stops when it is below etol times the
+// zero-field energy.  It is an extra exit beside the residual rule, which
+// still ends solves that are exact from the start.
+__device__ __forceinline__ void energy_record(CgScal* sc, int j, double dec) {
+  sc->edec[j & 3] = dec;
+  sc->esum += dec;
+}
+
+__device__ __forceinline__ bool energy_converged(const CgScal* sc, int it) {
+  if (it < 5) return false;
+  const double d1 = sc->edec[(it - 1) & 3], d4 = sc->edec[(it - 4) & 3];
+  if (!(d1 >= 0.0) || !(d4 > 0.0)) return false;
+  const double rho = cbrt(d1 / d4);
+  if (!(rho < 0.99)) return false;
+  const double rem = 2.0 * d1 * rho / (1.0 - rho);
+  return rem <= sc->etol * sc->energy0;
+}
+
 }  // namespace hom

@@ -652,7 +652,10 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_first_fast(Geo g, const
             }
           } else {
             alpha = gam / den;
-            if (blockIdx.x == 0 && lane == 0) sc->alpha[(it - 1) & 1] = alpha;
+            if (blockIdx.x == 0 && lane == 0) {
+              sc->alpha[(it - 1) & 1] = alpha;
+              energy_record(sc, it - 1, alpha * gam);
+            }
           }
         }
       }
@@ -824,7 +827,7 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
         if (act) {
           const double gam = wave_sum_arr(U.part_g + (size_t)(lo + w) * g.nbF, g.nbF);
           const bool bad = !(gam == gam) || gam > 1e300;
-          const bool conv = sqrt(gam) <= sc->tol * sc->normE;
+          const bool conv = sqrt(gam) <= sc->tol * sc->normE || (sc->stop && energy_converged(sc, it));
           if (bad || conv || it >= sc->maxit) {
             act = 0;
             if (blockIdx.x == 0 && lane == 0) {

@@ -38,7 +38,11 @@ struct CgScal {
   int32_t iters;     // iteration index at exit
   double tol;
   int32_t maxit;
-  int32_t pad_;
+  int32_t stop;      // 0: residual rule ||r|| <= tol ||E||; 1: energy rule (below)
+  double etol;       // energy rule: stop when the extrapolated remaining energy decrease <= etol * energy0
+  double energy0;    // energy of the zero field: E^T <A> E (primal) or E^T <A^-1> E (dual)
+  double esum;       // sum of the energy decrements alpha_j gamma_j so far
+  double edec[4];    // the last four decrements
 };
 
 // End-of-solve summary of one (unit, load): sum of the residual partials and the CG scalars.
@@ -130,7 +134,7 @@ hipError_t launch_line_fft(Cx<R>* data, int outer, int Lm, int inner, const Plan
 
 hipError_t launch_rhs(const Geo& g, const UnitDev* units, int nunits, hipStream_t st);
 hipError_t launch_init_scal(const Geo& g, const UnitDev* units, int nunits, int* iter_base, double tol, int maxit,
-                            hipStream_t st);
+                            int stop, double etol, hipStream_t st);
 hipError_t launch_start_vectors(const Geo& g, const UnitDev* units, int nunits, int have_x0, hipStream_t st);
 hipError_t launch_symmetrize(const Geo& g, const Cx<double>* src, Cx<double>* dst, int m, hipStream_t st);
 hipError_t launch_advance(const Geo& g, const UnitDev* units, int nunits, int* iter_base, int step,

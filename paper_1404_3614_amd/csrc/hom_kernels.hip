@@ -161,7 +161,10 @@ __global__ __launch_bounds__(kBlock) void k_first(Geo g, const UnitDev* __restri
             }
           } else {
             alpha = gam / den;
-            if (blockIdx.x == 0 && lane == 0) sc->alpha[(it - 1) & 1] = alpha;
+            if (blockIdx.x == 0 && lane == 0) {
+              sc->alpha[(it - 1) & 1] = alpha;
+              energy_record(sc, it - 1, alpha * gam);
+            }
           }
         }
       }
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_last(Geo g, const UnitDev* __restric
         if (act) {
           const double gam = wave_sum_arr(U.part_g + (size_t)w * g.nbF, g.nbF);
           const bool bad = !(gam == gam) || gam > 1e300;
-          const bool conv = sqrt(gam) <= sc->tol * sc->normE;
+          const bool conv = sqrt(gam) <= sc->tol * sc->normE || (sc->stop && energy_converged(sc, it));
           if (bad || conv || it >= sc->maxit) {
             act = 0;
             if (blockIdx.x == 0 && lane == 0) {
@@ -648,7 +651,7 @@ __global__ void k_start(Geo g, const UnitDev* __restrict__ units, int have_x0) {
 }
 
 __global__ void k_init_scal(Geo g, const UnitDev* __restrict__ units, int nunits, int* iter_base, double tol,
-                            int maxit) {
+                            int maxit, int stop, double etol) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u == 0 && iter_base) *iter_base = 0;
   if (u >= nunits) return;
@@ -666,6 +669,25 @@ __global__ void k_init_scal(Geo g, const UnitDev* __restrict__ units, int nunits
     sc->gamma0 = sc->gamma_last = 0.0;
     sc->tol = tol;
     sc->maxit = maxit;
+    sc->stop = stop;
+    sc->etol = etol;
+    // E^T <C> E from the zero frequency of the coefficient series (component order
+    // xx, yy(, zz), xy(, xz, yz) for symmetric matrices)
+    double c0[6];
+    for (int c = 0; c < g.nc; ++c) c0[c] = U.ahat[(size_t)c * g.S].x;
+    const double* E = U.E[l];
+    double en = 0.0;
+    if (g.nc == 1) {
+      en = c0[0] * e2;
+    } else if (g.d == 2) {
+      en = c0[0] * E[0] * E[0] + c0[1] * E[1] * E[1] + 2.0 * c0[2] * E[0] * E[1];
+    } else {
+      en = c0[0] * E[0] * E[0] + c0[1] * E[1] * E[1] + c0[2] * E[2] * E[2] +
+           2.0 * (c0[3] * E[0] * E[1] + c0[4] * E[0] * E[2] + c0[5] * E[1] * E[2]);
+    }
+    sc->energy0 = en;
+    sc->esum = 0.0;
+    for (int j = 0; j < 4; ++j) sc->edec[j] = 0.0;
   }
 }
 
@@ -966,9 +988,9 @@ hipError_t launch_start_vectors(const Geo& g, const UnitDev* units, int nunits, 
 }
 
 hipError_t launch_init_scal(const Geo& g, const UnitDev* units, int nunits, int* iter_base, double tol, int maxit,
-                            hipStream_t st) {
+                            int stop, double etol, hipStream_t st) {
   hipLaunchKernelGGL(k_init_scal, dim3((nunits + kBlock - 1) / kBlock), dim3(kBlock), 0, st, g, units, nunits,
-                     iter_base, tol, maxit);
+                     iter_base, tol, maxit, stop, etol);
   return hipGetLastError();
 }
 

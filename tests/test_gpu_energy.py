@@ -1,0 +1,134 @@
+"""GPU: the CG energy recurrence and the energy stopping rule.
+
+CG minimises the energy a(E + x, E + x) over its Krylov spaces, and each step
+lowers it by alpha gamma (Sec. 7.1).  Started from zero, the energy reported
+at exit is therefore the diagonal of the upper bound (primal) and of B_up, the
+inverse of the lower bound (dual); the FP64 quadrature of the returned fields
+recomputes both.  The energy rule stops on that quantity.  Every iterate gives
+guaranteed bounds (Sec. 5), and the energy of the iterates does not increase,
+so bounds from an earlier exit enclose the converged ones."""
+import numpy as np
+import pytest
+
+import homgen
+
+pytestmark = pytest.mark.gpu
+
+
+def _H():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    import paper_1404_3614_amd as H
+    from paper_1404_3614_amd import _lib
+    _lib.load()
+    return H
+
+
+def relerr(X, R):
+    return float(np.abs(np.asarray(X) - np.asarray(R)).max() / np.linalg.norm(np.asarray(R), 2))
+
+
+def _aniso_rects(seed=32):
+    rng = np.random.default_rng(seed)
+    c = homgen.Inclusions(d=2, Y=np.array([1.0, 1.3]), A0=homgen.random_spd(rng, 2, 0.5, 2.0))
+    c.add("rect", [0.2, -0.1], [0.3, 0.5], homgen.random_spd(rng, 2, 1.0, 30.0))
+    c.add("rect", [-0.3, 0.45], [0.25, 0.2], homgen.random_spd(rng, 2, 1.0, 30.0))
+    return c
+
+
+CELLS = {
+    "pix2d": (lambda: homgen.pixel_cell(seed=31, P=25, values=(1.0, 50.0)), 41),
+    "aniso2d": (_aniso_rects, (13, 41)),
+    "sph3d": (lambda: homgen.sphere_cell(seed=33, n=6, anisotropic=True), 13),
+}
+# precision -> (residual tolerance of the solve, energy vs bound-diagonal tolerance)
+PREC = {"fp64": (1e-10, 1e-10), "mixed": (1e-8, 1e-6)}
+
+
+@pytest.mark.parametrize("precision", list(PREC))
+@pytest.mark.parametrize("name", list(CELLS))
+def test_recurrence_energy_is_the_bound_diagonal(name, precision):
+    H = _H()
+    make, N = CELLS[name]
+    cell = make()
+    pb = H.problem_from_cell(cell, N, precision=precision)
+    tol, etol = PREC[precision]
+    r = pb.solve_bounds(tol=tol)
+    ep = np.array([i["energy"] for i in r["info_primal"]])
+    ed = np.array([i["energy"] for i in r["info_dual"]])
+    dp = np.abs(ep - np.diag(r["A_up"])).max() / np.linalg.norm(r["A_up"], 2)
+    dd = np.abs(ed - np.diag(r["B_up"])).max() / np.linalg.norm(r["B_up"], 2)
+    print(f"[energy] {name} {precision}: primal {dp:.2e} dual {dd:.2e}", flush=True)
+    assert dp <= etol and dd <= etol
+    # a warm start leaves the energy of the start unknown to the recurrence
+    xs, info = pb.solve(False, x0=r["fields_primal"], tol=tol)
+    assert all(np.isnan(i["energy"]) for i in info)
+
+
+def _solve_rule(b_or_pb, rule, etol, tol):
+    b_or_pb.set_stop(rule, etol)
+    out = b_or_pb.solve_bounds(tol=tol, maxit=2000, allow_not_converged=True)
+    b_or_pb.set_stop("residual")
+    return out
+
+
+def _iters(r):
+    return [i["iters"] for i in r["info_primal"] + r["info_dual"]]
+
+
+def _zero_field_energy(pb, dual):
+    _, info = pb.solve(dual, tol=1e-30, maxit=0, allow_not_converged=True)
+    assert all(i["iters"] == 0 for i in info)
+    return np.array([i["energy"] for i in info])
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_energy_rule_bounds_enclose_the_converged_ones(precision):
+    H = _H()
+    cell = homgen.pixel_cell(seed=41, P=25, values=(1.0, 100.0))
+    pb = H.problem_from_cell(cell, 41, precision=precision)
+    ref = pb.solve_bounds(tol=1e-10 if precision == "fp64" else 1e-8)
+    # zero-field energies: E^T <A> E and J^T <A^-1> J on the unit loads, the Voigt and
+    # Reuss bounds that any iterate improves on
+    e0p, e0d = _zero_field_energy(pb, False), _zero_field_energy(pb, True)
+    assert (e0p >= np.diag(ref["A_up"]) * (1 - 1e-12)).all() and (e0d >= np.diag(ref["B_up"]) * (1 - 1e-12)).all()
+    n = np.linalg.norm(ref["A_up"], 2)
+    for etol in (1e-3, 1e-5, 1e-8):
+        # the residual rule with a tolerance no solve reaches first: the energy rule decides
+        r = _solve_rule(pb, "energy", etol, 1e-14)
+        assert all(i["status"] == 0 for i in r["info_primal"] + r["info_dual"]), etol
+        ex_p = (np.diag(r["A_up"]) - np.diag(ref["A_up"])) / e0p
+        ex_d = (np.diag(r["B_up"]) - np.diag(ref["B_up"])) / e0d
+        print(f"[energy] {precision} etol {etol:g}: iterations {_iters(r)} vs residual rule {_iters(ref)}; "
+              f"excess over the converged energy / zero-field energy: primal {ex_p.max():.2e} dual {ex_d.max():.2e}",
+              flush=True)
+        # bounds stay ordered and enclose the converged ones
+        assert np.linalg.eigvalsh(r["A_up"] - r["A_low"]).min() >= -1e-9 * n
+        assert np.linalg.eigvalsh(r["A_up"] - ref["A_up"]).min() >= -1e-7 * n
+        assert np.linalg.eigvalsh(ref["A_low"] - r["A_low"]).min() >= -1e-7 * n
+        # each energy within the requested fraction of its zero-field energy
+        assert ex_p.max() <= etol + 1e-7 and ex_d.max() <= etol + 1e-7
+        if etol <= 1e-8:
+            assert relerr(r["A_up"], ref["A_up"]) <= 1e-6 and relerr(r["A_low"], ref["A_low"]) <= 1e-6
+
+
+def test_energy_rule_batch_equals_single_and_validation():
+    H = _H()
+    import torch
+    st = torch.cuda.Stream()
+    cells = [homgen.pixel_cell(seed=s, P=25, values=(1.0, 20.0 + 30 * i)) for i, s in enumerate((51, 52, 53))]
+    probs = [H.problem_from_cell(c, 41, precision="mixed", max_loads=2, stream=st) for c in cells]
+    b = H.Batch(probs)
+    b.set_stop("energy", 1e-6)
+    out = b.solve_bounds(tol=1e-12, maxit=2000, allow_not_converged=True)
+    for p, o in zip(probs, out):
+        p.set_stop("energy", 1e-6)
+        s = p.solve_bounds(tol=1e-12, maxit=2000, allow_not_converged=True)
+        assert _iters(s) == _iters(o)
+        assert relerr(s["A_up"], o["A_up"]) <= 1e-12 and relerr(s["A_low"], o["A_low"]) <= 1e-12
+    for bad in ((2, 1e-6), (1, 0.0), (1, 1.5), (1, float("nan"))):
+        with pytest.raises(H.HomError):
+            from paper_1404_3614_amd import _lib as L
+            L.check(L.load().hom_batch_set_stop(b.h, bad[0], bad[1]), "hom_batch_set_stop")
+    with pytest.raises(KeyError):
+        probs[0].set_stop("gap")
