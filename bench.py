@@ -52,6 +52,11 @@ def parse():
     ap.add_argument("--tiles", default=None,
                     help="pin the FP32 tile shape: row_pairs,row_threads,apply_points,apply_half_exchange,"
                          "apply_all_packs")
+    ap.add_argument("--stop", default="residual", choices=["residual", "energy", "guaranteed"],
+                    help="stopping rule: the residual rule at --tol, or that rule or an energy rule at --etol "
+                         "(energy: extrapolated tail; guaranteed: Gauss-Radau bound)")
+    ap.add_argument("--etol", type=float, default=1e-7,
+                    help="energy rules: remaining energy decrease / energy of the iterate")
     ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"])
     ap.add_argument("--c5-train", type=int, default=2048, help="c5: training cells")
     ap.add_argument("--c5-steps", type=int, default=1500, help="c5: Adam steps")
@@ -208,6 +213,9 @@ def main():
             batch.set_tiles(dual, 2, row_pairs=r, row_threads=t, apply_points=a, apply_half_exchange=x,
                             apply_all_packs=al)
 
+    # eigenvalue range of the phases (a in {1, 100}): the spectrum bound of the guaranteed rule
+    a_min, a_max = H.cell_eig_range(c2_cell(0))
+    batch.set_stop(args.stop, args.etol, a_min, a_max)
     pairs = [(Ah, Bh) for (Ah, Bh, nc) in coefs]
 
     def step():
@@ -250,11 +258,36 @@ def main():
     unit_launches = sum(max(i["iters"] for i in cell[key]) + 1
                         for r in results for cell in r for key in ("info_primal", "info_dual"))
 
+    # the guaranteed energy rule on the same steps (when the residual rule set the value):
+    # bounds within a relative etol of their converged values, in fewer iterations
+    energy_leg = None
+    if args.stop == "residual":
+        batch.set_stop("guaranteed", args.etol, a_min, a_max)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res_e = step()
+        torch.cuda.synchronize()
+        dt_e = time.perf_counter() - t0
+        batch.set_stop("residual")
+        diff = max(max(float(np.abs(a[k] - b[k]).max() / np.linalg.norm(b[k], 2)) for k in ("A_up", "A_low"))
+                   for a, b in zip(res_e, results[-1]))
+        energy_leg = dict(rule="guaranteed", etol=args.etol, a_min=a_min, a_max=a_max,
+                          bound_pairs_per_s=round(B * args.steps / dt_e, 3),
+                          cg_iters=[i["iters"] for i in res_e[0]["info_primal"] + res_e[0]["info_dual"]],
+                          max_rel_bound_diff_vs_residual_rule=diff,
+                          definition="residual rule at tol, or the Gauss-Radau bound on the remaining energy "
+                                     "(spectrum bound from the phases' eigenvalue range) below etol times the "
+                                     "energy of the iterate, whichever first")
+
     # plain CG for comparison: the same cells one at a time (one problem handle, no batching)
     nplain = 0 if args.no_plain else min(B, 4)
     if nplain:
         single = H.Problem(2, N, (1.0, 1.0), *coefs[0][:2], precision=args.precision, ncoef=coefs[0][2],
                            max_loads=2, stream=stream)
+        single.set_stop(args.stop, args.etol, a_min, a_max)
         single.solve_bounds(tol=args.tol)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -325,7 +358,8 @@ def main():
                             step_ms=step_ms,
                             batched="all cells of a step in lockstep (one launch per pass covers every cell)",
                             plain_bound_pairs_per_s=None if plain_value is None else round(plain_value, 3),
-                            tile_tuning=tuning),
+                            stop=args.stop, etol=args.etol if args.stop != "residual" else None,
+                            energy_rule=energy_leg, tile_tuning=tuning),
                 roofline=roofline)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_cells, args.tol)
@@ -338,6 +372,7 @@ def _line(args, value, dt, steps, workload, extra_cfg, dtype=None):
                 scaling="weak", vs_baseline=None,
                 dtype=dtype or ("f32 FFT/apply + f64 CG/bounds" if args.precision == "mixed" else "f64"),
                 data="synthetic", config=dict(workload=workload, tol=args.tol, precision=args.precision,
+                                              stop=args.stop, etol=args.etol if args.stop != "residual" else None,
                                               **extra_cfg),
                 roofline=None)
 
@@ -347,9 +382,12 @@ def run_c4(args):
     import numpy as np
     import torch
     import homgen
+    import paper_1404_3614_amd as H
     from paper_1404_3614_amd.mixed import MixedSolver
     specs = homgen.batch_specs()
-    ms = MixedSolver(precision=args.precision)
+    rng = [H.cell_eig_range(c) for _, c, _ in specs]
+    ms = MixedSolver(precision=args.precision, stop=args.stop, etol=args.etol,
+                     a_min=min(r[0] for r in rng), a_max=max(r[1] for r in rng))
     groups = ms.prepare([(N, c) for N, c, _ in specs])   # Fourier data on the device, before the timed region
     for _ in range(args.warmup):
         ms.solve(groups, len(specs), tol=args.tol)
@@ -403,6 +441,9 @@ def run_c5(args):
     st = torch.cuda.Stream()
     probs = [H.problem_from_cell(c, N, precision=args.precision, stream=st) for c in test]
     batch = H.Batch(probs)
+    rng = [H.cell_eig_range(c) for c in test]
+    a_min, a_max = min(r[0] for r in rng), max(r[1] for r in rng)
+    batch.set_stop(args.stop, args.etol, a_min, a_max)
     zero = batch.bounds([[p.new_field(False) for _ in range(2)] for p in probs],
                         [[p.new_field(True) for _ in range(2)] for p in probs])
     for _ in range(args.warmup):
@@ -433,6 +474,7 @@ def run_c5(args):
     # plain CG one cell at a time (no batching) on a subset
     nsingle = min(16, len(test))
     single = H.problem_from_cell(test[0], N, precision=args.precision)
+    single.set_stop(args.stop, args.etol, a_min, a_max)
     single.solve_bounds(tol=args.tol)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

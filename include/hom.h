@@ -82,8 +82,8 @@ typedef struct {
   double  rel_res_recur;  /* ||r|| / ||E|| from the CG recurrence at exit */
   double  rel_res_true;   /* ||b - C x|| / ||E|| recomputed at exit (FP64 path of the precision mode) */
   double  energy;         /* energy a(E + x, E + x) of the returned field from the CG energy
-                             decrements: primal, an upper bound on E^T A_H E; dual, J^T A_H^-1 J is
-                             bounded by it.  NaN for a solve started from a given x0. */
+                             decrements (and, from a given x0, the energy of x0): primal, an upper
+                             bound on E^T A_H E; dual, J^T A_H^-1 J is bounded by it. */
 } hom_info;
 
 typedef struct {
@@ -280,19 +280,34 @@ typedef struct {
   double apply_ms;       /* measured time of one column pass, ms */
 } hom_tuning;
 
-/* Stopping rule of later solves.  rule 0 (default): the residual rule of the
- * paper's Convergence-criteria remark, ||r|| <= tol ||E|| with the tol of
- * each solve call.  rule 1: that rule or, whichever holds first, an energy
- * rule for the bounds themselves.  Each CG
- * step lowers the energy a(E + x, E + x) of the iterate by alpha gamma; the
- * solve stops when the remaining decrease, extrapolated from the last four
- * decrements as a geometric tail with a factor 2 of margin, is below etol
- * times the energy of the zero field (E^T <A> E, or E^T <A^-1> E for the
- * dual), so the bounds are within about etol * <A> of their converged values
- * (0 < etol < 1).  Any iterate is admissible, so the bounds stay guaranteed
- * under either rule.  HOM_E_INVALID for other rules or tolerances. */
-hom_status hom_problem_set_stop(hom_problem* pb, int32_t rule, double etol);
-hom_status hom_batch_set_stop(hom_batch* b, int32_t rule, double etol);
+/* Stopping rule of later solves.  The Convergence-criteria remark (Sec. 7.2)
+ * picks a residual tolerance small enough that the algebraic error stays
+ * below the discretisation error; rules 1 and 2 measure the algebraic error
+ * of the bounds themselves, so a solve can stop once it is small beside the
+ * guaranteed error D (eq. GaNi_error) or a requested accuracy.  Each
+ * CG step lowers the energy a(E + x, E + x) of the iterate by alpha gamma, so
+ * the energy of every iterate, the primal upper bound on E^T A_H E (dual: the
+ * bound on J^T A_H^-1 J), is known from the recurrence.
+ *   rule 0 (default): the residual rule of the Convergence-criteria remark,
+ *     ||r|| <= tol ||E|| with the tol of each solve call.
+ *   rule 1: rule 0 or, whichever holds first, a heuristic energy rule: the
+ *     remaining decrease, extrapolated from the last four decrements as a
+ *     geometric tail with a factor 2 of margin, is below etol times the
+ *     current energy.  Irregular convergence can end it early.
+ *   rule 2: rule 0 or a guaranteed energy rule: the Gauss-Radau upper bound
+ *     on the remaining decrease (from a lower bound mu on the spectrum of the
+ *     operator) is below etol times the current energy, so the returned
+ *     energy exceeds the converged one by at most a relative etol / (1 - etol)
+ *     (in exact arithmetic; FP32 operators add their own rounding).  mu is the
+ *     larger of the smallest eigenvalue of the coefficient over the doubled
+ *     grid (the operator's quadratic form is a mean over those points) and
+ *     a_min (dual: 1 / a_max) when the caller gives one (> 0); a caller's
+ *     value must bound the coefficient's eigenvalues, or the guarantee is lost.
+ * 0 < etol < 1 for rules 1 and 2; a_min, a_max >= 0 (0: not given).  Every
+ * iterate is admissible, so the bounds stay guaranteed under every rule.
+ * HOM_E_INVALID for other values. */
+hom_status hom_problem_set_stop(hom_problem* pb, int32_t rule, double etol, double a_min, double a_max);
+hom_status hom_batch_set_stop(hom_batch* b, int32_t rule, double etol, double a_min, double a_max);
 
 /* mode 1: tune geometries not seen yet; 0: defaults for geometries not seen
  * yet.  Choices already made stay in use.  HOM_E_INVALID for other modes. */

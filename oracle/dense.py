@@ -37,23 +37,32 @@ def _index_set(N):
     return [np.array(k) for k in itertools.product(*[range(-(n - 1) // 2, (n - 1) // 2 + 1) for n in N])]
 
 
+def dense_matrix(Ahat_fn, N, Y, dual=False):
+    """The Hermitian Galerkin matrix K of the system below (unknowns c(k) in
+    the bases T(k), k in Z_N without 0), with the frequencies and bases."""
+    ks = [k for k in _index_set(N) if np.any(k != 0)]
+    bases = [_basis(k, Y, dual) for k in ks]
+    m = bases[0].shape[1]
+    n = len(ks) * m
+    K = np.zeros((n, n), dtype=np.complex128)
+    for i, (l, Tl) in enumerate(zip(ks, bases)):
+        for j, (k, Tk) in enumerate(zip(ks, bases)):
+            K[i * m:(i + 1) * m, j * m:(j + 1) * m] = Tl.T @ Ahat_fn(l - k) @ Tk
+    return K, ks, bases
+
+
 def dense_solve(Ahat_fn, N, Y, E, dual=False):
     """Solve the dense Galerkin system.
 
     Ahat_fn(n) -> d x d complex matrix A_hat(n) for an integer vector n
     (the series of A, or of A^{-1} for the dual).  Returns the Fourier
     coefficients of the minimiser as a dict {tuple(k): vector}."""
-    ks = [k for k in _index_set(N) if np.any(k != 0)]
-    bases = [_basis(k, Y, dual) for k in ks]
+    K, ks, bases = dense_matrix(Ahat_fn, N, Y, dual)
     m = bases[0].shape[1]
-    n = len(ks) * m
-    K = np.zeros((n, n), dtype=np.complex128)
-    f = np.zeros(n, dtype=np.complex128)
+    f = np.zeros(K.shape[0], dtype=np.complex128)
     E = np.asarray(E, float)
     for i, (l, Tl) in enumerate(zip(ks, bases)):
         f[i * m:(i + 1) * m] = -Tl.T @ (Ahat_fn(l) @ E)
-        for j, (k, Tk) in enumerate(zip(ks, bases)):
-            K[i * m:(i + 1) * m, j * m:(j + 1) * m] = Tl.T @ Ahat_fn(l - k) @ Tk
     c = np.linalg.solve(K, f)
     return {tuple(k): Tk @ c[i * m:(i + 1) * m] for i, (k, Tk) in enumerate(zip(ks, bases))}
 

@@ -1,0 +1,160 @@
+"""Energy of the CG iterates and stopping rules on it (oracle, FP64).
+
+Test infrastructure: only the tests, the smoke check and the CPU baseline of
+the benchmark use this package.
+
+The Galerkin problems of oracle/galerkin.py minimise the energy
+a(E + x, E + x) over x in E_N (primal; the dual minimises a^{-1}(J + j, J + j)
+over J_N), and the minimum is the diagonal entry of the guaranteed bound
+(Def. upper_lower_bounds).  CG minimises this energy over growing Krylov
+spaces (Sec. 7.1), so every iterate gives a guaranteed, non-increasing bound,
+and step i lowers the energy by alpha_i gamma_i (gamma_i = ||r_i||^2):
+
+    energy(x) - energy(x*) = (x* - x)^T C (x* - x),   energy(x) = e0 - <x, b + r>,
+
+e0 = E^T <A> E the energy of the zero field.  The Convergence-criteria remark
+(Sec. 7.2) stops on the residual, with a tolerance picked so that the
+algebraic error stays below the discretisation error; the rules here bound
+that algebraic error in the energy itself:
+
+* guaranteed: the Gauss-Radau quadrature of the Lanczos process behind CG
+  bounds the remaining decrease (x* - x_i)^T C (x* - x_i) from above by
+  gamma_i phi_i for any mu at or below the smallest eigenvalue of C, with
+  phi_0 = 1/mu and phi_i = t / (mu t + gamma_i / gamma_{i-1}),
+  t = phi_{i-1} - alpha_{i-1} (G. Meurant and P. Tichy, Numer. Algorithms,
+  2019); gamma_i / mu bounds it as well.  The rule stops when the bound is
+  below etol times the energy of the iterate.
+* heuristic: the remaining decrease extrapolated as a geometric tail of the
+  last four decrements (ratio rho = (d_{i-1} / d_{i-4})^{1/3}, remainder
+  2 d_{i-1} rho / (1 - rho)), below etol times the energy of the iterate.
+
+Both are extra exits beside the residual rule.  mu: the quadratic form of C
+is the integral of v . A v over the cell, so the smallest eigenvalue a_min of
+the coefficient bounds the spectrum of C from below (dual: 1 / a_max).  It is
+also the mean over the doubled grid of v . A_M v (Lemma
+integral_eval_double_grid), with sum |v|^2 the squared L2 norm of the field,
+so the smallest eigenvalue of A_M over the grid points bounds it as well; the
+truncated series oscillates near interfaces, which can make that second
+bound vacuous (negative) at high contrast.
+
+Pinned by tests/test_oracle_stopping.py: the energy recurrence against the
+double-grid quadrature of the bounds, mu against the eigenvalues of the
+dense Galerkin matrix, the Gauss-Radau bound against the exact remaining
+energy from a direct solve, and the stop decisions against their definitions.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .galerkin import constant_field, ga_apply
+from .spectral import apply_blockdiag, inner, proj_E, proj_J
+
+
+def spectrum_lower_bound(coef_M):
+    """Smallest eigenvalue of the symmetric coefficient over the doubled grid."""
+    d = coef_M.shape[0]
+    pts = np.moveaxis(coef_M.reshape(d, d, -1), -1, 0)
+    return float(np.linalg.eigvalsh(pts)[:, 0].min())
+
+
+@dataclass
+class EnergyCG:
+    x: np.ndarray
+    iters: int
+    status: str                                   # "residual", "energy" or "maxit"
+    energy: list = field(default_factory=list)     # energy of iterate i from the recurrence
+    radau: list = field(default_factory=list)      # Gauss-Radau bound on the remaining decrease of iterate i
+    gamma: list = field(default_factory=list)
+
+
+def operator(prob, dual):
+    coef = prob.Btil if dual else prob.Atil
+    G = proj_J(prob.N, prob.Y) if dual else proj_E(prob.N, prob.Y)
+
+    def C(x):
+        return apply_blockdiag(G, ga_apply(coef, x, prob.N))
+    return C, coef
+
+
+def zero_field_energy(prob, E, dual):
+    """E^T <A> E (dual: with <A^{-1}>) from the zero frequency of the series."""
+    E = np.asarray(E, float)
+    Ah = prob.Bhat if dual else prob.Ahat
+    A0 = Ah[(slice(None), slice(None)) + (0,) * prob.d].real
+    return float(E @ A0 @ E)
+
+
+def cg_energy(apply_C, b, e0, normE, tol=1e-8, rule="guaranteed", etol=1e-8, mu=0.0, maxit=20000):
+    """Hestenes-Stiefel CG for C x = b from x0 = 0, tracking the energy
+    e0 - sum alpha_i gamma_i and the Gauss-Radau bound of every iterate; the
+    residual rule ||r|| <= tol normE and, beside it, the energy rule `rule`
+    ("guaranteed", "heuristic" or None) at etol."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    p = r.copy()
+    gam = inner(r, r)
+    energy, dec = e0, []
+    out = EnergyCG(x=x, iters=0, status="maxit")
+    phi = 1.0 / mu if mu > 0 else np.inf
+    alpha_prev = gam_prev = None
+    i = 0
+    while True:
+        # Gauss-Radau factor of iterate i
+        if i > 0 and mu > 0:
+            t = phi - alpha_prev
+            ph = t / (mu * t + gam / gam_prev)
+            phi = ph if (t > 0 and 0 < ph < 1.0 / mu) else 1.0 / mu
+        out.energy.append(energy)
+        out.radau.append(gam * phi)
+        out.gamma.append(gam)
+        if np.sqrt(gam) <= tol * normE:
+            out.status = "residual"
+            break
+        if rule == "guaranteed" and gam * phi <= etol * energy:
+            out.status = "energy"
+            break
+        if rule == "heuristic" and i >= 5:
+            d1, d4 = dec[i - 1], dec[i - 4]
+            if d1 >= 0 and d4 > 0:
+                rho = (d1 / d4) ** (1.0 / 3.0)
+                if rho < 0.99 and 2 * d1 * rho / (1 - rho) <= etol * energy:
+                    out.status = "energy"
+                    break
+        if i >= maxit:
+            break
+        q = apply_C(p)
+        pq = inner(p, q)
+        if pq <= 0.0:
+            raise FloatingPointError("operator not positive definite on the subspace")
+        alpha = gam / pq
+        x = x + alpha * p
+        r = r - alpha * q
+        gam_new = inner(r, r)
+        dec.append(alpha * gam)
+        energy -= alpha * gam
+        p = r + (gam_new / gam) * p
+        alpha_prev, gam_prev, gam = alpha, gam, gam_new
+        i += 1
+    out.x, out.iters = x, i
+    return out
+
+
+def solve(prob, E, dual=False, tol=1e-8, rule="guaranteed", etol=1e-8, mu=None, maxit=20000):
+    """The primal (dual) Galerkin problem for load E by cg_energy.  mu: lower
+    bound on the spectrum (default: spectrum_lower_bound of the coefficient)."""
+    E = np.asarray(E, float)
+    C, coef = operator(prob, dual)
+    if mu is None:
+        mu = spectrum_lower_bound(coef)
+    b = -C(constant_field(E, prob.N))
+    return cg_energy(C, b, zero_field_energy(prob, E, dual), float(np.linalg.norm(E)), tol, rule, etol, mu, maxit)
+
+
+def energy_of(prob, x, E, dual=False):
+    """e0 - <x, b + r>: the energy of a field from the operator (no recurrence)."""
+    C, _ = operator(prob, dual)
+    b = -C(constant_field(np.asarray(E, float), prob.N))
+    r = b - C(x)
+    return zero_field_energy(prob, E, dual) - float(np.real(inner(x, b + r)))

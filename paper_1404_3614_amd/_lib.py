@@ -91,8 +91,8 @@ EXPORTS = {
     "hom_batch_set_timing": (C.c_int32, [C.c_void_p, C.c_int32]),
     "hom_batch_get_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "hom_set_tuning": (C.c_int32, [C.c_int32]),
-    "hom_problem_set_stop": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double]),
-    "hom_batch_set_stop": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double]),
+    "hom_problem_set_stop": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double]),
+    "hom_batch_set_stop": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double]),
     "hom_batch_solve_pair": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_double, C.c_int32,
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(Info),
                                          C.POINTER(Info)]),

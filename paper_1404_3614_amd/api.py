@@ -71,6 +71,17 @@ def cell_ncoef(cell):
     return 1 if all(_is_iso(A) for A in mats) else d * (d + 1) // 2
 
 
+def cell_eig_range(cell):
+    """Smallest and largest eigenvalue over the phases of a cell: the a_min and
+    a_max of the guaranteed stopping rule (set_stop)."""
+    if hasattr(cell, "phase"):
+        mats = [cell.phase_A[i] for i in np.unique(cell.phase)]
+    else:
+        mats = [cell.A0] + list(cell.A)
+    ev = np.concatenate([np.linalg.eigvalsh(np.asarray(A, float)) for A in mats])
+    return float(ev.min()), float(ev.max())
+
+
 def coef_inclusions(cell, N, ncoef, inverse=False, stream=None):
     """Fourier coefficients on Z_{2N-1} of a matrix-inclusion cell, on the device."""
     d = cell.d
@@ -239,10 +250,13 @@ class Problem:
         L.check(L.load().hom_net_input(self.h, C.c_void_p(out.data_ptr())), "hom_net_input")
         return out
 
-    def set_stop(self, rule="residual", etol=None):
-        """Stopping rule of later solves: "residual" (||r|| <= tol ||E||) or "energy" (etol)."""
-        r = {"residual": 0, "energy": 1}[rule]
-        L.check(L.load().hom_problem_set_stop(self.h, r, float(etol or 0.0)), "hom_problem_set_stop")
+    def set_stop(self, rule="residual", etol=None, a_min=0.0, a_max=0.0):
+        """Stopping rule of later solves (hom_problem_set_stop): "residual" (||r|| <= tol ||E||),
+        "energy" (or an extrapolated energy tail below etol) or "guaranteed" (or the
+        Gauss-Radau bound on the remaining energy below etol; a_min / a_max optionally
+        bound the coefficient's eigenvalues)."""
+        L.check(L.load().hom_problem_set_stop(self.h, _STOP_RULES[rule], float(etol or 0.0), float(a_min), float(a_max)),
+                "hom_problem_set_stop")
 
     def tuning(self, dual=False, nload=None):
         """Tile shapes of this problem's FP32 solves (tuned now if not chosen yet)."""
@@ -271,6 +285,9 @@ class Problem:
         b = self.bounds(xp, xd)
         b.update(info_primal=ip, info_dual=idl, fields_primal=xp, fields_dual=xd)
         return b
+
+
+_STOP_RULES = {"residual": 0, "energy": 1, "guaranteed": 2}
 
 
 def set_tuning(on=True):
@@ -353,10 +370,13 @@ class Batch:
         L.check(L.load().hom_batch_bounds(self.h, pp, dp, res), "hom_batch_bounds")
         return [_result_dict(res[i], d) for i in range(n)]
 
-    def set_stop(self, rule="residual", etol=None):
-        """Stopping rule of later solves: "residual" (||r|| <= tol ||E||) or "energy" (etol)."""
-        r = {"residual": 0, "energy": 1}[rule]
-        L.check(L.load().hom_batch_set_stop(self.h, r, float(etol or 0.0)), "hom_batch_set_stop")
+    def set_stop(self, rule="residual", etol=None, a_min=0.0, a_max=0.0):
+        """Stopping rule of later solves (hom_batch_set_stop): "residual" (||r|| <= tol ||E||),
+        "energy" (or an extrapolated energy tail below etol) or "guaranteed" (or the
+        Gauss-Radau bound on the remaining energy below etol; a_min / a_max optionally
+        bound the coefficient's eigenvalues)."""
+        L.check(L.load().hom_batch_set_stop(self.h, _STOP_RULES[rule], float(etol or 0.0), float(a_min), float(a_max)),
+                "hom_batch_set_stop")
 
     def tuning(self, dual=False, nload=None):
         """Tile shapes of this batch's FP32 solves (tuned now if not chosen yet)."""

@@ -118,8 +118,7 @@ struct hom_problem {
   int graph_chunk;
   Tuning tune[2][kMaxLoads + 1];        // tile shapes of the single-problem solves
   bool tuned[2][kMaxLoads + 1];
-  int stop_rule;                        // 0 residual rule, 1 energy rule (hom_problem_set_stop)
-  double stop_etol;
+  StopCfg stop;                         // stopping rule of later solves (hom_problem_set_stop)
 };
 
 namespace {
@@ -456,9 +455,7 @@ struct SolveRun {
   // optional per-kernel timing: events recorded around every launch of the chunk
   std::vector<hipEvent_t>* events = nullptr;
   bool use_graph = false;              // set by start_run
-  int stop = 0;                        // stopping rule (0 residual, 1 energy) and its tolerance
-  double etol = 0.0;
-  bool warm = false;                   // started from a given x0 (set by start_run)
+  StopCfg stop;                        // stopping rule
   int types[5] = {0, 0, 0, 0, 0};     // pass types of one iteration
   double* tsum = nullptr;              // [5] accumulated ms per pass type
   long long* tcnt = nullptr;           // [5] launches per pass type
@@ -537,11 +534,24 @@ hom_status start_run(SolveRun& R, int nload, double tol, int maxit, bool have_x0
   (void)nload;
   hipStream_t st = R.st;
   const Geo& g = R.g;
-  HIPCHK(launch_init_scal(g, R.units, R.n, R.iter_base, tol, maxit, R.stop, R.etol, st));
+  // the guaranteed rule needs a lower bound on the spectrum of the operator: the
+  // smallest eigenvalue of the coefficient over the doubled grid, per unit
+  int mu_parts = 0;
+  double mu_user = 0.0;
+  if (R.stop.rule == 2) {
+    const size_t npts = (size_t)g.M[0] * g.M[1] * g.M[2];
+    mu_parts = (int)std::min<size_t>(64, (npts + kBlock - 1) / kBlock);
+    HIPCHK(launch_coef_min_eig(R.fp32, g, R.units, R.n, mu_parts, st));
+    mu_user = g.dual ? (R.stop.a_max > 0.0 ? 1.0 / R.stop.a_max : 0.0) : R.stop.a_min;
+  }
+  HIPCHK(launch_init_scal(g, R.units, R.n, R.iter_base, tol, maxit, R.stop.rule, R.stop.etol, mu_parts, mu_user,
+                          st));
   HIPCHK(launch_rhs(g, R.units, R.n, st));
-  R.warm = have_x0;
   HIPCHK(launch_start_vectors(g, R.units, R.n, have_x0 ? 1 : 0, st));
-  if (have_x0) HIPCHK(enqueue_passes(R.fp32, g, R.units, FIRST_FIELD, LAST_RESID, 0, nullptr, st, R.n));
+  if (have_x0) {
+    HIPCHK(enqueue_passes(R.fp32, g, R.units, FIRST_FIELD, LAST_RESID, 0, nullptr, st, R.n));
+    HIPCHK(launch_start_energy(g, R.units, R.n, st));
+  }
   R.chunk = std::max(1, R.chunk);
   // events recorded inside a captured graph cannot be timed, so timing runs launch directly
   R.use_graph = st != nullptr && env_int("HOM_NO_GRAPH", 0) == 0 && R.events == nullptr;
@@ -671,8 +681,7 @@ hom_status finish_run(SolveRun& R, int nload, int maxit, hom_info* info) {
       in.iters = sc[ul].iters;
       in.rel_res_recur = std::sqrt(std::max(sc[ul].gamma_last, 0.0)) / sc[ul].normE;
       in.rel_res_true = std::sqrt(std::max(s, 0.0)) / sc[ul].normE;
-      // the recurrence knows the energy only relative to its start: exact from zero
-      in.energy = R.warm ? std::nan("") : sc[ul].energy0 - sc[ul].esum;
+      in.energy = sc[ul].energy0 - sc[ul].esum;
       const int stt = sc[ul].status;
       hom_status h;
       if (stt == 1) h = HOM_OK;
@@ -761,8 +770,7 @@ hom_status solve_impl(hom_problem* pb, int k, int nload, const double* E, const 
   R.pinned_active = pb->pinned_active;
   R.graph = &pb->graph[k][nload];
   R.chunk = pb->graph_chunk;
-  R.stop = pb->stop_rule;
-  R.etol = pb->stop_etol;
+  R.stop = pb->stop;
   R.part_d.push_back(sb.part_d);
   R.sc.push_back(sb.sc);
   return solve_units(R, nload, tol, maxit, have_x0, info);
@@ -1326,8 +1334,7 @@ struct hom_batch {
   int timing = 0;
   Tuning tune[2][kMaxLoads + 1];
   bool tuned[2][kMaxLoads + 1] = {};
-  int stop_rule = 0;                   // as in hom_problem
-  double stop_etol = 0.0;
+  StopCfg stop;                        // as in hom_problem
   SolveOut* collect_dev = nullptr;     // [2][n][kMaxLoads] end-of-solve summaries (workspace)
   hipStream_t stream2 = nullptr;       // library stream of the dual in side-by-side solves
   int* pinned = nullptr;               // [2] active counts of the primal and dual loops (pinned; the
@@ -1456,8 +1463,7 @@ hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const doub
   R.pinned_active = b->pinned + k;
   R.graph = &b->graph[k][nload];
   R.chunk = p0->graph_chunk;
-  R.stop = b->stop_rule;
-  R.etol = b->stop_etol;
+  R.stop = b->stop;
   if (b->timing) {
     R.events = &b->tevents[k][nload];
     R.tsum = b->tsum;
@@ -1521,8 +1527,7 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, do
     R[k].pinned_active = b->pinned + k;
     R[k].graph = &b->graph[k][nload];
     R[k].chunk = p0->graph_chunk;
-    R[k].stop = b->stop_rule;
-    R[k].etol = b->stop_etol;
+    R[k].stop = b->stop;
     for (int i = 0; i < n; ++i) {
       R[k].part_d.push_back(b->pbs[i]->slot[k].part_d);
       R[k].sc.push_back(b->pbs[i]->slot[k].sc);
@@ -1671,17 +1676,31 @@ static void tuning_report(const hom_problem* p0, int k, int nload, const Tuning&
   out->apply_ms = t.apply_ms;
 }
 
-hom_status hom_problem_set_stop(hom_problem* pb, int32_t rule, double etol) {
-  if (!pb || (rule != 0 && rule != 1) || (rule == 1 && !(etol > 0.0 && etol < 1.0))) return HOM_E_INVALID;
-  pb->stop_rule = rule;
-  pb->stop_etol = rule ? etol : 0.0;
+static bool stop_args_ok(int32_t rule, double etol, double a_min, double a_max) {
+  if (rule < 0 || rule > 2) return false;
+  if (rule > 0 && !(etol > 0.0 && etol < 1.0)) return false;
+  if (!(a_min >= 0.0 && a_min < INFINITY) || !(a_max >= 0.0 && a_max < INFINITY)) return false;
+  return !(a_min > 0.0 && a_max > 0.0 && a_min > a_max);
+}
+
+static StopCfg make_stop(int32_t rule, double etol, double a_min, double a_max) {
+  StopCfg c;
+  c.rule = rule;
+  c.etol = rule ? etol : 0.0;
+  c.a_min = a_min;
+  c.a_max = a_max;
+  return c;
+}
+
+hom_status hom_problem_set_stop(hom_problem* pb, int32_t rule, double etol, double a_min, double a_max) {
+  if (!pb || !stop_args_ok(rule, etol, a_min, a_max)) return HOM_E_INVALID;
+  pb->stop = make_stop(rule, etol, a_min, a_max);
   return HOM_OK;
 }
 
-hom_status hom_batch_set_stop(hom_batch* b, int32_t rule, double etol) {
-  if (!b || (rule != 0 && rule != 1) || (rule == 1 && !(etol > 0.0 && etol < 1.0))) return HOM_E_INVALID;
-  b->stop_rule = rule;
-  b->stop_etol = rule ? etol : 0.0;
+hom_status hom_batch_set_stop(hom_batch* b, int32_t rule, double etol, double a_min, double a_max) {
+  if (!b || !stop_args_ok(rule, etol, a_min, a_max)) return HOM_E_INVALID;
+  b->stop = make_stop(rule, etol, a_min, a_max);
   return HOM_OK;
 }
 

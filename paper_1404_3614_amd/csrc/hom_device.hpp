@@ -139,11 +139,11 @@ __host__ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) &
 // Energy rule.  A CG step x += alpha p lowers the energy a(E + x, E + x) of
 // the iterate by alpha gamma (gamma = <r, r>), so the energy of every iterate
 // (an upper bound on the primal side, on B on the dual side) is known from the
-// recurrence.  The remaining decrease is extrapolated from the last four
-// decrements as a geometric tail (ratio rho from the first and last of them),
-// with a factor 2 of margin; the rule stops when it is below etol times the
-// zero-field energy.  It is an extra exit beside the residual rule, which
-// still ends solves that are exact from the start.
+// recurrence: energy0 - esum.  The remaining decrease is extrapolated from the
+// last four decrements as a geometric tail (ratio rho from the first and last
+// of them), with a factor 2 of margin; the rule stops when it is below etol
+// times the current energy.  It is an extra exit beside the residual rule,
+// which still ends solves that are exact from the start.
 __device__ __forceinline__ void energy_record(CgScal* sc, int j, double dec) {
   sc->edec[j & 3] = dec;
   sc->esum += dec;
@@ -156,7 +156,38 @@ __device__ __forceinline__ bool energy_converged(const CgScal* sc, int it) {
   const double rho = cbrt(d1 / d4);
   if (!(rho < 0.99)) return false;
   const double rem = 2.0 * d1 * rho / (1.0 - rho);
-  return rem <= sc->etol * sc->energy0;
+  return rem <= sc->etol * (sc->energy0 - sc->esum);
+}
+
+// Guaranteed rule.  For a lower bound mu on the spectrum of the operator,
+// the Gauss-Radau quadrature of the CG Lanczos process bounds the remaining
+// energy decrease of iterate j from above by gamma_j phi_j, with phi_0 = 1/mu
+// and phi_j = t / (mu t + gamma_j / gamma_{j-1}), t = phi_{j-1} - alpha_{j-1}
+// (Meurant and Tichy, Numer. Algorithms 2019).  gamma / mu bounds it as well,
+// so phi never exceeds 1/mu, and 1/mu replaces a value that rounding has made
+// meaningless.
+__device__ __forceinline__ double radau_phi(const CgScal* sc, int it, double gam) {
+  if (!(sc->mu > 0.0)) return INFINITY;
+  const double inv = 1.0 / sc->mu;
+  if (it == 0) return inv;
+  const double t = sc->phi[(it - 1) & 1] - sc->alpha[(it - 1) & 1];
+  const double ph = t / (sc->mu * t + gam / sc->gamma[(it - 1) & 1]);
+  return (t > 0.0 && ph > 0.0 && ph < inv) ? ph : inv;
+}
+
+// Stopping test of iteration it with gamma = gam; the writer thread keeps the
+// state of the guaranteed rule (parity-buffered: other blocks of the same
+// launch read the previous iteration's entry).
+__device__ __forceinline__ bool stop_test(CgScal* sc, int it, double gam, bool writer) {
+  bool conv = sqrt(gam) <= sc->tol * sc->normE;
+  if (sc->stop == 1) {
+    conv = conv || energy_converged(sc, it);
+  } else if (sc->stop == 2) {
+    const double ph = radau_phi(sc, it, gam);
+    if (writer) sc->phi[it & 1] = ph;
+    conv = conv || gam * ph <= sc->etol * (sc->energy0 - sc->esum);
+  }
+  return conv;
 }
 
 }  // namespace hom

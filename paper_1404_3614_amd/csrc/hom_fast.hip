@@ -827,7 +827,7 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
         if (act) {
           const double gam = wave_sum_arr(U.part_g + (size_t)(lo + w) * g.nbF, g.nbF);
           const bool bad = !(gam == gam) || gam > 1e300;
-          const bool conv = sqrt(gam) <= sc->tol * sc->normE || (sc->stop && energy_converged(sc, it));
+          const bool conv = stop_test(sc, it, gam, blockIdx.x == 0 && lane == 0);
           if (bad || conv || it >= sc->maxit) {
             act = 0;
             if (blockIdx.x == 0 && lane == 0) {

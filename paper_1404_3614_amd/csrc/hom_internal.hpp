@@ -39,10 +39,21 @@ struct CgScal {
   double tol;
   int32_t maxit;
   int32_t stop;      // 0: residual rule ||r|| <= tol ||E||; 1: energy rule (below)
-  double etol;       // energy rule: stop when the extrapolated remaining energy decrease <= etol * energy0
+  double etol;       // energy rule: stop when the extrapolated remaining energy decrease <= etol * energy
   double energy0;    // energy of the zero field: E^T <A> E (primal) or E^T <A^-1> E (dual)
-  double esum;       // sum of the energy decrements alpha_j gamma_j so far
+  double esum;       // energy0 minus the energy of the iterate: decrease to a given x0 plus the
+                     // decrements alpha_j gamma_j so far
   double edec[4];    // the last four decrements
+  double mu;         // guaranteed rule: lower bound on the spectrum of the operator (0: none)
+  double phi[2];     // guaranteed rule: Gauss-Radau factor, remaining energy <= gamma phi
+};
+
+// Stopping rule of a solve: 0 residual; 1 residual or extrapolated energy;
+// 2 residual or guaranteed energy bound.  a_min / a_max: bounds on the
+// pointwise eigenvalues of the coefficient given by the caller (0: none).
+struct StopCfg {
+  int rule = 0;
+  double etol = 0.0, a_min = 0.0, a_max = 0.0;
 };
 
 // End-of-solve summary of one (unit, load): sum of the residual partials and the CG scalars.
@@ -134,8 +145,14 @@ hipError_t launch_line_fft(Cx<R>* data, int outer, int Lm, int inner, const Plan
 
 hipError_t launch_rhs(const Geo& g, const UnitDev* units, int nunits, hipStream_t st);
 hipError_t launch_init_scal(const Geo& g, const UnitDev* units, int nunits, int* iter_base, double tol, int maxit,
-                            int stop, double etol, hipStream_t st);
+                            int stop, double etol, int mu_parts, double mu_user, hipStream_t st);
+// Per unit: partial minima over the doubled grid of the smallest eigenvalue of
+// the coefficient (the unit's own, primal or dual), nparts of them in part_q.
+hipError_t launch_coef_min_eig(bool fp32, const Geo& g, const UnitDev* units, int nunits, int nparts,
+                               hipStream_t st);
 hipError_t launch_start_vectors(const Geo& g, const UnitDev* units, int nunits, int have_x0, hipStream_t st);
+// After the residual of a given start field: the energy decrease from the zero field to it (CgScal::esum).
+hipError_t launch_start_energy(const Geo& g, const UnitDev* units, int nunits, hipStream_t st);
 hipError_t launch_symmetrize(const Geo& g, const Cx<double>* src, Cx<double>* dst, int m, hipStream_t st);
 hipError_t launch_advance(const Geo& g, const UnitDev* units, int nunits, int* iter_base, int step,
                           int* active_out, hipStream_t st);

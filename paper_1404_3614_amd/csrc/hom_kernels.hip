@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void k_last(Geo g, const UnitDev* __restric
         if (act) {
           const double gam = wave_sum_arr(U.part_g + (size_t)w * g.nbF, g.nbF);
           const bool bad = !(gam == gam) || gam > 1e300;
-          const bool conv = sqrt(gam) <= sc->tol * sc->normE || (sc->stop && energy_converged(sc, it));
+          const bool conv = stop_test(sc, it, gam, blockIdx.x == 0 && lane == 0);
           if (bad || conv || it >= sc->maxit) {
             act = 0;
             if (blockIdx.x == 0 && lane == 0) {
@@ -650,8 +650,79 @@ __global__ void k_start(Geo g, const UnitDev* __restrict__ units, int have_x0) {
   }
 }
 
+// Energy of a given start field x0 relative to the zero field.  With
+// a(E + x, E + x) = e0 - 2 <x, b> + <x, C x> (b = -G A E, so that a(E, x) =
+// -<x, b>), the energy is e0 - <x, b + r> for r = b - C x.  The decrease
+// <x0, b + r0> is stored as the starting sum of the decrements, so energy0 -
+// esum is the energy of the iterate from the start on.  One block per unit,
+// loads in turn, sums in a fixed order.
+__global__ void k_start_energy(Geo g, const UnitDev* __restrict__ units) {
+  __shared__ double s_red[kBlock / 64];
+  const UnitDev& U = units[blockIdx.x];
+  const size_t n = (size_t)g.m * g.S;
+  const int plane = g.N[1] * g.N[2];
+  for (int l = 0; l < g.L; ++l) {
+    double acc = 0.0;
+    for (size_t t = threadIdx.x; t < n; t += kBlock) {
+      const int h0 = (int)((t / plane) % g.H0);
+      const Cx<double> xv = U.x[l][t], bv = U.b[l][t], rv = U.r[l][t];
+      acc += ((h0 == 0) ? 1.0 : 2.0) * (xv.x * (bv.x + rv.x) + xv.y * (bv.y + rv.y));
+    }
+    const double s = block_sum(acc, s_red);
+    if (threadIdx.x == 0) U.sc[l].esum = s;
+  }
+}
+
+// Smallest eigenvalue of a symmetric coefficient matrix (component order xx,
+// yy(, zz), xy(, xz, yz)), lowered by a small multiple of its scale so that
+// rounding keeps it below the exact value.  3x3: trigonometric solution of
+// the characteristic cubic (Smith 1961), whose angle loses up to half the
+// digits near a double eigenvalue, hence the larger margin there.
+__device__ double sym_min_eig(const double* c, int nc, int d) {
+  if (nc == 1) return c[0] - 1e-14 * fabs(c[0]);
+  if (d == 2) {
+    const double m = 0.5 * (c[0] + c[1]), h = 0.5 * (c[0] - c[1]);
+    const double r = sqrt(h * h + c[2] * c[2]);
+    return m - r - 1e-12 * (fabs(m) + r);
+  }
+  const double q = (c[0] + c[1] + c[2]) / 3.0;
+  const double a = c[0] - q, b = c[1] - q, e = c[2] - q;
+  const double off = c[3] * c[3] + c[4] * c[4] + c[5] * c[5];
+  const double p = sqrt((a * a + b * b + e * e + 2.0 * off) / 6.0);
+  if (!(p > 0.0)) return q - 1e-12 * fabs(q);
+  const double ip = 1.0 / p;
+  const double B00 = a * ip, B11 = b * ip, B22 = e * ip, B01 = c[3] * ip, B02 = c[4] * ip, B12 = c[5] * ip;
+  double r = 0.5 * (B00 * (B11 * B22 - B12 * B12) - B01 * (B01 * B22 - B12 * B02) + B02 * (B01 * B12 - B11 * B02));
+  r = fmin(1.0, fmax(-1.0, r));
+  const double ang = acos(r) / 3.0;
+  return q + 2.0 * p * cos(ang + 2.0943951023931957) - 1e-6 * (fabs(q) + 3.0 * p);
+}
+
+template <typename R>
+__global__ void k_coef_min_eig(Geo g, const UnitDev* __restrict__ units) {
+  __shared__ double s_min[kBlock / 64];
+  const UnitDev& U = units[blockIdx.z];
+  const R* __restrict__ coef = static_cast<const R*>(U.coef);
+  const size_t npts = (size_t)g.M[0] * g.M[1] * g.M[2];
+  double mn = INFINITY;
+  for (size_t t = blockIdx.x * (size_t)kBlock + threadIdx.x; t < npts; t += (size_t)gridDim.x * kBlock) {
+    double c[6];
+    for (int k = 0; k < g.nc; ++k) c[k] = (double)coef[(size_t)k * npts + t];
+    mn = fmin(mn, sym_min_eig(c, g.nc, g.d));
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) mn = fmin(mn, __shfl_down(mn, off, 64));
+  if ((threadIdx.x & 63) == 0) s_min[threadIdx.x >> 6] = mn;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double r = s_min[0];
+    for (int i = 1; i < kBlock / 64; ++i) r = fmin(r, s_min[i]);
+    U.part_q[blockIdx.x] = r;
+  }
+}
+
 __global__ void k_init_scal(Geo g, const UnitDev* __restrict__ units, int nunits, int* iter_base, double tol,
-                            int maxit, int stop, double etol) {
+                            int maxit, int stop, double etol, int mu_parts, double mu_user) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u == 0 && iter_base) *iter_base = 0;
   if (u >= nunits) return;
@@ -688,6 +759,15 @@ __global__ void k_init_scal(Geo g, const UnitDev* __restrict__ units, int nunits
     sc->energy0 = en;
     sc->esum = 0.0;
     for (int j = 0; j < 4; ++j) sc->edec[j] = 0.0;
+    // both the caller's bound and the doubled-grid minimum bound the spectrum from below
+    double mu = mu_user;
+    if (mu_parts > 0) {
+      double gm = INFINITY;
+      for (int q = 0; q < mu_parts; ++q) gm = fmin(gm, U.part_q[q]);
+      mu = fmax(mu, gm);
+    }
+    sc->mu = (mu > 0.0) ? mu : 0.0;
+    sc->phi[0] = sc->phi[1] = (mu > 0.0) ? 1.0 / mu : INFINITY;
   }
 }
 
@@ -982,15 +1062,30 @@ hipError_t launch_rhs(const Geo& g, const UnitDev* units, int nunits, hipStream_
   return hipGetLastError();
 }
 
+hipError_t launch_start_energy(const Geo& g, const UnitDev* units, int nunits, hipStream_t st) {
+  hipLaunchKernelGGL(k_start_energy, dim3(nunits), dim3(kBlock), 0, st, g, units);
+  return hipGetLastError();
+}
+
 hipError_t launch_start_vectors(const Geo& g, const UnitDev* units, int nunits, int have_x0, hipStream_t st) {
   hipLaunchKernelGGL(k_start, dim3(grid_for((size_t)g.m * g.S), 1, nunits), dim3(kBlock), 0, st, g, units, have_x0);
   return hipGetLastError();
 }
 
 hipError_t launch_init_scal(const Geo& g, const UnitDev* units, int nunits, int* iter_base, double tol, int maxit,
-                            int stop, double etol, hipStream_t st) {
+                            int stop, double etol, int mu_parts, double mu_user, hipStream_t st) {
   hipLaunchKernelGGL(k_init_scal, dim3((nunits + kBlock - 1) / kBlock), dim3(kBlock), 0, st, g, units, nunits,
-                     iter_base, tol, maxit, stop, etol);
+                     iter_base, tol, maxit, stop, etol, mu_parts, mu_user);
+  return hipGetLastError();
+}
+
+hipError_t launch_coef_min_eig(bool fp32, const Geo& g, const UnitDev* units, int nunits, int nparts,
+                               hipStream_t st) {
+  if (nparts < 1) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_coef_min_eig<float>, dim3(nparts, 1, nunits), dim3(kBlock), 0, st, g, units);
+  else
+    hipLaunchKernelGGL(k_coef_min_eig<double>, dim3(nparts, 1, nunits), dim3(kBlock), 0, st, g, units);
   return hipGetLastError();
 }
 

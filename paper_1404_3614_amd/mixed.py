@@ -20,9 +20,10 @@ from . import api
 
 
 class MixedSolver:
-    def __init__(self, precision="mixed", concurrent=True):
+    def __init__(self, precision="mixed", concurrent=True, stop="residual", etol=None, a_min=0.0, a_max=0.0):
         self.precision = precision
         self.concurrent = concurrent
+        self.stop = (stop, etol, a_min, a_max)   # Batch.set_stop arguments of every class
         self.classes = {}
 
     def _class(self, key, count, coefs):
@@ -33,6 +34,7 @@ class MixedSolver:
             probs = [api.Problem(d, N, Y, Ah, Bh, precision=self.precision, ncoef=nc, stream=stream)
                      for (Ah, Bh) in coefs]
             cls = dict(probs=probs, batch=api.Batch(probs), stream=stream)
+            cls["batch"].set_stop(*self.stop)
             # tile shapes are chosen now, on this thread, before classes run side by side
             for dual in (False, True):
                 cls["batch"].tuning(dual, d)
