@@ -138,28 +138,119 @@ def pass_bytes(pb, nload):
     return dict(first=6 * vec + rowbuf, apply=apply_bytes(pb, nload), last=rowbuf + 5 * vec)
 
 
-# FP32 flops of the register DFTs as written (a multiply-add counts 2): radix-5 and
-# radix-3 butterflies, compile-time rotations inside composite DFTs, run-time
-# twiddles between the two steps of a four-step transform
-DFT_FLOPS = {1: 0, 3: 16, 5: 48}
+# FP32 flops of the column pass as executed (a multiply-add counts 2).  The
+# register DFTs are built as small expression graphs with the same zero
+# propagation and dead-output removal as the kernels: inputs of the first
+# inverse DFT that lie outside Z_N are zero, outputs of the last forward DFT
+# outside Z_N are dropped.  Costs: complex add/sub 2, scale 2, multiply-add 4,
+# compile-time rotation 6, run-time twiddle 6, multiply by i 0.
 SPLIT = {9: (3, 3), 25: (5, 5), 81: (9, 9), 125: (25, 5), 625: (25, 25)}
 
 
-def dft_flops(n):
-    if n in DFT_FLOPS:
-        return DFT_FLOPS[n]
-    a, b = SPLIT[n]
-    return b * dft_flops(a) + 6 * (a - 1) * (b - 1) + a * dft_flops(b)
+class _Dag:
+    def __init__(self):
+        self.cost, self.args = [], []
+
+    def node(self, cost, *args):
+        self.cost.append(cost)
+        self.args.append(args)
+        return len(self.cost) - 1
+
+    def add(self, a, b, sub=False):
+        if a is None and b is None:
+            return None
+        if a is None:
+            return b if not sub else self.node(0, b)      # a negation folds into later operations
+        if b is None:
+            return a
+        return self.node(2, a, b)
+
+    def scl(self, a):
+        return None if a is None else self.node(2, a)
+
+    def axpy(self, acc, t):
+        if t is None:
+            return acc
+        if acc is None:
+            return self.node(2, t)
+        return self.node(4, acc, t)
+
+    def count(self, outs):
+        seen, stack, total = set(), [o for o in outs if o is not None], 0
+        while stack:
+            n = stack.pop()
+            if n in seen:
+                continue
+            seen.add(n)
+            total += self.cost[n]
+            stack.extend(self.args[n])
+        return total
+
+
+def _dft(g, x):
+    n = len(x)
+    if n == 1:
+        return list(x)
+    if n == 3:
+        t = g.add(x[1], x[2])
+        m = g.axpy(x[0], t)
+        j = g.scl(g.add(x[1], x[2], sub=True))
+        return [g.add(x[0], t), g.add(m, j), g.add(m, j, sub=True)]
+    if n == 5:
+        t1, t2 = g.add(x[1], x[4]), g.add(x[2], x[3])
+        t3, t4 = g.add(x[1], x[4], sub=True), g.add(x[2], x[3], sub=True)
+        b1 = g.axpy(g.axpy(x[0], t1), t2)
+        b2 = g.axpy(g.axpy(x[0], t1), t2)
+        j1 = g.axpy(g.scl(t3), t4)
+        j2 = g.axpy(g.scl(t3), t4)
+        return [g.add(x[0], g.add(t1, t2)), g.add(b1, j1), g.add(b2, j2), g.add(b2, j2, sub=True),
+                g.add(b1, j1, sub=True)]
+    n1, n2 = SPLIT[n]
+    t = {}
+    for b in range(n2):
+        a = _dft(g, [x[n2 * i + b] for i in range(n1)])
+        for k1 in range(n1):
+            t[b, k1] = a[k1] if (b * k1) % n == 0 or a[k1] is None else g.node(6, a[k1])
+    out = [None] * n
+    for k1 in range(n1):
+        bb = _dft(g, [t[b, k1] for b in range(n2)])
+        for k2 in range(n2):
+            out[k1 + n1 * k2] = bb[k2]
+    return out
+
+
+def _dead_row(M, n1):
+    a, b = SPLIT[M]
+    h = (M + 1) // 2 // 2
+    return b * n1 > h and b * n1 + b - 1 < M - h
+
+
+def column_line_flops(M):
+    """Flops of one line as executed (inverse transform, forward transform,
+    run-time twiddles; no coefficient), and those of the unpruned transforms."""
+    a, b = SPLIT[M]
+
+    def cnt(ins, keep=None):
+        g = _Dag()
+        out = _dft(g, [g.node(0) if i else None for i in ins])
+        return g.count([o for i, o in enumerate(out) if keep is None or keep[i]])
+
+    live = [not _dead_row(M, i) for i in range(a)]
+    inv_first, fwd_last = cnt(live), cnt([True] * a, live)
+    full_a, full_b = cnt([True] * a), cnt([True] * b)
+    twiddles = 6 * M
+    pruned = b * inv_first + a * full_b + a * full_b + b * fwd_last + 2 * twiddles
+    return pruned, 2 * (b * full_a + a * full_b) + 2 * twiddles
 
 
 def apply_flops(pb, nload):
-    """Algorithmic FP32 flops per unit of the 2D column pass: per point of the
-    row axis and pack, an inverse and a forward length-M0 transform and the
-    coefficient product (2 flops per complex value, isotropic)."""
+    """FP32 flops per unit of the 2D column pass as executed: per point of the
+    row axis and pack, the pruned inverse and forward length-M0 transforms and
+    the coefficient product (2 flops per complex value isotropic, 6 otherwise)."""
     M = [2 * n - 1 for n in pb.N]
     P = (nload * pb.d + 1) // 2
     coef = 2 if pb.ncoef == 1 else 6
-    return M[-1] * P * (2 * dft_flops(M[0]) + coef * M[0])
+    return M[-1] * P * (column_line_flops(M[0])[0] + coef * M[0])
 
 
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 256 CUs x 4 SIMD x 16 lanes x FMA at 2.4 GHz (no packed FP32)

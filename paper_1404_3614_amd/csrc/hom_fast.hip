@@ -41,6 +41,49 @@ __device__ __forceinline__ int kept(int pos) {
   return pos <= H ? pos : (pos >= M - H ? pos - (M - N) : -1);
 }
 
+// Rows n1 of the four-step layout (positions B n1 + q, q < B) that lie
+// outside Z_N for every thread q: the first register DFT of an inverse
+// transform reads zeros there, and the last register DFT of a forward
+// transform produces values that are dropped.  Both are known when the
+// kernel is compiled, so the pruned work is removed.
+template <int M>
+constexpr bool dead_row(int n1) {
+  return Cfg<M>::B * n1 > Cfg<M>::H && Cfg<M>::B * n1 + Cfg<M>::B - 1 < M - Cfg<M>::H;
+}
+// Global-memory access at a 32-bit byte offset from a block-uniform base:
+// the base stays in scalar registers and the access is a global (not flat)
+// instruction with a 32-bit vector offset.  Callers keep every buffer so
+// accessed below 4 GiB.
+typedef __attribute__((address_space(1))) unsigned char gbyte;
+template <typename T>
+__device__ __forceinline__ T gld(const void* base, unsigned boff) {
+  return *reinterpret_cast<const __attribute__((address_space(1))) T*>((const gbyte*)base + boff);
+}
+template <typename T>
+__device__ __forceinline__ void gst(void* base, unsigned boff, T v) {
+  *reinterpret_cast<__attribute__((address_space(1))) T*>((gbyte*)base + boff) = v;
+}
+// complex FP32 values move as one 64-bit word
+__device__ __forceinline__ Cx<float> gldc(const void* base, unsigned boff) {
+  return __builtin_bit_cast(Cx<float>, gld<unsigned long long>(base, boff));
+}
+__device__ __forceinline__ void gstc(void* base, unsigned boff, Cx<float> v) {
+  gst<unsigned long long>(base, boff, __builtin_bit_cast(unsigned long long, v));
+}
+
+// rows whose positions B n1 + q lie in Z_N for every q < B
+template <int M>
+constexpr bool full_row(int n1) {
+  return Cfg<M>::B * n1 + Cfg<M>::B - 1 <= Cfg<M>::H || Cfg<M>::B * n1 >= M - Cfg<M>::H;
+}
+template <int M>
+constexpr int dead_mask() {
+  int m = 0;
+  for (int n1 = 0; n1 < Cfg<M>::A; ++n1)
+    if (dead_row<M>(n1)) m |= 1 << n1;
+  return m;
+}
+
 }  // namespace
 
 // ============================================================== column pass
@@ -102,6 +145,7 @@ __global__ __launch_bounds__(PB * TP * Cfg<M>::T) void k_apply2_fast(Geo g, cons
                                                                      int cg) {
   constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T, NT = TP * Cfg<M>::T;
   static_assert(PB == 1 || PB == P, "a block holds one pack or all packs");
+  static_assert(sizeof(R) == 4, "FP32 pass");
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem);   // [M]
   const UnitDev& U = units[blockIdx.z];
@@ -122,22 +166,35 @@ __global__ __launch_bounds__(PB * TP * Cfg<M>::T) void k_apply2_fast(Geo g, cons
   const bool ok = (p0 + pt) < npts;
   const Cx<R>* twg = reinterpret_cast<const Cx<R>*>(g.tw[0]);
   for (int i = threadIdx.x; i < M; i += blockDim.x) tw[i] = twg[i];
-  Cx<R>* data = reinterpret_cast<Cx<R>*>(U.bufA);
-  // element (row i0, point p0 + pt, pack pk): pack-major [P][N0][npts] or packs interleaved
-  const size_t rs = g.pmaj ? (size_t)npts : (size_t)npts * P, ps = g.pmaj ? (size_t)g.N[0] * npts : 1;
-  const size_t cbase = g.pmaj ? (size_t)(p0 + pt) : (size_t)(p0 + pt) * P;
-  const R* coef = reinterpret_cast<const R*>(U.coef);
+  void* data = U.bufA;
+  // byte offset of element (row i0, point p0 + pt, pack pk): pack-major [P][N0][npts] or packs interleaved
+  constexpr unsigned es = sizeof(Cx<R>);
+  const unsigned rs = es * (g.pmaj ? (unsigned)npts : (unsigned)npts * P);
+  // threads past the last point load from the last one (nothing of theirs is stored)
+  const int pc = ok ? p0 + pt : npts - 1;
+  const unsigned dbase = es * (g.pmaj ? (unsigned)pc + (unsigned)pk * g.N[0] * npts : (unsigned)pc * P + (unsigned)pk);
+  const void* coef = U.coef;
   __syncthreads();
 
   Cx<R> v[T];
-  // inverse, step 1: thread n2 = q holds x[B n1 + n2] (zero-padded N -> M)
+  // inverse, step 1: thread n2 = q holds x[B n1 + n2] (zero-padded N -> M); rows
+  // wholly inside or outside Z_N0 need no per-thread test
+  constexpr int N = Cfg<M>::N, H = Cfg<M>::H;
 #pragma unroll
   for (int n1 = 0; n1 < A; ++n1) {
-    const int i0 = (q < B && ok) ? kept<M>(B * n1 + q) : -1;
-    v[n1] = i0 >= 0 ? data[i0 * rs + cbase + pk * ps] : rf::mk<R>(0, 0);
+    const int pos = B * n1 + q;
+    if (dead_row<M>(n1)) {
+      v[n1] = rf::mk<R>(0, 0);
+    } else if (full_row<M>(n1)) {
+      const int i0 = (B * n1 <= H) ? pos : pos - (M - N);
+      v[n1] = (T == B || q < B) ? gldc(data, (unsigned)i0 * rs + dbase) : rf::mk<R>(0, 0);
+    } else {
+      const int i0 = q < B ? kept<M>(pos) : -1;
+      v[n1] = i0 >= 0 ? gldc(data, (unsigned)i0 * rs + dbase) : rf::mk<R>(0, 0);
+    }
   }
   if (q < B) {
-    rf::Dft<R, A, 1>::run(v);
+    rf::Dft<R, A, 1>::template run_z<dead_mask<M>()>(v);
 #pragma unroll
     for (int k1 = 0; k1 < A; ++k1) {
       Cx<R> w = tw[q * k1];
@@ -149,18 +206,16 @@ __global__ __launch_bounds__(PB * TP * Cfg<M>::T) void k_apply2_fast(Geo g, cons
   if (q < A) {
     rf::Dft<R, B, 1>::run(v);
     // thread k1 = q holds u at x0 = q + A k2: the coefficient on the doubled grid
-    if (ok) {
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) {
-        const size_t ci = (size_t)(q + A * k2) * npts + p0 + pt;
-        R a[NC];
+    for (int k2 = 0; k2 < B; ++k2) {
+      const unsigned ci = (unsigned)((q + A * k2) * npts + pc) * (unsigned)sizeof(R);
+      R a[NC];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) a[c] = coef[c * Mtot + ci];
-        const R u[2] = {v[k2].x, v[k2].y};
-        R w[2];
-        coef_mul<R>(2, NC, a, u, w);
-        v[k2] = rf::mk<R>(w[0], w[1]);
-      }
+      for (int c = 0; c < NC; ++c) a[c] = gld<R>(coef, (unsigned)(c * Mtot * sizeof(R)) + ci);
+      const R u[2] = {v[k2].x, v[k2].y};
+      R w[2];
+      coef_mul<R>(2, NC, a, u, w);
+      v[k2] = rf::mk<R>(w[0], w[1]);
     }
     // forward: step over n2 in registers (thread n1 = q), exchange, step over n1
     rf::Dft<R, B, -1>::run(v);
@@ -174,8 +229,14 @@ __global__ __launch_bounds__(PB * TP * Cfg<M>::T) void k_apply2_fast(Geo g, cons
     if (ok) {
 #pragma unroll
       for (int m1 = 0; m1 < A; ++m1) {
-        const int i0 = kept<M>(q + B * m1);
-        if (i0 >= 0) data[i0 * rs + cbase + pk * ps] = v[m1];
+        const int pos = q + B * m1;
+        if (dead_row<M>(m1)) continue;
+        if (full_row<M>(m1)) {
+          gstc(data, (unsigned)((B * m1 <= H) ? pos : pos - (M - N)) * rs + dbase, v[m1]);
+        } else {
+          const int i0 = kept<M>(pos);
+          if (i0 >= 0) gstc(data, (unsigned)i0 * rs + dbase, v[m1]);
+        }
       }
     }
   }
@@ -207,7 +268,7 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply_fast(Geo g, const Unit
   Cx<R> v[P][T];
 #pragma unroll
   for (int n1 = 0; n1 < A; ++n1) {
-    const int i0 = (q < B && ok) ? kept<M>(B * n1 + q) : -1;
+    const int i0 = (q < B && ok && !dead_row<M>(n1)) ? kept<M>(B * n1 + q) : -1;
 #pragma unroll
     for (int pk = 0; pk < P; ++pk) v[pk][n1] = i0 >= 0 ? data[i0 * rowstride + col + pk] : rf::mk<R>(0, 0);
   }
@@ -215,7 +276,7 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply_fast(Geo g, const Unit
 #pragma unroll
   for (int pk = 0; pk < P; ++pk) {
     if (q < B) {
-      rf::Dft<R, A, 1>::run(v[pk]);
+      rf::Dft<R, A, 1>::template run_z<dead_mask<M>()>(v[pk]);
 #pragma unroll
       for (int k1 = 0; k1 < A; ++k1) {
         Cx<R> w = tw[q * k1];
@@ -270,6 +331,7 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_apply_fast(Geo g, const Unit
   if (q < B && ok) {
 #pragma unroll
     for (int m1 = 0; m1 < A; ++m1) {
+      if (dead_row<M>(m1)) continue;
       const int i0 = kept<M>(q + B * m1);
       if (i0 >= 0)
 #pragma unroll
@@ -306,12 +368,12 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_mid_fast(Geo g, const UnitDe
     // thread n2 = q holds x[B n1 + n2]
 #pragma unroll
     for (int n1 = 0; n1 < A; ++n1) {
-      const int i1 = (q < B && ok) ? kept<M>(B * n1 + q) : -1;
+      const int i1 = (q < B && ok && !dead_row<M>(n1)) ? kept<M>(B * n1 + q) : -1;
       v[n1] = i1 >= 0 ? in[(i0 * N1 + i1) * W + f] : rf::mk<float>(0, 0);
     }
     __syncthreads();
     if (q < B) {
-      rf::Dft<float, A, 1>::run(v);
+      rf::Dft<float, A, 1>::template run_z<dead_mask<M>()>(v);
 #pragma unroll
       for (int k1 = 0; k1 < A; ++k1) {
         Cx<float> w = tw[q * k1];
@@ -347,6 +409,7 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_mid_fast(Geo g, const UnitDe
       if (ok) {
 #pragma unroll
         for (int m1 = 0; m1 < A; ++m1) {
+          if (dead_row<M>(m1)) continue;
           const int i1 = kept<M>(q + B * m1);
           if (i1 >= 0) out[(i0 * N1 + i1) * W + f] = v[m1];
         }
@@ -772,11 +835,11 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_first_fast(Geo g, const
     Cx<R>* sp = stage + ((size_t)grp * P + pk) * M;
     if (live && q < B) {
 #pragma unroll
-      for (int n1 = 0; n1 < A; ++n1) v[n1] = sp[B * n1 + q];
+      for (int n1 = 0; n1 < A; ++n1) v[n1] = dead_row<M>(n1) ? rf::mk<R>(0, 0) : sp[B * n1 + q];
     }
     __syncthreads();
     if (live && q < B) {
-      rf::Dft<R, A, 1>::run(v);
+      rf::Dft<R, A, 1>::template run_z<dead_mask<M>()>(v);
 #pragma unroll
       for (int k1r = 0; k1r < A; ++k1r) {
         Cx<R> w = tw[q * k1r];
@@ -898,7 +961,8 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
     __syncthreads();
     if (live && q < B) {
 #pragma unroll
-      for (int m1 = 0; m1 < A; ++m1) sp[q + B * m1] = v[pk][m1];
+      for (int m1 = 0; m1 < A; ++m1)
+        if (!dead_row<M>(m1)) sp[q + B * m1] = v[pk][m1];
     }
   }
   __syncthreads();
@@ -1145,6 +1209,10 @@ bool fast_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t s
   if (std::getenv("HOM_NO_FAST")) return false;
   const int M = g.M[0], D = g.d, P = g.P, NC = g.nc;
   if (!apply_supported(M, D, P, NC)) return false;
+  // the 2D column pass addresses its buffers with 32-bit byte offsets
+  if (D == 2 && ((size_t)g.N[0] * g.M[2] * P * sizeof(Cx<float>) >= (size_t(1) << 32) ||
+                 (size_t)NC * M * g.M[2] * sizeof(float) >= (size_t(1) << 32)))
+    return false;
 #define HOM_AP(MM, DD, PP, CC)                                      \
   if (M == MM && D == DD && P == PP && NC == CC) {                 \
     *err = run_apply<MM, DD, PP, CC>(g, units, n, cg, st);         \

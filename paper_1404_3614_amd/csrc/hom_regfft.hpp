@@ -71,50 +71,131 @@ __device__ __forceinline__ Cx<R> rot(Cx<R> a) {
   }
 }
 
-// ---- prime radices, in place, natural order; S = -1 forward, +1 inverse
-template <typename R, int S>
-__device__ __forceinline__ void dft3(Cx<R>& a0, Cx<R>& a1, Cx<R>& a2) {
-  const R s3 = (R)(S * 0.86602540378443864676);
-  Cx<R> t = add(a1, a2), d = sub(a1, a2);
-  Cx<R> m = sub(a0, scl(t, (R)0.5));
-  Cx<R> j = mk(-d.y * s3, d.x * s3);
-  a0 = add(a0, t);
-  a1 = add(m, j);
-  a2 = sub(m, j);
+// ---- compile-time zero tracking.  ZC<R, true> is a value known to be zero
+// when the kernel is compiled (an input of a pruned transform): operations on
+// it fold away instead of adding or scaling zeros, which the compiler may not
+// remove itself (x + 0 is not x for x = -0).
+template <typename R, bool Z>
+struct ZC {
+  Cx<R> v;
+};
+template <typename R, bool A, bool B>
+__device__ __forceinline__ ZC<R, A && B> zadd(ZC<R, A> a, ZC<R, B> b) {
+  if constexpr (A && B) return {};
+  else if constexpr (A) return {b.v};
+  else if constexpr (B) return {a.v};
+  else return {add(a.v, b.v)};
+}
+template <typename R, bool A, bool B>
+__device__ __forceinline__ ZC<R, A && B> zsub(ZC<R, A> a, ZC<R, B> b) {
+  if constexpr (A && B) return {};
+  else if constexpr (A) return {mk(-b.v.x, -b.v.y)};
+  else if constexpr (B) return {a.v};
+  else return {sub(a.v, b.v)};
+}
+template <typename R, bool A>
+__device__ __forceinline__ ZC<R, A> zscl(ZC<R, A> a, R c) {
+  if constexpr (A) return {};
+  else return {scl(a.v, c)};
+}
+template <typename R>
+__device__ __forceinline__ R fmx(R a, R b, R c) {
+  if constexpr (sizeof(R) == 4) return __builtin_fmaf(a, b, c);
+  else return __builtin_fma(a, b, c);
+}
+// acc + c t, as one fused multiply-add per component
+template <typename R, bool A, bool B>
+__device__ __forceinline__ ZC<R, A && B> zaxpy(ZC<R, A> acc, R c, ZC<R, B> t) {
+  if constexpr (B) return {acc.v};
+  else if constexpr (A) return {scl(t.v, c)};
+  else return {mk(fmx(c, t.v.x, acc.v.x), fmx(c, t.v.y, acc.v.y))};
+}
+// multiply by i
+template <typename R, bool A>
+__device__ __forceinline__ ZC<R, A> zmuli(ZC<R, A> a) {
+  if constexpr (A) return {};
+  else return {mk(-a.v.y, a.v.x)};
+}
+template <typename R, bool A>
+__device__ __forceinline__ Cx<R> zval(ZC<R, A> a) {
+  if constexpr (A) return mk((R)0, (R)0);
+  else return a.v;
 }
 
-template <typename R, int S>
+// ---- prime radices, in place, natural order; S = -1 forward, +1 inverse.
+// Z: bit j set when input j is known to be zero.
+template <typename R, int S, int Z = 0>
+__device__ __forceinline__ void dft3(Cx<R>& a0, Cx<R>& a1, Cx<R>& a2) {
+  const R s3 = (R)(S * 0.86602540378443864676);
+  const ZC<R, (Z & 1) != 0> x0{a0};
+  const ZC<R, (Z & 2) != 0> x1{a1};
+  const ZC<R, (Z & 4) != 0> x2{a2};
+  const auto t = zadd(x1, x2);
+  const auto m = zaxpy(x0, (R)-0.5, t);
+  const auto j = zmuli(zscl(zsub(x1, x2), s3));
+  a0 = zval(zadd(x0, t));
+  a1 = zval(zadd(m, j));
+  a2 = zval(zsub(m, j));
+}
+
+template <typename R, int S, int Z = 0>
 __device__ __forceinline__ void dft5(Cx<R>& a0, Cx<R>& a1, Cx<R>& a2, Cx<R>& a3, Cx<R>& a4) {
   const R c1 = (R)0.30901699437494742410, c2 = (R)-0.80901699437494742410;
   const R s1 = (R)(S * 0.95105651629515357212), s2 = (R)(S * 0.58778525229247312917);
-  Cx<R> t1 = add(a1, a4), t2 = add(a2, a3), t3 = sub(a1, a4), t4 = sub(a2, a3);
-  Cx<R> b1 = add(a0, add(scl(t1, c1), scl(t2, c2)));
-  Cx<R> b2 = add(a0, add(scl(t1, c2), scl(t2, c1)));
-  Cx<R> e1 = add(scl(t3, s1), scl(t4, s2));
-  Cx<R> e2 = sub(scl(t3, s2), scl(t4, s1));
-  a0 = add(a0, add(t1, t2));
-  Cx<R> j1 = mk(-e1.y, e1.x), j2 = mk(-e2.y, e2.x);
-  a1 = add(b1, j1);
-  a4 = sub(b1, j1);
-  a2 = add(b2, j2);
-  a3 = sub(b2, j2);
+  const ZC<R, (Z & 1) != 0> x0{a0};
+  const ZC<R, (Z & 2) != 0> x1{a1};
+  const ZC<R, (Z & 4) != 0> x2{a2};
+  const ZC<R, (Z & 8) != 0> x3{a3};
+  const ZC<R, (Z & 16) != 0> x4{a4};
+  const auto t1 = zadd(x1, x4);
+  const auto t2 = zadd(x2, x3);
+  const auto t3 = zsub(x1, x4);
+  const auto t4 = zsub(x2, x3);
+  const auto b1 = zaxpy(zaxpy(x0, c1, t1), c2, t2);
+  const auto b2 = zaxpy(zaxpy(x0, c2, t1), c1, t2);
+  const auto j1 = zmuli(zaxpy(zscl(t3, s1), s2, t4));
+  const auto j2 = zmuli(zaxpy(zscl(t3, s2), -s1, t4));
+  a0 = zval(zadd(x0, zadd(t1, t2)));
+  a1 = zval(zadd(b1, j1));
+  a4 = zval(zsub(b1, j1));
+  a2 = zval(zadd(b2, j2));
+  a3 = zval(zsub(b2, j2));
 }
 
+// Dft<R, N, S>::run(v): in-place DFT of v[0..N-1]; run_z<Z>: the same with
+// the inputs of mask Z known to be zero (their registers are not read).
 template <typename R, int N, int S>
 struct Dft;
 
 template <typename R, int S>
 struct Dft<R, 1, S> {
+  template <int Z = 0>
+  static __device__ __forceinline__ void run_z(Cx<R>* v) {
+    if constexpr (Z & 1) v[0] = mk((R)0, (R)0);
+  }
   static __device__ __forceinline__ void run(Cx<R>* v) { (void)v; }
 };
 template <typename R, int S>
 struct Dft<R, 3, S> {
-  static __device__ __forceinline__ void run(Cx<R>* v) { dft3<R, S>(v[0], v[1], v[2]); }
+  template <int Z = 0>
+  static __device__ __forceinline__ void run_z(Cx<R>* v) { dft3<R, S, Z>(v[0], v[1], v[2]); }
+  static __device__ __forceinline__ void run(Cx<R>* v) { run_z<0>(v); }
 };
 template <typename R, int S>
 struct Dft<R, 5, S> {
-  static __device__ __forceinline__ void run(Cx<R>* v) { dft5<R, S>(v[0], v[1], v[2], v[3], v[4]); }
+  template <int Z = 0>
+  static __device__ __forceinline__ void run_z(Cx<R>* v) { dft5<R, S, Z>(v[0], v[1], v[2], v[3], v[4]); }
+  static __device__ __forceinline__ void run(Cx<R>* v) { run_z<0>(v); }
 };
+
+// bits n1 < N1 of mask Z at positions N2 n1 + n2 (the inputs of one first-step DFT)
+template <int Z, int N1, int N2, int n2>
+constexpr int sub_mask() {
+  int m = 0;
+  for (int n1 = 0; n1 < N1; ++n1)
+    if ((Z >> (N2 * n1 + n2)) & 1) m |= 1 << n1;
+  return m;
+}
 
 // composite N = N1 * N2: n = N2 n1 + n2, k = k1 + N1 k2
 template <typename R, int N1, int N2, int S>
@@ -124,20 +205,22 @@ struct DftComp {
     a[k1] = rot<R, S, n2 * k1, N1 * N2>(a[k1]);
     if constexpr (k1 + 1 < N1) twid<n2, k1 + 1>(a);
   }
-  template <int n2>
+  template <int n2, int Z>
   static __device__ __forceinline__ void step1(const Cx<R>* v, Cx<R>* t) {
     Cx<R> a[N1];
+    constexpr int zm = sub_mask<Z, N1, N2, n2>();
 #pragma unroll
-    for (int n1 = 0; n1 < N1; ++n1) a[n1] = v[N2 * n1 + n2];
-    Dft<R, N1, S>::run(a);
+    for (int n1 = 0; n1 < N1; ++n1) a[n1] = ((zm >> n1) & 1) ? mk((R)0, (R)0) : v[N2 * n1 + n2];
+    Dft<R, N1, S>::template run_z<zm>(a);
     twid<n2, 0>(a);
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) t[n2 * N1 + k1] = a[k1];
-    if constexpr (n2 + 1 < N2) step1<n2 + 1>(v, t);
+    if constexpr (n2 + 1 < N2) step1<n2 + 1, Z>(v, t);
   }
-  static __device__ __forceinline__ void run(Cx<R>* v) {
+  template <int Z = 0>
+  static __device__ __forceinline__ void run_z(Cx<R>* v) {
     Cx<R> t[N1 * N2];
-    step1<0>(v, t);
+    step1<0, Z>(v, t);
 #pragma unroll
     for (int k1 = 0; k1 < N1; ++k1) {
       Cx<R> b[N2];
@@ -148,6 +231,7 @@ struct DftComp {
       for (int k2 = 0; k2 < N2; ++k2) v[k1 + N1 * k2] = b[k2];
     }
   }
+  static __device__ __forceinline__ void run(Cx<R>* v) { run_z<0>(v); }
 };
 
 template <typename R, int S>
