@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-cells", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true", help="skip the one-cell-at-a-time comparison leg")
+    ap.add_argument("--no-energy", action="store_true", help="skip the guaranteed-energy-rule leg")
     ap.add_argument("--tiles", default=None,
                     help="pin the FP32 tile shape: row_pairs,row_threads,apply_points,apply_half_exchange,"
                          "apply_all_packs")
@@ -352,7 +353,7 @@ def main():
     # the guaranteed energy rule on the same steps (when the residual rule set the value):
     # bounds within a relative etol of their converged values, in fewer iterations
     energy_leg = None
-    if args.stop == "residual":
+    if args.stop == "residual" and not args.no_energy:
         batch.set_stop("guaranteed", args.etol, a_min, a_max)
         for _ in range(args.warmup):
             step()
@@ -425,7 +426,7 @@ def main():
                   bytes_model="pass_bytes() in bench.py; units per launch = active cells of the batch",
                   timed_region="second timed pass of the same steps, kernels launched directly by "
                                "hipExtLaunchKernelGGL with start/stop HIP events on the library stream",
-                  value_events_pass=round(B * args.steps / dt_events, 3))
+                  value_events_pass=round(B * args.steps / dt_events, 3), unit_launches=unit_launches)
     if dom == "apply":
         # the column pass issues vector ALU work for most of its duration (its FP32
         # transforms): it is measured against the FP32 vector peak without packed
