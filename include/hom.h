@@ -74,6 +74,13 @@ typedef struct {
                          right-hand side and the bound quadrature in FP64 */
   int32_t ncoef;      /* 1: isotropic a(x) I.  d(d+1)/2: symmetric matrix, components
                          ordered xx, yy, (zz), xy, (xz, yz) */
+  int32_t M[3];       /* quadrature grid per axis.  0: the doubled grid 2N - 1 of Lemma
+                         integral_eval_double_grid.  Otherwise an odd M >= 2N - 1 whose
+                         factors are 3 and 5: the product of two trigonometric polynomials
+                         of Z_N with the series of A on Z_M has no frequency that aliases
+                         onto Z_N on such a grid either, so the quadrature stays exact; it
+                         serves grids N whose 2N - 1 has other factors (M[2] ignored for
+                         d = 2).  Every "doubled grid" below means this grid. */
 } hom_desc;
 
 typedef struct {
@@ -182,6 +189,54 @@ hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n
  * out: device, Ahat layout of hom_setup. */
 hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t* phase, int32_t nphase,
                            const double* phase_A, int32_t inverse, void* out, void* stream);
+
+/* ---- GaNi: Galerkin approximation with numerical integration (Def. GaNi,
+ * Lemma FD_of_GaNi) and the paper's Algorithm (Sec. 7.2): the minimisers are
+ * computed with the trapezoidal rule on the N grid, whose fully discrete
+ * coefficient is the block-diagonal matrix of point values A(x_N^k)
+ * (eq. FD_A_GaNi; the dual uses A^-1(x_N^k), eq. FD_inverse_matrix_equality),
+ * and step (iii) evaluates the guaranteed bounds of those minimisers exactly
+ * (hom_bounds, unchanged).  N-point transforms: every N_a must have factors 3
+ * and 5 only (e.g. the paper's N = 5 3^j); the bounds need the quadrature grid
+ * of hom_desc.M (any odd 3/5-smooth M >= 2N - 1).
+ *
+ * Point values on the N grid, x_a = Y_a k_a / N_a (k in Z_N, eq.
+ * grid_points), of a matrix-inclusion cell (arguments as hom_coef_inclusions)
+ * or of a pixel image (as hom_coef_pixels).  A point belongs to a box iff
+ * |x_a - c_a| < h_a / 2 on every axis, to a ball iff |x - c| < R, with
+ * periodic minimum-image differences: interfaces belong to the matrix.
+ * out: device FP64 [ncoef][N0][N1]([N2]), row-major over the physical axes
+ * (2D: [ncoef][N0][N1]); components as hom_desc.ncoef; inverse = 1 gives the
+ * values of A^-1. */
+hom_status hom_sample_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
+                                 const double* center, const double* size, const double* A_in, int32_t inverse,
+                                 double* out, void* stream);
+hom_status hom_sample_pixels(const hom_desc* desc, const int32_t* P, const int32_t* phase, int32_t nphase,
+                             const double* phase_A, int32_t inverse, double* out, void* stream);
+
+/* Device workspace bytes of hom_set_gani (alignment 256). */
+hom_status hom_gani_workspace_bytes(const hom_desc* desc, size_t* bytes);
+
+/* Switch later solves and hom_apply of pb to GaNi: AN, BN are the point
+ * values of A and of A^-1 (layout of hom_sample_*, device, read during the
+ * call).  ws: device workspace of hom_gani_workspace_bytes bytes, kept until
+ * hom_clear_gani or hom_destroy (it holds the values, their FP32 copies, the
+ * N-point DFT of the values on the stored half of Z_N, which gives the
+ * right-hand side, and twiddles).  The solves then stop and report as before;
+ * the energy in hom_info is the GaNi energy.  Batches reject GaNi problems
+ * (HOM_E_INVALID).  HOM_E_UNSUPPORTED_SIZE when an N_a has other factors. */
+hom_status hom_set_gani(hom_problem* pb, const double* AN, const double* BN, void* ws, size_t ws_bytes);
+
+/* Back to the exact (Ga) operator for later solves. */
+hom_status hom_clear_gani(hom_problem* pb);
+
+/* GaNi homogenized matrices A_{H,N}, B_{H,N} (eq. GaNi): the trapezoidal-rule
+ * energies of primal and dual fields of the unit loads (host arrays of d
+ * device pointers, as hom_bounds), row-major d x d into A_HN and B_HN (host).
+ * For odd grids A_{H,N} = B_{H,N}^-1 at the GaNi minimisers.  Requires GaNi
+ * mode. */
+hom_status hom_gani_matrices(hom_problem* pb, const double* const* primal, const double* const* dual,
+                             double* A_HN, double* B_HN);
 
 /* Per-kernel timing of one operator application (measurement support).
  * Enqueues `reps` launches of each pass of the operator of the primal

@@ -20,7 +20,7 @@ HOM_MIXED = 1
 
 class Desc(C.Structure):
     _fields_ = [("d", C.c_int32), ("N", C.c_int32 * 3), ("Y", C.c_double * 3),
-                ("precision", C.c_int32), ("ncoef", C.c_int32)]
+                ("precision", C.c_int32), ("ncoef", C.c_int32), ("M", C.c_int32 * 3)]
 
 
 class Info(C.Structure):
@@ -92,6 +92,16 @@ EXPORTS = {
     "hom_batch_get_timing": (C.c_int32, [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "hom_set_tuning": (C.c_int32, [C.c_int32]),
     "hom_problem_set_stop": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double]),
+    "hom_sample_inclusions": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                          C.c_int32, C.c_void_p, C.c_void_p]),
+    "hom_sample_pixels": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
+                                      C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p]),
+    "hom_gani_workspace_bytes": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_size_t)]),
+    "hom_set_gani": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
+    "hom_clear_gani": (C.c_int32, [C.c_void_p]),
+    "hom_gani_matrices": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
+                                      C.POINTER(C.c_double)]),
     "hom_batch_set_stop": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double]),
     "hom_batch_solve_pair": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_double, C.c_int32,
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(Info),

@@ -22,15 +22,21 @@ def _dev():
     return torch.device("cuda", torch.cuda.current_device())
 
 
-def _desc(d, N, Y, precision, ncoef):
+def _desc(d, N, Y, precision, ncoef, M=None):
     ds = L.Desc()
     ds.d = d
     for a in range(3):
         ds.N[a] = int(N[a]) if a < d else 1
         ds.Y[a] = float(Y[a]) if a < d else 1.0
+        ds.M[a] = int(M[a]) if (M is not None and a < d) else 0
     ds.precision = {"fp64": L.HOM_FP64, "mixed": L.HOM_MIXED}.get(precision, precision)
     ds.ncoef = ncoef
     return ds
+
+
+def quad_grid(N, M=None):
+    """Quadrature grid per axis: M if given, else the doubled grid 2N - 1."""
+    return tuple(int(m) for m in M) if M is not None else tuple(2 * int(n) - 1 for n in N)
 
 
 def _stream_ptr(stream=None):
@@ -52,9 +58,9 @@ def field_len(d, N, dual, Y=(1, 1, 1)):
     return n.value
 
 
-def workspace_bytes(d, N, Y, precision, ncoef, max_loads):
+def workspace_bytes(d, N, Y, precision, ncoef, max_loads, M=None):
     n = C.c_size_t()
-    ds = _desc(d, N, Y, precision, ncoef)
+    ds = _desc(d, N, Y, precision, ncoef, M)
     L.check(L.load().hom_workspace_bytes(C.byref(ds), int(max_loads), C.byref(n)), "hom_workspace_bytes")
     return n.value
 
@@ -82,11 +88,11 @@ def cell_eig_range(cell):
     return float(ev.min()), float(ev.max())
 
 
-def coef_inclusions(cell, N, ncoef, inverse=False, stream=None):
-    """Fourier coefficients on Z_{2N-1} of a matrix-inclusion cell, on the device."""
+def coef_inclusions(cell, N, ncoef, inverse=False, stream=None, M=None):
+    """Fourier coefficients on Z_M (default M = 2N - 1) of a matrix-inclusion cell, on the device."""
     d = cell.d
-    ds = _desc(d, N, cell.Y, "fp64", ncoef)
-    M = [2 * n - 1 for n in N[:d]]
+    ds = _desc(d, N, cell.Y, "fp64", ncoef, M)
+    M = quad_grid(N[:d], M)
     out = torch.empty((ncoef,) + tuple(M), dtype=torch.complex128, device=_dev())
     n = cell.n
     kind = (C.c_int32 * max(n, 1))(*[0 if k == "rect" else 1 for k in cell.kind])
@@ -104,11 +110,11 @@ def coef_inclusions(cell, N, ncoef, inverse=False, stream=None):
     return out
 
 
-def coef_pixels(cell, N, ncoef, inverse=False, stream=None):
-    """Fourier coefficients on Z_{2N-1} of a pixel/voxel image, on the device."""
+def coef_pixels(cell, N, ncoef, inverse=False, stream=None, M=None):
+    """Fourier coefficients on Z_M (default M = 2N - 1) of a pixel/voxel image, on the device."""
     d = cell.d
-    ds = _desc(d, N, cell.Y, "fp64", ncoef)
-    M = [2 * n - 1 for n in N[:d]]
+    ds = _desc(d, N, cell.Y, "fp64", ncoef, M)
+    M = quad_grid(N[:d], M)
     out = torch.empty((ncoef,) + tuple(M), dtype=torch.complex128, device=_dev())
     P = (C.c_int32 * 3)(*(list(cell.phase.shape) + [1] * (3 - d)))
     ph = np.ascontiguousarray(cell.phase.astype(np.int32).reshape(-1))
@@ -120,20 +126,53 @@ def coef_pixels(cell, N, ncoef, inverse=False, stream=None):
     return out
 
 
-def coef_from_cell(cell, N, ncoef=None, stream=None):
+def sample_cell(cell, N, ncoef=None, inverse=False, stream=None):
+    """Point values of A (or A^-1) at the N-grid points of a cell, on the device
+    (hom_sample_inclusions / hom_sample_pixels): float64 [ncoef][*N]."""
+    d = cell.d
+    N = tuple(int(n) for n in (N if np.iterable(N) else [N] * d))
+    ncoef = cell_ncoef(cell) if ncoef is None else ncoef
+    ds = _desc(d, N, cell.Y, "fp64", ncoef)
+    out = torch.empty((ncoef,) + N, dtype=torch.float64, device=_dev())
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    if hasattr(cell, "phase"):
+        P = (C.c_int32 * 3)(*(list(cell.phase.shape) + [1] * (3 - d)))
+        ph = np.ascontiguousarray(cell.phase.astype(np.int32).reshape(-1))
+        pA = np.ascontiguousarray(np.asarray(cell.phase_A, float).reshape(-1))
+        st = L.load().hom_sample_pixels(C.byref(ds), P, ph.ctypes.data_as(C.POINTER(C.c_int32)), len(cell.phase_A),
+                                        dp(pA), int(inverse), C.c_void_p(out.data_ptr()), _stream_ptr(stream))
+        L.check(st, "hom_sample_pixels")
+        return out
+    n = cell.n
+    kind = (C.c_int32 * max(n, 1))(*[0 if k == "rect" else 1 for k in cell.kind])
+    cen = np.ascontiguousarray(np.array(cell.center, float).reshape(-1) if n else np.zeros(1))
+    siz = np.zeros((max(n, 1), d))
+    for j, (k, s) in enumerate(zip(cell.kind, cell.size)):
+        siz[j, :len(s)] = s
+    siz = np.ascontiguousarray(siz.reshape(-1))
+    Ain = np.ascontiguousarray(np.array(cell.A, float).reshape(-1) if n else np.zeros(1))
+    A0 = np.ascontiguousarray(np.asarray(cell.A0, float).reshape(-1))
+    st = L.load().hom_sample_inclusions(C.byref(ds), dp(A0), n, kind, dp(cen), dp(siz), dp(Ain), int(inverse),
+                                        C.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    L.check(st, "hom_sample_inclusions")
+    return out
+
+
+def coef_from_cell(cell, N, ncoef=None, stream=None, M=None):
     ncoef = cell_ncoef(cell) if ncoef is None else ncoef
     f = coef_pixels if hasattr(cell, "phase") else coef_inclusions
-    return f(cell, N, ncoef, False, stream), f(cell, N, ncoef, True, stream), ncoef
+    return f(cell, N, ncoef, False, stream, M), f(cell, N, ncoef, True, stream, M), ncoef
 
 
 class Problem:
     """One periodic cell on an odd grid N: the doubled-grid coefficients of A
     and A^{-1} live in a workspace tensor; solves return spectral fields."""
 
-    def __init__(self, d, N, Y, Ahat, Bhat, precision="mixed", ncoef=1, max_loads=None, stream=None):
+    def __init__(self, d, N, Y, Ahat, Bhat, precision="mixed", ncoef=1, max_loads=None, stream=None, M=None):
         lib = L.load()
         self.d = d
         self.N = tuple(int(n) for n in N[:d])
+        self.Mq = quad_grid(self.N, None if M is None else tuple(M)[:d])
         self.Y = tuple(float(y) for y in Y[:d])
         self.precision = precision
         self.ncoef = ncoef
@@ -141,8 +180,8 @@ class Problem:
         # a dedicated stream (not the legacy default stream) so that the CG chunks are graph-captured
         self.stream = stream if stream is not None else torch.cuda.Stream()
         self.stream.wait_stream(torch.cuda.current_stream())
-        self.desc = _desc(d, self.N, self.Y, precision, ncoef)
-        nbytes = workspace_bytes(d, self.N, self.Y, precision, ncoef, self.max_loads)
+        self.desc = _desc(d, self.N, self.Y, precision, ncoef, self.Mq)
+        nbytes = workspace_bytes(d, self.N, self.Y, precision, ncoef, self.max_loads, self.Mq)
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=_dev())
         off = (-self.ws.data_ptr()) % 256
         self._ws_ptr = self.ws.data_ptr() + off
@@ -221,7 +260,7 @@ class Problem:
 
     @property
     def M(self):
-        return tuple(2 * n - 1 for n in self.N)
+        return self.Mq
 
     def field_to_grid(self, fields, dual=False):
         """Doubled-grid values (float32, [nload][d][*M]) of field vectors."""
@@ -249,6 +288,35 @@ class Problem:
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_net_input(self.h, C.c_void_p(out.data_ptr())), "hom_net_input")
         return out
+
+    def set_gani(self, AN, BN):
+        """GaNi mode (hom_set_gani): later solves use the point values AN, BN of
+        A and A^-1 on the N grid (device float64 [ncoef][*N])."""
+        n = C.c_size_t()
+        L.check(L.load().hom_gani_workspace_bytes(C.byref(self.desc), C.byref(n)), "hom_gani_workspace_bytes")
+        self.gani_ws = torch.empty(n.value + 256, dtype=torch.uint8, device=_dev())
+        off = (-self.gani_ws.data_ptr()) % 256
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_set_gani(self.h, C.c_void_p(AN.data_ptr()), C.c_void_p(BN.data_ptr()),
+                                      C.c_void_p(self.gani_ws.data_ptr() + off), n.value), "hom_set_gani")
+
+    def set_gani_from_cell(self, cell):
+        """GaNi mode with the point values of a cell (sample_cell)."""
+        AN = sample_cell(cell, self.N, self.ncoef, False, self.stream)
+        BN = sample_cell(cell, self.N, self.ncoef, True, self.stream)
+        self.set_gani(AN, BN)
+
+    def clear_gani(self):
+        L.check(L.load().hom_clear_gani(self.h), "hom_clear_gani")
+
+    def gani_matrices(self, primal, dual):
+        """A_{H,N} and B_{H,N} (hom_gani_matrices) of fields of the unit loads."""
+        A = (C.c_double * 9)()
+        B = (C.c_double * 9)()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_gani_matrices(self.h, _dptrs(primal), _dptrs(dual), A, B), "hom_gani_matrices")
+        d = self.d
+        return np.array(A[:d * d]).reshape(d, d), np.array(B[:d * d]).reshape(d, d)
 
     def set_stop(self, rule="residual", etol=None, a_min=0.0, a_max=0.0):
         """Stopping rule of later solves (hom_problem_set_stop): "residual" (||r|| <= tol ||E||),
@@ -463,10 +531,13 @@ class Batch:
         return out
 
 
-def problem_from_cell(cell, N, precision="mixed", max_loads=None, stream=None):
+def problem_from_cell(cell, N, precision="mixed", max_loads=None, stream=None, M=None):
+    """Problem of a cell on the grid N; M: quadrature grid (default 2N - 1)."""
     N = tuple(int(n) for n in (N if np.iterable(N) else [N] * cell.d))
-    Ah, Bh, nc = coef_from_cell(cell, N, stream=stream)
-    pb = Problem(cell.d, N, cell.Y, Ah, Bh, precision=precision, ncoef=nc, max_loads=max_loads, stream=stream)
+    if M is not None:
+        M = tuple(int(m) for m in (M if np.iterable(M) else [M] * cell.d))
+    Ah, Bh, nc = coef_from_cell(cell, N, stream=stream, M=M)
+    pb = Problem(cell.d, N, cell.Y, Ah, Bh, precision=precision, ncoef=nc, max_loads=max_loads, stream=stream, M=M)
     return pb
 
 

@@ -91,6 +91,22 @@ struct Sizes {
 
 }  // namespace
 
+// GaNi mode of a problem (Def. GaNi, the paper's Algorithm): solves use the
+// trapezoidal rule on the N grid, i.e. point values of A and A^-1 there and
+// N-point transforms; the bounds keep the exact quadrature.  Buffers live in a
+// caller-owned workspace (hom_set_gani).
+struct GaniData {
+  bool on = false;
+  double* coef64[2] = {};          // [nc][Nt] point values of A (primal) and A^-1 (dual)
+  float* coef32[2] = {};           // FP32 copies (mixed precision)
+  Cx<double>* ahat[2] = {};        // [nc][S] N-point DFT of the point values, stored half
+  Cx<double>* tw64[3] = {};
+  Cx<float>* tw32[3] = {};
+  Cx<double>* scratch = nullptr;   // [nc][Nt] complex
+  Plan plan[3] = {};
+  hipGraphExec_t graph[2][kMaxLoads + 1] = {};
+};
+
 struct hom_problem {
   hom_desc desc;
   int max_loads;
@@ -119,6 +135,7 @@ struct hom_problem {
   Tuning tune[2][kMaxLoads + 1];        // tile shapes of the single-problem solves
   bool tuned[2][kMaxLoads + 1];
   StopCfg stop;                         // stopping rule of later solves (hom_problem_set_stop)
+  GaniData gani;
 };
 
 namespace {
@@ -138,7 +155,15 @@ bool fill_sizes(const hom_desc* desc, int max_loads, Sizes* z, Plan* plan) {
   } else {
     for (int a = 0; a < 3; ++a) z->N[a] = Nphys[a];
   }
-  for (int a = 0; a < 3; ++a) z->M[a] = 2 * z->N[a] - 1;
+  // quadrature grid: the doubled grid 2N - 1 unless the caller gives a larger one
+  int Mphys[3] = {desc->M[0], desc->M[1], d == 3 ? desc->M[2] : 0};
+  if (d == 2) {
+    z->M[0] = Mphys[0] ? Mphys[0] : 2 * z->N[0] - 1;
+    z->M[1] = 1;
+    z->M[2] = Mphys[1] ? Mphys[1] : 2 * z->N[2] - 1;
+  } else {
+    for (int a = 0; a < 3; ++a) z->M[a] = Mphys[a] ? Mphys[a] : 2 * z->N[a] - 1;
+  }
   for (int a = 0; a < 3; ++a) {
     if (a == 1 && d == 2) {
       plan[a].n = 0;
@@ -164,8 +189,10 @@ hom_status validate_desc(const hom_desc* desc, int max_loads) {
     if (!(desc->Y[a] > 0.0) || !std::isfinite(desc->Y[a])) return HOM_E_INVALID;
     if (desc->N[a] < 3 || desc->N[a] % 2 == 0) return HOM_E_UNSUPPORTED_SIZE;
     if (desc->N[a] > 4097) return HOM_E_UNSUPPORTED_SIZE;
+    const int Ma = desc->M[a] ? desc->M[a] : 2 * desc->N[a] - 1;
+    if (Ma < 2 * desc->N[a] - 1 || Ma % 2 == 0 || Ma > 8193) return HOM_E_UNSUPPORTED_SIZE;
     Plan pl;
-    if (!smooth35(2 * desc->N[a] - 1, &pl)) return HOM_E_UNSUPPORTED_SIZE;
+    if (!smooth35(Ma, &pl)) return HOM_E_UNSUPPORTED_SIZE;
   }
   return HOM_OK;
 }
@@ -309,9 +336,9 @@ Geo make_geo(const hom_problem* pb, int dual, int L, bool fp32, int P_override =
       g.apHX = tune->apHX;
       g.apAll = tune->apAll;
     }
-    const int G = fast_row_pairs(z.M[2], z.d, L, g.rowG);
+    const int G = fast_row_pairs(z.M[2], z.N[2], z.d, L, g.rowG);
     if (G > 0) g.nbF = g.nbL = (z.Q + G - 1) / G;
-    g.pmaj = (z.d == 2 && G > 0 && fast_apply_supported(z.M[0], z.d, g.P, z.nc)) ? 1 : 0;
+    g.pmaj = (z.d == 2 && G > 0 && z.M[0] == 2 * z.N[0] - 1 && fast_apply_supported(z.M[0], z.d, g.P, z.nc)) ? 1 : 0;
   }
   const size_t cs = fp32 ? sizeof(Cx<float>) : sizeof(Cx<double>);
   const int npts = z.M[1] * z.M[2];
@@ -332,6 +359,31 @@ Geo make_geo(const hom_problem* pb, int dual, int L, bool fp32, int P_override =
     }
   }
   g.invM = 1.0 / (double)z.Mt;
+  return g;
+}
+
+// Geometry of the GaNi operator: the N grid takes the place of the
+// quadrature grid (no padding, no truncation), N-point plans and twiddles;
+// the specialised passes never apply (they keep Z_N of a doubled grid).
+Geo make_geo_gani(const hom_problem* pb, int dual, int L, bool fp32, int P_override = 0) {
+  Geo g = make_geo(pb, dual, L, fp32, P_override, nullptr);
+  const Sizes& z = pb->z;
+  size_t Nt = 1;
+  for (int a = 0; a < 3; ++a) {
+    g.M[a] = z.N[a];
+    g.pl[a] = pb->gani.plan[a];
+    g.tw[a] = fp32 ? (const void*)pb->gani.tw32[a] : (const void*)pb->gani.tw64[a];
+    Nt *= (size_t)z.N[a];
+  }
+  g.rowG = g.rowThreads = g.apTP = g.apHX = g.apAll = 0;
+  g.pmaj = 0;
+  g.nbF = g.nbL = z.Q;
+  const size_t cs = fp32 ? sizeof(Cx<float>) : sizeof(Cx<double>);
+  const int npts = g.M[1] * g.M[2];
+  g.tileA = choose_tileA(g.M[0], npts, g.P, cs, min_radix(g.pl[0]));
+  g.nbA = (npts + g.tileA - 1) / g.tileA;
+  g.tileM = z.d == 3 ? choose_tileM(g.M[1], g.M[2] * g.P, cs, min_radix(g.pl[1])) : 1;
+  g.invM = 1.0 / (double)Nt;
   return g;
 }
 
@@ -365,12 +417,19 @@ hipError_t enqueue_passes(bool fp32, const Geo& g, const UnitDev* u, int fm, int
               : enqueue_matvec_passes<double>(g, u, nu, fm, lm, j, ib, st);
 }
 
-void fill_unit(hom_problem* pb, int k, int L, const double* E, double* const* x, UnitDev* hu) {
+// gani: the coefficients of the GaNi operator (solves and operator application in GaNi mode)
+void fill_unit(hom_problem* pb, int k, int L, const double* E, double* const* x, UnitDev* hu, bool gani = false) {
   std::memset(hu, 0, sizeof(*hu));
   SlotBufs& sb = pb->slot[k];
   const bool mixed = pb->desc.precision == HOM_MIXED;
-  hu->coef = mixed ? (const void*)pb->coef32[k] : (const void*)pb->coef64[k];
-  hu->ahat = pb->ahat_half[k];
+  const GaniData& gn = pb->gani;
+  if (gani) {
+    hu->coef = mixed ? (const void*)gn.coef32[k] : (const void*)gn.coef64[k];
+    hu->ahat = gn.ahat[k];
+  } else {
+    hu->coef = mixed ? (const void*)pb->coef32[k] : (const void*)pb->coef64[k];
+    hu->ahat = pb->ahat_half[k];
+  }
   for (int l = 0; l < L; ++l) {
     hu->x[l] = x ? reinterpret_cast<Cx<double>*>(x[l]) : sb.tmp[l];
     hu->r[l] = sb.r[l];
@@ -742,14 +801,15 @@ hom_status solve_impl(hom_problem* pb, int k, int nload, const double* E, const 
   hipStream_t st = pb->stream;
   const bool fp32 = pb->desc.precision == HOM_MIXED;
   SlotBufs& sb = pb->slot[k];
-  if (!pb->tuned[k][nload]) {
+  const bool gani = pb->gani.on;
+  if (!gani && !pb->tuned[k][nload]) {
     s = solve_tuning(&pb, 1, k, nload, sb.unit, st, &pb->tune[k][nload]);
     if (s != HOM_OK) return s;
     pb->tuned[k][nload] = true;
   }
-  Geo g = make_geo(pb, k, nload, fp32, 0, &pb->tune[k][nload]);
+  Geo g = gani ? make_geo_gani(pb, k, nload, fp32) : make_geo(pb, k, nload, fp32, 0, &pb->tune[k][nload]);
   UnitDev* hu = &pb->host_unit[k];
-  fill_unit(pb, k, nload, E, x_out, hu);
+  fill_unit(pb, k, nload, E, x_out, hu, gani);
   HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
   HIPCHK(hipStreamSynchronize(st));
   bool have_x0 = false;
@@ -768,7 +828,7 @@ hom_status solve_impl(hom_problem* pb, int k, int nload, const double* E, const 
   R.iter_base = sb.iter_base;
   R.active = sb.active;
   R.pinned_active = pb->pinned_active;
-  R.graph = &pb->graph[k][nload];
+  R.graph = gani ? &pb->gani.graph[k][nload] : &pb->graph[k][nload];
   R.chunk = pb->graph_chunk;
   R.stop = pb->stop;
   R.part_d.push_back(sb.part_d);
@@ -894,13 +954,15 @@ const char* hom_status_str(int32_t s) {
 }
 
 hom_status hom_field_len(const hom_desc* desc, int32_t dual, size_t* n) {
-  hom_status s = validate_desc(desc, 1);
-  if (s != HOM_OK) return s;
-  if (!n) return HOM_E_INVALID;
-  Sizes z;
-  Plan pl[3];
-  fill_sizes(desc, 1, &z, pl);
-  *n = (size_t)(dual ? desc->d - 1 : 1) * z.S;
+  // depends on N only: S = ((N0 + 1) / 2) N1 (N2) stored frequencies per component
+  if (!desc || !n || (desc->d != 2 && desc->d != 3)) return HOM_E_INVALID;
+  const int d = desc->d;
+  size_t S = 1;
+  for (int a = 0; a < d; ++a) {
+    if (desc->N[a] < 1 || desc->N[a] % 2 == 0) return HOM_E_UNSUPPORTED_SIZE;
+    S *= (size_t)(a == 0 ? (desc->N[0] + 1) / 2 : desc->N[a]);
+  }
+  *n = (size_t)(dual ? d - 1 : 1) * S;
   return HOM_OK;
 }
 
@@ -979,10 +1041,10 @@ hom_status hom_apply(hom_problem* pb, int32_t dual, const double* x, double* y) 
   const int k = dual;
   hipStream_t st = pb->stream;
   const bool fp32 = pb->desc.precision == HOM_MIXED;
-  Geo g = make_geo(pb, k, 1, fp32);
+  Geo g = pb->gani.on ? make_geo_gani(pb, k, 1, fp32) : make_geo(pb, k, 1, fp32);
   SlotBufs& sb = pb->slot[k];
   UnitDev* hu = &pb->host_unit[k];
-  fill_unit(pb, k, 1, nullptr, nullptr, hu);
+  fill_unit(pb, k, 1, nullptr, nullptr, hu, pb->gani.on);
   hu->x[0] = reinterpret_cast<Cx<double>*>(const_cast<double*>(x));
   hu->s[0] = reinterpret_cast<Cx<double>*>(y);
   HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
@@ -991,8 +1053,12 @@ hom_status hom_apply(hom_problem* pb, int32_t dual, const double* x, double* y) 
   return HOM_OK;
 }
 
-hom_status hom_bounds(hom_problem* pb, const double* const* primal, const double* const* dual, hom_result* out) {
-  if (!pb || !out) return HOM_E_INVALID;
+// Energy matrices a(e_b + x^(b), e_a + x^(a)) of primal and dual fields by the
+// FP64 quadrature of a geometry: the exact form on the quadrature grid (gani =
+// false, the bounds), or the trapezoidal rule on the N grid with the point
+// values of the coefficient (gani = true, the GaNi matrices).
+static hom_status energies(hom_problem* pb, const double* const* primal, const double* const* dual, bool gani,
+                           double Ebar[2][9], bool have[2]) {
   const int d = pb->desc.d;
   for (int k = 0; k < 2; ++k) {
     const double* const* f = k == 0 ? primal : dual;
@@ -1002,18 +1068,18 @@ hom_status hom_bounds(hom_problem* pb, const double* const* primal, const double
   }
   hipStream_t st = pb->stream;
   const int P = packs(d, d);
-  double Ebar[2][9];
-  bool have[2] = {primal != nullptr, dual != nullptr};
+  have[0] = primal != nullptr;
+  have[1] = dual != nullptr;
   std::vector<double> part[2];
   Geo g[2];
   for (int k = 0; k < 2; ++k) {
     if (!have[k]) continue;
     const double* const* f = k == 0 ? primal : dual;
-    g[k] = make_geo(pb, k, d, false, P);
+    g[k] = gani ? make_geo_gani(pb, k, d, false, P) : make_geo(pb, k, d, false, P);
     UnitDev* hu = &pb->host_bunit[k];
     std::memset(hu, 0, sizeof(*hu));
-    hu->coef = pb->coef64[k];
-    hu->ahat = pb->ahat_half[k];
+    hu->coef = gani ? pb->gani.coef64[k] : pb->coef64[k];
+    hu->ahat = gani ? pb->gani.ahat[k] : pb->ahat_half[k];
     for (int l = 0; l < d; ++l) {
       hu->x[l] = reinterpret_cast<Cx<double>*>(const_cast<double*>(f[l]));
       hu->E[l][l] = 1.0;
@@ -1040,35 +1106,162 @@ hom_status hom_bounds(hom_problem* pb, const double* const* primal, const double
         Ebar[k][a * d + b] = s * g[k].invM;
       }
   }
-  fill_result(d, Ebar, have, out);
   return HOM_OK;
 }
 
-hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
-                               const double* center, const double* size, const double* A_in, int32_t inverse,
-                               void* out, void* stream) {
+hom_status hom_bounds(hom_problem* pb, const double* const* primal, const double* const* dual, hom_result* out) {
+  if (!pb || !out) return HOM_E_INVALID;
+  double Ebar[2][9];
+  bool have[2];
+  hom_status s = energies(pb, primal, dual, false, Ebar, have);
+  if (s != HOM_OK) return s;
+  fill_result(pb->desc.d, Ebar, have, out);
+  return HOM_OK;
+}
+
+hom_status hom_gani_matrices(hom_problem* pb, const double* const* primal, const double* const* dual,
+                             double* A_HN, double* B_HN) {
+  if (!pb || !pb->gani.on || !A_HN || !B_HN) return HOM_E_INVALID;
+  double Ebar[2][9];
+  bool have[2];
+  hom_status s = energies(pb, primal, dual, true, Ebar, have);
+  if (s != HOM_OK) return s;
+  const int d = pb->desc.d;
+  for (int i = 0; i < d * d; ++i) {
+    A_HN[i] = Ebar[0][i];
+    B_HN[i] = Ebar[1][i];
+  }
+  return HOM_OK;
+}
+
+size_t gani_carve(const hom_desc* desc, const Sizes& z, GaniData* gd, char* base) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> size_t {
+    const size_t o = off;
+    off = up(off + bytes);
+    return o;
+  };
+  auto ptr = [&](size_t o) -> char* { return base ? base + o : nullptr; };
+  const int nc = z.nc;
+  const size_t Nt = (size_t)z.N[0] * z.N[1] * z.N[2];
+  const bool mixed = desc->precision == HOM_MIXED;
+  for (int k = 0; k < 2; ++k) {
+    size_t o = take(nc * Nt * sizeof(double));
+    if (gd) gd->coef64[k] = (double*)ptr(o);
+    if (mixed) {
+      o = take(nc * Nt * sizeof(float));
+      if (gd) gd->coef32[k] = (float*)ptr(o);
+    } else if (gd) {
+      gd->coef32[k] = nullptr;
+    }
+    o = take(nc * (size_t)z.S * sizeof(Cx<double>));
+    if (gd) gd->ahat[k] = (Cx<double>*)ptr(o);
+  }
+  for (int a = 0; a < 3; ++a) {
+    size_t o = take(z.N[a] * sizeof(Cx<double>));
+    if (gd) gd->tw64[a] = (Cx<double>*)ptr(o);
+    o = take(z.N[a] * sizeof(Cx<float>));
+    if (gd) gd->tw32[a] = (Cx<float>*)ptr(o);
+  }
+  size_t o = take(nc * Nt * sizeof(Cx<double>));
+  if (gd) gd->scratch = (Cx<double>*)ptr(o);
+  return off;
+}
+
+hom_status hom_gani_workspace_bytes(const hom_desc* desc, size_t* bytes) {
+  if (!bytes) return HOM_E_INVALID;
   hom_status s = validate_desc(desc, 1);
   if (s != HOM_OK) return s;
-  if (!A0 || !out || n_incl < 0 || (n_incl > 0 && (!kind || !center || !size || !A_in))) return HOM_E_INVALID;
-  const int d = desc->d, nc = desc->ncoef;
   Sizes z;
   Plan pl[3];
-  fill_sizes(desc, 1, &z, pl);
+  if (!fill_sizes(desc, 1, &z, pl)) return HOM_E_INVALID;
+  for (int a = 0; a < 3; ++a) {
+    Plan p;
+    if (z.N[a] > 1 && !smooth35(z.N[a], &p)) return HOM_E_UNSUPPORTED_SIZE;
+  }
+  *bytes = gani_carve(desc, z, nullptr, nullptr);
+  return HOM_OK;
+}
+
+hom_status hom_set_gani(hom_problem* pb, const double* AN, const double* BN, void* ws, size_t ws_bytes) {
+  if (!pb || !AN || !BN || !ws) return HOM_E_INVALID;
+  if (((uintptr_t)ws) % kAlign) return HOM_E_WORKSPACE;
+  size_t need = 0;
+  hom_status s = hom_gani_workspace_bytes(&pb->desc, &need);
+  if (s != HOM_OK) return s;
+  if (ws_bytes < need) return HOM_E_WORKSPACE;
+  GaniData& gd = pb->gani;
+  const Sizes& z = pb->z;
+  hipStream_t st = pb->stream;
+  HIPCHK(hipStreamSynchronize(st));
+  for (int k = 0; k < 2; ++k)
+    for (int l = 0; l <= kMaxLoads; ++l)
+      if (gd.graph[k][l]) {
+        (void)hipGraphExecDestroy(gd.graph[k][l]);
+        gd.graph[k][l] = nullptr;
+      }
+  gd.on = false;
+  gani_carve(&pb->desc, z, &gd, (char*)ws);
+  for (int a = 0; a < 3; ++a) {
+    if (z.N[a] == 1) {
+      gd.plan[a].n = 0;
+    } else if (!smooth35(z.N[a], &gd.plan[a])) {
+      return HOM_E_UNSUPPORTED_SIZE;
+    }
+    HIPCHK(launch_twiddles(gd.tw64[a], gd.tw32[a], z.N[a], st));
+  }
+  const int nc = z.nc;
+  const size_t Nt = (size_t)z.N[0] * z.N[1] * z.N[2];
+  Geo g = make_geo_gani(pb, 0, 1, false);
+  for (int k = 0; k < 2; ++k) {
+    const double* src = k == 0 ? AN : BN;
+    HIPCHK(hipMemcpyAsync(gd.coef64[k], src, nc * Nt * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(launch_real_to_cx(gd.coef64[k], gd.scratch, nc * Nt, 1.0, st));
+    if (gd.coef32[k]) HIPCHK(launch_coef_real(gd.scratch, gd.coef64[k], gd.coef32[k], (long)(nc * Nt), st));
+    // Fourier coefficients of the point values: the N-point DFT over 1 / |N| (Z_N part)
+    HIPCHK(launch_line_fft<double>(gd.scratch, nc, z.N[0], z.N[1] * z.N[2], gd.plan[0], gd.tw64[0], 0, st));
+    if (z.N[1] > 1)
+      HIPCHK(launch_line_fft<double>(gd.scratch, nc * z.N[0], z.N[1], z.N[2], gd.plan[1], gd.tw64[1], 0, st));
+    HIPCHK(launch_line_fft<double>(gd.scratch, nc * z.N[0] * z.N[1], z.N[2], 1, gd.plan[2], gd.tw64[2], 0, st));
+    HIPCHK(launch_scale_cx(gd.scratch, nc * Nt, 1.0 / (double)Nt, st));
+    HIPCHK(launch_extract_half(g, gd.scratch, gd.ahat[k], nc, st));
+  }
+  HIPCHK(hipStreamSynchronize(st));
+  gd.on = true;
+  return HOM_OK;
+}
+
+hom_status hom_clear_gani(hom_problem* pb) {
+  if (!pb) return HOM_E_INVALID;
+  pb->gani.on = false;
+  return HOM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct InclHost {
+  int kind;
+  double c[3];
+  double h[3];
+  double A[6];
+};
+
+// Inclusion table on internal axes: differences A_j - A0 (or of the inverses)
+// in coefficient components, and A0's components.
+hom_status incl_table(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
+                      const double* center, const double* size, const double* A_in, int32_t inverse,
+                      std::vector<InclHost>* inc, double* A0c) {
+  const int d = desc->d, nc = desc->ncoef;
   double A0m[9], A0i[9];
   std::memcpy(A0m, A0, sizeof(double) * d * d);
   inv_small(d, A0m, A0i);
   const double* base0 = inverse ? A0i : A0m;
-  struct InclHost {
-    int kind;
-    double c[3];
-    double h[3];
-    double A[6];
-  };
-  static_assert(sizeof(InclHost) > 0, "");
   if (incl_dev_size() != sizeof(InclHost)) return HOM_E_INVALID;
-  std::vector<InclHost> inc(n_incl);
+  inc->assign(n_incl, InclHost());
   for (int j = 0; j < n_incl; ++j) {
-    InclHost& I = inc[j];
+    InclHost& I = (*inc)[j];
     std::memset(&I, 0, sizeof(I));
     I.kind = kind[j];
     if (I.kind == 1 && d != 3) return HOM_E_INVALID;
@@ -1094,21 +1287,131 @@ hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n
     for (int i = 0; i < d * d; ++i) Dm[i] = (inverse ? Ai[i] : Am[i]) - base0[i];
     coef_components(d, nc, Dm, I.A);
   }
-  double A0c[6];
   coef_components(d, nc, base0, A0c);
+  return HOM_OK;
+}
+
+// Checks of a descriptor for point values on the N grid (no transform sizes
+// involved) and the internal N.
+hom_status sample_sizes(const hom_desc* desc, int* Nint) {
+  if (!desc || (desc->d != 2 && desc->d != 3)) return HOM_E_INVALID;
+  const int d = desc->d;
+  if (desc->ncoef != 1 && desc->ncoef != d * (d + 1) / 2) return HOM_E_INVALID;
+  for (int a = 0; a < d; ++a) {
+    if (!(desc->Y[a] > 0.0) || !std::isfinite(desc->Y[a])) return HOM_E_INVALID;
+    if (desc->N[a] < 1 || desc->N[a] % 2 == 0 || desc->N[a] > 8193) return HOM_E_UNSUPPORTED_SIZE;
+  }
+  Nint[0] = desc->N[0];
+  Nint[1] = d == 3 ? desc->N[1] : 1;
+  Nint[2] = d == 3 ? desc->N[2] : desc->N[1];
+  return HOM_OK;
+}
+
+// Device copy of A0's components (64 bytes) followed by the inclusion table.
+hom_status incl_upload(const std::vector<InclHost>& inc, const double* A0c, hipStream_t st, void** dev) {
+  const size_t bytes = sizeof(InclHost) * std::max<size_t>(inc.size(), 1) + 64;
+  if (hipMalloc(dev, bytes) != hipSuccess) return HOM_E_DEVICE;
+  if (hipMemcpyAsync(*dev, A0c, 6 * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      (!inc.empty() && hipMemcpyAsync((char*)*dev + 64, inc.data(), sizeof(InclHost) * inc.size(),
+                                      hipMemcpyHostToDevice, st) != hipSuccess)) {
+    (void)hipFree(*dev);
+    return HOM_E_DEVICE;
+  }
+  return HOM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
+                               const double* center, const double* size, const double* A_in, int32_t inverse,
+                               void* out, void* stream) {
+  hom_status s = validate_desc(desc, 1);
+  if (s != HOM_OK) return s;
+  if (!A0 || !out || n_incl < 0 || (n_incl > 0 && (!kind || !center || !size || !A_in))) return HOM_E_INVALID;
+  const int d = desc->d, nc = desc->ncoef;
+  Sizes z;
+  Plan pl[3];
+  fill_sizes(desc, 1, &z, pl);
+  std::vector<InclHost> inc;
+  double A0c[6] = {0, 0, 0, 0, 0, 0};
+  s = incl_table(desc, A0, n_incl, kind, center, size, A_in, inverse, &inc, A0c);
+  if (s != HOM_OK) return s;
   double iY[3] = {1.0 / desc->Y[0], 1.0, 1.0 / desc->Y[1]};
   if (d == 3) iY[1] = 1.0 / desc->Y[1], iY[2] = 1.0 / desc->Y[2];
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   void* dev = nullptr;
-  const size_t bytes = sizeof(InclHost) * std::max(n_incl, 1) + 64;
-  if (hipMalloc(&dev, bytes) != hipSuccess) return HOM_E_DEVICE;
+  s = incl_upload(inc, A0c, st, &dev);
+  if (s != HOM_OK) return s;
   hom_status rc = HOM_OK;
-  if (hipMemcpyAsync(dev, A0c, sizeof(A0c), hipMemcpyHostToDevice, st) != hipSuccess ||
-      (n_incl > 0 && hipMemcpyAsync((char*)dev + 64, inc.data(), sizeof(InclHost) * n_incl, hipMemcpyHostToDevice,
-                                    st) != hipSuccess) ||
-      launch_coef_incl(d, z.M, iY, nc, (const double*)dev, n_incl, (char*)dev + 64,
+  if (launch_coef_incl(d, z.M, iY, nc, (const double*)dev, n_incl, (char*)dev + 64,
                        reinterpret_cast<Cx<double>*>(out), st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
+    rc = HOM_E_DEVICE;
+  (void)hipFree(dev);
+  return rc;
+}
+
+hom_status hom_sample_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
+                                 const double* center, const double* size, const double* A_in, int32_t inverse,
+                                 double* out, void* stream) {
+  int Nint[3];
+  hom_status s = sample_sizes(desc, Nint);
+  if (s != HOM_OK) return s;
+  if (!A0 || !out || n_incl < 0 || (n_incl > 0 && (!kind || !center || !size || !A_in))) return HOM_E_INVALID;
+  const int d = desc->d, nc = desc->ncoef;
+  std::vector<InclHost> inc;
+  double A0c[6] = {0, 0, 0, 0, 0, 0};
+  s = incl_table(desc, A0, n_incl, kind, center, size, A_in, inverse, &inc, A0c);
+  if (s != HOM_OK) return s;
+  double Yint[3] = {desc->Y[0], 1.0, desc->Y[1]};
+  if (d == 3) Yint[1] = desc->Y[1], Yint[2] = desc->Y[2];
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  void* dev = nullptr;
+  s = incl_upload(inc, A0c, st, &dev);
+  if (s != HOM_OK) return s;
+  hom_status rc = HOM_OK;
+  if (launch_sample_incl(Nint, Yint, nc, (const double*)dev, n_incl, (char*)dev + 64, out, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    rc = HOM_E_DEVICE;
+  (void)hipFree(dev);
+  return rc;
+}
+
+hom_status hom_sample_pixels(const hom_desc* desc, const int32_t* P, const int32_t* phase, int32_t nphase,
+                             const double* phase_A, int32_t inverse, double* out, void* stream) {
+  int Nint[3];
+  hom_status s = sample_sizes(desc, Nint);
+  if (s != HOM_OK) return s;
+  if (!P || !phase || nphase < 1 || !phase_A || !out) return HOM_E_INVALID;
+  const int d = desc->d, nc = desc->ncoef;
+  int Pint[3] = {P[0], 1, P[1]};
+  if (d == 3) Pint[1] = P[1], Pint[2] = P[2];
+  for (int a = 0; a < 3; ++a)
+    if (Pint[a] < 1) return HOM_E_INVALID;
+  const size_t Pt = (size_t)Pint[0] * Pint[1] * Pint[2];
+  std::vector<double> comp((size_t)nphase * 6);
+  for (int q = 0; q < nphase; ++q) {
+    double Am[9], Ai[9];
+    std::memcpy(Am, phase_A + (size_t)q * d * d, sizeof(double) * d * d);
+    if (inverse) inv_small(d, Am, Ai);
+    coef_components(d, nc, inverse ? Ai : Am, &comp[(size_t)q * 6]);
+  }
+  std::vector<double> img(nc * Pt);
+  for (size_t t = 0; t < Pt; ++t) {
+    const int q = phase[t];
+    if (q < 0 || q >= nphase) return HOM_E_INVALID;
+    for (int c = 0; c < nc; ++c) img[c * Pt + t] = comp[(size_t)q * 6 + c];
+  }
+  double Yint[3] = {desc->Y[0], 1.0, desc->Y[1]};
+  if (d == 3) Yint[1] = desc->Y[1], Yint[2] = desc->Y[2];
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  double* dev = nullptr;
+  if (hipMalloc((void**)&dev, img.size() * sizeof(double)) != hipSuccess) return HOM_E_DEVICE;
+  hom_status rc = HOM_OK;
+  if (hipMemcpyAsync(dev, img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      launch_sample_pixels(Nint, Yint, Pint, nc, dev, out, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
     rc = HOM_E_DEVICE;
   (void)hipFree(dev);
   return rc;
@@ -1418,9 +1721,17 @@ hom_status hom_batch_create(hom_problem* const* pbs, int32_t n, void* ws, size_t
   return HOM_OK;
 }
 
+// Batches solve the exact (Ga) operator only.
+static bool batch_has_gani(const hom_batch* b) {
+  for (const hom_problem* p : b->pbs)
+    if (p->gani.on) return true;
+  return false;
+}
+
 hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const double* E, const double* const* x0,
                            double tol, int32_t maxit, double* const* x_out, hom_info* info) {
   if (!b || !info || (dual != 0 && dual != 1)) return HOM_E_INVALID;
+  if (batch_has_gani(b)) return HOM_E_INVALID;
   const int k = dual, n = b->n;
   for (int i = 0; i < n; ++i) {
     hom_status s = check_solve_args(b->pbs[i], nload, E, x_out + (size_t)i * nload, tol, maxit);
@@ -1482,6 +1793,7 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, do
                                 double* const* x_primal, double* const* x_dual, hom_info* info_primal,
                                 hom_info* info_dual) {
   if (!b || !info_primal || !info_dual || !x_primal || !x_dual) return HOM_E_INVALID;
+  if (batch_has_gani(b)) return HOM_E_INVALID;
   const int n = b->n;
   for (int i = 0; i < n; ++i) {
     hom_status s = check_solve_args(b->pbs[i], nload, E, x_primal + (size_t)i * nload, tol, maxit);
@@ -1666,7 +1978,7 @@ hom_status hom_batch_get_timing(hom_batch* b, double* ms_sum, int64_t* launches)
 
 static void tuning_report(const hom_problem* p0, int k, int nload, const Tuning& t, hom_tuning* out) {
   const Geo g = make_geo(p0, k, nload, p0->desc.precision == HOM_MIXED, 0, &t);
-  out->row_pairs = p0->desc.precision == HOM_MIXED ? fast_row_pairs(g.M[2], g.d, nload, t.rowG) : 0;
+  out->row_pairs = p0->desc.precision == HOM_MIXED ? fast_row_pairs(g.M[2], g.N[2], g.d, nload, t.rowG) : 0;
   out->row_threads = t.rowThreads;
   out->apply_points = t.apTP;
   out->apply_half_exchange = t.apHX;
@@ -1715,7 +2027,7 @@ hom_status hom_set_tuning(int32_t mode) {
 static bool tiles_ok(const hom_problem* p0, int nload, const hom_tuning* t) {
   if (p0->desc.precision != HOM_MIXED) return false;
   const Sizes& z = p0->z;
-  if (t->row_pairs != 0 && fast_row_pairs(z.M[2], z.d, nload, t->row_pairs) != t->row_pairs) return false;
+  if (t->row_pairs != 0 && fast_row_pairs(z.M[2], z.N[2], z.d, nload, t->row_pairs) != t->row_pairs) return false;
   if (t->row_threads != 0 && (t->row_threads % 64 != 0 || t->row_threads > 256)) return false;
   return fast_apply_shape_ok(z.M[0], z.d, t->apply_points, t->apply_half_exchange, t->apply_all_packs);
 }
@@ -1804,8 +2116,10 @@ void hom_batch_destroy(hom_batch* b) {
 void hom_destroy(hom_problem* pb) {
   if (!pb) return;
   for (int k = 0; k < 2; ++k)
-    for (int l = 0; l <= kMaxLoads; ++l)
+    for (int l = 0; l <= kMaxLoads; ++l) {
       if (pb->graph[k][l]) (void)hipGraphExecDestroy(pb->graph[k][l]);
+      if (pb->gani.graph[k][l]) (void)hipGraphExecDestroy(pb->gani.graph[k][l]);
+    }
   if (pb->pinned_active) (void)hipHostFree(pb->pinned_active);
   delete pb;
 }

@@ -437,7 +437,7 @@ static hipError_t run_mid(const Geo& g, const UnitDev* units, int n, int cg, hip
 // 3D middle pass for M1 in {25, 81, 125}; false when no specialisation exists.
 bool fast_mid(const Geo& g, const UnitDev* units, int n, int flags, hipStream_t st, hipError_t* err) {
   if (std::getenv("HOM_NO_FAST")) return false;
-  if (g.d != 3) return false;
+  if (g.d != 3 || g.M[1] != 2 * g.N[1] - 1) return false;
   const int inv = flags & 1, cg = (flags & MID_CG) ? 1 : 0;
   switch (g.M[1]) {
     case 81: *err = inv ? run_mid<81, 1>(g, units, n, cg, st) : run_mid<81, 0>(g, units, n, cg, st); return true;
@@ -1208,6 +1208,7 @@ static hipError_t run_apply(const Geo& g, const UnitDev* units, int n, int cg, h
 bool fast_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st, hipError_t* err) {
   if (std::getenv("HOM_NO_FAST")) return false;
   const int M = g.M[0], D = g.d, P = g.P, NC = g.nc;
+  if (M != 2 * g.N[0] - 1) return false;  // the register transforms keep Z_N of the doubled grid
   if (!apply_supported(M, D, P, NC)) return false;
   // the 2D column pass addresses its buffers with 32-bit byte offsets
   if (D == 2 && ((size_t)g.N[0] * g.M[2] * P * sizeof(Cx<float>) >= (size_t(1) << 32) ||
@@ -1235,8 +1236,9 @@ static int row_pairs_for(int requested) {
 
 // Row pairs per block of the specialised row passes, or 0 when no
 // specialisation exists (then the generic passes run).
-int fast_row_pairs(int M, int D, int L, int requested) {
+int fast_row_pairs(int M, int N, int D, int L, int requested) {
   if (std::getenv("HOM_NO_FAST")) return 0;
+  if (M != 2 * N - 1) return 0;  // the register transforms keep Z_N of the doubled grid
   if (!row_supported(M, D, L)) return 0;
   if (M == 625) return row_pairs_for<625>(requested);
   if (M == 125) return row_pairs_for<125>(requested);
@@ -1285,7 +1287,7 @@ static hipError_t run_row_d(bool first, const Geo& g, const UnitDev* units, int 
 
 bool fast_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, int jstep, const int* iter_base,
               hipStream_t st, hipError_t* err) {
-  if (!fast_row_pairs(g.M[2], g.d, g.L, g.rowG)) return false;
+  if (!fast_row_pairs(g.M[2], g.N[2], g.d, g.L, g.rowG)) return false;
   const int M = g.M[2], D = g.d, L = g.L;
   // 2D: one load per block (grid y = load); 3D: every load in one block
 #define HOM_RW2(MM)                                                                     \
@@ -1397,6 +1399,7 @@ hipError_t tune_fast(const Geo& g, const UnitDev* units, int n, hipStream_t st, 
   if (std::getenv("HOM_NO_FAST")) return hipSuccess;
   const int M = g.M[2];
   if (g.M[0] != M) return hipSuccess;  // tuned shapes cover equal row and column lengths
+  if (M != 2 * g.N[2] - 1 || g.M[0] != 2 * g.N[0] - 1) return hipSuccess;
   if (M == 625) return tune_m<625>(g, units, n, st, reps, best);
   if (M == 125) return tune_m<125>(g, units, n, st, reps, best);
   if (M == 81) return tune_m<81>(g, units, n, st, reps, best);

@@ -170,13 +170,21 @@ hipError_t launch_coef_incl(int d, const int* Mint, const double* iY, int nc, co
 hipError_t launch_pixel_factor(int d, const int* Mint, const int* Pint, int nc, const Cx<double>* dft,
                                Cx<double>* out, hipStream_t st);
 size_t incl_dev_size();
+// Point values of the coefficient on the N grid (internal axes, [nc][N0 N1 N2]).
+hipError_t launch_sample_incl(const int* Nint, const double* Yint, int nc, const double* A0c, int n_incl,
+                              const void* dev_incl, double* out, hipStream_t st);
+hipError_t launch_sample_pixels(const int* Nint, const double* Yint, const int* Pint, int nc, const double* img,
+                                double* out, hipStream_t st);
+// out = s * in as complex values with zero imaginary part; a *= s.
+hipError_t launch_real_to_cx(const double* in, Cx<double>* out, size_t n, double s, hipStream_t st);
+hipError_t launch_scale_cx(Cx<double>* a, size_t n, double s, hipStream_t st);
 
 // Specialised FP32 passes (hom_fast.hip); false/0 when no specialisation exists.
 bool fast_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st, hipError_t* err);
 bool fast_row(bool first, const Geo& g, const UnitDev* units, int n, int mode, int jstep, const int* iter_base,
               hipStream_t st, hipError_t* err);
 // Row pairs per block for a requested value (0 or an unsupported value: the default).
-int fast_row_pairs(int M, int D, int L, int requested);
+int fast_row_pairs(int M, int N, int D, int L, int requested);
 bool fast_apply_supported(int M, int D, int P, int NC);
 // 3D middle pass (axis 1) for M1 in {25, 81, 125}; flags as launch_mid.
 bool fast_mid(const Geo& g, const UnitDev* units, int n, int flags, hipStream_t st, hipError_t* err);

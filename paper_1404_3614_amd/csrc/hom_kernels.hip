@@ -1195,4 +1195,97 @@ hipError_t launch_pixel_factor(int d, const int* Mint, const int* Pint, int nc, 
 
 size_t incl_dev_size() { return sizeof(InclDev); }
 
+// ---- point values on the N grid (GaNi, eq. FD_A_GaNi)
+// Grid point x_a = Y_a k_a / N_a, k in Z_N (eq. grid_points).  A point is in a
+// box inclusion iff |x_a - c_a| < h_a / 2 on every axis, in a ball iff
+// |x - c|^2 < R^2, with periodic minimum-image differences (open sets: a point
+// on an interface belongs to the matrix).
+__global__ void k_sample_incl(int N0, int N1, int N2, double Y0, double Y1, double Y2, int nc,
+                              const double* __restrict__ A0c, int n_incl, const InclDev* __restrict__ inc,
+                              double* __restrict__ out) {
+  const size_t Nt = (size_t)N0 * N1 * N2;
+  const int Nn[3] = {N0, N1, N2};
+  const double Y[3] = {Y0, Y1, Y2};
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < Nt; t += (size_t)gridDim.x * blockDim.x) {
+    const int j[3] = {(int)(t / ((size_t)N1 * N2)), (int)((t / N2) % N1), (int)(t % N2)};
+    double x[3];
+    for (int a = 0; a < 3; ++a) x[a] = Y[a] * (double)fr(j[a], Nn[a]) / (double)Nn[a];
+    double v[6];
+    for (int c = 0; c < nc; ++c) v[c] = A0c[c];
+    for (int q = 0; q < n_incl; ++q) {
+      const InclDev& I = inc[q];
+      double dl[3];
+      for (int a = 0; a < 3; ++a) {
+        const double u = x[a] - I.c[a];
+        dl[a] = u - Y[a] * rint(u / Y[a]);
+      }
+      bool inside;
+      if (I.kind == 0) {
+        inside = true;
+        for (int a = 0; a < 3; ++a) inside = inside && fabs(dl[a]) < 0.5 * I.h[a];
+      } else {
+        inside = ((0.0 + dl[0] * dl[0]) + dl[1] * dl[1]) + dl[2] * dl[2] < I.h[0] * I.h[0];
+      }
+      if (inside)
+        for (int c = 0; c < nc; ++c) v[c] = A0c[c] + I.A[c];
+    }
+    for (int c = 0; c < nc; ++c) out[c * Nt + t] = v[c];
+  }
+}
+
+// Pixel i_a along axis a covers [-Y_a/2 + i_a Y_a/P_a, -Y_a/2 + (i_a+1) Y_a/P_a).
+__global__ void k_sample_pixels(int N0, int N1, int N2, double Y0, double Y1, double Y2, int P0, int P1, int P2,
+                                int nc, const double* __restrict__ img, double* __restrict__ out) {
+  const size_t Nt = (size_t)N0 * N1 * N2, Pt = (size_t)P0 * P1 * P2;
+  const int Nn[3] = {N0, N1, N2}, Pp[3] = {P0, P1, P2};
+  const double Y[3] = {Y0, Y1, Y2};
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < Nt; t += (size_t)gridDim.x * blockDim.x) {
+    const int j[3] = {(int)(t / ((size_t)N1 * N2)), (int)((t / N2) % N1), (int)(t % N2)};
+    long ip[3];
+    for (int a = 0; a < 3; ++a) {
+      const double x = Y[a] * (double)fr(j[a], Nn[a]) / (double)Nn[a];
+      long i = (long)floor((x / Y[a] + 0.5) * (double)Pp[a]);
+      ip[a] = i < 0 ? 0 : (i > Pp[a] - 1 ? Pp[a] - 1 : i);
+    }
+    const size_t pix = ((size_t)ip[0] * P1 + ip[1]) * P2 + ip[2];
+    for (int c = 0; c < nc; ++c) out[c * Nt + t] = img[c * Pt + pix];
+  }
+}
+
+__global__ void k_real_to_cx(const double* __restrict__ in, Cx<double>* __restrict__ out, size_t n, double s) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+    out[t] = cx(in[t] * s, 0.0);
+}
+
+__global__ void k_scale_cx(Cx<double>* __restrict__ a, size_t n, double s) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x)
+    a[t] = cx(a[t].x * s, a[t].y * s);
+}
+
+hipError_t launch_sample_incl(const int* Nint, const double* Yint, int nc, const double* A0c, int n_incl,
+                              const void* dev_incl, double* out, hipStream_t st) {
+  const size_t Nt = (size_t)Nint[0] * Nint[1] * Nint[2];
+  hipLaunchKernelGGL(k_sample_incl, dim3(grid_for(Nt)), dim3(kBlock), 0, st, Nint[0], Nint[1], Nint[2], Yint[0],
+                     Yint[1], Yint[2], nc, A0c, n_incl, (const InclDev*)dev_incl, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_pixels(const int* Nint, const double* Yint, const int* Pint, int nc, const double* img,
+                                double* out, hipStream_t st) {
+  const size_t Nt = (size_t)Nint[0] * Nint[1] * Nint[2];
+  hipLaunchKernelGGL(k_sample_pixels, dim3(grid_for(Nt)), dim3(kBlock), 0, st, Nint[0], Nint[1], Nint[2], Yint[0],
+                     Yint[1], Yint[2], Pint[0], Pint[1], Pint[2], nc, img, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_real_to_cx(const double* in, Cx<double>* out, size_t n, double s, hipStream_t st) {
+  hipLaunchKernelGGL(k_real_to_cx, dim3(grid_for(n)), dim3(kBlock), 0, st, in, out, n, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_cx(Cx<double>* a, size_t n, double s, hipStream_t st) {
+  hipLaunchKernelGGL(k_scale_cx, dim3(grid_for(n)), dim3(kBlock), 0, st, a, n, s);
+  return hipGetLastError();
+}
+
 }  // namespace hom

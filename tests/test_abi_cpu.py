@@ -84,8 +84,19 @@ def test_field_len_matches_layout():
     assert n.value == 7 * 13
     assert lib.hom_field_len(C.byref(_desc(L, d=3, N=(5, 13, 41))), 1, C.byref(n)) == 0
     assert n.value == 2 * 3 * 13 * 41
-    # N1 = 9 gives M1 = 17: unsupported
-    assert lib.hom_field_len(C.byref(_desc(L, d=3, N=(5, 9, 13))), 1, C.byref(n)) == L.HOM_E_UNSUPPORTED_SIZE
+    # the field length depends on N only (N1 = 9, whose 2N - 1 = 17 needs a larger quadrature grid)
+    assert lib.hom_field_len(C.byref(_desc(L, d=3, N=(5, 9, 13))), 1, C.byref(n)) == 0
+    assert n.value == 2 * 3 * 9 * 13
+    assert lib.hom_field_len(C.byref(_desc(L, d=3, N=(5, 8, 13))), 1, C.byref(n)) == L.HOM_E_UNSUPPORTED_SIZE
+    # a problem on N1 = 9 needs a quadrature grid: 2N - 1 = 17 has a factor 17, M = 25 is accepted
+    ws = C.c_size_t()
+    assert lib.hom_workspace_bytes(C.byref(_desc(L, d=3, N=(5, 9, 13))), 3, C.byref(ws)) == L.HOM_E_UNSUPPORTED_SIZE
+    ds = _desc(L, d=3, N=(5, 9, 13))
+    ds.M[0], ds.M[1], ds.M[2] = 9, 25, 25
+    assert lib.hom_workspace_bytes(C.byref(ds), 3, C.byref(ws)) == 0
+    for bad in ((9, 23, 25), (9, 26, 25), (9, 49, 25)):      # below 2N - 1, even, factor 7
+        ds.M[0], ds.M[1], ds.M[2] = bad
+        assert lib.hom_workspace_bytes(C.byref(ds), 3, C.byref(ws)) == L.HOM_E_UNSUPPORTED_SIZE
 
 
 def test_workspace_grows_with_loads_and_precision():
