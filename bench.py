@@ -58,7 +58,8 @@ def parse():
                          "(energy: extrapolated tail; guaranteed: Gauss-Radau bound)")
     ap.add_argument("--etol", type=float, default=1e-7,
                     help="energy rules: remaining energy decrease / energy of the iterate")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "e1"])
+    ap.add_argument("--e1-jmax", type=int, default=5, help="e1: grids N = 5 3^j for j <= jmax")
     ap.add_argument("--c5-train", type=int, default=2048, help="c5: training cells")
     ap.add_argument("--c5-steps", type=int, default=1500, help="c5: Adam steps")
     ap.add_argument("--c5-test", type=int, default=256, help="c5: held-out cells")
@@ -289,6 +290,8 @@ def main():
         return run_c4(args)
     if args.workload == "c5":
         return run_c5(args)
+    if args.workload == "e1":
+        return run_e1(args)
     N = (313, 313)
     B = args.cells
     # inputs resident in HBM: Fourier data of A and A^-1 for every cell
@@ -604,6 +607,75 @@ def run_c5(args):
                                     loss_first=round(float(np.mean(hist[:10])), 5),
                                     loss_last=round(float(np.mean(hist[-50:])), 5))),
                  dtype="f32 FFT/apply + f64 CG/bounds; f32 network")
+    print(json.dumps(line), flush=True)
+
+
+def smooth_odd_at_least(n):
+    """Smallest odd m >= n with no prime factors but 3 and 5."""
+    m = n if n % 2 else n + 1
+    while True:
+        v = m
+        for p in (3, 5):
+            while v % p == 0:
+                v //= p
+        if v == 1:
+            return m
+        m += 2
+
+
+def run_e1(args):
+    """The paper's odd-grid experiment: cell (-1, 1)^2, square inclusion
+    |x_a| < 3/5 of coefficient (1 + rho) I in I, rho in {10, 1e3}, N = 5 3^j.
+    For every grid: the Galerkin scheme with exact integration (Ga) and the
+    paper's Algorithm (GaNi solve, exact bounds of its minimisers), FP64, the
+    residual rule at 1e-8 of the paper's Convergence-criteria remark."""
+    import numpy as np
+    import torch
+    import homgen
+    import paper_1404_3614_amd as H
+    rows = []
+    t_all = 0.0
+    pairs = 0
+    for rho in (10.0, 1e3):
+        cell = homgen.Inclusions(d=2, Y=np.array([2.0, 2.0]), A0=np.eye(2))
+        cell.add("rect", [0.0, 0.0], [1.2, 1.2], (1.0 + rho) * np.eye(2))
+        for j in range(args.e1_jmax + 1):
+            n = 5 * 3 ** j
+            M = smooth_odd_at_least(2 * n - 1)
+            pb = H.problem_from_cell(cell, (n, n), precision="fp64", M=(M, M))
+            pb.solve_bounds(tol=1e-8)                      # warm-up: graphs, plans
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ga = pb.solve_bounds(tol=1e-8)
+            torch.cuda.synchronize()
+            t_ga = time.perf_counter() - t0
+            pb.set_gani_from_cell(cell)
+            pb.solve_bounds(tol=1e-8)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            gn = pb.solve_bounds(tol=1e-8)
+            AHN, BHN = pb.gani_matrices(gn["fields_primal"], gn["fields_dual"])
+            torch.cuda.synchronize()
+            t_gn = time.perf_counter() - t0
+            t_all += t_ga + t_gn
+            pairs += 2
+            it = lambda r: [i["iters"] for i in r["info_primal"] + r["info_dual"]]
+            rows.append(dict(rho=rho, N=n, M=M,
+                             Ga=dict(A_up=ga["A_up"][0, 0], A_low=ga["A_low"][0, 0], D=ga["D"][0, 0], iters=it(ga),
+                                     ms=round(1e3 * t_ga, 2)),
+                             GaNi=dict(A_HN=AHN[0, 0], inv_B_HN=float(np.linalg.inv(BHN)[0, 0]),
+                                       A_up=gn["A_up"][0, 0], A_low=gn["A_low"][0, 0], D=gn["D"][0, 0],
+                                       iters=it(gn), ms=round(1e3 * t_gn, 2))))
+            print(f"[e1] rho {rho:g} N {n} M {M}: Ga [{ga['A_low'][0, 0]:.6f}, {ga['A_up'][0, 0]:.6f}] "
+                  f"GaNi A_HN {AHN[0, 0]:.6f} [{gn['A_low'][0, 0]:.6f}, {gn['A_up'][0, 0]:.6f}] "
+                  f"({1e3 * t_ga:.1f} / {1e3 * t_gn:.1f} ms)", file=sys.stderr, flush=True)
+            del pb
+    line = _line(args, pairs / t_all, t_all, 1,
+                 "E1: cell (-1,1)^2, square |x_a| < 3/5 of (1 + rho) I in I, rho in {10, 1e3}, N = 5 3^j, "
+                 "Ga and GaNi (the paper's Algorithm) on each grid, FP64, residual rule 1e-8",
+                 dict(grids=rows), dtype="f64")
+    line["config"]["tol"] = 1e-8
+    line["config"]["precision"] = "fp64"
     print(json.dumps(line), flush=True)
 
 

@@ -100,8 +100,17 @@ def test_point_values_match_oracle(name, make, N, inverse):
     assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+def _paper_square(rho):
+    """The cell of the paper's experiments: (-1, 1)^2, square |x_a| < 3/5 of (1 + rho) I in I."""
+    c = homgen.Inclusions(d=2, Y=np.array([2.0, 2.0]), A0=np.eye(2))
+    c.add("rect", [0.0, 0.0], [1.2, 1.2], (1.0 + rho) * np.eye(2))
+    return c
+
+
 GANI = [
     ("square_N15", lambda: homgen.square_inclusion_cell(rho_in=10.0), (15, 15), (45, 45)),
+    ("paper_S_rho10_N5", lambda: _paper_square(10.0), (5, 5), (9, 9)),
+    ("paper_S_rho1e3_N45", lambda: _paper_square(1e3), (45, 45), (125, 125)),
     ("aniso_N15x9", _aniso_rects, (15, 9), (45, 25)),
     ("pix_N45", lambda: homgen.pixel_cell(seed=11, P=25, values=(1.0, 50.0)), (45, 45), (125, 125)),
     ("sph3d_N9", lambda: homgen.sphere_cell(seed=12, n=4, anisotropic=True), (9, 9, 9), (25, 25, 25)),
@@ -126,10 +135,18 @@ def test_gani_matches_oracle(name, make, N, M, precision):
     its = [i["iters"] for i in r["info_primal"] + r["info_dual"]]
     print(f"[gani] {name} {precision}: {', '.join(f'{k} {v:.1e}' for k, v in errs.items())}; iterations {its} "
           f"oracle {ref['iters']}", flush=True)
-    assert max(errs.values()) <= tol
-    # the CG energy of the GaNi solve is the diagonal of A_{H,N}
+    # A_{H,N} is the GaNi energy at its own minimiser: second order in the algebraic error
+    assert errs["A_HN"] <= tol and errs["B_HN"] <= tol
+    # the exact energy of a GaNi minimiser is not minimal in the exact form, so the bounds
+    # are first order in its error; with FP32 transforms that error grows like the square
+    # root of the coefficient's contrast
+    a_min, a_max = H.cell_eig_range(cell)
+    tol_b = tol if precision == "fp64" else tol * np.sqrt(a_max / a_min)
+    assert errs["A_up"] <= tol_b and errs["A_low"] <= tol_b
+    # the CG energy of the GaNi solve is the diagonal of A_{H,N} (the recurrence of the FP32
+    # operator carries its rounding, growing with the contrast like the bounds above)
     ep = np.array([i["energy"] for i in r["info_primal"]])
-    assert np.abs(ep - np.diag(AHN)).max() <= tol * np.linalg.norm(AHN, 2)
+    assert np.abs(ep - np.diag(AHN)).max() <= tol_b * np.linalg.norm(AHN, 2)
     # odd grids: A_{H,N} = B_{H,N}^{-1}; the exact bounds of the GaNi fields enclose those of the Ga fields
     n = np.linalg.norm(AHN, 2)
     assert relerr(AHN, np.linalg.inv(BHN)) <= (1e-8 if precision == "fp64" else 1e-5)
