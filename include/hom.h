@@ -214,6 +214,15 @@ hom_status hom_sample_inclusions(const hom_desc* desc, const double* A0, int32_t
 hom_status hom_sample_pixels(const hom_desc* desc, const int32_t* P, const int32_t* phase, int32_t nphase,
                              const double* phase_A, int32_t inverse, double* out, void* stream);
 
+/* The coefficient smoothing filter of the paper's fly-ash example (Sec. 8.3):
+ * each value of a 2D characteristic image f (device int32, P[0] x P[1]
+ * row-major, values 0 / 1) becomes 4/16 of itself plus 2/16 of each of its
+ * four axis neighbours and 1/16 of each of its four diagonal neighbours,
+ * periodically.  out (device int32, same shape) receives 16 f_smoothed, exact
+ * in integers; a pixel image with the phases k = 0..16 of coefficient
+ * A0 + (k/16)(A1 - A0) is the smoothed medium (hom_coef_pixels, hom_sample_pixels). */
+hom_status hom_smooth_pixels(const int32_t* P, const int32_t* f, int32_t* out, void* stream);
+
 /* Device workspace bytes of hom_set_gani (alignment 256). */
 hom_status hom_gani_workspace_bytes(const hom_desc* desc, size_t* bytes);
 

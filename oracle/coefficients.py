@@ -183,11 +183,25 @@ def point_values(cell, shape, inverse=False):
     return out
 
 
+def smooth_characteristic(f):
+    """The coefficient smoothing filter of the paper's fly-ash example (Sec. 8.3):
+    every grid value of a 2D characteristic function is replaced by a local
+    average, 4/16 of itself, 2/16 of each of its four axis neighbours and 1/16
+    of each of its four diagonal neighbours (periodic).  Returns the integer
+    image 16 f_smoothed (exact: the weights are sixteenths)."""
+    f = np.asarray(f, dtype=np.int64)
+    assert f.ndim == 2
+    sh = lambda a, b: np.roll(np.roll(f, -a, axis=0), -b, axis=1)     # f at k + (a, b)
+    return (4 * f
+            + 2 * (sh(1, 0) + sh(-1, 0) + sh(0, 1) + sh(0, -1))
+            + (sh(1, 1) + sh(-1, -1) + sh(-1, 1) + sh(1, -1)))
+
+
 def z_half_M(N):
     """Shape of the doubled grid for an N grid: M = 2N - 1 per axis."""
     return tuple(2 * n - 1 for n in N)
 
 
-__all__ = ["rect_hat", "ball_hat", "shift_phase", "fourier_inclusions", "fourier_pixels",
+__all__ = ["rect_hat", "ball_hat", "shift_phase", "fourier_inclusions", "fourier_pixels", "smooth_characteristic",
            "fourier_coefficients", "double_grid", "double_grid_direct", "point_values",
            "z_half_M", "freqs"]

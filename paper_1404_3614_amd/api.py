@@ -134,6 +134,8 @@ def sample_cell(cell, N, ncoef=None, inverse=False, stream=None):
     ncoef = cell_ncoef(cell) if ncoef is None else ncoef
     ds = _desc(d, N, cell.Y, "fp64", ncoef)
     out = torch.empty((ncoef,) + N, dtype=torch.float64, device=_dev())
+    if stream is not None:
+        stream.wait_stream(torch.cuda.current_stream())
     dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
     if hasattr(cell, "phase"):
         P = (C.c_int32 * 3)(*(list(cell.phase.shape) + [1] * (3 - d)))
@@ -156,6 +158,24 @@ def sample_cell(cell, N, ncoef=None, inverse=False, stream=None):
                                         C.c_void_p(out.data_ptr()), _stream_ptr(stream))
     L.check(st, "hom_sample_inclusions")
     return out
+
+
+def smooth_pixel_cell(cell, stream=None):
+    """The smoothed medium of a two-phase 2D pixel cell (hom_smooth_pixels): a
+    pixel cell with phases k = 0..16 of coefficient A0 + (k/16)(A1 - A0), k/16
+    the smoothed characteristic function of phase 1."""
+    import homgen
+    assert cell.d == 2 and len(cell.phase_A) == 2, "two-phase 2D pixel cells"
+    f = torch.as_tensor(np.ascontiguousarray(cell.phase == 1).astype(np.int32), device=_dev())
+    out = torch.empty_like(f)
+    if stream is not None:
+        stream.wait_stream(torch.cuda.current_stream())
+    P = (C.c_int32 * 2)(*cell.phase.shape)
+    L.check(L.load().hom_smooth_pixels(P, C.c_void_p(f.data_ptr()), C.c_void_p(out.data_ptr()),
+                                       _stream_ptr(stream)), "hom_smooth_pixels")
+    A0, A1 = (np.asarray(a, float) for a in cell.phase_A)
+    table = np.stack([A0 + (k / 16.0) * (A1 - A0) for k in range(17)])
+    return homgen.Pixels(d=2, Y=np.asarray(cell.Y, float), phase=out.cpu().numpy().astype(np.int64), phase_A=table)
 
 
 def coef_from_cell(cell, N, ncoef=None, stream=None, M=None):

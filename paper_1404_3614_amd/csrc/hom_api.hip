@@ -1168,6 +1168,14 @@ size_t gani_carve(const hom_desc* desc, const Sizes& z, GaniData* gd, char* base
   return off;
 }
 
+hom_status hom_smooth_pixels(const int32_t* P, const int32_t* f, int32_t* out, void* stream) {
+  if (!P || !f || !out || P[0] < 1 || P[1] < 1) return HOM_E_INVALID;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (launch_smooth2d(P[0], P[1], f, out, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
+    return HOM_E_DEVICE;
+  return HOM_OK;
+}
+
 hom_status hom_gani_workspace_bytes(const hom_desc* desc, size_t* bytes) {
   if (!bytes) return HOM_E_INVALID;
   hom_status s = validate_desc(desc, 1);

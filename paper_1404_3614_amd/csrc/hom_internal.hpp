@@ -178,6 +178,8 @@ hipError_t launch_sample_pixels(const int* Nint, const double* Yint, const int* 
 // out = s * in as complex values with zero imaginary part; a *= s.
 hipError_t launch_real_to_cx(const double* in, Cx<double>* out, size_t n, double s, hipStream_t st);
 hipError_t launch_scale_cx(Cx<double>* a, size_t n, double s, hipStream_t st);
+// 16 x the smoothed 2D characteristic image (periodic 3 x 3 stencil 4 / 2 / 1).
+hipError_t launch_smooth2d(int P0, int P1, const int* f, int* out, hipStream_t st);
 
 // Specialised FP32 passes (hom_fast.hip); false/0 when no specialisation exists.
 bool fast_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st, hipError_t* err);

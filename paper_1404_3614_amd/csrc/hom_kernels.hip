@@ -1278,6 +1278,25 @@ hipError_t launch_sample_pixels(const int* Nint, const double* Yint, const int* 
   return hipGetLastError();
 }
 
+// Smoothing filter of a 2D characteristic image (periodic 3 x 3 stencil with
+// weights 4 / 2 / 1 sixteenths): out = 16 f_smoothed, in integers.
+__global__ void k_smooth2d(int P0, int P1, const int* __restrict__ f, int* __restrict__ out) {
+  const size_t n = (size_t)P0 * P1;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(t / P1), j = (int)(t % P1);
+    const int im = i == 0 ? P0 - 1 : i - 1, ip = i == P0 - 1 ? 0 : i + 1;
+    const int jm = j == 0 ? P1 - 1 : j - 1, jp = j == P1 - 1 ? 0 : j + 1;
+    auto at = [&](int a, int b) { return f[(size_t)a * P1 + b]; };
+    out[t] = 4 * at(i, j) + 2 * (at(ip, j) + at(im, j) + at(i, jp) + at(i, jm)) +
+             (at(ip, jp) + at(im, jm) + at(im, jp) + at(ip, jm));
+  }
+}
+
+hipError_t launch_smooth2d(int P0, int P1, const int* f, int* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_smooth2d, dim3(grid_for((size_t)P0 * P1)), dim3(kBlock), 0, st, P0, P1, f, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_real_to_cx(const double* in, Cx<double>* out, size_t n, double s, hipStream_t st) {
   hipLaunchKernelGGL(k_real_to_cx, dim3(grid_for(n)), dim3(kBlock), 0, st, in, out, n, s);
   return hipGetLastError();

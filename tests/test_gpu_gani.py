@@ -174,3 +174,33 @@ def test_gani_rejects_batches_and_bad_grids():
     pb = H.problem_from_cell(cell, (13, 13), precision="mixed")
     with pytest.raises(H.HomError):
         pb.set_gani_from_cell(cell)
+
+
+def test_smoothing_filter_matches_oracle_and_bounds():
+    """Sec. 8.3 smoothing: the device filter is bitwise the oracle's; the smoothed
+    medium (17 phases) gives bounds equal to the oracle's, closer together than
+    the unsmoothed medium's on the same grid (Ga and GaNi)."""
+    H = _H()
+    for seed, P in ((1, (25, 25)), (2, (15, 45))):
+        rng = np.random.default_rng(seed)
+        cell = homgen.Pixels(d=2, Y=np.array([1.0, 1.0]), phase=(rng.random(P) < 0.45).astype(np.int64),
+                             phase_A=np.stack([np.eye(2), 30.0 * np.eye(2)]))
+        sm = H.smooth_pixel_cell(cell)
+        assert (sm.phase == co.smooth_characteristic(cell.phase)).all()
+        assert np.allclose(sm.phase_A[16], 30.0 * np.eye(2)) and np.allclose(sm.phase_A[0], np.eye(2))
+    cell = homgen.pixel_cell(seed=13, P=25, values=(1.0, 30.0))
+    sm = H.smooth_pixel_cell(cell)
+    ref = ga.bounds(ga.make_problem(sm, (13, 13)), tol=1e-11)
+    r = H.problem_from_cell(sm, (13, 13), precision="mixed").solve_bounds(tol=1e-8)
+    assert relerr(r["A_up"], ref["A_up"]) <= 1e-6 and relerr(r["A_low"], ref["A_low"]) <= 1e-6
+    raw = H.problem_from_cell(cell, (13, 13), precision="mixed").solve_bounds(tol=1e-8)
+    gap = lambda b: np.linalg.norm(b["D"], 2) / np.linalg.norm(b["A_mean"], 2)
+    print(f"[smooth] relative gap ||D||/||A_mean||: raw {gap(raw):.4f} smoothed {gap(r):.4f}", flush=True)
+    assert gap(r) < gap(raw)
+    # GaNi on the pixel grid (grid points at the pixel centres)
+    g = gani.gani_bounds(sm, (25, 25), tol=1e-11)
+    pb = H.problem_from_cell(sm, (25, 25), precision="fp64", M=(75, 75))
+    pb.set_gani_from_cell(sm)
+    rg = pb.solve_bounds(tol=1e-10)
+    AHN, BHN = pb.gani_matrices(rg["fields_primal"], rg["fields_dual"])
+    assert relerr(AHN, g["A_HN"]) <= 1e-9 and relerr(rg["A_up"], g["A_up"]) <= 1e-9

@@ -111,3 +111,27 @@ def test_point_values_open_set_and_periodic_wrap():
             dx -= np.round(dx)
             inside = abs(dx) < 0.15 and abs(y) < 0.1
             assert A[0, 0, i, j] == (5.0 if inside else 1.0)
+
+
+def test_smoothing_filter_stencil_and_invariants():
+    """Sec. 8.3 smoothing: a single inclusion pixel spreads as the stencil 1-2-1 x 1-2-1
+    (weights 4, 2, 1 sixteenths); constants stay; mass is conserved; the filter commutes
+    with transposition and with periodic shifts."""
+    f = np.zeros((7, 9), dtype=np.int64)
+    f[3, 4] = 1
+    g = co.smooth_characteristic(f)
+    expect = np.zeros_like(f)
+    expect[2:5, 3:6] = [[1, 2, 1], [2, 4, 2], [1, 2, 1]]
+    assert (g == expect).all()
+    # periodic wrap at the corner
+    f = np.zeros((5, 5), dtype=np.int64)
+    f[0, 0] = 1
+    g = co.smooth_characteristic(f)
+    assert g[4, 4] == 1 and g[0, 4] == 2 and g[4, 0] == 2 and g[0, 0] == 4 and g.sum() == 16
+    rng = np.random.default_rng(3)
+    f = (rng.random((25, 15)) < 0.4).astype(np.int64)
+    g = co.smooth_characteristic(f)
+    assert (co.smooth_characteristic(np.ones_like(f)) == 16).all()
+    assert g.sum() == 16 * f.sum() and g.min() >= 0 and g.max() <= 16
+    assert (co.smooth_characteristic(f.T) == g.T).all()
+    assert (co.smooth_characteristic(np.roll(f, (2, -3), axis=(0, 1))) == np.roll(g, (2, -3), axis=(0, 1))).all()
