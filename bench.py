@@ -14,7 +14,9 @@ Other workloads (--workload): c4, a mixed batch of 512 2D cells of uneven N
 (13, 41, 63, 313) and 64 3D cells (N = 41), random inclusions with contrast
 log-uniform in [2, 1e3], solved class by class in lockstep batches; c5, the
 learned initial guess (U-Net trained on solver fields of 2D N = 63 cells),
-plain versus learned + batched on held-out cells of contrast 1e2 - 1e3.
+plain versus learned + batched on held-out cells of contrast 1e2 - 1e3; e1
+and e2, the paper's square experiments on odd grids N = 5 3^j and on even
+GaNi grids n = 2^j (Ga and the paper's Algorithm per grid, FP64).
 
 Prints one JSON line.  The roofline object divides the algorithmic bytes per
 launch of the dominant kernel by its duration measured with HIP events; its
@@ -58,8 +60,9 @@ def parse():
                          "(energy: extrapolated tail; guaranteed: Gauss-Radau bound)")
     ap.add_argument("--etol", type=float, default=1e-7,
                     help="energy rules: remaining energy decrease / energy of the iterate")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "e1"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "e1", "e2"])
     ap.add_argument("--e1-jmax", type=int, default=5, help="e1: grids N = 5 3^j for j <= jmax")
+    ap.add_argument("--e2-jmax", type=int, default=9, help="e2: even grids n = 2^j for 2 <= j <= jmax")
     ap.add_argument("--c5-train", type=int, default=2048, help="c5: training cells")
     ap.add_argument("--c5-steps", type=int, default=1500, help="c5: Adam steps")
     ap.add_argument("--c5-test", type=int, default=256, help="c5: held-out cells")
@@ -292,6 +295,8 @@ def main():
         return run_c5(args)
     if args.workload == "e1":
         return run_e1(args)
+    if args.workload == "e2":
+        return run_e2(args)
     N = (313, 313)
     B = args.cells
     # inputs resident in HBM: Fourier data of A and A^-1 for every cell
@@ -623,57 +628,108 @@ def smooth_odd_at_least(n):
         m += 2
 
 
+def _ga_and_gani(H, cell, n, M, grid=None, closed=False):
+    """One grid of the paper's square experiments: the Ga bounds on Z_n and the
+    paper's Algorithm on the GaNi grid `grid` (n, or the even n + 1), FP64,
+    residual rule 1e-8; each timed after a warm-up solve."""
+    import numpy as np
+    import torch
+    pb = H.problem_from_cell(cell, (n, n), precision="fp64", M=(M, M))
+    pb.solve_bounds(tol=1e-8)                      # warm-up: graphs, plans
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ga = pb.solve_bounds(tol=1e-8)
+    torch.cuda.synchronize()
+    t_ga = time.perf_counter() - t0
+    pb.set_gani_from_cell(cell, grid=grid, closed=closed)
+    pb.solve_bounds(tol=1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gn = pb.solve_bounds(tol=1e-8)
+    AHN, BHN = pb.gani_matrices(gn["fields_primal"], gn["fields_dual"])
+    torch.cuda.synchronize()
+    t_gn = time.perf_counter() - t0
+    del pb
+    it = lambda r: [i["iters"] for i in r["info_primal"] + r["info_dual"]]
+    row = dict(Ga=dict(A_up=ga["A_up"][0, 0], A_low=ga["A_low"][0, 0], D=ga["D"][0, 0], iters=it(ga),
+                       ms=round(1e3 * t_ga, 2)),
+               GaNi=dict(A_HN=AHN[0, 0], inv_B_HN=float(np.linalg.inv(BHN)[0, 0]), A_up=gn["A_up"][0, 0],
+                         A_low=gn["A_low"][0, 0], D=gn["D"][0, 0], iters=it(gn), ms=round(1e3 * t_gn, 2)))
+    return row, t_ga + t_gn
+
+
+def _square_cell(half, rho):
+    import numpy as np
+    import homgen
+    cell = homgen.Inclusions(d=2, Y=np.array([2.0, 2.0]), A0=np.eye(2))
+    cell.add("rect", [0.0, 0.0], [2 * half, 2 * half], (1.0 + rho) * np.eye(2))
+    return cell
+
+
 def run_e1(args):
     """The paper's odd-grid experiment: cell (-1, 1)^2, square inclusion
     |x_a| < 3/5 of coefficient (1 + rho) I in I, rho in {10, 1e3}, N = 5 3^j.
     For every grid: the Galerkin scheme with exact integration (Ga) and the
     paper's Algorithm (GaNi solve, exact bounds of its minimisers), FP64, the
     residual rule at 1e-8 of the paper's Convergence-criteria remark."""
-    import numpy as np
-    import torch
-    import homgen
     import paper_1404_3614_amd as H
     rows = []
     t_all = 0.0
     pairs = 0
     for rho in (10.0, 1e3):
-        cell = homgen.Inclusions(d=2, Y=np.array([2.0, 2.0]), A0=np.eye(2))
-        cell.add("rect", [0.0, 0.0], [1.2, 1.2], (1.0 + rho) * np.eye(2))
+        cell = _square_cell(0.6, rho)
         for j in range(args.e1_jmax + 1):
             n = 5 * 3 ** j
             M = smooth_odd_at_least(2 * n - 1)
-            pb = H.problem_from_cell(cell, (n, n), precision="fp64", M=(M, M))
-            pb.solve_bounds(tol=1e-8)                      # warm-up: graphs, plans
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ga = pb.solve_bounds(tol=1e-8)
-            torch.cuda.synchronize()
-            t_ga = time.perf_counter() - t0
-            pb.set_gani_from_cell(cell)
-            pb.solve_bounds(tol=1e-8)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            gn = pb.solve_bounds(tol=1e-8)
-            AHN, BHN = pb.gani_matrices(gn["fields_primal"], gn["fields_dual"])
-            torch.cuda.synchronize()
-            t_gn = time.perf_counter() - t0
-            t_all += t_ga + t_gn
+            row, dt = _ga_and_gani(H, cell, n, M)
+            t_all += dt
             pairs += 2
-            it = lambda r: [i["iters"] for i in r["info_primal"] + r["info_dual"]]
-            rows.append(dict(rho=rho, N=n, M=M,
-                             Ga=dict(A_up=ga["A_up"][0, 0], A_low=ga["A_low"][0, 0], D=ga["D"][0, 0], iters=it(ga),
-                                     ms=round(1e3 * t_ga, 2)),
-                             GaNi=dict(A_HN=AHN[0, 0], inv_B_HN=float(np.linalg.inv(BHN)[0, 0]),
-                                       A_up=gn["A_up"][0, 0], A_low=gn["A_low"][0, 0], D=gn["D"][0, 0],
-                                       iters=it(gn), ms=round(1e3 * t_gn, 2))))
-            print(f"[e1] rho {rho:g} N {n} M {M}: Ga [{ga['A_low'][0, 0]:.6f}, {ga['A_up'][0, 0]:.6f}] "
-                  f"GaNi A_HN {AHN[0, 0]:.6f} [{gn['A_low'][0, 0]:.6f}, {gn['A_up'][0, 0]:.6f}] "
-                  f"({1e3 * t_ga:.1f} / {1e3 * t_gn:.1f} ms)", file=sys.stderr, flush=True)
-            del pb
+            rows.append(dict(rho=rho, N=n, M=M, **row))
+            ga, gn = row["Ga"], row["GaNi"]
+            print(f"[e1] rho {rho:g} N {n} M {M}: Ga [{ga['A_low']:.6f}, {ga['A_up']:.6f}] "
+                  f"GaNi A_HN {gn['A_HN']:.6f} [{gn['A_low']:.6f}, {gn['A_up']:.6f}] "
+                  f"({ga['ms']:.1f} / {gn['ms']:.1f} ms)", file=sys.stderr, flush=True)
     line = _line(args, pairs / t_all, t_all, 1,
                  "E1: cell (-1,1)^2, square |x_a| < 3/5 of (1 + rho) I in I, rho in {10, 1e3}, N = 5 3^j, "
                  "Ga and GaNi (the paper's Algorithm) on each grid, FP64, residual rule 1e-8",
                  dict(grids=rows), dtype="f64")
+    line["config"]["tol"] = 1e-8
+    line["config"]["precision"] = "fp64"
+    print(json.dumps(line), flush=True)
+
+
+def run_e2(args):
+    """The paper's even-grid experiment: cell (-1, 1)^2, the open square
+    |x_a| < 3/4 (S1) and the closed square |x_a| <= 3/4 (S2) of coefficient
+    (1 + rho) I in I, rho in {10, 1e3}, GaNi grids n = 2^j.  The GaNi fields
+    are the trigonometric polynomials of the reduced set, Z_{n-1}; per grid:
+    A_{H,N}, B_{H,N}^-1 (a duality gap on even grids), the exact bounds of the
+    minimisers, and the Ga bounds on the same space Z_{n-1}.  FP64, residual
+    rule 1e-8."""
+    import paper_1404_3614_amd as H
+    rows = []
+    t_all = 0.0
+    pairs = 0
+    for topo, closed in (("S1", False), ("S2", True)):
+        for rho in (10.0, 1e3):
+            cell = _square_cell(0.75, rho)
+            for j in range(2, args.e2_jmax + 1):
+                g = 2 ** j
+                n = g - 1
+                M = smooth_odd_at_least(2 * n - 1)
+                row, dt = _ga_and_gani(H, cell, n, M, grid=(g, g), closed=closed)
+                t_all += dt
+                pairs += 2
+                rows.append(dict(cell=topo, rho=rho, grid=g, N=n, M=M, **row))
+                ga, gn = row["Ga"], row["GaNi"]
+                print(f"[e2] {topo} rho {rho:g} grid {g} (fields {n}, M {M}): GaNi A_HN {gn['A_HN']:.6f} "
+                      f"B_HN^-1 {gn['inv_B_HN']:.6f} bounds [{gn['A_low']:.6f}, {gn['A_up']:.6f}]; "
+                      f"Ga [{ga['A_low']:.6f}, {ga['A_up']:.6f}] ({ga['ms']:.1f} / {gn['ms']:.1f} ms)",
+                      file=sys.stderr, flush=True)
+    line = _line(args, pairs / t_all, t_all, 1,
+                 "E2: cell (-1,1)^2, open square |x_a| < 3/4 (S1) and closed |x_a| <= 3/4 (S2) of (1 + rho) I in I, "
+                 "rho in {10, 1e3}, GaNi on even grids n = 2^j (fields on Z_{n-1}) and Ga on Z_{n-1}, FP64, "
+                 "residual rule 1e-8", dict(grids=rows), dtype="f64")
     line["config"]["tol"] = 1e-8
     line["config"]["precision"] = "fp64"
     print(json.dumps(line), flush=True)

@@ -183,7 +183,8 @@ hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n
 
 /* Device-side Fourier coefficients of a pixel/voxel image (Remark inclusion
  * summed over pixels): pixel i_a along axis a covers
- * [-Y_a/2 + i_a Y_a/P_a, -Y_a/2 + (i_a+1) Y_a/P_a); P_a must be of the form 3^p 5^q.
+ * [-Y_a/2 + i_a Y_a/P_a, -Y_a/2 + (i_a+1) Y_a/P_a); P_a must have factors 2, 3 and 5
+ * only (a P-point transform of the image).
  * phase: host int32 array (P0 x P1 (x P2), row-major) of phase ids;
  * phase_A: host nphase x d x d.  inverse = 1 uses the inverse phase matrices.
  * out: device, Ahat layout of hom_setup. */
@@ -196,21 +197,28 @@ hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t
  * coefficient is the block-diagonal matrix of point values A(x_N^k)
  * (eq. FD_A_GaNi; the dual uses A^-1(x_N^k), eq. FD_inverse_matrix_equality),
  * and step (iii) evaluates the guaranteed bounds of those minimisers exactly
- * (hom_bounds, unchanged).  N-point transforms: every N_a must have factors 3
- * and 5 only (e.g. the paper's N = 5 3^j); the bounds need the quadrature grid
- * of hom_desc.M (any odd 3/5-smooth M >= 2N - 1).
+ * (hom_bounds, unchanged).  The GaNi grid G is the problem's N (odd grids) or
+ * the even N + 1 (general grids, Sec. 4.4): on an even grid the spaces E_N =
+ * G^E_{N,0}[X_N] and J_N drop the Nyquist frequencies, so their fields are the
+ * trigonometric polynomials of the reduced set, which is the problem's odd Z_N,
+ * and the solve truncates the grid's Nyquist content after each product.  G_a
+ * must have factors 2, 3 and 5 only (e.g. the paper's N = 5 3^j or 2^j); the
+ * bounds need the quadrature grid of hom_desc.M (any odd 3/5-smooth
+ * M >= 2N - 1).
  *
- * Point values on the N grid, x_a = Y_a k_a / N_a (k in Z_N, eq.
- * grid_points), of a matrix-inclusion cell (arguments as hom_coef_inclusions)
+ * Point values on a grid of hom_desc.N points per axis (odd or even here),
+ * x_a = Y_a k_a / N_a with -N_a/2 <= k_a < N_a/2 (eqs. grid_points,
+ * index_sets), of a matrix-inclusion cell (arguments as hom_coef_inclusions)
  * or of a pixel image (as hom_coef_pixels).  A point belongs to a box iff
- * |x_a - c_a| < h_a / 2 on every axis, to a ball iff |x - c| < R, with
- * periodic minimum-image differences: interfaces belong to the matrix.
+ * |x_a - c_a| < h_a / 2 on every axis (<= with closed = 1: the paper's closed
+ * square of its even-grid experiment), to a ball iff |x - c| < R, with
+ * periodic minimum-image differences: otherwise interfaces belong to the matrix.
  * out: device FP64 [ncoef][N0][N1]([N2]), row-major over the physical axes
  * (2D: [ncoef][N0][N1]); components as hom_desc.ncoef; inverse = 1 gives the
  * values of A^-1. */
 hom_status hom_sample_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
                                  const double* center, const double* size, const double* A_in, int32_t inverse,
-                                 double* out, void* stream);
+                                 int32_t closed, double* out, void* stream);
 hom_status hom_sample_pixels(const hom_desc* desc, const int32_t* P, const int32_t* phase, int32_t nphase,
                              const double* phase_A, int32_t inverse, double* out, void* stream);
 
@@ -223,18 +231,20 @@ hom_status hom_sample_pixels(const hom_desc* desc, const int32_t* P, const int32
  * A0 + (k/16)(A1 - A0) is the smoothed medium (hom_coef_pixels, hom_sample_pixels). */
 hom_status hom_smooth_pixels(const int32_t* P, const int32_t* f, int32_t* out, void* stream);
 
-/* Device workspace bytes of hom_set_gani (alignment 256). */
-hom_status hom_gani_workspace_bytes(const hom_desc* desc, size_t* bytes);
+/* Device workspace bytes of hom_set_gani for the GaNi grid `grid` (host,
+ * d entries, each N_a or N_a + 1; NULL: N), alignment 256. */
+hom_status hom_gani_workspace_bytes(const hom_desc* desc, const int32_t* grid, size_t* bytes);
 
-/* Switch later solves and hom_apply of pb to GaNi: AN, BN are the point
- * values of A and of A^-1 (layout of hom_sample_*, device, read during the
- * call).  ws: device workspace of hom_gani_workspace_bytes bytes, kept until
+/* Switch later solves and hom_apply of pb to GaNi on the grid `grid` (as
+ * above): AN, BN are the point values of A and of A^-1 on that grid (layout
+ * of hom_sample_*, device, read during the call).  ws: device workspace of hom_gani_workspace_bytes bytes, kept until
  * hom_clear_gani or hom_destroy (it holds the values, their FP32 copies, the
  * N-point DFT of the values on the stored half of Z_N, which gives the
  * right-hand side, and twiddles).  The solves then stop and report as before;
  * the energy in hom_info is the GaNi energy.  Batches reject GaNi problems
  * (HOM_E_INVALID).  HOM_E_UNSUPPORTED_SIZE when an N_a has other factors. */
-hom_status hom_set_gani(hom_problem* pb, const double* AN, const double* BN, void* ws, size_t ws_bytes);
+hom_status hom_set_gani(hom_problem* pb, const int32_t* grid, const double* AN, const double* BN, void* ws,
+                        size_t ws_bytes);
 
 /* Back to the exact (Ga) operator for later solves. */
 hom_status hom_clear_gani(hom_problem* pb);
@@ -242,8 +252,8 @@ hom_status hom_clear_gani(hom_problem* pb);
 /* GaNi homogenized matrices A_{H,N}, B_{H,N} (eq. GaNi): the trapezoidal-rule
  * energies of primal and dual fields of the unit loads (host arrays of d
  * device pointers, as hom_bounds), row-major d x d into A_HN and B_HN (host).
- * For odd grids A_{H,N} = B_{H,N}^-1 at the GaNi minimisers.  Requires GaNi
- * mode. */
+ * For odd grids A_{H,N} = B_{H,N}^-1 at the GaNi minimisers; on even grids
+ * B_{H,N}^-1 <= A_{H,N} (Proposition FD_even_problem).  Requires GaNi mode. */
 hom_status hom_gani_matrices(hom_problem* pb, const double* const* primal, const double* const* dual,
                              double* A_HN, double* B_HN);
 

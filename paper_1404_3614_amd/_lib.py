@@ -94,12 +94,12 @@ EXPORTS = {
     "hom_problem_set_stop": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double]),
     "hom_sample_inclusions": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
                                           C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                          C.c_int32, C.c_void_p, C.c_void_p]),
+                                          C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
     "hom_sample_pixels": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
                                       C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p]),
-    "hom_gani_workspace_bytes": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_size_t)]),
+    "hom_gani_workspace_bytes": (C.c_int32, [C.POINTER(Desc), C.c_void_p, C.POINTER(C.c_size_t)]),
     "hom_smooth_pixels": (C.c_int32, [C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p]),
-    "hom_set_gani": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
+    "hom_set_gani": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
     "hom_clear_gani": (C.c_int32, [C.c_void_p]),
     "hom_gani_matrices": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]),

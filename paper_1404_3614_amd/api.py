@@ -126,9 +126,10 @@ def coef_pixels(cell, N, ncoef, inverse=False, stream=None, M=None):
     return out
 
 
-def sample_cell(cell, N, ncoef=None, inverse=False, stream=None):
-    """Point values of A (or A^-1) at the N-grid points of a cell, on the device
-    (hom_sample_inclusions / hom_sample_pixels): float64 [ncoef][*N]."""
+def sample_cell(cell, N, ncoef=None, inverse=False, stream=None, closed=False):
+    """Point values of A (or A^-1) at the points of the grid N (odd or even) of a
+    cell, on the device (hom_sample_inclusions / hom_sample_pixels): float64
+    [ncoef][*N]; closed: box faces belong to the inclusion."""
     d = cell.d
     N = tuple(int(n) for n in (N if np.iterable(N) else [N] * d))
     ncoef = cell_ncoef(cell) if ncoef is None else ncoef
@@ -155,7 +156,7 @@ def sample_cell(cell, N, ncoef=None, inverse=False, stream=None):
     Ain = np.ascontiguousarray(np.array(cell.A, float).reshape(-1) if n else np.zeros(1))
     A0 = np.ascontiguousarray(np.asarray(cell.A0, float).reshape(-1))
     st = L.load().hom_sample_inclusions(C.byref(ds), dp(A0), n, kind, dp(cen), dp(siz), dp(Ain), int(inverse),
-                                        C.c_void_p(out.data_ptr()), _stream_ptr(stream))
+                                        int(bool(closed)), C.c_void_p(out.data_ptr()), _stream_ptr(stream))
     L.check(st, "hom_sample_inclusions")
     return out
 
@@ -309,22 +310,26 @@ class Problem:
         L.check(L.load().hom_net_input(self.h, C.c_void_p(out.data_ptr())), "hom_net_input")
         return out
 
-    def set_gani(self, AN, BN):
-        """GaNi mode (hom_set_gani): later solves use the point values AN, BN of
-        A and A^-1 on the N grid (device float64 [ncoef][*N])."""
+    def set_gani(self, AN, BN, grid=None):
+        """GaNi mode (hom_set_gani) on the grid `grid` (default N; N + 1 per axis
+        for the even grid whose reduced frequencies are Z_N): later solves use the
+        point values AN, BN of A and A^-1 there (device float64 [ncoef][*grid])."""
+        g = None if grid is None else (C.c_int32 * 3)(*(list(grid) + [1] * (3 - len(grid))))
         n = C.c_size_t()
-        L.check(L.load().hom_gani_workspace_bytes(C.byref(self.desc), C.byref(n)), "hom_gani_workspace_bytes")
+        L.check(L.load().hom_gani_workspace_bytes(C.byref(self.desc), g, C.byref(n)), "hom_gani_workspace_bytes")
         self.gani_ws = torch.empty(n.value + 256, dtype=torch.uint8, device=_dev())
         off = (-self.gani_ws.data_ptr()) % 256
         self.stream.wait_stream(torch.cuda.current_stream())
-        L.check(L.load().hom_set_gani(self.h, C.c_void_p(AN.data_ptr()), C.c_void_p(BN.data_ptr()),
+        L.check(L.load().hom_set_gani(self.h, g, C.c_void_p(AN.data_ptr()), C.c_void_p(BN.data_ptr()),
                                       C.c_void_p(self.gani_ws.data_ptr() + off), n.value), "hom_set_gani")
+        self.gani_grid = tuple(self.N if grid is None else grid)
 
-    def set_gani_from_cell(self, cell):
-        """GaNi mode with the point values of a cell (sample_cell)."""
-        AN = sample_cell(cell, self.N, self.ncoef, False, self.stream)
-        BN = sample_cell(cell, self.N, self.ncoef, True, self.stream)
-        self.set_gani(AN, BN)
+    def set_gani_from_cell(self, cell, grid=None, closed=False):
+        """GaNi mode with the point values of a cell on `grid` (sample_cell)."""
+        grid = tuple(self.N if grid is None else grid)
+        AN = sample_cell(cell, grid, self.ncoef, False, self.stream, closed)
+        BN = sample_cell(cell, grid, self.ncoef, True, self.stream, closed)
+        self.set_gani(AN, BN, grid)
 
     def clear_gani(self):
         L.check(L.load().hom_clear_gani(self.h), "hom_clear_gani")

@@ -38,6 +38,31 @@ bool smooth35(int M, Plan* pl) {
   return v == 1;
 }
 
+// Plan for lengths 2^a 3^b 5^c (the transforms of even GaNi grids): radix-4
+// stages for pairs of twos, one radix-2 stage for an odd power, then 5s and 3s.
+bool smooth235(int M, Plan* pl) {
+  int n = 0;
+  int v = M;
+  while (v % 4 == 0 && n < kMaxStages) {
+    pl->r[n++] = 4;
+    v /= 4;
+  }
+  if (v % 2 == 0 && n < kMaxStages) {
+    pl->r[n++] = 2;
+    v /= 2;
+  }
+  while (v % 5 == 0 && n < kMaxStages) {
+    pl->r[n++] = 5;
+    v /= 5;
+  }
+  while (v % 3 == 0 && n < kMaxStages) {
+    pl->r[n++] = 3;
+    v /= 3;
+  }
+  pl->n = n;
+  return v == 1;
+}
+
 int env_int(const char* name, int def) {
   const char* s = std::getenv(name);
   return s ? std::atoi(s) : def;
@@ -104,6 +129,7 @@ struct GaniData {
   Cx<float>* tw32[3] = {};
   Cx<double>* scratch = nullptr;   // [nc][Nt] complex
   Plan plan[3] = {};
+  int grid[3] = {};                // GaNi grid on internal axes: N (odd) or N + 1 (even; fields on Z_N = its Z^r)
   hipGraphExec_t graph[2][kMaxLoads + 1] = {};
 };
 
@@ -370,10 +396,10 @@ Geo make_geo_gani(const hom_problem* pb, int dual, int L, bool fp32, int P_overr
   const Sizes& z = pb->z;
   size_t Nt = 1;
   for (int a = 0; a < 3; ++a) {
-    g.M[a] = z.N[a];
+    g.M[a] = pb->gani.grid[a];
     g.pl[a] = pb->gani.plan[a];
     g.tw[a] = fp32 ? (const void*)pb->gani.tw32[a] : (const void*)pb->gani.tw64[a];
-    Nt *= (size_t)z.N[a];
+    Nt *= (size_t)g.M[a];
   }
   g.rowG = g.rowThreads = g.apTP = g.apHX = g.apAll = 0;
   g.pmaj = 0;
@@ -1134,7 +1160,7 @@ hom_status hom_gani_matrices(hom_problem* pb, const double* const* primal, const
   return HOM_OK;
 }
 
-size_t gani_carve(const hom_desc* desc, const Sizes& z, GaniData* gd, char* base) {
+size_t gani_carve(const hom_desc* desc, const Sizes& z, const int* grid, GaniData* gd, char* base) {
   size_t off = 0;
   auto take = [&](size_t bytes) -> size_t {
     const size_t o = off;
@@ -1143,7 +1169,7 @@ size_t gani_carve(const hom_desc* desc, const Sizes& z, GaniData* gd, char* base
   };
   auto ptr = [&](size_t o) -> char* { return base ? base + o : nullptr; };
   const int nc = z.nc;
-  const size_t Nt = (size_t)z.N[0] * z.N[1] * z.N[2];
+  const size_t Nt = (size_t)grid[0] * grid[1] * grid[2];
   const bool mixed = desc->precision == HOM_MIXED;
   for (int k = 0; k < 2; ++k) {
     size_t o = take(nc * Nt * sizeof(double));
@@ -1158,9 +1184,9 @@ size_t gani_carve(const hom_desc* desc, const Sizes& z, GaniData* gd, char* base
     if (gd) gd->ahat[k] = (Cx<double>*)ptr(o);
   }
   for (int a = 0; a < 3; ++a) {
-    size_t o = take(z.N[a] * sizeof(Cx<double>));
+    size_t o = take(grid[a] * sizeof(Cx<double>));
     if (gd) gd->tw64[a] = (Cx<double>*)ptr(o);
-    o = take(z.N[a] * sizeof(Cx<float>));
+    o = take(grid[a] * sizeof(Cx<float>));
     if (gd) gd->tw32[a] = (Cx<float>*)ptr(o);
   }
   size_t o = take(nc * Nt * sizeof(Cx<double>));
@@ -1176,26 +1202,52 @@ hom_status hom_smooth_pixels(const int32_t* P, const int32_t* f, int32_t* out, v
   return HOM_OK;
 }
 
-hom_status hom_gani_workspace_bytes(const hom_desc* desc, size_t* bytes) {
+// GaNi grid on internal axes from the caller's physical grid (NULL: N); every
+// grid[a] is N_a or the even N_a + 1 with factors 2, 3 and 5 only.
+hom_status gani_grid(const hom_desc* desc, const Sizes& z, const int32_t* grid, int* gi, Plan* plans) {
+  const int d = desc->d;
+  int phys[3] = {0, 0, 0};
+  for (int a = 0; a < d; ++a) phys[a] = grid ? grid[a] : desc->N[a];
+  if (d == 2) {
+    gi[0] = phys[0];
+    gi[1] = 1;
+    gi[2] = phys[1];
+  } else {
+    for (int a = 0; a < 3; ++a) gi[a] = phys[a];
+  }
+  for (int a = 0; a < 3; ++a) {
+    if (gi[a] != z.N[a] && gi[a] != z.N[a] + 1) return HOM_E_UNSUPPORTED_SIZE;
+    if (gi[a] > z.M[a]) return HOM_E_UNSUPPORTED_SIZE;  // the passes' buffers hold the quadrature grid
+    if (gi[a] == 1) {
+      plans[a].n = 0;
+    } else if (!smooth235(gi[a], &plans[a])) {
+      return HOM_E_UNSUPPORTED_SIZE;
+    }
+  }
+  return HOM_OK;
+}
+
+hom_status hom_gani_workspace_bytes(const hom_desc* desc, const int32_t* grid, size_t* bytes) {
   if (!bytes) return HOM_E_INVALID;
   hom_status s = validate_desc(desc, 1);
   if (s != HOM_OK) return s;
   Sizes z;
   Plan pl[3];
   if (!fill_sizes(desc, 1, &z, pl)) return HOM_E_INVALID;
-  for (int a = 0; a < 3; ++a) {
-    Plan p;
-    if (z.N[a] > 1 && !smooth35(z.N[a], &p)) return HOM_E_UNSUPPORTED_SIZE;
-  }
-  *bytes = gani_carve(desc, z, nullptr, nullptr);
+  int gi[3];
+  Plan gp[3];
+  s = gani_grid(desc, z, grid, gi, gp);
+  if (s != HOM_OK) return s;
+  *bytes = gani_carve(desc, z, gi, nullptr, nullptr);
   return HOM_OK;
 }
 
-hom_status hom_set_gani(hom_problem* pb, const double* AN, const double* BN, void* ws, size_t ws_bytes) {
+hom_status hom_set_gani(hom_problem* pb, const int32_t* grid, const double* AN, const double* BN, void* ws,
+                        size_t ws_bytes) {
   if (!pb || !AN || !BN || !ws) return HOM_E_INVALID;
   if (((uintptr_t)ws) % kAlign) return HOM_E_WORKSPACE;
   size_t need = 0;
-  hom_status s = hom_gani_workspace_bytes(&pb->desc, &need);
+  hom_status s = hom_gani_workspace_bytes(&pb->desc, grid, &need);
   if (s != HOM_OK) return s;
   if (ws_bytes < need) return HOM_E_WORKSPACE;
   GaniData& gd = pb->gani;
@@ -1209,28 +1261,24 @@ hom_status hom_set_gani(hom_problem* pb, const double* AN, const double* BN, voi
         gd.graph[k][l] = nullptr;
       }
   gd.on = false;
-  gani_carve(&pb->desc, z, &gd, (char*)ws);
-  for (int a = 0; a < 3; ++a) {
-    if (z.N[a] == 1) {
-      gd.plan[a].n = 0;
-    } else if (!smooth35(z.N[a], &gd.plan[a])) {
-      return HOM_E_UNSUPPORTED_SIZE;
-    }
-    HIPCHK(launch_twiddles(gd.tw64[a], gd.tw32[a], z.N[a], st));
-  }
+  s = gani_grid(&pb->desc, z, grid, gd.grid, gd.plan);
+  if (s != HOM_OK) return s;
+  gani_carve(&pb->desc, z, gd.grid, &gd, (char*)ws);
+  for (int a = 0; a < 3; ++a) HIPCHK(launch_twiddles(gd.tw64[a], gd.tw32[a], gd.grid[a], st));
   const int nc = z.nc;
-  const size_t Nt = (size_t)z.N[0] * z.N[1] * z.N[2];
+  const int* G = gd.grid;
+  const size_t Nt = (size_t)G[0] * G[1] * G[2];
   Geo g = make_geo_gani(pb, 0, 1, false);
   for (int k = 0; k < 2; ++k) {
     const double* src = k == 0 ? AN : BN;
     HIPCHK(hipMemcpyAsync(gd.coef64[k], src, nc * Nt * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(launch_real_to_cx(gd.coef64[k], gd.scratch, nc * Nt, 1.0, st));
     if (gd.coef32[k]) HIPCHK(launch_coef_real(gd.scratch, gd.coef64[k], gd.coef32[k], (long)(nc * Nt), st));
-    // Fourier coefficients of the point values: the N-point DFT over 1 / |N| (Z_N part)
-    HIPCHK(launch_line_fft<double>(gd.scratch, nc, z.N[0], z.N[1] * z.N[2], gd.plan[0], gd.tw64[0], 0, st));
-    if (z.N[1] > 1)
-      HIPCHK(launch_line_fft<double>(gd.scratch, nc * z.N[0], z.N[1], z.N[2], gd.plan[1], gd.tw64[1], 0, st));
-    HIPCHK(launch_line_fft<double>(gd.scratch, nc * z.N[0] * z.N[1], z.N[2], 1, gd.plan[2], gd.tw64[2], 0, st));
+    // Fourier coefficients of the point values: the grid DFT over the number of points, kept on
+    // Z_N (the Nyquist frequencies of an even grid are dropped with the truncation)
+    if (G[0] > 1) HIPCHK(launch_line_fft<double>(gd.scratch, nc, G[0], G[1] * G[2], gd.plan[0], gd.tw64[0], 0, st));
+    if (G[1] > 1) HIPCHK(launch_line_fft<double>(gd.scratch, nc * G[0], G[1], G[2], gd.plan[1], gd.tw64[1], 0, st));
+    if (G[2] > 1) HIPCHK(launch_line_fft<double>(gd.scratch, nc * G[0] * G[1], G[2], 1, gd.plan[2], gd.tw64[2], 0, st));
     HIPCHK(launch_scale_cx(gd.scratch, nc * Nt, 1.0 / (double)Nt, st));
     HIPCHK(launch_extract_half(g, gd.scratch, gd.ahat[k], nc, st));
   }
@@ -1307,7 +1355,7 @@ hom_status sample_sizes(const hom_desc* desc, int* Nint) {
   if (desc->ncoef != 1 && desc->ncoef != d * (d + 1) / 2) return HOM_E_INVALID;
   for (int a = 0; a < d; ++a) {
     if (!(desc->Y[a] > 0.0) || !std::isfinite(desc->Y[a])) return HOM_E_INVALID;
-    if (desc->N[a] < 1 || desc->N[a] % 2 == 0 || desc->N[a] > 8193) return HOM_E_UNSUPPORTED_SIZE;
+    if (desc->N[a] < 1 || desc->N[a] > 8193) return HOM_E_UNSUPPORTED_SIZE;
   }
   Nint[0] = desc->N[0];
   Nint[1] = d == 3 ? desc->N[1] : 1;
@@ -1363,7 +1411,7 @@ hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n
 
 hom_status hom_sample_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
                                  const double* center, const double* size, const double* A_in, int32_t inverse,
-                                 double* out, void* stream) {
+                                 int32_t closed, double* out, void* stream) {
   int Nint[3];
   hom_status s = sample_sizes(desc, Nint);
   if (s != HOM_OK) return s;
@@ -1380,7 +1428,8 @@ hom_status hom_sample_inclusions(const hom_desc* desc, const double* A0, int32_t
   s = incl_upload(inc, A0c, st, &dev);
   if (s != HOM_OK) return s;
   hom_status rc = HOM_OK;
-  if (launch_sample_incl(Nint, Yint, nc, (const double*)dev, n_incl, (char*)dev + 64, out, st) != hipSuccess ||
+  if (launch_sample_incl(Nint, Yint, nc, (const double*)dev, n_incl, (char*)dev + 64, closed != 0, out, st) !=
+          hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     rc = HOM_E_DEVICE;
   (void)hipFree(dev);
@@ -1443,7 +1492,7 @@ hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t
       pp[a].n = 0;
       continue;
     }
-    if (!smooth35(Pint[a], &pp[a])) return HOM_E_UNSUPPORTED_SIZE;
+    if (!smooth235(Pint[a], &pp[a])) return HOM_E_UNSUPPORTED_SIZE;
   }
   const size_t Pt = (size_t)Pint[0] * Pint[1] * Pint[2];
   std::vector<double> comp((size_t)nphase * 6);

@@ -172,7 +172,7 @@ hipError_t launch_pixel_factor(int d, const int* Mint, const int* Pint, int nc, 
 size_t incl_dev_size();
 // Point values of the coefficient on the N grid (internal axes, [nc][N0 N1 N2]).
 hipError_t launch_sample_incl(const int* Nint, const double* Yint, int nc, const double* A0c, int n_incl,
-                              const void* dev_incl, double* out, hipStream_t st);
+                              const void* dev_incl, bool closed, double* out, hipStream_t st);
 hipError_t launch_sample_pixels(const int* Nint, const double* Yint, const int* Pint, int nc, const double* img,
                                 double* out, hipStream_t st);
 // out = s * in as complex values with zero imaginary part; a *= s.

@@ -15,7 +15,7 @@
 //                               onto range G^E / G^J by T(k)^T, CG direction update,
 //                               <r, C r> partial
 //
-// FFTs are self-sorting (Stockham) radix-3/5 passes on lines staged in LDS,
+// FFTs are self-sorting (Stockham) radix-2/3/4/5 passes on lines staged in LDS,
 // in place with register staging: every stage loads its butterfly inputs into
 // registers, synchronises, then stores the outputs.  The doubled-grid field
 // never goes to HBM: only the intermediates with one pruned axis do.
@@ -28,6 +28,23 @@ namespace hom {
 ExtTiming g_ext_timing;
 
 // ------------------------------------------------------------------ FFT
+template <typename R>
+__device__ __forceinline__ void bfly2(Cx<R>* v) {
+  const Cx<R> a = v[0];
+  v[0] = a + v[1];
+  v[1] = a - v[1];
+}
+
+// X_k = sum_n x_n w^(n k), w = exp(sgn 2 pi i / 4) = sgn i
+template <typename R>
+__device__ __forceinline__ void bfly4(Cx<R>* v, R sgn) {
+  const Cx<R> a = v[0] + v[2], b = v[0] - v[2], c = v[1] + v[3], e = imul(v[1] - v[3], sgn);
+  v[0] = a + c;
+  v[2] = a - c;
+  v[1] = b + e;
+  v[3] = b - e;
+}
+
 template <typename R>
 __device__ __forceinline__ void bfly3(Cx<R>* v, R sgn) {
   const R s3 = (R)0.86602540378443864676;
@@ -101,8 +118,12 @@ __device__ void lds_fft(Cx<R>* buf, int nl, int M, const Plan& pl, const Cx<R>* 
         }
         if (Rr == 5)
           bfly5(v[i], sgn);
-        else
+        else if (Rr == 3)
           bfly3(v[i], sgn);
+        else if (Rr == 4)
+          bfly4(v[i], sgn);
+        else
+          bfly2(v[i]);
         const int base = (j / Ns) * Ns * Rr + k;
 #pragma unroll
         for (int r = 0; r < 5; ++r)
@@ -1199,10 +1220,10 @@ size_t incl_dev_size() { return sizeof(InclDev); }
 // Grid point x_a = Y_a k_a / N_a, k in Z_N (eq. grid_points).  A point is in a
 // box inclusion iff |x_a - c_a| < h_a / 2 on every axis, in a ball iff
 // |x - c|^2 < R^2, with periodic minimum-image differences (open sets: a point
-// on an interface belongs to the matrix).
+// on an interface belongs to the matrix; closed = 1 puts box faces inside).
 __global__ void k_sample_incl(int N0, int N1, int N2, double Y0, double Y1, double Y2, int nc,
                               const double* __restrict__ A0c, int n_incl, const InclDev* __restrict__ inc,
-                              double* __restrict__ out) {
+                              int closed, double* __restrict__ out) {
   const size_t Nt = (size_t)N0 * N1 * N2;
   const int Nn[3] = {N0, N1, N2};
   const double Y[3] = {Y0, Y1, Y2};
@@ -1222,7 +1243,7 @@ __global__ void k_sample_incl(int N0, int N1, int N2, double Y0, double Y1, doub
       bool inside;
       if (I.kind == 0) {
         inside = true;
-        for (int a = 0; a < 3; ++a) inside = inside && fabs(dl[a]) < 0.5 * I.h[a];
+        for (int a = 0; a < 3; ++a) inside = inside && (closed ? fabs(dl[a]) <= 0.5 * I.h[a] : fabs(dl[a]) < 0.5 * I.h[a]);
       } else {
         inside = ((0.0 + dl[0] * dl[0]) + dl[1] * dl[1]) + dl[2] * dl[2] < I.h[0] * I.h[0];
       }
@@ -1263,10 +1284,10 @@ __global__ void k_scale_cx(Cx<double>* __restrict__ a, size_t n, double s) {
 }
 
 hipError_t launch_sample_incl(const int* Nint, const double* Yint, int nc, const double* A0c, int n_incl,
-                              const void* dev_incl, double* out, hipStream_t st) {
+                              const void* dev_incl, bool closed, double* out, hipStream_t st) {
   const size_t Nt = (size_t)Nint[0] * Nint[1] * Nint[2];
   hipLaunchKernelGGL(k_sample_incl, dim3(grid_for(Nt)), dim3(kBlock), 0, st, Nint[0], Nint[1], Nint[2], Yint[0],
-                     Yint[1], Yint[2], nc, A0c, n_incl, (const InclDev*)dev_incl, out);
+                     Yint[1], Yint[2], nc, A0c, n_incl, (const InclDev*)dev_incl, closed ? 1 : 0, out);
   return hipGetLastError();
 }
 

@@ -204,3 +204,114 @@ def test_smoothing_filter_matches_oracle_and_bounds():
     rg = pb.solve_bounds(tol=1e-10)
     AHN, BHN = pb.gani_matrices(rg["fields_primal"], rg["fields_dual"])
     assert relerr(AHN, g["A_HN"]) <= 1e-9 and relerr(rg["A_up"], g["A_up"]) <= 1e-9
+
+
+# ------------------------------------------------------------------ even grids
+def _paper_square_closed(rho):
+    """The paper's even-grid variant: the closed square |x_a| <= 3/4 on (-1, 1)^2."""
+    c = homgen.Inclusions(d=2, Y=np.array([2.0, 2.0]), A0=np.eye(2))
+    c.add("rect", [0.0, 0.0], [1.5, 1.5], (1.0 + rho) * np.eye(2))
+    return c
+
+
+def _odd_smooth_at_least(n):
+    m = n if n % 2 else n + 1
+    while True:
+        v = m
+        for p in (3, 5):
+            while v % p == 0:
+                v //= p
+        if v == 1:
+            return m
+        m += 2
+
+
+EVEN_SAMPLES = [
+    ("square_open_G8", lambda: _paper_square_closed(10.0), (8, 8), False),
+    ("square_closed_G16", lambda: _paper_square_closed(10.0), (16, 16), True),
+    ("aniso_G12x10", _aniso_rects, (12, 10), True),
+    ("pix_G16x20", lambda: homgen.pixel_cell(seed=9, P=8, values=(1.0, 30.0)), (16, 20), False),
+    ("sph3d_G8x6x10", lambda: homgen.sphere_cell(seed=10, n=6, anisotropic=True), (8, 6, 10), False),
+]
+
+
+@pytest.mark.parametrize("name,make,G,closed", EVEN_SAMPLES, ids=[s[0] for s in EVEN_SAMPLES])
+def test_point_values_on_even_grids_match_oracle(name, make, G, closed):
+    """Grid points x_a = Y_a k_a / G_a for -G_a/2 <= k_a < G_a/2, open or closed
+    boxes: the inside/outside decisions are bitwise those of the oracle."""
+    from oracle import even
+    H = _H()
+    cell = make()
+    nc = H.api.cell_ncoef(cell)
+    for inverse in (False, True):
+        got = H.sample_cell(cell, G, nc, inverse=inverse, closed=closed).cpu().numpy()
+        ref = _components(even.point_values(cell, G, inverse=inverse, closed=closed), nc)
+        assert got.shape == ref.shape
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+EVEN_GANI = [
+    # (name, cell, GaNi grid, closed boxes)
+    ("paper_S2_rho10_G8", lambda: _paper_square_closed(10.0), (8, 8), True),
+    ("paper_S1_rho10_G16", lambda: _paper_square_closed(10.0), (16, 16), False),
+    ("paper_S2_rho1e3_G32", lambda: _paper_square_closed(1e3), (32, 32), True),
+    ("aniso_G16x9", _aniso_rects, (16, 9), True),
+    ("pix_G20x16", lambda: homgen.pixel_cell(seed=11, P=10, values=(1.0, 50.0)), (20, 16), False),
+    ("pix_G32", lambda: homgen.pixel_cell(seed=14, P=16, values=(1.0, 20.0)), (32, 32), False),
+    ("sph3d_G8", lambda: homgen.sphere_cell(seed=12, n=4, anisotropic=True), (8, 8, 8), False),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,make,G,closed", EVEN_GANI, ids=[g[0] for g in EVEN_GANI])
+def test_gani_even_grids_match_oracle(name, make, G, closed, precision):
+    """GaNi on a grid with even sizes (Sec. 4.4): the fields are the trigonometric
+    polynomials of the reduced set Z_G^r, the problem's odd grid N = G - 1 on the
+    even axes, and the Nyquist frequencies are dropped after each product.
+    A_{H,N}, B_{H,N} and the exact bounds of the minimisers against the oracle;
+    the duality gap B_{H,N}^-1 <= A_{H,N} of Proposition FD_even_problem."""
+    from oracle import even
+    H = _H()
+    cell = make()
+    N = tuple(g - 1 if g % 2 == 0 else g for g in G)
+    M = tuple(_odd_smooth_at_least(2 * n - 1) for n in N)
+    ref = even.gani_general(cell, G, tol=1e-11, closed=closed, tilde=False)
+    pb = H.problem_from_cell(cell, N, precision=precision, M=M)
+    pb.set_gani_from_cell(cell, grid=G, closed=closed)
+    # FP64: a residual tolerance below the contrast-amplified error of the bounds
+    tol_cg = 1e-12 if precision == "fp64" else 1e-8
+    r = pb.solve_bounds(tol=tol_cg)
+    AHN, BHN = pb.gani_matrices(r["fields_primal"], r["fields_dual"])
+    tol = 1e-9 if precision == "fp64" else 1e-6
+    errs = dict(A_HN=relerr(AHN, ref["A_HN"]), B_HN=relerr(BHN, ref["B_HN"]), A_up=relerr(r["A_up"], ref["A_up"]),
+                A_low=relerr(r["A_low"], ref["A_low"]))
+    its = [i["iters"] for i in r["info_primal"] + r["info_dual"]]
+    print(f"[gani-even] {name} {precision}: {', '.join(f'{k} {v:.1e}' for k, v in errs.items())}; "
+          f"iterations {its} oracle {ref['iters']}", flush=True)
+    assert errs["A_HN"] <= tol and errs["B_HN"] <= tol
+    a_min, a_max = H.cell_eig_range(cell)
+    tol_b = tol if precision == "fp64" else tol * np.sqrt(a_max / a_min)
+    assert errs["A_up"] <= tol_b and errs["A_low"] <= tol_b
+    ep = np.array([i["energy"] for i in r["info_primal"]])
+    assert np.abs(ep - np.diag(AHN)).max() <= tol_b * np.linalg.norm(AHN, 2)
+    # B_{H,N}^-1 <= A_{H,N}, with a gap where some axis is even
+    n = np.linalg.norm(AHN, 2)
+    gap = np.linalg.eigvalsh(AHN - np.linalg.inv(BHN))
+    gref = np.linalg.eigvalsh(ref["A_HN"] - np.linalg.inv(ref["B_HN"]))
+    assert gap.min() >= -1e-8 * n and gap.max() > 0.5 * gref.max()
+    assert np.linalg.eigvalsh(r["A_up"] - r["A_low"]).min() >= -1e-9 * n
+
+
+def test_gani_grid_validation():
+    H = _H()
+    cell = _paper_square_closed(10.0)
+    pb = H.problem_from_cell(cell, (15, 15), precision="mixed", M=(45, 45))
+    # a grid is N or N + 1 per axis; 14 = 2 * 7 has no radix-2/3/5 transform
+    for G in ((17, 16), (16, 14), (14, 15)):
+        with pytest.raises(H.HomError):
+            pb.set_gani_from_cell(cell, grid=G)
+    pb13 = H.problem_from_cell(cell, (13, 13), precision="mixed", M=(25, 25))
+    with pytest.raises(H.HomError):
+        pb13.set_gani_from_cell(cell, grid=(14, 14))
+    pb.set_gani_from_cell(cell, grid=(16, 15), closed=True)
+    pb.solve_bounds(tol=1e-8)

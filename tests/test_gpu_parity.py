@@ -217,13 +217,22 @@ def test_deterministic_and_graph_equals_eager(monkeypatch):
         assert bool((u == v).all()) and bool((u == w).all())
 
 
+def _voxels(P, seed):
+    rng = np.random.default_rng(seed)
+    return homgen.Pixels(d=3, Y=np.array([1.0, 0.8, 1.2]), phase=rng.integers(0, 3, size=P),
+                         phase_A=np.stack([homgen.random_spd(rng, 3, 1.0, 5.0) for _ in range(3)]))
+
+
 def test_setup_coefficients_match_oracle():
     # device Fourier coefficients (hom_coef_inclusions / hom_coef_pixels) against the oracle's
     H = _H()
     from oracle import coefficients as co
     for cell, N in ((homgen.sphere_cell(seed=1, n=7, anisotropic=True), (5, 13, 13)),
                     (homgen.pixel_cell(seed=4, P=25, values=(2.0, 7.0)), (13, 41)),
-                    (aniso_squares(2), (13, 13))):
+                    (aniso_squares(2), (13, 13)),
+                    # images of 2^k pixels: the image transform has radix-2/4 stages
+                    (homgen.pixel_cell(seed=6, P=16, values=(1.0, 9.0)), (13, 23)),
+                    (_voxels((8, 4, 10), seed=7), (5, 13, 5))):
         M = tuple(2 * n - 1 for n in N)
         Ah, Bh, nc = H.coef_from_cell(cell, N)
         ref = co.fourier_coefficients(cell, M)
