@@ -204,6 +204,8 @@ bool fill_sizes(const hom_desc* desc, int max_loads, Sizes* z, Plan* plan) {
   return true;
 }
 
+int packs(int L, int d) { return (L * d + 1) / 2; }
+
 hom_status validate_desc(const hom_desc* desc, int max_loads) {
   if (!desc) return HOM_E_INVALID;
   if (desc->d != 2 && desc->d != 3) return HOM_E_INVALID;
@@ -220,10 +222,19 @@ hom_status validate_desc(const hom_desc* desc, int max_loads) {
     Plan pl;
     if (!smooth35(Ma, &pl)) return HOM_E_UNSUPPORTED_SIZE;
   }
+  // LDS of the generic passes: the column pass holds one column of every pack
+  // (FP64 for the bounds, whose packs carry d loads), the row passes stage the
+  // stored rows of every load
+  const int M0 = desc->M[0] ? desc->M[0] : 2 * desc->N[0] - 1;
+  const int Nlast = desc->N[d - 1];
+  const size_t cs = desc->precision == HOM_MIXED ? sizeof(float) * 2 : sizeof(double) * 2;
+  const int L = std::max(max_loads, d);
+  if ((size_t)M0 * packs(d, d) * 2 * sizeof(double) > kLdsMax) return HOM_E_UNSUPPORTED_SIZE;
+  if ((size_t)M0 * packs(max_loads, d) * cs > kLdsMax) return HOM_E_UNSUPPORTED_SIZE;
+  if ((size_t)L * std::max(1, d - 1) * Nlast * 2 * sizeof(double) > kLdsMax) return HOM_E_UNSUPPORTED_SIZE;
   return HOM_OK;
 }
 
-int packs(int L, int d) { return (L * d + 1) / 2; }
 
 // Points per apply-pass block: largest count with LDS within budget and the
 // per-thread butterfly registers within 16 sets.

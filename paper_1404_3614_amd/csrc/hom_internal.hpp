@@ -12,6 +12,7 @@ namespace hom {
 
 constexpr int kMaxLoads = 3;      // loads solved together per coefficient field
 constexpr int kMaxPacks = 5;      // ceil(3 loads * 3 components / 2)
+constexpr size_t kLdsMax = 160 * 1024;  // LDS bytes per workgroup (gfx950)
 constexpr int kMaxStages = 12;    // radix-3/5 stages per FFT length
 constexpr int kBlock = 256;       // threads per block of every pipeline kernel
 

@@ -19,6 +19,7 @@
 // in place with register staging: every stage loads its butterfly inputs into
 // registers, synchronises, then stores the outputs.  The doubled-grid field
 // never goes to HBM: only the intermediates with one pruned axis do.
+#include <cstdlib>
 #include "hom_device.hpp"
 
 #include <hip/hip_ext.h>
@@ -276,18 +277,26 @@ __global__ __launch_bounds__(kBlock) void k_first(Geo g, const UnitDev* __restri
       }
       o = cx((R)(X[0].x - X[1].y), (R)(X[0].y + X[1].x));
     }
-    buf[j * nl + l] = o;
+    if constexpr (MAXB == 0) {
+      // long lines: the row transform runs afterwards over HBM (k_unit_lines)
+      const int i0 = line ? ixn(-h0, N0) : h0, i1 = line ? i1B : i1A;
+      reinterpret_cast<Cx<R>*>(U.bufA)[(((size_t)i0 * N1 + i1) * M2 + j) * P + pk] = o;
+    } else {
+      buf[j * nl + l] = o;
+    }
   }
-  __syncthreads();
-  lds_fft<R, MAXB>(buf, nl, M2, g.pl[2], reinterpret_cast<const Cx<R>*>(g.tw[2]), true);
+  if constexpr (MAXB > 0) {
+    __syncthreads();
+    lds_fft<R, MAXB>(buf, nl, M2, g.pl[2], reinterpret_cast<const Cx<R>*>(g.tw[2]), true);
 
-  Cx<R>* out = reinterpret_cast<Cx<R>*>(U.bufA);
-  const int i0A = h0, i0B = ixn(-h0, N0);
-  for (int t = tid; t < M2 * nl; t += kBlock) {
-    const int j = t / nl, l = t - (t / nl) * nl;
-    const int line = l / P, pk = l - line * P;
-    const int i0 = line ? i0B : i0A, i1 = line ? i1B : i1A;
-    out[(((size_t)i0 * N1 + i1) * M2 + j) * P + pk] = buf[j * nl + l];
+    Cx<R>* out = reinterpret_cast<Cx<R>*>(U.bufA);
+    const int i0A = h0, i0B = ixn(-h0, N0);
+    for (int t = tid; t < M2 * nl; t += kBlock) {
+      const int j = t / nl, l = t - (t / nl) * nl;
+      const int line = l / P, pk = l - line * P;
+      const int i0 = line ? i0B : i0A, i1 = line ? i1B : i1A;
+      out[(((size_t)i0 * N1 + i1) * M2 + j) * P + pk] = buf[j * nl + l];
+    }
   }
 }
 
@@ -354,17 +363,28 @@ __global__ __launch_bounds__(kBlock) void k_last(Geo g, const UnitDev* __restric
   for (int l = 0; l < L; ++l) any |= s_act[l];
   if (!any) return;  // uniform over the block
 
-  // ---- load both lines and transform forward
+  // ---- load both lines and transform forward (long lines: transformed in HBM
+  // beforehand by k_unit_lines, read in place)
   const Cx<R>* in = reinterpret_cast<const Cx<R>*>(U.bufA);
   const int i0A = h0, i0B = ixn(-h0, N0);
-  for (int t = tid; t < M2 * nl; t += kBlock) {
-    const int j = t / nl, l = t - (t / nl) * nl;
-    const int line = l / P, pk = l - line * P;
-    const int i0 = line ? i0B : i0A, i1 = line ? i1B : i1A;
-    buf[j * nl + l] = in[(((size_t)i0 * N1 + i1) * M2 + j) * P + pk];
+  if constexpr (MAXB > 0) {
+    for (int t = tid; t < M2 * nl; t += kBlock) {
+      const int j = t / nl, l = t - (t / nl) * nl;
+      const int line = l / P, pk = l - line * P;
+      const int i0 = line ? i0B : i0A, i1 = line ? i1B : i1A;
+      buf[j * nl + l] = in[(((size_t)i0 * N1 + i1) * M2 + j) * P + pk];
+    }
+    __syncthreads();
+    lds_fft<R, MAXB>(buf, nl, M2, g.pl[2], reinterpret_cast<const Cx<R>*>(g.tw[2]), false);
   }
-  __syncthreads();
-  lds_fft<R, MAXB>(buf, nl, M2, g.pl[2], reinterpret_cast<const Cx<R>*>(g.tw[2]), false);
+  auto line_at = [&](int pos, int line, int pk) -> Cx<R> {
+    if constexpr (MAXB > 0) {
+      return buf[pos * nl + line * P + pk];
+    } else {
+      const int i0 = line ? i0B : i0A, i1 = line ? i1B : i1A;
+      return in[(((size_t)i0 * N1 + i1) * M2 + pos) * P + pk];
+    }
+  };
 
   // ---- epilogue on the stored entries of row A (and of row B when it is stored)
   double dp0 = 0.0, dp1 = 0.0, dp2 = 0.0;
@@ -385,8 +405,8 @@ __global__ __launch_bounds__(kBlock) void k_last(Geo g, const UnitDev* __restric
       Cx<double> wv[3];
       for (int gam = 0; gam < d; ++gam) {
         const int f = l * d + gam, pk = f >> 1;
-        const Cx<R> za = buf[posK * nl + lineK * P + pk];
-        const Cx<R> zb = buf[posM * nl + lineM * P + pk];
+        const Cx<R> za = line_at(posK, lineK, pk);
+        const Cx<R> zb = line_at(posM, lineM, pk);
         if ((f & 1) == 0)
           wv[gam] = cx(((double)za.x + (double)zb.x) * sc_m, ((double)za.y - (double)zb.y) * sc_m);
         else
@@ -610,6 +630,33 @@ __global__ __launch_bounds__(kBlock) void k_line_fft(Cx<R>* data, int outer, int
   for (int t = tid; t < Lm * tile; t += kBlock) {
     const int j = t / tile, e = t - (t / tile) * tile;
     if (e < te) data[base + (size_t)j * inner + e0 + e] = buf[j * tile + e];
+  }
+}
+
+// Row transform (length M2) of every row of each unit's line buffer
+// [N0][N1][M2][P], in place: blocks of `tile` packs of one row; grid.x = rows *
+// ceil(P / tile), grid.z = unit.  Used by the row passes when their lines do not
+// fit in LDS.
+template <typename R, int MAXB>
+__global__ __launch_bounds__(kBlock) void k_unit_lines(Geo g, const UnitDev* __restrict__ units, int tile, int nbi,
+                                                       int inverse) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<R>* buf = reinterpret_cast<Cx<R>*>(smem);
+  const UnitDev& U = units[blockIdx.z];
+  Cx<R>* data = reinterpret_cast<Cx<R>*>(U.bufA);
+  const int M2 = g.M[2], P = g.P, tid = threadIdx.x;
+  const int row = blockIdx.x / nbi, e0 = (blockIdx.x - row * nbi) * tile;
+  const int te = min(tile, P - e0);
+  const size_t base = (size_t)row * M2 * P;
+  for (int t = tid; t < M2 * tile; t += kBlock) {
+    const int j = t / tile, e = t - (t / tile) * tile;
+    buf[j * tile + e] = (e < te) ? data[base + (size_t)j * P + e0 + e] : cx((R)0, (R)0);
+  }
+  __syncthreads();
+  lds_fft<R, MAXB>(buf, tile, M2, g.pl[2], reinterpret_cast<const Cx<R>*>(g.tw[2]), inverse != 0);
+  for (int t = tid; t < M2 * tile; t += kBlock) {
+    const int j = t / tile, e = t - (t / tile) * tile;
+    if (e < te) data[base + (size_t)j * P + e0 + e] = buf[j * tile + e];
   }
 }
 
@@ -987,7 +1034,7 @@ static int max_butterflies(const Plan& pl, int M, int nl) {
       case 16: fn_ = (const void*)KERN<R, 16>; break;                                                \
       default: return hipErrorInvalidValue;                                                          \
     }                                                                                                \
-    if ((LDS) > 160 * 1024) return hipErrorInvalidValue;                                             \
+    if ((LDS) > kLdsMax) return hipErrorInvalidValue;                                                \
     hipError_t e_ = hipFuncSetAttribute(fn_, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(LDS)); \
     if (e_ != hipSuccess) return e_;                                                                 \
     switch (mb_) {                                                                                   \
@@ -1000,6 +1047,50 @@ static int max_butterflies(const Plan& pl, int M, int nl) {
     return hipGetLastError();                                                                        \
   } while (0)
 
+// The fused row passes hold both lines of a row pair (2P complex lines of M2)
+// in LDS; beyond the LDS size or the butterfly registers they run as a gather
+// (or epilogue) kernel plus a separate row transform over HBM.
+template <typename R>
+static bool rows_fit(const Geo& g, size_t extra) {
+  if (std::getenv("HOM_LONG_ROWS")) return false;  // the split form at any size (tests)
+  const int nl = 2 * g.P;
+  const size_t lds = extra + (size_t)g.M[2] * nl * sizeof(Cx<R>);
+  return lds <= kLdsMax && (max_butterflies(g.pl[2], g.M[2], nl) + kBlock - 1) / kBlock <= 16;
+}
+
+template <typename R>
+static hipError_t launch_unit_lines(const Geo& g, const UnitDev* units, int nunits, int inverse, hipStream_t st) {
+  int tile = 1;
+  while (tile * 2 <= g.P && (size_t)g.M[2] * tile * 2 * sizeof(Cx<R>) <= 48 * 1024) tile *= 2;
+  const int nbi = (g.P + tile - 1) / tile;
+  const long rows = (long)g.N[0] * g.N[1];
+  if (rows * nbi > 0x7fffffffL) return hipErrorInvalidValue;
+  const size_t lds = (size_t)g.M[2] * tile * sizeof(Cx<R>);
+  HOM_DISPATCH(k_unit_lines, max_butterflies(g.pl[2], g.M[2], tile), lds, dim3((unsigned)(rows * nbi), 1, nunits), g,
+               units, tile, nbi, inverse);
+}
+
+template <typename R>
+static hipError_t launch_first_long(const Geo& g, const UnitDev* units, int nunits, int mode, int jstep,
+                                    const int* iter_base, size_t lds, hipStream_t st) {
+  if (lds > kLdsMax) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void*)k_first<R, 0>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  HOM_LAUNCH1((k_first<R, 0>), dim3(g.Q, 1, nunits), lds, g, units, mode, jstep, iter_base);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_unit_lines<R>(g, units, nunits, 1, st);
+}
+
+template <typename R>
+static hipError_t launch_last_long(const Geo& g, const UnitDev* units, int nunits, int mode, int jstep,
+                                   const int* iter_base, hipStream_t st) {
+  hipError_t e = launch_unit_lines<R>(g, units, nunits, 0, st);
+  if (e != hipSuccess) return e;
+  HOM_LAUNCH1((k_last<R, 0>), dim3(g.Q, 1, nunits), 0, g, units, mode, jstep, iter_base);
+  return hipGetLastError();
+}
+
 template <typename R>
 hipError_t launch_first(const Geo& g, const UnitDev* units, int nunits, int mode, int jstep, const int* iter_base,
                         hipStream_t st) {
@@ -1008,7 +1099,9 @@ hipError_t launch_first(const Geo& g, const UnitDev* units, int nunits, int mode
     if (fast_row(true, g, units, nunits, mode, jstep, iter_base, st, &e)) return e;
   }
   const int nl = 2 * g.P;
-  const size_t lds = align16((size_t)g.L * g.m * g.N[2] * sizeof(Cx<double>)) + (size_t)g.M[2] * nl * sizeof(Cx<R>);
+  const size_t staged = align16((size_t)g.L * g.m * g.N[2] * sizeof(Cx<double>));
+  if (!rows_fit<R>(g, staged)) return launch_first_long<R>(g, units, nunits, mode, jstep, iter_base, staged, st);
+  const size_t lds = staged + (size_t)g.M[2] * nl * sizeof(Cx<R>);
   HOM_DISPATCH(k_first, max_butterflies(g.pl[2], g.M[2], nl), lds, dim3(g.Q, 1, nunits), g, units, mode, jstep,
                iter_base);
 }
@@ -1021,6 +1114,7 @@ hipError_t launch_last(const Geo& g, const UnitDev* units, int nunits, int mode,
     if (fast_row(false, g, units, nunits, mode, jstep, iter_base, st, &e)) return e;
   }
   const int nl = 2 * g.P;
+  if (!rows_fit<R>(g, 0)) return launch_last_long<R>(g, units, nunits, mode, jstep, iter_base, st);
   const size_t lds = (size_t)g.M[2] * nl * sizeof(Cx<R>);
   HOM_DISPATCH(k_last, max_butterflies(g.pl[2], g.M[2], nl), lds, dim3(g.Q, 1, nunits), g, units, mode, jstep,
                iter_base);

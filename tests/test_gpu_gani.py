@@ -315,3 +315,27 @@ def test_gani_grid_validation():
         pb13.set_gani_from_cell(cell, grid=(14, 14))
     pb.set_gani_from_cell(cell, grid=(16, 15), closed=True)
     pb.solve_bounds(tol=1e-8)
+
+
+def test_paper_even_grid_bounds_at_grid_1024():
+    """The paper's own values (tests/golden/paper_even_grid_bounds.json): the
+    exact bounds of the GaNi minimisers of the open and closed squares, contrast
+    1e3, GaNi grid 1024 (fields on Z_1023, quadrature grid 2187, FP64)."""
+    import json
+    import os
+    H = _H()
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_even_grid_bounds.json")))
+    n = gold["grid"]
+    for topo, closed in (("S1", False), ("S2", True)):
+        cell = _paper_square_closed(1e3)
+        pb = H.problem_from_cell(cell, (n - 1, n - 1), precision="fp64", M=(2187, 2187))
+        pb.set_gani_from_cell(cell, grid=(n, n), closed=closed)
+        r = pb.solve_bounds(tol=1e-10)
+        ref = gold["values"][topo]
+        eu = abs(r["A_up"][0, 0] - ref["A_up"]) / ref["A_up"]
+        el = abs(r["A_low"][0, 0] - ref["A_low"]) / ref["A_low"]
+        print(f"[paper-even] {topo}: A_up {r['A_up'][0, 0]:.10f} (paper {ref['A_up']}, rel {eu:.1e}); "
+              f"A_low {r['A_low'][0, 0]:.10f} (paper {ref['A_low']}, rel {el:.1e})", flush=True)
+        # the paper stops CG at a relative residual 1e-8; its bounds are first order in that error
+        assert eu <= 2e-7 and el <= 2e-7
+        assert abs(r["A_up"][0, 1]) <= 1e-9 * ref["A_up"] and abs(r["A_up"][0, 0] - r["A_up"][1, 1]) <= 1e-9 * ref["A_up"]
