@@ -24,7 +24,8 @@ the Ga quadrature of galerkin.py on the odd set.
 
 Pinned by tests/test_oracle_even.py: the projections (identities of Lemma
 matrix_orthogonality_E), Proposition FD_even_problem (i) and (iii), odd grids
-against oracle/gani.py, homogeneous media.
+against oracle/gani.py, homogeneous media, and the bound values the paper gives
+for its open square at contrast 1e3 on the grid 1024.
 """
 from __future__ import annotations
 

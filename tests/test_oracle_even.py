@@ -6,6 +6,7 @@ E2 Proposition FD_even_problem: A_{H,N} = Btilde^-1 and B_{H,N}^-1 = Atilde on e
    grids, with B_{H,N}^-1 <= A_{H,N}; the gap is nonzero on even grids.
 E3 odd grids reduce to oracle/gani.py; homogeneous media give A0 on any grid.
 E4 the exact bounds of the minimisers enclose the Ga bounds of the same space Z_N^r.
+E5 the paper's own bound values for the open square at contrast 1e3 on the grid 1024.
 """
 import numpy as np
 import pytest
@@ -94,3 +95,18 @@ def test_E4_exact_bounds_enclose_the_ga_bounds_of_the_reduced_space():
     n = np.linalg.norm(g["A_up"], 2)
     assert np.linalg.eigvalsh(r["A_up"] - g["A_up"]).min() >= -1e-10 * n
     assert np.linalg.eigvalsh(g["A_low"] - r["A_low"]).min() >= -1e-10 * n
+
+
+def test_E5_paper_values_on_the_grid_1024():
+    """The paper's own numbers (tests/golden/paper_even_grid_bounds.json): the
+    upper and lower bounds of the GaNi minimisers of the open square S1 at
+    contrast 1e3 on the grid 1024, with the paper's residual criterion 1e-8
+    (remark on convergence criteria).  About two minutes on the CPU."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_even_grid_bounds.json")))
+    n = gold["grid"]
+    r = even.gani_general(_square(1e3), (n, n), tol=gold["residual_tolerance"], closed=False, tilde=False)
+    ref = gold["values"]["S1"]
+    assert abs(r["A_up"][0, 0] - ref["A_up"]) <= 1e-8 * ref["A_up"]
+    assert abs(r["A_low"][0, 0] - ref["A_low"]) <= 1e-8 * ref["A_low"]
