@@ -30,7 +30,7 @@ import numpy as np
 __all__ = [
     "Inclusions", "Pixels", "square_inclusion_cell", "laminate_cell",
     "pixel_cell", "sphere_cell", "random_squares_cell", "random_spheres_cell",
-    "random_spd", "batch_specs", "homogeneous_cell",
+    "random_spd", "batch_specs", "homogeneous_cell", "foam_cell",
 ]
 
 
@@ -207,3 +207,36 @@ def batch_specs(seed0=1404004, n2d=512, n3d=64, Ns2d=(13, 41, 63, 313), N3d=41,
         cell, rho = random_spheres_cell(seed0 + 200000 + i, logrho=logrho)
         out.append((N3d, cell, rho))
     return out
+
+
+def foam_cell(seed, P=1200, porosity=0.5, rmin=0.01, rmax=0.04, values=(0.029, 0.49)):
+    """Foam-like two-phase pixel image on P x P pixels of the unit cell: a
+    solid phase (phase 1, coefficient values[1]) with overlapping circular
+    pores (phase 0, values[0]) of radii uniform in [rmin, rmax], centres
+    uniform, periodic, added until the pore fraction reaches `porosity`.  The
+    default coefficients are the thermal conductivities of fly ash and air of
+    the paper's foam example."""
+    rng = np.random.default_rng(seed)
+    c = (np.arange(P) + 0.5) / P - 0.5               # pixel centres on (-1/2, 1/2)
+    solid = np.ones((P, P), dtype=bool)
+    target = int(round(porosity * P * P))
+    pores = 0
+    while pores < target:
+        cx, cy = rng.random(2) - 0.5
+        r = rng.uniform(rmin, rmax)
+        h = int(math.ceil(r * P)) + 1
+        i0 = int(math.floor((cx + 0.5) * P))
+        j0 = int(math.floor((cy + 0.5) * P))
+        ii = np.arange(i0 - h, i0 + h + 1) % P
+        jj = np.arange(j0 - h, j0 + h + 1) % P
+        dx = c[ii] - cx
+        dx -= np.round(dx)
+        dy = c[jj] - cy
+        dy -= np.round(dy)
+        inside = dx[:, None] ** 2 + dy[None, :] ** 2 < r * r
+        sub = solid[np.ix_(ii, jj)]
+        pores += int(np.count_nonzero(sub & inside))
+        sub &= ~inside
+        solid[np.ix_(ii, jj)] = sub
+    phase_A = np.stack([_eye(2, values[0]), _eye(2, values[1])])
+    return Pixels(d=2, Y=np.ones(2), phase=solid.astype(np.int32), phase_A=phase_A)

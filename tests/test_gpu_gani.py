@@ -259,6 +259,8 @@ EVEN_GANI = [
     ("pix_G20x16", lambda: homgen.pixel_cell(seed=11, P=10, values=(1.0, 50.0)), (20, 16), False),
     ("pix_G32", lambda: homgen.pixel_cell(seed=14, P=16, values=(1.0, 20.0)), (32, 32), False),
     ("sph3d_G8", lambda: homgen.sphere_cell(seed=12, n=4, anisotropic=True), (8, 8, 8), False),
+    # the foam-like image on its own pixel grid (the setting of the paper's foam example)
+    ("foam_G60", lambda: homgen.foam_cell(5, P=60, rmin=0.03, rmax=0.1), (60, 60), False),
 ]
 
 
