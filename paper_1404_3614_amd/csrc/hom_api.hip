@@ -239,7 +239,8 @@ hom_status validate_desc(const hom_desc* desc, int max_loads) {
 // Points per apply-pass block: largest count with LDS within budget and the
 // per-thread butterfly registers within 16 sets.
 int choose_tileA(int M0, int npts, int P, size_t csize, int min_radix) {
-  const size_t budget = (size_t)env_int("HOM_LDS_BUDGET", 80 * 1024);
+  // FP64 blocks are twice the bytes per line: half the budget keeps more of them per CU
+  const size_t budget = (size_t)env_int("HOM_LDS_BUDGET", csize > sizeof(Cx<float>) ? 40 * 1024 : 80 * 1024);
   int best = 1;
   for (int t = 1; t <= 64 && t <= npts; ++t) {
     const size_t lds = (size_t)M0 * t * P * csize;
@@ -1712,6 +1713,8 @@ struct hom_batch {
                                        // captured chunk graphs copy into these)
   hipEvent_t order_ev = nullptr;       // orders the library stream after the caller's
   double* bcollect_dev = nullptr;      // [2][n][9] bounds quadrature sums (workspace)
+  CoefJob* jobs_dev = nullptr;         // [n] coefficient set-up table (workspace)
+  std::vector<CoefJob> host_jobs;
   SolveOut* collect_host = nullptr;    // pinned mirrors
   double* bcollect_host = nullptr;
   double tsum[5] = {0, 0, 0, 0, 0};
@@ -1739,9 +1742,11 @@ static size_t batch_layout(int n, char* base, hom_batch* b) {
   }
   char* cs = take((size_t)2 * n * kMaxLoads * sizeof(SolveOut));
   char* cb = take((size_t)n * 2 * 9 * sizeof(double));
+  char* cj = take((size_t)n * sizeof(CoefJob));
   if (b) {
     b->collect_dev = (SolveOut*)cs;
     b->bcollect_dev = (double*)cb;
+    b->jobs_dev = (CoefJob*)cj;
   }
   return off;
 }
@@ -1945,7 +1950,34 @@ hom_status hom_batch_update_coefficients(hom_batch* b, const void* const* Ahat, 
   if (!b || !Ahat || !Bhat) return HOM_E_INVALID;
   for (int i = 0; i < b->n; ++i)
     if (!Ahat[i] || !Bhat[i]) return HOM_E_INVALID;
-  for (int i = 0; i < b->n; ++i) {
+  // every cell in two transform launches and one extraction launch where the
+  // specialised set-up exists, else cell by cell
+  hom_problem* p0 = b->pbs[0];
+  const Sizes& z = p0->z;
+  const int n = b->n;
+  b->host_jobs.resize(n);
+  for (int i = 0; i < n; ++i) {
+    const hom_problem* pb = b->pbs[i];
+    CoefJob& J = b->host_jobs[i];
+    J.A = reinterpret_cast<const Cx<double>*>(Ahat[i]);
+    J.B = reinterpret_cast<const Cx<double>*>(Bhat[i]);
+    J.scratch = pb->scratch;
+    J.a64 = pb->coef64[0];
+    J.a32 = pb->coef32[0];
+    J.b64 = pb->coef64[1];
+    J.b32 = pb->coef32[1];
+    J.half[0] = pb->ahat_half[0];
+    J.half[1] = pb->ahat_half[1];
+  }
+  hipStream_t st = b->stream;
+  HIPCHK(hipMemcpyAsync(b->jobs_dev, b->host_jobs.data(), (size_t)n * sizeof(CoefJob), hipMemcpyHostToDevice, st));
+  hipError_t e = hipSuccess;
+  if (fast_coef_setup_jobs(z.d, z.M, z.nc, b->jobs_dev, n, p0->tw64[0], st, &e)) {
+    HIPCHK(e);
+    HIPCHK(launch_extract_half_jobs(make_geo(p0, 0, 1, false), b->jobs_dev, n, z.nc, st));
+    return HOM_OK;
+  }
+  for (int i = 0; i < n; ++i) {
     hom_status s = setup_coefficients(b->pbs[i], Ahat[i], Bhat[i]);
     if (s != HOM_OK) return s;
   }

@@ -70,35 +70,56 @@ __device__ __forceinline__ double block_sum(double v, double* sred) {
 // Orthonormal basis of the range of G^E(k) (primal, one column xi/|xi|) or of
 // G^J(k) (dual: d = 2 the rotated normal, d = 3 two tangents), Def. projection.
 __device__ __forceinline__ void basis(const Geo& g, int k0, int k1, int k2, double T[3][2]) {
-  const int kk[3] = {k0, k1, k2};
+  // loops unrolled and axes selected, so every private array has constant indices
   double n[3] = {0.0, 0.0, 0.0};
   double n2 = 0.0;
-  for (int c = 0; c < g.d; ++c) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (c >= g.d) continue;
     const int a = g.phys_axis[c];
-    n[c] = kk[a] * g.iY[a];
+    const int ka = a == 0 ? k0 : (a == 1 ? k1 : k2);
+    const double iy = a == 0 ? g.iY[0] : (a == 1 ? g.iY[1] : g.iY[2]);
+    n[c] = ka * iy;
     n2 += n[c] * n[c];
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c) T[c][0] = T[c][1] = 0.0;
   if (n2 == 0.0) return;
   const double inv = 1.0 / sqrt(n2);
-  for (int c = 0; c < g.d; ++c) n[c] *= inv;
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+    if (c < g.d) n[c] *= inv;
   if (!g.dual) {
-    for (int c = 0; c < g.d; ++c) T[c][0] = n[c];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      if (c < g.d) T[c][0] = n[c];
   } else if (g.d == 2) {
     T[0][0] = -n[1];
     T[1][0] = n[0];
   } else {
     int a = 0;
-    if (fabs(n[1]) < fabs(n[a])) a = 1;
-    if (fabs(n[2]) < fabs(n[a])) a = 2;
-    double t1[3] = {-n[a] * n[0], -n[a] * n[1], -n[a] * n[2]};
-    t1[a] += 1.0;
+    double na = n[0];
+    if (fabs(n[1]) < fabs(na)) {
+      a = 1;
+      na = n[1];
+    }
+    if (fabs(n[2]) < fabs(na)) {
+      a = 2;
+      na = n[2];
+    }
+    double t1[3] = {-na * n[0], -na * n[1], -na * n[2]};
+    if (a == 0)
+      t1[0] += 1.0;
+    else if (a == 1)
+      t1[1] += 1.0;
+    else
+      t1[2] += 1.0;
     const double in1 = 1.0 / sqrt(t1[0] * t1[0] + t1[1] * t1[1] + t1[2] * t1[2]);
     t1[0] *= in1;
     t1[1] *= in1;
     t1[2] *= in1;
     const double t2[3] = {n[1] * t1[2] - n[2] * t1[1], n[2] * t1[0] - n[0] * t1[2], n[0] * t1[1] - n[1] * t1[0]};
+#pragma unroll
     for (int c = 0; c < 3; ++c) {
       T[c][0] = t1[c];
       T[c][1] = t2[c];

@@ -460,12 +460,10 @@ __device__ __forceinline__ double coef_pair_scale(const Cx<double>* A, const Cx<
 }
 
 // Inverse transform along axis 0 (columns of the [M][M] plane): TP columns
-// per block, T threads per column; grid (column blocks, component).
+// per block, T threads per column; grid (column blocks, component[, cell]).
 template <int M, int TP>
-__global__ __launch_bounds__(TP * Cfg<M>::T) void k_coef_cols(const Cx<double>* __restrict__ Ah,
-                                                              const Cx<double>* __restrict__ Bh,
-                                                              Cx<double>* __restrict__ out,
-                                                              const Cx<double>* __restrict__ twg) {
+__device__ __forceinline__ void coef_cols(const Cx<double>* __restrict__ Ah, const Cx<double>* __restrict__ Bh,
+                                          Cx<double>* __restrict__ out, const Cx<double>* __restrict__ twg) {
   constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<double>* tw = reinterpret_cast<Cx<double>*>(smem);  // [M]
@@ -508,15 +506,28 @@ __global__ __launch_bounds__(TP * Cfg<M>::T) void k_coef_cols(const Cx<double>* 
   }
 }
 
+template <int M, int TP>
+__global__ __launch_bounds__(TP * Cfg<M>::T) void k_coef_cols(const Cx<double>* __restrict__ Ah,
+                                                              const Cx<double>* __restrict__ Bh,
+                                                              Cx<double>* __restrict__ out,
+                                                              const Cx<double>* __restrict__ twg) {
+  coef_cols<M, TP>(Ah, Bh, out, twg);
+}
+
+template <int M, int TP>
+__global__ __launch_bounds__(TP * Cfg<M>::T) void k_coef_cols_jobs(const CoefJob* __restrict__ jobs,
+                                                                   const Cx<double>* __restrict__ twg) {
+  const CoefJob& J = jobs[blockIdx.z];
+  coef_cols<M, TP>(J.A, J.B, J.scratch, twg);
+}
+
 // Inverse transform along axis 2 (rows), G rows per block, T threads per row,
 // then the real and imaginary parts split into A_M and B_M (FP64 and FP32).
 template <int M, int G>
-__global__ __launch_bounds__(G * Cfg<M>::T) void k_coef_rows(const Cx<double>* __restrict__ in,
-                                                             const Cx<double>* __restrict__ Ah,
-                                                             const Cx<double>* __restrict__ Bh,
-                                                             double* __restrict__ a64, float* __restrict__ a32,
-                                                             double* __restrict__ b64, float* __restrict__ b32,
-                                                             const Cx<double>* __restrict__ twg) {
+__device__ __forceinline__ void coef_rows(const Cx<double>* __restrict__ in, const Cx<double>* __restrict__ Ah,
+                                          const Cx<double>* __restrict__ Bh, double* __restrict__ a64,
+                                          float* __restrict__ a32, double* __restrict__ b64, float* __restrict__ b32,
+                                          const Cx<double>* __restrict__ twg) {
   constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = Cfg<M>::T;
   extern __shared__ __align__(16) unsigned char smem[];
   Cx<double>* tw = reinterpret_cast<Cx<double>*>(smem);  // [M]
@@ -558,6 +569,23 @@ __global__ __launch_bounds__(G * Cfg<M>::T) void k_coef_rows(const Cx<double>* _
   }
 }
 
+template <int M, int G>
+__global__ __launch_bounds__(G * Cfg<M>::T) void k_coef_rows(const Cx<double>* __restrict__ in,
+                                                             const Cx<double>* __restrict__ Ah,
+                                                             const Cx<double>* __restrict__ Bh,
+                                                             double* __restrict__ a64, float* __restrict__ a32,
+                                                             double* __restrict__ b64, float* __restrict__ b32,
+                                                             const Cx<double>* __restrict__ twg) {
+  coef_rows<M, G>(in, Ah, Bh, a64, a32, b64, b32, twg);
+}
+
+template <int M, int G>
+__global__ __launch_bounds__(G * Cfg<M>::T) void k_coef_rows_jobs(const CoefJob* __restrict__ jobs,
+                                                                  const Cx<double>* __restrict__ twg) {
+  const CoefJob& J = jobs[blockIdx.z];
+  coef_rows<M, G>(J.scratch, J.A, J.B, J.a64, J.a32, J.b64, J.b32, twg);
+}
+
 template <int M>
 struct CoefTiles;
 template <>
@@ -585,6 +613,36 @@ static hipError_t run_coef_setup(int nc, const Cx<double>* Ah, const Cx<double>*
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k2, dim3((M + G - 1) / G, nc), dim3(G * T), lds2, st, scratch, Ah, Bh, a64, a32, b64, b32, tw);
   return hipGetLastError();
+}
+
+template <int M>
+static hipError_t run_coef_setup_jobs(int nc, const CoefJob* jobs, int n, const Cx<double>* tw, hipStream_t st) {
+  constexpr int T = Cfg<M>::T, TP = CoefTiles<M>::TP, G = CoefTiles<M>::G;
+  const size_t lds1 = (size_t)M * sizeof(Cx<double>) * (1 + TP);
+  const size_t lds2 = (size_t)M * sizeof(Cx<double>) * (1 + G);
+  auto k1 = k_coef_cols_jobs<M, TP>;
+  auto k2 = k_coef_rows_jobs<M, G>;
+  hipError_t e = hipFuncSetAttribute((const void*)k1, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds1);
+  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)k2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds2);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k1, dim3((M + TP - 1) / TP, nc, n), dim3(TP * T), lds1, st, jobs, tw);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k2, dim3((M + G - 1) / G, nc, n), dim3(G * T), lds2, st, jobs, tw);
+  return hipGetLastError();
+}
+
+bool fast_coef_setup_jobs(int d, const int* Mz, int nc, const CoefJob* jobs, int n, const Cx<double>* tw,
+                          hipStream_t st, hipError_t* err) {
+  if (std::getenv("HOM_NO_FAST")) return false;
+  if (d != 2 || Mz[0] != Mz[2] || n < 1 || n > 65535) return false;
+  switch (Mz[0]) {
+    case 625: *err = run_coef_setup_jobs<625>(nc, jobs, n, tw, st); return true;
+    case 125: *err = run_coef_setup_jobs<125>(nc, jobs, n, tw, st); return true;
+    case 81: *err = run_coef_setup_jobs<81>(nc, jobs, n, tw, st); return true;
+    case 25: *err = run_coef_setup_jobs<25>(nc, jobs, n, tw, st); return true;
+    default: return false;
+  }
 }
 
 // 2D problems with M0 = M2 in {25, 81, 125, 625}: both coefficients on the

@@ -197,6 +197,23 @@ bool fast_apply_shape_ok(int M, int D, int tp, int hx, int all);
 bool fast_coef_setup(int d, const int* Mz, int nc, const Cx<double>* Ah, const Cx<double>* Bh, Cx<double>* scratch,
                      double* a64, float* a32, double* b64, float* b32, const Cx<double>* tw, hipStream_t st,
                      hipError_t* err);
+// Per-cell pointers of a batched coefficient set-up (a device table, one entry
+// per cell): the Fourier data on Z_M, the transform scratch, the grid values
+// of A and A^-1, and the stored halves of their Z_N parts.
+struct CoefJob {
+  const Cx<double>* A;
+  const Cx<double>* B;
+  Cx<double>* scratch;
+  double* a64;
+  float* a32;
+  double* b64;
+  float* b32;
+  Cx<double>* half[2];
+};
+// The same set-up for n cells of one geometry in two launches (grid z = cell).
+bool fast_coef_setup_jobs(int d, const int* Mz, int nc, const CoefJob* jobs, int n, const Cx<double>* tw,
+                          hipStream_t st, hipError_t* err);
+hipError_t launch_extract_half_jobs(const Geo& g, const CoefJob* jobs, int n, int nc, hipStream_t st);
 
 // Tile shapes of the specialised passes: row pairs and threads per block of the
 // row passes, points per block of the column pass (0 = default).

@@ -268,8 +268,11 @@ __global__ __launch_bounds__(kBlock) void k_first(Geo g, const UnitDev* __restri
         X[s] = cx(0.0, 0.0);
         if (f < L * d) {
           const int lf = f / d, gam = f - (f / d) * d;
-          Cx<double> xv = cx(0.0, 0.0);
-          for (int c = 0; c < m; ++c) xv = xv + rA[(lf * m + c) * N2 + src] * T[gam][c];
+          // row gam of T by selection (constant indices keep T in registers)
+          const double t0 = gam == 0 ? T[0][0] : (gam == 1 ? T[1][0] : T[2][0]);
+          const double t1 = gam == 0 ? T[0][1] : (gam == 1 ? T[1][1] : T[2][1]);
+          Cx<double> xv = rA[(lf * m) * N2 + src] * t0;
+          if (m > 1) xv = xv + rA[(lf * m + 1) * N2 + src] * t1;
           if (line) xv.y = -xv.y;
           if (mode == FIRST_BOUNDS && self && k2 == 0) xv.x += U.E[lf][gam];
           X[s] = xv;
@@ -402,8 +405,10 @@ __global__ __launch_bounds__(kBlock) void k_last(Geo g, const UnitDev* __restric
     basis(g, kk0, kk1, k2, T);
     for (int l = 0; l < L; ++l) {
       if (mode == LAST_CG && !s_act[l]) continue;
-      Cx<double> wv[3];
-      for (int gam = 0; gam < d; ++gam) {
+      Cx<double> wv[3] = {cx(0.0, 0.0), cx(0.0, 0.0), cx(0.0, 0.0)};
+#pragma unroll
+      for (int gam = 0; gam < 3; ++gam) {
+        if (gam >= d) continue;
         const int f = l * d + gam, pk = f >> 1;
         const Cx<R> za = line_at(posK, lineK, pk);
         const Cx<R> zb = line_at(posM, lineM, pk);
@@ -412,9 +417,13 @@ __global__ __launch_bounds__(kBlock) void k_last(Geo g, const UnitDev* __restric
         else
           wv[gam] = cx(((double)za.y + (double)zb.y) * sc_m, -((double)za.x - (double)zb.x) * sc_m);
       }
-      for (int c = 0; c < m; ++c) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (c >= m) continue;
         Cx<double> w = cx(0.0, 0.0);
-        for (int gam = 0; gam < d; ++gam) w = w + wv[gam] * T[gam][c];
+#pragma unroll
+        for (int gam = 0; gam < 3; ++gam)
+          if (gam < d) w = w + wv[gam] * T[gam][c];
         const size_t idx = ((size_t)(c * g.H0 + kk0) * N1 + i1) * N2 + i2;
         double e;
         if (mode == LAST_CG) {
@@ -445,6 +454,34 @@ __global__ __launch_bounds__(kBlock) void k_last(Geo g, const UnitDev* __restric
   for (int l = 0; l < L; ++l) {
     const double s = block_sum(l == 0 ? dp0 : (l == 1 ? dp1 : dp2), s_red);
     if (tid == 0) U.part_d[(size_t)l * g.nbL + blockIdx.x] = s;
+  }
+}
+
+// Per-point coefficient product and FP64 quadrature with the dimension fixed
+// at compile time and the load loops unrolled, so that the per-point arrays
+// are indexed by constants and stay in registers.
+template <typename R, int D>
+__device__ __forceinline__ void point_coef(int nc, int L, const R* a, const R* u, R* w) {
+#pragma unroll
+  for (int l = 0; l < kMaxLoads; ++l)
+    if (l < L) coef_mul<R>(D, nc, a, u + l * D, w + l * D);
+}
+
+template <typename R, int D>
+__device__ __forceinline__ void point_quad(int nc, int L, const R* a, const R* u, double* acc) {
+#pragma unroll
+  for (int la = 0; la < kMaxLoads; ++la) {
+    if (la >= L) continue;
+    R w[D];
+    coef_mul<R>(D, nc, a, u + la * D, w);
+#pragma unroll
+    for (int lb = 0; lb < kMaxLoads; ++lb) {
+      if (lb >= L) continue;
+      double s = 0.0;
+#pragma unroll
+      for (int c = 0; c < D; ++c) s += (double)u[lb * D + c] * (double)w[c];
+      acc[la * kMaxLoads + lb] += s;
+    }
   }
 }
 
@@ -561,16 +598,23 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo g, const UnitDev* __restri
       if (pt >= tp) continue;
       const size_t ci = (size_t)j * npts + p0 + pt;
       R a[6];
-      for (int c = 0; c < nc; ++c) a[c] = coef[c * Mtot + ci];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) a[c] = c < nc ? coef[c * Mtot + ci] : (R)0;
       R u[2 * kMaxPacks], w[2 * kMaxPacks];
-      for (int pk = 0; pk < P; ++pk) {
-        const Cx<R> z = buf[j * nl + pt * P + pk];
+#pragma unroll
+      for (int pk = 0; pk < kMaxPacks; ++pk) {
+        const Cx<R> z = pk < P ? buf[j * nl + pt * P + pk] : cx((R)0, (R)0);
         u[2 * pk] = z.x;
         u[2 * pk + 1] = z.y;
+        w[2 * pk] = w[2 * pk + 1] = (R)0;
       }
-      for (int l = 0; l < L; ++l) coef_mul<R>(d, nc, a, u + l * d, w + l * d);
-      for (int f = L * d; f < 2 * P; ++f) w[f] = (R)0;
-      for (int pk = 0; pk < P; ++pk) buf[j * nl + pt * P + pk] = cx(w[2 * pk], w[2 * pk + 1]);
+      if (d == 2)
+        point_coef<R, 2>(nc, L, a, u, w);
+      else
+        point_coef<R, 3>(nc, L, a, u, w);
+#pragma unroll
+      for (int pk = 0; pk < kMaxPacks; ++pk)
+        if (pk < P) buf[j * nl + pt * P + pk] = cx(w[2 * pk], w[2 * pk + 1]);
     }
     __syncthreads();
     lds_fft<R, MAXB>(buf, nl, M0, g.pl[0], reinterpret_cast<const Cx<R>*>(g.tw[0]), false);
@@ -581,30 +625,30 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo g, const UnitDev* __restri
   } else {
     // FP64 quadrature of the bilinear forms: sum_x v_b(x) . A(x) v_a(x)
     double acc[kMaxLoads * kMaxLoads];
+#pragma unroll
     for (int i = 0; i < kMaxLoads * kMaxLoads; ++i) acc[i] = 0.0;
     for (int t = tid; t < M0 * tileA; t += kBlock) {
       const int j = t / tileA, pt = t - (t / tileA) * tileA;
       if (pt >= tp) continue;
       const size_t ci = (size_t)j * npts + p0 + pt;
       R a[6];
-      for (int c = 0; c < nc; ++c) a[c] = coef[c * Mtot + ci];
-      R u[2 * kMaxPacks], w[2 * kMaxPacks];
-      for (int pk = 0; pk < P; ++pk) {
-        const Cx<R> z = buf[j * nl + pt * P + pk];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) a[c] = c < nc ? coef[c * Mtot + ci] : (R)0;
+      R u[2 * kMaxPacks];
+#pragma unroll
+      for (int pk = 0; pk < kMaxPacks; ++pk) {
+        const Cx<R> z = pk < P ? buf[j * nl + pt * P + pk] : cx((R)0, (R)0);
         u[2 * pk] = z.x;
         u[2 * pk + 1] = z.y;
       }
-      for (int la = 0; la < L; ++la) {
-        coef_mul<R>(d, nc, a, u + la * d, w);
-        for (int lb = 0; lb < L; ++lb) {
-          double s = 0.0;
-          for (int c = 0; c < d; ++c) s += (double)u[lb * d + c] * (double)w[c];
-          acc[la * kMaxLoads + lb] += s;
-        }
-      }
+      if (d == 2)
+        point_quad<R, 2>(nc, L, a, u, acc);
+      else
+        point_quad<R, 3>(nc, L, a, u, acc);
     }
-    for (int i = 0; i < L * kMaxLoads; ++i) {
-      if ((i % kMaxLoads) >= L) continue;
+#pragma unroll
+    for (int i = 0; i < kMaxLoads * kMaxLoads; ++i) {
+      if (i / kMaxLoads >= L || i % kMaxLoads >= L) continue;  // uniform over the block
       const double s = block_sum(acc[i], s_red);
       if (tid == 0) U.part_q[(size_t)blockIdx.x * 9 + i] = s;
     }
@@ -672,13 +716,19 @@ __global__ void k_rhs(Geo g, const UnitDev* __restrict__ units) {
     const int k1 = fr(i1, g.N[1]), k2 = fr(i2, g.N[2]);
     double T[3][2];
     basis(g, h0, k1, k2, T);
+    // loops unrolled with guards: constant indices keep a, v and T in registers
     Cx<double> a[6];
-    for (int c = 0; c < nc; ++c) a[c] = U.ahat[(size_t)c * S + t];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) a[c] = c < nc ? U.ahat[(size_t)c * S + t] : cx(0.0, 0.0);
     for (int l = 0; l < g.L; ++l) {
-      Cx<double> v[3];
-      for (int gam = 0; gam < d; ++gam) {
+      Cx<double> v[3] = {cx(0.0, 0.0), cx(0.0, 0.0), cx(0.0, 0.0)};
+#pragma unroll
+      for (int gam = 0; gam < 3; ++gam) {
+        if (gam >= d) continue;
         Cx<double> s = cx(0.0, 0.0);
-        for (int dl = 0; dl < d; ++dl) {
+#pragma unroll
+        for (int dl = 0; dl < 3; ++dl) {
+          if (dl >= d) continue;
           Cx<double> A;
           if (nc == 1) A = (gam == dl) ? a[0] : cx(0.0, 0.0);
           else if (d == 2) A = (gam == dl) ? a[gam] : a[2];
@@ -693,9 +743,13 @@ __global__ void k_rhs(Geo g, const UnitDev* __restrict__ units) {
         }
         v[gam] = s;
       }
-      for (int c = 0; c < g.m; ++c) {
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        if (c >= g.m) continue;
         Cx<double> s = cx(0.0, 0.0);
-        for (int gam = 0; gam < d; ++gam) s = s + v[gam] * T[gam][c];
+#pragma unroll
+        for (int gam = 0; gam < 3; ++gam)
+          if (gam < d) s = s + v[gam] * T[gam][c];
         U.b[l][(size_t)c * S + t] = cx(-s.x, -s.y);
       }
     }
@@ -909,6 +963,21 @@ __global__ void k_coef_real(const Cx<double>* __restrict__ full, double* __restr
 
 // Z_N part of a Z_M array (stored half), component-major.
 __global__ void k_extract_half(Geo g, const Cx<double>* __restrict__ full, Cx<double>* __restrict__ half, int nc) {
+  const int S = g.S;
+  const size_t Mt = (size_t)g.M[0] * g.M[1] * g.M[2];
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S * nc; t += gridDim.x * blockDim.x) {
+    const int c = t / S, s = t - c * S;
+    const int i2 = s % g.N[2], i1 = (s / g.N[2]) % g.N[1], h0 = s / (g.N[2] * g.N[1]);
+    const int j0 = h0, j1 = padpos(i1, g.N[1], g.M[1]), j2 = padpos(i2, g.N[2], g.M[2]);
+    half[t] = full[c * Mt + ((size_t)j0 * g.M[1] + j1) * g.M[2] + j2];
+  }
+}
+
+// The same for the A and B data of every cell of a batch: grid (blocks, 2, cell).
+__global__ void k_extract_half_jobs(Geo g, const CoefJob* __restrict__ jobs, int nc) {
+  const CoefJob& J = jobs[blockIdx.z];
+  const Cx<double>* full = blockIdx.y ? J.B : J.A;
+  Cx<double>* half = J.half[blockIdx.y];
   const int S = g.S;
   const size_t Mt = (size_t)g.M[0] * g.M[1] * g.M[2];
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S * nc; t += gridDim.x * blockDim.x) {
@@ -1232,6 +1301,8 @@ __global__ void k_collect_bounds(const UnitDev* __restrict__ units, int n, int n
   const int u = t / 9, j = t - u * 9;
   const double* p = units[u].part_q;
   double s = 0.0;
+  // the host's order (q = 0, 1, ...), with the loads of eight terms in flight
+#pragma unroll 8
   for (int q = 0; q < nbA; ++q) s += p[(size_t)q * 9 + j];
   out[t] = s;
 }
@@ -1288,6 +1359,13 @@ hipError_t launch_coef_real(const Cx<double>* full, double* c64, float* c32, lon
 
 hipError_t launch_extract_half(const Geo& g, const Cx<double>* full, Cx<double>* half, int nc, hipStream_t st) {
   hipLaunchKernelGGL(k_extract_half, dim3(grid_for((size_t)g.S * nc)), dim3(kBlock), 0, st, g, full, half, nc);
+  return hipGetLastError();
+}
+
+hipError_t launch_extract_half_jobs(const Geo& g, const CoefJob* jobs, int n, int nc, hipStream_t st) {
+  if (n < 1 || n > 65535) return hipErrorInvalidValue;
+  const unsigned nb = (unsigned)std::min<size_t>(grid_for((size_t)g.S * nc), 1024);
+  hipLaunchKernelGGL(k_extract_half_jobs, dim3(nb, 2, n), dim3(kBlock), 0, st, g, jobs, nc);
   return hipGetLastError();
 }
 
