@@ -25,8 +25,12 @@
  *    results (solves, bounds) synchronise that stream before returning.
  *  - No exception crosses the ABI; every entry point returns hom_status.
  *    Arguments are validated before anything is launched.
- *  - Grid sizes N_a must be odd and M_a = 2 N_a - 1 must be of the form
- *    3^p 5^q (the FFT radices implemented), else HOM_E_UNSUPPORTED_SIZE.
+ *  - Grid sizes N_a must be odd (3 <= N_a <= 4097) and the quadrature grid
+ *    M_a (2 N_a - 1, or hom_desc.M) odd with factors 3 and 5 only (the FFT
+ *    radices of the solve), M_a <= 8193; sizes whose passes cannot hold a
+ *    column of every pack in LDS (2D FP64: M_0 above 5120) are refused too,
+ *    with HOM_E_UNSUPPORTED_SIZE.  Even grids enter only as GaNi grids
+ *    (hom_set_gani) and as sampling grids (hom_sample_*).
  *
  * Spectral layout of a solution ("field") vector.
  *   A field x in E_N (primal) or J_N (dual) is stored by its Fourier
@@ -57,7 +61,8 @@ typedef enum {
   HOM_OK = 0,
   HOM_NOT_CONVERGED = 1,        /* warning: maxit reached; outputs are valid, the bounds still guaranteed */
   HOM_E_INVALID = -1,           /* bad argument (null pointer, d, tolerance, ...) */
-  HOM_E_UNSUPPORTED_SIZE = -2,  /* even N, or M = 2N-1 not of the form 3^p 5^q, or a size class not built */
+  HOM_E_UNSUPPORTED_SIZE = -2,  /* even N, M not odd 3/5-smooth, a size beyond the LDS of the passes, or a
+                                   GaNi grid without a 2/3/5 transform */
   HOM_E_NOT_SPD = -3,           /* CG met <p, C p> <= 0: the coefficient is not SPD */
   HOM_E_DEVICE = -4,            /* a HIP call failed */
   HOM_E_WORKSPACE = -5          /* workspace too small or misaligned */
