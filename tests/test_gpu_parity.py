@@ -303,6 +303,35 @@ def test_update_coefficients_matches_fresh_setup_and_timing_counts():
     assert np.array_equal(swapped[1]["A_low"], first[0]["A_low"])
 
 
+@pytest.mark.parametrize("d,N", [(2, 41), (2, 313), (3, 13)])
+def test_batch_coefficient_update_equals_per_problem_setup(d, N):
+    """hom_batch_update_coefficients sets up every cell in three launches where
+    the specialised 2D set-up exists (cell by cell otherwise); the grid
+    coefficients, and so the bounds, are bitwise those of single set-ups."""
+    H = _H()
+    import torch
+    st = torch.cuda.Stream()
+    n = 3
+    if d == 2:
+        cells = [homgen.pixel_cell(seed=70 + i, P=25, values=(1.0, 5.0 + 20 * i)) for i in range(2 * n)]
+    else:
+        cells = [homgen.sphere_cell(seed=70 + i, n=4, rho=5.0 + 10 * i) for i in range(2 * n)]
+    NN = (N,) * d
+    coefs = [H.coef_from_cell(c, NN) for c in cells]
+    nc = coefs[0][2]
+    assert all(c[2] == nc for c in coefs)
+    probs = [H.Problem(d, NN, cells[i].Y, *coefs[i][:2], precision="mixed", ncoef=nc, max_loads=d, stream=st)
+             for i in range(n)]
+    batch = H.Batch(probs)
+    batch.update_coefficients([coefs[n + i][:2] for i in range(n)])
+    got = batch.solve_bounds(tol=1e-8)
+    for i in range(n):
+        ref = H.Problem(d, NN, cells[n + i].Y, *coefs[n + i][:2], precision="mixed", ncoef=nc, max_loads=d,
+                        stream=st)
+        rb = H.Batch([ref]).solve_bounds(tol=1e-8)[0]
+        assert np.array_equal(got[i]["A_up"], rb["A_up"]) and np.array_equal(got[i]["A_low"], rb["A_low"]), i
+
+
 def test_side_by_side_pair_equals_sequential_solves():
     # the dual on the library's second stream: same kernels, same reductions, so bitwise equal;
     # sequential solves reuse the same captured graphs afterwards
