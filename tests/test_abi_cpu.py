@@ -110,3 +110,23 @@ def test_workspace_grows_with_loads_and_precision():
             assert n.value % 256 == 0
     assert sizes[(0, 2)] > sizes[(0, 1)]
     assert sizes[(1, 1)] != sizes[(0, 1)]
+
+
+def test_sizes_beyond_the_lds_of_the_passes_are_refused():
+    # the column pass holds one FP64 column of every pack (2D bounds: two packs): M0 = 5625
+    # (3^2 5^4) does not fit in 160 KB, M0 = 3125 does; the rows stay within their split form
+    L, lib = _lib()
+    ws = C.c_size_t()
+    for prec in (0, 1):
+        ok = _desc(L, N=(1563, 1563, 1), prec=prec)
+        ok.M[0], ok.M[1] = 3125, 3125
+        assert lib.hom_workspace_bytes(C.byref(ok), 2, C.byref(ws)) == 0
+        big = _desc(L, N=(2813, 13, 1), prec=prec)
+        big.M[0], big.M[1] = 5625, 25
+        assert lib.hom_workspace_bytes(C.byref(big), 2, C.byref(ws)) == L.HOM_E_UNSUPPORTED_SIZE
+    # GaNi grids: N or N + 1 with a radix-2/3/5 transform, and not beyond the quadrature grid
+    ds = _desc(L, N=(15, 15, 1))
+    ds.M[0], ds.M[1] = 45, 45
+    for grid, expect in (((15, 15), 0), ((16, 15), 0), ((16, 16), 0), ((17, 15), -2), ((14, 15), -2)):
+        g = (C.c_int32 * 3)(grid[0], grid[1], 1)
+        assert lib.hom_gani_workspace_bytes(C.byref(ds), g, C.byref(ws)) == expect, grid

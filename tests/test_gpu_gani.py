@@ -250,6 +250,15 @@ def test_point_values_on_even_grids_match_oracle(name, make, G, closed):
         assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max()
 
 
+def _box3d(seed=15):
+    """A 3D cell with two anisotropic boxes whose faces meet grid planes of even grids."""
+    rng = np.random.default_rng(seed)
+    c = homgen.Inclusions(d=3, Y=np.array([1.0, 1.2, 0.9]), A0=np.eye(3))
+    c.add("rect", [0.0, 0.0, 0.0], [0.5, 0.4, 0.36], homgen.random_spd(rng, 3, 1.0, 20.0))
+    c.add("rect", [0.375, -0.45, 0.27], [0.25, 0.2, 0.18], homgen.random_spd(rng, 3, 1.0, 20.0))
+    return c
+
+
 EVEN_GANI = [
     # (name, cell, GaNi grid, closed boxes)
     ("paper_S2_rho10_G8", lambda: _paper_square_closed(10.0), (8, 8), True),
@@ -259,6 +268,7 @@ EVEN_GANI = [
     ("pix_G20x16", lambda: homgen.pixel_cell(seed=11, P=10, values=(1.0, 50.0)), (20, 16), False),
     ("pix_G32", lambda: homgen.pixel_cell(seed=14, P=16, values=(1.0, 20.0)), (32, 32), False),
     ("sph3d_G8", lambda: homgen.sphere_cell(seed=12, n=4, anisotropic=True), (8, 8, 8), False),
+    ("box3d_G8x6x10_closed", lambda: _box3d(), (8, 6, 10), True),
     # the foam-like image on its own pixel grid (the setting of the paper's foam example)
     ("foam_G60", lambda: homgen.foam_cell(5, P=60, rmin=0.03, rmax=0.1), (60, 60), False),
 ]
