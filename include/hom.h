@@ -312,7 +312,11 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, do
                                 hom_info* info_dual);
 
 /* hom_update_coefficients for every problem of the batch (Ahat[i], Bhat[i]
- * for problem i, same layout and ownership), enqueued in one call. */
+ * for problem i, same layout and ownership; host arrays of n device
+ * pointers), enqueued in one call.  2D problems with equal doubled-grid
+ * lengths 25, 81, 125 or 625 are set up together (three launches over all
+ * cells, the pointer table in the batch workspace); others cell by cell.
+ * The results are bitwise those of per-problem updates. */
 hom_status hom_batch_update_coefficients(hom_batch* b, const void* const* Ahat, const void* const* Bhat);
 
 /* Bounds of every problem (as hom_bounds): primal, dual: host arrays of
