@@ -174,6 +174,21 @@ hom_status hom_bounds(hom_problem* pb, const double* const* primal, const double
  * field vectors.  Used to check the operator against a reference. */
 hom_status hom_apply(hom_problem* pb, int32_t dual, const double* x, double* y);
 
+/* Dual start from the primal minimisers (Proposition FD_odd_problem (ii), eq.
+ * FD_superposition_odd_A, and the remark on avoiding the dual solution): for
+ * each dual load J = e_b, with E = Abar^-1 e_b,
+ *     J + j0 = A sum_a E_a (e_a + x^(a)),  projected onto J_N,
+ * the product taken by the problem's operator (the exact form on the
+ * quadrature grid, or the GaNi form in GaNi mode, where the relation is exact
+ * for exact GaNi minimisers on odd grids).  primal: host array of d device
+ * primal fields for the unit loads e_1..e_d; Abar: host d x d row-major,
+ * symmetric with a positive diagonal (the upper bound of those fields, or
+ * A_{H,N} in GaNi mode); x0_dual: host array of d device dual fields (outputs,
+ * the fluctuations j0 in the dual layout), a valid x0 of hom_solve_dual.
+ * Synchronises the stream.  HOM_E_INVALID for null pointers or a non-finite,
+ * non-symmetric or singular Abar. */
+hom_status hom_dual_start(hom_problem* pb, const double* const* primal, const double* Abar, double* const* x0_dual);
+
 /* Device-side Fourier coefficients of a matrix-inclusion medium (eq.
  * A_with_inclusions, Remark inclusion): A_hat(n) = A0 delta_n0 +
  * sum_j (A_j - A0) f_hat_j(n) phi_{-n}(x_j) on Z_M, written in the Ahat layout of

@@ -272,6 +272,17 @@ class Problem:
                 "hom_apply")
         return y
 
+    def dual_start(self, primal, Abar):
+        """Dual start fields from the primal fields of the unit loads (hom_dual_start):
+        J + j0 = A sum_a E_a (e_a + x^(a)) projected onto J_N, E = Abar^-1 J, for J = e_1..e_d."""
+        d = self.d
+        out = [self.new_field(True) for _ in range(d)]
+        A = np.ascontiguousarray(np.asarray(Abar, float).reshape(d, d))
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_dual_start(self.h, _dptrs(primal), A.ctypes.data_as(C.POINTER(C.c_double)),
+                                        _dptrs(out)), "hom_dual_start")
+        return out
+
     def profile_passes(self, dual=False, nload=None, reps=20):
         """Average per-launch milliseconds of the five operator passes (HIP events)."""
         ms = (C.c_double * 5)()

@@ -449,6 +449,27 @@ hipError_t enqueue_matvec_passes(const Geo& g, const UnitDev* u, int nu, int fir
   return launch_last<R>(g, u, nu, last_mode, jstep, iter_base, st);
 }
 
+// One operator application from a primal-layout field to a dual-layout one: the
+// first passes expand E + T^E(k) x (primal basis, E at k = 0), the column pass
+// applies the coefficient on the quadrature grid, the last pass projects onto
+// the dual basis T^J(k).
+template <typename R>
+hipError_t enqueue_cross_passes(const Geo& gin, const Geo& gout, const UnitDev* u, hipStream_t st) {
+  hipError_t e = launch_first<R>(gin, u, 1, FIRST_BOUNDS, 0, nullptr, st);
+  if (e != hipSuccess) return e;
+  if (gin.d == 3) {
+    e = launch_mid<R>(gin, u, 1, 1, st);
+    if (e != hipSuccess) return e;
+  }
+  e = launch_apply<R>(gin, u, 1, APPLY_COEF, st);
+  if (e != hipSuccess) return e;
+  if (gin.d == 3) {
+    e = launch_mid<R>(gin, u, 1, 0, st);
+    if (e != hipSuccess) return e;
+  }
+  return launch_last<R>(gout, u, 1, LAST_MATVEC, 0, nullptr, st);
+}
+
 hipError_t enqueue_passes(bool fp32, const Geo& g, const UnitDev* u, int fm, int lm, int j, const int* ib,
                           hipStream_t st, int nu = 1) {
   return fp32 ? enqueue_matvec_passes<float>(g, u, nu, fm, lm, j, ib, st)
@@ -1088,6 +1109,51 @@ hom_status hom_apply(hom_problem* pb, int32_t dual, const double* x, double* y) 
   HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
   HIPCHK(enqueue_passes(fp32, g, sb.unit, FIRST_FIELD, LAST_MATVEC, 0, nullptr, st));
   HIPCHK(hipStreamSynchronize(st));
+  return HOM_OK;
+}
+
+hom_status hom_dual_start(hom_problem* pb, const double* const* primal, const double* Abar, double* const* x0_dual) {
+  if (!pb || !primal || !Abar || !x0_dual) return HOM_E_INVALID;
+  const int d = pb->desc.d;
+  for (int a = 0; a < d; ++a)
+    if (!primal[a] || !x0_dual[a]) return HOM_E_INVALID;
+  // E^(b) = Abar^-1 e_b, column b of the inverse of the (symmetric positive definite) homogenised matrix
+  double Am[9], Ai[9];
+  for (int i = 0; i < d * d; ++i) {
+    Am[i] = Abar[i];
+    if (!std::isfinite(Am[i])) return HOM_E_INVALID;
+  }
+  for (int a = 0; a < d; ++a) {
+    if (!(Am[a * d + a] > 0.0)) return HOM_E_INVALID;
+    for (int b = 0; b < a; ++b)
+      if (std::fabs(Am[a * d + b] - Am[b * d + a]) > 1e-12 * (std::fabs(Am[a * d + a]) + std::fabs(Am[b * d + b])))
+        return HOM_E_INVALID;
+  }
+  inv_small(d, Am, Ai);
+  for (int i = 0; i < d * d; ++i)
+    if (!std::isfinite(Ai[i])) return HOM_E_INVALID;
+  hipStream_t st = pb->stream;
+  const bool fp32 = pb->desc.precision == HOM_MIXED;
+  const bool gani = pb->gani.on;
+  const Geo gin = gani ? make_geo_gani(pb, 0, 1, fp32) : make_geo(pb, 0, 1, fp32);
+  const Geo gout = gani ? make_geo_gani(pb, 1, 1, fp32) : make_geo(pb, 1, 1, fp32);
+  SlotBufs& sb = pb->slot[0];
+  const size_t n = (size_t)gin.m * gin.S;   // complex entries of a primal field
+  FieldTriple xt{};
+  for (int a = 0; a < d; ++a) xt.p[a] = reinterpret_cast<const Cx<double>*>(primal[a]);
+  UnitDev* hu = &pb->host_unit[0];
+  for (int b = 0; b < d; ++b) {
+    double w[3] = {0.0, 0.0, 0.0};
+    for (int a = 0; a < d; ++a) w[a] = Ai[a * d + b];
+    // the combined fluctuation sum_a E_a x^(a) (linear in the fields), and E itself at k = 0
+    HIPCHK(launch_combine(xt, d, w, sb.tmp[0], n, st));
+    fill_unit(pb, 0, 1, w, nullptr, hu, gani);
+    hu->s[0] = reinterpret_cast<Cx<double>*>(x0_dual[b]);
+    HIPCHK(hipMemcpyAsync(sb.unit, hu, sizeof(UnitDev), hipMemcpyHostToDevice, st));
+    HIPCHK(fp32 ? enqueue_cross_passes<float>(gin, gout, sb.unit, st)
+                : enqueue_cross_passes<double>(gin, gout, sb.unit, st));
+    HIPCHK(hipStreamSynchronize(st));   // the host unit record is reused for the next load
+  }
   return HOM_OK;
 }
 

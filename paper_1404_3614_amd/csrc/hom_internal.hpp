@@ -214,6 +214,12 @@ struct CoefJob {
 bool fast_coef_setup_jobs(int d, const int* Mz, int nc, const CoefJob* jobs, int n, const Cx<double>* tw,
                           hipStream_t st, hipError_t* err);
 hipError_t launch_extract_half_jobs(const Geo& g, const CoefJob* jobs, int n, int nc, hipStream_t st);
+// Up to three device field vectors, passed by value to a kernel.
+struct FieldTriple {
+  const Cx<double>* p[3];
+};
+// out = sum_a w[a] x.p[a] over n complex entries.
+hipError_t launch_combine(const FieldTriple& x, int d, const double* w, Cx<double>* out, size_t n, hipStream_t st);
 
 // Tile shapes of the specialised passes: row pairs and threads per block of the
 // row passes, points per block of the column pass (0 = default).

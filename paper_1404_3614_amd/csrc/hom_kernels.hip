@@ -655,6 +655,17 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo g, const UnitDev* __restri
   }
 }
 
+// out = sum_a w_a x_a over n complex entries (d <= 3 fields).
+__global__ void k_combine(FieldTriple x, int d, double w0, double w1, double w2, Cx<double>* __restrict__ out,
+                          size_t n) {
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    Cx<double> s = x.p[0][t] * w0;
+    if (d > 1) s = s + x.p[1][t] * w1;
+    if (d > 2) s = s + x.p[2][t] * w2;
+    out[t] = s;
+  }
+}
+
 // ============================================================== setup FFT
 template <typename R, int MAXB>
 __global__ __launch_bounds__(kBlock) void k_line_fft(Cx<R>* data, int outer, int Lm, int inner, int tile, Plan pl,
@@ -1314,6 +1325,12 @@ hipError_t launch_collect_solve(const UnitDev* units, int n, int L, int nbL, Sol
 
 hipError_t launch_collect_bounds(const UnitDev* units, int n, int nbA, double* out, hipStream_t st) {
   hipLaunchKernelGGL(k_collect_bounds, dim3((n * 9 + 63) / 64), dim3(64), 0, st, units, n, nbA, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_combine(const FieldTriple& x, int d, const double* w, Cx<double>* out, size_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_combine, dim3(grid_for(n)), dim3(kBlock), 0, st, x, d, w[0], d > 1 ? w[1] : 0.0,
+                     d > 2 ? w[2] : 0.0, out, n);
   return hipGetLastError();
 }
 
