@@ -302,6 +302,9 @@ def main():
         return run_e3(args)
     N = (313, 313)
     B = args.cells
+    # measured streaming peak of the device (project copy kernel, 4 GiB: well beyond the 256 MB
+    # cache), beside the published HBM peak
+    probe_gbs = H.probe_copy_gbs(1 << 32, reps=5)
     # inputs resident in HBM: Fourier data of A and A^-1 for every cell
     coefs = [H.coef_from_cell(c2_cell(i), N) for i in range(B)]
     stream = torch.cuda.Stream()
@@ -431,7 +434,10 @@ def main():
     it_ms = sum(per_pass[k]["ms_per_launch"] for k in per_pass)
     matvec = dict(bytes_per_iteration=int(it_bytes), ms_per_iteration=round(it_ms, 5),
                   gbs=round(it_bytes / (it_ms * 1e-3) / 1e9, 1),
-                  frac=round(it_bytes / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4))
+                  frac=round(it_bytes / (it_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  measured_peak_gbs=round(probe_gbs, 1),
+                  frac_of_measured=round(it_bytes / (it_ms * 1e-3) / 1e9 / probe_gbs, 4),
+                  measured_peak_probe="hom_probe_copy: 4 GiB device copy, bytes read plus written")
     common = dict(kernel=names[dom], ms_per_launch=round(ms, 5), traffic=traffic, traffic_unit="bytes/launch",
                   traffic_per_pass=traffic_all, per_pass=per_pass, matvec=matvec,
                   bytes_model="pass_bytes() in bench.py; units per launch = active cells of the batch",

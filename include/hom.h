@@ -174,6 +174,12 @@ hom_status hom_bounds(hom_problem* pb, const double* const* primal, const double
  * field vectors.  Used to check the operator against a reference. */
 hom_status hom_apply(hom_problem* pb, int32_t dual, const double* x, double* y);
 
+/* Bandwidth probe: copies `bytes` (a multiple of 16) from src to dst (device,
+ * 16-byte aligned, not overlapping) reps times after one untimed copy, on
+ * `stream`, and returns the rate in GB/s of bytes read plus bytes written
+ * (HIP events).  The measured streaming peak beside the published HBM one. */
+hom_status hom_probe_copy(const void* src, void* dst, size_t bytes, int32_t reps, void* stream, double* gbs);
+
 /* Dual start from the primal minimisers (Proposition FD_odd_problem (ii), eq.
  * FD_superposition_odd_A, and the remark on avoiding the dual solution): for
  * each dual load J = e_b, with E = Abar^-1 e_b,

@@ -6,8 +6,8 @@ only marshals arguments and provides PyTorch-owned device memory and streams.
 """
 from .api import (Problem, Batch, coef_inclusions, coef_pixels, coef_from_cell, problem_from_cell, field_len,
                   workspace_bytes, spectrum_from_field, field_from_spectrum, HomError, set_tuning, cell_eig_range,
-                  sample_cell, quad_grid, smooth_pixel_cell)
+                  sample_cell, quad_grid, smooth_pixel_cell, probe_copy_gbs)
 
 __all__ = ["Problem", "Batch", "coef_inclusions", "coef_pixels", "coef_from_cell", "problem_from_cell", "field_len",
            "workspace_bytes", "spectrum_from_field", "field_from_spectrum", "HomError", "set_tuning",
-           "cell_eig_range", "sample_cell", "quad_grid", "smooth_pixel_cell"]
+           "cell_eig_range", "sample_cell", "quad_grid", "smooth_pixel_cell", "probe_copy_gbs"]

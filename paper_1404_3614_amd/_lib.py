@@ -58,6 +58,8 @@ EXPORTS = {
                                    C.c_double, C.c_int32, C.POINTER(C.c_void_p), C.POINTER(Info)]),
     "hom_bounds": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(Result)]),
     "hom_apply": (C.c_int32, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "hom_probe_copy": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p,
+                                   C.POINTER(C.c_double)]),
     "hom_dual_start": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
     "hom_coef_inclusions": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_double), C.c_int32,
                                         C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double),

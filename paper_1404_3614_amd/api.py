@@ -161,6 +161,21 @@ def sample_cell(cell, N, ncoef=None, inverse=False, stream=None, closed=False):
     return out
 
 
+def probe_copy_gbs(nbytes=1 << 30, reps=10, stream=None):
+    """Streaming rate of the device (hom_probe_copy): GB/s of bytes read plus written
+    by a copy of nbytes, the measured peak for the HBM roofline."""
+    n = (int(nbytes) // 16) * 16
+    src = torch.ones(n // 4, dtype=torch.float32, device=_dev())
+    dst = torch.empty_like(src)
+    g = C.c_double()
+    L.check(L.load().hom_probe_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), n, int(reps),
+                                    _stream_ptr(stream), C.byref(g)), "hom_probe_copy")
+    torch.cuda.synchronize()
+    assert bool(torch.equal(src, dst)), "probe copy mismatch"
+    del src, dst
+    return g.value
+
+
 def smooth_pixel_cell(cell, stream=None):
     """The smoothed medium of a two-phase 2D pixel cell (hom_smooth_pixels): a
     pixel cell with phases k = 0..16 of coefficient A0 + (k/16)(A1 - A0), k/16

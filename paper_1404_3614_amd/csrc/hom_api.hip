@@ -1112,6 +1112,29 @@ hom_status hom_apply(hom_problem* pb, int32_t dual, const double* x, double* y) 
   return HOM_OK;
 }
 
+hom_status hom_probe_copy(const void* src, void* dst, size_t bytes, int32_t reps, void* stream, double* gbs) {
+  if (!src || !dst || !gbs || reps < 1 || bytes < 16 || bytes % 16) return HOM_E_INVALID;
+  if (((uintptr_t)src) % 16 || ((uintptr_t)dst) % 16) return HOM_E_INVALID;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return HOM_E_DEVICE;
+  }
+  hipError_t e = launch_stream_copy(src, dst, bytes, st);   // untimed: first-launch costs
+  if (e == hipSuccess) e = hipEventRecord(e0, st);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_stream_copy(src, dst, bytes, st);
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (e != hipSuccess || !(ms > 0.f)) return HOM_E_DEVICE;
+  *gbs = 2.0 * (double)bytes * reps / (ms * 1e-3) / 1e9;   // bytes read plus bytes written
+  return HOM_OK;
+}
+
 hom_status hom_dual_start(hom_problem* pb, const double* const* primal, const double* Abar, double* const* x0_dual) {
   if (!pb || !primal || !Abar || !x0_dual) return HOM_E_INVALID;
   const int d = pb->desc.d;

@@ -214,6 +214,8 @@ struct CoefJob {
 bool fast_coef_setup_jobs(int d, const int* Mz, int nc, const CoefJob* jobs, int n, const Cx<double>* tw,
                           hipStream_t st, hipError_t* err);
 hipError_t launch_extract_half_jobs(const Geo& g, const CoefJob* jobs, int n, int nc, hipStream_t st);
+// Device-to-device copy of `bytes` (a multiple of 16, 16-byte aligned pointers).
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st);
 // Up to three device field vectors, passed by value to a kernel.
 struct FieldTriple {
   const Cx<double>* p[3];

@@ -655,6 +655,36 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo g, const UnitDev* __restri
   }
 }
 
+// Streaming copy of n 16-byte words (the bandwidth probe): each block moves
+// contiguous chunks of 4 kBlock words, four loads in flight per thread before
+// the stores; the tail word by word.
+__global__ void k_stream_copy(const float4* __restrict__ src, float4* __restrict__ dst, size_t n) {
+  constexpr int U = 4;
+  const size_t chunk = (size_t)U * blockDim.x;
+  const size_t nfull = n / chunk;
+  for (size_t c = blockIdx.x; c < nfull; c += gridDim.x) {
+    const size_t base = c * chunk + threadIdx.x;
+    float4 v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = src[base + (size_t)u * blockDim.x];
+#pragma unroll
+    for (int u = 0; u < U; ++u) dst[base + (size_t)u * blockDim.x] = v[u];
+  }
+  for (size_t t = nfull * chunk + blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n;
+       t += (size_t)gridDim.x * blockDim.x)
+    dst[t] = src[t];
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, size_t bytes, hipStream_t st) {
+  const size_t n = bytes / 16;
+  size_t nb = (n + 4 * kBlock - 1) / (4 * kBlock);
+  if (nb > 256 * 16) nb = 256 * 16;   // 16 blocks per CU
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)nb), dim3(kBlock), 0, st, reinterpret_cast<const float4*>(src),
+                     reinterpret_cast<float4*>(dst), n);
+  return hipGetLastError();
+}
+
 // out = sum_a w_a x_a over n complex entries (d <= 3 fields).
 __global__ void k_combine(FieldTriple x, int d, double w0, double w1, double w2, Cx<double>* __restrict__ out,
                           size_t n) {

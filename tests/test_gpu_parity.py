@@ -350,3 +350,19 @@ def test_side_by_side_pair_equals_sequential_solves():
                 assert bool((fp[i][l] == sp[i][l]).all()) and bool((fd[i][l] == sd[i][l]).all())
                 assert ip[i][l]["iters"] == isp[i][l]["iters"] and idl[i][l]["iters"] == isd[i][l]["iters"]
                 assert ip[i][l]["status"] == 0 and idl[i][l]["status"] == 0
+
+
+def test_bandwidth_probe_copies_and_reports_a_rate():
+    H = _H()
+    import torch
+    g = H.probe_copy_gbs(1 << 26, reps=3)
+    print(f"[probe] copy of 64 MiB: {g:.0f} GB/s", flush=True)
+    assert 100.0 < g < 20000.0
+    from paper_1404_3614_amd import _lib as L
+    src = torch.zeros(1024, dtype=torch.float32, device="cuda")
+    gbs = L.C.c_double()
+    for bad in ((src.data_ptr() + 4, src.data_ptr(), 1024, 1), (src.data_ptr(), src.data_ptr(), 1000, 1),
+                (src.data_ptr(), src.data_ptr(), 1024, 0)):
+        with pytest.raises(H.HomError):
+            L.check(L.load().hom_probe_copy(L.C.c_void_p(bad[0]), L.C.c_void_p(bad[1]), bad[2], bad[3], None,
+                                            L.C.byref(gbs)), "hom_probe_copy")
