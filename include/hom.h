@@ -278,6 +278,7 @@ hom_status hom_clear_gani(hom_problem* pb);
 /* GaNi homogenized matrices A_{H,N}, B_{H,N} (eq. GaNi): the trapezoidal-rule
  * energies of primal and dual fields of the unit loads (host arrays of d
  * device pointers, as hom_bounds), row-major d x d into A_HN and B_HN (host).
+ * Either array may be NULL: its matrix is then NaN.
  * For odd grids A_{H,N} = B_{H,N}^-1 at the GaNi minimisers; on even grids
  * B_{H,N}^-1 <= A_{H,N} (Proposition FD_even_problem).  Requires GaNi mode. */
 hom_status hom_gani_matrices(hom_problem* pb, const double* const* primal, const double* const* dual,

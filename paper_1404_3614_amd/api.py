@@ -360,12 +360,15 @@ class Problem:
     def clear_gani(self):
         L.check(L.load().hom_clear_gani(self.h), "hom_clear_gani")
 
-    def gani_matrices(self, primal, dual):
-        """A_{H,N} and B_{H,N} (hom_gani_matrices) of fields of the unit loads."""
+    def gani_matrices(self, primal, dual=None):
+        """A_{H,N} and B_{H,N} (hom_gani_matrices) of fields of the unit loads (either may be
+        None: its matrix is NaN)."""
         A = (C.c_double * 9)()
         B = (C.c_double * 9)()
         self.stream.wait_stream(torch.cuda.current_stream())
-        L.check(L.load().hom_gani_matrices(self.h, _dptrs(primal), _dptrs(dual), A, B), "hom_gani_matrices")
+        pp = _dptrs(primal) if primal is not None else None
+        dp = _dptrs(dual) if dual is not None else None
+        L.check(L.load().hom_gani_matrices(self.h, pp, dp, A, B), "hom_gani_matrices")
         d = self.d
         return np.array(A[:d * d]).reshape(d, d), np.array(B[:d * d]).reshape(d, d)
 

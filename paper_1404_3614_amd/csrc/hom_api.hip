@@ -1255,8 +1255,8 @@ hom_status hom_gani_matrices(hom_problem* pb, const double* const* primal, const
   if (s != HOM_OK) return s;
   const int d = pb->desc.d;
   for (int i = 0; i < d * d; ++i) {
-    A_HN[i] = Ebar[0][i];
-    B_HN[i] = Ebar[1][i];
+    A_HN[i] = have[0] ? Ebar[0][i] : NAN;
+    B_HN[i] = have[1] ? Ebar[1][i] : NAN;
   }
   return HOM_OK;
 }
