@@ -83,6 +83,9 @@ def test_gani_dual_start_is_the_dual_minimiser(precision):
     tol = 1e-10 if precision == "fp64" else 1e-8
     r = pb.solve_bounds(tol=tol)
     AHN, BHN = pb.gani_matrices(r["fields_primal"], r["fields_dual"])
+    # one side only: the same A_{H,N}, B_{H,N} NaN
+    A1, B1 = pb.gani_matrices(r["fields_primal"])
+    assert np.array_equal(A1, AHN) and np.isnan(B1).all()
     x0 = pb.dual_start(r["fields_primal"], AHN)
     xs, info = pb.solve(True, x0=x0, tol=10 * tol)
     its0 = [i["iters"] for i in r["info_dual"]]
