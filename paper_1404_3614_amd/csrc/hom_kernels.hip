@@ -540,7 +540,12 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo g, const UnitDev* __restri
   const int npts = g.M[1] * g.M[2];
   const size_t Mtot = (size_t)M0 * npts;
   const int tileA = g.tileA;
-  const int p0 = blockIdx.x * tileA;
+  // XCD-aware tile order: workgroups go round-robin to the 8 XCDs, so XCD x (blocks x, x + 8, ...)
+  // takes the contiguous tiles [x nb8, (x + 1) nb8) and its L2 serves the neighbouring tiles' lines
+  const int nb8 = (g.nbA + 7) / 8;
+  const int tb = (int)(blockIdx.x % 8) * nb8 + (int)(blockIdx.x / 8);
+  if (tb >= g.nbA) return;  // uniform over the block
+  const int p0 = tb * tileA;
   const int tp = min(tileA, npts - p0);
   const int nl = tileA * P;
   Cx<R>* data = reinterpret_cast<Cx<R>*>(g.N[1] > 1 ? U.bufB : U.bufA);
@@ -650,7 +655,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Geo g, const UnitDev* __restri
     for (int i = 0; i < kMaxLoads * kMaxLoads; ++i) {
       if (i / kMaxLoads >= L || i % kMaxLoads >= L) continue;  // uniform over the block
       const double s = block_sum(acc[i], s_red);
-      if (tid == 0) U.part_q[(size_t)blockIdx.x * 9 + i] = s;
+      if (tid == 0) U.part_q[(size_t)tb * 9 + i] = s;
     }
   }
 }
@@ -1238,7 +1243,8 @@ hipError_t launch_apply(const Geo& g, const UnitDev* units, int nunits, int mode
   }
   const int nl = g.tileA * g.P;
   const size_t lds = (size_t)g.M[0] * nl * sizeof(Cx<R>);
-  HOM_DISPATCH(k_apply, max_butterflies(g.pl[0], g.M[0], nl), lds, dim3(g.nbA, 1, nunits), g, units, mode);
+  HOM_DISPATCH(k_apply, max_butterflies(g.pl[0], g.M[0], nl), lds, dim3(8 * ((g.nbA + 7) / 8), 1, nunits), g, units,
+               mode);
 }
 
 template <typename R>
