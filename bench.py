@@ -464,6 +464,7 @@ def main():
                 config=dict(workload="C2: 2D N=313 (doubled grid 625^2), random two-phase 125x125 pixel image, "
                                      "a in {1,100}, both loads, primal+dual, batched lockstep CG",
                             cells_per_step=B, tol=args.tol, precision=args.precision, cg_iters=iters,
+                            solves_per_s=round(value * 2 * 2, 3),   # a bound pair: 2 primal + 2 dual load solves
                             step_ms=step_ms,
                             batched="all cells of a step in lockstep (one launch per pass covers every cell)",
                             plain_bound_pairs_per_s=None if plain_value is None else round(plain_value, 3),
