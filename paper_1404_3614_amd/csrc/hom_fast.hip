@@ -88,44 +88,62 @@ constexpr int dead_mask() {
 
 // ============================================================== column pass
 // Exchange of register lines between the two steps of a four-step FFT
-// through LDS: threads with `wr` store NW values at slots (wbase + j), threads
-// with `rd` load NR values from slots (rbase + j rstep); a slot holds TP
-// points.  HX = 1 moves the real parts and then the imaginary parts through a
-// real-valued buffer of half the size (more blocks per CU for the same LDS).
-template <typename R, int NW, int NR, int TP, int HX>
-__device__ __forceinline__ void xchg(Cx<R>* ex, Cx<R>* v, bool wr, int wbase, bool rd, int rbase, int rstep, int pt) {
+// through LDS.  Threads with `wr` store their NW values of group q (the
+// slots q G + j, j < NW), threads with `rd` load NR values of column q (the
+// slots q + j G, j < NR); a slot holds TP points.  Groups of slots are laid
+// out RS = G TP + pad elements apart, with RS = TP modulo the bank count, so
+// that lane (q, pt) of a wave, lane number q TP + pt, touches bank
+// (q TP + pt + j TP) mod banks on both sides: no bank conflicts for the 64
+// lanes (HX, 4-byte words, 64 banks) or 32 lanes (complex words).  HX = 1
+// moves the real parts and then the imaginary parts through a real-valued
+// buffer of half the size (more blocks per CU for the same LDS).
+template <int G, int TP, int HX>
+constexpr int xpad() {
+  constexpr int W = HX ? 64 : 32;
+  return ((TP - G * TP) % W + W) % W;
+}
+// elements of one thread group's exchange area for M = A B
+template <int A, int B, int TP, int HX>
+constexpr int xarea() {
+  constexpr int e1 = B * (A * TP + xpad<A, TP, HX>()), e2 = A * (B * TP + xpad<B, TP, HX>());
+  return e1 > e2 ? e1 : e2;
+}
+template <typename R, int NW, int NR, int G, int TP, int HX>
+__device__ __forceinline__ void xchg(Cx<R>* ex, Cx<R>* v, bool wr, bool rd, int q, int pt) {
+  constexpr int RS = G * TP + xpad<G, TP, HX>();
+  const int wb = q * RS + pt, rb = q * TP + pt;
   if constexpr (!HX) {
     if (wr) {
 #pragma unroll
-      for (int j = 0; j < NW; ++j) ex[(wbase + j) * TP + pt] = v[j];
+      for (int j = 0; j < NW; ++j) ex[wb + j * TP] = v[j];
     }
     __syncthreads();
     if (rd) {
 #pragma unroll
-      for (int j = 0; j < NR; ++j) v[j] = ex[(rbase + j * rstep) * TP + pt];
+      for (int j = 0; j < NR; ++j) v[j] = ex[rb + j * RS];
     }
     __syncthreads();
   } else {
+    // the real parts are stored before they are overwritten by the loads
     R* e = reinterpret_cast<R*>(ex);
-    R t[NR];
     if (wr) {
 #pragma unroll
-      for (int j = 0; j < NW; ++j) e[(wbase + j) * TP + pt] = v[j].x;
+      for (int j = 0; j < NW; ++j) e[wb + j * TP] = v[j].x;
     }
     __syncthreads();
     if (rd) {
 #pragma unroll
-      for (int j = 0; j < NR; ++j) t[j] = e[(rbase + j * rstep) * TP + pt];
+      for (int j = 0; j < NR; ++j) v[j].x = e[rb + j * RS];
     }
     __syncthreads();
     if (wr) {
 #pragma unroll
-      for (int j = 0; j < NW; ++j) e[(wbase + j) * TP + pt] = v[j].y;
+      for (int j = 0; j < NW; ++j) e[wb + j * TP] = v[j].y;
     }
     __syncthreads();
     if (rd) {
 #pragma unroll
-      for (int j = 0; j < NR; ++j) v[j] = rf::mk<R>(t[j], e[(rbase + j * rstep) * TP + pt]);
+      for (int j = 0; j < NR; ++j) v[j].y = e[rb + j * RS];
     }
     __syncthreads();
   }
@@ -158,9 +176,9 @@ __global__ __launch_bounds__(PB * TP * Cfg<M>::T) void k_apply2_fast(Geo g, cons
   if (cbl >= nbx8 || cb >= nbx) return;
   const int grp = (PB == 1) ? 0 : (int)threadIdx.x / NT, tid = (int)threadIdx.x - grp * NT;
   const int pk = (PB == P) ? grp : w8 % P;
-  // exchange area of this thread group: [M][TP] complex, or real with HX
+  // exchange area of this thread group (complex, or real with HX)
   Cx<R>* ex = reinterpret_cast<Cx<R>*>(smem + (size_t)M * sizeof(Cx<R>) +
-                                       (size_t)grp * M * TP * (HX ? sizeof(R) : sizeof(Cx<R>)));
+                                       (size_t)grp * xarea<A, B, TP, HX>() * (HX ? sizeof(R) : sizeof(Cx<R>)));
   const int p0 = cb * TP;
   const int pt = tid % TP, q = tid / TP;
   const bool ok = (p0 + pt) < npts;
@@ -202,7 +220,7 @@ __global__ __launch_bounds__(PB * TP * Cfg<M>::T) void k_apply2_fast(Geo g, cons
       v[k1] = rf::mul(v[k1], w);
     }
   }
-  xchg<R, A, B, TP, HX>(ex, v, q < B, q * A, q < A, q, A, pt);
+  xchg<R, A, B, A, TP, HX>(ex, v, q < B, q < A, q, pt);
   if (q < A) {
     rf::Dft<R, B, 1>::run(v);
     // thread k1 = q holds u at x0 = q + A k2: the coefficient on the doubled grid
@@ -222,7 +240,7 @@ __global__ __launch_bounds__(PB * TP * Cfg<M>::T) void k_apply2_fast(Geo g, cons
 #pragma unroll
     for (int m2 = 0; m2 < B; ++m2) v[m2] = rf::mul(v[m2], tw[q * m2]);
   }
-  xchg<R, B, A, TP, HX>(ex, v, q < A, q * B, q < B, q, B, pt);
+  xchg<R, B, A, B, TP, HX>(ex, v, q < A, q < B, q, pt);
   if (q < B) {
     rf::Dft<R, A, -1>::run(v);
     // thread m2 = q holds X[q + B m1]: store the Z_N0 part
@@ -1224,7 +1242,8 @@ template <int M, int P, int NC, int TP, int HX, int ALL>
 static hipError_t run_apply2_tp(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st) {
   constexpr int T = Cfg<M>::T, PB = ALL ? P : 1;
   const int npts = g.M[2];
-  const size_t lds = (size_t)M * sizeof(Cx<float>) + (size_t)PB * M * TP * (HX ? sizeof(float) : sizeof(Cx<float>));
+  const size_t lds = (size_t)M * sizeof(Cx<float>) +
+                     (size_t)PB * xarea<Cfg<M>::A, Cfg<M>::B, TP, HX>() * (HX ? sizeof(float) : sizeof(Cx<float>));
   auto kern = k_apply2_fast<float, M, P, NC, TP, HX, PB>;
   hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
