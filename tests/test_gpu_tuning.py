@@ -22,6 +22,8 @@ SHAPES = {
          [(28, 0, 0), (14, 0, 0), (28, 1, 0), (14, 1, 0), (14, 0, 1), (14, 1, 1)]),
     125: ([(4, 0), (2, 0), (1, 0), (2, 256), (1, 256)],
           [(10, 0, 0), (5, 0, 0), (10, 1, 0), (5, 1, 0), (5, 0, 1), (5, 1, 1)]),
+    625: ([(2, 0), (1, 0), (4, 0), (2, 256), (1, 256)],
+          [(8, 0, 0), (10, 1, 0), (5, 1, 0), (4, 0, 0), (10, 1, 1), (5, 1, 1)]),
 }
 
 
@@ -55,7 +57,7 @@ def _iters(out):
     return [[i["iters"] for i in r["info_primal"] + r["info_dual"]] for r in out]
 
 
-@pytest.mark.parametrize("N", [13, 41, 63], ids=["M25", "M81", "M125"])
+@pytest.mark.parametrize("N", [13, 41, 63, 313], ids=["M25", "M81", "M125", "M625"])
 def test_every_tile_shape_gives_the_same_bounds(N):
     H = _H()
     M = 2 * N - 1
