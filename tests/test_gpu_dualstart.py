@@ -45,7 +45,7 @@ CASES = [
 def test_dual_start_matches_oracle(name, make, N, precision):
     H = _H()
     import torch
-    from paper_1404_3614_amd.api import field_from_spectrum, spectrum_from_field
+    from layout import field_from_spectrum, spectrum_from_field
     cell = make()
     d = cell.d
     Y = tuple(cell.Y)

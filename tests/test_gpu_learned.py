@@ -170,7 +170,7 @@ def _rand_spectrum(d, N, Y, dual, rng):
 def test_field_to_grid_matches_oracle(name, mk, N, dual):
     H = _H()
     import torch
-    from paper_1404_3614_amd.api import field_from_spectrum
+    from layout import field_from_spectrum
     cell = mk()
     d = cell.d
     pb = H.problem_from_cell(cell, N, precision="fp64")
@@ -191,7 +191,7 @@ def test_field_to_grid_matches_oracle(name, mk, N, dual):
 def test_grid_to_field_matches_oracle(name, mk, N, dual):
     H = _H()
     import torch
-    from paper_1404_3614_amd.api import spectrum_from_field
+    from layout import spectrum_from_field
     cell = mk()
     d = cell.d
     pb = H.problem_from_cell(cell, N, precision="mixed")

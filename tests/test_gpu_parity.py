@@ -67,7 +67,7 @@ CASES_OP = [
 def test_operator_matches_oracle(name, mk, N, prec, dual):
     H = _H()
     import torch
-    from paper_1404_3614_amd.api import field_from_spectrum
+    from layout import field_from_spectrum
     cell = mk()
     d = cell.d
     pb = H.problem_from_cell(cell, N, precision=prec)

@@ -6,7 +6,7 @@ import pytest
 
 import homgen
 from oracle import galerkin as ga
-from paper_1404_3614_amd.api import spectrum_from_field, field_from_spectrum, basis_np
+from layout import spectrum_from_field, field_from_spectrum, basis_np
 
 
 @pytest.mark.parametrize("cell,N", [
