@@ -195,6 +195,14 @@ hom_status hom_probe_copy(const void* src, void* dst, size_t bytes, int32_t reps
  * non-symmetric or singular Abar. */
 hom_status hom_dual_start(hom_problem* pb, const double* const* primal, const double* Abar, double* const* x0_dual);
 
+/* Device scratch bytes of the coefficient and sampling helpers below: P NULL
+ * gives the size for n_incl inclusions (hom_coef_inclusions,
+ * hom_sample_inclusions), P (host, d pixel counts) the size for that image
+ * (hom_coef_pixels, hom_sample_pixels), for desc->d and desc->ncoef.
+ * HOM_E_INVALID for a bad descriptor, n_incl < 0 or a pixel count outside
+ * [1, 65536]. */
+hom_status hom_coef_scratch_bytes(const hom_desc* desc, int32_t n_incl, const int32_t* P, size_t* bytes);
+
 /* Device-side Fourier coefficients of a matrix-inclusion medium (eq.
  * A_with_inclusions, Remark inclusion): A_hat(n) = A0 delta_n0 +
  * sum_j (A_j - A0) f_hat_j(n) phi_{-n}(x_j) on Z_M, written in the Ahat layout of
@@ -202,10 +210,16 @@ hom_status hom_dual_start(hom_problem* pb, const double* const* primal, const do
  * (valid for non-overlapping inclusions: A0^{-1} and A_j^{-1} - A0^{-1}).
  * Host inputs: A0 (d x d), n_incl inclusions with kind[j] (0 box, 1 ball (d = 3)),
  * center[j*d + a], size[j*d + a] (box sides; ball radius in size[j*d]),
- * A_in[j*d*d ...] (coefficient inside, d x d row-major).  out: device. */
+ * A_in[j*d*d ...] (coefficient inside, d x d row-major).  out: device.
+ * scratch: device, caller-owned, at least hom_coef_scratch_bytes(desc, n_incl,
+ * NULL) bytes (HOM_E_WORKSPACE if smaller): it receives the inclusion table.
+ * The host inputs are copied into scratch before the call returns (the call
+ * waits for the stream's earlier work and that copy); the transform itself
+ * runs asynchronously on stream, so scratch must stay allocated until the
+ * stream has passed it.  The library allocates no device memory here. */
 hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
                                const double* center, const double* size, const double* A_in,
-                               int32_t inverse, void* out, void* stream);
+                               int32_t inverse, void* out, void* scratch, size_t scratch_bytes, void* stream);
 
 /* Device-side Fourier coefficients of a pixel/voxel image (Remark inclusion
  * summed over pixels): pixel i_a along axis a covers
@@ -213,9 +227,20 @@ hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n
  * only (a P-point transform of the image).
  * phase: host int32 array (P0 x P1 (x P2), row-major) of phase ids;
  * phase_A: host nphase x d x d.  inverse = 1 uses the inverse phase matrices.
- * out: device, Ahat layout of hom_setup. */
+ * out: device, Ahat layout of hom_setup.  scratch: device, caller-owned, at
+ * least hom_coef_scratch_bytes(desc, 0, P) bytes (the image and its
+ * transforms); staging and asynchrony as hom_coef_inclusions. */
 hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t* phase, int32_t nphase,
-                           const double* phase_A, int32_t inverse, void* out, void* stream);
+                           const double* phase_A, int32_t inverse, void* out, void* scratch, size_t scratch_bytes,
+                           void* stream);
+
+/* Smallest and largest eigenvalue over nphase symmetric d x d phase
+ * matrices (host, row-major): range[0] = a_min, range[1] = a_max (host), the
+ * spectrum bounds of the coefficient (Sec. 3: A is uniformly elliptic and
+ * bounded, which bounds the spectrum of the Galerkin operators), as taken by
+ * hom_problem_set_stop / hom_batch_set_stop.  HOM_E_NOT_SPD if a_min <= 0,
+ * HOM_E_INVALID for non-finite entries. */
+hom_status hom_phase_eig_range(int32_t d, int32_t nphase, const double* phase_A, double* range);
 
 /* ---- GaNi: Galerkin approximation with numerical integration (Def. GaNi,
  * Lemma FD_of_GaNi) and the paper's Algorithm (Sec. 7.2): the minimisers are
@@ -241,12 +266,15 @@ hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t
  * periodic minimum-image differences: otherwise interfaces belong to the matrix.
  * out: device FP64 [ncoef][N0][N1]([N2]), row-major over the physical axes
  * (2D: [ncoef][N0][N1]); components as hom_desc.ncoef; inverse = 1 gives the
- * values of A^-1. */
+ * values of A^-1.  scratch: device, caller-owned, at least
+ * hom_coef_scratch_bytes bytes for these inputs; staging and asynchrony as
+ * hom_coef_inclusions. */
 hom_status hom_sample_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
                                  const double* center, const double* size, const double* A_in, int32_t inverse,
-                                 int32_t closed, double* out, void* stream);
+                                 int32_t closed, double* out, void* scratch, size_t scratch_bytes, void* stream);
 hom_status hom_sample_pixels(const hom_desc* desc, const int32_t* P, const int32_t* phase, int32_t nphase,
-                             const double* phase_A, int32_t inverse, double* out, void* stream);
+                             const double* phase_A, int32_t inverse, double* out, void* scratch, size_t scratch_bytes,
+                             void* stream);
 
 /* The coefficient smoothing filter of the paper's fly-ash example (Sec. 8.3):
  * each value of a 2D characteristic image f (device int32, P[0] x P[1]
@@ -254,8 +282,11 @@ hom_status hom_sample_pixels(const hom_desc* desc, const int32_t* P, const int32
  * four axis neighbours and 1/16 of each of its four diagonal neighbours,
  * periodically.  out (device int32, same shape) receives 16 f_smoothed, exact
  * in integers; a pixel image with the phases k = 0..16 of coefficient
- * A0 + (k/16)(A1 - A0) is the smoothed medium (hom_coef_pixels, hom_sample_pixels). */
-hom_status hom_smooth_pixels(const int32_t* P, const int32_t* f, int32_t* out, void* stream);
+ * A0 + (k/16)(A1 - A0) is the smoothed medium (hom_coef_pixels, hom_sample_pixels).
+ * table (host, 17 x d x d, may be NULL) receives those phase matrices from
+ * A01 (host, 2 x d x d: A0 then A1; d = 2).  Synchronises the stream. */
+hom_status hom_smooth_pixels(const int32_t* P, const int32_t* f, int32_t* out, int32_t d, const double* A01,
+                             double* table, void* stream);
 
 /* Device workspace bytes of hom_set_gani for the GaNi grid `grid` (host,
  * d entries, each N_a or N_a + 1; NULL: N), alignment 256. */

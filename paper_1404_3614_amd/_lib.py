@@ -61,11 +61,15 @@ EXPORTS = {
     "hom_probe_copy": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32, C.c_void_p,
                                    C.POINTER(C.c_double)]),
     "hom_dual_start": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_void_p]),
+    "hom_coef_scratch_bytes": (C.c_int32, [C.POINTER(Desc), C.c_int32, C.c_void_p, C.POINTER(C.c_size_t)]),
     "hom_coef_inclusions": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_double), C.c_int32,
                                         C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                        C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p]),
+                                        C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                        C.c_void_p]),
     "hom_coef_pixels": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
-                                    C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p]),
+                                    C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                    C.c_void_p]),
+    "hom_phase_eig_range": (C.c_int32, [C.c_int32, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "hom_profile_passes": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double)]),
     "hom_destroy": (None, [C.c_void_p]),
     "hom_field_to_grid": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p]),
@@ -97,11 +101,13 @@ EXPORTS = {
     "hom_problem_set_stop": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double]),
     "hom_sample_inclusions": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_double), C.c_int32, C.POINTER(C.c_int32),
                                           C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
-                                          C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]),
+                                          C.c_int32, C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "hom_sample_pixels": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
-                                      C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p]),
+                                      C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
+                                      C.c_void_p]),
     "hom_gani_workspace_bytes": (C.c_int32, [C.POINTER(Desc), C.c_void_p, C.POINTER(C.c_size_t)]),
-    "hom_smooth_pixels": (C.c_int32, [C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hom_smooth_pixels": (C.c_int32, [C.POINTER(C.c_int32), C.c_void_p, C.c_void_p, C.c_int32,
+                                      C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_void_p]),
     "hom_set_gani": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t]),
     "hom_clear_gani": (C.c_int32, [C.c_void_p]),
     "hom_gani_matrices": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),

@@ -77,15 +77,61 @@ def cell_ncoef(cell):
     return 1 if all(_is_iso(A) for A in mats) else d * (d + 1) // 2
 
 
+def _dbl(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
 def cell_eig_range(cell):
-    """Smallest and largest eigenvalue over the phases of a cell: the a_min and
-    a_max of the guaranteed stopping rule (set_stop)."""
+    """Smallest and largest eigenvalue over the phases of a cell
+    (hom_phase_eig_range): the a_min and a_max of the guaranteed stopping rule
+    (set_stop)."""
     if hasattr(cell, "phase"):
         mats = [cell.phase_A[i] for i in np.unique(cell.phase)]
     else:
         mats = [cell.A0] + list(cell.A)
-    ev = np.concatenate([np.linalg.eigvalsh(np.asarray(A, float)) for A in mats])
-    return float(ev.min()), float(ev.max())
+    A = np.ascontiguousarray(np.stack([np.asarray(m, float) for m in mats]).reshape(-1))
+    out = (C.c_double * 2)()
+    L.check(L.load().hom_phase_eig_range(cell.d, len(mats), _dbl(A), out), "hom_phase_eig_range")
+    return float(out[0]), float(out[1])
+
+
+def _scratch(ds, n_incl=0, P=None, stream=None):
+    """Caller-owned device scratch of the coefficient helpers (hom_coef_scratch_bytes),
+    kept alive until `stream` has passed the work that reads it."""
+    n = C.c_size_t()
+    Pc = None if P is None else (C.c_int32 * 3)(*(list(P) + [1] * (3 - len(P))))
+    L.check(L.load().hom_coef_scratch_bytes(C.byref(ds), int(n_incl), Pc, C.byref(n)), "hom_coef_scratch_bytes")
+    t = torch.empty(max(int(n.value), 1), dtype=torch.uint8, device=_dev())
+    s = stream if stream is not None else torch.cuda.current_stream()
+    if s != torch.cuda.current_stream():
+        t.record_stream(s)
+    return t
+
+
+def _incl_args(cell):
+    d, n = cell.d, cell.n
+    kind = (C.c_int32 * max(n, 1))(*[0 if k == "rect" else 1 for k in cell.kind])
+    cen = np.ascontiguousarray(np.array(cell.center, float).reshape(-1) if n else np.zeros(1))
+    siz = np.zeros((max(n, 1), d))
+    for j, s in enumerate(cell.size):
+        siz[j, :len(s)] = s
+    siz = np.ascontiguousarray(siz.reshape(-1))
+    Ain = np.ascontiguousarray(np.array(cell.A, float).reshape(-1) if n else np.zeros(1))
+    A0 = np.ascontiguousarray(np.asarray(cell.A0, float).reshape(-1))
+    return A0, n, kind, cen, siz, Ain
+
+
+def _pixel_args(cell):
+    d = cell.d
+    P = (C.c_int32 * 3)(*(list(cell.phase.shape) + [1] * (3 - d)))
+    ph = np.ascontiguousarray(cell.phase.astype(np.int32).reshape(-1))
+    pA = np.ascontiguousarray(np.asarray(cell.phase_A, float).reshape(-1))
+    return P, ph, pA
+
+
+def _wait(stream):
+    if stream is not None:
+        stream.wait_stream(torch.cuda.current_stream())
 
 
 def coef_inclusions(cell, N, ncoef, inverse=False, stream=None, M=None):
@@ -94,18 +140,12 @@ def coef_inclusions(cell, N, ncoef, inverse=False, stream=None, M=None):
     ds = _desc(d, N, cell.Y, "fp64", ncoef, M)
     M = quad_grid(N[:d], M)
     out = torch.empty((ncoef,) + tuple(M), dtype=torch.complex128, device=_dev())
-    n = cell.n
-    kind = (C.c_int32 * max(n, 1))(*[0 if k == "rect" else 1 for k in cell.kind])
-    cen = np.ascontiguousarray(np.array(cell.center, float).reshape(-1) if n else np.zeros(1))
-    siz = np.zeros((max(n, 1), d))
-    for j, (k, s) in enumerate(zip(cell.kind, cell.size)):
-        siz[j, :len(s)] = s
-    Ain = np.ascontiguousarray(np.array(cell.A, float).reshape(-1) if n else np.zeros(1))
-    A0 = np.ascontiguousarray(np.asarray(cell.A0, float).reshape(-1))
-    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
-    siz = np.ascontiguousarray(siz.reshape(-1))
-    st = L.load().hom_coef_inclusions(C.byref(ds), dp(A0), n, kind, dp(cen), dp(siz), dp(Ain), int(inverse),
-                                      C.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    A0, n, kind, cen, siz, Ain = _incl_args(cell)
+    scr = _scratch(ds, n, None, stream)
+    _wait(stream)
+    st = L.load().hom_coef_inclusions(C.byref(ds), _dbl(A0), n, kind, _dbl(cen), _dbl(siz), _dbl(Ain), int(inverse),
+                                      C.c_void_p(out.data_ptr()), C.c_void_p(scr.data_ptr()), scr.numel(),
+                                      _stream_ptr(stream))
     L.check(st, "hom_coef_inclusions")
     return out
 
@@ -116,12 +156,12 @@ def coef_pixels(cell, N, ncoef, inverse=False, stream=None, M=None):
     ds = _desc(d, N, cell.Y, "fp64", ncoef, M)
     M = quad_grid(N[:d], M)
     out = torch.empty((ncoef,) + tuple(M), dtype=torch.complex128, device=_dev())
-    P = (C.c_int32 * 3)(*(list(cell.phase.shape) + [1] * (3 - d)))
-    ph = np.ascontiguousarray(cell.phase.astype(np.int32).reshape(-1))
-    pA = np.ascontiguousarray(np.asarray(cell.phase_A, float).reshape(-1))
+    P, ph, pA = _pixel_args(cell)
+    scr = _scratch(ds, 0, cell.phase.shape, stream)
+    _wait(stream)
     st = L.load().hom_coef_pixels(C.byref(ds), P, ph.ctypes.data_as(C.POINTER(C.c_int32)), len(cell.phase_A),
-                                  pA.ctypes.data_as(C.POINTER(C.c_double)), int(inverse),
-                                  C.c_void_p(out.data_ptr()), _stream_ptr(stream))
+                                  _dbl(pA), int(inverse), C.c_void_p(out.data_ptr()), C.c_void_p(scr.data_ptr()),
+                                  scr.numel(), _stream_ptr(stream))
     L.check(st, "hom_coef_pixels")
     return out
 
@@ -135,28 +175,21 @@ def sample_cell(cell, N, ncoef=None, inverse=False, stream=None, closed=False):
     ncoef = cell_ncoef(cell) if ncoef is None else ncoef
     ds = _desc(d, N, cell.Y, "fp64", ncoef)
     out = torch.empty((ncoef,) + N, dtype=torch.float64, device=_dev())
-    if stream is not None:
-        stream.wait_stream(torch.cuda.current_stream())
-    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
     if hasattr(cell, "phase"):
-        P = (C.c_int32 * 3)(*(list(cell.phase.shape) + [1] * (3 - d)))
-        ph = np.ascontiguousarray(cell.phase.astype(np.int32).reshape(-1))
-        pA = np.ascontiguousarray(np.asarray(cell.phase_A, float).reshape(-1))
+        P, ph, pA = _pixel_args(cell)
+        scr = _scratch(ds, 0, cell.phase.shape, stream)
+        _wait(stream)
         st = L.load().hom_sample_pixels(C.byref(ds), P, ph.ctypes.data_as(C.POINTER(C.c_int32)), len(cell.phase_A),
-                                        dp(pA), int(inverse), C.c_void_p(out.data_ptr()), _stream_ptr(stream))
+                                        _dbl(pA), int(inverse), C.c_void_p(out.data_ptr()),
+                                        C.c_void_p(scr.data_ptr()), scr.numel(), _stream_ptr(stream))
         L.check(st, "hom_sample_pixels")
         return out
-    n = cell.n
-    kind = (C.c_int32 * max(n, 1))(*[0 if k == "rect" else 1 for k in cell.kind])
-    cen = np.ascontiguousarray(np.array(cell.center, float).reshape(-1) if n else np.zeros(1))
-    siz = np.zeros((max(n, 1), d))
-    for j, (k, s) in enumerate(zip(cell.kind, cell.size)):
-        siz[j, :len(s)] = s
-    siz = np.ascontiguousarray(siz.reshape(-1))
-    Ain = np.ascontiguousarray(np.array(cell.A, float).reshape(-1) if n else np.zeros(1))
-    A0 = np.ascontiguousarray(np.asarray(cell.A0, float).reshape(-1))
-    st = L.load().hom_sample_inclusions(C.byref(ds), dp(A0), n, kind, dp(cen), dp(siz), dp(Ain), int(inverse),
-                                        int(bool(closed)), C.c_void_p(out.data_ptr()), _stream_ptr(stream))
+    A0, n, kind, cen, siz, Ain = _incl_args(cell)
+    scr = _scratch(ds, n, None, stream)
+    _wait(stream)
+    st = L.load().hom_sample_inclusions(C.byref(ds), _dbl(A0), n, kind, _dbl(cen), _dbl(siz), _dbl(Ain), int(inverse),
+                                        int(bool(closed)), C.c_void_p(out.data_ptr()), C.c_void_p(scr.data_ptr()),
+                                        scr.numel(), _stream_ptr(stream))
     L.check(st, "hom_sample_inclusions")
     return out
 
@@ -184,13 +217,12 @@ def smooth_pixel_cell(cell, stream=None):
     assert cell.d == 2 and len(cell.phase_A) == 2, "two-phase 2D pixel cells"
     f = torch.as_tensor(np.ascontiguousarray(cell.phase == 1).astype(np.int32), device=_dev())
     out = torch.empty_like(f)
-    if stream is not None:
-        stream.wait_stream(torch.cuda.current_stream())
+    _wait(stream)
     P = (C.c_int32 * 2)(*cell.phase.shape)
-    L.check(L.load().hom_smooth_pixels(P, C.c_void_p(f.data_ptr()), C.c_void_p(out.data_ptr()),
-                                       _stream_ptr(stream)), "hom_smooth_pixels")
-    A0, A1 = (np.asarray(a, float) for a in cell.phase_A)
-    table = np.stack([A0 + (k / 16.0) * (A1 - A0) for k in range(17)])
+    A01 = np.ascontiguousarray(np.asarray(cell.phase_A, float).reshape(-1))
+    table = np.zeros((17, 2, 2))
+    L.check(L.load().hom_smooth_pixels(P, C.c_void_p(f.data_ptr()), C.c_void_p(out.data_ptr()), 2, _dbl(A01),
+                                       _dbl(table), _stream_ptr(stream)), "hom_smooth_pixels")
     return homgen.Pixels(d=2, Y=np.asarray(cell.Y, float), phase=out.cpu().numpy().astype(np.int64), phase_A=table)
 
 

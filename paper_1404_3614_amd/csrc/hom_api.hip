@@ -1295,12 +1295,16 @@ size_t gani_carve(const hom_desc* desc, const Sizes& z, const int* grid, GaniDat
   return off;
 }
 
-hom_status hom_smooth_pixels(const int32_t* P, const int32_t* f, int32_t* out, void* stream) {
+hom_status hom_smooth_pixels(const int32_t* P, const int32_t* f, int32_t* out, int32_t d, const double* A01,
+                             double* table, void* stream) {
   if (!P || !f || !out || P[0] < 1 || P[1] < 1) return HOM_E_INVALID;
+  if (table && (d != 2 || !A01)) return HOM_E_INVALID;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  if (launch_smooth2d(P[0], P[1], f, out, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
-    return HOM_E_DEVICE;
-  return HOM_OK;
+  if (launch_smooth2d(P[0], P[1], f, out, st) != hipSuccess) return HOM_E_DEVICE;
+  if (table)       // phase k of the smoothed medium: A0 + (k/16)(A1 - A0), k = 0..16
+    for (int k = 0; k <= 16; ++k)
+      for (int i = 0; i < d * d; ++i) table[k * d * d + i] = A01[i] + (k / 16.0) * (A01[d * d + i] - A01[i]);
+  return hipStreamSynchronize(st) == hipSuccess ? HOM_OK : HOM_E_DEVICE;
 }
 
 // GaNi grid on internal axes from the caller's physical grid (NULL: N); every
@@ -1409,16 +1413,15 @@ struct InclHost {
 // in coefficient components, and A0's components.
 hom_status incl_table(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
                       const double* center, const double* size, const double* A_in, int32_t inverse,
-                      std::vector<InclHost>* inc, double* A0c) {
+                      InclHost* inc, double* A0c) {
   const int d = desc->d, nc = desc->ncoef;
   double A0m[9], A0i[9];
   std::memcpy(A0m, A0, sizeof(double) * d * d);
   inv_small(d, A0m, A0i);
   const double* base0 = inverse ? A0i : A0m;
   if (incl_dev_size() != sizeof(InclHost)) return HOM_E_INVALID;
-  inc->assign(n_incl, InclHost());
   for (int j = 0; j < n_incl; ++j) {
-    InclHost& I = (*inc)[j];
+    InclHost& I = inc[j];
     std::memset(&I, 0, sizeof(I));
     I.kind = kind[j];
     if (I.kind == 1 && d != 3) return HOM_E_INVALID;
@@ -1464,98 +1467,167 @@ hom_status sample_sizes(const hom_desc* desc, int* Nint) {
   return HOM_OK;
 }
 
-// Device copy of A0's components (64 bytes) followed by the inclusion table.
-hom_status incl_upload(const std::vector<InclHost>& inc, const double* A0c, hipStream_t st, void** dev) {
-  const size_t bytes = sizeof(InclHost) * std::max<size_t>(inc.size(), 1) + 64;
-  if (hipMalloc(dev, bytes) != hipSuccess) return HOM_E_DEVICE;
-  if (hipMemcpyAsync(*dev, A0c, 6 * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
-      (!inc.empty() && hipMemcpyAsync((char*)*dev + 64, inc.data(), sizeof(InclHost) * inc.size(),
-                                      hipMemcpyHostToDevice, st) != hipSuccess)) {
-    (void)hipFree(*dev);
+// Device bytes of the inclusion table: A0's components (64 bytes), then the records.
+size_t incl_scratch_bytes(int n_incl) { return 64 + sizeof(InclHost) * (size_t)std::max(n_incl, 1); }
+
+// Copies A0's components and the inclusion table into the device buffer dev
+// (incl_scratch_bytes(n) bytes) and waits for the copies: the host table may
+// be released when this returns.
+hom_status incl_upload(const InclHost* inc, int n, const double* A0c, void* dev, hipStream_t st) {
+  if (hipMemcpyAsync(dev, A0c, 6 * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
+      (n > 0 && hipMemcpyAsync((char*)dev + 64, inc, sizeof(InclHost) * n, hipMemcpyHostToDevice, st) != hipSuccess) ||
+      hipStreamSynchronize(st) != hipSuccess)
     return HOM_E_DEVICE;
-  }
   return HOM_OK;
+}
+
+// Bytes of the pixel-image scratch: the complex image (nc * Pt) and the
+// twiddles of the three axes, each 256-byte aligned; offsets in tw_off.
+size_t pixel_scratch_layout(int nc, const int* Pint, size_t* tw_off) {
+  const size_t Pt = (size_t)Pint[0] * Pint[1] * Pint[2];
+  size_t off = up(nc * Pt * sizeof(Cx<double>));
+  for (int a = 0; a < 3; ++a) {
+    if (tw_off) tw_off[a] = off;
+    off = up(off + Pint[a] * sizeof(Cx<double>));
+  }
+  return off;
+}
+
+// Physical pixel counts to internal axes (2D embeds as (P0, 1, P1)).
+bool pixel_axes(int d, const int32_t* P, int* Pint) {
+  Pint[0] = P[0];
+  Pint[1] = d == 3 ? P[1] : 1;
+  Pint[2] = d == 3 ? P[2] : P[1];
+  for (int a = 0; a < 3; ++a)
+    if (Pint[a] < 1 || Pint[a] > (1 << 16)) return false;
+  return true;
+}
+
+// Coefficient components of every phase (nc per phase, stride 6).
+void phase_components(int d, int nc, int nphase, const double* phase_A, int32_t inverse, double* comp) {
+  for (int q = 0; q < nphase; ++q) {
+    double Am[9], Ai[9];
+    std::memcpy(Am, phase_A + (size_t)q * d * d, sizeof(double) * d * d);
+    if (inverse) inv_small(d, Am, Ai);
+    coef_components(d, nc, inverse ? Ai : Am, comp + (size_t)q * 6);
+  }
+}
+
+// Eigenvalues of a symmetric 3x3 matrix by cyclic Jacobi rotations (host).
+void sym3_eigs(const double* A, double* ev) {
+  double a[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) a[i][j] = 0.5 * (A[3 * i + j] + A[3 * j + i]);
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    const double off = a[0][1] * a[0][1] + a[0][2] * a[0][2] + a[1][2] * a[1][2];
+    const double dia = a[0][0] * a[0][0] + a[1][1] * a[1][1] + a[2][2] * a[2][2];
+    if (off <= 1e-34 * dia) break;
+    for (int p = 0; p < 2; ++p)
+      for (int q = p + 1; q < 3; ++q) {
+        if (a[p][q] == 0.0) continue;
+        const double th = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < 3; ++k) {       // columns p, q
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = c * akp - sn * akq;
+          a[k][q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < 3; ++k) {       // rows p, q
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = c * apk - sn * aqk;
+          a[q][k] = sn * apk + c * aqk;
+        }
+      }
+  }
+  for (int i = 0; i < 3; ++i) ev[i] = a[i][i];
 }
 
 }  // namespace
 
 extern "C" {
 
+hom_status hom_coef_scratch_bytes(const hom_desc* desc, int32_t n_incl, const int32_t* P, size_t* bytes) {
+  if (!desc || !bytes || (desc->d != 2 && desc->d != 3)) return HOM_E_INVALID;
+  const int nc = desc->ncoef;
+  if (nc != 1 && nc != desc->d * (desc->d + 1) / 2) return HOM_E_INVALID;
+  if (!P) {
+    if (n_incl < 0) return HOM_E_INVALID;
+    *bytes = incl_scratch_bytes(n_incl);
+    return HOM_OK;
+  }
+  int Pint[3];
+  if (!pixel_axes(desc->d, P, Pint)) return HOM_E_INVALID;
+  *bytes = pixel_scratch_layout(nc, Pint, nullptr);
+  return HOM_OK;
+}
+
 hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
                                const double* center, const double* size, const double* A_in, int32_t inverse,
-                               void* out, void* stream) {
+                               void* out, void* scratch, size_t scratch_bytes, void* stream) {
   hom_status s = validate_desc(desc, 1);
   if (s != HOM_OK) return s;
-  if (!A0 || !out || n_incl < 0 || (n_incl > 0 && (!kind || !center || !size || !A_in))) return HOM_E_INVALID;
+  if (!A0 || !out || !scratch || n_incl < 0 || (n_incl > 0 && (!kind || !center || !size || !A_in)))
+    return HOM_E_INVALID;
+  if (scratch_bytes < incl_scratch_bytes(n_incl)) return HOM_E_WORKSPACE;
   const int d = desc->d, nc = desc->ncoef;
   Sizes z;
   Plan pl[3];
   fill_sizes(desc, 1, &z, pl);
-  std::vector<InclHost> inc;
+  std::vector<InclHost> inc(std::max(n_incl, 1));
   double A0c[6] = {0, 0, 0, 0, 0, 0};
-  s = incl_table(desc, A0, n_incl, kind, center, size, A_in, inverse, &inc, A0c);
+  s = incl_table(desc, A0, n_incl, kind, center, size, A_in, inverse, inc.data(), A0c);
   if (s != HOM_OK) return s;
   double iY[3] = {1.0 / desc->Y[0], 1.0, 1.0 / desc->Y[1]};
   if (d == 3) iY[1] = 1.0 / desc->Y[1], iY[2] = 1.0 / desc->Y[2];
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  void* dev = nullptr;
-  s = incl_upload(inc, A0c, st, &dev);
+  s = incl_upload(inc.data(), n_incl, A0c, scratch, st);
   if (s != HOM_OK) return s;
-  hom_status rc = HOM_OK;
-  if (launch_coef_incl(d, z.M, iY, nc, (const double*)dev, n_incl, (char*)dev + 64,
-                       reinterpret_cast<Cx<double>*>(out), st) != hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    rc = HOM_E_DEVICE;
-  (void)hipFree(dev);
-  return rc;
+  if (launch_coef_incl(d, z.M, iY, nc, (const double*)scratch, n_incl, (char*)scratch + 64,
+                       reinterpret_cast<Cx<double>*>(out), st) != hipSuccess)
+    return HOM_E_DEVICE;
+  return HOM_OK;
 }
 
 hom_status hom_sample_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
                                  const double* center, const double* size, const double* A_in, int32_t inverse,
-                                 int32_t closed, double* out, void* stream) {
+                                 int32_t closed, double* out, void* scratch, size_t scratch_bytes, void* stream) {
   int Nint[3];
   hom_status s = sample_sizes(desc, Nint);
   if (s != HOM_OK) return s;
-  if (!A0 || !out || n_incl < 0 || (n_incl > 0 && (!kind || !center || !size || !A_in))) return HOM_E_INVALID;
+  if (!A0 || !out || !scratch || n_incl < 0 || (n_incl > 0 && (!kind || !center || !size || !A_in)))
+    return HOM_E_INVALID;
+  if (scratch_bytes < incl_scratch_bytes(n_incl)) return HOM_E_WORKSPACE;
   const int d = desc->d, nc = desc->ncoef;
-  std::vector<InclHost> inc;
+  std::vector<InclHost> inc(std::max(n_incl, 1));
   double A0c[6] = {0, 0, 0, 0, 0, 0};
-  s = incl_table(desc, A0, n_incl, kind, center, size, A_in, inverse, &inc, A0c);
+  s = incl_table(desc, A0, n_incl, kind, center, size, A_in, inverse, inc.data(), A0c);
   if (s != HOM_OK) return s;
   double Yint[3] = {desc->Y[0], 1.0, desc->Y[1]};
   if (d == 3) Yint[1] = desc->Y[1], Yint[2] = desc->Y[2];
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  void* dev = nullptr;
-  s = incl_upload(inc, A0c, st, &dev);
+  s = incl_upload(inc.data(), n_incl, A0c, scratch, st);
   if (s != HOM_OK) return s;
-  hom_status rc = HOM_OK;
-  if (launch_sample_incl(Nint, Yint, nc, (const double*)dev, n_incl, (char*)dev + 64, closed != 0, out, st) !=
-          hipSuccess ||
-      hipStreamSynchronize(st) != hipSuccess)
-    rc = HOM_E_DEVICE;
-  (void)hipFree(dev);
-  return rc;
+  if (launch_sample_incl(Nint, Yint, nc, (const double*)scratch, n_incl, (char*)scratch + 64, closed != 0, out, st) !=
+      hipSuccess)
+    return HOM_E_DEVICE;
+  return HOM_OK;
 }
 
 hom_status hom_sample_pixels(const hom_desc* desc, const int32_t* P, const int32_t* phase, int32_t nphase,
-                             const double* phase_A, int32_t inverse, double* out, void* stream) {
+                             const double* phase_A, int32_t inverse, double* out, void* scratch, size_t scratch_bytes,
+                             void* stream) {
   int Nint[3];
   hom_status s = sample_sizes(desc, Nint);
   if (s != HOM_OK) return s;
-  if (!P || !phase || nphase < 1 || !phase_A || !out) return HOM_E_INVALID;
+  if (!P || !phase || nphase < 1 || !phase_A || !out || !scratch) return HOM_E_INVALID;
   const int d = desc->d, nc = desc->ncoef;
-  int Pint[3] = {P[0], 1, P[1]};
-  if (d == 3) Pint[1] = P[1], Pint[2] = P[2];
-  for (int a = 0; a < 3; ++a)
-    if (Pint[a] < 1) return HOM_E_INVALID;
+  int Pint[3];
+  if (!pixel_axes(d, P, Pint)) return HOM_E_INVALID;
+  if (scratch_bytes < pixel_scratch_layout(nc, Pint, nullptr)) return HOM_E_WORKSPACE;
   const size_t Pt = (size_t)Pint[0] * Pint[1] * Pint[2];
   std::vector<double> comp((size_t)nphase * 6);
-  for (int q = 0; q < nphase; ++q) {
-    double Am[9], Ai[9];
-    std::memcpy(Am, phase_A + (size_t)q * d * d, sizeof(double) * d * d);
-    if (inverse) inv_small(d, Am, Ai);
-    coef_components(d, nc, inverse ? Ai : Am, &comp[(size_t)q * 6]);
-  }
+  phase_components(d, nc, nphase, phase_A, inverse, comp.data());
   std::vector<double> img(nc * Pt);
   for (size_t t = 0; t < Pt; ++t) {
     const int q = phase[t];
@@ -1565,44 +1637,38 @@ hom_status hom_sample_pixels(const hom_desc* desc, const int32_t* P, const int32
   double Yint[3] = {desc->Y[0], 1.0, desc->Y[1]};
   if (d == 3) Yint[1] = desc->Y[1], Yint[2] = desc->Y[2];
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  double* dev = nullptr;
-  if (hipMalloc((void**)&dev, img.size() * sizeof(double)) != hipSuccess) return HOM_E_DEVICE;
-  hom_status rc = HOM_OK;
+  double* dev = reinterpret_cast<double*>(scratch);
   if (hipMemcpyAsync(dev, img.data(), img.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess ||
-      launch_sample_pixels(Nint, Yint, Pint, nc, dev, out, st) != hipSuccess || hipStreamSynchronize(st) != hipSuccess)
-    rc = HOM_E_DEVICE;
-  (void)hipFree(dev);
-  return rc;
+      hipStreamSynchronize(st) != hipSuccess || launch_sample_pixels(Nint, Yint, Pint, nc, dev, out, st) != hipSuccess)
+    return HOM_E_DEVICE;
+  return HOM_OK;
 }
 
 hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t* phase, int32_t nphase,
-                           const double* phase_A, int32_t inverse, void* out, void* stream) {
+                           const double* phase_A, int32_t inverse, void* out, void* scratch, size_t scratch_bytes,
+                           void* stream) {
   hom_status s = validate_desc(desc, 1);
   if (s != HOM_OK) return s;
-  if (!P || !phase || nphase < 1 || !phase_A || !out) return HOM_E_INVALID;
+  if (!P || !phase || nphase < 1 || !phase_A || !out || !scratch) return HOM_E_INVALID;
   const int d = desc->d, nc = desc->ncoef;
   Sizes z;
   Plan pl[3];
   fill_sizes(desc, 1, &z, pl);
-  int Pint[3] = {P[0], 1, P[1]};
-  if (d == 3) Pint[1] = P[1], Pint[2] = P[2];
+  int Pint[3];
+  if (!pixel_axes(d, P, Pint)) return HOM_E_INVALID;
   Plan pp[3];
   for (int a = 0; a < 3; ++a) {
-    if (Pint[a] < 1) return HOM_E_INVALID;
     if (Pint[a] == 1) {
       pp[a].n = 0;
       continue;
     }
     if (!smooth235(Pint[a], &pp[a])) return HOM_E_UNSUPPORTED_SIZE;
   }
+  size_t twoff[3];
+  if (scratch_bytes < pixel_scratch_layout(nc, Pint, twoff)) return HOM_E_WORKSPACE;
   const size_t Pt = (size_t)Pint[0] * Pint[1] * Pint[2];
   std::vector<double> comp((size_t)nphase * 6);
-  for (int q = 0; q < nphase; ++q) {
-    double Am[9], Ai[9];
-    std::memcpy(Am, phase_A + (size_t)q * d * d, sizeof(double) * d * d);
-    if (inverse) inv_small(d, Am, Ai);
-    coef_components(d, nc, inverse ? Ai : Am, &comp[(size_t)q * 6]);
-  }
+  phase_components(d, nc, nphase, phase_A, inverse, comp.data());
   std::vector<Cx<double>> img(nc * Pt);
   for (size_t t = 0; t < Pt; ++t) {
     const int q = phase[t];
@@ -1614,19 +1680,14 @@ hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t
   }
   std::vector<Cx<double>> tw[3];
   std::vector<Cx<float>> tw32;
-  size_t twoff[3], off = up(nc * Pt * sizeof(Cx<double>));
-  for (int a = 0; a < 3; ++a) {
-    twiddles(Pint[a], tw[a], tw32);
-    twoff[a] = off;
-    off = up(off + Pint[a] * sizeof(Cx<double>));
-  }
+  for (int a = 0; a < 3; ++a) twiddles(Pint[a], tw[a], tw32);
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  char* dev = nullptr;
-  if (hipMalloc((void**)&dev, off) != hipSuccess) return HOM_E_DEVICE;
+  char* dev = reinterpret_cast<char*>(scratch);
   Cx<double>* D = reinterpret_cast<Cx<double>*>(dev);
   hipError_t e = hipMemcpyAsync(D, img.data(), img.size() * sizeof(Cx<double>), hipMemcpyHostToDevice, st);
   for (int a = 0; a < 3 && e == hipSuccess; ++a)
     e = hipMemcpyAsync(dev + twoff[a], tw[a].data(), Pint[a] * sizeof(Cx<double>), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);     // the host staging vectors end with this call
   // unnormalised forward DFT of the image along each axis
   if (e == hipSuccess && Pint[0] > 1)
     e = launch_line_fft<double>(D, nc, Pint[0], Pint[1] * Pint[2], pp[0], (const Cx<double>*)(dev + twoff[0]), 0, st);
@@ -1636,9 +1697,33 @@ hom_status hom_coef_pixels(const hom_desc* desc, const int32_t* P, const int32_t
     e = launch_line_fft<double>(D, nc * Pint[0] * Pint[1], Pint[2], 1, pp[2], (const Cx<double>*)(dev + twoff[2]), 0,
                                 st);
   if (e == hipSuccess) e = launch_pixel_factor(d, z.M, Pint, nc, D, reinterpret_cast<Cx<double>*>(out), st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(dev);
   return e == hipSuccess ? HOM_OK : HOM_E_DEVICE;
+}
+
+hom_status hom_phase_eig_range(int32_t d, int32_t nphase, const double* phase_A, double* range) {
+  if ((d != 2 && d != 3) || nphase < 1 || !phase_A || !range) return HOM_E_INVALID;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int q = 0; q < nphase; ++q) {
+    const double* A = phase_A + (size_t)q * d * d;
+    for (int i = 0; i < d * d; ++i)
+      if (!std::isfinite(A[i])) return HOM_E_INVALID;
+    double ev[3];
+    if (d == 2) {
+      const double a = A[0], c = A[3], b = 0.5 * (A[1] + A[2]);
+      const double m = 0.5 * (a + c), r = std::hypot(0.5 * (a - c), b);
+      ev[0] = m - r;
+      ev[1] = m + r;
+    } else {
+      sym3_eigs(A, ev);
+    }
+    for (int i = 0; i < d; ++i) {
+      lo = std::min(lo, ev[i]);
+      hi = std::max(hi, ev[i]);
+    }
+  }
+  range[0] = lo;
+  range[1] = hi;
+  return lo > 0.0 ? HOM_OK : HOM_E_NOT_SPD;
 }
 
 // Average per-launch time of each operator pass over n units (HIP events on the stream).

@@ -130,3 +130,41 @@ def test_sizes_beyond_the_lds_of_the_passes_are_refused():
     for grid, expect in (((15, 15), 0), ((16, 15), 0), ((16, 16), 0), ((17, 15), -2), ((14, 15), -2)):
         g = (C.c_int32 * 3)(grid[0], grid[1], 1)
         assert lib.hom_gani_workspace_bytes(C.byref(ds), g, C.byref(ws)) == expect, grid
+
+
+def test_phase_eig_range_matches_eigvalsh():
+    """hom_phase_eig_range (host arithmetic, no device) against LAPACK's
+    symmetric eigenvalues, with ill-conditioned and rotated phases."""
+    L, lib = _lib()
+    import homgen
+    rng = np.random.default_rng(11)
+    for d in (2, 3):
+        for trial in range(20):
+            mats = [homgen.random_spd(rng, d, 1e-3, 1e3) for _ in range(1 + trial % 4)]
+            A = np.ascontiguousarray(np.stack(mats).reshape(-1))
+            out = (C.c_double * 2)()
+            st = lib.hom_phase_eig_range(d, len(mats), A.ctypes.data_as(C.POINTER(C.c_double)), out)
+            assert st == 0
+            ev = np.concatenate([np.linalg.eigvalsh(m) for m in mats])
+            assert abs(out[0] - ev.min()) <= 1e-12 * ev.max()
+            assert abs(out[1] - ev.max()) <= 1e-12 * ev.max()
+    bad = np.ascontiguousarray(np.array([[1.0, 2.0], [2.0, 1.0]]).reshape(-1))     # eigenvalues -1, 3
+    out = (C.c_double * 2)()
+    assert lib.hom_phase_eig_range(2, 1, bad.ctypes.data_as(C.POINTER(C.c_double)), out) == L.HOM_E_NOT_SPD
+    assert lib.hom_phase_eig_range(4, 1, bad.ctypes.data_as(C.POINTER(C.c_double)), out) == L.HOM_E_INVALID
+
+
+def test_coef_scratch_bytes():
+    L, lib = _lib()
+    n = C.c_size_t()
+    ds = _desc(L)
+    assert lib.hom_coef_scratch_bytes(C.byref(ds), 10, None, C.byref(n)) == 0
+    small = n.value
+    assert lib.hom_coef_scratch_bytes(C.byref(ds), 100, None, C.byref(n)) == 0
+    assert n.value > small >= 64
+    P = (C.c_int32 * 3)(125, 125, 1)
+    assert lib.hom_coef_scratch_bytes(C.byref(ds), 0, P, C.byref(n)) == 0
+    assert n.value >= 125 * 125 * 16
+    assert lib.hom_coef_scratch_bytes(C.byref(ds), -1, None, C.byref(n)) == L.HOM_E_INVALID
+    P0 = (C.c_int32 * 3)(0, 125, 1)
+    assert lib.hom_coef_scratch_bytes(C.byref(ds), 0, P0, C.byref(n)) == L.HOM_E_INVALID
