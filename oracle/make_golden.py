@@ -7,6 +7,11 @@ reference tolerance 1e-11 (relative residual, Convergence-criteria remark of
 Sec. 7.2) and records the guaranteed bounds (Def. upper_lower_bounds), the
 Voigt/Reuss means and the CG iteration counts needed to reach 1e-6, 1e-8 and
 1e-11.  Inputs come from the seeded generators in ``homgen``.
+
+The C4 sample ("C4s_<d>d_N<N>") is the highest-contrast cell of every size
+class of the mixed batch ``homgen.batch_specs()`` (512 random-square 2D cells
+with N in {13, 41, 63, 313} and 64 random-sphere 3D cells at N = 41, contrast
+log-uniform in [2, 1e3]); the entry records its index in the batch.
 """
 from __future__ import annotations
 
@@ -36,6 +41,21 @@ CONFIGS = {
 }
 
 
+def c4_sample():
+    """{name: (index, N, cell)}: the highest-contrast cell of each size class of
+    the default mixed batch."""
+    pick = {}
+    for i, (N, cell, rho) in enumerate(homgen.batch_specs()):
+        key = (cell.d, N)
+        if key not in pick or rho > pick[key][2]:
+            pick[key] = (i, cell, rho)
+    return {f"C4s_{d}d_N{N}": (i, N, cell, rho) for (d, N), (i, cell, rho) in sorted(pick.items())}
+
+
+for _name, (_i, _N, _cell, _rho) in c4_sample().items():
+    CONFIGS[_name] = dict(cell=(lambda c=_cell: c), N=_N, batch_index=_i, rho=_rho)
+
+
 def first_below(hist, tol):
     for i, r in enumerate(hist):
         if r <= tol:
@@ -58,6 +78,8 @@ def run(name, spec, tol=1e-11):
     b = ga.bounds_from_fields(prob, prim, dual)
     voigt, reuss = ga.voigt_reuss(prob)
     out = {k: np.asarray(v).tolist() for k, v in b.items()}
+    if "batch_index" in spec:
+        out.update(batch_index=spec["batch_index"], rho=spec["rho"])
     out.update(d=d, N=list(prob.N), M=list(prob.M), tol=tol, iters=its,
                voigt=voigt.tolist(), reuss=reuss.tolist(), seconds=round(time.time() - t0, 2))
     return out
