@@ -295,11 +295,15 @@ hom_status hom_gani_workspace_bytes(const hom_desc* desc, const int32_t* grid, s
 /* Switch later solves and hom_apply of pb to GaNi on the grid `grid` (as
  * above): AN, BN are the point values of A and of A^-1 on that grid (layout
  * of hom_sample_*, device, read during the call).  ws: device workspace of hom_gani_workspace_bytes bytes, kept until
- * hom_clear_gani or hom_destroy (it holds the values, their FP32 copies, the
- * N-point DFT of the values on the stored half of Z_N, which gives the
- * right-hand side, and twiddles).  The solves then stop and report as before;
- * the energy in hom_info is the GaNi energy.  Batches reject GaNi problems
- * (HOM_E_INVALID).  HOM_E_UNSUPPORTED_SIZE when an N_a has other factors. */
+ * hom_clear_gani or hom_destroy (it holds the values, the N-point DFT of the
+ * values on the stored half of Z_N, which gives the right-hand side, and
+ * twiddles).  The solves then stop and report as before; the energy in
+ * hom_info is the GaNi energy.  GaNi solves, hom_apply and hom_dual_start run
+ * in FP64 whatever hom_desc.precision says: the exact bounds of a GaNi
+ * minimiser (step (iii)) are first order in its algebraic error, because it
+ * does not minimise the exact form, so FP32 transforms would enter the bounds
+ * at full strength.  Batches reject GaNi problems (HOM_E_INVALID).
+ * HOM_E_UNSUPPORTED_SIZE when an N_a has other factors. */
 hom_status hom_set_gani(hom_problem* pb, const int32_t* grid, const double* AN, const double* BN, void* ws,
                         size_t ws_bytes);
 

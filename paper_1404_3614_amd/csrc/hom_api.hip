@@ -119,11 +119,14 @@ struct Sizes {
 // GaNi mode of a problem (Def. GaNi, the paper's Algorithm): solves use the
 // trapezoidal rule on the N grid, i.e. point values of A and A^-1 there and
 // N-point transforms; the bounds keep the exact quadrature.  Buffers live in a
-// caller-owned workspace (hom_set_gani).
+// caller-owned workspace (hom_set_gani).  GaNi solves run in FP64 in either
+// precision mode: the exact bounds of a GaNi minimiser are first order in its
+// algebraic error (it does not minimise the exact form), so FP32 transforms
+// would cost their rounding error at full strength; in mixed problems the FP64
+// intermediates use the problem's (FP64) bound-evaluation buffers.
 struct GaniData {
   bool on = false;
   double* coef64[2] = {};          // [nc][Nt] point values of A (primal) and A^-1 (dual)
-  float* coef32[2] = {};           // FP32 copies (mixed precision)
   Cx<double>* ahat[2] = {};        // [nc][S] N-point DFT of the point values, stored half
   Cx<double>* tw64[3] = {};
   Cx<float>* tw32[3] = {};
@@ -483,7 +486,7 @@ void fill_unit(hom_problem* pb, int k, int L, const double* E, double* const* x,
   const bool mixed = pb->desc.precision == HOM_MIXED;
   const GaniData& gn = pb->gani;
   if (gani) {
-    hu->coef = mixed ? (const void*)gn.coef32[k] : (const void*)gn.coef64[k];
+    hu->coef = gn.coef64[k];
     hu->ahat = gn.ahat[k];
   } else {
     hu->coef = mixed ? (const void*)pb->coef32[k] : (const void*)pb->coef64[k];
@@ -497,8 +500,10 @@ void fill_unit(hom_problem* pb, int k, int L, const double* E, double* const* x,
     hu->b[l] = sb.b[l];
     for (int c = 0; c < 3; ++c) hu->E[l][c] = (E && c < pb->desc.d) ? E[l * pb->desc.d + c] : 0.0;
   }
-  hu->bufA = sb.bufA;
-  hu->bufB = sb.bufB;
+  // GaNi runs FP64 (see GaniData): the FP32-sized pass buffers of a mixed
+  // problem are too small for it, the FP64 bound buffers hold its N-grid lines
+  hu->bufA = (gani && mixed) ? pb->bbufA : sb.bufA;
+  hu->bufB = (gani && mixed) ? pb->bbufB : sb.bufB;
   hu->part_g = sb.part_g;
   hu->part_d = sb.part_d;
   hu->part_q = sb.part_q;
@@ -858,9 +863,9 @@ hom_status solve_impl(hom_problem* pb, int k, int nload, const double* E, const 
   if (s != HOM_OK) return s;
   if (!info) return HOM_E_INVALID;
   hipStream_t st = pb->stream;
-  const bool fp32 = pb->desc.precision == HOM_MIXED;
-  SlotBufs& sb = pb->slot[k];
   const bool gani = pb->gani.on;
+  const bool fp32 = pb->desc.precision == HOM_MIXED && !gani;
+  SlotBufs& sb = pb->slot[k];
   if (!gani && !pb->tuned[k][nload]) {
     s = solve_tuning(&pb, 1, k, nload, sb.unit, st, &pb->tune[k][nload]);
     if (s != HOM_OK) return s;
@@ -1099,7 +1104,7 @@ hom_status hom_apply(hom_problem* pb, int32_t dual, const double* x, double* y) 
   if (!pb || !x || !y || (dual != 0 && dual != 1)) return HOM_E_INVALID;
   const int k = dual;
   hipStream_t st = pb->stream;
-  const bool fp32 = pb->desc.precision == HOM_MIXED;
+  const bool fp32 = pb->desc.precision == HOM_MIXED && !pb->gani.on;
   Geo g = pb->gani.on ? make_geo_gani(pb, k, 1, fp32) : make_geo(pb, k, 1, fp32);
   SlotBufs& sb = pb->slot[k];
   UnitDev* hu = &pb->host_unit[k];
@@ -1156,8 +1161,8 @@ hom_status hom_dual_start(hom_problem* pb, const double* const* primal, const do
   for (int i = 0; i < d * d; ++i)
     if (!std::isfinite(Ai[i])) return HOM_E_INVALID;
   hipStream_t st = pb->stream;
-  const bool fp32 = pb->desc.precision == HOM_MIXED;
   const bool gani = pb->gani.on;
+  const bool fp32 = pb->desc.precision == HOM_MIXED && !gani;
   const Geo gin = gani ? make_geo_gani(pb, 0, 1, fp32) : make_geo(pb, 0, 1, fp32);
   const Geo gout = gani ? make_geo_gani(pb, 1, 1, fp32) : make_geo(pb, 1, 1, fp32);
   SlotBufs& sb = pb->slot[0];
@@ -1271,16 +1276,10 @@ size_t gani_carve(const hom_desc* desc, const Sizes& z, const int* grid, GaniDat
   auto ptr = [&](size_t o) -> char* { return base ? base + o : nullptr; };
   const int nc = z.nc;
   const size_t Nt = (size_t)grid[0] * grid[1] * grid[2];
-  const bool mixed = desc->precision == HOM_MIXED;
+  (void)desc;
   for (int k = 0; k < 2; ++k) {
     size_t o = take(nc * Nt * sizeof(double));
     if (gd) gd->coef64[k] = (double*)ptr(o);
-    if (mixed) {
-      o = take(nc * Nt * sizeof(float));
-      if (gd) gd->coef32[k] = (float*)ptr(o);
-    } else if (gd) {
-      gd->coef32[k] = nullptr;
-    }
     o = take(nc * (size_t)z.S * sizeof(Cx<double>));
     if (gd) gd->ahat[k] = (Cx<double>*)ptr(o);
   }
@@ -1378,7 +1377,6 @@ hom_status hom_set_gani(hom_problem* pb, const int32_t* grid, const double* AN, 
     const double* src = k == 0 ? AN : BN;
     HIPCHK(hipMemcpyAsync(gd.coef64[k], src, nc * Nt * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(launch_real_to_cx(gd.coef64[k], gd.scratch, nc * Nt, 1.0, st));
-    if (gd.coef32[k]) HIPCHK(launch_coef_real(gd.scratch, gd.coef64[k], gd.coef32[k], (long)(nc * Nt), st));
     // Fourier coefficients of the point values: the grid DFT over the number of points, kept on
     // Z_N (the Nyquist frequencies of an even grid are dropped with the truncation)
     if (G[0] > 1) HIPCHK(launch_line_fft<double>(gd.scratch, nc, G[0], G[1] * G[2], gd.plan[0], gd.tw64[0], 0, st));
