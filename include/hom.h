@@ -221,6 +221,22 @@ hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n
                                const double* center, const double* size, const double* A_in,
                                int32_t inverse, void* out, void* scratch, size_t scratch_bytes, void* stream);
 
+/* hom_coef_inclusions without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Arguments and result as hom_coef_inclusions, without the
+ * scratch: the inclusion table goes to a device array of the library, one
+ * fixed copy of 53,504 bytes per GPU, held until the process ends, which
+ * limits n_incl to 512 (HOM_E_UNSUPPORTED_SIZE above that, before anything is
+ * launched).  stream must belong to the current device (HOM_E_INVALID
+ * otherwise).  The call synchronises the stream before returning, so calls
+ * made one after another from one host thread never overlap; calls that
+ * overlap on one GPU (concurrent host threads) race on the shared table and
+ * must be serialised by the caller.  No hipMalloc, hipFree or allocating
+ * library routine is called; the host table is staged on the stack. */
+hom_status hom_coef_inclusions_static(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
+                                      const double* center, const double* size, const double* A_in,
+                                      int32_t inverse, void* out, void* stream);
+
 /* Device-side Fourier coefficients of a pixel/voxel image (Remark inclusion
  * summed over pixels): pixel i_a along axis a covers
  * [-Y_a/2 + i_a Y_a/P_a, -Y_a/2 + (i_a+1) Y_a/P_a); P_a must have factors 2, 3 and 5

@@ -66,6 +66,9 @@ EXPORTS = {
                                         C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
                                         C.c_void_p]),
+    "hom_coef_inclusions_static": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_double), C.c_int32,
+                                               C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                               C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p]),
     "hom_coef_pixels": (C.c_int32, [C.POINTER(Desc), C.POINTER(C.c_int32), C.POINTER(C.c_int32), C.c_int32,
                                     C.POINTER(C.c_double), C.c_int32, C.c_void_p, C.c_void_p, C.c_size_t,
                                     C.c_void_p]),

@@ -1587,6 +1587,80 @@ hom_status hom_coef_inclusions(const hom_desc* desc, const double* A0, int32_t n
   return HOM_OK;
 }
 
+}  // extern "C"
+
+// ---- allocation-free variant of hom_coef_inclusions: the inclusion table goes
+// to a fixed device array of the library instead of caller scratch.
+
+namespace {
+constexpr int kStaticMaxIncl = 512;
+constexpr size_t kStaticInclBytes = (64 + sizeof(InclHost) * kStaticMaxIncl + 255) & ~size_t(255);
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+}  // namespace
+
+// One copy per GPU; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (static_table below).
+static __device__ __align__(256) unsigned char scratch[kStaticInclBytes];
+
+namespace {
+// Device address of this GPU's copy of the array, looked up once per device
+// with that device current.
+hom_status static_table(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return HOM_E_DEVICE;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return HOM_E_DEVICE;
+    g_static_ptr[dev] = p;
+  }
+  *out = g_static_ptr[dev];
+  return HOM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+hom_status hom_coef_inclusions_static(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
+                                      const double* center, const double* size, const double* A_in, int32_t inverse,
+                                      void* out, void* stream) {
+  hom_status s = validate_desc(desc, 1);
+  if (s != HOM_OK) return s;
+  if (!A0 || !out || n_incl < 0 || (n_incl > 0 && (!kind || !center || !size || !A_in))) return HOM_E_INVALID;
+  if (n_incl > kStaticMaxIncl) return HOM_E_UNSUPPORTED_SIZE;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return HOM_E_DEVICE;
+  if (st) {
+    hipDevice_t sdev = -1;
+    if (hipStreamGetDevice(st, &sdev) != hipSuccess) return HOM_E_DEVICE;
+    if (sdev != dev) return HOM_E_INVALID;
+  }
+  void* table = nullptr;
+  s = static_table(&table);
+  if (s != HOM_OK) return s;
+  const int d = desc->d, nc = desc->ncoef;
+  Sizes z;
+  Plan pl[3];
+  fill_sizes(desc, 1, &z, pl);
+  InclHost inc[kStaticMaxIncl];          // host staging on the stack: no heap either
+  double A0c[6] = {0, 0, 0, 0, 0, 0};
+  s = incl_table(desc, A0, n_incl, kind, center, size, A_in, inverse, inc, A0c);
+  if (s != HOM_OK) return s;
+  double iY[3] = {1.0 / desc->Y[0], 1.0, 1.0 / desc->Y[1]};
+  if (d == 3) iY[1] = 1.0 / desc->Y[1], iY[2] = 1.0 / desc->Y[2];
+  // every word the kernel reads (A0's components, n_incl records) is written here
+  s = incl_upload(inc, n_incl, A0c, table, st);
+  if (s != HOM_OK) return s;
+  if (launch_coef_incl(d, z.M, iY, nc, (const double*)table, n_incl, (char*)table + 64,
+                       reinterpret_cast<Cx<double>*>(out), st) != hipSuccess)
+    return HOM_E_DEVICE;
+  // the next call may overwrite the table: finish reading it first
+  return hipStreamSynchronize(st) == hipSuccess ? HOM_OK : HOM_E_DEVICE;
+}
+
 hom_status hom_sample_inclusions(const hom_desc* desc, const double* A0, int32_t n_incl, const int32_t* kind,
                                  const double* center, const double* size, const double* A_in, int32_t inverse,
                                  int32_t closed, double* out, void* scratch, size_t scratch_bytes, void* stream) {
