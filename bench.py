@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--cpu-cells", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true", help="skip the one-cell-at-a-time comparison leg")
     ap.add_argument("--no-energy", action="store_true", help="skip the guaranteed-energy-rule leg")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 leg of the same cells")
     ap.add_argument("--tiles", default=None,
                     help="pin the FP32 tile shape: row_pairs,row_threads,apply_points,apply_half_exchange,"
                          "apply_all_packs")
@@ -98,6 +99,40 @@ def measured_traffic(tiles):
     return blob.get("bytes_per_launch")
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "reference_bounds.json")
+
+
+def golden(name):
+    """Oracle bounds (CG to 1e-11) of a configuration, written by oracle/make_golden.py."""
+    import numpy as np
+    try:
+        with open(GOLDEN) as f:
+            g = json.load(f)[name]
+    except (OSError, KeyError, ValueError):
+        return None
+    return {k: np.array(g[k]) for k in ("A_up", "A_low")}
+
+
+def bound_error(res, ref):
+    """Relative bound error max_ab |X - X_ref|_ab / ||X_ref||_2 for X in {upper, lower}."""
+    import numpy as np
+    if ref is None:
+        return None
+    return {k: float(np.abs(res[k] - ref[k]).max() / np.linalg.norm(ref[k], 2)) for k in ("A_up", "A_low")}
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def c2_cell(i):
     import homgen
     return homgen.pixel_cell(1404002 + 7919 * i, P=125, values=(1.0, 100.0))
@@ -123,10 +158,14 @@ def apply_bytes(pb, nload):
 def pass_bytes(pb, nload):
     """Algorithmic bytes per unit (one cell, nload loads) of each pass of one
     CG iteration (primal, m = 1 component per load):
-      first: CG vectors x, p, r, s read and x, r written (FP64 complex on the
-             stored half of Z_N) + the row-transformed intermediate written;
-      apply: intermediate read and written + coefficient on the doubled grid read;
-      last : intermediate read + r, p, s read and p, s written."""
+      first  : CG vectors x, p, r, s read and x, r written (FP64 complex on the
+               stored half of Z_N) + the row-transformed intermediate written
+               (N0 x N1 x M2 per pack; 2D: N0 x M1);
+      mid_inv: (3D) that intermediate read, N0 x M1 x M2 written;
+      apply  : intermediate (N0 x M1 x M2) read and written + coefficient on the
+               doubled grid read;
+      mid_fwd: (3D) N0 x M1 x M2 read, N0 x N1 x M2 written;
+      last   : row intermediate read + r, p, s read and p, s written."""
     d = pb.d
     N = list(pb.N)
     M = [2 * n - 1 for n in N]
@@ -141,7 +180,25 @@ def pass_bytes(pb, nload):
     for n in N[1:-1]:
         inner *= n
     rowbuf = N[0] * inner * M[-1] * P * cs
-    return dict(first=6 * vec + rowbuf, apply=apply_bytes(pb, nload), last=rowbuf + 5 * vec)
+    out = dict(first=6 * vec + rowbuf, apply=apply_bytes(pb, nload), last=rowbuf + 5 * vec)
+    if d == 3:
+        full = N[0] * M[1] * M[2] * P * cs
+        out.update(mid_inv=rowbuf + full, mid_fwd=full + rowbuf)
+    return out
+
+
+def survey_matvec_bytes(pb, nload):
+    """The minimum bytes of one operator application to the nload loads of a
+    cell: the coefficient on the doubled grid read once (FP32 in mixed mode,
+    FP64 otherwise) and, per load, the FP64 potential coefficients of Z_N read
+    and the result written (N^d reals each: the stored half of the complex
+    spectrum)."""
+    Mt, Nt = 1, 1
+    for n in pb.N:
+        Mt *= 2 * n - 1
+        Nt *= n
+    rs = 4 if pb.precision == "mixed" else 8
+    return pb.ncoef * Mt * rs + nload * 2 * Nt * 8
 
 
 # FP32 flops of the column pass as executed (a multiply-add counts 2).  The
@@ -256,25 +313,41 @@ def apply_flops(pb, nload):
     M = [2 * n - 1 for n in pb.N]
     P = (nload * pb.d + 1) // 2
     coef = 2 if pb.ncoef == 1 else 6
-    return M[-1] * P * (column_line_flops(M[0])[0] + coef * M[0])
+    lines = 1
+    for m in M[1:]:
+        lines *= m
+    return lines * P * (column_line_flops(M[0])[0] + coef * M[0])
 
 
-VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12   # 256 CUs x 4 SIMD x 16 lanes x FMA at 2.4 GHz (no packed FP32)
+# FP32 vector peak of the chip: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed FP32) x 2.4 GHz =
+# 157.3 TFLOP/s; without packed FP32 instructions (this build emits none) half of it
+VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2 * 2.4e9 / 1e12
+VALU_UNPACKED_TFLOPS = VALU_PEAK_TFLOPS / 2
 
 
-def cpu_baseline(ncells, tol):
-    """The FP64 oracle on a bounded sample: ncells C2 bound pairs on the host."""
-    import numpy as np
+def cpu_baseline(ncells, tol, gpu_results=None):
+    """The FP64 oracle on a bounded sample: ncells C2 bound pairs on the host
+    (and the GPU bounds of the same cells against it)."""
     from oracle import galerkin as ga, spectral as sp
     sp.WORKERS = min(16, os.cpu_count() or 1)
     t0 = time.perf_counter()
+    errs = []
     for i in range(ncells):
         prob = ga.make_problem(c2_cell(i), 313)
-        ga.bounds(prob, tol=tol)
+        ref = ga.bounds(prob, tol=tol)
+        if gpu_results is not None and i < len(gpu_results):
+            errs.append(bound_error(gpu_results[i], ref))
     dt = time.perf_counter() - t0
-    return dict(value=ncells / dt, unit="bound pairs/s", cores=sp.WORKERS, kind="oracle",
-                sample=f"{ncells} C2 cell(s): setup + 2 primal + 2 dual FP64 CG solves to {tol:g} + bounds, "
-                       f"{dt:.1f} s; scipy.fft with {sp.WORKERS} worker threads, other NumPy work single-threaded")
+    out = dict(value=ncells / dt, unit="bound pairs/s", cores=sp.WORKERS, kind="oracle",
+               sample=f"{ncells} C2 cell(s): setup + 2 primal + 2 dual FP64 CG solves to {tol:g} + bounds, "
+                      f"{dt:.1f} s; scipy.fft with {sp.WORKERS} worker threads, other NumPy work single-threaded",
+               cpu_model=cpu_model(), host_cpus=os.cpu_count())
+    if errs:
+        out["gpu_bound_diff_vs_this_oracle_run"] = dict(
+            A_up=max(e["A_up"] for e in errs), A_low=max(e["A_low"] for e in errs),
+            note="both sides stop at the same residual tolerance; the reference at 1e-11 is in "
+                 "config.bound_error_vs_oracle")
+    return out
 
 
 def main():
@@ -395,6 +468,37 @@ def main():
                                      "(spectrum bound from the phases' eigenvalue range) below etol times the "
                                      "energy of the iterate, whichever first")
 
+    # bound error of cell 0 (the C2 cell of the golden file) against the oracle (CG to 1e-11)
+    err_mixed = bound_error(results[-1][0], golden("C2"))
+
+    # the same cells in all-FP64 (FP64 transforms and coefficient), batched the same way
+    fp64_leg = None
+    if not args.no_fp64 and args.precision == "mixed":
+        probs64 = [H.Problem(2, N, (1.0, 1.0), Ah, Bh, precision="fp64", ncoef=nc, max_loads=2, stream=stream)
+                   for (Ah, Bh, nc) in coefs]
+        batch64 = H.Batch(probs64)
+
+        def step64():
+            batch64.update_coefficients(pairs)
+            return batch64.solve_bounds(tol=args.tol)
+
+        step64()
+        torch.cuda.synchronize()
+        n64 = max(1, min(args.steps, 3))
+        t0 = time.perf_counter()
+        for _ in range(n64):
+            res64 = step64()
+        torch.cuda.synchronize()
+        dt64 = time.perf_counter() - t0
+        fp64_leg = dict(bound_pairs_per_s=round(B * n64 / dt64, 3), steps=n64,
+                        ms_per_step=round(1e3 * dt64 / n64, 3),
+                        cg_iters=[i["iters"] for i in res64[0]["info_primal"] + res64[0]["info_dual"]],
+                        bound_error_vs_oracle=bound_error(res64[0], golden("C2")),
+                        max_rel_bound_diff_vs_mixed=max(
+                            max(float(np.abs(a[k] - b[k]).max() / np.linalg.norm(b[k], 2)) for k in ("A_up", "A_low"))
+                            for a, b in zip(results[-1], res64)))
+        del batch64, probs64
+
     # plain CG for comparison: the same cells one at a time (one problem handle, no batching)
     nplain = 0 if args.no_plain else min(B, 4)
     if nplain:
@@ -451,14 +555,24 @@ def main():
                   timed_region="second timed pass of the same steps, kernels launched directly by "
                                "hipExtLaunchKernelGGL with start/stop HIP events on the library stream",
                   value_events_pass=round(B * args.steps / dt_events, 3), unit_launches=unit_launches)
+    # the minimum bytes of the operator (coefficient once, FP64 potentials in and out per load) over the
+    # whole CG iteration: how far the pass structure is from the algorithmic roofline of the matvec
+    sv = survey_matvec_bytes(probs[0], 2)
+    units_per_it = unit_launches / max(launches["first"], 1)
+    it_gbs = units_per_it * sv / (it_ms * 1e-3) / 1e9
+    common["matvec"]["algorithmic"] = dict(
+        bytes_per_cell=int(sv), bytes_per_load_matvec=int(survey_matvec_bytes(probs[0], 1)),
+        cells_per_iteration=round(units_per_it, 2), gbs=round(it_gbs, 1), frac=round(it_gbs / HBM_PEAK_GBS, 4),
+        model="survey_matvec_bytes() in bench.py: coefficient read once per cell and iteration, FP64 potential "
+              "coefficients of Z_N read and written per load; divided by the time of the whole CG iteration")
     if dom == "apply":
         # the column pass issues vector ALU work for most of its duration (its FP32
-        # transforms): it is measured against the FP32 vector peak without packed
-        # instructions (the build emits none), with its HBM view beside it
+        # transforms): it is measured against the FP32 vector peak of the chip, with the
+        # rate without packed FP32 instructions (which this build never emits) and its HBM view beside it
         tf = aflops / (ms * 1e-3) / 1e12
         roofline = dict(bound="alu", achieved=round(tf, 2), peak=round(VALU_PEAK_TFLOPS, 1), unit="TFLOP/s",
-                        frac=round(tf / VALU_PEAK_TFLOPS, 4), peak_published_packed=157.3,
-                        frac_of_published=round(tf / 157.3, 4), flops_per_launch=int(aflops),
+                        frac=round(tf / VALU_PEAK_TFLOPS, 4), peak_unpacked=round(VALU_UNPACKED_TFLOPS, 1),
+                        frac_of_unpacked=round(tf / VALU_UNPACKED_TFLOPS, 4), flops_per_launch=int(aflops),
                         flops_model="apply_flops() in bench.py", hbm=hbm, **common)
     else:
         roofline = dict(bound="hbm", achieved=hbm["achieved"], peak=HBM_PEAK_GBS, unit="GB/s", frac=hbm["frac"],
@@ -476,10 +590,14 @@ def main():
                             batched="all cells of a step in lockstep (one launch per pass covers every cell)",
                             plain_bound_pairs_per_s=None if plain_value is None else round(plain_value, 3),
                             stop=args.stop, etol=args.etol if args.stop != "residual" else None,
-                            energy_rule=energy_leg, tile_tuning=tuning),
+                            energy_rule=energy_leg, tile_tuning=tuning,
+                            bound_error_vs_oracle=dict(cell=0, reference="oracle, CG to 1e-11 "
+                                                                         "(tests/golden/reference_bounds.json C2)",
+                                                       **(err_mixed or {})),
+                            fp64=fp64_leg),
                 roofline=roofline)
     if not args.no_cpu:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_cells, args.tol)
+        line["cpu_baseline"] = cpu_baseline(args.cpu_cells, args.tol, results[-1])
     print(json.dumps(line), flush=True)
 
 
@@ -525,7 +643,66 @@ def run_c4(args):
                  "contrast log-uniform in [2,1e3], d loads, primal+dual; one lockstep batch per size class, "
                  "classes concurrent on their own streams",
                  dict(cells_per_step=len(specs), classes=classes))
+    # bound error of the sampled cells (the highest-contrast cell of every class) against the oracle
+    sample_err = {}
+    for name in ("C4s_2d_N13", "C4s_2d_N41", "C4s_2d_N63", "C4s_2d_N313", "C4s_3d_N41"):
+        idx = golden_index(name)
+        if idx is not None:
+            sample_err[name] = dict(cell=idx, **bound_error(res[idx], golden(name)))
+    line["config"]["bound_error_vs_oracle"] = sample_err
+    line["roofline"] = mixed_roofline(args, ms, groups, len(specs))
     print(json.dumps(line), flush=True)
+
+
+def golden_index(name):
+    try:
+        with open(GOLDEN) as f:
+            return int(json.load(f)[name]["batch_index"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def mixed_roofline(args, ms, groups, n_total):
+    """Roofline of the dominant kernel of a mixed batch: every class solved once more,
+    class after class with each kernel between HIP events; the (class, pass) with the
+    largest total time is the dominant kernel; its algorithmic bytes (and FP32 flops
+    for a column pass) per launch over its average duration."""
+    res, timing = ms.solve_timed(groups, n_total, tol=args.tol)
+    best, rows = None, []
+    for key, items in groups.items():
+        avg, cnt = timing[key]
+        pb = ms.classes[key]["probs"][0]
+        d = key[0]
+        # a cell takes part in the launches of a solve until all its loads stopped
+        units = sum(max(i["iters"] for i in res[j][k]) + 1 for j, _, _ in items for k in ("info_primal", "info_dual"))
+        pbytes = pass_bytes(pb, d)
+        for p, c in cnt.items():
+            if not c:
+                continue
+            tot = avg[p] * c
+            b = units * pbytes[p] / c
+            row = dict(cls=f"{d}D N={key[1][0]}", kernel_pass=p, ms_per_launch=round(avg[p], 5), launches=c,
+                       total_ms=round(tot, 2), bytes_per_launch=int(b), gbs=round(b / (avg[p] * 1e-3) / 1e9, 1))
+            if p == "apply" and args.precision == "mixed" and 2 * key[1][0] - 1 in SPLIT:
+                fl = units * apply_flops(pb, d) / c
+                row.update(flops_per_launch=int(fl), tflops=round(fl / (avg[p] * 1e-3) / 1e12, 2))
+            rows.append(row)
+            if best is None or tot > best["total_ms"]:
+                best = row
+    rows.sort(key=lambda r: -r["total_ms"])
+    hbm = dict(achieved=best["gbs"], peak=HBM_PEAK_GBS, unit="GB/s", frac=round(best["gbs"] / HBM_PEAK_GBS, 4),
+               bytes_per_launch=best["bytes_per_launch"])
+    common = dict(kernel=f"{best['kernel_pass']} pass of the {best['cls']} class", ms_per_launch=best["ms_per_launch"],
+                  traffic=None, per_kernel=rows[:8], bytes_model="pass_bytes() in bench.py",
+                  timed_region="classes solved once more one after another, each kernel launched directly "
+                               "between HIP events on its class stream")
+    if "tflops" in best:
+        tf = best["tflops"]
+        return dict(bound="alu", achieved=tf, peak=round(VALU_PEAK_TFLOPS, 1), unit="TFLOP/s",
+                    frac=round(tf / VALU_PEAK_TFLOPS, 4), peak_unpacked=round(VALU_UNPACKED_TFLOPS, 1),
+                    frac_of_unpacked=round(tf / VALU_UNPACKED_TFLOPS, 4), hbm=hbm, **common)
+    return dict(bound="hbm", achieved=hbm["achieved"], peak=HBM_PEAK_GBS, unit="GB/s", frac=hbm["frac"],
+                bytes_per_launch=hbm["bytes_per_launch"], **common)
 
 
 def run_c5(args):

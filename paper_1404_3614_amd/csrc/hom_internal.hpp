@@ -118,14 +118,14 @@ enum LastMode { LAST_CG = 0, LAST_RESID = 1, LAST_MATVEC = 2, LAST_PROF = 3 };
 enum ApplyMode { APPLY_COEF = 0, APPLY_QUAD = 1, APPLY_COEF_CG = 2, APPLY_GRID = 3, APPLY_FWD = 4 };
 constexpr int MID_CG = 2;  // flag or-ed into the inverse argument of launch_mid
 
-// Host-side switch: when `on`, the next pipeline kernel launch is issued with
+// Host-side switch of the calling thread: when `on`, its next pipeline kernel launch is issued with
 // hipExtLaunchKernelGGL and these start/stop events (kernel-execution
 // timestamps), used by the timing mode of batched solves.
 struct ExtTiming {
   bool on = false;
   hipEvent_t start = nullptr, stop = nullptr;
 };
-extern ExtTiming g_ext_timing;
+extern thread_local ExtTiming g_ext_timing;
 
 // Launch wrappers (hom_kernels.hip).  All return hipError_t of the launch.
 template <typename R>

@@ -26,7 +26,7 @@
 
 namespace hom {
 
-ExtTiming g_ext_timing;
+thread_local ExtTiming g_ext_timing;
 
 // ------------------------------------------------------------------ FFT
 template <typename R>

@@ -83,3 +83,25 @@ class MixedSolver:
                 r["class"] = dict(d=key[0], N=key[1])
                 out[i] = r
         return out
+
+    def solve_timed(self, groups, n_total, tol=1e-6, maxit=20000):
+        """As solve, but class after class on this thread with every kernel launched
+        directly between HIP events (Batch.set_timing), so that the durations are
+        those of each kernel alone.  Returns (results, {key: (ms per launch, launches)})."""
+        out = [None] * n_total
+        timing = {}
+        for key, items in groups.items():
+            cls = self._class(key, len(items), [(Ah, Bh) for _, Ah, Bh in items])
+            b = cls["batch"]
+            torch.cuda.synchronize()
+            b.set_timing(True)
+            with torch.cuda.stream(cls["stream"]):
+                res = b.solve_bounds(tol=tol, maxit=maxit)
+            cls["stream"].synchronize()
+            timing[key] = b.get_timing()
+            b.set_timing(False)
+            for (i, _, _), r in zip(items, res):
+                r["class"] = dict(d=key[0], N=key[1])
+                out[i] = r
+        return out, timing
+
