@@ -37,6 +37,21 @@ so the smallest eigenvalue of A_M over the grid points bounds it as well; the
 truncated series oscillates near interfaces, which can make that second
 bound vacuous (negative) at high contrast.
 
+* gap (primal and dual together): for a load E, the primal energy U of the
+  iterate is an upper bound on E . A_H E and |E|^4 / V, with V the dual
+  energy of the dual iterate for J = E, a lower bound (V >= E . A_H^{-1} E and
+  (E . E)^2 <= (E . A_H E)(E . A_H^{-1} E)); their difference is the
+  guaranteed gap of eq. approx_homog_with_error on this entry.  Following the
+  Convergence-criteria remark (Sec. 7.2: the algebraic error should stay below
+  the discretisation error), each side stops once the Gauss-Radau bound of
+  its own remaining improvement is below theta times the current gap: the
+  primal when gamma phi <= theta (U - |E|^4 / V), the dual when the
+  improvement of its lower bound, at most |E|^4 R / (V (V - R)) for the
+  remaining dual decrease R, is.  The two solves advance in lockstep chunks of
+  m iterations and read each other's energy as it was at the end of the
+  previous chunk (the start energy during the first), so the rule is
+  deterministic when the two run concurrently.
+
 Pinned by tests/test_oracle_stopping.py: the energy recurrence against the
 double-grid quadrature of the bounds, mu against the eigenvalues of the
 dense Galerkin matrix, the Gauss-Radau bound against the exact remaining
@@ -158,3 +173,99 @@ def energy_of(prob, x, E, dual=False):
     b = -C(constant_field(np.asarray(E, float), prob.N))
     r = b - C(x)
     return zero_field_energy(prob, E, dual) - float(np.real(inner(x, b + r)))
+
+
+class _CGRun:
+    """One Hestenes-Stiefel CG from x0 = 0 advanced an iteration at a time, with
+    the energy and the Gauss-Radau factor of every iterate (as cg_energy)."""
+
+    def __init__(self, apply_C, b, e0, normE, mu):
+        self.C, self.x, self.r = apply_C, np.zeros_like(b), b.copy()
+        self.p = self.r.copy()
+        self.gam = inner(self.r, self.r)
+        self.mu, self.normE = mu, normE
+        self.phi = 1.0 / mu if mu > 0 else np.inf
+        self.alpha_prev = self.gam_prev = None
+        self.energy = [e0]            # energy of iterate i
+        self.radau = []               # Gauss-Radau bound of iterate i (filled by the test of iterate i)
+        self.i = 0
+        self.done = False
+        self.status = "maxit"
+
+    def radau_bound(self):
+        if self.i > 0 and self.mu > 0:
+            t = self.phi - self.alpha_prev
+            ph = t / (self.mu * t + self.gam / self.gam_prev)
+            self.phi = ph if (t > 0 and 0 < ph < 1.0 / self.mu) else 1.0 / self.mu
+        self.radau.append(self.gam * self.phi)
+        return self.radau[-1]
+
+    def step(self):
+        q = self.C(self.p)
+        pq = inner(self.p, q)
+        if pq <= 0.0:
+            raise FloatingPointError("operator not positive definite on the subspace")
+        alpha = self.gam / pq
+        self.x = self.x + alpha * self.p
+        self.r = self.r - alpha * q
+        gam_new = inner(self.r, self.r)
+        self.energy.append(self.energy[-1] - alpha * self.gam)
+        self.p = self.r + (gam_new / self.gam) * self.p
+        self.alpha_prev, self.gam_prev, self.gam = alpha, self.gam, gam_new
+        self.i += 1
+
+
+def cg_pair_gap(primal, dual, normE, tol=1e-8, theta=0.01, chunk=8, maxit=20000):
+    """The gap rule (module docstring) for one load E: primal = (apply_C, b, e0, mu)
+    of the primal problem, dual = the same for the dual problem with J = E.
+    Both CGs run iteration by iteration in lockstep; at iteration i (chunk
+    c = i // chunk) a side reads the other's energy at iterate
+    min(c chunk - 1, its stop) for c >= 1 and its start energy for c = 0.
+    Returns (primal EnergyCG-like run, dual run, gaps seen at the two stops)."""
+    runs = [_CGRun(*primal[:3], normE, primal[3]), _CGRun(*dual[:3], normE, dual[3])]
+    n4 = normE ** 4
+    gaps = [None, None]
+
+    def partner_energy(k, i):
+        o = runs[1 - k]
+        c = i // chunk
+        j = 0 if c == 0 else c * chunk - 1
+        return o.energy[min(j, len(o.energy) - 1)]
+
+    i = 0
+    while not (runs[0].done and runs[1].done):
+        for k, rk in enumerate(runs):
+            if rk.done:
+                continue
+            R = rk.radau_bound()
+            own, other = rk.energy[-1], partner_energy(k, i)
+            if k == 0:
+                gap = own - n4 / other
+                by_gap = R <= theta * gap
+            else:
+                gap = other - n4 / own
+                by_gap = (own - R) > 0 and n4 * R / (own * (own - R)) <= theta * gap
+            if np.sqrt(rk.gam) <= tol * normE:
+                rk.done, rk.status, gaps[k] = True, "residual", gap
+            elif by_gap:
+                rk.done, rk.status, gaps[k] = True, "gap", gap
+            elif i >= maxit:
+                rk.done, gaps[k] = True, gap
+        for rk in runs:
+            if not rk.done:
+                rk.step()
+        i += 1
+    return runs[0], runs[1], gaps
+
+
+def solve_pair_gap(prob, E, tol=1e-8, theta=0.01, chunk=8, mu=None, maxit=20000):
+    """cg_pair_gap on the primal and dual Galerkin problems of a load E; mu: a
+    pair (primal, dual) of spectrum lower bounds (default from the coefficients)."""
+    E = np.asarray(E, float)
+    sides = []
+    for k, dual in enumerate((False, True)):
+        C, coef = operator(prob, dual)
+        m = spectrum_lower_bound(coef) if mu is None else mu[k]
+        sides.append((C, -C(constant_field(E, prob.N)), zero_field_energy(prob, E, dual), m))
+    return cg_pair_gap(sides[0], sides[1], float(np.linalg.norm(E)), tol, theta, chunk, maxit)
+

@@ -12,6 +12,12 @@ S3 Gauss-Radau bound >= exact remaining energy (from the dense direct solve)
 S4 the guaranteed rule stops at the first iterate whose bound meets etol, with
    the energy within etol of the converged one; the heuristic rule ends near
    the converged energy on a smooth case.
+S5 the gap rule (primal and dual in lockstep): against the exact minimum
+   energies of the dense direct solves, each side's final bound is within
+   theta times the gap it stopped on, the enclosure |E|^4 / V <= E . A_H E <= U
+   holds at every pair of iterates, and the partner energies it read are those
+   of the previous chunk's last iterate (brute force over the recorded
+   histories).
 """
 import numpy as np
 import pytest
@@ -151,3 +157,59 @@ def test_S4_guaranteed_rule_accuracy_and_savings(dual):
     res = stp.solve(prob, E, dual=dual, tol=1e-30, rule="heuristic", etol=1e-8)
     assert res.status == "energy"
     assert res.energy[-1] - ref.energy[-1] <= 1e-7 * ref.energy[-1]
+
+
+def _pair_case(rho=50.0, N=(9, 9)):
+    cell = homgen.square_inclusion_cell(rho_in=rho)
+    prob = ga.make_problem(cell, N)
+    a_min, a_max = phase_eig_range(cell)
+    return prob, (a_min, 1.0 / a_max)
+
+
+@pytest.mark.parametrize("E", [np.array([1.0, 0.0]), np.array([0.6, -0.8]), np.array([2.0, 1.0])],
+                         ids=["e1", "unit_oblique", "norm_sqrt5"])
+@pytest.mark.parametrize("theta", [0.1, 1e-3])
+def test_S5_gap_rule_final_bounds_within_theta_of_the_gap(E, theta):
+    prob, mu = _pair_case()
+    U_star = _exact_remaining(prob, E, False)       # min primal energy: E . Abar E of the minimiser
+    V_star = _exact_remaining(prob, E, True)        # min dual energy for J = E
+    n4 = float(E @ E) ** 2
+    P, D, gaps = stp.solve_pair_gap(prob, E, tol=1e-30, theta=theta, chunk=8, mu=mu)
+    assert P.status == "gap" and D.status == "gap"
+    U, V = P.energy[-1], D.energy[-1]
+    # guaranteed enclosure of E . A_H E by the iterates, and exactness of the limits
+    assert n4 / V <= n4 / V_star * (1 + 1e-12) and U_star <= U * (1 + 1e-12)
+    assert n4 / V_star <= U_star * (1 + 1e-12)
+    # each side's remaining error is below theta times the gap it stopped on
+    assert gaps[0] > 0 and gaps[1] > 0
+    assert U - U_star <= theta * gaps[0] * (1 + 1e-9)
+    assert n4 / V_star - n4 / V <= theta * gaps[1] * (1 + 1e-9)
+    # the looser theta stops earlier, and no later than the residual rule at 1e-10
+    ref_p = stp.solve(prob, E, dual=False, tol=1e-10, rule=None)
+    assert P.i <= ref_p.iters
+
+
+def test_S5_gap_rule_reads_the_previous_chunk():
+    """Brute force: replay the recorded histories and check that every stop
+    decision used the partner energy of iterate c m - 1 (c = i // m >= 1), or
+    the start energy during the first chunk, and that no earlier iterate met it."""
+    prob, mu = _pair_case(rho=200.0, N=(11, 11))
+    E = np.array([1.0, 0.0])
+    theta, m = 1e-2, 5
+    P, D, gaps = stp.solve_pair_gap(prob, E, tol=1e-30, theta=theta, chunk=m, mu=mu)
+    runs = (P, D)
+    for k, rk in enumerate(runs):
+        other = runs[1 - k]
+        for i in range(rk.i + 1):
+            c = i // m
+            j = 0 if c == 0 else min(c * m - 1, other.i)
+            own, oth, R = rk.energy[i], other.energy[j], rk.radau[i]
+            if k == 0:
+                gap = own - 1.0 / oth
+                hit = R <= theta * gap
+            else:
+                gap = oth - 1.0 / own
+                hit = own - R > 0 and R / (own * (own - R)) <= theta * gap
+            assert hit == (i == rk.i), (k, i)
+        assert abs(gaps[k] - gap) <= 1e-15 * abs(gap)
+
