@@ -38,19 +38,23 @@ truncated series oscillates near interfaces, which can make that second
 bound vacuous (negative) at high contrast.
 
 * gap (primal and dual together): for a load E, the primal energy U of the
-  iterate is an upper bound on E . A_H E and |E|^4 / V, with V the dual
+  iterate is an upper bound on E . A_H E and L = |E|^4 / V, with V the dual
   energy of the dual iterate for J = E, a lower bound (V >= E . A_H^{-1} E and
-  (E . E)^2 <= (E . A_H E)(E . A_H^{-1} E)); their difference is the
-  guaranteed gap of eq. approx_homog_with_error on this entry.  Following the
-  Convergence-criteria remark (Sec. 7.2: the algebraic error should stay below
-  the discretisation error), each side stops once the Gauss-Radau bound of
-  its own remaining improvement is below theta times the current gap: the
-  primal when gamma phi <= theta (U - |E|^4 / V), the dual when the
-  improvement of its lower bound, at most |E|^4 R / (V (V - R)) for the
-  remaining dual decrease R, is.  The two solves advance in lockstep chunks of
-  m iterations and read each other's energy as it was at the end of the
-  previous chunk (the start energy during the first), so the rule is
-  deterministic when the two run concurrently.
+  (E . E)^2 <= (E . A_H E)(E . A_H^{-1} E)); the converged difference
+  D* = U* - L* is the discretisation gap of eq. approx_homog_with_error on
+  this entry.  Following the Convergence-criteria remark (Sec. 7.2: the
+  algebraic error should stay below the discretisation error), each side
+  stops once the Gauss-Radau bound of its own remaining error is below theta
+  times a guaranteed lower bound on D*: with R the primal bound (U - U* <= R)
+  and R' = |E|^4 R_V / (V (V - R_V)) the bound on L* - L from the dual one
+  (R' infinite unless V > R_V), D* >= (U - R) - (L + R'), and a side stops
+  when its own R (R') is at most theta times that.  Both R and R' are valid
+  at every iterate, so the partner's values may be old: the two solves
+  advance in lockstep chunks of m iterations and each reads the other's
+  (energy, bound) pair at the last iterate of the previous chunk (during the
+  first chunk: its start energy with an infinite bound, so nothing stops
+  there).  The rule is deterministic when the two run concurrently, and at
+  the stop U - U* <= theta D* and L* - L <= theta D*.
 
 Pinned by tests/test_oracle_stopping.py: the energy recurrence against the
 double-grid quadrature of the bounds, mu against the eigenvalues of the
@@ -219,18 +223,28 @@ def cg_pair_gap(primal, dual, normE, tol=1e-8, theta=0.01, chunk=8, maxit=20000)
     """The gap rule (module docstring) for one load E: primal = (apply_C, b, e0, mu)
     of the primal problem, dual = the same for the dual problem with J = E.
     Both CGs run iteration by iteration in lockstep; at iteration i (chunk
-    c = i // chunk) a side reads the other's energy at iterate
-    min(c chunk - 1, its stop) for c >= 1 and its start energy for c = 0.
-    Returns (primal EnergyCG-like run, dual run, gaps seen at the two stops)."""
+    c = i // chunk) a side reads the other's energy and Gauss-Radau bound at
+    iterate min(c chunk - 1, its stop) for c >= 1 (its start energy and an
+    infinite bound for c = 0).  Returns (primal run, dual run, the lower bounds
+    on D* that the two stops used)."""
     runs = [_CGRun(*primal[:3], normE, primal[3]), _CGRun(*dual[:3], normE, dual[3])]
     n4 = normE ** 4
-    gaps = [None, None]
+    dlow = [None, None]
 
-    def partner_energy(k, i):
+    def upper_and_bound(i_energy, i_radau):
+        return i_energy, i_radau                       # U and R of a primal iterate
+
+    def lower_and_bound(V, RV):
+        # L = |E|^4 / V and the bound R' on L* - L from the dual remainder RV
+        return n4 / V, (n4 * RV / (V * (V - RV)) if V - RV > 0 else np.inf)
+
+    def partner_state(k, i):
         o = runs[1 - k]
         c = i // chunk
-        j = 0 if c == 0 else c * chunk - 1
-        return o.energy[min(j, len(o.energy) - 1)]
+        if c == 0:
+            return o.energy[0], np.inf
+        j = min(c * chunk - 1, o.i)
+        return o.energy[j], o.radau[j]
 
     i = 0
     while not (runs[0].done and runs[1].done):
@@ -238,24 +252,27 @@ def cg_pair_gap(primal, dual, normE, tol=1e-8, theta=0.01, chunk=8, maxit=20000)
             if rk.done:
                 continue
             R = rk.radau_bound()
-            own, other = rk.energy[-1], partner_energy(k, i)
+            oe, orad = partner_state(k, i)
             if k == 0:
-                gap = own - n4 / other
-                by_gap = R <= theta * gap
+                U, RU = rk.energy[-1], R
+                L, RL = lower_and_bound(oe, orad)
+                own = RU
             else:
-                gap = other - n4 / own
-                by_gap = (own - R) > 0 and n4 * R / (own * (own - R)) <= theta * gap
+                U, RU = oe, orad
+                L, RL = lower_and_bound(rk.energy[-1], R)
+                own = RL
+            d_low = (U - RU) - (L + RL)               # guaranteed: D* >= d_low
             if np.sqrt(rk.gam) <= tol * normE:
-                rk.done, rk.status, gaps[k] = True, "residual", gap
-            elif by_gap:
-                rk.done, rk.status, gaps[k] = True, "gap", gap
+                rk.done, rk.status, dlow[k] = True, "residual", d_low
+            elif d_low > 0 and own <= theta * d_low:
+                rk.done, rk.status, dlow[k] = True, "gap", d_low
             elif i >= maxit:
-                rk.done, gaps[k] = True, gap
+                rk.done, dlow[k] = True, d_low
         for rk in runs:
             if not rk.done:
                 rk.step()
         i += 1
-    return runs[0], runs[1], gaps
+    return runs[0], runs[1], dlow
 
 
 def solve_pair_gap(prob, E, tol=1e-8, theta=0.01, chunk=8, mu=None, maxit=20000):

@@ -14,10 +14,10 @@ S4 the guaranteed rule stops at the first iterate whose bound meets etol, with
    the converged energy on a smooth case.
 S5 the gap rule (primal and dual in lockstep): against the exact minimum
    energies of the dense direct solves, each side's final bound is within
-   theta times the gap it stopped on, the enclosure |E|^4 / V <= E . A_H E <= U
-   holds at every pair of iterates, and the partner energies it read are those
-   of the previous chunk's last iterate (brute force over the recorded
-   histories).
+   theta times the converged discretisation gap D*, the lower bound on D* it
+   stopped on is one, the enclosure |E|^4 / V <= E . A_H E <= U holds, and
+   the partner values it read are those of the previous chunk's last iterate
+   (brute force over the recorded histories).
 """
 import numpy as np
 import pytest
@@ -174,42 +174,53 @@ def test_S5_gap_rule_final_bounds_within_theta_of_the_gap(E, theta):
     U_star = _exact_remaining(prob, E, False)       # min primal energy: E . Abar E of the minimiser
     V_star = _exact_remaining(prob, E, True)        # min dual energy for J = E
     n4 = float(E @ E) ** 2
-    P, D, gaps = stp.solve_pair_gap(prob, E, tol=1e-30, theta=theta, chunk=8, mu=mu)
+    D_star = U_star - n4 / V_star
+    P, D, dlow = stp.solve_pair_gap(prob, E, tol=1e-30, theta=theta, chunk=8, mu=mu)
     assert P.status == "gap" and D.status == "gap"
     U, V = P.energy[-1], D.energy[-1]
-    # guaranteed enclosure of E . A_H E by the iterates, and exactness of the limits
+    # guaranteed enclosure of E . A_H E by the iterates and by the limits
     assert n4 / V <= n4 / V_star * (1 + 1e-12) and U_star <= U * (1 + 1e-12)
-    assert n4 / V_star <= U_star * (1 + 1e-12)
-    # each side's remaining error is below theta times the gap it stopped on
-    assert gaps[0] > 0 and gaps[1] > 0
-    assert U - U_star <= theta * gaps[0] * (1 + 1e-9)
-    assert n4 / V_star - n4 / V <= theta * gaps[1] * (1 + 1e-9)
-    # the looser theta stops earlier, and no later than the residual rule at 1e-10
+    assert 0 < D_star
+    # the stops used true lower bounds on D*, and each side's error is within theta D*
+    assert 0 < dlow[0] <= D_star * (1 + 1e-9) and 0 < dlow[1] <= D_star * (1 + 1e-9)
+    assert U - U_star <= theta * D_star * (1 + 1e-9)
+    assert n4 / V_star - n4 / V <= theta * D_star * (1 + 1e-9)
+    # no later than the residual rule at 1e-10
     ref_p = stp.solve(prob, E, dual=False, tol=1e-10, rule=None)
-    assert P.i <= ref_p.iters
+    ref_d = stp.solve(prob, E, dual=True, tol=1e-10, rule=None)
+    assert P.i <= ref_p.iters and D.i <= ref_d.iters
 
 
 def test_S5_gap_rule_reads_the_previous_chunk():
     """Brute force: replay the recorded histories and check that every stop
-    decision used the partner energy of iterate c m - 1 (c = i // m >= 1), or
-    the start energy during the first chunk, and that no earlier iterate met it."""
+    decision used the partner state of iterate c m - 1 (c = i // m >= 1; during
+    the first chunk nothing stops), and that no earlier iterate met the rule."""
     prob, mu = _pair_case(rho=200.0, N=(11, 11))
     E = np.array([1.0, 0.0])
     theta, m = 1e-2, 5
-    P, D, gaps = stp.solve_pair_gap(prob, E, tol=1e-30, theta=theta, chunk=m, mu=mu)
+    P, D, dlow = stp.solve_pair_gap(prob, E, tol=1e-30, theta=theta, chunk=m, mu=mu)
     runs = (P, D)
+
+    def low(V, RV):
+        return 1.0 / V, (RV / (V * (V - RV)) if V > RV else np.inf)
+
     for k, rk in enumerate(runs):
         other = runs[1 - k]
         for i in range(rk.i + 1):
             c = i // m
-            j = 0 if c == 0 else min(c * m - 1, other.i)
-            own, oth, R = rk.energy[i], other.energy[j], rk.radau[i]
+            if c == 0:
+                assert i != rk.i
+                continue
+            j = min(c * m - 1, other.i)
             if k == 0:
-                gap = own - 1.0 / oth
-                hit = R <= theta * gap
+                U, RU = rk.energy[i], rk.radau[i]
+                L, RL = low(other.energy[j], other.radau[j])
+                own = RU
             else:
-                gap = oth - 1.0 / own
-                hit = own - R > 0 and R / (own * (own - R)) <= theta * gap
+                U, RU = other.energy[j], other.radau[j]
+                L, RL = low(rk.energy[i], rk.radau[i])
+                own = RL
+            dl = (U - RU) - (L + RL)
+            hit = dl > 0 and own <= theta * dl
             assert hit == (i == rk.i), (k, i)
-        assert abs(gaps[k] - gap) <= 1e-15 * abs(gap)
-
+        assert abs(dlow[k] - dl) <= 1e-15 * abs(dl)
