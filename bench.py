@@ -54,10 +54,12 @@ def parse():
     ap.add_argument("--no-plain", action="store_true", help="skip the one-cell-at-a-time comparison leg")
     ap.add_argument("--no-energy", action="store_true", help="skip the guaranteed-energy-rule leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 leg of the same cells")
+    ap.add_argument("--theta", type=float, default=1e-2,
+                    help="gap rule: each bound's algebraic error below theta times the discretisation gap")
     ap.add_argument("--tiles", default=None,
                     help="pin the FP32 tile shape: row_pairs,row_threads,apply_points,apply_half_exchange,"
                          "apply_all_packs")
-    ap.add_argument("--stop", default="residual", choices=["residual", "energy", "guaranteed"],
+    ap.add_argument("--stop", default="residual", choices=["residual", "energy", "guaranteed", "gap"],
                     help="stopping rule: the residual rule at --tol, or that rule or an energy rule at --etol "
                          "(energy: extrapolated tail; guaranteed: Gauss-Radau bound)")
     ap.add_argument("--etol", type=float, default=1e-7,
@@ -446,7 +448,7 @@ def main():
 
     # the guaranteed energy rule on the same steps (when the residual rule set the value):
     # bounds within a relative etol of their converged values, in fewer iterations
-    energy_leg = None
+    energy_leg = gap_leg = None
     if args.stop == "residual" and not args.no_energy:
         batch.set_stop("guaranteed", args.etol, a_min, a_max)
         for _ in range(args.warmup):
@@ -460,6 +462,26 @@ def main():
         batch.set_stop("residual")
         diff = max(max(float(np.abs(a[k] - b[k]).max() / np.linalg.norm(b[k], 2)) for k in ("A_up", "A_low"))
                    for a, b in zip(res_e, results[-1]))
+        # the gap rule: each bound within theta of the discretisation gap of its entry
+        batch.set_stop("gap", args.theta, a_min, a_max)
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            res_g = step()
+        torch.cuda.synchronize()
+        dt_g = time.perf_counter() - t0
+        batch.set_stop("residual")
+        ref_c2 = golden("C2")
+        gap_leg = dict(rule="gap", theta=args.theta, bound_pairs_per_s=round(B * args.steps / dt_g, 3),
+                       cg_iters=[i["iters"] for i in res_g[0]["info_primal"] + res_g[0]["info_dual"]],
+                       bound_error_vs_oracle=bound_error(res_g[0], ref_c2),
+                       gap_vs_oracle=None if ref_c2 is None else
+                       float(np.abs(np.diag(ref_c2["A_up"]) - np.diag(ref_c2["A_low"])).max()),
+                       definition="residual rule at tol, or each side's Gauss-Radau bound on its remaining error "
+                                  "below theta times a guaranteed lower bound on the converged gap of its "
+                                  "diagonal entry (primal and dual read each other's state chunk by chunk)")
         energy_leg = dict(rule="guaranteed", etol=args.etol, a_min=a_min, a_max=a_max,
                           bound_pairs_per_s=round(B * args.steps / dt_e, 3),
                           cg_iters=[i["iters"] for i in res_e[0]["info_primal"] + res_e[0]["info_dual"]],
@@ -590,7 +612,7 @@ def main():
                             batched="all cells of a step in lockstep (one launch per pass covers every cell)",
                             plain_bound_pairs_per_s=None if plain_value is None else round(plain_value, 3),
                             stop=args.stop, etol=args.etol if args.stop != "residual" else None,
-                            energy_rule=energy_leg, tile_tuning=tuning,
+                            energy_rule=energy_leg, gap_rule=gap_leg, tile_tuning=tuning,
                             bound_error_vs_oracle=dict(cell=0, reference="oracle, CG to 1e-11 "
                                                                          "(tests/golden/reference_bounds.json C2)",
                                                        **(err_mixed or {})),

@@ -441,7 +441,7 @@ class Problem:
         return b
 
 
-_STOP_RULES = {"residual": 0, "energy": 1, "guaranteed": 2}
+_STOP_RULES = {"residual": 0, "energy": 1, "guaranteed": 2, "gap": 3}
 
 
 def set_tuning(on=True):
@@ -526,9 +526,11 @@ class Batch:
 
     def set_stop(self, rule="residual", etol=None, a_min=0.0, a_max=0.0):
         """Stopping rule of later solves (hom_batch_set_stop): "residual" (||r|| <= tol ||E||),
-        "energy" (or an extrapolated energy tail below etol) or "guaranteed" (or the
-        Gauss-Radau bound on the remaining energy below etol; a_min / a_max optionally
-        bound the coefficient's eigenvalues)."""
+        "energy" (or an extrapolated energy tail below etol), "guaranteed" (or the
+        Gauss-Radau bound on the remaining energy below etol) or "gap" (solve_pair /
+        solve_bounds only: or each side's remaining error below etol times a
+        guaranteed lower bound on the converged gap of its bound); a_min / a_max
+        optionally bound the coefficient's eigenvalues."""
         L.check(L.load().hom_batch_set_stop(self.h, _STOP_RULES[rule], float(etol or 0.0), float(a_min), float(a_max)),
                 "hom_batch_set_stop")
 

@@ -661,21 +661,21 @@ hom_status start_run(SolveRun& R, int nload, double tol, int maxit, bool have_x0
   // smallest eigenvalue of the coefficient over the doubled grid, per unit
   int mu_parts = 0;
   double mu_user = 0.0;
-  if (R.stop.rule == 2) {
+  R.chunk = std::max(1, R.chunk);
+  if (R.stop.rule == 2 || R.stop.rule == 3) {
     const size_t npts = (size_t)g.M[0] * g.M[1] * g.M[2];
     mu_parts = (int)std::min<size_t>(64, (npts + kBlock - 1) / kBlock);
     HIPCHK(launch_coef_min_eig(R.fp32, g, R.units, R.n, mu_parts, st));
     mu_user = g.dual ? (R.stop.a_max > 0.0 ? 1.0 / R.stop.a_max : 0.0) : R.stop.a_min;
   }
-  HIPCHK(launch_init_scal(g, R.units, R.n, R.iter_base, tol, maxit, R.stop.rule, R.stop.etol, mu_parts, mu_user,
-                          st));
+  HIPCHK(launch_init_scal(g, R.units, R.n, R.iter_base, R.chunk, tol, maxit, R.stop.rule, R.stop.etol, mu_parts,
+                          mu_user, st));
   HIPCHK(launch_rhs(g, R.units, R.n, st));
   HIPCHK(launch_start_vectors(g, R.units, R.n, have_x0 ? 1 : 0, st));
   if (have_x0) {
     HIPCHK(enqueue_passes(R.fp32, g, R.units, FIRST_FIELD, LAST_RESID, 0, nullptr, st, R.n));
     HIPCHK(launch_start_energy(g, R.units, R.n, st));
   }
-  R.chunk = std::max(1, R.chunk);
   // events recorded inside a captured graph cannot be timed, so timing runs launch directly
   R.use_graph = st != nullptr && env_int("HOM_NO_GRAPH", 0) == 0 && R.events == nullptr;
   const int npass = pass_types(g.d, R.types);
@@ -701,21 +701,33 @@ hom_status start_run(SolveRun& R, int nload, double tol, int maxit, bool have_x0
 // stays in flight while the host reads the active count of the one before:
 // the count is monotone and every pass of a finished unit returns at once, so
 // a chunk enqueued after the last unit stopped changes nothing.
-hom_status loop_runs(SolveRun* const* runs, int nr, int maxit) {
+// partner (optional, per run: index of the partner run or -1): chunk c of a
+// run starts after chunk c - 1 of its partner has ended (the partner's last
+// chunk once it has stopped), so under the gap rule each reads the other's
+// state at the end of the previous chunk, never a chunk being written.
+hom_status loop_runs(SolveRun* const* runs, int nr, int maxit, const int* partner = nullptr) {
   std::vector<hipEvent_t> ev((size_t)2 * nr, nullptr);
-  std::vector<int> it(nr, 0), done(nr, 0), fin(nr, 0);
+  std::vector<int> it(nr, 0), done(nr, 0), fin(nr, 0), launched(nr, 0);
   hipError_t e = hipSuccess;
   for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
-  for (int r = 0; r < nr && e == hipSuccess; ++r) {
-    e = hipGraphLaunch(*runs[r]->graph, runs[r]->st);
-    if (e == hipSuccess) e = hipEventRecord(ev[2 * r], runs[r]->st);
-  }
+  auto launch = [&](int r) {
+    const int c = launched[r];
+    const int p = partner ? partner[r] : -1;
+    if (p >= 0 && c > 0) {
+      // the partner's chunk c - 1, or its last one: slot parity of that chunk
+      const int pc = std::min(c - 1, launched[p] - 1);
+      if (pc >= 0) e = hipStreamWaitEvent(runs[r]->st, ev[2 * p + (pc & 1)], 0);
+    }
+    if (e == hipSuccess) e = hipGraphLaunch(*runs[r]->graph, runs[r]->st);
+    if (e == hipSuccess) e = hipEventRecord(ev[2 * r + (c & 1)], runs[r]->st);
+    ++launched[r];
+  };
+  for (int r = 0; r < nr && e == hipSuccess; ++r) launch(r);
   int left = nr;
   while (e == hipSuccess && left > 0) {
     for (int r = 0; r < nr && e == hipSuccess; ++r) {
       if (fin[r]) continue;
-      e = hipGraphLaunch(*runs[r]->graph, runs[r]->st);
-      if (e == hipSuccess) e = hipEventRecord(ev[2 * r + ((it[r] + 1) & 1)], runs[r]->st);
+      launch(r);
     }
     for (int r = 0; r < nr && e == hipSuccess; ++r) {
       if (fin[r]) continue;
@@ -735,28 +747,42 @@ hom_status loop_runs(SolveRun* const* runs, int nr, int maxit) {
   return e == hipSuccess ? HOM_OK : HOM_E_DEVICE;
 }
 
-// Stage 2 of direct runs (no graph, optionally with per-kernel events).
-hom_status loop_direct(SolveRun& R, int maxit) {
-  hipStream_t st = R.st;
+// Per-kernel event times of the chunk just completed, into the run's sums.
+hom_status collect_events(SolveRun& R) {
+  if (!R.events) return HOM_OK;
   const int npass = pass_types(R.g.d, R.types);
-  int done_iters = 0;
-  while (true) {
-    HIPCHK(enqueue_chunk(R));
-    HIPCHK(hipStreamSynchronize(st));
-    if (R.events) {
-      for (int j = 0; j < R.chunk; ++j) {
-        hipEvent_t* ev = R.events->data() + (size_t)j * 2 * npass;
-        for (int p = 0; p < npass; ++p) {
-          float ms = 0.f;
-          HIPCHK(hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]));
-          R.tsum[R.types[p]] += ms;
-          R.tcnt[R.types[p]] += 1;
-        }
+  for (int j = 0; j < R.chunk; ++j) {
+    hipEvent_t* ev = R.events->data() + (size_t)j * 2 * npass;
+    for (int p = 0; p < npass; ++p) {
+      float ms = 0.f;
+      HIPCHK(hipEventElapsedTime(&ms, ev[2 * p], ev[2 * p + 1]));
+      R.tsum[R.types[p]] += ms;
+      R.tcnt[R.types[p]] += 1;
+    }
+  }
+  return HOM_OK;
+}
+
+// Stage 2 of direct runs (no graph, optionally with per-kernel events): the
+// runs advance one chunk each in turn (for partners, chunk c of each after
+// chunk c - 1 of the other, as in loop_runs), each chunk waited for.
+hom_status loop_direct(SolveRun* const* runs, int nr, int maxit) {
+  std::vector<int> done(nr, 0), fin(nr, 0);
+  int left = nr;
+  while (left > 0) {
+    for (int r = 0; r < nr; ++r) {
+      if (fin[r]) continue;
+      SolveRun& R = *runs[r];
+      HIPCHK(enqueue_chunk(R));
+      HIPCHK(hipStreamSynchronize(R.st));
+      hom_status s = collect_events(R);
+      if (s != HOM_OK) return s;
+      done[r] += R.chunk;
+      if (*R.pinned_active == 0 || done[r] > maxit + R.chunk) {
+        fin[r] = 1;
+        --left;
       }
     }
-    done_iters += R.chunk;
-    if (*R.pinned_active == 0) break;
-    if (done_iters > maxit + R.chunk) break;
   }
   return HOM_OK;
 }
@@ -823,7 +849,7 @@ hom_status solve_units(SolveRun& R, int nload, double tol, int maxit, bool have_
   hom_status s = start_run(R, nload, tol, maxit, have_x0);
   if (s != HOM_OK) return s;
   SolveRun* one = &R;
-  s = R.use_graph ? loop_runs(&one, 1, maxit) : loop_direct(R, maxit);
+  s = R.use_graph ? loop_runs(&one, 1, maxit) : loop_direct(&one, 1, maxit);
   if (s != HOM_OK) return s;
   return finish_run(R, nload, maxit, info);
 }
@@ -861,7 +887,7 @@ hom_status solve_impl(hom_problem* pb, int k, int nload, const double* E, const 
                       int maxit, double* const* x_out, hom_info* info) {
   hom_status s = check_solve_args(pb, nload, E, x_out, tol, maxit);
   if (s != HOM_OK) return s;
-  if (!info) return HOM_E_INVALID;
+  if (!info || pb->stop.rule == 3) return HOM_E_INVALID;   // the gap rule needs the pair solve
   hipStream_t st = pb->stream;
   const bool gani = pb->gani.on;
   const bool fp32 = pb->desc.precision == HOM_MIXED && !gani;
@@ -2050,7 +2076,7 @@ static bool batch_has_gani(const hom_batch* b) {
 hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const double* E, const double* const* x0,
                            double tol, int32_t maxit, double* const* x_out, hom_info* info) {
   if (!b || !info || (dual != 0 && dual != 1)) return HOM_E_INVALID;
-  if (batch_has_gani(b)) return HOM_E_INVALID;
+  if (batch_has_gani(b) || b->stop.rule == 3) return HOM_E_INVALID;   // the gap rule needs the pair solve
   const int k = dual, n = b->n;
   for (int i = 0; i < n; ++i) {
     hom_status s = check_solve_args(b->pbs[i], nload, E, x_out + (size_t)i * nload, tol, maxit);
@@ -2119,15 +2145,8 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, do
     if (s == HOM_OK) s = check_solve_args(b->pbs[i], nload, E, x_dual + (size_t)i * nload, tol, maxit);
     if (s != HOM_OK) return s;
   }
-  // per-kernel timing measures kernels one at a time: then the two solves run in turn
-  if (b->timing || env_int("HOM_NO_GRAPH", 0) != 0) {
-    hom_status s1 = hom_batch_solve(b, 0, nload, E, nullptr, tol, maxit, x_primal, info_primal);
-    if (s1 < 0) return s1;
-    hom_status s2 = hom_batch_solve(b, 1, nload, E, nullptr, tol, maxit, x_dual, info_dual);
-    if (s2 < 0) return s2;
-    return s1 != HOM_OK ? s1 : s2;
-  }
   hom_problem* p0 = b->pbs[0];
+  const bool gap_rule = b->stop.rule == 3;
   const bool fp32 = p0->desc.precision == HOM_MIXED;
   if (!b->stream2) {
     if (hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess) {
@@ -2145,7 +2164,11 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, do
   SolveRun R[2];
   for (int k = 0; k < 2; ++k) {
     double* const* xo = k == 0 ? x_primal : x_dual;
-    for (int i = 0; i < n; ++i) fill_unit(b->pbs[i], k, nload, E, xo + (size_t)i * nload, &b->host_units[k][i]);
+    for (int i = 0; i < n; ++i) {
+      fill_unit(b->pbs[i], k, nload, E, xo + (size_t)i * nload, &b->host_units[k][i]);
+      // gap rule: each load reads the same load of the other solve of its cell
+      if (gap_rule) b->host_units[k][i].partner_sc = b->pbs[i]->slot[1 - k].sc;
+    }
     HIPCHK(hipMemcpyAsync(b->units[k], b->host_units[k].data(), (size_t)n * sizeof(UnitDev), hipMemcpyHostToDevice,
                           b->stream));
     R[k].st = st[k];
@@ -2165,6 +2188,12 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, do
     }
     R[k].collect_dev = b->collect_dev + (size_t)k * n * kMaxLoads;
     R[k].collect_host = b->collect_host + (size_t)k * n * kMaxLoads;
+    // per-kernel timing measures kernels one at a time (the runs then advance chunk by chunk in turn)
+    if (b->timing) {
+      R[k].events = &b->tevents[k][nload];
+      R[k].tsum = b->tsum;
+      R[k].tcnt = b->tcnt;
+    }
   }
   // the second stream starts after everything the caller's stream holds (coefficient setup, unit tables)
   if (!b->order_ev && hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming) != hipSuccess) {
@@ -2177,11 +2206,11 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, do
   for (int k = 0; k < 2 && s == HOM_OK; ++k) s = start_run(R[k], nload, tol, maxit, false);
   if (s != HOM_OK) return s;
   SolveRun* runs[2] = {&R[0], &R[1]};
-  if (R[0].use_graph && R[1].use_graph) {
-    s = loop_runs(runs, 2, maxit);
-  } else {
-    for (int k = 0; k < 2 && s == HOM_OK; ++k) s = R[k].use_graph ? loop_runs(&runs[k], 1, maxit) : loop_direct(R[k], maxit);
-  }
+  const int partners[2] = {1, 0};
+  if (R[0].use_graph && R[1].use_graph)
+    s = loop_runs(runs, 2, maxit, gap_rule ? partners : nullptr);
+  else
+    s = loop_direct(runs, 2, maxit);
   if (s != HOM_OK) return s;
   hom_status s0 = finish_run(R[0], nload, maxit, info_primal);
   hom_status s1 = finish_run(R[1], nload, maxit, info_dual);
@@ -2335,7 +2364,7 @@ static void tuning_report(const hom_problem* p0, int k, int nload, const Tuning&
 }
 
 static bool stop_args_ok(int32_t rule, double etol, double a_min, double a_max) {
-  if (rule < 0 || rule > 2) return false;
+  if (rule < 0 || rule > 3) return false;
   if (rule > 0 && !(etol > 0.0 && etol < 1.0)) return false;
   if (!(a_min >= 0.0 && a_min < INFINITY) || !(a_max >= 0.0 && a_max < INFINITY)) return false;
   return !(a_min > 0.0 && a_max > 0.0 && a_min > a_max);

@@ -196,9 +196,41 @@ __device__ __forceinline__ double radau_phi(const CgScal* sc, int it, double gam
   return (t > 0.0 && ph > 0.0 && ph < inv) ? ph : inv;
 }
 
+// Gap rule.  For a load E the primal energy U of the iterate bounds E.A_H E
+// from above and L = |E|^4 / V, V the dual energy for J = E, from below
+// (Cauchy-Schwarz with V >= E.A_H^-1 E).  With the Gauss-Radau bounds R on
+// U - U* and R' = |E|^4 R_V / (V (V - R_V)) on L* - L (infinite unless
+// V > R_V), the converged gap D* = U* - L* of this entry (eq.
+// approx_homog_with_error) is at least (U - R) - (L + R').  A side stops when
+// its own bound is at most etol (theta) times that: its algebraic error is
+// then below theta D* (Convergence-criteria remark, Sec. 7.2).  The partner's
+// (energy, bound) is its state at the last iterate of the previous chunk of
+// iterations (start energy with an infinite bound during the first chunk):
+// any iterate's values are valid, and the chunk-lockstep launch order of the
+// two solves makes the decision deterministic.
+__device__ __forceinline__ bool gap_converged(const CgScal* sc, int it, double own_rem) {
+  const CgScal* o = sc->partner;
+  if (!o) return false;
+  const int slot = ((it / sc->chunk) + 1) & 1;          // the partner's previous chunk
+  const double oe = o->snap_e[slot], orem = o->snap_r[slot];
+  const double own_e = sc->energy0 - sc->esum;
+  const double n2 = sc->normE * sc->normE, n4 = n2 * n2;
+  double U, RU, V, RV;
+  if (sc->side == 0) {
+    U = own_e, RU = own_rem, V = oe, RV = orem;
+  } else {
+    U = oe, RU = orem, V = own_e, RV = own_rem;
+  }
+  const double L = n4 / V;
+  const double RL = (V - RV > 0.0) ? n4 * RV / (V * (V - RV)) : INFINITY;
+  const double dlow = (U - RU) - (L + RL);
+  const double own = sc->side == 0 ? RU : RL;
+  return dlow > 0.0 && own <= sc->etol * dlow;
+}
+
 // Stopping test of iteration it with gamma = gam; the writer thread keeps the
-// state of the guaranteed rule (parity-buffered: other blocks of the same
-// launch read the previous iteration's entry).
+// state of the guaranteed and gap rules (parity-buffered: other blocks of the
+// same launch read the previous iteration's entry).
 __device__ __forceinline__ bool stop_test(CgScal* sc, int it, double gam, bool writer) {
   bool conv = sqrt(gam) <= sc->tol * sc->normE;
   if (sc->stop == 1) {
@@ -207,6 +239,13 @@ __device__ __forceinline__ bool stop_test(CgScal* sc, int it, double gam, bool w
     const double ph = radau_phi(sc, it, gam);
     if (writer) sc->phi[it & 1] = ph;
     conv = conv || gam * ph <= sc->etol * (sc->energy0 - sc->esum);
+  } else if (sc->stop == 3) {
+    const double ph = radau_phi(sc, it, gam);
+    if (writer) {
+      sc->phi[it & 1] = ph;
+      sc->rem = gam * ph;
+    }
+    conv = conv || gap_converged(sc, it, gam * ph);
   }
   return conv;
 }

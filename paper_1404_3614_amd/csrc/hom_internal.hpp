@@ -47,10 +47,20 @@ struct CgScal {
   double edec[4];    // the last four decrements
   double mu;         // guaranteed rule: lower bound on the spectrum of the operator (0: none)
   double phi[2];     // guaranteed rule: Gauss-Radau factor, remaining energy <= gamma phi
+  // gap rule (3): the partner solve of the same load (the dual of a primal solve and the
+  // reverse) and, per chunk of iterations, this solve's energy and Gauss-Radau bound at the
+  // chunk's last iterate (slot c & 1 for chunk c; slot 1 holds the start, bound infinite)
+  const CgScal* partner;
+  double snap_e[2];
+  double snap_r[2];
+  double rem;        // Gauss-Radau bound of the latest tested iterate
+  int32_t chunk;     // iterations per chunk
+  int32_t side;      // 0 primal, 1 dual
 };
 
 // Stopping rule of a solve: 0 residual; 1 residual or extrapolated energy;
-// 2 residual or guaranteed energy bound.  a_min / a_max: bounds on the
+// 2 residual or guaranteed energy bound; 3 residual or the gap rule (primal
+// and dual side by side, etol = theta).  a_min / a_max: bounds on the
 // pointwise eigenvalues of the coefficient given by the caller (0: none).
 struct StopCfg {
   int rule = 0;
@@ -79,6 +89,7 @@ struct UnitDev {
   double* part_q;                    // [nbApply][9]
   CgScal* sc;                        // [L]
   double E[kMaxLoads][3];            // loads (physical components)
+  CgScal* partner_sc;                // [L] CG scalars of the partner solve (gap rule), or null
   float* grid;                       // real fields on the doubled grid [L*d][M^d] (grid transfers)
 };
 
@@ -145,7 +156,7 @@ hipError_t launch_line_fft(Cx<R>* data, int outer, int Lm, int inner, const Plan
                            int inverse, hipStream_t st);
 
 hipError_t launch_rhs(const Geo& g, const UnitDev* units, int nunits, hipStream_t st);
-hipError_t launch_init_scal(const Geo& g, const UnitDev* units, int nunits, int* iter_base, double tol, int maxit,
+hipError_t launch_init_scal(const Geo& g, const UnitDev* units, int nunits, int* iter_base, int chunk, double tol, int maxit,
                             int stop, double etol, int mu_parts, double mu_user, hipStream_t st);
 // Per unit: partial minima over the doubled grid of the smallest eigenvalue of
 // the coefficient (the unit's own, primal or dual), nparts of them in part_q.

@@ -837,7 +837,10 @@ __global__ void k_start_energy(Geo g, const UnitDev* __restrict__ units) {
       acc += ((h0 == 0) ? 1.0 : 2.0) * (xv.x * (bv.x + rv.x) + xv.y * (bv.y + rv.y));
     }
     const double s = block_sum(acc, s_red);
-    if (threadIdx.x == 0) U.sc[l].esum = s;
+    if (threadIdx.x == 0) {
+      U.sc[l].esum = s;
+      U.sc[l].snap_e[0] = U.sc[l].snap_e[1] = U.sc[l].energy0 - s;
+    }
   }
 }
 
@@ -889,8 +892,8 @@ __global__ void k_coef_min_eig(Geo g, const UnitDev* __restrict__ units) {
   }
 }
 
-__global__ void k_init_scal(Geo g, const UnitDev* __restrict__ units, int nunits, int* iter_base, double tol,
-                            int maxit, int stop, double etol, int mu_parts, double mu_user) {
+__global__ void k_init_scal(Geo g, const UnitDev* __restrict__ units, int nunits, int* iter_base, int chunk,
+                            double tol, int maxit, int stop, double etol, int mu_parts, double mu_user) {
   const int u = blockIdx.x * blockDim.x + threadIdx.x;
   if (u == 0 && iter_base) *iter_base = 0;
   if (u >= nunits) return;
@@ -936,6 +939,13 @@ __global__ void k_init_scal(Geo g, const UnitDev* __restrict__ units, int nunits
     }
     sc->mu = (mu > 0.0) ? mu : 0.0;
     sc->phi[0] = sc->phi[1] = (mu > 0.0) ? 1.0 / mu : INFINITY;
+    // gap rule: the state before the first chunk is the start (infinite bound)
+    sc->partner = U.partner_sc ? U.partner_sc + l : nullptr;
+    sc->snap_e[0] = sc->snap_e[1] = en;
+    sc->snap_r[0] = sc->snap_r[1] = INFINITY;
+    sc->rem = INFINITY;
+    sc->chunk = chunk;
+    sc->side = g.dual;
   }
 }
 
@@ -971,13 +981,21 @@ __global__ void k_symmetrize(Geo g, const Cx<double>* __restrict__ src, Cx<doubl
   }
 }
 
-// After a chunk of iterations: advance the iteration base and count active loads.
+// After a chunk of iterations: advance the iteration base, count active loads
+// and record every load's energy and Gauss-Radau bound at the chunk's last
+// iterate (read by the partner solve under the gap rule during the next chunk).
 __global__ void k_advance(Geo g, const UnitDev* __restrict__ units, int nunits, int* iter_base, int step,
                           int* active_out) {
   __shared__ int cnt[kBlock];
   int c = 0;
+  const int slot = (*iter_base / step) & 1;
   for (int u = threadIdx.x; u < nunits; u += blockDim.x)
-    for (int l = 0; l < g.L; ++l) c += (units[u].sc[l].status == 0);
+    for (int l = 0; l < g.L; ++l) {
+      CgScal* sc = units[u].sc + l;
+      c += (sc->status == 0);
+      sc->snap_e[slot] = sc->energy0 - sc->esum;
+      sc->snap_r[slot] = sc->rem;
+    }
   cnt[threadIdx.x] = c;
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -1303,10 +1321,10 @@ hipError_t launch_start_vectors(const Geo& g, const UnitDev* units, int nunits, 
   return hipGetLastError();
 }
 
-hipError_t launch_init_scal(const Geo& g, const UnitDev* units, int nunits, int* iter_base, double tol, int maxit,
-                            int stop, double etol, int mu_parts, double mu_user, hipStream_t st) {
+hipError_t launch_init_scal(const Geo& g, const UnitDev* units, int nunits, int* iter_base, int chunk, double tol,
+                            int maxit, int stop, double etol, int mu_parts, double mu_user, hipStream_t st) {
   hipLaunchKernelGGL(k_init_scal, dim3((nunits + kBlock - 1) / kBlock), dim3(kBlock), 0, st, g, units, nunits,
-                     iter_base, tol, maxit, stop, etol, mu_parts, mu_user);
+                     iter_base, chunk, tol, maxit, stop, etol, mu_parts, mu_user);
   return hipGetLastError();
 }
 

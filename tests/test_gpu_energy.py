@@ -133,12 +133,12 @@ def test_energy_rule_batch_equals_single_and_validation():
         assert _iters(s) == _iters(o)
         assert relerr(s["A_up"], o["A_up"]) <= 1e-12 and relerr(s["A_low"], o["A_low"]) <= 1e-12
     from paper_1404_3614_amd import _lib as L
-    for bad in ((3, 1e-6, 0, 0), (1, 0.0, 0, 0), (1, 1.5, 0, 0), (1, float("nan"), 0, 0), (2, 1e-6, -1.0, 0),
+    for bad in ((4, 1e-6, 0, 0), (1, 0.0, 0, 0), (1, 1.5, 0, 0), (1, float("nan"), 0, 0), (2, 1e-6, -1.0, 0),
                 (2, 1e-6, 2.0, 1.0), (2, 1e-6, float("inf"), 0)):
         with pytest.raises(H.HomError):
             L.check(L.load().hom_batch_set_stop(b.h, *bad), "hom_batch_set_stop")
     with pytest.raises(KeyError):
-        probs[0].set_stop("gap")
+        probs[0].set_stop("bogus")
 
 
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
