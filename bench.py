@@ -65,6 +65,9 @@ def parse():
     ap.add_argument("--etol", type=float, default=1e-7,
                     help="energy rules: remaining energy decrease / energy of the iterate")
     ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "e1", "e2", "e3"])
+    ap.add_argument("--c4-mode", default="streams", choices=["graph", "streams", "threads"],
+                    help="c4: one captured graph for all classes per chunk, every solve's own graph from one "
+                         "host loop, or a host thread per class")
     ap.add_argument("--e1-jmax", type=int, default=5, help="e1: grids N = 5 3^j for j <= jmax")
     ap.add_argument("--e2-jmax", type=int, default=9, help="e2: even grids n = 2^j for 2 <= j <= jmax")
     ap.add_argument("--c5-train", type=int, default=2048, help="c5: training cells")
@@ -643,8 +646,9 @@ def run_c4(args):
     from paper_1404_3614_amd.mixed import MixedSolver
     specs = homgen.batch_specs()
     rng = [H.cell_eig_range(c) for _, c, _ in specs]
-    ms = MixedSolver(precision=args.precision, stop=args.stop, etol=args.etol,
-                     a_min=min(r[0] for r in rng), a_max=max(r[1] for r in rng))
+    stop_kw = dict(precision=args.precision, stop=args.stop, etol=args.theta if args.stop == "gap" else args.etol,
+                   a_min=min(r[0] for r in rng), a_max=max(r[1] for r in rng))
+    ms = MixedSolver(mode=args.c4_mode, **stop_kw)
     groups = ms.prepare([(N, c) for N, c, _ in specs])   # Fourier data on the device, before the timed region
     for _ in range(args.warmup):
         ms.solve(groups, len(specs), tol=args.tol)
@@ -655,6 +659,21 @@ def run_c4(args):
         res = ms.solve(groups, len(specs), tol=args.tol, timings=timings)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # the other launch modes on the same cells, for comparison
+    other_modes = {}
+    for other in ("graph", "streams", "threads"):
+        if other == args.c4_mode:
+            continue
+        ms2 = MixedSolver(mode=other, **stop_kw)
+        groups2 = ms2.prepare([(N, c) for N, c, _ in specs])
+        ms2.solve(groups2, len(specs), tol=args.tol)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ms2.solve(groups2, len(specs), tol=args.tol)
+        torch.cuda.synchronize()
+        other_modes[other] = round(len(specs) * args.steps / (time.perf_counter() - t0), 3)
+        del ms2, groups2
     classes = []
     for key, items in groups.items():
         its = np.array([[i["iters"] for i in res[j]["info_primal"] + res[j]["info_dual"]] for j, _, _ in items])
@@ -664,7 +683,8 @@ def run_c4(args):
                  "C4: 512 2D cells (random squares, N in {13,41,63,313}) + 64 3D cells (random spheres, N=41), "
                  "contrast log-uniform in [2,1e3], d loads, primal+dual; one lockstep batch per size class, "
                  "classes concurrent on their own streams",
-                 dict(cells_per_step=len(specs), classes=classes))
+                 dict(cells_per_step=len(specs), classes=classes, mode=args.c4_mode,
+                      other_modes=other_modes))
     # bound error of the sampled cells (the highest-contrast cell of every class) against the oracle
     sample_err = {}
     for name in ("C4s_2d_N13", "C4s_2d_N41", "C4s_2d_N63", "C4s_2d_N313", "C4s_3d_N41"):

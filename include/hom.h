@@ -379,7 +379,10 @@ hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const doub
  * kernels of the two solves share the GPU.  Same results as hom_batch_solve
  * with dual = 0 and dual = 1 (no initial guesses); x_primal, x_dual and the
  * info arrays as there.  Synchronises the caller's stream on entry and both
- * streams on return.  With per-kernel timing on, the two solves run in turn. */
+ * streams on return.  With per-kernel timing on, the two solves advance one
+ * chunk of iterations each in turn.  Under the gap rule (stop rule 3) each
+ * load of one solve reads the same load of the other at the end of the
+ * previous chunk, so the two advance in chunk lockstep (cross-stream waits). */
 hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, double tol, int32_t maxit,
                                 double* const* x_primal, double* const* x_dual, hom_info* info_primal,
                                 hom_info* info_dual);
@@ -412,6 +415,40 @@ hom_status hom_batch_set_timing(hom_batch* b, int32_t on);
 hom_status hom_batch_get_timing(hom_batch* b, double* ms_sum, int64_t* launches);
 
 void hom_batch_destroy(hom_batch* b);
+
+/* ---- groups: several batches (size classes, e.g. of a mixed batch of uneven
+ * N and d) solved together.  hom_group_solve_pair runs the primal and dual
+ * solves of the unit loads e_1..e_d of every problem of every batch with one
+ * captured HIP graph: a fork on the first batch's stream, one branch per solve
+ * on the batch's own stream (primal) and library stream (dual), a join.  One
+ * hipGraphLaunch advances every solve of every batch by one chunk of
+ * iterations, and the host reads the active counts once per chunk (one chunk
+ * in flight); finished units return at once.  Results equal those of
+ * hom_batch_solve_pair on each batch (same kernels, same reduction order).
+ * The graph is captured on the first call and again when a batch's tile
+ * shapes change.  batches: host array of n distinct batch handles (no GaNi
+ * problems), which must outlive the group. */
+typedef struct hom_group hom_group;
+hom_status hom_group_create(hom_batch* const* batches, int32_t n, hom_group** out);
+
+/* x_primal, x_dual: host arrays of device field pointers, batch-major, then
+ * problem, then load (d_b loads for batch b, d_b its dimension); info_primal,
+ * info_dual: host arrays of the same length.  Stopping rule and tile shapes
+ * are each batch's own (hom_batch_set_stop, hom_batch_set_tiles).  Waits for
+ * the work already on every batch's stream, synchronises every stream before
+ * returning; with per-kernel timing on in any batch, the solves advance one
+ * chunk each in turn without graphs.  Returns the worst status over the group
+ * (as hom_solve_primal). */
+hom_status hom_group_solve_pair(hom_group* g, double tol, int32_t maxit, double* const* x_primal,
+                                double* const* x_dual, hom_info* info_primal, hom_info* info_dual);
+/* Launch mode of later hom_group_solve_pair calls: 0 (default) one captured
+ * graph advances every solve by a chunk per launch, as above; 1 each solve
+ * replays its own captured chunk graph on its own stream and one host loop
+ * polls them all, so that no solve waits for the chunks of another batch (the
+ * primal and dual of a batch still advance in chunk lockstep under the gap
+ * rule).  Results are the same in both modes.  HOM_E_INVALID for other modes. */
+hom_status hom_group_set_launch(hom_group* g, int32_t mode);
+void hom_group_destroy(hom_group* g);
 
 /* ---- Tile tuning of the FP32 passes.
  * The specialised FP32 kernels (doubled-grid lengths 25, 81, 125, 625) have
@@ -459,7 +496,20 @@ typedef struct {
  *     grid (the operator's quadratic form is a mean over those points) and
  *     a_min (dual: 1 / a_max) when the caller gives one (> 0); a caller's
  *     value must bound the coefficient's eigenvalues, or the guarantee is lost.
- * 0 < etol < 1 for rules 1 and 2; a_min, a_max >= 0 (0: not given).  Every
+ *   rule 3: rule 0 or the gap rule, relative to the discretisation error
+ *     (Convergence-criteria remark of Sec. 7.2; eq. approx_homog_with_error):
+ *     for a load E the primal energy U bounds E.A_H E from above and
+ *     |E|^4 / V, V the dual energy for J = E, from below; with the
+ *     Gauss-Radau bounds R (on U - U*) and R' = |E|^4 R_V / (V (V - R_V)) (on
+ *     L* - L, infinite unless V > R_V, mu as in rule 2), the converged gap
+ *     D* = U* - L* of the entry is at least (U - R) - (L + R'), and each side
+ *     stops when its own bound is at most etol (theta) times that, so that its
+ *     algebraic error is below theta D*.  The partner's state is the one at
+ *     the last iterate of the previous chunk of iterations (start energy,
+ *     infinite bound, during the first).  Only the side-by-side solves
+ *     (hom_batch_solve_pair, hom_group_solve_pair) run it; other solves
+ *     return HOM_E_INVALID under rule 3.
+ * 0 < etol < 1 for rules 1 to 3; a_min, a_max >= 0 (0: not given).  Every
  * iterate is admissible, so the bounds stay guaranteed under every rule.
  * HOM_E_INVALID for other values. */
 hom_status hom_problem_set_stop(hom_problem* pb, int32_t rule, double etol, double a_min, double a_max);

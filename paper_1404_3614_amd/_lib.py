@@ -47,6 +47,11 @@ class Result(C.Structure):
 
 EXPORTS = {
     "hom_status_str": (C.c_char_p, [C.c_int32]),
+    "hom_group_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
+    "hom_group_solve_pair": (C.c_int32, [C.c_void_p, C.c_double, C.c_int32, C.POINTER(C.c_void_p),
+                                         C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
+    "hom_group_destroy": (None, [C.c_void_p]),
+    "hom_group_set_launch": (C.c_int32, [C.c_void_p, C.c_int32]),
     "hom_field_len": (C.c_int32, [C.POINTER(Desc), C.c_int32, C.POINTER(C.c_size_t)]),
     "hom_workspace_bytes": (C.c_int32, [C.POINTER(Desc), C.c_int32, C.POINTER(C.c_size_t)]),
     "hom_setup": (C.c_int32, [C.POINTER(Desc), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,

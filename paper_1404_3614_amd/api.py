@@ -10,7 +10,7 @@ import torch
 
 from . import _lib as L
 
-__all__ = ["Problem", "Batch", "coef_inclusions", "coef_pixels", "coef_from_cell", "problem_from_cell",
+__all__ = ["Problem", "Batch", "Group", "coef_inclusions", "coef_pixels", "coef_from_cell", "problem_from_cell",
            "field_len", "workspace_bytes", "HomError"]
 
 HomError = L.HomError
@@ -616,6 +616,62 @@ class Batch:
         out = self.bounds(xp, xd)
         for i, b in enumerate(out):
             b.update(info_primal=ip[i], info_dual=idl[i])
+        return out
+
+
+class Group:
+    """Batches (size classes) whose primal and dual solves of the unit loads run
+    together from one captured HIP graph (hom_group_solve_pair)."""
+
+    def __init__(self, batches):
+        self.batches = list(batches)
+        hs = (C.c_void_p * len(self.batches))(*[b.h.value for b in self.batches])
+        h = C.c_void_p()
+        L.check(L.load().hom_group_create(hs, len(self.batches), C.byref(h)), "hom_group_create")
+        self.h = h
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            try:
+                L.load().hom_group_destroy(h)
+            except Exception:
+                pass
+            self.h = None
+
+    def set_launch(self, mode):
+        """"graph": one captured graph advances every solve per launch; "streams": every
+        solve replays its own chunk graph, one host loop polls them all (hom_group_set_launch)."""
+        L.check(L.load().hom_group_set_launch(self.h, {"graph": 0, "streams": 1}[mode]), "hom_group_set_launch")
+
+    def solve_bounds(self, tol=1e-6, maxit=10000, allow_not_converged=False):
+        """Bounds of every problem of every batch (a list per batch), fields in the batches' buffers."""
+        fp, fd, counts = [], [], []
+        for b in self.batches:
+            xp, xd = b._fields(False, b.d), b._fields(True, b.d)
+            fp += [t for ts in xp for t in ts]
+            fd += [t for ts in xd for t in ts]
+            counts.append(len(b.problems) * b.d)
+        n = sum(counts)
+        ip, idl = (L.Info * n)(), (L.Info * n)()
+        for b in self.batches:
+            b.stream.wait_stream(torch.cuda.current_stream())
+        st = L.load().hom_group_solve_pair(self.h, float(tol), int(maxit), _dptrs(fp), _dptrs(fd),
+                                           C.cast(ip, C.c_void_p), C.cast(idl, C.c_void_p))
+        L.check(st, "hom_group_solve_pair", allow_not_converged)
+        out, off = [], 0
+        for b, cnt in zip(self.batches, counts):
+            d = b.d
+            conv = lambda infos: [[dict(iters=infos[off + i * d + l].iters, status=infos[off + i * d + l].status,
+                                        rel_res_recur=infos[off + i * d + l].rel_res_recur,
+                                        rel_res_true=infos[off + i * d + l].rel_res_true,
+                                        energy=infos[off + i * d + l].energy) for l in range(d)]
+                                  for i in range(len(b.problems))]
+            res = b.bounds(b._fields(False, d), b._fields(True, d))
+            for r, a, c in zip(res, conv(ip), conv(idl)):
+                r.update(info_primal=a, info_dual=c)
+            out.append(res)
+            off += cnt
         return out
 
 

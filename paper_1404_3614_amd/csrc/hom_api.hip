@@ -578,6 +578,7 @@ struct SolveRun {
   // optional per-kernel timing: events recorded around every launch of the chunk
   std::vector<hipEvent_t>* events = nullptr;
   bool use_graph = false;              // set by start_run
+  bool capture = true;                 // start_run captures the run's own chunk graph (groups capture theirs)
   StopCfg stop;                        // stopping rule
   int types[5] = {0, 0, 0, 0, 0};     // pass types of one iteration
   double* tsum = nullptr;              // [5] accumulated ms per pass type
@@ -684,7 +685,7 @@ hom_status start_run(SolveRun& R, int nload, double tol, int maxit, bool have_x0
     for (auto& ev : *R.events) HIPCHK(hipEventCreate(&ev));
   }
   hipGraphExec_t& gx = *R.graph;
-  if (R.use_graph && !gx) {
+  if (R.use_graph && R.capture && !gx) {
     hipGraph_t graph;
     HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     hipError_t e = enqueue_chunk(R);
@@ -2219,6 +2220,286 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, do
   if (s0 < 0) return s0;
   if (s1 < 0) return s1;
   return s0 != HOM_OK ? s0 : s1;
+}
+
+// ---- groups: the primal and dual solves of several batches in one captured graph
+
+struct hom_group {
+  std::vector<hom_batch*> bs;
+  hipGraphExec_t graph = nullptr;      // `chunks` chunks of every solve of every batch
+  std::vector<Tuning> graph_tiles;     // tile shapes the graph was captured with
+  int graph_rule = -1;
+  int chunks = 1;                      // chunks of iterations per graph launch (HOM_GROUP_CHUNKS; 1 under
+                                       // the gap rule, whose partners exchange state between launches)
+  int graph_chunks = 0;                // chunks per launch of the captured graph
+  int launch = 0;                      // 0: one graph for all solves; 1: each solve's own chunk graph, one host loop
+  std::vector<hipEvent_t> evs;         // fork, joins, per-batch order events, chunk-end pair
+};
+
+}  // extern "C"
+
+namespace {
+// Fill the units of both sides of a batch (unit loads), partner pointers for the gap rule.
+hom_status group_units(hom_batch* b, double* const* xp, double* const* xd) {
+  const int n = b->n, d = b->pbs[0]->desc.d;
+  double E[kMaxLoads * 3] = {};
+  for (int l = 0; l < d; ++l) E[l * d + l] = 1.0;
+  for (int k = 0; k < 2; ++k) {
+    double* const* xo = k == 0 ? xp : xd;
+    for (int i = 0; i < n; ++i) {
+      fill_unit(b->pbs[i], k, d, E, xo + (size_t)i * d, &b->host_units[k][i]);
+      if (b->stop.rule == 3) b->host_units[k][i].partner_sc = b->pbs[i]->slot[1 - k].sc;
+    }
+    HIPCHK(hipMemcpyAsync(b->units[k], b->host_units[k].data(), (size_t)n * sizeof(UnitDev), hipMemcpyHostToDevice,
+                          b->stream));
+  }
+  return HOM_OK;
+}
+
+void group_run(hom_batch* b, int k, SolveRun& R) {
+  hom_problem* p0 = b->pbs[0];
+  const int n = b->n, d = p0->desc.d;
+  R.st = k == 0 ? b->stream : b->stream2;
+  R.g = make_geo(p0, k, d, p0->desc.precision == HOM_MIXED, 0, &b->tune[k][d]);
+  R.fp32 = p0->desc.precision == HOM_MIXED;
+  R.units = b->units[k];
+  R.n = n;
+  R.iter_base = b->iter_base[k];
+  R.active = b->active[k];
+  R.pinned_active = b->pinned + k;
+  R.graph = &b->graph[k][d];
+  R.capture = false;
+  R.chunk = p0->graph_chunk;
+  R.stop = b->stop;
+  for (int i = 0; i < n; ++i) {
+    R.part_d.push_back(b->pbs[i]->slot[k].part_d);
+    R.sc.push_back(b->pbs[i]->slot[k].sc);
+  }
+  R.collect_dev = b->collect_dev + (size_t)k * n * kMaxLoads;
+  R.collect_host = b->collect_host + (size_t)k * n * kMaxLoads;
+  if (b->timing) {
+    R.events = &b->tevents[k][d];
+    R.tsum = b->tsum;
+    R.tcnt = b->tcnt;
+  }
+}
+
+// `chunks` chunks of every run captured on the root stream: a fork event, each
+// run's chunks on its own stream, each joined back.
+hom_status group_capture(std::vector<SolveRun>& runs, hipStream_t root, std::vector<hipEvent_t>& evs, int chunks,
+                         hipGraphExec_t* out) {
+  const size_t nr = runs.size();
+  hipEvent_t fork = evs[0];
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(root, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipEventRecord(fork, root);
+  for (size_t r = 0; r < nr && e == hipSuccess; ++r)
+    if (runs[r].st != root) e = hipStreamWaitEvent(runs[r].st, fork, 0);
+  for (int c = 0; c < chunks && e == hipSuccess; ++c)
+    for (size_t r = 0; r < nr && e == hipSuccess; ++r) e = enqueue_chunk(runs[r]);
+  for (size_t r = 0; r < nr && e == hipSuccess; ++r) {
+    if (runs[r].st != root) {
+      e = hipEventRecord(evs[1 + r], runs[r].st);
+      if (e == hipSuccess) e = hipStreamWaitEvent(root, evs[1 + r], 0);
+    }
+  }
+  hipError_t e2 = hipStreamEndCapture(root, &graph);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return HOM_E_DEVICE;
+  }
+  e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  return e == hipSuccess ? HOM_OK : HOM_E_DEVICE;
+}
+}  // namespace
+
+extern "C" {
+
+hom_status hom_group_create(hom_batch* const* batches, int32_t n, hom_group** out) {
+  if (!batches || n < 1 || !out) return HOM_E_INVALID;
+  for (int i = 0; i < n; ++i) {
+    if (!batches[i] || batch_has_gani(batches[i])) return HOM_E_INVALID;
+    for (int j = 0; j < i; ++j)
+      if (batches[j] == batches[i]) return HOM_E_INVALID;
+  }
+  hom_group* g = new hom_group();
+  g->bs.assign(batches, batches + n);
+  g->chunks = std::max(1, std::min(16, env_int("HOM_GROUP_CHUNKS", 1)));
+  // fork, one join per run (2 per batch), one order event per batch
+  g->evs.assign((size_t)1 + 2 * n + n, nullptr);
+  for (auto& ev : g->evs)
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+      for (auto x : g->evs)
+        if (x) (void)hipEventDestroy(x);
+      delete g;
+      return HOM_E_DEVICE;
+    }
+  *out = g;
+  return HOM_OK;
+}
+
+hom_status hom_group_solve_pair(hom_group* grp, double tol, int32_t maxit, double* const* x_primal,
+                                double* const* x_dual, hom_info* info_primal, hom_info* info_dual) {
+  if (!grp || !x_primal || !x_dual || !info_primal || !info_dual) return HOM_E_INVALID;
+  const int nb = (int)grp->bs.size();
+  // validation of every batch before anything is launched
+  size_t off = 0;
+  for (hom_batch* b : grp->bs) {
+    const int d = b->pbs[0]->desc.d;
+    double E[9] = {};
+    for (int l = 0; l < d; ++l) E[l * d + l] = 1.0;
+    if (batch_has_gani(b) || b->pbs[0]->max_loads < d) return HOM_E_INVALID;
+    for (int i = 0; i < b->n; ++i) {
+      hom_status s = check_solve_args(b->pbs[i], d, E, x_primal + off + (size_t)i * d, tol, maxit);
+      if (s == HOM_OK) s = check_solve_args(b->pbs[i], d, E, x_dual + off + (size_t)i * d, tol, maxit);
+      if (s != HOM_OK) return s;
+    }
+    off += (size_t)b->n * d;
+  }
+  std::vector<SolveRun> runs(2 * (size_t)nb);
+  hipStream_t root = grp->bs[0]->stream;
+  bool timing = false;
+  off = 0;
+  for (int bi = 0; bi < nb; ++bi) {
+    hom_batch* b = grp->bs[bi];
+    const int d = b->pbs[0]->desc.d;
+    if (!b->stream2 && hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess) {
+      b->stream2 = nullptr;
+      return HOM_E_DEVICE;
+    }
+    for (int k = 0; k < 2; ++k)
+      if (!b->tuned[k][d]) {
+        hom_status s = solve_tuning(b->pbs.data(), b->n, k, d, b->units[k], b->stream, &b->tune[k][d]);
+        if (s != HOM_OK) return s;
+        b->tuned[k][d] = true;
+      }
+    hom_status s = group_units(b, x_primal + off, x_dual + off);
+    if (s != HOM_OK) return s;
+    off += (size_t)b->n * d;
+    group_run(b, 0, runs[2 * bi]);
+    group_run(b, 1, runs[2 * bi + 1]);
+    timing = timing || b->timing;
+    // everything on this batch's stream so far (the caller's setup, the unit tables) before the group's work
+    HIPCHK(hipEventRecord(grp->evs[1 + 2 * nb + bi], b->stream));
+  }
+  for (int bi = 0; bi < nb; ++bi) {
+    hom_batch* b = grp->bs[bi];
+    for (int bj = 0; bj < nb; ++bj)
+      for (hipStream_t st : {b->stream, b->stream2})
+        if (bj != bi || st != b->stream) HIPCHK(hipStreamWaitEvent(st, grp->evs[1 + 2 * nb + bj], 0));
+  }
+  for (auto& R : runs) {
+    R.capture = grp->launch == 1;      // launch mode 1 replays each solve's own chunk graph
+    hom_status s = start_run(R, R.g.L, tol, maxit, false);
+    if (s != HOM_OK) return s;
+  }
+  hom_status s = HOM_OK;
+  const bool graphs = !timing && std::all_of(runs.begin(), runs.end(), [](const SolveRun& R) { return R.use_graph; });
+  if (graphs && grp->launch == 1) {
+    // every solve's chunk graph on its own stream, one host loop over all of them; the
+    // primal and dual of a batch are partners under the gap rule
+    std::vector<SolveRun*> rp;
+    std::vector<int> partner(runs.size(), -1);
+    for (size_t r = 0; r < runs.size(); ++r) {
+      rp.push_back(&runs[r]);
+      if (grp->bs[r / 2]->stop.rule == 3) partner[r] = (int)(r ^ 1);
+    }
+    s = loop_runs(rp.data(), (int)rp.size(), maxit, partner.data());
+    if (s != HOM_OK) return s;
+  } else if (graphs) {
+    // the captured graph holds the geometry (tile shapes) and the stopping rule of every run
+    std::vector<Tuning> tiles;
+    for (hom_batch* b : grp->bs)
+      for (int k = 0; k < 2; ++k) tiles.push_back(b->tune[k][b->pbs[0]->desc.d]);
+    const int rule = grp->bs[0]->stop.rule;
+    bool gap = false;
+    for (hom_batch* b : grp->bs) gap = gap || b->stop.rule == 3;
+    // under the gap rule a chunk must see its partner's previous chunk complete: one chunk per launch
+    const int chunks = gap ? 1 : grp->chunks;
+    bool same = grp->graph && grp->graph_rule == rule && grp->graph_chunks == chunks &&
+                tiles.size() == grp->graph_tiles.size();
+    for (size_t i = 0; same && i < tiles.size(); ++i) same = std::memcmp(&tiles[i], &grp->graph_tiles[i], sizeof(Tuning)) == 0;
+    if (!same) {
+      if (grp->graph) (void)hipGraphExecDestroy(grp->graph);
+      grp->graph = nullptr;
+      // the start kernels of every run come before the capture's fork on the root stream
+      for (size_t r = 0; r < runs.size(); ++r)
+        if (runs[r].st != root) {
+          HIPCHK(hipEventRecord(grp->evs[1 + r], runs[r].st));
+          HIPCHK(hipStreamWaitEvent(root, grp->evs[1 + r], 0));
+        }
+      s = group_capture(runs, root, grp->evs, chunks, &grp->graph);
+      if (s != HOM_OK) return s;
+      grp->graph_tiles = tiles;
+      grp->graph_rule = rule;
+      grp->graph_chunks = chunks;
+    } else {
+      for (size_t r = 0; r < runs.size(); ++r)
+        if (runs[r].st != root) {
+          HIPCHK(hipEventRecord(grp->evs[1 + r], runs[r].st));
+          HIPCHK(hipStreamWaitEvent(root, grp->evs[1 + r], 0));
+        }
+    }
+    // one launch advances every solve by a chunk; one chunk stays in flight while the
+    // host reads the active counts of the one before
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    int it = 0, done = 0;
+    const int chunk = runs[0].chunk * grp->graph_chunks;
+    if (e == hipSuccess) e = hipGraphLaunch(grp->graph, root);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], root);
+    while (e == hipSuccess) {
+      e = hipGraphLaunch(grp->graph, root);
+      if (e == hipSuccess) e = hipEventRecord(ev[(it + 1) & 1], root);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[it & 1]);
+      if (e != hipSuccess) break;
+      done += chunk;
+      ++it;
+      bool any = false;
+      for (auto& R : runs) any = any || *R.pinned_active != 0;
+      if (!any || done > maxit + chunk) break;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(root);
+    for (auto x : ev)
+      if (x) (void)hipEventDestroy(x);
+    if (e != hipSuccess) return HOM_E_DEVICE;
+  } else {
+    std::vector<SolveRun*> rp;
+    for (auto& R : runs) rp.push_back(&R);
+    s = loop_direct(rp.data(), (int)rp.size(), maxit);
+    if (s != HOM_OK) return s;
+  }
+  // per-run residual checks and summaries, worst status over the group
+  hom_status worst = HOM_OK;
+  off = 0;
+  for (int bi = 0; bi < nb; ++bi) {
+    const int d = grp->bs[bi]->pbs[0]->desc.d;
+    for (int k = 0; k < 2; ++k) {
+      hom_info* info = (k == 0 ? info_primal : info_dual) + off;
+      hom_status r = finish_run(runs[2 * bi + k], d, maxit, info);
+      if (r < 0 && (worst >= 0 || r < worst)) worst = r;
+      else if (r == HOM_NOT_CONVERGED && worst == HOM_OK) worst = r;
+    }
+    off += (size_t)grp->bs[bi]->n * d;
+  }
+  for (hom_batch* b : grp->bs) HIPCHK(hipStreamSynchronize(b->stream2));
+  return worst;
+}
+
+hom_status hom_group_set_launch(hom_group* grp, int32_t mode) {
+  if (!grp || (mode != 0 && mode != 1)) return HOM_E_INVALID;
+  grp->launch = mode;
+  return HOM_OK;
+}
+
+void hom_group_destroy(hom_group* grp) {
+  if (!grp) return;
+  if (grp->graph) (void)hipGraphExecDestroy(grp->graph);
+  for (auto x : grp->evs)
+    if (x) (void)hipEventDestroy(x);
+  delete grp;
 }
 
 hom_status hom_batch_update_coefficients(hom_batch* b, const void* const* Ahat, const void* const* Bhat) {

@@ -1,11 +1,16 @@
 """Mixed batches of uneven size: cells are grouped by size class (d, N, ncoef)
 and every class is solved as one lockstep batch (one launch per pass covers
-all cells of the class, iterations replayed from a captured graph).
+all cells of the class).
 
 A class keeps its problem handles, workspaces and batch between calls, so a
 stream of new cells of the same classes re-uses them through
-hom_batch_update_coefficients.  Classes run on streams of their own, driven
-by one host thread each, so small classes overlap the large ones on the GPU.
+hom_batch_update_coefficients.  Classes run on streams of their own, so
+small classes overlap the large ones on the GPU, in one of three modes:
+"graph": every class's primal and dual solves advance together from one
+captured HIP graph per chunk of iterations (hom_group_solve_pair), one host
+poll per chunk; "streams": every solve replays its own chunk graph on its own
+stream, one host loop polls them all (no class waits for another's chunks);
+"threads": each class's pair solve is driven by a host thread of its own.
 """
 from __future__ import annotations
 
@@ -20,11 +25,15 @@ from . import api
 
 
 class MixedSolver:
-    def __init__(self, precision="mixed", concurrent=True, stop="residual", etol=None, a_min=0.0, a_max=0.0):
+    def __init__(self, precision="mixed", concurrent=True, stop="residual", etol=None, a_min=0.0, a_max=0.0,
+                 mode="streams"):
+        assert mode in ("graph", "streams", "threads")
         self.precision = precision
         self.concurrent = concurrent
+        self.mode = mode
         self.stop = (stop, etol, a_min, a_max)   # Batch.set_stop arguments of every class
         self.classes = {}
+        self._group = None                       # (class keys, api.Group) of the last graph-mode solve
 
     def _class(self, key, count, coefs):
         d, N, nc, Y = key
@@ -62,6 +71,23 @@ class MixedSolver:
         work = [(key, items, self._class(key, len(items), [(Ah, Bh) for _, Ah, Bh in items]))
                 for key, items in groups.items()]
         torch.cuda.synchronize()
+        if self.mode in ("graph", "streams") and self.concurrent:
+            keys = tuple(k for k, _, _ in work)
+            batches = [cls["batch"] for _, _, cls in work]
+            if self._group is None or self._group[0] != keys or \
+                    any(a is not b for a, b in zip(self._group[1].batches, batches)):
+                self._group = (keys, api.Group(batches))
+                self._group[1].set_launch(self.mode)
+            t0 = time.perf_counter()
+            res_all = self._group[1].solve_bounds(tol=tol, maxit=maxit)
+            dt = time.perf_counter() - t0
+            for (key, items, cls), res in zip(work, res_all):
+                if timings is not None:
+                    timings[key] = dt
+                for (i, _, _), r in zip(items, res):
+                    r["class"] = dict(d=key[0], N=key[1])
+                    out[i] = r
+            return out
 
         def run(job):
             key, items, cls = job
