@@ -522,6 +522,24 @@ hom_status hom_set_tuning(int32_t mode);
  * this problem / batch has chosen them yet. */
 hom_status hom_problem_tuning(hom_problem* pb, int32_t dual, int32_t nload, hom_tuning* out);
 hom_status hom_batch_tuning(hom_batch* b, int32_t dual, int32_t nload, hom_tuning* out);
+/* The tuner's choices on disk, so that later processes skip the timing.  One
+ * JSON object per line: the device architecture (gcnArchName up to its first
+ * ':'), the geometry key (doubled grid M0 M1 M2 on internal axes, d, loads,
+ * dual, coefficient components, packs) and the shape with its measured
+ * times; shapes are shared by every batch size of a geometry, so that batches
+ * and single solves run the same kernels.  hom_tune_cache_load merges the
+ * entries of `arch` (NULL: the current device's) into the process cache
+ * (*loaded, may be NULL: their count; HOM_E_INVALID for an unreadable file or
+ * a line that does not parse, entries read before it stay); hom_tune_cache_save
+ * writes the whole process cache tagged with `arch` (replacing the file);
+ * hom_tune_cache_clear empties the process cache.  With the environment
+ * variable HOM_TUNE_CACHE set to a path, the first tuning of the process
+ * loads that file and every new choice rewrites it.  HOM_E_DEVICE when arch
+ * is NULL and no device is present. */
+hom_status hom_tune_cache_load(const char* path, const char* arch, int32_t* loaded);
+hom_status hom_tune_cache_save(const char* path, const char* arch);
+hom_status hom_tune_cache_clear(void);
+
 /* Pin the tile shape of the solves of (dual, nload): row_pairs, row_threads,
  * apply_points, apply_half_exchange and apply_all_packs of *t (all 0 =
  * default; the timing fields are ignored).  For bitwise-reproducible results

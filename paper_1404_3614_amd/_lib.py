@@ -52,6 +52,9 @@ EXPORTS = {
                                          C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
     "hom_group_destroy": (None, [C.c_void_p]),
     "hom_group_set_launch": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "hom_tune_cache_load": (C.c_int32, [C.c_char_p, C.c_char_p, C.POINTER(C.c_int32)]),
+    "hom_tune_cache_save": (C.c_int32, [C.c_char_p, C.c_char_p]),
+    "hom_tune_cache_clear": (C.c_int32, []),
     "hom_field_len": (C.c_int32, [C.POINTER(Desc), C.c_int32, C.POINTER(C.c_size_t)]),
     "hom_workspace_bytes": (C.c_int32, [C.POINTER(Desc), C.c_int32, C.POINTER(C.c_size_t)]),
     "hom_setup": (C.c_int32, [C.POINTER(Desc), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,

@@ -449,6 +449,25 @@ def set_tuning(on=True):
     L.check(L.load().hom_set_tuning(1 if on else 0), "hom_set_tuning")
 
 
+def tune_cache_load(path, arch=None):
+    """Merge the tuner choices of `arch` (default: the current device's) from a
+    JSON-lines file into the process cache (hom_tune_cache_load); returns their count."""
+    n = C.c_int32()
+    L.check(L.load().hom_tune_cache_load(str(path).encode(), None if arch is None else arch.encode(), C.byref(n)),
+            "hom_tune_cache_load")
+    return n.value
+
+
+def tune_cache_save(path, arch=None):
+    """Write the process's tuner choices to a JSON-lines file (hom_tune_cache_save)."""
+    L.check(L.load().hom_tune_cache_save(str(path).encode(), None if arch is None else arch.encode()),
+            "hom_tune_cache_save")
+
+
+def tune_cache_clear():
+    L.check(L.load().hom_tune_cache_clear(), "hom_tune_cache_clear")
+
+
 def _tuning_dict(t):
     return dict(row_pairs=t.row_pairs, row_threads=t.row_threads, apply_points=t.apply_points,
                 apply_half_exchange=t.apply_half_exchange, apply_all_packs=t.apply_all_packs,

@@ -6,9 +6,11 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdlib>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <string>
 #include <tuple>
 #include <vector>
 
@@ -82,6 +84,102 @@ struct TuneKey {
 std::mutex g_tune_mu;
 std::map<TuneKey, Tuning> g_tune_cache;
 int g_tune_mode = -1;  // -1: not read yet (HOM_TUNE, default 1)
+bool g_tune_file_read = false;   // HOM_TUNE_CACHE read into the cache (once per process)
+
+// ---- the tuner cache on disk: one JSON object per line, per device architecture
+// (the gcnArchName up to its first ':'), so that later processes skip the timing.
+
+// Architecture of the current device, or "" without one.
+std::string device_arch() {
+  int dev = -1;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "";
+  std::string a = prop.gcnArchName;
+  return a.substr(0, a.find(':'));
+}
+
+bool json_num(const std::string& line, const char* key, double* v) {
+  const std::string k = std::string("\"") + key + "\":";
+  const size_t at = line.find(k);
+  if (at == std::string::npos) return false;
+  const char* p = line.c_str() + at + k.size();
+  char* end = nullptr;
+  *v = std::strtod(p, &end);
+  return end != p;
+}
+
+bool json_str(const std::string& line, const char* key, std::string* v) {
+  const std::string k = std::string("\"") + key + "\":";
+  size_t at = line.find(k);
+  if (at == std::string::npos) return false;
+  at = line.find('"', at + k.size());
+  if (at == std::string::npos) return false;
+  const size_t e = line.find('"', at + 1);
+  if (e == std::string::npos) return false;
+  *v = line.substr(at + 1, e - at - 1);
+  return true;
+}
+
+// Entries of `arch` from the file into the cache (caller holds g_tune_mu);
+// false when the file cannot be read or a line does not parse.
+bool tune_file_read(const char* path, const std::string& arch, int* loaded) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  bool ok = true;
+  int cnt = 0;
+  char buf[1024];
+  while (std::fgets(buf, sizeof(buf), f)) {
+    std::string line(buf);
+    if (line.find('{') == std::string::npos) continue;
+    std::string a;
+    double v[16];
+    const char* keys[16] = {"M0", "M1", "M2", "d", "loads", "dual", "nc", "packs", "row_pairs", "row_threads",
+                            "apply_points", "apply_half_exchange", "apply_all_packs", "row_ms", "apply_ms",
+                            "candidates"};
+    bool good = json_str(line, "arch", &a);
+    for (int i = 0; i < 16 && good; ++i) good = json_num(line, keys[i], &v[i]);
+    if (!good) {
+      ok = false;
+      break;
+    }
+    if (a != arch) continue;
+    TuneKey k{(int)v[0], (int)v[1], (int)v[2], (int)v[3], (int)v[4], (int)v[5], (int)v[6], (int)v[7]};
+    Tuning t;
+    t.rowG = (int)v[8];
+    t.rowThreads = (int)v[9];
+    t.apTP = (int)v[10];
+    t.apHX = (int)v[11];
+    t.apAll = (int)v[12];
+    t.row_ms = v[13];
+    t.apply_ms = v[14];
+    t.candidates = (int)v[15];
+    g_tune_cache[k] = t;
+    ++cnt;
+  }
+  std::fclose(f);
+  if (loaded) *loaded = cnt;
+  return ok;
+}
+
+// The whole cache, tagged with `arch`, to the file (caller holds g_tune_mu).
+bool tune_file_write(const char* path, const std::string& arch) {
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  for (const auto& kv : g_tune_cache) {
+    const TuneKey& k = kv.first;
+    const Tuning& t = kv.second;
+    std::fprintf(f,
+                 "{\"arch\": \"%s\", \"M0\": %d, \"M1\": %d, \"M2\": %d, \"d\": %d, \"loads\": %d, \"dual\": %d, "
+                 "\"nc\": %d, \"packs\": %d, \"row_pairs\": %d, \"row_threads\": %d, \"apply_points\": %d, "
+                 "\"apply_half_exchange\": %d, \"apply_all_packs\": %d, \"row_ms\": %.9g, \"apply_ms\": %.9g, "
+                 "\"candidates\": %d}\n",
+                 arch.c_str(), k.M0, k.M1, k.M2, k.d, k.L, k.dual, k.nc, k.P, t.rowG, t.rowThreads, t.apTP, t.apHX,
+                 t.apAll, t.row_ms, t.apply_ms, t.candidates);
+  }
+  const bool ok = std::fclose(f) == 0;
+  return ok && std::rename(tmp.c_str(), path) == 0;
+}
 
 bool tuning_on() {
   std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -865,8 +963,13 @@ hom_status solve_tuning(hom_problem* const* pbs, int n, int k, int nload, UnitDe
   if (p0->desc.precision != HOM_MIXED || !tuning_on()) return HOM_OK;
   const Geo g = make_geo(p0, k, nload, true);
   const TuneKey key{g.M[0], g.M[1], g.M[2], g.d, nload, k, g.nc, g.P};
+  const char* file = std::getenv("HOM_TUNE_CACHE");
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (file && *file && !g_tune_file_read) {
+      g_tune_file_read = true;
+      (void)tune_file_read(file, device_arch(), nullptr);    // a missing or foreign file only costs the timing
+    }
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
       *out = it->second;
@@ -881,6 +984,7 @@ hom_status solve_tuning(hom_problem* const* pbs, int n, int k, int nload, UnitDe
   HIPCHK(hipStreamSynchronize(st));
   std::lock_guard<std::mutex> lk(g_tune_mu);
   *out = g_tune_cache.emplace(key, t).first->second;
+  if (file && *file) (void)tune_file_write(file, device_arch());
   return HOM_OK;
 }
 
@@ -2669,6 +2773,31 @@ hom_status hom_problem_set_stop(hom_problem* pb, int32_t rule, double etol, doub
 hom_status hom_batch_set_stop(hom_batch* b, int32_t rule, double etol, double a_min, double a_max) {
   if (!b || !stop_args_ok(rule, etol, a_min, a_max)) return HOM_E_INVALID;
   b->stop = make_stop(rule, etol, a_min, a_max);
+  return HOM_OK;
+}
+
+hom_status hom_tune_cache_load(const char* path, const char* arch, int32_t* loaded) {
+  if (!path) return HOM_E_INVALID;
+  const std::string a = arch ? std::string(arch) : device_arch();
+  if (a.empty()) return HOM_E_DEVICE;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  int n = 0;
+  const bool ok = tune_file_read(path, a, &n);
+  if (loaded) *loaded = n;
+  return ok ? HOM_OK : HOM_E_INVALID;
+}
+
+hom_status hom_tune_cache_save(const char* path, const char* arch) {
+  if (!path) return HOM_E_INVALID;
+  const std::string a = arch ? std::string(arch) : device_arch();
+  if (a.empty()) return HOM_E_DEVICE;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  return tune_file_write(path, a) ? HOM_OK : HOM_E_INVALID;
+}
+
+hom_status hom_tune_cache_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache.clear();
   return HOM_OK;
 }
 

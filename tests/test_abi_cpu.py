@@ -168,3 +168,35 @@ def test_coef_scratch_bytes():
     assert lib.hom_coef_scratch_bytes(C.byref(ds), -1, None, C.byref(n)) == L.HOM_E_INVALID
     P0 = (C.c_int32 * 3)(0, 125, 1)
     assert lib.hom_coef_scratch_bytes(C.byref(ds), 0, P0, C.byref(n)) == L.HOM_E_INVALID
+
+
+def test_tuner_cache_file_roundtrip(tmp_path):
+    """The tuner cache on disk (host code, no device): entries of the named
+    architecture are merged, others skipped; saving writes them back; a line
+    that does not parse is an error."""
+    L, lib = _lib()
+    src = tmp_path / "tune.jsonl"
+    src.write_text(
+        '{"arch": "gfx950", "M0": 625, "M1": 1, "M2": 625, "d": 2, "loads": 2, "dual": 0, "nc": 1, "packs": 1, '
+        '"row_pairs": 2, "row_threads": 256, "apply_points": 10, "apply_half_exchange": 1, "apply_all_packs": 0, '
+        '"row_ms": 0.1505, "apply_ms": 0.0672, "candidates": 11}\n'
+        '{"arch": "gfx942", "M0": 81, "M1": 81, "M2": 81, "d": 3, "loads": 3, "dual": 1, "nc": 1, "packs": 5, '
+        '"row_pairs": 7, "row_threads": 0, "apply_points": 14, "apply_half_exchange": 0, "apply_all_packs": 0, '
+        '"row_ms": 0.2, "apply_ms": 0.1, "candidates": 9}\n')
+    assert lib.hom_tune_cache_clear() == 0
+    n = C.c_int32()
+    assert lib.hom_tune_cache_load(str(src).encode(), b"gfx950", C.byref(n)) == 0
+    assert n.value == 1
+    out = tmp_path / "out.jsonl"
+    assert lib.hom_tune_cache_save(str(out).encode(), b"gfx950") == 0
+    lines = out.read_text().strip().splitlines()
+    assert len(lines) == 1
+    import json
+    rec = json.loads(lines[0])
+    assert rec["arch"] == "gfx950" and rec["M0"] == 625 and rec["apply_points"] == 10
+    assert rec["apply_half_exchange"] == 1 and abs(rec["row_ms"] - 0.1505) < 1e-12 and rec["candidates"] == 11
+    bad = tmp_path / "bad.jsonl"
+    bad.write_text('{"arch": "gfx950", "M0": 625}\n')
+    assert lib.hom_tune_cache_load(str(bad).encode(), b"gfx950", C.byref(n)) == L.HOM_E_INVALID
+    assert lib.hom_tune_cache_load(str(tmp_path / "missing").encode(), b"gfx950", C.byref(n)) == L.HOM_E_INVALID
+    assert lib.hom_tune_cache_clear() == 0

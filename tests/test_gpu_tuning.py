@@ -115,3 +115,24 @@ def test_fp64_problems_reject_pinned_tiles():
     with pytest.raises(H.HomError):
         pb.set_tiles(False, 2, row_pairs=25)
     assert pb.tuning(False, 2)["candidates"] == 0
+
+
+def test_tuner_cache_persists_choices(tmp_path):
+    """A tuned choice written to disk and read back after the process cache was
+    emptied is the one later batches of the geometry use (its recorded timings
+    come from the file, not from a new timing run), and gives the same bounds."""
+    H = _H()
+    from paper_1404_3614_amd import api
+    probs, b = _batch(H, 41, [101, 102])
+    t0 = b.tuning(False, 2)
+    ref = b.solve_bounds(tol=1e-8)
+    path = tmp_path / "tune.jsonl"
+    api.tune_cache_save(path)
+    api.tune_cache_clear()
+    assert api.tune_cache_load(path) >= 1
+    probs2, b2 = _batch(H, 41, [101, 102])
+    t1 = b2.tuning(False, 2)
+    assert t1 == t0
+    out = b2.solve_bounds(tol=1e-8)
+    for x, y in zip(out, ref):
+        assert np.array_equal(x["A_up"], y["A_up"]) and np.array_equal(x["A_low"], y["A_low"])
