@@ -37,190 +37,227 @@ struct View {
 
 // ------------------------------------------------------------------ convolution
 // out[b, off_o + co, q] = act( bias[co] + sum_ci sum_tap w[co, ci, tap] in[b, off_i + ci, q + tap] )
-// periodic neighbours; KS = 3 (or 1).  Block: TPX output points x COT output
-// channels; threads: each handles PPT points x CPT channels.
-constexpr int CT = 256;      // threads
+// with periodic neighbours, KS = 3 (or 1), as implicit GEMMs on the matrix cores:
+// M = output channels, N = points, K = input channels x taps, FP32 operands and
+// accumulation (v_mfma_f32_16x16x4f32; lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and holds D[4 (l / 16) + r][l % 16], r < 4).
+constexpr int CT = 256;      // threads per block (4 waves)
 constexpr int COT = 32;      // output channels per block
-constexpr int CIC = 8;       // input channels per LDS chunk
+constexpr int CIC = 8;       // input channels per LDS stage (forward)
+constexpr int WCI = 16;      // input channels per block (weight gradient)
+constexpr int WST = 48;      // LDS row stride of [k][channel] tiles: two k rows of a half-wave 16 banks apart
+constexpr int kWgradChunks = 64;   // weight-gradient partials per layer (summed in a fixed order)
+
+typedef float v4f __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int wrap(int i, int n) {
   i %= n;
   return i < 0 ? i + n : i;
 }
 
-// 2D tile 16 x 16 points, 3D tile 4 x 8 x 8
+// Point tile of a block: 128 points, 2D 16 x 8, 3D 8 x 4 x 4 (x fastest)
 template <int D>
 struct Tile {
-  static constexpr int X = D == 2 ? 16 : 8, Y = D == 2 ? 16 : 8, Z = D == 2 ? 1 : 4;
+  static constexpr int X = D == 2 ? 16 : 8, Y = D == 2 ? 8 : 4, Z = D == 2 ? 1 : 4;
   static constexpr int NP = X * Y * Z;
 };
 
+// Smallest s >= n with s = want (mod 32): LDS channel strides that spread the
+// channels read by one half-wave over distinct banks.
+constexpr int pad_to(int n, int want) { return n + (((want - n % 32) % 32) + 32) % 32; }
+
+template <int D, int KS>
+struct Halo {
+  static constexpr int R = KS / 2;
+  static constexpr int X = Tile<D>::X + 2 * R, Y = Tile<D>::Y + 2 * R, Z = D == 3 ? Tile<D>::Z + 2 * R : 1;
+  static constexpr int N = X * Y * Z;
+  static constexpr int TAPS = D == 3 ? KS * KS * KS : KS * KS;
+};
+
+// Stage the periodic halo of a point tile for channels [c0, c0 + nc) of in into s (channel stride HS).
+template <int D, int KS, int HS>
+__device__ __forceinline__ void stage_halo(float* s, const float* __restrict__ in, int Cin, int inCtot, int inOff,
+                                           int c0, int nc, int b, int tx0, int ty0, int tz0, int Zs, int Hs, int Ws,
+                                           size_t plane) {
+  using H = Halo<D, KS>;
+  for (int t = threadIdx.x; t < nc * H::N; t += CT) {
+    const int c = t / H::N, r = t - c * H::N;
+    const int hx = r % H::X, hy = (r / H::X) % H::Y, hz = r / (H::X * H::Y);
+    float v = 0.f;
+    if (c0 + c < Cin) {
+      const int gx = wrap(tx0 + hx - H::R, Ws), gy = wrap(ty0 + hy - H::R, Hs);
+      const int gz = (D == 3) ? wrap(tz0 + hz - H::R, Zs) : 0;
+      v = in[((size_t)b * inCtot + inOff + c0 + c) * plane + ((size_t)gz * Hs + gy) * Ws + gx];
+    }
+    s[c * HS + r] = v;
+  }
+}
+
+template <int D>
+__device__ __forceinline__ void tile_origin(int tile, int Hs, int Ws, int* tx0, int* ty0, int* tz0) {
+  const int tiles_x = (Ws + Tile<D>::X - 1) / Tile<D>::X, tiles_y = (Hs + Tile<D>::Y - 1) / Tile<D>::Y;
+  *tx0 = (tile % tiles_x) * Tile<D>::X;
+  tile /= tiles_x;
+  *ty0 = (tile % tiles_y) * Tile<D>::Y;
+  *tz0 = (tile / tiles_y) * Tile<D>::Z;
+}
+
+// Forward convolution (also the data gradient with flipped, transposed weights).
+// Block: 128 points x 32 output channels; wave w: points 32 w .. 32 w + 31 (two
+// tiles of 16) x the 32 channels (two tiles of 16).  K runs tap-major over
+// stages of CIC input channels, so the four k of an MFMA step share a tap.
 template <int D, int KS>
 __global__ __launch_bounds__(CT) void k_conv_fwd(const float* __restrict__ in, int Cin, int inCtot, int inOff,
                                                  const float* __restrict__ w, const float* __restrict__ bias,
                                                  float* __restrict__ out, int Cout, int outCtot, int outOff, int Zs,
                                                  int Hs, int Ws, int relu, int accumulate) {
-  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z, NP = Tile<D>::NP;
-  constexpr int R = KS / 2;
-  constexpr int HX = TX + 2 * R, HY = TY + 2 * R, HZ = (D == 3) ? TZ + 2 * R : 1;
-  constexpr int TAPS = (D == 3) ? KS * KS * KS : KS * KS;
-  constexpr int PPT = NP / (CT / 8);   // points per thread (8 channel groups of 4)
-  constexpr int CPT = COT / 8;
-  __shared__ float s_in[CIC][HZ * HY * HX];
-  __shared__ float s_w[CIC][TAPS][COT];
-  const int tiles_x = (Ws + TX - 1) / TX, tiles_y = (Hs + TY - 1) / TY;
-  int tile = blockIdx.x;
-  const int tx0 = (tile % tiles_x) * TX;
-  tile /= tiles_x;
-  const int ty0 = (tile % tiles_y) * TY;
-  tile /= tiles_y;
-  const int tz0 = tile * TZ;
+  using H = Halo<D, KS>;
+  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
+  constexpr int TAPS = H::TAPS;
+  constexpr int HS = pad_to(H::N, 16);     // channel stride: lanes 16..31 read the next channel 16 banks away
+  __shared__ float s_in[CIC * HS];
+  __shared__ float s_w[TAPS * CIC * WST];  // [tap][c][co]
+  int tx0, ty0, tz0;
+  tile_origin<D>(blockIdx.x, Hs, Ws, &tx0, &ty0, &tz0);
   const int co0 = blockIdx.y * COT;
   const int b = blockIdx.z;
-  const int tid = threadIdx.x;
-  const int cg = tid & 7;           // channel group: channels co0 + cg*CPT ..
-  const int pg = tid >> 3;          // point group: points pg*PPT ..
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lk = lane >> 4, ln = lane & 15;
   const size_t plane = (size_t)Zs * Hs * Ws;
-  float acc[PPT][CPT];
+  // the two points of this lane (one per point tile of the wave), as halo offsets of their centres
+  int hoff[2];
 #pragma unroll
-  for (int i = 0; i < PPT; ++i)
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) acc[i][j] = 0.f;
-  int px[PPT], py[PPT], pz[PPT];
-#pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    const int pidx = pg * PPT + i;
-    px[i] = pidx % TX;
-    py[i] = (pidx / TX) % TY;
-    pz[i] = pidx / (TX * TY);
+  for (int pt = 0; pt < 2; ++pt) {
+    const int p = wave * 32 + pt * 16 + ln;
+    const int px = p % TX, py = (p / TX) % TY, pz = p / (TX * TY);
+    hoff[pt] = (pz * H::Y + py) * H::X + px;
   }
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   for (int ci0 = 0; ci0 < Cin; ci0 += CIC) {
     __syncthreads();
-    for (int t = tid; t < CIC * HZ * HY * HX; t += CT) {
-      const int c = t / (HZ * HY * HX), r = t - c * (HZ * HY * HX);
-      const int hx = r % HX, hy = (r / HX) % HY, hz = r / (HX * HY);
-      float v = 0.f;
-      if (ci0 + c < Cin) {
-        const int gx = wrap(tx0 + hx - R, Ws), gy = wrap(ty0 + hy - R, Hs);
-        const int gz = (D == 3) ? wrap(tz0 + hz - R, Zs) : 0;
-        v = in[((size_t)b * inCtot + inOff + ci0 + c) * plane + ((size_t)gz * Hs + gy) * Ws + gx];
-      }
-      s_in[c][r] = v;
-    }
-    for (int t = tid; t < CIC * TAPS * COT; t += CT) {
-      const int co = t % COT, r = t / COT;
-      const int tap = r % TAPS, c = r / TAPS;
+    stage_halo<D, KS, HS>(s_in, in, Cin, inCtot, inOff, ci0, CIC, b, tx0, ty0, tz0, Zs, Hs, Ws, plane);
+    // weights w[co][ci][tap], read along (ci, tap) for coalescing
+    for (int t = tid; t < COT * CIC * TAPS; t += CT) {
+      const int tap = t % TAPS, r = t / TAPS;
+      const int c = r % CIC, co = r / CIC;
       float v = 0.f;
       if (ci0 + c < Cin && co0 + co < Cout) v = w[((size_t)(co0 + co) * Cin + ci0 + c) * TAPS + tap];
-      s_w[c][tap][co] = v;
+      s_w[(tap * CIC + c) * WST + co] = v;
     }
     __syncthreads();
 #pragma unroll 1
-    for (int c = 0; c < CIC; ++c) {
+    for (int tap = 0; tap < TAPS; ++tap) {
+      const int kx = tap % KS, ky = (tap / KS) % KS, kz = tap / (KS * KS);
+      const int toff = (kz * H::Y + ky) * H::X + kx;
 #pragma unroll
-      for (int tap = 0; tap < TAPS; ++tap) {
-        const int kx = tap % KS, ky = (tap / KS) % KS, kz = tap / (KS * KS);
-        float wv[CPT];
-#pragma unroll
-        for (int j = 0; j < CPT; ++j) wv[j] = s_w[c][tap][cg * CPT + j];
-#pragma unroll
-        for (int i = 0; i < PPT; ++i) {
-          const float v = s_in[c][((pz[i] + kz) * HY + py[i] + ky) * HX + px[i] + kx];
-#pragma unroll
-          for (int j = 0; j < CPT; ++j) acc[i][j] = fmaf(wv[j], v, acc[i][j]);
-        }
+      for (int c0 = 0; c0 < CIC; c0 += 4) {
+        const int c = c0 + lk;
+        const float* wr = s_w + (tap * CIC + c) * WST + ln;
+        const float a0 = wr[0], a1 = wr[16];
+        const float* ir = s_in + c * HS + toff;
+        const float b0 = ir[hoff[0]], b1 = ir[hoff[1]];
+        acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
       }
     }
   }
 #pragma unroll
-  for (int i = 0; i < PPT; ++i) {
-    const int gx = tx0 + px[i], gy = ty0 + py[i], gz = tz0 + pz[i];
+  for (int pt = 0; pt < 2; ++pt) {
+    const int p = wave * 32 + pt * 16 + ln;
+    const int gx = tx0 + p % TX, gy = ty0 + (p / TX) % TY, gz = tz0 + p / (TX * TY);
     if (gx >= Ws || gy >= Hs || gz >= Zs) continue;
+    const size_t q = ((size_t)gz * Hs + gy) * Ws + gx;
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-      const int co = co0 + cg * CPT + j;
-      if (co >= Cout) continue;
-      float v = acc[i][j] + (bias ? bias[co] : 0.f);
-      if (relu) v = fmaxf(v, 0.f);
-      float* o = out + ((size_t)b * outCtot + outOff + co) * plane + ((size_t)gz * Hs + gy) * Ws + gx;
-      if (accumulate) v += *o;
-      *o = v;
-    }
+    for (int ct = 0; ct < 2; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int co = co0 + ct * 16 + 4 * lk + r;
+        if (co >= Cout) continue;
+        float v = acc[ct][pt][r] + (bias ? bias[co] : 0.f);
+        if (relu) v = fmaxf(v, 0.f);
+        float* o = out + ((size_t)b * outCtot + outOff + co) * plane + q;
+        if (accumulate) v += *o;
+        *o = v;
+      }
   }
 }
 
-// Weight gradient partials: for a block of (COT output channels x CIC input
-// channels) and one chunk of points, sum over the chunk of g[co, q] in[ci, q + tap];
-// partial sums go to part[chunk][co][ci][tap] (summed in a fixed order later).
+// Weight gradient partials: dW[co][ci][tap] = sum over points q of
+// g[co, q] in[ci, q + tap], as GEMMs with M = output channels, N = input
+// channels (WCI per block), K = points, one per tap.  Block (chunk, co tile,
+// ci tile) sums the point tiles tile0 .. tile1 of the whole batch (b-major)
+// and writes part[chunk][co][ci][tap]; the chunks are summed in a fixed order
+// later.  The 2 x TAPS output tiles (co half, tap) of a block are dealt to
+// the 4 waves in turn.
 template <int D, int KS>
 __global__ __launch_bounds__(CT) void k_conv_wgrad(const float* __restrict__ in, int Cin, int inCtot, int inOff,
                                                    const float* __restrict__ g, int Cout, int gCtot, int gOff, int Zs,
-                                                   int Hs, int Ws, int B, int chunk, float* __restrict__ part) {
-  constexpr int TAPS = (D == 3) ? KS * KS * KS : KS * KS;
-  constexpr int R = KS / 2;
-  constexpr int PT = 64;  // points per LDS stage
-  __shared__ float s_g[PT][COT];
-  __shared__ float s_x[PT][CIC][TAPS];
-  const int co0 = blockIdx.y * COT;
-  const int ci0 = (blockIdx.z % ((Cin + CIC - 1) / CIC)) * CIC;
+                                                   int Hs, int Ws, int ntiles, int per_chunk, float* __restrict__ part) {
+  using H = Halo<D, KS>;
+  constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, NP = Tile<D>::NP;
+  constexpr int TAPS = H::TAPS;
+  constexpr int HS = pad_to(H::N, 2);      // channel stride: the 16 channels of a k row on even banks, the next point odd
+  constexpr int NT = 2 * TAPS;             // output tiles (co half, tap)
+  constexpr int TPW = (NT + 3) / 4;        // tiles per wave
+  __shared__ float s_in[WCI * HS];
+  __shared__ float s_g[NP * WST];          // [point][co]
+  const int co0 = blockIdx.y * COT, ci0 = blockIdx.z * WCI;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int lk = lane >> 4, ln = lane & 15;
   const size_t plane = (size_t)Zs * Hs * Ws;
-  const size_t total = (size_t)B * plane;
-  const size_t q0 = (size_t)blockIdx.x * chunk;
-  const size_t q1 = q0 + chunk < total ? q0 + chunk : total;
-  const int tid = threadIdx.x;
-  // thread -> (co, ci, tap) outputs: COT*CIC*TAPS outputs over CT threads
-  constexpr int NOUT = COT * CIC * TAPS;
-  constexpr int OPT = (NOUT + CT - 1) / CT;
-  float acc[OPT];
+  const int tiles_img = ((Ws + TX - 1) / TX) * ((Hs + TY - 1) / TY) * ((Zs + Tile<D>::Z - 1) / Tile<D>::Z);
+  v4f acc[TPW];
 #pragma unroll
-  for (int i = 0; i < OPT; ++i) acc[i] = 0.f;
-  for (size_t qs = q0; qs < q1; qs += PT) {
+  for (int i = 0; i < TPW; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int t0 = blockIdx.x * per_chunk, t1 = min(t0 + per_chunk, ntiles);
+  for (int tt = t0; tt < t1; ++tt) {
+    const int b = tt / tiles_img;
+    int tx0, ty0, tz0;
+    tile_origin<D>(tt - b * tiles_img, Hs, Ws, &tx0, &ty0, &tz0);
     __syncthreads();
-    for (int t = tid; t < PT * COT; t += CT) {
-      const int p = t / COT, co = t % COT;
-      const size_t q = qs + p;
+    stage_halo<D, KS, HS>(s_in, in, Cin, inCtot, inOff, ci0, WCI, b, tx0, ty0, tz0, Zs, Hs, Ws, plane);
+    for (int t = tid; t < COT * NP; t += CT) {
+      const int p = t % NP, co = t / NP;
+      const int gx = tx0 + p % TX, gy = ty0 + (p / TX) % TY, gz = tz0 + p / (TX * TY);
       float v = 0.f;
-      if (q < q1 && co0 + co < Cout) {
-        const size_t bb = q / plane, r = q % plane;
-        v = g[(bb * gCtot + gOff + co0 + co) * plane + r];
-      }
-      s_g[p][co] = v;
-    }
-    for (int t = tid; t < PT * CIC * TAPS; t += CT) {
-      const int p = t / (CIC * TAPS), r = t % (CIC * TAPS);
-      const int c = r / TAPS, tap = r % TAPS;
-      const size_t q = qs + p;
-      float v = 0.f;
-      if (q < q1 && ci0 + c < Cin) {
-        const size_t bb = q / plane, rr = q % plane;
-        const int x = rr % Ws, y = (rr / Ws) % Hs, z = rr / ((size_t)Ws * Hs);
-        const int kx = tap % KS, ky = (tap / KS) % KS, kz = tap / (KS * KS);
-        const int gx = wrap(x + kx - R, Ws), gy = wrap(y + ky - R, Hs), gz = (D == 3) ? wrap(z + kz - R, Zs) : 0;
-        v = in[(bb * inCtot + inOff + ci0 + c) * plane + ((size_t)gz * Hs + gy) * Ws + gx];
-      }
-      s_x[p][c][tap] = v;
+      if (co0 + co < Cout && gx < Ws && gy < Hs && gz < Zs)
+        v = g[((size_t)b * gCtot + gOff + co0 + co) * plane + ((size_t)gz * Hs + gy) * Ws + gx];
+      s_g[p * WST + co] = v;
     }
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < OPT; ++i) {
-      const int o = tid + i * CT;
-      if (o < NOUT) {
-        const int co = o / (CIC * TAPS), r = o % (CIC * TAPS);
-        const int c = r / TAPS, tap = r % TAPS;
-        float s = acc[i];
-        for (int p = 0; p < PT; ++p) s = fmaf(s_g[p][co], s_x[p][c][tap], s);
-        acc[i] = s;
+    for (int i = 0; i < TPW; ++i) {
+      const int j = wave + 4 * i;
+      if (j >= NT) break;
+      const int ct = j & 1, tap = j >> 1;
+      const int kx = tap % KS, ky = (tap / KS) % KS, kz = tap / (KS * KS);
+      const int toff = (kz * H::Y + ky) * H::X + kx;
+#pragma unroll 4
+      for (int k0 = 0; k0 < NP; k0 += 4) {
+        const int p = k0 + lk;
+        const int px = p % TX, py = (p / TX) % TY, pz = p / (TX * TY);
+        const float a = s_g[p * WST + ct * 16 + ln];
+        const float bv = s_in[ln * HS + (pz * H::Y + py) * H::X + px + toff];
+        acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[i], 0, 0, 0);
       }
     }
   }
 #pragma unroll
-  for (int i = 0; i < OPT; ++i) {
-    const int o = tid + i * CT;
-    if (o < NOUT) {
-      const int co = o / (CIC * TAPS), r = o % (CIC * TAPS);
-      const int c = r / TAPS, tap = r % TAPS;
-      if (co0 + co < Cout && ci0 + c < Cin)
-        part[(((size_t)blockIdx.x * Cout + co0 + co) * Cin + ci0 + c) * TAPS + tap] = acc[i];
+  for (int i = 0; i < TPW; ++i) {
+    const int j = wave + 4 * i;
+    if (j >= NT) break;
+    const int ct = j & 1, tap = j >> 1;
+    const int ci = ci0 + ln;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int co = co0 + ct * 16 + 4 * lk + r;
+      if (co < Cout && ci < Cin) part[(((size_t)blockIdx.x * Cout + co) * Cin + ci) * TAPS + tap] = acc[i][r];
     }
   }
 }
@@ -569,8 +606,7 @@ static size_t build_net(Net& n, char* base, size_t* nparams) {
   size_t maxw = 0;
   for (auto& c : n.convs) maxw = std::max(maxw, (size_t)c.cout * c.cin * (c.ks == 3 ? (d == 3 ? 27 : 9) : 1));
   n.wflip = take(maxw);
-  const size_t nchunk = 64;
-  n.wpart_floats = nchunk * maxw;
+  n.wpart_floats = (size_t)kWgradChunks * maxw;
   n.wpart = take(n.wpart_floats);
   n.lpart = reinterpret_cast<double*>(take(2 * 8192));
   *nparams = poff;
@@ -636,19 +672,22 @@ static hipError_t backward(Net& n) {
       hipLaunchKernelGGL(k_relu_mask, dim3(gridn(tot)), dim3(CT), 0, n.st, c.gout.p, c.out.p, c.cout, c.gout.Ctot,
                          c.gout.off, c.out.Ctot, c.out.off, pl, B);
     }
-    // weight gradient: partials over point chunks, then a fixed-order sum
-    const size_t total = (size_t)B * pl;
-    int nchunk = (int)std::min<size_t>(64, (total + 1023) / 1024);
-    if (nchunk < 1) nchunk = 1;
-    const int chunk = (int)((total + nchunk - 1) / nchunk);
+    // weight gradient: partials over chunks of point tiles, then a fixed-order sum
+    const int tiles_img = ((n.sz[l][2] + Tile<D>::X - 1) / Tile<D>::X) * ((n.sz[l][1] + Tile<D>::Y - 1) / Tile<D>::Y) *
+                          ((n.sz[l][0] + Tile<D>::Z - 1) / Tile<D>::Z);
+    const int ntiles = tiles_img * B;
+    const int nchunk = std::min(ntiles, kWgradChunks);
+    const int per_chunk = (ntiles + nchunk - 1) / nchunk;
     const size_t nw = (size_t)c.cout * c.cin * taps;
-    dim3 gw(nchunk, (c.cout + COT - 1) / COT, (c.cin + CIC - 1) / CIC);
+    dim3 gw(nchunk, (c.cout + COT - 1) / COT, (c.cin + WCI - 1) / WCI);
     if (c.ks == 3)
       hipLaunchKernelGGL((k_conv_wgrad<D, 3>), gw, dim3(CT), 0, n.st, c.in.p, c.cin, c.in.Ctot, c.in.off, c.gout.p,
-                         c.cout, c.gout.Ctot, c.gout.off, n.sz[l][0], n.sz[l][1], n.sz[l][2], B, chunk, n.wpart);
+                         c.cout, c.gout.Ctot, c.gout.off, n.sz[l][0], n.sz[l][1], n.sz[l][2], ntiles, per_chunk,
+                         n.wpart);
     else
       hipLaunchKernelGGL((k_conv_wgrad<D, 1>), gw, dim3(CT), 0, n.st, c.in.p, c.cin, c.in.Ctot, c.in.off, c.gout.p,
-                         c.cout, c.gout.Ctot, c.gout.off, n.sz[l][0], n.sz[l][1], n.sz[l][2], B, chunk, n.wpart);
+                         c.cout, c.gout.Ctot, c.gout.off, n.sz[l][0], n.sz[l][1], n.sz[l][2], ntiles, per_chunk,
+                         n.wpart);
     hipLaunchKernelGGL(k_reduce_chunks, dim3(gridn(nw)), dim3(CT), 0, n.st, n.wpart, nchunk, nw, n.grads + c.w);
     hipLaunchKernelGGL(k_bias_grad, dim3(c.cout), dim3(CT), 0, n.st, c.gout.p, c.cout, c.gout.Ctot, c.gout.off, pl, B,
                        n.grads + c.b);
