@@ -377,15 +377,16 @@ hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const doub
 /* Primal and dual solves of the same nload loads for every problem, side by
  * side: the dual runs on a stream of the library (default priority), so the
  * kernels of the two solves share the GPU.  Same results as hom_batch_solve
- * with dual = 0 and dual = 1 (no initial guesses); x_primal, x_dual and the
- * info arrays as there.  Synchronises the caller's stream on entry and both
+ * with dual = 0 and dual = 1; x0_primal, x0_dual (each NULL or as x0 there:
+ * re-projected starting fields), x_primal, x_dual and the info arrays as
+ * there.  Synchronises the caller's stream on entry and both
  * streams on return.  With per-kernel timing on, the two solves advance one
  * chunk of iterations each in turn.  Under the gap rule (stop rule 3) each
  * load of one solve reads the same load of the other at the end of the
  * previous chunk, so the two advance in chunk lockstep (cross-stream waits). */
-hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, double tol, int32_t maxit,
-                                double* const* x_primal, double* const* x_dual, hom_info* info_primal,
-                                hom_info* info_dual);
+hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, const double* const* x0_primal,
+                                const double* const* x0_dual, double tol, int32_t maxit, double* const* x_primal,
+                                double* const* x_dual, hom_info* info_primal, hom_info* info_dual);
 
 /* hom_update_coefficients for every problem of the batch (Ahat[i], Bhat[i]
  * for problem i, same layout and ownership; host arrays of n device
@@ -571,6 +572,21 @@ hom_status hom_grid_to_field(hom_problem* pb, int32_t dual, int32_t nload, const
  * coefficient on the doubled grid and <a> its mean.  out: device. */
 hom_status hom_net_input(hom_problem* pb, float* out);
 
+/* The three transfers above for every problem of a batch at once (one launch
+ * per pass covers all cells), on the batch's stream.  Cell i's grid block
+ * starts at in / out + i * stride floats (stride >= nload d M^d, or 2 M^d
+ * for the network inputs, so that a cell's block may sit inside a larger
+ * sample record); fields / out: host arrays of n * nload device pointers,
+ * problem-major.  hom_batch_field_to_grid and hom_batch_grid_to_field
+ * synchronise the stream (their unit table is reused); hom_batch_net_input
+ * writes the input channels (weights = 0) or the energy weights (weights = 1)
+ * of every cell and returns without synchronising. */
+hom_status hom_batch_field_to_grid(hom_batch* b, int32_t dual, int32_t nload, const double* const* fields, float* out,
+                                   size_t stride);
+hom_status hom_batch_grid_to_field(hom_batch* b, int32_t dual, int32_t nload, const float* in, size_t stride,
+                                   double* const* out);
+hom_status hom_batch_net_input(hom_batch* b, float* out, size_t stride, int32_t weights);
+
 /* Pointwise energy weights on the doubled grid, FP32 [2][M^d]: channel 0
  * max(a, 1e-3 <a>)/<a> for a = trace(A_M)/d (primal), channel 1 the same for
  * b = trace((A^-1)_M)/d (dual): the weights of the double-grid quadrature of
@@ -598,8 +614,15 @@ hom_status hom_unet_sizes(const hom_unet_desc* desc, size_t* n_params, size_t* w
  * owned; params initialised by the caller).  work: device, 256-byte aligned. */
 hom_status hom_unet_create(const hom_unet_desc* desc, float* params, float* grads, float* adam_m, float* adam_v,
                            void* work, size_t work_bytes, void* stream, hom_unet** out);
-/* in: device [batch][cin][size]; out: device [batch][cout][size] or NULL. */
+/* in: device [batch][cin][size]; out: device [batch][cout][size] or NULL.
+ * With a stream the forward kernels are captured into a HIP graph on the
+ * first call and replayed after (the input is copied into the network's own
+ * buffer first, so the graph serves every input). */
 hom_status hom_unet_forward(hom_unet* u, const float* in, float* out);
+/* The same with the batch's samples gathered from `batch` device pointers
+ * (host array), each [cin][size]: a minibatch of stored samples without a
+ * separate gather. */
+hom_status hom_unet_forward_samples(hom_unet* u, const float* const* in, float* out);
 /* Mean squared error of the last forward output against target (device); sets
  * the output gradient; *loss on the host (synchronises the stream). */
 hom_status hom_unet_loss(hom_unet* u, const float* target, double* loss);
@@ -610,6 +633,10 @@ hom_status hom_unet_loss(hom_unet* u, const float* target, double* loss);
  * norm of the field error. */
 hom_status hom_unet_loss_weighted(hom_unet* u, const float* target, const float* weight, int32_t wch,
                                   double* loss);
+/* hom_unet_loss_weighted with the targets ([cout][size] each) and the weights
+ * ([wch][size] each, or NULL) gathered from `batch` device pointers (host arrays). */
+hom_status hom_unet_loss_samples(hom_unet* u, const float* const* target, const float* const* weight, int32_t wch,
+                                 double* loss);
 /* Parameter gradients of the last forward pass for the output gradient gout
  * (device) or, when gout is NULL, the gradient set by hom_unet_loss. */
 hom_status hom_unet_backward(hom_unet* u, const float* gout);

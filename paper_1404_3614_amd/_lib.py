@@ -52,6 +52,11 @@ EXPORTS = {
                                          C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
     "hom_group_destroy": (None, [C.c_void_p]),
     "hom_group_set_launch": (C.c_int32, [C.c_void_p, C.c_int32]),
+    "hom_batch_field_to_grid": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p,
+                                            C.c_size_t]),
+    "hom_batch_grid_to_field": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_size_t,
+                                            C.POINTER(C.c_void_p)]),
+    "hom_batch_net_input": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int32]),
     "hom_tune_cache_load": (C.c_int32, [C.c_char_p, C.c_char_p, C.POINTER(C.c_int32)]),
     "hom_tune_cache_save": (C.c_int32, [C.c_char_p, C.c_char_p]),
     "hom_tune_cache_clear": (C.c_int32, []),
@@ -91,6 +96,9 @@ EXPORTS = {
     "hom_unet_create": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
                                     C.c_size_t, C.c_void_p, C.POINTER(C.c_void_p)]),
     "hom_unet_forward": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hom_unet_forward_samples": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.c_void_p]),
+    "hom_unet_loss_samples": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_int32,
+                                          C.POINTER(C.c_double)]),
     "hom_unet_loss": (C.c_int32, [C.c_void_p, C.c_void_p, C.POINTER(C.c_double)]),
     "hom_unet_loss_weighted": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.POINTER(C.c_double)]),
     "hom_unet_backward": (C.c_int32, [C.c_void_p, C.c_void_p]),
@@ -124,9 +132,9 @@ EXPORTS = {
     "hom_gani_matrices": (C.c_int32, [C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                       C.POINTER(C.c_double)]),
     "hom_batch_set_stop": (C.c_int32, [C.c_void_p, C.c_int32, C.c_double, C.c_double, C.c_double]),
-    "hom_batch_solve_pair": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.c_double, C.c_int32,
-                                         C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.POINTER(Info),
-                                         C.POINTER(Info)]),
+    "hom_batch_solve_pair": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_void_p),
+                                         C.POINTER(C.c_void_p), C.c_double, C.c_int32, C.POINTER(C.c_void_p),
+                                         C.POINTER(C.c_void_p), C.POINTER(Info), C.POINTER(Info)]),
     "hom_batch_update_coefficients": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "hom_problem_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
     "hom_batch_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Tuning)]),

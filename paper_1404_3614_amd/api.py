@@ -585,6 +585,43 @@ class Batch:
                 "hom_batch_profile_passes")
         return dict(first=ms[0], mid_inv=ms[1], apply=ms[2], mid_fwd=ms[3], last=ms[4])
 
+    def field_to_grid(self, fields, dual, out, stride=None):
+        """Doubled-grid values (FP32) of fields [[d tensors] per problem] into out, cell i's
+        [nload][d][*M] block at float offset i * stride (hom_batch_field_to_grid)."""
+        nl = len(fields[0])
+        Mt = int(np.prod(self.problems[0].M))
+        stride = nl * self.d * Mt if stride is None else int(stride)
+        flat = [t for ts in fields for t in ts]
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_batch_field_to_grid(self.h, int(dual), nl, _dptrs(flat), C.c_void_p(out.data_ptr()),
+                                                 stride), "hom_batch_field_to_grid")
+        return out
+
+    def grid_to_field(self, grids, dual, nload=None, stride=None):
+        """Admissible fields (projected on E_N / J_N) of every problem from doubled-grid
+        fields, cell i's [nload][d][*M] block at float offset i * stride of the tensor
+        `grids` (hom_batch_grid_to_field); returns [[nload tensors] per problem]."""
+        nl = self.d if nload is None else nload
+        Mt = int(np.prod(self.problems[0].M))
+        stride = nl * self.d * Mt if stride is None else int(stride)
+        out = [[p.new_field(dual) for _ in range(nl)] for p in self.problems]
+        flat = [t for ts in out for t in ts]
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_batch_grid_to_field(self.h, int(dual), nl, C.c_void_p(grids.data_ptr()), stride,
+                                                 _dptrs(flat)), "hom_batch_grid_to_field")
+        return out
+
+    def net_input(self, out, stride=None, weights=False):
+        """Network input channels (or energy weights) [2][*M] of every problem into out,
+        cell i's block at float offset i * stride (hom_batch_net_input)."""
+        Mt = int(np.prod(self.problems[0].M))
+        stride = 2 * Mt if stride is None else int(stride)
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_batch_net_input(self.h, C.c_void_p(out.data_ptr()), stride, int(bool(weights))),
+                "hom_batch_net_input")
+        torch.cuda.current_stream().wait_stream(self.stream)
+        return out
+
     def update_coefficients(self, coefs):
         """New coefficients [(Ahat, Bhat)] for every problem of the batch (hom_batch_update_coefficients)."""
         n = len(self.problems)
@@ -604,8 +641,10 @@ class Batch:
             cache[key] = [[p.new_field(dual) for _ in range(nl)] for p in self.problems]
         return cache[key]
 
-    def solve_pair(self, E=None, tol=1e-6, maxit=10000, out_primal=None, out_dual=None, allow_not_converged=False):
-        """Primal and dual solves of the same loads side by side (hom_batch_solve_pair)."""
+    def solve_pair(self, E=None, tol=1e-6, maxit=10000, out_primal=None, out_dual=None, allow_not_converged=False,
+                   x0_primal=None, x0_dual=None):
+        """Primal and dual solves of the same loads side by side (hom_batch_solve_pair);
+        x0_primal / x0_dual: optional starting fields [[nload tensors] per problem]."""
         d, n = self.d, len(self.problems)
         E = np.eye(d) if E is None else np.atleast_2d(np.asarray(E, float))
         nl = E.shape[0]
@@ -614,8 +653,10 @@ class Batch:
         ip, idl = (L.Info * (n * nl))(), (L.Info * (n * nl))()
         Ec = np.ascontiguousarray(E.reshape(-1))
         self.stream.wait_stream(torch.cuda.current_stream())
-        st = L.load().hom_batch_solve_pair(self.h, nl, Ec.ctypes.data_as(C.POINTER(C.c_double)), float(tol),
-                                           int(maxit), _dptrs([t for ts in fp for t in ts]),
+        x0p = _dptrs([t for ts in x0_primal for t in ts]) if x0_primal is not None else None
+        x0d = _dptrs([t for ts in x0_dual for t in ts]) if x0_dual is not None else None
+        st = L.load().hom_batch_solve_pair(self.h, nl, Ec.ctypes.data_as(C.POINTER(C.c_double)), x0p, x0d,
+                                           float(tol), int(maxit), _dptrs([t for ts in fp for t in ts]),
                                            _dptrs([t for ts in fd for t in ts]), ip, idl)
         L.check(st, "hom_batch_solve_pair", allow_not_converged)
         conv = lambda infos: [[dict(iters=infos[i * nl + l].iters, status=infos[i * nl + l].status,
@@ -625,13 +666,14 @@ class Batch:
                               for i in range(n)]
         return fp, conv(ip), fd, conv(idl)
 
-    def solve_bounds(self, tol=1e-6, maxit=10000, allow_not_converged=False):
-        """Primal and dual solves of the unit loads (side by side) and the bounds of every
-        problem.  The fields live in buffers owned by the batch and are overwritten by the
-        next call."""
+    def solve_bounds(self, tol=1e-6, maxit=10000, allow_not_converged=False, x0_primal=None, x0_dual=None):
+        """Primal and dual solves of the unit loads (side by side, optionally from starting
+        fields) and the bounds of every problem.  The fields live in buffers owned by the
+        batch and are overwritten by the next call."""
         d = self.d
         xp, ip, xd, idl = self.solve_pair(tol=tol, maxit=maxit, out_primal=self._fields(False, d),
-                                          out_dual=self._fields(True, d), allow_not_converged=allow_not_converged)
+                                          out_dual=self._fields(True, d), allow_not_converged=allow_not_converged,
+                                          x0_primal=x0_primal, x0_dual=x0_dual)
         out = self.bounds(xp, xd)
         for i, b in enumerate(out):
             b.update(info_primal=ip[i], info_dual=idl[i])

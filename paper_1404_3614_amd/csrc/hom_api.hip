@@ -2239,9 +2239,9 @@ hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const doub
   return solve_units(R, nload, tol, maxit, have_x0, info);
 }
 
-hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, double tol, int32_t maxit,
-                                double* const* x_primal, double* const* x_dual, hom_info* info_primal,
-                                hom_info* info_dual) {
+hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, const double* const* x0_primal,
+                                const double* const* x0_dual, double tol, int32_t maxit, double* const* x_primal,
+                                double* const* x_dual, hom_info* info_primal, hom_info* info_dual) {
   if (!b || !info_primal || !info_dual || !x_primal || !x_dual) return HOM_E_INVALID;
   if (batch_has_gani(b)) return HOM_E_INVALID;
   const int n = b->n;
@@ -2267,13 +2267,27 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, do
       b->tuned[k][nload] = true;
     }
   SolveRun R[2];
+  bool have_x0[2] = {false, false};
   for (int k = 0; k < 2; ++k) {
     double* const* xo = k == 0 ? x_primal : x_dual;
+    const double* const* x0 = k == 0 ? x0_primal : x0_dual;
+    const Geo gk = make_geo(p0, k, nload, fp32, 0, &b->tune[k][nload]);
     for (int i = 0; i < n; ++i) {
       fill_unit(b->pbs[i], k, nload, E, xo + (size_t)i * nload, &b->host_units[k][i]);
       // gap rule: each load reads the same load of the other solve of its cell
       if (gap_rule) b->host_units[k][i].partner_sc = b->pbs[i]->slot[1 - k].sc;
+      if (x0) {
+        bool h = false;
+        hom_status s = prepare_x0(b->pbs[i], k, nload, gk, x0 + (size_t)i * nload, xo + (size_t)i * nload, &h);
+        if (s != HOM_OK) return s;
+        have_x0[k] = have_x0[k] || h;
+      }
     }
+    if (have_x0[k])
+      for (int i = 0; i < n; ++i) {
+        hom_status s = zero_missing_x0(b->pbs[i], k, nload, gk, x0 + (size_t)i * nload, xo + (size_t)i * nload);
+        if (s != HOM_OK) return s;
+      }
     HIPCHK(hipMemcpyAsync(b->units[k], b->host_units[k].data(), (size_t)n * sizeof(UnitDev), hipMemcpyHostToDevice,
                           b->stream));
     R[k].st = st[k];
@@ -2308,7 +2322,7 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, do
   HIPCHK(hipEventRecord(b->order_ev, b->stream));
   HIPCHK(hipStreamWaitEvent(b->stream2, b->order_ev, 0));
   hom_status s = HOM_OK;
-  for (int k = 0; k < 2 && s == HOM_OK; ++k) s = start_run(R[k], nload, tol, maxit, false);
+  for (int k = 0; k < 2 && s == HOM_OK; ++k) s = start_run(R[k], nload, tol, maxit, have_x0[k]);
   if (s != HOM_OK) return s;
   SolveRun* runs[2] = {&R[0], &R[1]};
   const int partners[2] = {1, 0};
@@ -2324,6 +2338,84 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, do
   if (s0 < 0) return s0;
   if (s1 < 0) return s1;
   return s0 != HOM_OK ? s0 : s1;
+}
+
+// ---- grid transfers and network inputs of every problem of a batch (one launch per pass)
+
+// Units of the bound-evaluation buffers of every problem, with grid[i] = base + i * stride.
+static hom_status batch_grid_units(hom_batch* b, int k, int nload, float* base, size_t stride) {
+  for (int i = 0; i < b->n; ++i) {
+    grid_unit(b->pbs[i], k, nload, &b->host_bunits[k][i]);
+    b->host_bunits[k][i].grid = base + (size_t)i * stride;
+  }
+  return HOM_OK;
+}
+
+hom_status hom_batch_field_to_grid(hom_batch* b, int32_t dual, int32_t nload, const double* const* fields, float* out,
+                                   size_t stride) {
+  if (!b || !fields || !out || (dual != 0 && dual != 1)) return HOM_E_INVALID;
+  hom_problem* p0 = b->pbs[0];
+  if (nload < 1 || nload > p0->max_loads) return HOM_E_INVALID;
+  if (stride < (size_t)nload * p0->z.d * p0->z.Mt) return HOM_E_INVALID;
+  for (size_t i = 0; i < (size_t)b->n * nload; ++i)
+    if (!fields[i]) return HOM_E_INVALID;
+  const int k = dual;
+  hipStream_t st = b->stream;
+  Geo g = make_geo(p0, k, nload, false);
+  batch_grid_units(b, k, nload, out, stride);
+  for (int i = 0; i < b->n; ++i)
+    for (int l = 0; l < nload; ++l)
+      b->host_bunits[k][i].x[l] = reinterpret_cast<Cx<double>*>(const_cast<double*>(fields[(size_t)i * nload + l]));
+  HIPCHK(hipMemcpyAsync(b->bunits[k], b->host_bunits[k].data(), (size_t)b->n * sizeof(UnitDev), hipMemcpyHostToDevice,
+                        st));
+  HIPCHK(launch_first<double>(g, b->bunits[k], b->n, FIRST_FIELD, 0, nullptr, st));
+  if (g.d == 3) HIPCHK(launch_mid<double>(g, b->bunits[k], b->n, 1, st));
+  HIPCHK(launch_apply<double>(g, b->bunits[k], b->n, APPLY_GRID, st));
+  HIPCHK(hipStreamSynchronize(st));   // the host unit table is reused by the next call
+  return HOM_OK;
+}
+
+hom_status hom_batch_grid_to_field(hom_batch* b, int32_t dual, int32_t nload, const float* in, size_t stride,
+                                   double* const* out) {
+  if (!b || !in || !out || (dual != 0 && dual != 1)) return HOM_E_INVALID;
+  hom_problem* p0 = b->pbs[0];
+  if (nload < 1 || nload > p0->max_loads) return HOM_E_INVALID;
+  if (stride < (size_t)nload * p0->z.d * p0->z.Mt) return HOM_E_INVALID;
+  for (size_t i = 0; i < (size_t)b->n * nload; ++i)
+    if (!out[i]) return HOM_E_INVALID;
+  const int k = dual;
+  hipStream_t st = b->stream;
+  Geo g = make_geo(p0, k, nload, false);
+  batch_grid_units(b, k, nload, const_cast<float*>(in), stride);
+  for (int i = 0; i < b->n; ++i)
+    for (int l = 0; l < nload; ++l)
+      b->host_bunits[k][i].s[l] = reinterpret_cast<Cx<double>*>(out[(size_t)i * nload + l]);
+  HIPCHK(hipMemcpyAsync(b->bunits[k], b->host_bunits[k].data(), (size_t)b->n * sizeof(UnitDev), hipMemcpyHostToDevice,
+                        st));
+  HIPCHK(launch_apply<double>(g, b->bunits[k], b->n, APPLY_FWD, st));
+  if (g.d == 3) HIPCHK(launch_mid<double>(g, b->bunits[k], b->n, 0, st));
+  HIPCHK(launch_last<double>(g, b->bunits[k], b->n, LAST_MATVEC, 0, nullptr, st));
+  HIPCHK(hipStreamSynchronize(st));   // the host unit table is reused by the next call
+  return HOM_OK;
+}
+
+hom_status hom_batch_net_input(hom_batch* b, float* out, size_t stride, int32_t weights) {
+  if (!b || !out || (weights != 0 && weights != 1)) return HOM_E_INVALID;
+  const size_t Mt = b->pbs[0]->z.Mt;
+  if (stride < 2 * Mt) return HOM_E_INVALID;
+  for (int i = 0; i < b->n; ++i) {
+    hom_problem* pb = b->pbs[i];
+    float* o = out + (size_t)i * stride;
+    if (!weights) {
+      HIPCHK(launch_net_input(pb->coef64[0], pb->z.nc, pb->z.d, (long)Mt, pb->ahat_half[0], (long)pb->z.S, o, 0,
+                              b->stream));
+    } else {
+      for (int k = 0; k < 2; ++k)
+        HIPCHK(launch_net_input(pb->coef64[k], pb->z.nc, pb->z.d, (long)Mt, pb->ahat_half[k], (long)pb->z.S,
+                                o + (size_t)k * Mt, 1, b->stream));
+    }
+  }
+  return HOM_OK;
 }
 
 // ---- groups: the primal and dual solves of several batches in one captured graph

@@ -481,6 +481,8 @@ struct Net {
   float* gout;          // gradient of the output
   float* wflip;         // flipped weights scratch
   float* wpart;         // weight-gradient partials
+  float* tgt;           // loss targets gathered from sample pointers [batch][cout][plane]
+  float* wgt;           // loss weights gathered from sample pointers [batch][cout][plane]
   size_t wpart_floats;
   double* lpart;        // loss partials
   std::vector<float*> act_bufs;
@@ -608,6 +610,8 @@ static size_t build_net(Net& n, char* base, size_t* nparams) {
   n.wflip = take(maxw);
   n.wpart_floats = (size_t)kWgradChunks * maxw;
   n.wpart = take(n.wpart_floats);
+  n.tgt = take((size_t)B * ds.cout * plane(n, 0));
+  n.wgt = take((size_t)B * ds.cout * plane(n, 0));
   n.lpart = reinterpret_cast<double*>(take(2 * 8192));
   *nparams = poff;
   return off;
@@ -726,6 +730,10 @@ using hom::cnn::Net;
 
 struct hom_unet {
   Net net;
+  hipGraphExec_t fwd_graph = nullptr;   // the forward kernels, captured on the first forward of a stream
+  ~hom_unet() {
+    if (fwd_graph) (void)hipGraphExecDestroy(fwd_graph);
+  }
 };
 
 namespace {
@@ -781,14 +789,70 @@ hom_status hom_unet_create(const hom_unet_desc* desc, float* params, float* grad
   return HOM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+// The forward kernels from the network's own input copy: replayed from a
+// graph captured on the first call (a stream is needed), direct otherwise.
+hom_status run_forward(hom_unet* u) {
+  Net& n = u->net;
+  if (!n.st) {
+    hipError_t e = n.desc.d == 3 ? hom::cnn::forward<3>(n) : hom::cnn::forward<2>(n);
+    return e == hipSuccess ? HOM_OK : HOM_E_DEVICE;
+  }
+  if (!u->fwd_graph) {
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(n.st, hipStreamCaptureModeThreadLocal) != hipSuccess) return HOM_E_DEVICE;
+    hipError_t e = n.desc.d == 3 ? hom::cnn::forward<3>(n) : hom::cnn::forward<2>(n);
+    hipError_t e2 = hipStreamEndCapture(n.st, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return HOM_E_DEVICE;
+    }
+    e = hipGraphInstantiate(&u->fwd_graph, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return HOM_E_DEVICE;
+  }
+  return hipGraphLaunch(u->fwd_graph, n.st) == hipSuccess ? HOM_OK : HOM_E_DEVICE;
+}
+
+// Copies of `count` samples of `each` floats from sample pointers into dst (device to device).
+hom_status gather(float* dst, const float* const* src, int count, size_t each, hipStream_t st) {
+  for (int i = 0; i < count; ++i) {
+    if (!src[i]) return HOM_E_INVALID;
+    if (hipMemcpyAsync(dst + (size_t)i * each, src[i], each * sizeof(float), hipMemcpyDeviceToDevice, st) !=
+        hipSuccess)
+      return HOM_E_DEVICE;
+  }
+  return HOM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+hom_status hom_unet_forward_samples(hom_unet* u, const float* const* in, float* out) {
+  if (!u || !in) return HOM_E_INVALID;
+  Net& n = u->net;
+  hom_status s = gather(n.in0, in, n.desc.batch, (size_t)n.desc.cin * hom::cnn::plane(n, 0), n.st);
+  if (s != HOM_OK) return s;
+  s = run_forward(u);
+  if (s != HOM_OK) return s;
+  if (out) {
+    const size_t no = (size_t)n.desc.batch * n.desc.cout * hom::cnn::plane(n, 0);
+    if (hipMemcpyAsync(out, n.out, no * sizeof(float), hipMemcpyDeviceToDevice, n.st) != hipSuccess)
+      return HOM_E_DEVICE;
+  }
+  return HOM_OK;
+}
+
 hom_status hom_unet_forward(hom_unet* u, const float* in, float* out) {
   if (!u || !in) return HOM_E_INVALID;
   Net& n = u->net;
   const size_t nin = (size_t)n.desc.batch * n.desc.cin * hom::cnn::plane(n, 0);
   if (hipMemcpyAsync(n.in0, in, nin * sizeof(float), hipMemcpyDeviceToDevice, n.st) != hipSuccess)
     return HOM_E_DEVICE;
-  hipError_t e = n.desc.d == 3 ? hom::cnn::forward<3>(n) : hom::cnn::forward<2>(n);
-  if (e != hipSuccess) return HOM_E_DEVICE;
+  hom_status s = run_forward(u);
+  if (s != HOM_OK) return s;
   if (out) {
     const size_t no = (size_t)n.desc.batch * n.desc.cout * hom::cnn::plane(n, 0);
     if (hipMemcpyAsync(out, n.out, no * sizeof(float), hipMemcpyDeviceToDevice, n.st) != hipSuccess)
@@ -820,6 +884,18 @@ hom_status hom_unet_loss_weighted(hom_unet* u, const float* target, const float*
 
 hom_status hom_unet_loss(hom_unet* u, const float* target, double* loss) {
   return hom_unet_loss_weighted(u, target, nullptr, 1, loss);
+}
+
+hom_status hom_unet_loss_samples(hom_unet* u, const float* const* target, const float* const* weight, int32_t wch,
+                                 double* loss) {
+  if (!u || !target || !loss) return HOM_E_INVALID;
+  Net& n = u->net;
+  if (weight && (wch < 1 || wch > n.desc.cout || n.desc.cout % wch != 0)) return HOM_E_INVALID;
+  const size_t pl = hom::cnn::plane(n, 0);
+  hom_status s = gather(n.tgt, target, n.desc.batch, (size_t)n.desc.cout * pl, n.st);
+  if (s == HOM_OK && weight) s = gather(n.wgt, weight, n.desc.batch, (size_t)wch * pl, n.st);
+  if (s != HOM_OK) return s;
+  return hom_unet_loss_weighted(u, n.tgt, weight ? n.wgt : nullptr, wch, loss);
 }
 
 hom_status hom_unet_backward(hom_unet* u, const float* gout) {

@@ -99,15 +99,27 @@ class UNet:
     def set_params(self, theta):
         self.params.copy_(theta.to(self.params.device, torch.float32))
 
-    def forward(self, x):
-        """x: [batch, cin, *size] float32 on the device -> [batch, cout, *size]."""
+    def forward(self, x, out=None):
+        """x: [batch, cin, *size] float32 on the device -> [batch, cout, *size] (out, or the
+        network's output tensor)."""
         x = x.contiguous()
         assert tuple(x.shape) == (self.batch, self.cin) + self.size
+        o = self.out if out is None else out
         self.stream.wait_stream(torch.cuda.current_stream())
-        L.check(L.load().hom_unet_forward(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(self.out.data_ptr())),
+        L.check(L.load().hom_unet_forward(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(o.data_ptr())),
                 "hom_unet_forward")
         torch.cuda.current_stream().wait_stream(self.stream)
-        return self.out
+        return o
+
+    def forward_samples(self, X, idx, out=None):
+        """Forward of the samples X[idx] (X: [n, cin, *size], contiguous) without a
+        separate gather (hom_unet_forward_samples)."""
+        o = self.out if out is None else out
+        self.stream.wait_stream(torch.cuda.current_stream())
+        L.check(L.load().hom_unet_forward_samples(self.h, sample_ptrs(X, idx), C.c_void_p(o.data_ptr())),
+                "hom_unet_forward_samples")
+        torch.cuda.current_stream().wait_stream(self.stream)
+        return o
 
     def loss(self, target, weight=None):
         """(Weighted) mean squared error of the last output; weight [batch][wch][*size] or None."""
@@ -121,6 +133,16 @@ class UNet:
             L.check(L.load().hom_unet_loss_weighted(self.h, C.c_void_p(target.data_ptr()),
                                                     C.c_void_p(weight.data_ptr()), int(weight.shape[1]),
                                                     C.byref(val)), "hom_unet_loss_weighted")
+        return val.value
+
+    def loss_samples(self, Y, idx, W=None):
+        """Loss of the last output against the samples Y[idx] (and weights W[idx])
+        without a separate gather (hom_unet_loss_samples)."""
+        val = C.c_double()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        wp = sample_ptrs(W, idx) if W is not None else None
+        L.check(L.load().hom_unet_loss_samples(self.h, sample_ptrs(Y, idx), wp, 1 if W is None else int(W.shape[1]),
+                                               C.byref(val)), "hom_unet_loss_samples")
         return val.value
 
     def backward(self, gout=None):
@@ -147,60 +169,115 @@ class UNet:
 
 
 # ---------------------------------------------------------------- data and training
-def solver_samples(cells, N, tol=1e-6, precision="mixed", chunk=64, stream=None):
-    """Network inputs and targets from solver fields for cells of one size class
-    (same d, N and cell size, isotropic or not alike).
+def sample_ptrs(T, idx):
+    """Device pointers of the samples T[i], i in idx (T contiguous, sample-major)."""
+    assert T.is_contiguous()
+    step = T[0].numel() * T.element_size()
+    base = T.data_ptr()
+    return (C.c_void_p * len(idx))(*[base + int(i) * step for i in idx])
 
-    The cells are solved in lockstep batches of up to `chunk`, the problem
-    handles of a batch being re-used through new coefficients.  Returns
-    (inputs [n, 2, *M], targets [n, 2 d^2, *M], energy weights [n, 2, *M],
-    iterations [n, 2 d])."""
+
+def _class_batch(cells, N, precision, stream):
+    d = cells[0].d
+    nc = max(api.cell_ncoef(c) for c in cells)
+    coefs = [api.coef_from_cell(c, N, ncoef=nc, stream=stream)[:2] for c in cells]
+    probs = [api.Problem(d, N, cells[0].Y, Ah, Bh, precision=precision, ncoef=nc, stream=stream)
+             for Ah, Bh in coefs]
+    return probs, api.Batch(probs), nc
+
+
+def solver_samples(cells, N, tol=1e-6, precision="mixed", chunk=64, stream=None, targets="grid"):
+    """Network inputs and targets from solver fields for cells of one size class
+    (same d, N and cell size).
+
+    The cells are solved in lockstep batches of up to `chunk` (primal and dual side
+    by side), the problem handles of a batch being re-used through new
+    coefficients; inputs and targets of a batch are written by one call each.
+    Returns (inputs [n, 2, *M], targets, energy weights [n, 2, *M], iterations
+    [n, 2 d]).  targets = "grid": the fields on the doubled grid [n, 2 d^2, *M]
+    (primal loads then dual loads); targets = "spectra": the solver fields
+    themselves, a pair of complex tensors [n, d, len] (primal, dual), to be
+    brought to the grid per minibatch (grid_targets) where the grids of every
+    sample would not fit."""
     d = cells[0].d
     N = tuple(int(n) for n in (N if np.iterable(N) else [N] * d))
     M = tuple(2 * n - 1 for n in N)
+    Mt = int(np.prod(M))
     stream = stream if stream is not None else torch.cuda.Stream()
     n = len(cells)
-    X = torch.empty((n, 2) + M, dtype=torch.float32, device=api._dev())
-    Yt = torch.empty((n, 2 * d * d) + M, dtype=torch.float32, device=api._dev())
-    W = torch.empty((n, 2) + M, dtype=torch.float32, device=api._dev())
+    dev = api._dev()
+    X = torch.empty((n, 2) + M, dtype=torch.float32, device=dev)
+    W = torch.empty((n, 2) + M, dtype=torch.float32, device=dev)
+    if targets == "grid":
+        Yt = torch.empty((n, 2 * d * d) + M, dtype=torch.float32, device=dev)
+    else:
+        fl = [api.field_len(d, N, k, cells[0].Y) for k in (0, 1)]
+        Yt = (torch.empty((n, d, fl[0]), dtype=torch.complex128, device=dev),
+              torch.empty((n, d, fl[1]), dtype=torch.complex128, device=dev))
     iters = np.zeros((n, 2 * d), dtype=np.int64)
-    probs, batch, nc0 = None, None, None
+    probs = batch = None
+    nc0 = None
     for i0 in range(0, n, chunk):
         part = cells[i0:i0 + chunk]
         nc = max(api.cell_ncoef(c) for c in part)
-        coefs = [api.coef_from_cell(c, N, ncoef=nc, stream=stream)[:2] for c in part]
         if probs is None or len(probs) != len(part) or nc != nc0:
-            probs = [api.Problem(d, N, part[0].Y, Ah, Bh, precision=precision, ncoef=nc, stream=stream)
-                     for Ah, Bh in coefs]
-            batch, nc0 = api.Batch(probs), nc
+            probs, batch, nc0 = _class_batch(part, N, precision, stream)
         else:
-            for p, (Ah, Bh) in zip(probs, coefs):
-                p.update_coefficients(Ah, Bh)
-        xp, ip = batch.solve(False, tol=tol)
-        xd, idl = batch.solve(True, tol=tol)
-        for j, p in enumerate(probs):
-            p.net_input(out=X[i0 + j])
-            p.net_weights(out=W[i0 + j])
-            Yt[i0 + j, :d * d] = p.field_to_grid(xp[j], dual=False).reshape((d * d,) + M)
-            Yt[i0 + j, d * d:] = p.field_to_grid(xd[j], dual=True).reshape((d * d,) + M)
-            iters[i0 + j] = [r["iters"] for r in ip[j] + idl[j]]
-        torch.cuda.synchronize()
+            batch.update_coefficients([api.coef_from_cell(c, N, ncoef=nc, stream=stream)[:2] for c in part])
+        if targets == "grid":
+            xp, ip, xd, idl = batch.solve_pair(tol=tol)
+        else:
+            m = len(part)
+            out_p = [[Yt[0][i0 + j, a] for a in range(d)] for j in range(m)]
+            out_d = [[Yt[1][i0 + j, a] for a in range(d)] for j in range(m)]
+            xp, ip, xd, idl = batch.solve_pair(tol=tol, out_primal=out_p, out_dual=out_d)
+        batch.net_input(X[i0:])
+        batch.net_input(W[i0:], weights=True)
+        if targets == "grid":
+            stride = 2 * d * d * Mt
+            batch.field_to_grid(xp, False, Yt[i0:], stride)
+            batch.field_to_grid(xd, True, Yt[i0:, d * d:], stride)
+        iters[i0:i0 + len(part)] = [[r["iters"] for r in a + b] for a, b in zip(ip, idl)]
+    torch.cuda.synchronize()
     return X, Yt, W, iters
 
 
-def train(net, X, Y, steps, lr=1e-3, seed=0, log_every=0, lr_final=None, W=None):
+def grid_targets(geo, spectra, idx, out):
+    """Targets [len(idx), 2 d^2, *M] of stored solver fields (solver_samples with
+    targets="spectra") on the doubled grid; geo: a Batch of len(idx) problems of
+    the class (only its geometry is used)."""
+    d = geo.d
+    Mt = int(np.prod(geo.problems[0].M))
+    stride = 2 * d * d * Mt
+    P, D = spectra
+    geo.field_to_grid([[P[i, a] for a in range(d)] for i in idx], False, out, stride)
+    geo.field_to_grid([[D[i, a] for a in range(d)] for i in idx], True, out[:, d * d:], stride)
+    return out
+
+
+def train(net, X, Y, steps, lr=1e-3, seed=0, log_every=0, lr_final=None, W=None, geo=None):
     """Adam on random minibatches of (X, Y) (cosine decay to lr_final); returns the loss history.
-    With W (energy weights, one channel per half of the outputs) the loss is the
-    weighted squared error, an approximation of the energy norms of the errors."""
-    g = torch.Generator(device="cpu")
-    g.manual_seed(seed)
+    Minibatches are read through sample pointers (no gather).  Y: target grids, or
+    stored solver fields (a pair of spectra tensors) with geo, a Batch of net.batch
+    problems of the class, bringing them to the grid per step.  With W (energy
+    weights, one channel per half of the outputs) the loss is the weighted squared
+    error, an approximation of the energy norms of the errors."""
+    rng = np.random.default_rng(seed)
     n = X.shape[0]
     hist = []
     lr_final = lr if lr_final is None else lr_final
+    tgt = None
+    if isinstance(Y, tuple):
+        assert geo is not None and len(geo.problems) == net.batch
+        tgt = torch.empty((net.batch, net.cout) + net.size, dtype=torch.float32, device=X.device)
     for s in range(steps):
-        idx = torch.randint(0, n, (net.batch,), generator=g).to(X.device)
-        net.forward(X[idx])
-        loss = net.loss(Y[idx], None if W is None else W[idx])
+        idx = rng.integers(0, n, net.batch)
+        net.forward_samples(X, idx)
+        if tgt is None:
+            loss = net.loss_samples(Y, idx, W)
+        else:
+            grid_targets(geo, Y, idx, tgt)
+            loss = net.loss(tgt)
         net.backward()
         t = s / max(steps - 1, 1)
         net.adam(lr=lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * t)))
@@ -210,29 +287,23 @@ def train(net, X, Y, steps, lr=1e-3, seed=0, log_every=0, lr_final=None, W=None)
     return hist
 
 
-def predict_grids(net, problems):
-    """Network outputs [n, 2 d^2, *M] for problems of one class (batches of net.batch)."""
-    M = problems[0].M
-    out = torch.empty((len(problems), net.cout) + M, dtype=torch.float32, device=api._dev())
-    X = torch.zeros((net.batch, 2) + M, dtype=torch.float32, device=api._dev())
-    for i0 in range(0, len(problems), net.batch):
-        chunk = problems[i0:i0 + net.batch]
-        for j, p in enumerate(chunk):
-            p.net_input(out=X[j])
-        torch.cuda.synchronize()
-        y = net.forward(X)
-        out[i0:i0 + len(chunk)] = y[:len(chunk)]
-    torch.cuda.synchronize()
-    return out
-
-
-def predict_x0(net, problems):
-    """Admissible initial fields, primal and dual, d unit loads each, for problems of one class:
-    the network output projected by the solver (hom_grid_to_field)."""
-    d, M = problems[0].d, problems[0].M
-    grids = predict_grids(net, problems)
-    xs_p, xs_d = [], []
-    for j, p in enumerate(problems):
-        xs_p.append(p.grid_to_field(grids[j, :d * d].reshape((d, d) + M), dual=False))
-        xs_d.append(p.grid_to_field(grids[j, d * d:].reshape((d, d) + M), dual=True))
-    return xs_p, xs_d
+def predict_x0(net, batch):
+    """Admissible initial fields, primal and dual, d unit loads each, for every
+    problem of a batch: the network inputs of all cells in one call, the network
+    (a captured graph) over minibatches without host synchronisation, and the
+    projection of all predictions onto E_N / J_N by one call per side
+    (hom_batch_grid_to_field).  Returns (primal, dual): [[d fields] per problem]."""
+    d, M = batch.d, batch.problems[0].M
+    Mt = int(np.prod(M))
+    n, B = len(batch.problems), net.batch
+    npad = -(-n // B) * B
+    dev = api._dev()
+    X = torch.zeros((npad, 2) + M, dtype=torch.float32, device=dev)
+    G = torch.empty((npad, net.cout) + M, dtype=torch.float32, device=dev)
+    batch.net_input(X)
+    for i0 in range(0, npad, B):
+        net.forward(X[i0:i0 + B], out=G[i0:i0 + B])
+    stride = net.cout * Mt
+    x0p = batch.grid_to_field(G, False, stride=stride)
+    x0d = batch.grid_to_field(G[:, d * d:], True, stride=stride)
+    return x0p, x0d

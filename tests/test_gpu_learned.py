@@ -268,7 +268,7 @@ def test_learned_x0_tighter_start_same_bounds():
     plain = batch.solve_bounds(tol=1e-6)
     zero = batch.bounds([[p.new_field(False) for _ in range(2)] for p in probs],
                         [[p.new_field(True) for _ in range(2)] for p in probs])
-    x0p, x0d = lr_.predict_x0(net, probs)
+    x0p, x0d = lr_.predict_x0(net, batch)
     start = batch.bounds(x0p, x0d)
     fp, ip = batch.solve(False, x0=x0p, tol=1e-6)
     fd, idl = batch.solve(True, x0=x0d, tol=1e-6)
@@ -291,3 +291,67 @@ def test_learned_x0_tighter_start_same_bounds():
           f"iterations plain {it_plain.mean(axis=0)} learned {it_learn.mean(axis=0)}", flush=True)
     assert ep < 0.5 and ed < 0.8
     assert it_learn.mean() <= 1.25 * it_plain.mean()
+
+
+@pytest.mark.parametrize("d,N", [(2, (41, 41)), (3, (13, 13, 13))], ids=["2d", "3d"])
+def test_batched_transfers_equal_per_problem(d, N):
+    """hom_batch_field_to_grid / hom_batch_grid_to_field / hom_batch_net_input
+    (one launch per pass for every cell) against the per-problem calls: the same
+    kernels on the same data, so equal bit for bit; strided blocks land where
+    the stride says."""
+    H = _H()
+    import torch
+    cells = ([homgen.random_squares_cell(900 + i)[0] for i in range(3)] if d == 2 else
+             [homgen.random_spheres_cell(900 + i, kmin=3, kmax=5)[0] for i in range(3)])
+    st = torch.cuda.Stream()
+    probs = [H.problem_from_cell(c, N, precision="mixed", stream=st) for c in cells]
+    b = H.Batch(probs)
+    xp, _, xd, _ = b.solve_pair(tol=1e-6)
+    M = probs[0].M
+    Mt = int(np.prod(M))
+    stride = 2 * d * d * Mt + 7 * Mt          # room for a record larger than one block
+    G = torch.full((len(probs), stride // Mt) + M, float("nan"), dtype=torch.float32, device="cuda")
+    b.field_to_grid(xp, False, G, stride)
+    b.field_to_grid(xd, True, G[:, d * d:], stride)
+    X = torch.empty((len(probs), 2) + M, dtype=torch.float32, device="cuda")
+    Wt = torch.empty_like(X)
+    b.net_input(X)
+    b.net_input(Wt, weights=True)
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        gp = p.field_to_grid(xp[i], dual=False).reshape((d * d,) + M)
+        gd = p.field_to_grid(xd[i], dual=True).reshape((d * d,) + M)
+        assert torch.equal(G[i, :d * d], gp) and torch.equal(G[i, d * d:2 * d * d], gd)
+        assert torch.isnan(G[i, 2 * d * d:]).all()
+        assert torch.equal(X[i], p.net_input()) and torch.equal(Wt[i], p.net_weights())
+    back_p = b.grid_to_field(G, False, stride=stride)
+    back_d = b.grid_to_field(G[:, d * d:], True, stride=stride)
+    for i, p in enumerate(probs):
+        ref_p = p.grid_to_field(G[i, :d * d].reshape((d, d) + M).contiguous(), dual=False)
+        ref_d = p.grid_to_field(G[i, d * d:2 * d * d].reshape((d, d) + M).contiguous(), dual=True)
+        for a in range(d):
+            assert torch.equal(back_p[i][a], ref_p[a]) and torch.equal(back_d[i][a], ref_d[a])
+
+
+def test_pair_solve_from_starting_fields_equals_separate_solves():
+    """hom_batch_solve_pair with starting fields: the same iterations and fields as
+    the primal and dual solves from those fields one after the other."""
+    H = _H()
+    import torch
+    cells = [homgen.random_squares_cell(950 + i)[0] for i in range(3)]
+    st = torch.cuda.Stream()
+    probs = [H.problem_from_cell(c, (41, 41), precision="mixed", stream=st) for c in cells]
+    b = H.Batch(probs)
+    coarse_p, _, coarse_d, _ = b.solve_pair(tol=1e-2)
+    x0p = [[t.clone() for t in ts] for ts in coarse_p]
+    x0d = [[t.clone() for t in ts] for ts in coarse_d]
+    fp, ip, fd, idl = b.solve_pair(tol=1e-8, x0_primal=x0p, x0_dual=x0d)
+    sp, isp = b.solve(False, x0=x0p, tol=1e-8)
+    sd, isd = b.solve(True, x0=x0d, tol=1e-8)
+    for i in range(len(probs)):
+        assert [r["iters"] for r in ip[i] + idl[i]] == [r["iters"] for r in isp[i] + isd[i]]
+        for a in range(2):
+            assert torch.equal(fp[i][a], sp[i][a]) and torch.equal(fd[i][a], sd[i][a])
+    # and fewer iterations than from zero
+    _, iz, _, idz = b.solve_pair(tol=1e-8)
+    assert sum(r["iters"] for c in ip for r in c) < sum(r["iters"] for c in iz for r in c)
