@@ -70,9 +70,12 @@ def parse():
                          "host loop, or a host thread per class")
     ap.add_argument("--e1-jmax", type=int, default=5, help="e1: grids N = 5 3^j for j <= jmax")
     ap.add_argument("--e2-jmax", type=int, default=9, help="e2: even grids n = 2^j for 2 <= j <= jmax")
-    ap.add_argument("--c5-train", type=int, default=2048, help="c5: training cells")
-    ap.add_argument("--c5-steps", type=int, default=1500, help="c5: Adam steps")
-    ap.add_argument("--c5-test", type=int, default=256, help="c5: held-out cells")
+    ap.add_argument("--c5-train", type=int, default=16384, help="c5: 2D training cells (0: no 2D class)")
+    ap.add_argument("--c5-steps", type=int, default=3000, help="c5: Adam steps of the 2D network (batch 16)")
+    ap.add_argument("--c5-test", type=int, default=256, help="c5: held-out 2D cells")
+    ap.add_argument("--c5-train3d", type=int, default=4096, help="c5: 3D training cells (0: no 3D class)")
+    ap.add_argument("--c5-steps3d", type=int, default=1500, help="c5: Adam steps of the 3D network (batch 2)")
+    ap.add_argument("--c5-test3d", type=int, default=64, help="c5: held-out 3D cells")
     return ap.parse_args()
 
 
@@ -747,107 +750,167 @@ def mixed_roofline(args, ms, groups, n_total):
                 bytes_per_launch=hbm["bytes_per_launch"], **common)
 
 
-def run_c5(args):
-    """Learned initial guess: a 4-level, 32-channel U-Net trained on solver fields
-    of 2D N = 63 cells; plain versus learned + batched CG on held-out cells of
-    contrast 1e2 - 1e3, inference and projection inside the timed region."""
+def unet_flops(d, size, levels, base, cin, cout):
+    """Flops of one U-Net forward pass of one sample (2 per multiply-add of every
+    convolution at its level's size; pooling, upsampling and bias not counted)."""
     import math
     import numpy as np
-    import torch
-    import homgen
-    import paper_1404_3614_amd as H
     from paper_1404_3614_amd import learned as LL
-    N, M = (63, 63), (125, 125)
-    logrho = (math.log10(2.0), 3.0)
-    train_cells = [homgen.random_squares_cell(5_000_000 + i, logrho=logrho)[0] for i in range(args.c5_train)]
+    sz = [list(size)]
+    for _ in range(1, levels):
+        sz.append([math.ceil(x / 2) for x in sz[-1]])
+    pl = [int(np.prod(x)) for x in sz]
+    lv = [l for l in range(levels) for _ in range(2)] + [l for l in range(levels - 2, -1, -1) for _ in range(3)] + [0]
+    return sum(2 * ci * co * ks ** d * pl[l] for (ci, co, ks), l in zip(LL.layer_shapes(d, levels, base, cin, cout), lv))
+
+
+def _c5_class(args, d, N, train_cells, test_cells, net_batch, steps, targets, lr, warmup):
+    """Train the surrogate of one size class on solver fields, then time plain and
+    learned + batched solves of the held-out cells under the three stopping rules."""
+    import ctypes as C
+    import numpy as np
+    import torch
+    import paper_1404_3614_amd as H
+    from paper_1404_3614_amd import _lib as L
+    from paper_1404_3614_amd import learned as LL
+    M = tuple(2 * n - 1 for n in N)
     t0 = time.perf_counter()
-    X, Y, W, it_train = LL.solver_samples(train_cells, N, tol=args.tol, chunk=256)
+    X, Y, W, it_train = LL.solver_samples(train_cells, N, tol=args.tol, chunk=256 if d == 2 else 64,
+                                          targets=targets)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
-    print(f"[c5] {len(train_cells)} training fields in {t_gen:.1f} s", file=sys.stderr, flush=True)
-    net = LL.UNet(2, M, levels=4, base=32, batch=16)
+    print(f"[c5] {d}D: {len(train_cells)} training fields in {t_gen:.1f} s", file=sys.stderr, flush=True)
+    net = LL.UNet(d, M, levels=4, base=32, batch=net_batch)
     net.init_params(seed=1)
+    geo = None
+    if targets == "spectra":
+        st = torch.cuda.Stream()
+        geo = H.Batch([H.problem_from_cell(c, N, precision=args.precision, stream=st)
+                       for c in train_cells[:net_batch]])
     t0 = time.perf_counter()
-    hist = LL.train(net, X, Y, steps=args.c5_steps, lr=2e-3, lr_final=1e-4, seed=3,
-                    log_every=max(1, args.c5_steps // 5))
+    hist = LL.train(net, X, Y, steps=steps, lr=lr, lr_final=lr / 20, seed=3, log_every=max(1, steps // 5), geo=geo,
+                    warmup=warmup)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    del X, Y, W
-    test = [homgen.random_squares_cell(6_000_000 + i, logrho=(2.0, 3.0))[0] for i in range(args.c5_test)]
+    del X, Y, W, geo
+    torch.cuda.empty_cache()
     st = torch.cuda.Stream()
-    probs = [H.problem_from_cell(c, N, precision=args.precision, stream=st) for c in test]
+    probs = [H.problem_from_cell(c, N, precision=args.precision, stream=st) for c in test_cells]
     batch = H.Batch(probs)
-    rng = [H.cell_eig_range(c) for c in test]
+    rng = [H.cell_eig_range(c) for c in test_cells]
     a_min, a_max = min(r[0] for r in rng), max(r[1] for r in rng)
-    batch.set_stop(args.stop, args.etol, a_min, a_max)
-    zero = batch.bounds([[p.new_field(False) for _ in range(2)] for p in probs],
-                        [[p.new_field(True) for _ in range(2)] for p in probs])
-    for _ in range(args.warmup):
-        batch.solve_bounds(tol=args.tol)
+    zero = batch.bounds([[p.new_field(False) for _ in range(d)] for p in probs],
+                        [[p.new_field(True) for _ in range(d)] for p in probs])
+    n = len(test_cells)
+    # inference alone (the network's inputs, forward passes from the captured graph, projection)
+    LL.predict_x0(net, batch)
     torch.cuda.synchronize()
-    # plain batched CG from x0 = 0
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        plain = batch.solve_bounds(tol=args.tol)
-    torch.cuda.synchronize()
-    t_plain = (time.perf_counter() - t0) / args.steps
-    # learned + batched: inference, projection onto E_N / J_N, CG from the projected fields, bounds
-    outp = [[p.new_field(False) for _ in range(2)] for p in probs]
-    outd = [[p.new_field(True) for _ in range(2)] for p in probs]
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        x0p, x0d = LL.predict_x0(net, probs)
-        fp, ip = batch.solve(False, x0=x0p, tol=args.tol, out=outp)
-        fd, idl = batch.solve(True, x0=x0d, tol=args.tol, out=outd)
-        learned = batch.bounds(fp, fd)
-    torch.cuda.synchronize()
-    t_learned = (time.perf_counter() - t0) / args.steps
-    t0 = time.perf_counter()
-    x0p, x0d = LL.predict_x0(net, probs)
+    x0p, x0d = LL.predict_x0(net, batch)
     torch.cuda.synchronize()
     t_infer = time.perf_counter() - t0
     start = batch.bounds(x0p, x0d)
-    # plain CG one cell at a time (no batching) on a subset
-    nsingle = min(16, len(test))
-    single = H.problem_from_cell(test[0], N, precision=args.precision)
-    single.set_stop(args.stop, args.etol, a_min, a_max)
-    single.solve_bounds(tol=args.tol)
+    # the forward passes alone, with events on the network's stream (the inputs of every
+    # test cell are written, the first net.batch of them run)
+    Xall = torch.zeros((max(n, net.batch), 2) + M, dtype=torch.float32, device="cuda")
+    batch.net_input(Xall)
+    Xin = Xall[:net.batch]
+    net.forward(Xin)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 10 if d == 2 else 3
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for c in test[:nsingle]:
-        Ah, Bh, _ = H.coef_from_cell(c, N)
-        single.update_coefficients(Ah, Bh)
-        single.solve_bounds(tol=args.tol)
+    e0.record(net.stream)
+    for _ in range(reps):
+        L.check(L.load().hom_unet_forward(net.h, C.c_void_p(Xin.data_ptr()), None), "hom_unet_forward")
+    e1.record(net.stream)
     torch.cuda.synchronize()
-    t_single = (time.perf_counter() - t0) / nsingle
-    itp = np.array([[i["iters"] for i in b["info_primal"] + b["info_dual"]] for b in plain])
-    itl = np.array([[r["iters"] for r in a + b] for a, b in zip(ip, idl)])
-    err = max(float(np.abs(b1["A_up"] - b0["A_up"]).max() / np.linalg.norm(b0["A_up"], 2)) for b0, b1 in
-              zip(plain, learned))
-    ep = float(np.mean([(np.diag(s["A_up"]) - np.diag(r["A_up"])) / (np.diag(z["A_up"]) - np.diag(r["A_up"]))
-                        for s, r, z in zip(start, plain, zero)]))
-    ed = float(np.mean([(np.diag(s["B_up"]) - np.diag(r["B_up"])) / (np.diag(z["B_up"]) - np.diag(r["B_up"]))
-                        for s, r, z in zip(start, plain, zero)]))
-    n = len(test)
-    line = _line(args, n / t_learned, t_learned * args.steps, args.steps,
-                 "C5: learned + batched CG, 2D N=63 (doubled grid 125^2) random squares, contrast 1e2-1e3, "
-                 "U-Net 4 levels x 32 base channels (FP32, hand-written kernels) trained on solver fields",
-                 dict(cells_per_step=n,
-                      learned_batched_bound_pairs_per_s=round(n / t_learned, 2),
-                      plain_batched_bound_pairs_per_s=round(n / t_plain, 2),
-                      plain_unbatched_bound_pairs_per_s=round(1.0 / t_single, 2),
-                      inference_and_projection_ms=round(1e3 * t_infer, 2),
-                      iterations_plain_mean=round(float(itp.mean()), 2),
-                      iterations_plain_p95=float(np.percentile(itp, 95)),
-                      iterations_learned_mean=round(float(itl.mean()), 2),
-                      iterations_learned_p95=float(np.percentile(itl, 95)),
-                      start_energy_error_vs_zero_start=dict(primal=round(ep, 4), dual=round(ed, 4)),
-                      max_rel_bound_diff_learned_vs_plain=err,
-                      training=dict(cells=len(train_cells), field_generation_s=round(t_gen, 2),
-                                    adam_steps=args.c5_steps, batch=16, train_s=round(t_train, 2),
-                                    loss_first=round(float(np.mean(hist[:10])), 5),
-                                    loss_last=round(float(np.mean(hist[-50:])), 5))),
+    fwd_ms = e0.elapsed_time(e1) / reps
+    fwd_flops = unet_flops(d, M, 4, 32, 2, net.cout) * net.batch
+    rules = {}
+    for rule, etol in (("residual", None), ("guaranteed", args.etol), ("gap", args.theta)):
+        batch.set_stop(rule, etol, a_min, a_max)
+        tol = args.tol if rule == "residual" else 1e-12
+        for _ in range(max(1, args.warmup)):
+            batch.solve_bounds(tol=tol)
+            x0p, x0d = LL.predict_x0(net, batch)
+            batch.solve_bounds(tol=tol, x0_primal=x0p, x0_dual=x0d)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            plain = batch.solve_bounds(tol=tol)
+        torch.cuda.synchronize()
+        t_plain = (time.perf_counter() - t0) / args.steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            x0p, x0d = LL.predict_x0(net, batch)
+            learned = batch.solve_bounds(tol=tol, x0_primal=x0p, x0_dual=x0d)
+        torch.cuda.synchronize()
+        t_learned = (time.perf_counter() - t0) / args.steps
+        itp = np.array([[i["iters"] for i in b["info_primal"] + b["info_dual"]] for b in plain])
+        itl = np.array([[i["iters"] for i in b["info_primal"] + b["info_dual"]] for b in learned])
+        diff = max(max(float(np.abs(b1[k] - b0[k]).max() / np.linalg.norm(b0[k], 2)) for k in ("A_up", "A_low"))
+                   for b0, b1 in zip(plain, learned))
+        rules[rule] = dict(etol=etol, plain_batched_bound_pairs_per_s=round(n / t_plain, 2),
+                           learned_batched_bound_pairs_per_s=round(n / t_learned, 2),
+                           iterations_plain_mean=round(float(itp.mean()), 2),
+                           iterations_plain_p95=float(np.percentile(itp, 95)),
+                           iterations_learned_mean=round(float(itl.mean()), 2),
+                           iterations_learned_p95=float(np.percentile(itl, 95)),
+                           max_rel_bound_diff_learned_vs_plain=diff)
+    batch.set_stop("residual")
+    ref = batch.solve_bounds(tol=args.tol)
+    ep = float(np.mean([(np.diag(s_["A_up"]) - np.diag(r["A_up"])) / (np.diag(z["A_up"]) - np.diag(r["A_up"]))
+                        for s_, r, z in zip(start, ref, zero)]))
+    ed = float(np.mean([(np.diag(s_["B_up"]) - np.diag(r["B_up"])) / (np.diag(z["B_up"]) - np.diag(r["B_up"]))
+                        for s_, r, z in zip(start, ref, zero)]))
+    return dict(d=d, N=N[0], train_cells=len(train_cells), test_cells=n,
+                field_generation_s=round(t_gen, 2), adam_steps=steps, net_batch=net_batch, lr=lr, warmup=warmup,
+                train_s=round(t_train, 2), loss_first=round(float(np.mean(hist[:10])), 5),
+                loss_last=round(float(np.mean(hist[-max(1, steps // 20):])), 5),
+                inference_and_projection_ms=round(1e3 * t_infer, 2),
+                start_energy_error_vs_zero_start=dict(primal=round(ep, 4), dual=round(ed, 4)),
+                forward=dict(ms_per_launch=round(fwd_ms, 4), flops_per_launch=int(fwd_flops),
+                             tflops=round(fwd_flops / (fwd_ms * 1e-3) / 1e12, 2)),
+                rules=rules)
+
+
+def run_c5(args):
+    """Learned initial guess: 4-level, 32-channel U-Nets trained on solver fields of
+    2D N = 63 cells and of 3D N = 41 cells; plain versus learned + batched CG on
+    held-out cells of contrast 1e2 - 1e3 under the residual, guaranteed-energy and
+    gap rules, inference and projection inside the timed region."""
+    import math
+    import homgen
+    logrho = (math.log10(2.0), 3.0)
+    out = {}
+    if args.c5_train > 0:
+        train = [homgen.random_squares_cell(5_000_000 + i, logrho=logrho)[0] for i in range(args.c5_train)]
+        test = [homgen.random_squares_cell(6_000_000 + i, logrho=(2.0, 3.0))[0] for i in range(args.c5_test)]
+        out["2d"] = _c5_class(args, 2, (63, 63), train, test, 16, args.c5_steps, "grid", 2e-3, 0)
+    if args.c5_train3d > 0:
+        train = [homgen.random_spheres_cell(5_500_000 + i, logrho=logrho)[0] for i in range(args.c5_train3d)]
+        test = [homgen.random_spheres_cell(6_500_000 + i, logrho=(2.0, 3.0))[0] for i in range(args.c5_test3d)]
+        # the 3D layers have 3x the fan-in of the 2D ones: a smaller step and a warm-up keep Adam's
+        # first, sign-like steps from blowing the activations up
+        out["3d"] = _c5_class(args, 3, (41, 41, 41), train, test, 2, args.c5_steps3d, "spectra", 5e-4,
+                              max(1, args.c5_steps3d // 10))
+    main = out.get("2d") or out["3d"]
+    r = main["rules"]["residual"]
+    value = r["learned_batched_bound_pairs_per_s"]
+    line = _line(args, value, main["test_cells"] / value * args.steps, args.steps,
+                 "C5: learned + batched CG, 2D N=63 (doubled grid 125^2) random squares and 3D N=41 (81^3) random "
+                 "spheres, contrast 1e2-1e3; U-Net 4 levels x 32 base channels (FP32, MFMA implicit-GEMM "
+                 "convolutions) trained on solver fields",
+                 dict(classes=out, value_is="2D class, residual rule, learned + batched"),
                  dtype="f32 FFT/apply + f64 CG/bounds; f32 network")
+    fw = main["forward"]
+    line["roofline"] = dict(bound="mfma", achieved=fw["tflops"], peak=157.3, unit="TFLOP/s",
+                            frac=round(fw["tflops"] / 157.3, 4), traffic=None,
+                            kernel="U-Net forward (implicit-GEMM convolutions on v_mfma_f32_16x16x4f32, pooling, "
+                                   "upsampling), whole network per launch of net_batch samples",
+                            ms_per_launch=fw["ms_per_launch"], flops_per_launch=fw["flops_per_launch"],
+                            flops_model="unet_flops() in bench.py: 2 per multiply-add of every convolution",
+                            timed_region="hom_unet_forward replays on the network stream between HIP events")
     print(json.dumps(line), flush=True)
 
 

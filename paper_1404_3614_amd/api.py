@@ -585,12 +585,20 @@ class Batch:
                 "hom_batch_profile_passes")
         return dict(first=ms[0], mid_inv=ms[1], apply=ms[2], mid_fwd=ms[3], last=ms[4])
 
+    def _check_span(self, t, stride, block):
+        """The n strided blocks of `block` floats from t's first element stay inside t's storage."""
+        need = (len(self.problems) - 1) * stride + block
+        end = t.untyped_storage().data_ptr() + t.untyped_storage().nbytes()
+        if t.dtype != torch.float32 or t.data_ptr() + 4 * need > end:
+            raise ValueError(f"tensor too small for {len(self.problems)} blocks of {block} floats at stride {stride}")
+
     def field_to_grid(self, fields, dual, out, stride=None):
         """Doubled-grid values (FP32) of fields [[d tensors] per problem] into out, cell i's
         [nload][d][*M] block at float offset i * stride (hom_batch_field_to_grid)."""
         nl = len(fields[0])
         Mt = int(np.prod(self.problems[0].M))
         stride = nl * self.d * Mt if stride is None else int(stride)
+        self._check_span(out, stride, nl * self.d * Mt)
         flat = [t for ts in fields for t in ts]
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_batch_field_to_grid(self.h, int(dual), nl, _dptrs(flat), C.c_void_p(out.data_ptr()),
@@ -604,6 +612,7 @@ class Batch:
         nl = self.d if nload is None else nload
         Mt = int(np.prod(self.problems[0].M))
         stride = nl * self.d * Mt if stride is None else int(stride)
+        self._check_span(grids, stride, nl * self.d * Mt)
         out = [[p.new_field(dual) for _ in range(nl)] for p in self.problems]
         flat = [t for ts in out for t in ts]
         self.stream.wait_stream(torch.cuda.current_stream())
@@ -616,6 +625,7 @@ class Batch:
         cell i's block at float offset i * stride (hom_batch_net_input)."""
         Mt = int(np.prod(self.problems[0].M))
         stride = 2 * Mt if stride is None else int(stride)
+        self._check_span(out, stride, 2 * Mt)
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_batch_net_input(self.h, C.c_void_p(out.data_ptr()), stride, int(bool(weights))),
                 "hom_batch_net_input")

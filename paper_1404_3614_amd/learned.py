@@ -115,6 +115,8 @@ class UNet:
         """Forward of the samples X[idx] (X: [n, cin, *size], contiguous) without a
         separate gather (hom_unet_forward_samples)."""
         o = self.out if out is None else out
+        assert tuple(X.shape[1:]) == (self.cin,) + self.size and len(idx) == self.batch
+        assert 0 <= min(idx) and max(idx) < X.shape[0]
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_unet_forward_samples(self.h, sample_ptrs(X, idx), C.c_void_p(o.data_ptr())),
                 "hom_unet_forward_samples")
@@ -139,6 +141,9 @@ class UNet:
         """Loss of the last output against the samples Y[idx] (and weights W[idx])
         without a separate gather (hom_unet_loss_samples)."""
         val = C.c_double()
+        assert tuple(Y.shape[1:]) == (self.cout,) + self.size and len(idx) == self.batch
+        assert 0 <= min(idx) and max(idx) < Y.shape[0]
+        assert W is None or (tuple(W.shape[2:]) == self.size and W.shape[0] == Y.shape[0])
         self.stream.wait_stream(torch.cuda.current_stream())
         wp = sample_ptrs(W, idx) if W is not None else None
         L.check(L.load().hom_unet_loss_samples(self.h, sample_ptrs(Y, idx), wp, 1 if W is None else int(W.shape[1]),
@@ -255,8 +260,9 @@ def grid_targets(geo, spectra, idx, out):
     return out
 
 
-def train(net, X, Y, steps, lr=1e-3, seed=0, log_every=0, lr_final=None, W=None, geo=None):
-    """Adam on random minibatches of (X, Y) (cosine decay to lr_final); returns the loss history.
+def train(net, X, Y, steps, lr=1e-3, seed=0, log_every=0, lr_final=None, W=None, geo=None, warmup=0):
+    """Adam on random minibatches of (X, Y) (linear warm-up over `warmup` steps, then
+    cosine decay to lr_final); returns the loss history.
     Minibatches are read through sample pointers (no gather).  Y: target grids, or
     stored solver fields (a pair of spectra tensors) with geo, a Batch of net.batch
     problems of the class, bringing them to the grid per step.  With W (energy
@@ -280,7 +286,10 @@ def train(net, X, Y, steps, lr=1e-3, seed=0, log_every=0, lr_final=None, W=None,
             loss = net.loss(tgt)
         net.backward()
         t = s / max(steps - 1, 1)
-        net.adam(lr=lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * t)))
+        rate = lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * t))
+        if s < warmup:
+            rate *= (s + 1) / warmup
+        net.adam(lr=rate)
         hist.append(loss)
         if log_every and (s % log_every == 0 or s == steps - 1):
             print(f"[train] step {s} loss {loss:.5g}", flush=True)

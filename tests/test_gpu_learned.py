@@ -235,18 +235,18 @@ def _cells(seed0, n, logrho):
 
 
 def test_learned_x0_tighter_start_same_bounds():
-    """Train a small surrogate on solver fields (2D, N = 41), then solve held-out high-contrast cells from x0 = 0 and from the
-    projected prediction.
+    """Train a small surrogate on solver fields (2D, N = 41), then solve held-out
+    high-contrast cells from x0 = 0 and from the projected prediction.
 
-    What the network gains: its projected output is an admissible field, so
-    it already gives guaranteed bounds, and these are much closer to the
-    converged ones than those of the zero field (the Voigt / Reuss bounds):
-    the energy error Abar(x0) - Abar(x*) is a fraction of Abar(0) - Abar(x*).
-    CG from that start reaches the same bounds.  The iteration counts are
-    reported; at the residual tolerance 1e-6 they stay close to those from
-    x0 = 0 (the stopping test is governed by the interface content of the
-    residual, which the prediction does not remove), so they are only
-    bounded here, not required to drop."""
+    What the network gains: its projected output is an admissible field, so it
+    already gives guaranteed bounds (Def. upper_lower_bounds: any field of E_N /
+    J_N does), much closer to the converged ones than those of the zero field
+    (the Voigt / Reuss bounds): the energy error Abar(x0) - Abar(x*) is a
+    fraction of Abar(0) - Abar(x*).  CG from that start reaches the same bounds.
+    Under the gap rule, which stops on the bounds' own error, the start saves
+    iterations; under the residual rule it does not (the stopping test is
+    governed by the interface content of the residual, which the prediction
+    does not remove), and that count is only bounded here."""
     H = _H()
     import torch
     from paper_1404_3614_amd import learned as lr_
@@ -265,16 +265,16 @@ def test_learned_x0_tighter_start_same_bounds():
     st = torch.cuda.Stream()
     probs = [H.problem_from_cell(c, N, precision="mixed", stream=st) for c in test_cells]
     batch = H.Batch(probs)
+    rng = [H.cell_eig_range(c) for c in test_cells]
+    a_min, a_max = min(r[0] for r in rng), max(r[1] for r in rng)
     plain = batch.solve_bounds(tol=1e-6)
     zero = batch.bounds([[p.new_field(False) for _ in range(2)] for p in probs],
                         [[p.new_field(True) for _ in range(2)] for p in probs])
     x0p, x0d = lr_.predict_x0(net, batch)
     start = batch.bounds(x0p, x0d)
-    fp, ip = batch.solve(False, x0=x0p, tol=1e-6)
-    fd, idl = batch.solve(True, x0=x0d, tol=1e-6)
-    learned = batch.bounds(fp, fd)
-    it_plain = np.array([[r["iters"] for r in b["info_primal"] + b["info_dual"]] for b in plain])
-    it_learn = np.array([[r["iters"] for r in a + b] for a, b in zip(ip, idl)])
+    learned = batch.solve_bounds(tol=1e-6, x0_primal=x0p, x0_dual=x0d)
+    its = lambda res: np.array([[r["iters"] for r in b["info_primal"] + b["info_dual"]] for b in res])
+    it_plain, it_learn = its(plain), its(learned)
     ep, ed = [], []
     for b0, z, s, b1 in zip(plain, zero, start, learned):
         scale = np.linalg.norm(b0["A_up"], 2)
@@ -287,9 +287,21 @@ def test_learned_x0_tighter_start_same_bounds():
         ep.append((np.diag(s["A_up"]) - np.diag(b0["A_up"])) / (np.diag(z["A_up"]) - np.diag(b0["A_up"])))
         ed.append((np.diag(s["B_up"]) - np.diag(b0["B_up"])) / (np.diag(z["B_up"]) - np.diag(b0["B_up"])))
     ep, ed = float(np.mean(ep)), float(np.mean(ed))
+    # the gap rule (each bound within 1 % of the discretisation gap) from both starts
+    batch.set_stop("gap", 1e-2, a_min, a_max)
+    gap_plain = batch.solve_bounds(tol=1e-12)
+    gap_learn = batch.solve_bounds(tol=1e-12, x0_primal=x0p, x0_dual=x0d)
+    batch.set_stop("residual")
+    g_plain, g_learn = its(gap_plain), its(gap_learn)
     print(f"[learned] energy error of the start vs zero start: primal {ep:.3f} dual {ed:.3f}; "
-          f"iterations plain {it_plain.mean(axis=0)} learned {it_learn.mean(axis=0)}", flush=True)
+          f"iterations residual rule plain {it_plain.mean():.1f} learned {it_learn.mean():.1f}; "
+          f"gap rule plain {g_plain.mean():.1f} learned {g_learn.mean():.1f}", flush=True)
     assert ep < 0.5 and ed < 0.8
+    assert g_learn.mean() < g_plain.mean()
+    for b0, b1 in zip(gap_plain, gap_learn):
+        n = np.linalg.norm(b0["A_up"], 2)
+        for key in ("A_up", "A_low"):
+            assert np.abs(b1[key] - b0[key]).max() <= 0.02 * n      # both within 1 % of the gap of the same bounds
     assert it_learn.mean() <= 1.25 * it_plain.mean()
 
 
