@@ -46,7 +46,8 @@ constexpr int COT = 32;      // output channels per block
 constexpr int CIC = 8;       // input channels per LDS stage (forward)
 constexpr int WCI = 16;      // input channels per block (weight gradient)
 constexpr int WST = 48;      // LDS row stride of [k][channel] tiles: two k rows of a half-wave 16 banks apart
-constexpr int kWgradChunks = 64;   // weight-gradient partials per layer (summed in a fixed order)
+constexpr int kWgradBlocks = 2048;      // weight-gradient blocks a layer aims for (chunks of point tiles)
+constexpr int kMaxWgradChunks = 1024;   // weight-gradient partials per layer at most (summed in a fixed order)
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
@@ -93,6 +94,104 @@ __device__ __forceinline__ void stage_halo(float* s, const float* __restrict__ i
   }
 }
 
+// Packed weights of a convolution, in the order the forward kernel stages them:
+// wp[co block][ci stage][tap][c][COT] = w[co][ci][tap] (co = COT block + j,
+// ci = CIC stage + c), zero past Cout and Cin, so that a stage's weights are one
+// contiguous run of TAPS CIC COT floats, copied to LDS without re-indexing.
+constexpr int kMaxPack = 32;
+static_assert(5 * 6 - 2 <= kMaxPack, "a U-Net of 6 levels has 28 convolutions");
+struct PackEntry {
+  size_t src, dst;      // offsets of w in the parameters and of its packed copy
+  int co, ci, taps;     // as seen by the packed convolution
+  int flip;             // 1: the adjoint, w'[co][ci][tap] = w[ci][co][taps - 1 - tap]
+};
+struct PackTable {
+  int n;
+  PackEntry e[kMaxPack];
+};
+
+__host__ __device__ inline size_t packed_floats(int co, int ci, int taps) {
+  return (size_t)((co + COT - 1) / COT) * ((ci + CIC - 1) / CIC) * taps * CIC * COT;
+}
+
+// One layer per grid row.
+__global__ void k_pack_w(const float* __restrict__ params, PackTable tab, float* __restrict__ wp) {
+  const PackEntry e = tab.e[blockIdx.y];
+  const int nst = (e.ci + CIC - 1) / CIC;
+  const size_t n = packed_floats(e.co, e.ci, e.taps);
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const int j = t % COT;
+    size_t r = t / COT;
+    const int c = r % CIC;
+    r /= CIC;
+    const int tap = r % e.taps;
+    r /= e.taps;
+    const int st = r % nst, cob = r / nst;
+    const int co = cob * COT + j, ci = st * CIC + c;
+    float v = 0.f;
+    if (co < e.co && ci < e.ci)
+      v = e.flip ? params[e.src + ((size_t)ci * e.co + co) * e.taps + (e.taps - 1 - tap)]
+                 : params[e.src + ((size_t)co * e.ci + ci) * e.taps + tap];
+    wp[e.dst + t] = v;
+  }
+}
+
+// One stage of the forward convolution (the halo of CIC input channels and
+// their packed weights), loaded into registers while the previous stage is
+// multiplied, then stored to LDS: the global loads' latency hides behind the
+// matrix-core work.  Thread t holds halo points t, t + CT, ... of every channel
+// (the channel offset is the same for the whole block) and float4s t, t + CT,
+// ... of the weights; both land in LDS as contiguous runs (no bank conflicts).
+template <int D, int KS>
+struct Stage {
+  using H = Halo<D, KS>;
+  static constexpr int NJ = (H::N + CT - 1) / CT;           // halo points per thread and channel
+  static constexpr int WQ = H::TAPS * CIC * COT / 4;        // float4s of a stage's weights
+  static constexpr int NW = (WQ + CT - 1) / CT;
+  int goff[NJ];                                             // point offsets in a channel plane, -1 past the halo
+  float h[CIC][NJ];
+  float4 w[NW];
+
+  __device__ __forceinline__ void init(int tx0, int ty0, int tz0, int Zs, int Hs, int Ws) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int r = (int)threadIdx.x + j * CT;
+      const int hx = r % H::X, hy = (r / H::X) % H::Y, hz = r / (H::X * H::Y);
+      const int gx = wrap(tx0 + hx - H::R, Ws), gy = wrap(ty0 + hy - H::R, Hs);
+      const int gz = (D == 3) ? wrap(tz0 + hz - H::R, Zs) : 0;
+      goff[j] = r < H::N ? (gz * Hs + gy) * Ws + gx : -1;
+    }
+  }
+
+  // in_c: channel ci0 of the image; nvalid channels of the stage exist; ws: the stage's packed weights
+  __device__ __forceinline__ void load(const float* __restrict__ in_c, size_t plane, int nvalid,
+                                       const float4* __restrict__ ws) {
+#pragma unroll
+    for (int c = 0; c < CIC; ++c)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) h[c][j] = (c < nvalid && goff[j] >= 0) ? in_c[c * plane + goff[j]] : 0.f;
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const int f = (int)threadIdx.x + i * CT;
+      w[i] = (WQ % CT == 0 || f < WQ) ? ws[f] : float4{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+
+  template <int HS>
+  __device__ __forceinline__ void store(float* s_in, float* s_w) const {
+#pragma unroll
+    for (int c = 0; c < CIC; ++c)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        if (goff[j] >= 0) s_in[c * HS + (int)threadIdx.x + j * CT] = h[c][j];
+#pragma unroll
+    for (int i = 0; i < NW; ++i) {
+      const int f = (int)threadIdx.x + i * CT;
+      if (WQ % CT == 0 || f < WQ) *reinterpret_cast<float4*>(s_w + (f / (COT / 4)) * WST + (f % (COT / 4)) * 4) = w[i];
+    }
+  }
+};
+
 template <int D>
 __device__ __forceinline__ void tile_origin(int tile, int Hs, int Ws, int* tx0, int* ty0, int* tz0) {
   const int tiles_x = (Ws + Tile<D>::X - 1) / Tile<D>::X, tiles_y = (Hs + Tile<D>::Y - 1) / Tile<D>::Y;
@@ -102,24 +201,33 @@ __device__ __forceinline__ void tile_origin(int tile, int Hs, int Ws, int* tx0, 
   *tz0 = (tile / tiles_y) * Tile<D>::Z;
 }
 
-// Forward convolution (also the data gradient with flipped, transposed weights).
+// Forward convolution (also the data gradient with flipped, transposed weights),
+// weights packed by k_pack_w.
 // Block: 128 points x 32 output channels; wave w: points 32 w .. 32 w + 31 (two
 // tiles of 16) x the 32 channels (two tiles of 16).  K runs tap-major over
 // stages of CIC input channels, so the four k of an MFMA step share a tap.
+// Split K: grid.y = co tiles x nsplit; split s of a block sums the input
+// channels [s cps, (s + 1) cps).  With nsplit > 1 the block writes its raw
+// partial sums to part[s][b][co][q] and k_splitk_sum adds the splits in a fixed
+// order and applies the epilogue (bias, activation, accumulation).
 template <int D, int KS>
 __global__ __launch_bounds__(CT) void k_conv_fwd(const float* __restrict__ in, int Cin, int inCtot, int inOff,
-                                                 const float* __restrict__ w, const float* __restrict__ bias,
+                                                 const float* __restrict__ wp, const float* __restrict__ bias,
                                                  float* __restrict__ out, int Cout, int outCtot, int outOff, int Zs,
-                                                 int Hs, int Ws, int relu, int accumulate) {
+                                                 int Hs, int Ws, int relu, int accumulate, int cps,
+                                                 float* __restrict__ part) {
   using H = Halo<D, KS>;
   constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
   constexpr int TAPS = H::TAPS;
   constexpr int HS = pad_to(H::N, 16);     // channel stride: lanes 16..31 read the next channel 16 banks away
   __shared__ float s_in[CIC * HS];
-  __shared__ float s_w[TAPS * CIC * WST];  // [tap][c][co]
+  __shared__ __align__(16) float s_w[TAPS * CIC * WST];  // [tap][c][co], stored as float4s
   int tx0, ty0, tz0;
   tile_origin<D>(blockIdx.x, Hs, Ws, &tx0, &ty0, &tz0);
-  const int co0 = blockIdx.y * COT;
+  const int cot = (Cout + COT - 1) / COT;
+  const int split = blockIdx.y / cot;
+  const int co0 = (blockIdx.y - split * cot) * COT;
+  const int ci_lo = split * cps, ci_hi = min(Cin, ci_lo + cps);
   const int b = blockIdx.z;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lk = lane >> 4, ln = lane & 15;
@@ -137,18 +245,20 @@ __global__ __launch_bounds__(CT) void k_conv_fwd(const float* __restrict__ in, i
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int ci0 = 0; ci0 < Cin; ci0 += CIC) {
+  // ci_lo is a multiple of CIC: stage s of the packed weights holds channels [s CIC, (s + 1) CIC)
+  const float* in_b = in + ((size_t)b * inCtot + inOff) * plane;
+  const float4* w_blk = reinterpret_cast<const float4*>(wp) +
+                        (size_t)(co0 / COT) * ((Cin + CIC - 1) / CIC) * (Stage<D, KS>::WQ);
+  Stage<D, KS> stg;
+  stg.init(tx0, ty0, tz0, Zs, Hs, Ws);
+  if (ci_lo < ci_hi) stg.load(in_b + (size_t)ci_lo * plane, plane, ci_hi - ci_lo, w_blk + (size_t)(ci_lo / CIC) * Stage<D, KS>::WQ);
+  for (int ci0 = ci_lo; ci0 < ci_hi; ci0 += CIC) {
+    __syncthreads();                       // the previous stage's reads of LDS are done
+    stg.template store<HS>(s_in, s_w);
     __syncthreads();
-    stage_halo<D, KS, HS>(s_in, in, Cin, inCtot, inOff, ci0, CIC, b, tx0, ty0, tz0, Zs, Hs, Ws, plane);
-    // weights w[co][ci][tap], read along (ci, tap) for coalescing
-    for (int t = tid; t < COT * CIC * TAPS; t += CT) {
-      const int tap = t % TAPS, r = t / TAPS;
-      const int c = r % CIC, co = r / CIC;
-      float v = 0.f;
-      if (ci0 + c < Cin && co0 + co < Cout) v = w[((size_t)(co0 + co) * Cin + ci0 + c) * TAPS + tap];
-      s_w[(tap * CIC + c) * WST + co] = v;
-    }
-    __syncthreads();
+    const int nx = ci0 + CIC;
+    if (nx < ci_hi)                        // the next stage's loads fly during this stage's products
+      stg.load(in_b + (size_t)nx * plane, plane, ci_hi - nx, w_blk + (size_t)(nx / CIC) * Stage<D, KS>::WQ);
 #pragma unroll 1
     for (int tap = 0; tap < TAPS; ++tap) {
       const int kx = tap % KS, ky = (tap / KS) % KS, kz = tap / (KS * KS);
@@ -179,12 +289,34 @@ __global__ __launch_bounds__(CT) void k_conv_fwd(const float* __restrict__ in, i
       for (int r = 0; r < 4; ++r) {
         const int co = co0 + ct * 16 + 4 * lk + r;
         if (co >= Cout) continue;
+        if (part) {
+          part[(((size_t)split * gridDim.z + b) * Cout + co) * plane + q] = acc[ct][pt][r];
+          continue;
+        }
         float v = acc[ct][pt][r] + (bias ? bias[co] : 0.f);
         if (relu) v = fmaxf(v, 0.f);
         float* o = out + ((size_t)b * outCtot + outOff + co) * plane + q;
         if (accumulate) v += *o;
         *o = v;
       }
+  }
+}
+
+// Sum of the split-K partials in split order, then the epilogue of k_conv_fwd.
+__global__ void k_splitk_sum(const float* __restrict__ part, int nsplit, int B, int Cout, size_t plane,
+                             const float* __restrict__ bias, float* __restrict__ out, int outCtot, int outOff, int relu,
+                             int accumulate) {
+  const size_t n = (size_t)B * Cout * plane;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+    const size_t q = t % plane, bc = t / plane;
+    const int co = (int)(bc % Cout), b = (int)(bc / Cout);
+    float v = 0.f;
+    for (int s = 0; s < nsplit; ++s) v += part[(size_t)s * n + t];
+    v += bias ? bias[co] : 0.f;
+    if (relu) v = fmaxf(v, 0.f);
+    float* o = out + ((size_t)b * outCtot + outOff + co) * plane + q;
+    if (accumulate) v += *o;
+    *o = v;
   }
 }
 
@@ -203,10 +335,11 @@ __global__ __launch_bounds__(CT) void k_conv_wgrad(const float* __restrict__ in,
   constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, NP = Tile<D>::NP;
   constexpr int TAPS = H::TAPS;
   constexpr int HS = pad_to(H::N, 2);      // channel stride: the 16 channels of a k row on even banks, the next point odd
+  constexpr int PS = pad_to(NP, 2);        // point stride of s_g: a half-wave reads 16 channels x 2 points conflict-free
   constexpr int NT = 2 * TAPS;             // output tiles (co half, tap)
   constexpr int TPW = (NT + 3) / 4;        // tiles per wave
   __shared__ float s_in[WCI * HS];
-  __shared__ float s_g[NP * WST];          // [point][co]
+  __shared__ float s_g[COT * PS];          // [co][point]
   const int co0 = blockIdx.y * COT, ci0 = blockIdx.z * WCI;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lk = lane >> 4, ln = lane & 15;
@@ -228,7 +361,7 @@ __global__ __launch_bounds__(CT) void k_conv_wgrad(const float* __restrict__ in,
       float v = 0.f;
       if (co0 + co < Cout && gx < Ws && gy < Hs && gz < Zs)
         v = g[((size_t)b * gCtot + gOff + co0 + co) * plane + ((size_t)gz * Hs + gy) * Ws + gx];
-      s_g[p * WST + co] = v;
+      s_g[co * PS + p] = v;
     }
     __syncthreads();
 #pragma unroll
@@ -242,7 +375,7 @@ __global__ __launch_bounds__(CT) void k_conv_wgrad(const float* __restrict__ in,
       for (int k0 = 0; k0 < NP; k0 += 4) {
         const int p = k0 + lk;
         const int px = p % TX, py = (p / TX) % TY, pz = p / (TX * TY);
-        const float a = s_g[p * WST + ct * 16 + ln];
+        const float a = s_g[(ct * 16 + ln) * PS + p];
         const float bv = s_in[ln * HS + (pz * H::Y + py) * H::X + px + toff];
         acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv, acc[i], 0, 0, 0);
       }
@@ -262,24 +395,57 @@ __global__ __launch_bounds__(CT) void k_conv_wgrad(const float* __restrict__ in,
   }
 }
 
-// Sum of the partials over chunks (fixed order) into the gradient (accumulate).
-__global__ void k_reduce_chunks(const float* __restrict__ part, int nchunk, size_t n, float* __restrict__ grad) {
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    float s = 0.f;
-    for (int c = 0; c < nchunk; ++c) s += part[(size_t)c * n + t];
-    grad[t] += s;
+// Fixed-order sum of partials.  Block (x, s) covers the 64 values t in
+// [64 x, 64 x + 64) and the chunks [s cs, min((s + 1) cs, nchunk)) of part[c][t]
+// (n values per chunk); wave w sums the w-th quarter of those chunks in order,
+// and the four quarters are added in order.  The result is added to dst[t]
+// (accumulate) or written to dst[s n + t] (the partials of a second pass).
+constexpr int kSumLanes = 64;
+__global__ __launch_bounds__(CT) void k_sum_chunks(const float* __restrict__ part, int nchunk, int cs, size_t n,
+                                                   float* __restrict__ dst, int accumulate) {
+  __shared__ float red[CT / 64][kSumLanes];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const size_t t = (size_t)blockIdx.x * kSumLanes + lane;
+  const int c_lo = blockIdx.y * cs, len = min(cs, nchunk - c_lo);
+  const int q = (len + 3) / 4;
+  const int a = c_lo + min(len, wave * q), e = c_lo + min(len, (wave + 1) * q);
+  float sum = 0.f;
+  if (t < n) {
+    const float* p = part + t;
+    int c = a;
+    for (; c + 8 <= e; c += 8) {
+      float v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = p[(size_t)(c + k) * n];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) sum += v[k];
+    }
+    for (; c < e; ++c) sum += p[(size_t)c * n];
+  }
+  red[wave][lane] = sum;
+  __syncthreads();
+  if (wave == 0 && t < n) {
+    const float v = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+    if (accumulate)
+      dst[t] += v;
+    else
+      dst[(size_t)blockIdx.y * n + t] = v;
   }
 }
 
-// Bias gradient: db[co] += sum_{b, q} g[b, co, q]  (one block per channel, fixed order)
-__global__ void k_bias_grad(const float* __restrict__ g, int Cout, int gCtot, int gOff, size_t plane, int B,
-                            float* __restrict__ db) {
+// Bias gradient partials: bpart[s][co] = sum of g[b, co, q] over the flat
+// indices i = b plane + q of segment s (len consecutive i), in a fixed order;
+// k_sum_chunks then adds the segments in order.  Grid (segments, Cout).
+__global__ void k_bias_part(const float* __restrict__ g, int Cout, int gCtot, int gOff, size_t plane, int B,
+                            size_t len, float* __restrict__ bpart) {
   __shared__ float red[CT];
-  const int co = blockIdx.x;
+  const int co = blockIdx.y;
+  const size_t n = (size_t)B * plane;
+  const size_t i0 = blockIdx.x * len, i1 = min(n, i0 + len);
   float s = 0.f;
-  for (int b = 0; b < B; ++b) {
-    const float* p = g + ((size_t)b * gCtot + gOff + co) * plane;
-    for (size_t q = threadIdx.x; q < plane; q += CT) s += p[q];
+  for (size_t i = i0 + threadIdx.x; i < i1; i += CT) {
+    const size_t b = i / plane, q = i - b * plane;
+    s += g[(b * gCtot + gOff + co) * plane + q];
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -287,18 +453,7 @@ __global__ void k_bias_grad(const float* __restrict__ g, int Cout, int gCtot, in
     if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0) db[co] += red[0];
-}
-
-// w'[ci][co][tap'] = w[co][ci][taps-1-tap]: the adjoint of a periodic convolution.
-__global__ void k_flip(const float* __restrict__ w, int Cout, int Cin, int taps, float* __restrict__ wf) {
-  const size_t n = (size_t)Cout * Cin * taps;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    const int tap = t % taps;
-    const size_t r = t / taps;
-    const int ci = r % Cin, co = r / Cin;
-    wf[((size_t)ci * Cout + co) * taps + (taps - 1 - tap)] = w[t];
-  }
+  if (threadIdx.x == 0) bpart[(size_t)blockIdx.x * Cout + co] = red[0];
 }
 
 // g <- g * (y > 0) on a view (relu derivative; y is the relu output)
@@ -455,6 +610,7 @@ static int gridn(size_t n) {
 struct Conv {
   int cin, cout, ks;
   size_t w, b;          // offsets into the parameter array
+  size_t pk, pkf;       // offsets of the packed weights and of the packed adjoint weights
   int lvl;              // spatial level of input and output
   View in, out;         // activations
   View gin, gout;       // gradients
@@ -479,9 +635,16 @@ struct Net {
   float* in0;           // input copy
   float* out;           // network output
   float* gout;          // gradient of the output
-  float* wflip;         // flipped weights scratch
+  float* wpk;           // packed weights of every layer (k_pack_w), refreshed by each forward
+  float* wpkf;          // packed adjoint weights (data gradients), refreshed by each backward
+  PackTable fwd_pack, bwd_pack;
+  size_t pack_max;      // largest packed layer (floats)
   float* wpart;         // weight-gradient partials
+  float* bpart;         // bias-gradient partials
+  float* rpart;         // second-level partials of the fixed-order sums
   float* tgt;           // loss targets gathered from sample pointers [batch][cout][plane]
+  float* spart;         // split-K partial sums of the forward convolutions
+  size_t spart_floats;
   float* wgt;           // loss weights gathered from sample pointers [batch][cout][plane]
   size_t wpart_floats;
   double* lpart;        // loss partials
@@ -494,6 +657,73 @@ struct Net {
 };
 
 static size_t plane(const Net& n, int l) { return (size_t)n.sz[l][0] * n.sz[l][1] * n.sz[l][2]; }
+
+// point tiles of one image at level l
+static int tiles_at(const Net& n, int l) {
+  if (n.desc.d == 3)
+    return ((n.sz[l][2] + Tile<3>::X - 1) / Tile<3>::X) * ((n.sz[l][1] + Tile<3>::Y - 1) / Tile<3>::Y) *
+           ((n.sz[l][0] + Tile<3>::Z - 1) / Tile<3>::Z);
+  return ((n.sz[l][2] + Tile<2>::X - 1) / Tile<2>::X) * ((n.sz[l][1] + Tile<2>::Y - 1) / Tile<2>::Y);
+}
+
+// Chunks of point tiles of a weight gradient: about kWgradBlocks blocks in all,
+// at most kMaxWgradChunks partials, none empty.
+static void wgrad_chunks(const Net& n, const Conv& c, int* nchunk, int* per_chunk) {
+  const int ntiles = tiles_at(n, c.lvl) * n.desc.batch;
+  const int blocks = ((c.cout + COT - 1) / COT) * ((c.cin + WCI - 1) / WCI);
+  int want = (kWgradBlocks + blocks - 1) / blocks;
+  want = std::max(1, std::min(std::min(want, kMaxWgradChunks), ntiles));
+  *per_chunk = (ntiles + want - 1) / want;
+  *nchunk = (ntiles + *per_chunk - 1) / *per_chunk;
+}
+
+// Chunks per segment of a fixed-order sum of nchunk partials of n values: about
+// 2048 blocks in all, at least 8 chunks per segment, the segments' partials
+// within kRpartFloats.
+constexpr size_t kRpartFloats = 1 << 18;
+static int sum_segment_chunks(int nchunk, size_t n) {
+  const size_t bx = (n + kSumLanes - 1) / kSumLanes;
+  size_t ns = bx >= 2048 ? 1 : (2048 + bx - 1) / bx;
+  ns = std::min(ns, (size_t)(nchunk + 7) / 8);
+  ns = std::min(ns, kRpartFloats / n);
+  ns = std::max<size_t>(ns, 1);
+  const int cs = (int)((nchunk + ns - 1) / ns);
+  return cs;
+}
+
+// grad[t] += sum over c < nchunk of part[c n + t], in a fixed order.
+static void sum_partials(const Net& n, const float* part, int nchunk, size_t nv, float* grad) {
+  const int cs = sum_segment_chunks(nchunk, nv), ns = (nchunk + cs - 1) / cs;
+  const int bx = (int)((nv + kSumLanes - 1) / kSumLanes);
+  if (ns == 1) {
+    hipLaunchKernelGGL(k_sum_chunks, dim3(bx, 1), dim3(CT), 0, n.st, part, nchunk, cs, nv, grad, 1);
+    return;
+  }
+  hipLaunchKernelGGL(k_sum_chunks, dim3(bx, ns), dim3(CT), 0, n.st, part, nchunk, cs, nv, n.rpart, 0);
+  hipLaunchKernelGGL(k_sum_chunks, dim3(bx, 1), dim3(CT), 0, n.st, n.rpart, ns, ns, nv, grad, 1);
+}
+
+// Segments of a bias gradient: about 2048 values each, at most 256.
+static int bias_segments(const Net& n, const Conv& c, size_t* len) {
+  const size_t tot = (size_t)n.desc.batch * plane(n, c.lvl);
+  const int ns = (int)std::min<size_t>(256, std::max<size_t>(1, (tot + 2047) / 2048));
+  *len = (tot + ns - 1) / ns;
+  return (int)((tot + *len - 1) / *len);
+}
+
+// Input-channel splits of a forward convolution with `blocks` blocks: enough for
+// kSplitBlocks blocks, at most kMaxSplit, at least CIC channels per split, and
+// the partials (nsplit x outputs floats) within the scratch.
+constexpr int kSplitBlocks = 1024, kMaxSplit = 8;
+static int splitk_factor(int blocks, int cin, size_t outputs, size_t scratch_floats) {
+  int ns = 1;
+  while (ns < kMaxSplit && blocks * ns < kSplitBlocks && cin >= 2 * ns * CIC &&
+         (size_t)(2 * ns) * outputs <= scratch_floats)
+    ns *= 2;
+  // with few channels per split the last one may be empty: use as many as the channels fill
+  const int cps = ((cin + ns - 1) / ns + CIC - 1) / CIC * CIC;
+  return (cin + cps - 1) / cps;
+}
 
 // Build the layer list; with base == nullptr only sizes are computed.
 static size_t build_net(Net& n, char* base, size_t* nparams) {
@@ -604,13 +834,58 @@ static size_t build_net(Net& n, char* base, size_t* nparams) {
   conv(c0, ds.cout, 1, 0, cur, o, gcur, go, false, false);
   n.out = o.p;
   n.gout = go.p;
-  // scratch: flipped weights and weight-gradient partials (largest layer), loss partials
-  size_t maxw = 0;
-  for (auto& c : n.convs) maxw = std::max(maxw, (size_t)c.cout * c.cin * (c.ks == 3 ? (d == 3 ? 27 : 9) : 1));
-  n.wflip = take(maxw);
-  n.wpart_floats = (size_t)kWgradChunks * maxw;
+  // packed weights, forward and adjoint (the first layer's adjoint is never used)
+  size_t pk = 0, pkf = 0;
+  n.fwd_pack.n = n.bwd_pack.n = 0;
+  n.pack_max = 0;
+  for (size_t i = 0; i < n.convs.size(); ++i) {
+    Conv& c = n.convs[i];
+    const int taps = c.ks == 3 ? (d == 3 ? 27 : 9) : 1;
+    c.pk = pk;
+    const size_t f = packed_floats(c.cout, c.cin, taps), g = packed_floats(c.cin, c.cout, taps);
+    n.fwd_pack.e[n.fwd_pack.n++] = PackEntry{c.w, pk, c.cout, c.cin, taps, 0};
+    pk += (f + 63) / 64 * 64;
+    n.pack_max = std::max(n.pack_max, f);
+    c.pkf = pkf;
+    if (i > 0) {
+      n.bwd_pack.e[n.bwd_pack.n++] = PackEntry{c.w, pkf, c.cin, c.cout, taps, 1};
+      pkf += (g + 63) / 64 * 64;
+      n.pack_max = std::max(n.pack_max, g);
+    }
+  }
+  n.wpk = take(pk);
+  n.wpkf = take(pkf);
+  // scratch: weight-gradient partials (largest layer), loss partials
+  size_t wp = 0, bp = 0;
+  for (auto& c : n.convs) {
+    int nchunk, per;
+    size_t len;
+    wgrad_chunks(n, c, &nchunk, &per);
+    const int taps = c.ks == 3 ? (d == 3 ? 27 : 9) : 1;
+    wp = std::max(wp, (size_t)nchunk * c.cout * c.cin * taps);
+    bp = std::max(bp, (size_t)bias_segments(n, c, &len) * c.cout);
+  }
+  n.wpart_floats = wp;
   n.wpart = take(n.wpart_floats);
+  n.bpart = take(bp);
+  n.rpart = take(kRpartFloats);
   n.tgt = take((size_t)B * ds.cout * plane(n, 0));
+  // split-K partials: the largest output (B x cout x plane) of a conv whose level gives it fewer
+  // than kSplitBlocks blocks, times kMaxSplit
+  size_t sp = 0;
+  for (auto& c : n.convs) {
+    const int tiles = ((n.sz[c.lvl][2] + Tile<3>::X - 1) / Tile<3>::X) * ((n.sz[c.lvl][1] + Tile<3>::Y - 1) / Tile<3>::Y) *
+                      ((n.sz[c.lvl][0] + Tile<3>::Z - 1) / Tile<3>::Z);
+    const int tiles2 = ((n.sz[c.lvl][2] + Tile<2>::X - 1) / Tile<2>::X) * ((n.sz[c.lvl][1] + Tile<2>::Y - 1) / Tile<2>::Y);
+    const int t = d == 3 ? tiles : tiles2;
+    for (int dir = 0; dir < 2; ++dir) {          // forward (cout outputs) and data gradient (cin outputs)
+      const int co = dir ? c.cin : c.cout;
+      if (t * ((co + COT - 1) / COT) * B < kSplitBlocks)
+        sp = std::max(sp, (size_t)kMaxSplit * B * co * plane(n, c.lvl));
+    }
+  }
+  n.spart_floats = sp;
+  n.spart = sp ? take(sp) : nullptr;
   n.wgt = take((size_t)B * ds.cout * plane(n, 0));
   n.lpart = reinterpret_cast<double*>(take(2 * 8192));
   *nparams = poff;
@@ -618,23 +893,37 @@ static size_t build_net(Net& n, char* base, size_t* nparams) {
 }
 
 template <int D>
+// w: the layer's packed weights (k_pack_w)
 static hipError_t conv_fwd_launch(const Net& n, const View& in, const float* w, const float* b, const View& out,
                                   int cin, int cout, int ks, int lvl, bool relu, bool acc) {
   const int Z = n.sz[lvl][0], H = n.sz[lvl][1], W = n.sz[lvl][2];
   const int tiles = ((W + Tile<D>::X - 1) / Tile<D>::X) * ((H + Tile<D>::Y - 1) / Tile<D>::Y) *
                     ((Z + Tile<D>::Z - 1) / Tile<D>::Z);
-  dim3 grid(tiles, (cout + COT - 1) / COT, n.desc.batch);
+  const int cot = (cout + COT - 1) / COT, B = n.desc.batch;
+  const size_t pl = (size_t)Z * H * W;
+  const int ns = splitk_factor(tiles * cot * B, cin, (size_t)B * cout * pl, n.spart_floats);
+  const int cps = ((cin + ns - 1) / ns + CIC - 1) / CIC * CIC;
+  float* part = ns > 1 ? n.spart : nullptr;
+  dim3 grid(tiles, cot * ns, B);
   if (ks == 3)
     hipLaunchKernelGGL((k_conv_fwd<D, 3>), grid, dim3(CT), 0, n.st, in.p, cin, in.Ctot, in.off, w, b, out.p, cout,
-                       out.Ctot, out.off, Z, H, W, relu ? 1 : 0, acc ? 1 : 0);
+                       out.Ctot, out.off, Z, H, W, relu ? 1 : 0, acc ? 1 : 0, cps, part);
   else
     hipLaunchKernelGGL((k_conv_fwd<D, 1>), grid, dim3(CT), 0, n.st, in.p, cin, in.Ctot, in.off, w, b, out.p, cout,
-                       out.Ctot, out.off, Z, H, W, relu ? 1 : 0, acc ? 1 : 0);
+                       out.Ctot, out.off, Z, H, W, relu ? 1 : 0, acc ? 1 : 0, cps, part);
+  if (ns > 1)
+    hipLaunchKernelGGL(k_splitk_sum, dim3(gridn((size_t)B * cout * pl)), dim3(CT), 0, n.st, part, ns, B, cout, pl, b,
+                       out.p, out.Ctot, out.off, relu ? 1 : 0, acc ? 1 : 0);
   return hipGetLastError();
+}
+
+static void pack_weights(const Net& n, const PackTable& t, float* wp) {
+  if (t.n > 0) hipLaunchKernelGGL(k_pack_w, dim3(gridn(n.pack_max), t.n), dim3(CT), 0, n.st, n.params, t, wp);
 }
 
 template <int D>
 static hipError_t forward(Net& n) {
+  pack_weights(n, n.fwd_pack, n.wpk);
   for (size_t i = 0, pi = 0, ui = 0; i < n.convs.size(); ++i) {
     const Conv& c = n.convs[i];
     // decoder upsampling precedes the first conv of each decoder level
@@ -646,7 +935,7 @@ static hipError_t forward(Net& n) {
                          u.out.Ctot, u.out.off, u.out.C, n.sz[li][0], n.sz[li][1], n.sz[li][2], n.sz[lo][0],
                          n.sz[lo][1], n.sz[lo][2], n.desc.batch);
     }
-    hipError_t e = conv_fwd_launch<D>(n, c.in, n.params + c.w, n.params + c.b, c.out, c.cin, c.cout, c.ks, c.lvl,
+    hipError_t e = conv_fwd_launch<D>(n, c.in, n.wpk + c.pk, n.params + c.b, c.out, c.cin, c.cout, c.ks, c.lvl,
                                       c.relu, false);
     if (e != hipSuccess) return e;
     // pooling follows the second conv of each encoder level
@@ -666,6 +955,7 @@ template <int D>
 static hipError_t backward(Net& n) {
   const int B = n.desc.batch;
   const int d = n.desc.d;
+  pack_weights(n, n.bwd_pack, n.wpkf);
   for (int i = (int)n.convs.size() - 1; i >= 0; --i) {
     const Conv& c = n.convs[i];
     const int l = c.lvl;
@@ -677,11 +967,9 @@ static hipError_t backward(Net& n) {
                          c.gout.off, c.out.Ctot, c.out.off, pl, B);
     }
     // weight gradient: partials over chunks of point tiles, then a fixed-order sum
-    const int tiles_img = ((n.sz[l][2] + Tile<D>::X - 1) / Tile<D>::X) * ((n.sz[l][1] + Tile<D>::Y - 1) / Tile<D>::Y) *
-                          ((n.sz[l][0] + Tile<D>::Z - 1) / Tile<D>::Z);
-    const int ntiles = tiles_img * B;
-    const int nchunk = std::min(ntiles, kWgradChunks);
-    const int per_chunk = (ntiles + nchunk - 1) / nchunk;
+    const int ntiles = tiles_at(n, l) * B;
+    int nchunk, per_chunk;
+    wgrad_chunks(n, c, &nchunk, &per_chunk);
     const size_t nw = (size_t)c.cout * c.cin * taps;
     dim3 gw(nchunk, (c.cout + COT - 1) / COT, (c.cin + WCI - 1) / WCI);
     if (c.ks == 3)
@@ -692,13 +980,15 @@ static hipError_t backward(Net& n) {
       hipLaunchKernelGGL((k_conv_wgrad<D, 1>), gw, dim3(CT), 0, n.st, c.in.p, c.cin, c.in.Ctot, c.in.off, c.gout.p,
                          c.cout, c.gout.Ctot, c.gout.off, n.sz[l][0], n.sz[l][1], n.sz[l][2], ntiles, per_chunk,
                          n.wpart);
-    hipLaunchKernelGGL(k_reduce_chunks, dim3(gridn(nw)), dim3(CT), 0, n.st, n.wpart, nchunk, nw, n.grads + c.w);
-    hipLaunchKernelGGL(k_bias_grad, dim3(c.cout), dim3(CT), 0, n.st, c.gout.p, c.cout, c.gout.Ctot, c.gout.off, pl, B,
-                       n.grads + c.b);
+    sum_partials(n, n.wpart, nchunk, nw, n.grads + c.w);
+    size_t len;
+    const int nseg = bias_segments(n, c, &len);
+    hipLaunchKernelGGL(k_bias_part, dim3(nseg, c.cout), dim3(CT), 0, n.st, c.gout.p, c.cout, c.gout.Ctot, c.gout.off,
+                       pl, B, len, n.bpart);
+    sum_partials(n, n.bpart, nseg, (size_t)c.cout, n.grads + c.b);
     // data gradient (not needed for the input of the network)
     if (i > 0) {
-      hipLaunchKernelGGL(k_flip, dim3(gridn(nw)), dim3(CT), 0, n.st, n.params + c.w, c.cout, c.cin, taps, n.wflip);
-      hipError_t e = conv_fwd_launch<D>(n, c.gout, n.wflip, nullptr, c.gin, c.cout, c.cin, c.ks, l, false,
+      hipError_t e = conv_fwd_launch<D>(n, c.gout, n.wpkf + c.pkf, nullptr, c.gin, c.cout, c.cin, c.ks, l, false,
                                         c.accumulate_gin);
       if (e != hipSuccess) return e;
     }
