@@ -75,25 +75,6 @@ struct Halo {
   static constexpr int TAPS = D == 3 ? KS * KS * KS : KS * KS;
 };
 
-// Stage the periodic halo of a point tile for channels [c0, c0 + nc) of in into s (channel stride HS).
-template <int D, int KS, int HS>
-__device__ __forceinline__ void stage_halo(float* s, const float* __restrict__ in, int Cin, int inCtot, int inOff,
-                                           int c0, int nc, int b, int tx0, int ty0, int tz0, int Zs, int Hs, int Ws,
-                                           size_t plane) {
-  using H = Halo<D, KS>;
-  for (int t = threadIdx.x; t < nc * H::N; t += CT) {
-    const int c = t / H::N, r = t - c * H::N;
-    const int hx = r % H::X, hy = (r / H::X) % H::Y, hz = r / (H::X * H::Y);
-    float v = 0.f;
-    if (c0 + c < Cin) {
-      const int gx = wrap(tx0 + hx - H::R, Ws), gy = wrap(ty0 + hy - H::R, Hs);
-      const int gz = (D == 3) ? wrap(tz0 + hz - H::R, Zs) : 0;
-      v = in[((size_t)b * inCtot + inOff + c0 + c) * plane + ((size_t)gz * Hs + gy) * Ws + gx];
-    }
-    s[c * HS + r] = v;
-  }
-}
-
 // Packed weights of a convolution, in the order the forward kernel stages them:
 // wp[co block][ci stage][tap][c][COT] = w[co][ci][tap] (co = COT block + j,
 // ci = CIC stage + c), zero past Cout and Cin, so that a stage's weights are one
@@ -119,14 +100,14 @@ __global__ void k_pack_w(const float* __restrict__ params, PackTable tab, float*
   const PackEntry e = tab.e[blockIdx.y];
   const int nst = (e.ci + CIC - 1) / CIC;
   const size_t n = packed_floats(e.co, e.ci, e.taps);
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
+  for (unsigned t = blockIdx.x * blockDim.x + threadIdx.x; t < n; t += gridDim.x * blockDim.x) {
     const int j = t % COT;
-    size_t r = t / COT;
+    unsigned r = t / COT;
     const int c = r % CIC;
     r /= CIC;
-    const int tap = r % e.taps;
-    r /= e.taps;
-    const int st = r % nst, cob = r / nst;
+    const int tap = r % (unsigned)e.taps;
+    r /= (unsigned)e.taps;
+    const int st = r % (unsigned)nst, cob = r / (unsigned)nst;
     const int co = cob * COT + j, ci = st * CIC + c;
     float v = 0.f;
     if (co < e.co && ci < e.ci)
@@ -307,18 +288,88 @@ __global__ void k_splitk_sum(const float* __restrict__ part, int nsplit, int B, 
                              const float* __restrict__ bias, float* __restrict__ out, int outCtot, int outOff, int relu,
                              int accumulate) {
   const size_t n = (size_t)B * Cout * plane;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    const size_t q = t % plane, bc = t / plane;
-    const int co = (int)(bc % Cout), b = (int)(bc / Cout);
-    float v = 0.f;
-    for (int s = 0; s < nsplit; ++s) v += part[(size_t)s * n + t];
-    v += bias ? bias[co] : 0.f;
-    if (relu) v = fmaxf(v, 0.f);
-    float* o = out + ((size_t)b * outCtot + outOff + co) * plane + q;
-    if (accumulate) v += *o;
-    *o = v;
+  const int npl = (int)plane;
+  for (int bc = blockIdx.y; bc < B * Cout; bc += gridDim.y) {
+    const int b = bc / Cout, co = bc - b * Cout;
+    const float* pp = part + (size_t)bc * plane;
+    float* o = out + ((size_t)b * outCtot + outOff + co) * plane;
+    const float bv = bias ? bias[co] : 0.f;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npl; q += gridDim.x * blockDim.x) {
+      float v = 0.f;
+      for (int s = 0; s < nsplit; ++s) v += pp[(size_t)s * n + q];
+      v += bv;
+      if (relu) v = fmaxf(v, 0.f);
+      if (accumulate) v += o[q];
+      o[q] = v;
+    }
   }
 }
+
+// One point tile of the weight gradient (the halo of WCI input channels and the
+// output gradient of COT channels at the tile's points), loaded into registers
+// while the previous tile is multiplied, then stored to LDS.  Thread t holds
+// halo points t, t + CT, ... of every channel and point t % NP of channels
+// t / NP + i CT / NP of the gradient; channel offsets are the same for the
+// whole block.
+template <int D, int KS>
+struct WStage {
+  using H = Halo<D, KS>;
+  static constexpr int NP = Tile<D>::NP;
+  static_assert(CT % NP == 0, "whole gradient rows per pass");
+  static constexpr int NJ = (H::N + CT - 1) / CT;
+  static constexpr int NG = COT * NP / CT;
+  int b;
+  int goff[NJ];   // halo point offsets in a channel plane, -1 past the halo
+  int gq;         // this thread's tile point in a channel plane, -1 outside the grid
+  float h[WCI][NJ];
+  float gv[NG];
+
+  __device__ __forceinline__ void init(int tile, int tiles_img, int Zs, int Hs, int Ws) {
+    b = tile / tiles_img;
+    int tx0, ty0, tz0;
+    tile_origin<D>(tile - b * tiles_img, Hs, Ws, &tx0, &ty0, &tz0);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int r = (int)threadIdx.x + j * CT;
+      const int hx = r % H::X, hy = (r / H::X) % H::Y, hz = r / (H::X * H::Y);
+      const int gx = wrap(tx0 + hx - H::R, Ws), gy = wrap(ty0 + hy - H::R, Hs);
+      const int gz = (D == 3) ? wrap(tz0 + hz - H::R, Zs) : 0;
+      goff[j] = r < H::N ? (gz * Hs + gy) * Ws + gx : -1;
+    }
+    const int p = (int)threadIdx.x % NP;
+    const int gx = tx0 + p % Tile<D>::X, gy = ty0 + (p / Tile<D>::X) % Tile<D>::Y, gz = tz0 + p / (Tile<D>::X * Tile<D>::Y);
+    gq = (gx < Ws && gy < Hs && gz < Zs) ? (gz * Hs + gy) * Ws + gx : -1;
+  }
+
+  // in_c: channel ci0 of image b (nci channels exist); g_c: channel co0 of image b (nco exist)
+  __device__ __forceinline__ void load(const float* __restrict__ in_c, int nci, const float* __restrict__ g_c, int nco,
+                                       size_t plane) {
+#pragma unroll
+    for (int c = 0; c < WCI; ++c)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        h[c][j] = (c < nci && goff[j] >= 0) ? in_c[(unsigned)c * (unsigned)plane + (unsigned)goff[j]] : 0.f;
+    const int co_t = (int)threadIdx.x / NP;
+    const unsigned gbase = (unsigned)co_t * (unsigned)plane + (unsigned)gq;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) {
+      const int co = co_t + i * (CT / NP);
+      gv[i] = (co < nco && gq >= 0) ? g_c[gbase + (unsigned)(i * (CT / NP)) * (unsigned)plane] : 0.f;
+    }
+  }
+
+  template <int HS, int PS>
+  __device__ __forceinline__ void store(float* s_in, float* s_g) const {
+#pragma unroll
+    for (int c = 0; c < WCI; ++c)
+#pragma unroll
+      for (int j = 0; j < NJ; ++j)
+        if (goff[j] >= 0) s_in[c * HS + (int)threadIdx.x + j * CT] = h[c][j];
+    const int co_t = (int)threadIdx.x / NP, p = (int)threadIdx.x % NP;
+#pragma unroll
+    for (int i = 0; i < NG; ++i) s_g[(co_t + i * (CT / NP)) * PS + p] = gv[i];
+  }
+};
 
 // Weight gradient partials: dW[co][ci][tap] = sum over points q of
 // g[co, q] in[ci, q + tap], as GEMMs with M = output channels, N = input
@@ -349,21 +400,19 @@ __global__ __launch_bounds__(CT) void k_conv_wgrad(const float* __restrict__ in,
 #pragma unroll
   for (int i = 0; i < TPW; ++i) acc[i] = v4f{0.f, 0.f, 0.f, 0.f};
   const int t0 = blockIdx.x * per_chunk, t1 = min(t0 + per_chunk, ntiles);
+  const int nci = min(WCI, Cin - ci0), nco = min(COT, Cout - co0);
+  WStage<D, KS> stg;
+  auto fetch = [&](int tile) {
+    stg.init(tile, tiles_img, Zs, Hs, Ws);
+    stg.load(in + ((size_t)stg.b * inCtot + inOff + ci0) * plane, nci,
+             g + ((size_t)stg.b * gCtot + gOff + co0) * plane, nco, plane);
+  };
+  if (t0 < t1) fetch(t0);
   for (int tt = t0; tt < t1; ++tt) {
-    const int b = tt / tiles_img;
-    int tx0, ty0, tz0;
-    tile_origin<D>(tt - b * tiles_img, Hs, Ws, &tx0, &ty0, &tz0);
+    __syncthreads();                       // the previous tile's reads of LDS are done
+    stg.template store<HS, PS>(s_in, s_g);
     __syncthreads();
-    stage_halo<D, KS, HS>(s_in, in, Cin, inCtot, inOff, ci0, WCI, b, tx0, ty0, tz0, Zs, Hs, Ws, plane);
-    for (int t = tid; t < COT * NP; t += CT) {
-      const int p = t % NP, co = t / NP;
-      const int gx = tx0 + p % TX, gy = ty0 + (p / TX) % TY, gz = tz0 + p / (TX * TY);
-      float v = 0.f;
-      if (co0 + co < Cout && gx < Ws && gy < Hs && gz < Zs)
-        v = g[((size_t)b * gCtot + gOff + co0 + co) * plane + ((size_t)gz * Hs + gy) * Ws + gx];
-      s_g[co * PS + p] = v;
-    }
-    __syncthreads();
+    if (tt + 1 < t1) fetch(tt + 1);        // the next tile's loads fly during this tile's products
 #pragma unroll
     for (int i = 0; i < TPW; ++i) {
       const int j = wave + 4 * i;
@@ -433,19 +482,18 @@ __global__ __launch_bounds__(CT) void k_sum_chunks(const float* __restrict__ par
   }
 }
 
-// Bias gradient partials: bpart[s][co] = sum of g[b, co, q] over the flat
-// indices i = b plane + q of segment s (len consecutive i), in a fixed order;
-// k_sum_chunks then adds the segments in order.  Grid (segments, Cout).
+// Bias gradient partials: bpart[s][co] = sum of g[b, co, q] over every image b
+// and the points q of segment s (len consecutive points of a plane), in a fixed
+// order; k_sum_chunks then adds the segments in order.  Grid (segments, Cout).
 __global__ void k_bias_part(const float* __restrict__ g, int Cout, int gCtot, int gOff, size_t plane, int B,
-                            size_t len, float* __restrict__ bpart) {
+                            int len, float* __restrict__ bpart) {
   __shared__ float red[CT];
   const int co = blockIdx.y;
-  const size_t n = (size_t)B * plane;
-  const size_t i0 = blockIdx.x * len, i1 = min(n, i0 + len);
+  const int q0 = blockIdx.x * len, q1 = min((int)plane, q0 + len);
   float s = 0.f;
-  for (size_t i = i0 + threadIdx.x; i < i1; i += CT) {
-    const size_t b = i / plane, q = i - b * plane;
-    s += g[(b * gCtot + gOff + co) * plane + q];
+  for (int b = 0; b < B; ++b) {
+    const float* gp = g + ((size_t)b * gCtot + gOff + co) * plane;
+    for (int q = q0 + (int)threadIdx.x; q < q1; q += CT) s += gp[q];
   }
   red[threadIdx.x] = s;
   __syncthreads();
@@ -459,13 +507,13 @@ __global__ void k_bias_part(const float* __restrict__ g, int Cout, int gCtot, in
 // g <- g * (y > 0) on a view (relu derivative; y is the relu output)
 __global__ void k_relu_mask(float* g, const float* y, int C, int gCtot, int gOff, int yCtot, int yOff, size_t plane,
                             int B) {
-  const size_t n = (size_t)B * C * plane;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    const size_t q = t % plane, r = t / plane;
-    const int c = r % C, b = r / C;
-    const float yv = y[((size_t)b * yCtot + yOff + c) * plane + q];
-    float& gv = g[((size_t)b * gCtot + gOff + c) * plane + q];
-    if (!(yv > 0.f)) gv = 0.f;
+  const int npl = (int)plane;
+  for (int bc = blockIdx.y; bc < B * C; bc += gridDim.y) {
+    const int b = bc / C, c = bc - b * C;
+    const float* yp = y + ((size_t)b * yCtot + yOff + c) * plane;
+    float* gp = g + ((size_t)b * gCtot + gOff + c) * plane;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npl; q += gridDim.x * blockDim.x)
+      if (!(yp[q] > 0.f)) gp[q] = 0.f;
   }
 }
 
@@ -473,21 +521,23 @@ __global__ void k_relu_mask(float* g, const float* y, int C, int gCtot, int gOff
 template <int D>
 __global__ void k_pool(const float* __restrict__ in, int inCtot, int inOff, float* __restrict__ out, int outCtot,
                        int outOff, int C, int Z, int H, int W, int Zo, int Ho, int Wo, int B) {
-  const size_t n = (size_t)B * C * Zo * Ho * Wo;
   const float sc = D == 3 ? 0.125f : 0.25f;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    const int x = t % Wo, y = (t / Wo) % Ho, z = (t / ((size_t)Wo * Ho)) % Zo;
-    const size_t r = t / ((size_t)Wo * Ho * Zo);
-    const int c = r % C, b = r / C;
+  const int npo = Zo * Ho * Wo;
+  for (int bc = blockIdx.y; bc < B * C; bc += gridDim.y) {
+    const int b = bc / C, c = bc - b * C;
     const float* src = in + ((size_t)b * inCtot + inOff + c) * ((size_t)Z * H * W);
-    float s = 0.f;
-    for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
-      for (int dy = 0; dy < 2; ++dy)
-        for (int dx = 0; dx < 2; ++dx) {
-          const int gz = D == 3 ? (2 * z + dz) % Z : 0;
-          s += src[((size_t)gz * H + (2 * y + dy) % H) * W + (2 * x + dx) % W];
-        }
-    out[((size_t)b * outCtot + outOff + c) * ((size_t)Zo * Ho * Wo) + ((size_t)z * Ho + y) * Wo + x] = s * sc;
+    float* dst = out + ((size_t)b * outCtot + outOff + c) * (size_t)npo;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npo; q += gridDim.x * blockDim.x) {
+      const int x = q % Wo, y = (q / Wo) % Ho, z = q / (Wo * Ho);
+      float s = 0.f;
+      for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            const int gz = D == 3 ? (2 * z + dz) % Z : 0;
+            s += src[((size_t)gz * H + (2 * y + dy) % H) * W + (2 * x + dx) % W];
+          }
+      dst[q] = s * sc;
+    }
   }
 }
 
@@ -495,28 +545,30 @@ __global__ void k_pool(const float* __restrict__ in, int inCtot, int inOff, floa
 template <int D>
 __global__ void k_pool_bwd(const float* __restrict__ gout, int goCtot, int goOff, float* __restrict__ gin,
                            int giCtot, int giOff, int C, int Z, int H, int W, int Zo, int Ho, int Wo, int B) {
-  const size_t n = (size_t)B * C * Z * H * W;
   const float sc = D == 3 ? 0.125f : 0.25f;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    const int x = t % W, y = (t / W) % H, z = (t / ((size_t)W * H)) % Z;
-    const size_t r = t / ((size_t)W * H * Z);
-    const int c = r % C, b = r / C;
-    // output indices j along an axis of length n (ceil(n/2) outputs) covering input i
-    auto cands = [](int i, int nn, int no, int* js) {
-      int k = 0;
-      js[k++] = i / 2;
-      if ((nn & 1) && i == 0) js[k++] = no - 1;
-      return k;
-    };
-    int jx[2], jy[2], jz[2] = {0, 0};
-    const int nx = cands(x, W, Wo, jx), ny = cands(y, H, Ho, jy);
-    const int nz = D == 3 ? cands(z, Z, Zo, jz) : 1;
+  const int npi = Z * H * W;
+  // output indices j along an axis of length nn (ceil(nn/2) outputs) covering input i
+  auto cands = [](int i, int nn, int no, int* js) {
+    int k = 0;
+    js[k++] = i / 2;
+    if ((nn & 1) && i == 0) js[k++] = no - 1;
+    return k;
+  };
+  for (int bc = blockIdx.y; bc < B * C; bc += gridDim.y) {
+    const int b = bc / C, c = bc - b * C;
     const float* g = gout + ((size_t)b * goCtot + goOff + c) * ((size_t)Zo * Ho * Wo);
-    float s = 0.f;
-    for (int a = 0; a < nz; ++a)
-      for (int bq = 0; bq < ny; ++bq)
-        for (int e = 0; e < nx; ++e) s += g[((size_t)jz[a] * Ho + jy[bq]) * Wo + jx[e]];
-    gin[((size_t)b * giCtot + giOff + c) * ((size_t)Z * H * W) + ((size_t)z * H + y) * W + x] += s * sc;
+    float* dst = gin + ((size_t)b * giCtot + giOff + c) * (size_t)npi;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npi; q += gridDim.x * blockDim.x) {
+      const int x = q % W, y = (q / W) % H, z = q / (W * H);
+      int jx[2], jy[2], jz[2] = {0, 0};
+      const int nx = cands(x, W, Wo, jx), ny = cands(y, H, Ho, jy);
+      const int nz = D == 3 ? cands(z, Z, Zo, jz) : 1;
+      float s = 0.f;
+      for (int a = 0; a < nz; ++a)
+        for (int bq = 0; bq < ny; ++bq)
+          for (int e = 0; e < nx; ++e) s += g[((size_t)jz[a] * Ho + jy[bq]) * Wo + jx[e]];
+      dst[q] += s * sc;
+    }
   }
 }
 
@@ -524,14 +576,16 @@ __global__ void k_pool_bwd(const float* __restrict__ gout, int goCtot, int goOff
 template <int D>
 __global__ void k_up(const float* __restrict__ in, int inCtot, int inOff, float* __restrict__ out, int outCtot,
                      int outOff, int C, int Zi, int Hi, int Wi, int Z, int H, int W, int B) {
-  const size_t n = (size_t)B * C * Z * H * W;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    const int x = t % W, y = (t / W) % H, z = (t / ((size_t)W * H)) % Z;
-    const size_t r = t / ((size_t)W * H * Z);
-    const int c = r % C, b = r / C;
-    const int zi = D == 3 ? z / 2 : 0;
-    out[((size_t)b * outCtot + outOff + c) * ((size_t)Z * H * W) + ((size_t)z * H + y) * W + x] =
-        in[((size_t)b * inCtot + inOff + c) * ((size_t)Zi * Hi * Wi) + ((size_t)zi * Hi + y / 2) * Wi + x / 2];
+  const int npo = Z * H * W;
+  for (int bc = blockIdx.y; bc < B * C; bc += gridDim.y) {
+    const int b = bc / C, c = bc - b * C;
+    const float* src = in + ((size_t)b * inCtot + inOff + c) * ((size_t)Zi * Hi * Wi);
+    float* dst = out + ((size_t)b * outCtot + outOff + c) * (size_t)npo;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npo; q += gridDim.x * blockDim.x) {
+      const int x = q % W, y = (q / W) % H, z = q / (W * H);
+      const int zi = D == 3 ? z / 2 : 0;
+      dst[q] = src[(zi * Hi + y / 2) * Wi + x / 2];
+    }
   }
 }
 
@@ -539,20 +593,22 @@ __global__ void k_up(const float* __restrict__ in, int inCtot, int inOff, float*
 template <int D>
 __global__ void k_up_bwd(const float* __restrict__ gout, int goCtot, int goOff, float* __restrict__ gin, int giCtot,
                          int giOff, int C, int Zi, int Hi, int Wi, int Z, int H, int W, int B) {
-  const size_t n = (size_t)B * C * Zi * Hi * Wi;
-  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < n; t += (size_t)gridDim.x * blockDim.x) {
-    const int x = t % Wi, y = (t / Wi) % Hi, z = (t / ((size_t)Wi * Hi)) % Zi;
-    const size_t r = t / ((size_t)Wi * Hi * Zi);
-    const int c = r % C, b = r / C;
+  const int npi = Zi * Hi * Wi;
+  for (int bc = blockIdx.y; bc < B * C; bc += gridDim.y) {
+    const int b = bc / C, c = bc - b * C;
     const float* g = gout + ((size_t)b * goCtot + goOff + c) * ((size_t)Z * H * W);
-    float s = 0.f;
-    for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
-      for (int dy = 0; dy < 2; ++dy)
-        for (int dx = 0; dx < 2; ++dx) {
-          const int oz = D == 3 ? 2 * z + dz : 0, oy = 2 * y + dy, ox = 2 * x + dx;
-          if (oz < Z && oy < H && ox < W) s += g[((size_t)oz * H + oy) * W + ox];
-        }
-    gin[((size_t)b * giCtot + giOff + c) * ((size_t)Zi * Hi * Wi) + ((size_t)z * Hi + y) * Wi + x] = s;
+    float* dst = gin + ((size_t)b * giCtot + giOff + c) * (size_t)npi;
+    for (int q = blockIdx.x * blockDim.x + threadIdx.x; q < npi; q += gridDim.x * blockDim.x) {
+      const int x = q % Wi, y = (q / Wi) % Hi, z = q / (Wi * Hi);
+      float s = 0.f;
+      for (int dz = 0; dz < (D == 3 ? 2 : 1); ++dz)
+        for (int dy = 0; dy < 2; ++dy)
+          for (int dx = 0; dx < 2; ++dx) {
+            const int oz = D == 3 ? 2 * z + dz : 0, oy = 2 * y + dy, ox = 2 * x + dx;
+            if (oz < Z && oy < H && ox < W) s += g[(oz * H + oy) * W + ox];
+          }
+      dst[q] = s;
+    }
   }
 }
 
@@ -604,6 +660,12 @@ __global__ void k_fill(float* p, size_t n, float v) {
 static int gridn(size_t n) {
   size_t b = (n + CT - 1) / CT;
   return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+
+// Grid of the per-plane elementwise kernels: x over the points of a plane, y over the planes.
+static dim3 plane_grid(size_t pts, int planes) {
+  const size_t bx = std::max<size_t>(1, std::min<size_t>((pts + CT - 1) / CT, 1024));
+  return dim3((unsigned)bx, (unsigned)std::max(1, std::min(planes, 65535)));
 }
 
 // ------------------------------------------------------------------ runtime
@@ -703,12 +765,13 @@ static void sum_partials(const Net& n, const float* part, int nchunk, size_t nv,
   hipLaunchKernelGGL(k_sum_chunks, dim3(bx, 1), dim3(CT), 0, n.st, n.rpart, ns, ns, nv, grad, 1);
 }
 
-// Segments of a bias gradient: about 2048 values each, at most 256.
-static int bias_segments(const Net& n, const Conv& c, size_t* len) {
-  const size_t tot = (size_t)n.desc.batch * plane(n, c.lvl);
-  const int ns = (int)std::min<size_t>(256, std::max<size_t>(1, (tot + 2047) / 2048));
-  *len = (tot + ns - 1) / ns;
-  return (int)((tot + *len - 1) / *len);
+// Segments of a plane for a bias gradient: about 2048 values each (over the
+// batch), at most 256.
+static int bias_segments(const Net& n, const Conv& c, int* len) {
+  const size_t pl = plane(n, c.lvl), tot = (size_t)n.desc.batch * pl;
+  const size_t ns = std::min<size_t>(std::min<size_t>(256, pl), std::max<size_t>(1, (tot + 2047) / 2048));
+  *len = (int)((pl + ns - 1) / ns);
+  return (int)((pl + *len - 1) / *len);
 }
 
 // Input-channel splits of a forward convolution with `blocks` blocks: enough for
@@ -858,8 +921,7 @@ static size_t build_net(Net& n, char* base, size_t* nparams) {
   // scratch: weight-gradient partials (largest layer), loss partials
   size_t wp = 0, bp = 0;
   for (auto& c : n.convs) {
-    int nchunk, per;
-    size_t len;
+    int nchunk, per, len;
     wgrad_chunks(n, c, &nchunk, &per);
     const int taps = c.ks == 3 ? (d == 3 ? 27 : 9) : 1;
     wp = std::max(wp, (size_t)nchunk * c.cout * c.cin * taps);
@@ -912,13 +974,14 @@ static hipError_t conv_fwd_launch(const Net& n, const View& in, const float* w, 
     hipLaunchKernelGGL((k_conv_fwd<D, 1>), grid, dim3(CT), 0, n.st, in.p, cin, in.Ctot, in.off, w, b, out.p, cout,
                        out.Ctot, out.off, Z, H, W, relu ? 1 : 0, acc ? 1 : 0, cps, part);
   if (ns > 1)
-    hipLaunchKernelGGL(k_splitk_sum, dim3(gridn((size_t)B * cout * pl)), dim3(CT), 0, n.st, part, ns, B, cout, pl, b,
+    hipLaunchKernelGGL(k_splitk_sum, plane_grid(pl, B * cout), dim3(CT), 0, n.st, part, ns, B, cout, pl, b,
                        out.p, out.Ctot, out.off, relu ? 1 : 0, acc ? 1 : 0);
   return hipGetLastError();
 }
 
 static void pack_weights(const Net& n, const PackTable& t, float* wp) {
-  if (t.n > 0) hipLaunchKernelGGL(k_pack_w, dim3(gridn(n.pack_max), t.n), dim3(CT), 0, n.st, n.params, t, wp);
+  if (t.n > 0)
+    hipLaunchKernelGGL(k_pack_w, dim3(std::min(gridn(n.pack_max), 512), t.n), dim3(CT), 0, n.st, n.params, t, wp);
 }
 
 template <int D>
@@ -930,8 +993,7 @@ static hipError_t forward(Net& n) {
     if (ui < n.ups.size() && c.in.p == n.ups[ui].out.p) {
       const auto& u = n.ups[ui++];
       const int lo = u.lvl, li = lo + 1;
-      const size_t tot = (size_t)n.desc.batch * u.out.C * plane(n, lo);
-      hipLaunchKernelGGL(k_up<D>, dim3(gridn(tot)), dim3(CT), 0, n.st, u.in.p, u.in.Ctot, u.in.off, u.out.p,
+      hipLaunchKernelGGL(k_up<D>, plane_grid(plane(n, lo), n.desc.batch * u.out.C), dim3(CT), 0, n.st, u.in.p, u.in.Ctot, u.in.off, u.out.p,
                          u.out.Ctot, u.out.off, u.out.C, n.sz[li][0], n.sz[li][1], n.sz[li][2], n.sz[lo][0],
                          n.sz[lo][1], n.sz[lo][2], n.desc.batch);
     }
@@ -942,8 +1004,7 @@ static hipError_t forward(Net& n) {
     if (pi < n.pools.size() && c.out.p == n.pools[pi].in.p && c.out.off == n.pools[pi].in.off) {
       const auto& p = n.pools[pi++];
       const int li = p.lvl, lo = li + 1;
-      const size_t tot = (size_t)n.desc.batch * p.out.C * plane(n, lo);
-      hipLaunchKernelGGL(k_pool<D>, dim3(gridn(tot)), dim3(CT), 0, n.st, p.in.p, p.in.Ctot, p.in.off, p.out.p,
+      hipLaunchKernelGGL(k_pool<D>, plane_grid(plane(n, lo), n.desc.batch * p.out.C), dim3(CT), 0, n.st, p.in.p, p.in.Ctot, p.in.off, p.out.p,
                          p.out.Ctot, p.out.off, p.in.C, n.sz[li][0], n.sz[li][1], n.sz[li][2], n.sz[lo][0],
                          n.sz[lo][1], n.sz[lo][2], n.desc.batch);
     }
@@ -962,8 +1023,7 @@ static hipError_t backward(Net& n) {
     const size_t pl = plane(n, l);
     const int taps = c.ks == 3 ? (d == 3 ? 27 : 9) : 1;
     if (c.relu) {
-      const size_t tot = (size_t)B * c.cout * pl;
-      hipLaunchKernelGGL(k_relu_mask, dim3(gridn(tot)), dim3(CT), 0, n.st, c.gout.p, c.out.p, c.cout, c.gout.Ctot,
+      hipLaunchKernelGGL(k_relu_mask, plane_grid(pl, B * c.cout), dim3(CT), 0, n.st, c.gout.p, c.out.p, c.cout, c.gout.Ctot,
                          c.gout.off, c.out.Ctot, c.out.off, pl, B);
     }
     // weight gradient: partials over chunks of point tiles, then a fixed-order sum
@@ -981,7 +1041,7 @@ static hipError_t backward(Net& n) {
                          c.cout, c.gout.Ctot, c.gout.off, n.sz[l][0], n.sz[l][1], n.sz[l][2], ntiles, per_chunk,
                          n.wpart);
     sum_partials(n, n.wpart, nchunk, nw, n.grads + c.w);
-    size_t len;
+    int len;
     const int nseg = bias_segments(n, c, &len);
     hipLaunchKernelGGL(k_bias_part, dim3(nseg, c.cout), dim3(CT), 0, n.st, c.gout.p, c.cout, c.gout.Ctot, c.gout.off,
                        pl, B, len, n.bpart);
@@ -996,16 +1056,14 @@ static hipError_t backward(Net& n) {
     for (const auto& p : n.pools)
       if (p.out.p == c.in.p) {
         const int li = p.lvl, lo = li + 1;
-        const size_t tot = (size_t)B * p.in.C * plane(n, li);
-        hipLaunchKernelGGL(k_pool_bwd<D>, dim3(gridn(tot)), dim3(CT), 0, n.st, p.gout.p, p.gout.Ctot, p.gout.off,
+        hipLaunchKernelGGL(k_pool_bwd<D>, plane_grid(plane(n, li), B * p.in.C), dim3(CT), 0, n.st, p.gout.p, p.gout.Ctot, p.gout.off,
                            p.gin.p, p.gin.Ctot, p.gin.off, p.in.C, n.sz[li][0], n.sz[li][1], n.sz[li][2],
                            n.sz[lo][0], n.sz[lo][1], n.sz[lo][2], B);
       }
     for (const auto& u : n.ups)
       if (u.out.p == c.in.p) {
         const int lo = u.lvl, li = lo + 1;
-        const size_t tot = (size_t)B * u.in.C * plane(n, li);
-        hipLaunchKernelGGL(k_up_bwd<D>, dim3(gridn(tot)), dim3(CT), 0, n.st, u.gout.p, u.gout.Ctot, u.gout.off,
+        hipLaunchKernelGGL(k_up_bwd<D>, plane_grid(plane(n, li), B * u.in.C), dim3(CT), 0, n.st, u.gout.p, u.gout.Ctot, u.gout.off,
                            u.gin.p, u.gin.Ctot, u.gin.off, u.in.C, n.sz[li][0], n.sz[li][1], n.sz[li][2],
                            n.sz[lo][0], n.sz[lo][1], n.sz[lo][2], B);
       }
