@@ -515,11 +515,18 @@ class Batch:
                 pass
             self.h = None
 
+    def new_fields(self, dual, nl):
+        """Zero fields [[nl tensors] per problem]: views of one allocation."""
+        p0 = self.problems[0]
+        big = torch.zeros((len(self.problems) * nl, p0.flen[int(dual)]), dtype=torch.complex128, device=_dev())
+        self.stream.wait_stream(torch.cuda.current_stream())
+        return [[big[i * nl + l] for l in range(nl)] for i in range(len(self.problems))]
+
     def solve(self, dual=False, E=None, x0=None, tol=1e-6, maxit=10000, out=None, allow_not_converged=False):
         d, n = self.d, len(self.problems)
         E = np.eye(d) if E is None else np.atleast_2d(np.asarray(E, float))
         nl = E.shape[0]
-        fields = out if out is not None else [[p.new_field(dual) for _ in range(nl)] for p in self.problems]
+        fields = out if out is not None else self.new_fields(dual, nl)
         flat = [f for fs in fields for f in fs]
         infos = (L.Info * (n * nl))()
         Ec = np.ascontiguousarray(E.reshape(-1))
@@ -613,7 +620,7 @@ class Batch:
         Mt = int(np.prod(self.problems[0].M))
         stride = nl * self.d * Mt if stride is None else int(stride)
         self._check_span(grids, stride, nl * self.d * Mt)
-        out = [[p.new_field(dual) for _ in range(nl)] for p in self.problems]
+        out = self.new_fields(dual, nl)
         flat = [t for ts in out for t in ts]
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_batch_grid_to_field(self.h, int(dual), nl, C.c_void_p(grids.data_ptr()), stride,
@@ -648,7 +655,7 @@ class Batch:
         key = (bool(dual), nl)
         cache = self.__dict__.setdefault("_field_cache", {})
         if key not in cache:
-            cache[key] = [[p.new_field(dual) for _ in range(nl)] for p in self.problems]
+            cache[key] = self.new_fields(dual, nl)
         return cache[key]
 
     def solve_pair(self, E=None, tol=1e-6, maxit=10000, out_primal=None, out_dual=None, allow_not_converged=False,
@@ -658,8 +665,8 @@ class Batch:
         d, n = self.d, len(self.problems)
         E = np.eye(d) if E is None else np.atleast_2d(np.asarray(E, float))
         nl = E.shape[0]
-        fp = out_primal if out_primal is not None else [[p.new_field(False) for _ in range(nl)] for p in self.problems]
-        fd = out_dual if out_dual is not None else [[p.new_field(True) for _ in range(nl)] for p in self.problems]
+        fp = out_primal if out_primal is not None else self.new_fields(False, nl)
+        fd = out_dual if out_dual is not None else self.new_fields(True, nl)
         ip, idl = (L.Info * (n * nl))(), (L.Info * (n * nl))()
         Ec = np.ascontiguousarray(E.reshape(-1))
         self.stream.wait_stream(torch.cuda.current_stream())

@@ -2092,6 +2092,10 @@ struct hom_batch {
   double* bcollect_dev = nullptr;      // [2][n][9] bounds quadrature sums (workspace)
   CoefJob* jobs_dev = nullptr;         // [n] coefficient set-up table (workspace)
   std::vector<CoefJob> host_jobs;
+  SymJob* xjobs_dev[2] = {nullptr, nullptr};   // [n kMaxLoads] starting-field symmetrisations per side (workspace)
+  std::vector<SymJob> host_xjobs[2];
+  NetJob* njobs_dev = nullptr;         // [n] network-input table (workspace), uploaded once
+  bool njobs_ready = false;
   SolveOut* collect_host = nullptr;    // pinned mirrors
   double* bcollect_host = nullptr;
   double tsum[5] = {0, 0, 0, 0, 0};
@@ -2120,10 +2124,16 @@ static size_t batch_layout(int n, char* base, hom_batch* b) {
   char* cs = take((size_t)2 * n * kMaxLoads * sizeof(SolveOut));
   char* cb = take((size_t)n * 2 * 9 * sizeof(double));
   char* cj = take((size_t)n * sizeof(CoefJob));
+  char* xj0 = take((size_t)n * kMaxLoads * sizeof(SymJob));
+  char* xj1 = take((size_t)n * kMaxLoads * sizeof(SymJob));
+  char* nj = take((size_t)n * sizeof(NetJob));
   if (b) {
     b->collect_dev = (SolveOut*)cs;
     b->bcollect_dev = (double*)cb;
     b->jobs_dev = (CoefJob*)cj;
+    b->xjobs_dev[0] = (SymJob*)xj0;
+    b->xjobs_dev[1] = (SymJob*)xj1;
+    b->njobs_dev = (NetJob*)nj;
   }
   return off;
 }
@@ -2276,11 +2286,31 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, co
       fill_unit(b->pbs[i], k, nload, E, xo + (size_t)i * nload, &b->host_units[k][i]);
       // gap rule: each load reads the same load of the other solve of its cell
       if (gap_rule) b->host_units[k][i].partner_sc = b->pbs[i]->slot[1 - k].sc;
-      if (x0) {
-        bool h = false;
-        hom_status s = prepare_x0(b->pbs[i], k, nload, gk, x0 + (size_t)i * nload, xo + (size_t)i * nload, &h);
-        if (s != HOM_OK) return s;
-        have_x0[k] = have_x0[k] || h;
+    }
+    // starting fields: every given one symmetrised into its output in one launch (a field given
+    // in place goes through the problem's scratch first)
+    if (x0) {
+      auto& jobs = b->host_xjobs[k];
+      jobs.clear();
+      const size_t vbytes = (size_t)gk.m * gk.S * sizeof(Cx<double>);
+      for (int i = 0; i < n; ++i)
+        for (int l = 0; l < nload; ++l) {
+          const double* src = x0[(size_t)i * nload + l];
+          if (!src) continue;
+          double* dst = xo[(size_t)i * nload + l];
+          const Cx<double>* sp = reinterpret_cast<const Cx<double>*>(src);
+          if (src == dst) {
+            Cx<double>* tmp = b->pbs[i]->slot[k].tmp[l];
+            HIPCHK(hipMemcpyAsync(tmp, src, vbytes, hipMemcpyDeviceToDevice, b->stream));
+            sp = tmp;
+          }
+          jobs.push_back(SymJob{sp, reinterpret_cast<Cx<double>*>(dst)});
+        }
+      have_x0[k] = !jobs.empty();
+      if (have_x0[k]) {
+        HIPCHK(hipMemcpyAsync(b->xjobs_dev[k], jobs.data(), jobs.size() * sizeof(SymJob), hipMemcpyHostToDevice,
+                              b->stream));
+        HIPCHK(launch_symmetrize_jobs(gk, b->xjobs_dev[k], (int)jobs.size(), gk.m, b->stream));
       }
     }
     if (have_x0[k])
@@ -2403,18 +2433,20 @@ hom_status hom_batch_net_input(hom_batch* b, float* out, size_t stride, int32_t 
   if (!b || !out || (weights != 0 && weights != 1)) return HOM_E_INVALID;
   const size_t Mt = b->pbs[0]->z.Mt;
   if (stride < 2 * Mt) return HOM_E_INVALID;
-  for (int i = 0; i < b->n; ++i) {
-    hom_problem* pb = b->pbs[i];
-    float* o = out + (size_t)i * stride;
-    if (!weights) {
-      HIPCHK(launch_net_input(pb->coef64[0], pb->z.nc, pb->z.d, (long)Mt, pb->ahat_half[0], (long)pb->z.S, o, 0,
-                              b->stream));
-    } else {
-      for (int k = 0; k < 2; ++k)
-        HIPCHK(launch_net_input(pb->coef64[k], pb->z.nc, pb->z.d, (long)Mt, pb->ahat_half[k], (long)pb->z.S,
-                                o + (size_t)k * Mt, 1, b->stream));
-    }
+  if (!b->njobs_ready) {     // the coefficient pointers of the cells never change: one upload
+    std::vector<NetJob> h(b->n);
+    for (int i = 0; i < b->n; ++i)
+      for (int k = 0; k < 2; ++k) {
+        h[i].coef64[k] = b->pbs[i]->coef64[k];
+        h[i].ahat0[k] = b->pbs[i]->ahat_half[k];
+      }
+    HIPCHK(hipMemcpyAsync(b->njobs_dev, h.data(), (size_t)b->n * sizeof(NetJob), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(hipStreamSynchronize(b->stream));
+    b->njobs_ready = true;
   }
+  const hom_problem* p0 = b->pbs[0];
+  HIPCHK(launch_net_input_jobs(b->njobs_dev, b->n, p0->z.nc, p0->z.d, (long)Mt, (long)p0->z.S, out, stride, weights,
+                               b->stream));
   return HOM_OK;
 }
 

@@ -166,6 +166,12 @@ hipError_t launch_start_vectors(const Geo& g, const UnitDev* units, int nunits, 
 // After the residual of a given start field: the energy decrease from the zero field to it (CgScal::esum).
 hipError_t launch_start_energy(const Geo& g, const UnitDev* units, int nunits, hipStream_t st);
 hipError_t launch_symmetrize(const Geo& g, const Cx<double>* src, Cx<double>* dst, int m, hipStream_t st);
+// The same for many fields of one geometry, one launch.
+struct SymJob {
+  const Cx<double>* src;
+  Cx<double>* dst;
+};
+hipError_t launch_symmetrize_jobs(const Geo& g, const SymJob* jobs, int njobs, int m, hipStream_t st);
 hipError_t launch_advance(const Geo& g, const UnitDev* units, int nunits, int* iter_base, int step,
                           int* active_out, hipStream_t st);
 hipError_t launch_twiddles(Cx<double>* t64, Cx<float>* t32, int M, hipStream_t st);
@@ -173,6 +179,14 @@ hipError_t launch_twiddles(Cx<double>* t64, Cx<float>* t32, int M, hipStream_t s
 hipError_t launch_collect_solve(const UnitDev* units, int n, int L, int nbL, SolveOut* out, hipStream_t st);
 // Per (unit, entry < 9): bounds quadrature partials summed in index order.
 hipError_t launch_collect_bounds(const UnitDev* units, int n, int nbA, double* out, hipStream_t st);
+// Network inputs of n cells of one geometry, cell i at out + i stride (weights:
+// the primal and dual weight channels, k Mt apart), one launch.
+struct NetJob {
+  const double* coef64[2];
+  const Cx<double>* ahat0[2];
+};
+hipError_t launch_net_input_jobs(const NetJob* jobs, int n, int nc, int d, long Mt, long S, float* out, size_t stride,
+                                 int weights, hipStream_t st);
 hipError_t launch_net_input(const double* coef64, int nc, int d, long Mt, const Cx<double>* ahat0, long S, float* out,
                             int weight_only, hipStream_t st);
 hipError_t launch_coef_real(const Cx<double>* full, double* c64, float* c32, long n, hipStream_t st);

@@ -951,7 +951,8 @@ __global__ void k_init_scal(Geo g, const UnitDev* __restrict__ units, int nunits
 
 // Symmetrise a field on the k0 = 0 plane so that it is the spectrum of a real
 // field: x_hat(k) <- (x_hat(k) + conj(x_hat(-k))) / 2, and zero the mean.
-__global__ void k_symmetrize(Geo g, const Cx<double>* __restrict__ src, Cx<double>* __restrict__ dst, int m) {
+__device__ __forceinline__ void symmetrize_field(const Geo& g, const Cx<double>* __restrict__ src,
+                                                 Cx<double>* __restrict__ dst, int m) {
   const int S = g.S;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < S; t += gridDim.x * blockDim.x) {
     const int i2 = t % g.N[2], i1 = (t / g.N[2]) % g.N[1], h0 = t / (g.N[2] * g.N[1]);
@@ -979,6 +980,14 @@ __global__ void k_symmetrize(Geo g, const Cx<double>* __restrict__ src, Cx<doubl
       dst[(size_t)c * S + t] = s;
     }
   }
+}
+__global__ void k_symmetrize(Geo g, const Cx<double>* __restrict__ src, Cx<double>* __restrict__ dst, int m) {
+  symmetrize_field(g, src, dst, m);
+}
+// One field per grid row: jobs[blockIdx.y].
+__global__ void k_symmetrize_jobs(Geo g, const SymJob* __restrict__ jobs, int m) {
+  const SymJob j = jobs[blockIdx.y];
+  symmetrize_field(g, j.src, j.dst, m);
 }
 
 // After a chunk of iterations: advance the iteration base, count active loads
@@ -1342,6 +1351,14 @@ hipError_t launch_symmetrize(const Geo& g, const Cx<double>* src, Cx<double>* ds
   hipLaunchKernelGGL(k_symmetrize, dim3(grid_for(g.S)), dim3(kBlock), 0, st, g, src, dst, m);
   return hipGetLastError();
 }
+hipError_t launch_symmetrize_jobs(const Geo& g, const SymJob* jobs, int njobs, int m, hipStream_t st) {
+  if (njobs < 1) return hipSuccess;
+  const int gx = std::max(1, std::min(grid_for(g.S), std::max(1, 2048 / njobs)));
+  for (int j0 = 0; j0 < njobs; j0 += 65535)
+    hipLaunchKernelGGL(k_symmetrize_jobs, dim3(gx, std::min(65535, njobs - j0)), dim3(kBlock), 0, st, g, jobs + j0,
+                       m);
+  return hipGetLastError();
+}
 
 hipError_t launch_advance(const Geo& g, const UnitDev* units, int nunits, int* iter_base, int step, int* active_out,
                           hipStream_t st) {
@@ -1397,8 +1414,9 @@ hipError_t launch_twiddles(Cx<double>* t64, Cx<float>* t32, int M, hipStream_t s
 // weight_only: one channel max(a, 1e-3 <a>)/<a> (the pointwise weight of the
 // quadrature of the energy, kept positive where the truncated series of a
 // discontinuous coefficient overshoots below zero).
-__global__ void k_net_input(const double* __restrict__ c, int nc, int d, long Mt, const Cx<double>* __restrict__ ahat0,
-                            long S, float* __restrict__ out, int weight_only) {
+__device__ __forceinline__ void net_input_cell(const double* __restrict__ c, int nc, int d, long Mt,
+                                               const Cx<double>* __restrict__ ahat0, long S, float* __restrict__ out,
+                                               int weight_only) {
   const int nd = (nc == 1) ? 1 : d;
   double mean = 0.0;
   for (int k = 0; k < nd; ++k) mean += ahat0[(size_t)k * S].x;
@@ -1415,7 +1433,27 @@ __global__ void k_net_input(const double* __restrict__ c, int nc, int d, long Mt
     }
   }
 }
+__global__ void k_net_input(const double* __restrict__ c, int nc, int d, long Mt, const Cx<double>* __restrict__ ahat0,
+                            long S, float* __restrict__ out, int weight_only) {
+  net_input_cell(c, nc, d, Mt, ahat0, S, out, weight_only);
+}
+// Cell blockIdx.y of a batch into out + cell stride; with weights, blockIdx.z
+// = k selects the primal (0) or dual (1) coefficient and its channel.
+__global__ void k_net_input_jobs(const NetJob* __restrict__ jobs, int nc, int d, long Mt, long S, float* __restrict__ out,
+                                 size_t stride, int weights) {
+  const NetJob j = jobs[blockIdx.y];
+  const int k = blockIdx.z;
+  net_input_cell(j.coef64[k], nc, d, Mt, j.ahat0[k], S, out + blockIdx.y * stride + (size_t)k * Mt, weights);
+}
 
+hipError_t launch_net_input_jobs(const NetJob* jobs, int n, int nc, int d, long Mt, long S, float* out, size_t stride,
+                                 int weights, hipStream_t st) {
+  const int gx = std::max(1, std::min(grid_for(Mt), std::max(1, 4096 / n)));
+  for (int i0 = 0; i0 < n; i0 += 65535)
+    hipLaunchKernelGGL(k_net_input_jobs, dim3(gx, std::min(65535, n - i0), weights ? 2 : 1), dim3(kBlock), 0, st,
+                       jobs + i0, nc, d, Mt, S, out + (size_t)i0 * stride, stride, weights);
+  return hipGetLastError();
+}
 hipError_t launch_net_input(const double* coef64, int nc, int d, long Mt, const Cx<double>* ahat0, long S, float* out,
                             int weight_only, hipStream_t st) {
   hipLaunchKernelGGL(k_net_input, dim3(grid_for(Mt)), dim3(kBlock), 0, st, coef64, nc, d, Mt, ahat0, S, out,
