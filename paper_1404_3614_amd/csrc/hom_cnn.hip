@@ -45,7 +45,6 @@ constexpr int CT = 256;      // threads per block (4 waves)
 constexpr int COT = 32;      // output channels per block
 constexpr int CIC = 8;       // input channels per LDS stage (forward)
 constexpr int WCI = 16;      // input channels per block (weight gradient)
-constexpr int WST = 48;      // LDS row stride of [k][channel] tiles: two k rows of a half-wave 16 banks apart
 constexpr int kWgradBlocks = 2048;      // weight-gradient blocks a layer aims for (chunks of point tiles)
 constexpr int kMaxWgradChunks = 1024;   // weight-gradient partials per layer at most (summed in a fixed order)
 
@@ -168,7 +167,10 @@ struct Stage {
 #pragma unroll
     for (int i = 0; i < NW; ++i) {
       const int f = (int)threadIdx.x + i * CT;
-      if (WQ % CT == 0 || f < WQ) *reinterpret_cast<float4*>(s_w + (f / (COT / 4)) * WST + (f % (COT / 4)) * 4) = w[i];
+      if (WQ % CT == 0 || f < WQ) {
+        const int row = f / (COT / 4), co = (f % (COT / 4)) * 4;
+        *reinterpret_cast<float4*>(s_w + row * COT + ((co + 16 * (row & 1)) & (COT - 1))) = w[i];
+      }
     }
   }
 };
@@ -202,7 +204,10 @@ __global__ __launch_bounds__(CT) void k_conv_fwd(const float* __restrict__ in, i
   constexpr int TAPS = H::TAPS;
   constexpr int HS = pad_to(H::N, 16);     // channel stride: lanes 16..31 read the next channel 16 banks away
   __shared__ float s_in[CIC * HS];
-  __shared__ __align__(16) float s_w[TAPS * CIC * WST];  // [tap][c][co], stored as float4s
+  // [tap][c][co]: rows of COT = 32 channels, odd rows rotated by 16 so that the
+  // two rows read by a half-wave fall on different banks
+  static_assert(COT == 32 && CIC % 2 == 0, "row swizzle");
+  __shared__ __align__(16) float s_w[TAPS * CIC * COT];
   int tx0, ty0, tz0;
   tile_origin<D>(blockIdx.x, Hs, Ws, &tx0, &ty0, &tz0);
   const int cot = (Cout + COT - 1) / COT;
@@ -213,6 +218,7 @@ __global__ __launch_bounds__(CT) void k_conv_fwd(const float* __restrict__ in, i
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int lk = lane >> 4, ln = lane & 15;
   const size_t plane = (size_t)Zs * Hs * Ws;
+  const int wo0 = (ln + 16 * (lk & 1)) & (COT - 1), wo1 = wo0 ^ 16;   // swizzled channels ln, ln + 16
   // the two points of this lane (one per point tile of the wave), as halo offsets of their centres
   int hoff[2];
 #pragma unroll
@@ -240,15 +246,15 @@ __global__ __launch_bounds__(CT) void k_conv_fwd(const float* __restrict__ in, i
     const int nx = ci0 + CIC;
     if (nx < ci_hi)                        // the next stage's loads fly during this stage's products
       stg.load(in_b + (size_t)nx * plane, plane, ci_hi - nx, w_blk + (size_t)(nx / CIC) * Stage<D, KS>::WQ);
-#pragma unroll 1
+#pragma unroll 3
     for (int tap = 0; tap < TAPS; ++tap) {
       const int kx = tap % KS, ky = (tap / KS) % KS, kz = tap / (KS * KS);
       const int toff = (kz * H::Y + ky) * H::X + kx;
 #pragma unroll
       for (int c0 = 0; c0 < CIC; c0 += 4) {
         const int c = c0 + lk;
-        const float* wr = s_w + (tap * CIC + c) * WST + ln;
-        const float a0 = wr[0], a1 = wr[16];
+        const float* wr = s_w + (tap * CIC + c) * COT;
+        const float a0 = wr[wo0], a1 = wr[wo1];
         const float* ir = s_in + c * HS + toff;
         const float b0 = ir[hoff[0]], b1 = ir[hoff[1]];
         acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
