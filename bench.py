@@ -834,18 +834,24 @@ def _c5_class(args, d, N, train_cells, test_cells, net_batch, steps, targets, lr
             batch.solve_bounds(tol=tol)
             x0p, x0d = LL.predict_x0(net, batch)
             batch.solve_bounds(tol=tol, x0_primal=x0p, x0_dual=x0d)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
+        # each solve timed on its own between synchronisations, the median taken: a solve of
+        # a few milliseconds is otherwise at the mercy of one host-side stall
+        reps = max(args.steps, 5)
+        tp, tl = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             plain = batch.solve_bounds(tol=tol)
-        torch.cuda.synchronize()
-        t_plain = (time.perf_counter() - t0) / args.steps
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            tp.append(time.perf_counter() - t0)
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
             x0p, x0d = LL.predict_x0(net, batch)
             learned = batch.solve_bounds(tol=tol, x0_primal=x0p, x0_dual=x0d)
-        torch.cuda.synchronize()
-        t_learned = (time.perf_counter() - t0) / args.steps
+            torch.cuda.synchronize()
+            tl.append(time.perf_counter() - t0)
+        t_plain, t_learned = float(np.median(tp)), float(np.median(tl))
         itp = np.array([[i["iters"] for i in b["info_primal"] + b["info_dual"]] for b in plain])
         itl = np.array([[i["iters"] for i in b["info_primal"] + b["info_dual"]] for b in learned])
         diff = max(max(float(np.abs(b1[k] - b0[k]).max() / np.linalg.norm(b0[k], 2)) for k in ("A_up", "A_low"))
@@ -901,7 +907,9 @@ def run_c5(args):
                  "C5: learned + batched CG, 2D N=63 (doubled grid 125^2) random squares and 3D N=41 (81^3) random "
                  "spheres, contrast 1e2-1e3; U-Net 4 levels x 32 base channels (FP32, MFMA implicit-GEMM "
                  "convolutions) trained on solver fields",
-                 dict(classes=out, value_is="2D class, residual rule, learned + batched"),
+                 dict(classes=out, value_is="2D class, residual rule, learned + batched",
+                      timing="per rule: median over max(steps, 5) solves of all held-out cells, each timed "
+                             "between synchronisations (learned: inference, projection and solve)"),
                  dtype="f32 FFT/apply + f64 CG/bounds; f32 network")
     fw = main["forward"]
     line["roofline"] = dict(bound="mfma", achieved=fw["tflops"], peak=157.3, unit="TFLOP/s",
