@@ -93,11 +93,6 @@ __device__ __forceinline__ ZC<R, A && B> zsub(ZC<R, A> a, ZC<R, B> b) {
   else if constexpr (B) return {a.v};
   else return {sub(a.v, b.v)};
 }
-template <typename R, bool A>
-__device__ __forceinline__ ZC<R, A> zscl(ZC<R, A> a, R c) {
-  if constexpr (A) return {};
-  else return {scl(a.v, c)};
-}
 template <typename R>
 __device__ __forceinline__ R fmx(R a, R b, R c) {
   if constexpr (sizeof(R) == 4) return __builtin_fmaf(a, b, c);
@@ -110,11 +105,12 @@ __device__ __forceinline__ ZC<R, A && B> zaxpy(ZC<R, A> acc, R c, ZC<R, B> t) {
   else if constexpr (A) return {scl(t.v, c)};
   else return {mk(fmx(c, t.v.x, acc.v.x), fmx(c, t.v.y, acc.v.y))};
 }
-// multiply by i
-template <typename R, bool A>
-__device__ __forceinline__ ZC<R, A> zmuli(ZC<R, A> a) {
-  if constexpr (A) return {};
-  else return {mk(-a.v.y, a.v.x)};
+// acc + i c t, as one fused multiply-add per component
+template <typename R, bool A, bool B>
+__device__ __forceinline__ ZC<R, A && B> zaxpyi(ZC<R, A> acc, R c, ZC<R, B> t) {
+  if constexpr (B) return {acc.v};
+  else if constexpr (A) return {mk(-c * t.v.y, c * t.v.x)};
+  else return {mk(fmx(-c, t.v.y, acc.v.x), fmx(c, t.v.x, acc.v.y))};
 }
 template <typename R, bool A>
 __device__ __forceinline__ Cx<R> zval(ZC<R, A> a) {
@@ -132,16 +128,19 @@ __device__ __forceinline__ void dft3(Cx<R>& a0, Cx<R>& a1, Cx<R>& a2) {
   const ZC<R, (Z & 4) != 0> x2{a2};
   const auto t = zadd(x1, x2);
   const auto m = zaxpy(x0, (R)-0.5, t);
-  const auto j = zmuli(zscl(zsub(x1, x2), s3));
+  const auto u = zsub(x1, x2);
   a0 = zval(zadd(x0, t));
-  a1 = zval(zadd(m, j));
-  a2 = zval(zsub(m, j));
+  a1 = zval(zaxpyi(m, s3, u));    // m + i s3 (x1 - x2)
+  a2 = zval(zaxpyi(m, -s3, u));
 }
 
+// The odd part i (s1 t3 + s2 t4) is formed as i s1 (t3 + (s2/s1) t4) and its
+// scale folded into the final sums, so every multiplication is part of an FMA.
 template <typename R, int S, int Z = 0>
 __device__ __forceinline__ void dft5(Cx<R>& a0, Cx<R>& a1, Cx<R>& a2, Cx<R>& a3, Cx<R>& a4) {
   const R c1 = (R)0.30901699437494742410, c2 = (R)-0.80901699437494742410;
   const R s1 = (R)(S * 0.95105651629515357212), s2 = (R)(S * 0.58778525229247312917);
+  const R r21 = (R)0.61803398874989484820, r12 = (R)1.61803398874989484820;   // s2 / s1, s1 / s2
   const ZC<R, (Z & 1) != 0> x0{a0};
   const ZC<R, (Z & 2) != 0> x1{a1};
   const ZC<R, (Z & 4) != 0> x2{a2};
@@ -153,13 +152,13 @@ __device__ __forceinline__ void dft5(Cx<R>& a0, Cx<R>& a1, Cx<R>& a2, Cx<R>& a3,
   const auto t4 = zsub(x2, x3);
   const auto b1 = zaxpy(zaxpy(x0, c1, t1), c2, t2);
   const auto b2 = zaxpy(zaxpy(x0, c2, t1), c1, t2);
-  const auto j1 = zmuli(zaxpy(zscl(t3, s1), s2, t4));
-  const auto j2 = zmuli(zaxpy(zscl(t3, s2), -s1, t4));
+  const auto u1 = zaxpy(t3, r21, t4);    // (s1 t3 + s2 t4) / s1
+  const auto u2 = zaxpy(t3, -r12, t4);   // (s2 t3 - s1 t4) / s2
   a0 = zval(zadd(x0, zadd(t1, t2)));
-  a1 = zval(zadd(b1, j1));
-  a4 = zval(zsub(b1, j1));
-  a2 = zval(zadd(b2, j2));
-  a3 = zval(zsub(b2, j2));
+  a1 = zval(zaxpyi(b1, s1, u1));
+  a4 = zval(zaxpyi(b1, -s1, u1));
+  a2 = zval(zaxpyi(b2, s2, u2));
+  a3 = zval(zaxpyi(b2, -s2, u2));
 }
 
 // Dft<R, N, S>::run(v): in-place DFT of v[0..N-1]; run_z<Z>: the same with
