@@ -593,8 +593,10 @@ hom_status hom_batch_net_input(hom_batch* b, float* out, size_t stride, int32_t 
  * the energies (Lemma integral_eval_double_grid), kept positive.  out: device. */
 hom_status hom_net_weights(hom_problem* pb, float* out);
 
-/* U-Net surrogate (FP32, hand-written kernels): levels, base width, input and
- * output channels, spatial size (2D: H, W; 3D: Z, H, W) and batch. */
+/* U-Net surrogate (FP32, hand-written kernels): levels (1..6), base width
+ * (1..256), input and output channels, spatial size (2D: H, W; 3D: Z, H, W;
+ * each at least 2, at most 2^24 points in all) and batch.  Other values:
+ * HOM_E_INVALID. */
 typedef struct {
   int32_t d;
   int32_t levels;

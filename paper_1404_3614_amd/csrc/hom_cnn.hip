@@ -1096,8 +1096,13 @@ hom_status check_udesc(const hom_unet_desc* d) {
   if (d->d != 2 && d->d != 3) return HOM_E_INVALID;
   if (d->levels < 1 || d->levels > 6 || d->base < 1 || d->base > 256 || d->cin < 1 || d->cout < 1 || d->batch < 1)
     return HOM_E_INVALID;
-  for (int a = 0; a < d->d; ++a)
+  long long pts = 1;
+  for (int a = 0; a < d->d; ++a) {
     if (d->size[a] < 2) return HOM_E_INVALID;
+    pts *= d->size[a];
+  }
+  // the kernels index a channel plane, and 32 planes of it, with 32-bit offsets
+  if (pts > (1LL << 24)) return HOM_E_INVALID;
   return HOM_OK;
 }
 }  // namespace

@@ -200,3 +200,26 @@ def test_tuner_cache_file_roundtrip(tmp_path):
     assert lib.hom_tune_cache_load(str(bad).encode(), b"gfx950", C.byref(n)) == L.HOM_E_INVALID
     assert lib.hom_tune_cache_load(str(tmp_path / "missing").encode(), b"gfx950", C.byref(n)) == L.HOM_E_INVALID
     assert lib.hom_tune_cache_clear() == 0
+
+
+def test_unet_sizes_validation():
+    """hom_unet_sizes (host code): parameters and work memory grow with the
+    width; descriptors outside the documented ranges are refused."""
+    L, lib = _lib()
+    npar, work = C.c_size_t(), C.c_size_t()
+
+    def sizes(d, size, levels=3, base=8, batch=2):
+        ds = L.UNetDesc(d, levels, base, 2, 4, (C.c_int32 * 3)(*size), batch)
+        st = lib.hom_unet_sizes(C.byref(ds), C.byref(npar), C.byref(work))
+        return st, npar.value, work.value
+
+    st, p8, w8 = sizes(2, (33, 33, 0))
+    assert st == 0 and p8 > 0 and w8 > 0
+    st, p16, w16 = sizes(2, (33, 33, 0), base=16)
+    assert st == 0 and p16 > 3 * p8 and w16 > w8
+    assert sizes(3, (17, 17, 17))[0] == 0
+    assert sizes(2, (4096, 4096, 0))[0] == 0                  # 2^24 points: the largest plane
+    assert sizes(2, (4097, 4096, 0))[0] == L.HOM_E_INVALID
+    assert sizes(2, (1, 33, 0))[0] == L.HOM_E_INVALID
+    assert sizes(2, (33, 33, 0), levels=7)[0] == L.HOM_E_INVALID
+    assert sizes(4, (33, 33, 33))[0] == L.HOM_E_INVALID
