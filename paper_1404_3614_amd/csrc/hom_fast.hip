@@ -1153,7 +1153,7 @@ template <>
 struct Cands<625> {
   static constexpr int G[3] = {2, 1, 4};
   static constexpr int TP[2] = {8, 4};
-  static constexpr ApC AP2[6] = {{8, 0, 0}, {10, 1, 0}, {5, 1, 0}, {4, 0, 0}, {10, 1, 1}, {5, 1, 1}};
+  static constexpr ApC AP2[6] = {{8, 0, 0}, {10, 1, 0}, {20, 1, 0}, {5, 1, 0}, {10, 1, 1}, {5, 1, 1}};
 };
 template <>
 struct Cands<125> {

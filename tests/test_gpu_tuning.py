@@ -23,7 +23,7 @@ SHAPES = {
     125: ([(4, 0), (2, 0), (1, 0), (2, 256), (1, 256)],
           [(10, 0, 0), (5, 0, 0), (10, 1, 0), (5, 1, 0), (5, 0, 1), (5, 1, 1)]),
     625: ([(2, 0), (1, 0), (4, 0), (2, 256), (1, 256)],
-          [(8, 0, 0), (10, 1, 0), (5, 1, 0), (4, 0, 0), (10, 1, 1), (5, 1, 1)]),
+          [(8, 0, 0), (10, 1, 0), (20, 1, 0), (5, 1, 0), (10, 1, 1), (5, 1, 1)]),
 }
 
 
