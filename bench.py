@@ -50,7 +50,7 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-cells", type=int, default=1)
+    ap.add_argument("--cpu-cells", type=int, default=2, help="C2 cells the CPU oracle solves (about 6 s each)")
     ap.add_argument("--no-plain", action="store_true", help="skip the one-cell-at-a-time comparison leg")
     ap.add_argument("--no-energy", action="store_true", help="skip the guaranteed-energy-rule leg")
     ap.add_argument("--no-fp64", action="store_true", help="skip the all-FP64 leg of the same cells")
