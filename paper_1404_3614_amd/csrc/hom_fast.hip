@@ -1447,6 +1447,22 @@ static hipError_t tune_m(const Geo& g0, const UnitDev* units, int n, hipStream_t
   if (e == hipSuccess && apply_supported(M, g0.d, g0.P, g0.nc) && g0.M[0] == M) {
     double bms = 1e30;
     const int ncand = g0.d == 2 ? kAp2 : 2;
+    // 2D: each candidate is timed after the row pass that writes its input (in the chosen row
+    // shape), as in a solve; timed alone, the column pass finds its input in the caches and
+    // ranks the shapes differently.  The row pass's own time is subtracted.
+    const bool with_first = g0.d == 2 && row_supported(M, g0.d, g0.L) && t.rowG > 0;
+    Geo gr = g0;
+    float first_ms = 0.f;
+    if (with_first) {
+      gr.rowG = t.rowG;
+      gr.rowThreads = t.rowThreads;
+      gr.nbF = gr.nbL = (gr.Q + gr.rowG - 1) / gr.rowG;
+      e = time_ms(st, reps, &first_ms, [&]() -> hipError_t {
+        hipError_t x = hipSuccess;
+        if (!fast_row(true, gr, units, n, FIRST_PROF, 0, nullptr, st, &x)) return hipErrorInvalidValue;
+        return x;
+      });
+    }
     for (int ci = 0; ci < ncand && e == hipSuccess; ++ci) {
       Geo g = g0;
       g.apTP = g0.d == 2 ? Cands<M>::AP2[ci].tp : Cands<M>::TP[ci];
@@ -1456,9 +1472,12 @@ static hipError_t tune_m(const Geo& g0, const UnitDev* units, int n, hipStream_t
       float ms = 0.f;
       e = time_ms(st, reps, &ms, [&]() -> hipError_t {
         hipError_t x = hipSuccess;
+        if (with_first && !fast_row(true, gr, units, n, FIRST_PROF, 0, nullptr, st, &x)) return hipErrorInvalidValue;
+        if (x != hipSuccess) return x;
         if (!fast_apply(g, units, n, 0, st, &x)) return hipErrorInvalidValue;
         return x;
       });
+      ms -= first_ms;
       ++cand;
       if (e == hipSuccess && ms < bms) {
         bms = ms;
