@@ -64,7 +64,8 @@ def parse():
                          "(energy: extrapolated tail; guaranteed: Gauss-Radau bound)")
     ap.add_argument("--etol", type=float, default=1e-7,
                     help="energy rules: remaining energy decrease / energy of the iterate")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4", "c5", "e1", "e2", "e3"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "e1", "e2", "e3"])
+    ap.add_argument("--c3-cells", type=int, default=64, help="c3: cells per batch (C3a and C3b each)")
     ap.add_argument("--c4-mode", default="streams", choices=["graph", "streams", "threads"],
                     help="c4: one captured graph for all classes per chunk, every solve's own graph from one "
                          "host loop, or a host thread per class")
@@ -371,6 +372,8 @@ def main():
 
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    if args.workload == "c3":
+        return run_c3(args)
     if args.workload == "c4":
         return run_c4(args)
     if args.workload == "c5":
@@ -638,6 +641,90 @@ def _line(args, value, dt, steps, workload, extra_cfg, dtype=None):
                                               stop=args.stop, etol=args.etol if args.stop != "residual" else None,
                                               **extra_cfg),
                 roofline=None)
+
+
+def _c3_variant(args, anisotropic):
+    """One 3D class of the C3 geometry (20 spheres, N = 41): a lockstep batch of
+    args.c3_cells cells (cell 0 the configuration's own, the others new seeds),
+    solved args.steps times; then the same solves with every kernel between HIP
+    events for the per-pass durations."""
+    import numpy as np
+    import torch
+    import homgen
+    import paper_1404_3614_amd as H
+    N = (41, 41, 41)
+    name = "C3b" if anisotropic else "C3a"
+    cells = [homgen.sphere_cell(1404003 + 100003 * i, n=20, anisotropic=anisotropic, rho=10.0)
+             for i in range(args.c3_cells)]
+    stream = torch.cuda.Stream()
+    probs = [H.problem_from_cell(c, N, precision=args.precision, stream=stream) for c in cells]
+    batch = H.Batch(probs)
+    rng = [H.cell_eig_range(c) for c in cells]
+    batch.set_stop(args.stop, args.etol, min(r[0] for r in rng), max(r[1] for r in rng))
+    for _ in range(max(1, args.warmup)):
+        batch.solve_bounds(tol=args.tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        res = batch.solve_bounds(tol=args.tol)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    batch.set_timing(True)
+    for _ in range(args.steps):
+        batch.solve_bounds(tol=args.tol)
+    torch.cuda.synchronize()
+    avg_ms, launches = batch.get_timing()
+    batch.set_timing(False)
+    unit_launches = args.steps * sum(max(i["iters"] for i in cell[key]) + 1
+                                     for cell in res for key in ("info_primal", "info_dual"))
+    pbytes = pass_bytes(probs[0], 3)
+    per_pass = {}
+    for k in ("first", "mid_inv", "apply", "mid_fwd", "last"):
+        if launches[k]:
+            b = unit_launches * pbytes[k] / launches[k]
+            per_pass[k] = dict(ms_per_launch=round(avg_ms[k], 5), bytes_per_launch=int(b),
+                               gbs=round(b / (avg_ms[k] * 1e-3) / 1e9, 1), launches=launches[k])
+    dom = max(per_pass, key=lambda k: per_pass[k]["ms_per_launch"] * per_pass[k]["launches"])
+    iters = [[i["iters"] for i in cell["info_primal"] + cell["info_dual"]] for cell in res]
+    ref = golden(name)
+    return dict(variant=name, cells=args.c3_cells, coefficient="10 I in I" if not anisotropic else
+                "per-sphere SPD, eigenvalues log-uniform in [0.1, 10]",
+                bound_pairs_per_s=round(args.c3_cells * args.steps / dt, 3), ms_per_step=round(1e3 * dt / args.steps, 3),
+                cg_iters_cell0=iters[0], cg_iters_max=int(np.max(iters)),
+                bound_error_vs_oracle=dict(cell=0, reference=f"oracle, CG to 1e-11 (tests/golden/reference_bounds.json "
+                                                              f"{name})", **(bound_error(res[0], ref) or {})),
+                per_pass=per_pass, dominant=dom)
+
+
+def run_c3(args):
+    """C3: the 3D hot path on its own, lockstep batches of the configuration's
+    sphere geometry (isotropic C3a, the value; anisotropic C3b beside it); the
+    roofline of the dominant pass of C3a (HBM-bound: every 3D pass streams the
+    doubled-grid intermediate)."""
+    out = {}
+    for aniso in (False, True):
+        r = _c3_variant(args, aniso)
+        out[r["variant"]] = r
+        print(f"[c3] {r['variant']}: {r['bound_pairs_per_s']} bound pairs/s, iterations of cell 0 {r['cg_iters_cell0']}, "
+              f"bound error vs oracle {r['bound_error_vs_oracle']}", file=sys.stderr, flush=True)
+    a = out["C3a"]
+    dom = a["dominant"]
+    pp = a["per_pass"][dom]
+    line = _line(args, a["bound_pairs_per_s"], a["ms_per_step"] * 1e-3 * args.steps, args.steps,
+                 "C3: 3D N=41 (doubled grid 81^3), 20 random spheres, 3 loads, primal+dual, lockstep batch of "
+                 f"{args.c3_cells} cells (C3a 10 I inclusions, the value; C3b anisotropic SPD beside it)",
+                 dict(variants=out))
+    names = dict(first="k_first_fast (row pass of the last axis)", mid_inv="k_mid_fast (middle axis, inverse)",
+                 apply="k_apply_fast (column pass: inverse FFT, coefficient, forward FFT)",
+                 mid_fwd="k_mid_fast (middle axis, forward)", last="k_last_fast (row pass of the last axis)")
+    line["roofline"] = dict(bound="hbm", achieved=pp["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
+                            frac=round(pp["gbs"] / HBM_PEAK_GBS, 4), bytes_per_launch=pp["bytes_per_launch"],
+                            traffic=None, kernel=f"{names[dom]} of C3a", ms_per_launch=pp["ms_per_launch"],
+                            per_pass=a["per_pass"],
+                            bytes_model="pass_bytes() in bench.py; units per launch = active cells of the batch",
+                            timed_region="a second run of the same solves, kernels launched directly by "
+                                         "hipExtLaunchKernelGGL with start/stop HIP events on the library stream")
+    print(json.dumps(line), flush=True)
 
 
 def run_c4(args):

@@ -277,6 +277,7 @@ class Problem:
         L.check(L.load().hom_update_coefficients(self.h, C.c_void_p(Ahat.data_ptr()), C.c_void_p(Bhat.data_ptr())),
                 "hom_update_coefficients")
         self._coef_refs = (Ahat, Bhat)
+        _join(self.stream)
 
     def new_field(self, dual=False):
         t = torch.zeros(self.flen[int(dual)], dtype=torch.complex128, device=_dev())
@@ -317,6 +318,7 @@ class Problem:
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_apply(self.h, int(dual), C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())),
                 "hom_apply")
+        _join(self.stream)
         return y
 
     def dual_start(self, primal, Abar):
@@ -328,6 +330,7 @@ class Problem:
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_dual_start(self.h, _dptrs(primal), A.ctypes.data_as(C.POINTER(C.c_double)),
                                         _dptrs(out)), "hom_dual_start")
+        _join(self.stream)
         return out
 
     def profile_passes(self, dual=False, nload=None, reps=20):
@@ -348,6 +351,7 @@ class Problem:
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_field_to_grid(self.h, int(dual), n, _dptrs(fields), C.c_void_p(out.data_ptr())),
                 "hom_field_to_grid")
+        _join(self.stream)
         return out
 
     def grid_to_field(self, grid, dual=False):
@@ -358,6 +362,7 @@ class Problem:
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_grid_to_field(self.h, int(dual), n, C.c_void_p(grid.data_ptr()), _dptrs(out)),
                 "hom_grid_to_field")
+        _join(self.stream)
         return out
 
     def net_input(self, out=None):
@@ -366,6 +371,7 @@ class Problem:
             out = torch.empty((2,) + self.M, dtype=torch.float32, device=_dev())
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_net_input(self.h, C.c_void_p(out.data_ptr())), "hom_net_input")
+        _join(self.stream)
         return out
 
     def set_gani(self, AN, BN, grid=None):
@@ -431,6 +437,7 @@ class Problem:
             out = torch.empty((2,) + self.M, dtype=torch.float32, device=_dev())
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_net_weights(self.h, C.c_void_p(out.data_ptr())), "hom_net_weights")
+        _join(self.stream)
         return out
 
     def solve_bounds(self, tol=1e-6, maxit=10000, allow_not_converged=False):
@@ -466,6 +473,13 @@ def tune_cache_save(path, arch=None):
 
 def tune_cache_clear():
     L.check(L.load().hom_tune_cache_clear(), "hom_tune_cache_clear")
+
+
+def _join(stream):
+    """Order later work of the caller's current stream after what was queued on
+    `stream`: outputs of an asynchronous call are then ready for it, and inputs
+    it frees stay untouched until the call has read them."""
+    torch.cuda.current_stream().wait_stream(stream)
 
 
 def _tuning_dict(t):
@@ -610,6 +624,7 @@ class Batch:
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_batch_field_to_grid(self.h, int(dual), nl, _dptrs(flat), C.c_void_p(out.data_ptr()),
                                                  stride), "hom_batch_field_to_grid")
+        _join(self.stream)
         return out
 
     def grid_to_field(self, grids, dual, nload=None, stride=None):
@@ -625,6 +640,7 @@ class Batch:
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_batch_grid_to_field(self.h, int(dual), nl, C.c_void_p(grids.data_ptr()), stride,
                                                  _dptrs(flat)), "hom_batch_grid_to_field")
+        _join(self.stream)
         return out
 
     def net_input(self, out, stride=None, weights=False):
@@ -636,7 +652,7 @@ class Batch:
         self.stream.wait_stream(torch.cuda.current_stream())
         L.check(L.load().hom_batch_net_input(self.h, C.c_void_p(out.data_ptr()), stride, int(bool(weights))),
                 "hom_batch_net_input")
-        torch.cuda.current_stream().wait_stream(self.stream)
+        _join(self.stream)
         return out
 
     def update_coefficients(self, coefs):
@@ -649,6 +665,7 @@ class Batch:
         L.check(L.load().hom_batch_update_coefficients(self.h, A, B), "hom_batch_update_coefficients")
         for p, c in zip(self.problems, coefs):
             p._coef_refs = (c[0], c[1])   # the setup reads them asynchronously
+        _join(self.stream)
 
     def _fields(self, dual, nl):
         """Output fields of solve_bounds, allocated once per (dual, loads) and reused."""

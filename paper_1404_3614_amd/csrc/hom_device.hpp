@@ -52,6 +52,39 @@ __device__ __forceinline__ double wave_sum_arr(const double* __restrict__ p, int
   return __shfl(s, 0, 64);
 }
 
+// wave_sum_arr over L rows of n values each (row w at p + w * stride), the
+// result of row w in s[w] on every lane.  Each lane's loads of one trip (four
+// per row) are all issued before the first add, so a short row costs one
+// memory round trip instead of one per element; the additions keep
+// wave_sum_arr's order, so the sums are the same to the bit.
+template <int L>
+__device__ __forceinline__ void wave_sum_rows(const double* __restrict__ p, size_t stride, int n, double (&s)[L]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int w = 0; w < L; ++w) s[w] = 0.0;
+  for (int base = 0; base < n; base += 256) {
+    double v[L][4];
+#pragma unroll
+    for (int w = 0; w < L; ++w)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = base + lane + 64 * j;
+        v[w][j] = i < n ? p[w * stride + i] : 0.0;
+      }
+#pragma unroll
+    for (int w = 0; w < L; ++w)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (base + lane + 64 * j < n) s[w] += v[w][j];
+  }
+#pragma unroll
+  for (int w = 0; w < L; ++w) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s[w] += __shfl_down(s[w], off, 64);
+    s[w] = __shfl(s[w], 0, 64);
+  }
+}
+
 // Sum over the block in a fixed order; every thread must call it.
 __device__ __forceinline__ double block_sum(double v, double* sred) {
 #pragma unroll
@@ -165,9 +198,23 @@ __host__ __device__ __forceinline__ size_t align16(size_t b) { return (b + 15) &
 // of them), with a factor 2 of margin; the rule stops when it is below etol
 // times the current energy.  It is an extra exit beside the residual rule,
 // which still ends solves that are exact from the start.
-__device__ __forceinline__ void energy_record(CgScal* sc, int j, double dec) {
-  sc->edec[j & 3] = dec;
-  sc->esum += dec;
+// Copy of the CG states of L consecutive loads into shared memory, read by
+// every thread of the block at once (one word each); the block synchronises
+// before using it.
+template <int L>
+__device__ __forceinline__ void copy_states(const CgScal* __restrict__ src, CgScal* dst, int tid, int nthr) {
+  static_assert(sizeof(CgScal) % 8 == 0, "CG state is a whole number of 8-byte words");
+  constexpr int W = (int)(sizeof(CgScal) / 8);
+  const unsigned long long* s = reinterpret_cast<const unsigned long long*>(src);
+  unsigned long long* d = reinterpret_cast<unsigned long long*>(dst);
+  for (int i = tid; i < L * W; i += nthr) d[i] = s[i];
+}
+
+// The state is read from r and written to w (the same record, or a copy of it
+// taken before the writes).
+__device__ __forceinline__ void energy_record(const CgScal* r, CgScal* w, int j, double dec) {
+  w->edec[j & 3] = dec;
+  w->esum = r->esum + dec;
 }
 
 __device__ __forceinline__ bool energy_converged(const CgScal* sc, int it) {
@@ -228,22 +275,23 @@ __device__ __forceinline__ bool gap_converged(const CgScal* sc, int it, double o
   return dlow > 0.0 && own <= sc->etol * dlow;
 }
 
-// Stopping test of iteration it with gamma = gam; the writer thread keeps the
-// state of the guaranteed and gap rules (parity-buffered: other blocks of the
-// same launch read the previous iteration's entry).
-__device__ __forceinline__ bool stop_test(CgScal* sc, int it, double gam, bool writer) {
+// Stopping test of iteration it with gamma = gam, on the state sc; the writer
+// thread (w not null) keeps the state of the guaranteed and gap rules in w
+// (parity-buffered: other blocks of the same launch read the previous
+// iteration's entry).
+__device__ __forceinline__ bool stop_test(const CgScal* sc, CgScal* w, int it, double gam) {
   bool conv = sqrt(gam) <= sc->tol * sc->normE;
   if (sc->stop == 1) {
     conv = conv || energy_converged(sc, it);
   } else if (sc->stop == 2) {
     const double ph = radau_phi(sc, it, gam);
-    if (writer) sc->phi[it & 1] = ph;
+    if (w) w->phi[it & 1] = ph;
     conv = conv || gam * ph <= sc->etol * (sc->energy0 - sc->esum);
   } else if (sc->stop == 3) {
     const double ph = radau_phi(sc, it, gam);
-    if (writer) {
-      sc->phi[it & 1] = ph;
-      sc->rem = gam * ph;
+    if (w) {
+      w->phi[it & 1] = ph;
+      w->rem = gam * ph;
     }
     conv = conv || gap_converged(sc, it, gam * ph);
   }

@@ -766,6 +766,7 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_first_fast(Geo g, const
   __shared__ int s_act[kMaxLoads];
   __shared__ double s_red[16];
   __shared__ RowInfo s_row[G];
+  __shared__ CgScal s_sc[L];
   const UnitDev& U = units[blockIdx.z];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int N1 = g.N[1];
@@ -773,31 +774,48 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_first_fast(Geo g, const
   Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem);                          // [M]
   Cx<R>* stage = reinterpret_cast<Cx<R>*>(smem + align16(M * sizeof(Cx<R>)));  // [2G][P][M]
 
+  // CG scalars of the step: the states of the block's loads and the sums of the
+  // <p, C p> partials of the last pass are read at once, ahead of the set-up
+  double delta[L];
+#pragma unroll
+  for (int w = 0; w < L; ++w) delta[w] = 0.0;
+  if (mode == FIRST_CG) {
+    copy_states<L>(U.sc + lo, s_sc, tid, nthr);
+    if (tid < 64) wave_sum_rows<L>(U.part_d + (size_t)lo * g.nbL, g.nbL, g.nbL, delta);
+  }
+  if (tid < G) row_info(g, blockIdx.x * G + tid, s_row[tid]);
+  const Cx<R>* twg = reinterpret_cast<const Cx<R>*>(g.tw[2]);
+  for (int i = tid; i < M; i += nthr) tw[i] = twg[i];
+  for (int i = tid; i < 2 * G * P * M; i += nthr) stage[i] = rf::mk<R>(0, 0);
+  __syncthreads();
+  // alpha_{it-1} = gamma_{it-1} / delta_{it-1} per load, from the shared copy of
+  // its state; block 0 records the step in the state itself
   if (tid < 64) {
     const int lane = tid;
+#pragma unroll
     for (int w = 0; w < L; ++w) {
       int act = 1;
       double alpha = 0.0;
       if (mode == FIRST_CG) {
-        CgScal* sc = U.sc + lo + w;
+        const CgScal* sc = &s_sc[w];
+        CgScal* out = (blockIdx.x == 0 && lane == 0) ? U.sc + lo + w : nullptr;
         act = (sc->status == 0);
         if (act && it > 0) {
-          const double delta = wave_sum_arr(U.part_d + (size_t)(lo + w) * g.nbL, g.nbL);
           const double gam = sc->gamma[(it - 1) & 1];
-          double den = delta;
-          if (it > 1) den = delta - sc->beta[(it - 1) & 1] * gam / sc->alpha[(it - 2) & 1];
+          double den = delta[w];
+          if (it > 1) den = delta[w] - sc->beta[(it - 1) & 1] * gam / sc->alpha[(it - 2) & 1];
           if (!(den > 0.0)) {
             act = 0;
-            if (blockIdx.x == 0 && lane == 0) {
-              sc->status = -3;
-              sc->iters = it - 1;
-              sc->gamma_last = gam;
+            if (out) {
+              out->status = -3;
+              out->iters = it - 1;
+              out->gamma_last = gam;
             }
           } else {
             alpha = gam / den;
-            if (blockIdx.x == 0 && lane == 0) {
-              sc->alpha[(it - 1) & 1] = alpha;
-              energy_record(sc, it - 1, alpha * gam);
+            if (out) {
+              out->alpha[(it - 1) & 1] = alpha;
+              energy_record(sc, out, it - 1, alpha * gam);
             }
           }
         }
@@ -808,10 +826,6 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_first_fast(Geo g, const
       }
     }
   }
-  if (tid < G) row_info(g, blockIdx.x * G + tid, s_row[tid]);
-  const Cx<R>* twg = reinterpret_cast<const Cx<R>*>(g.tw[2]);
-  for (int i = tid; i < M; i += nthr) tw[i] = twg[i];
-  for (int i = tid; i < 2 * G * P * M; i += nthr) stage[i] = rf::mk<R>(0, 0);
   __syncthreads();
   if (mode == FIRST_CG) {
     int any = 0;
@@ -952,6 +966,7 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
   __shared__ int s_act[kMaxLoads];
   __shared__ double s_red[16];
   __shared__ RowInfo s_row[G];
+  __shared__ CgScal s_sc[L];
   const UnitDev& U = units[blockIdx.z];
   const int tid = threadIdx.x, nthr = blockDim.x;
   const int N1 = g.N[1];
@@ -959,32 +974,49 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
   Cx<R>* tw = reinterpret_cast<Cx<R>*>(smem);                                   // [M]
   Cx<R>* stage = reinterpret_cast<Cx<R>*>(smem + align16(M * sizeof(Cx<R>)));  // [2G][P][M]
 
+  // the states of the block's loads and the sums of the <r, r> partials of the
+  // first pass, read at once
+  double gsum[L];
+#pragma unroll
+  for (int w = 0; w < L; ++w) gsum[w] = 0.0;
+  if (mode == LAST_CG) {
+    copy_states<L>(U.sc + lo, s_sc, tid, nthr);
+    if (tid < 64) wave_sum_rows<L>(U.part_g + (size_t)lo * g.nbF, g.nbF, g.nbF, gsum);
+  }
+  if (tid < G) row_info(g, blockIdx.x * G + tid, s_row[tid]);
+  const Cx<R>* twg = reinterpret_cast<const Cx<R>*>(g.tw[2]);
+  for (int i = tid; i < M; i += nthr) tw[i] = twg[i];
+  __syncthreads();
+  // convergence and beta_it per load, from the shared copy of its state; block 0
+  // records them in the state itself
   if (tid < 64) {
     const int lane = tid;
+#pragma unroll
     for (int w = 0; w < L; ++w) {
       int act = 1;
       double beta = 0.0;
       if (mode == LAST_CG) {
-        CgScal* sc = U.sc + lo + w;
+        const CgScal* sc = &s_sc[w];
+        CgScal* out = (blockIdx.x == 0 && lane == 0) ? U.sc + lo + w : nullptr;
         act = (sc->status == 0);
         if (act) {
-          const double gam = wave_sum_arr(U.part_g + (size_t)(lo + w) * g.nbF, g.nbF);
+          const double gam = gsum[w];
           const bool bad = !(gam == gam) || gam > 1e300;
-          const bool conv = stop_test(sc, it, gam, blockIdx.x == 0 && lane == 0);
+          const bool conv = stop_test(sc, out, it, gam);
           if (bad || conv || it >= sc->maxit) {
             act = 0;
-            if (blockIdx.x == 0 && lane == 0) {
-              sc->status = bad ? -1 : (conv ? 1 : 2);
-              sc->iters = it;
-              sc->gamma_last = gam;
-              if (it == 0) sc->gamma0 = gam;
+            if (out) {
+              out->status = bad ? -1 : (conv ? 1 : 2);
+              out->iters = it;
+              out->gamma_last = gam;
+              if (it == 0) out->gamma0 = gam;
             }
           } else {
             beta = (it == 0) ? 0.0 : gam / sc->gamma[(it - 1) & 1];
-            if (blockIdx.x == 0 && lane == 0) {
-              sc->gamma[it & 1] = gam;
-              sc->beta[it & 1] = beta;
-              if (it == 0) sc->gamma0 = gam;
+            if (out) {
+              out->gamma[it & 1] = gam;
+              out->beta[it & 1] = beta;
+              if (it == 0) out->gamma0 = gam;
             }
           }
         }
@@ -995,9 +1027,6 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
       }
     }
   }
-  if (tid < G) row_info(g, blockIdx.x * G + tid, s_row[tid]);
-  const Cx<R>* twg = reinterpret_cast<const Cx<R>*>(g.tw[2]);
-  for (int i = tid; i < M; i += nthr) tw[i] = twg[i];
   __syncthreads();
   {
     int any = 0;

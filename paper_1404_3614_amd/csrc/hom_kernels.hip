@@ -185,7 +185,7 @@ __global__ __launch_bounds__(kBlock) void k_first(Geo g, const UnitDev* __restri
             alpha = gam / den;
             if (blockIdx.x == 0 && lane == 0) {
               sc->alpha[(it - 1) & 1] = alpha;
-              energy_record(sc, it - 1, alpha * gam);
+              energy_record(sc, sc, it - 1, alpha * gam);
             }
           }
         }
@@ -336,7 +336,7 @@ __global__ __launch_bounds__(kBlock) void k_last(Geo g, const UnitDev* __restric
         if (act) {
           const double gam = wave_sum_arr(U.part_g + (size_t)w * g.nbF, g.nbF);
           const bool bad = !(gam == gam) || gam > 1e300;
-          const bool conv = stop_test(sc, it, gam, blockIdx.x == 0 && lane == 0);
+          const bool conv = stop_test(sc, blockIdx.x == 0 && lane == 0 ? sc : nullptr, it, gam);
           if (bad || conv || it >= sc->maxit) {
             act = 0;
             if (blockIdx.x == 0 && lane == 0) {
