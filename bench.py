@@ -164,7 +164,7 @@ def apply_bytes(pb, nload):
     return 2 * N0 * plane * P * cs + pb.ncoef * Mt * rs
 
 
-def pass_bytes(pb, nload):
+def pass_bytes(pb, nload, plane=False):
     """Algorithmic bytes per unit (one cell, nload loads) of each pass of one
     CG iteration (primal, m = 1 component per load):
       first  : CG vectors x, p, r, s read and x, r written (FP64 complex on the
@@ -174,7 +174,9 @@ def pass_bytes(pb, nload):
       apply  : intermediate (N0 x M1 x M2) read and written + coefficient on the
                doubled grid read;
       mid_fwd: (3D) N0 x M1 x M2 read, N0 x N1 x M2 written;
-      last   : row intermediate read + r, p, s read and p, s written."""
+      last   : row intermediate read + r, p, s read and p, s written.
+    plane (3D plane pass in place of mid_inv, apply and mid_fwd): the row
+    intermediate read and written + the coefficient on the doubled grid read."""
     d = pb.d
     N = list(pb.N)
     M = [2 * n - 1 for n in N]
@@ -190,7 +192,10 @@ def pass_bytes(pb, nload):
         inner *= n
     rowbuf = N[0] * inner * M[-1] * P * cs
     out = dict(first=6 * vec + rowbuf, apply=apply_bytes(pb, nload), last=rowbuf + 5 * vec)
-    if d == 3:
+    if d == 3 and plane:
+        Mt = M[0] * M[1] * M[2]
+        out["apply"] = 2 * rowbuf + pb.ncoef * Mt * (4 if pb.precision == "mixed" else 8)
+    elif d == 3:
         full = N[0] * M[1] * M[2] * P * cs
         out.update(mid_inv=rowbuf + full, mid_fwd=full + rowbuf)
     return out
@@ -677,7 +682,8 @@ def _c3_variant(args, anisotropic):
     batch.set_timing(False)
     unit_launches = args.steps * sum(max(i["iters"] for i in cell[key]) + 1
                                      for cell in res for key in ("info_primal", "info_dual"))
-    pbytes = pass_bytes(probs[0], 3)
+    plane = launches["mid_inv"] == 0        # the plane pass ran in place of the middle and column passes
+    pbytes = pass_bytes(probs[0], 3, plane)
     per_pass = {}
     for k in ("first", "mid_inv", "apply", "mid_fwd", "last"):
         if launches[k]:
@@ -693,7 +699,7 @@ def _c3_variant(args, anisotropic):
                 cg_iters_cell0=iters[0], cg_iters_max=int(np.max(iters)),
                 bound_error_vs_oracle=dict(cell=0, reference=f"oracle, CG to 1e-11 (tests/golden/reference_bounds.json "
                                                               f"{name})", **(bound_error(res[0], ref) or {})),
-                per_pass=per_pass, dominant=dom)
+                per_pass=per_pass, dominant=dom, plane_pass=plane)
 
 
 def run_c3(args):
@@ -715,7 +721,8 @@ def run_c3(args):
                  f"{args.c3_cells} cells (C3a 10 I inclusions, the value; C3b anisotropic SPD beside it)",
                  dict(variants=out))
     names = dict(first="k_first_fast (row pass of the last axis)", mid_inv="k_mid_fast (middle axis, inverse)",
-                 apply="k_apply_fast (column pass: inverse FFT, coefficient, forward FFT)",
+                 apply="k_plane_fast (plane pass: axes 1 and 0 inverse, coefficient, axes 0 and 1 forward)"
+                 if a["plane_pass"] else "k_apply_fast (column pass: inverse FFT, coefficient, forward FFT)",
                  mid_fwd="k_mid_fast (middle axis, forward)", last="k_last_fast (row pass of the last axis)")
     line["roofline"] = dict(bound="hbm", achieved=pp["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
                             frac=round(pp["gbs"] / HBM_PEAK_GBS, 4), bytes_per_launch=pp["bytes_per_launch"],
@@ -807,7 +814,8 @@ def mixed_roofline(args, ms, groups, n_total):
         d = key[0]
         # a cell takes part in the launches of a solve until all its loads stopped
         units = sum(max(i["iters"] for i in res[j][k]) + 1 for j, _, _ in items for k in ("info_primal", "info_dual"))
-        pbytes = pass_bytes(pb, d)
+        plane = d == 3 and cnt.get("mid_inv", 0) == 0
+        pbytes = pass_bytes(pb, d, plane)
         for p, c in cnt.items():
             if not c:
                 continue
@@ -815,7 +823,7 @@ def mixed_roofline(args, ms, groups, n_total):
             b = units * pbytes[p] / c
             row = dict(cls=f"{d}D N={key[1][0]}", kernel_pass=p, ms_per_launch=round(avg[p], 5), launches=c,
                        total_ms=round(tot, 2), bytes_per_launch=int(b), gbs=round(b / (avg[p] * 1e-3) / 1e9, 1))
-            if p == "apply" and args.precision == "mixed" and 2 * key[1][0] - 1 in SPLIT:
+            if p == "apply" and args.precision == "mixed" and 2 * key[1][0] - 1 in SPLIT and not plane:
                 fl = units * apply_flops(pb, d) / c
                 row.update(flops_per_launch=int(fl), tflops=round(fl / (avg[p] * 1e-3) / 1e12, 2))
             rows.append(row)

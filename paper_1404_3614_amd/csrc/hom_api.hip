@@ -244,6 +244,7 @@ struct hom_problem {
   Plan plan[3];
   double* coef64[2];
   float* coef32[2];
+  float* coefp[2];      // FP32 coefficient in plane order (3D plane pass), or null
   Cx<double>* ahat_half[2];
   Cx<double>* tw64[3];
   Cx<float>* tw32[3];
@@ -389,6 +390,12 @@ size_t carve(const hom_desc* desc, int max_loads, const Sizes& z, hom_problem* p
     } else if (pb) {
       pb->coef32[k] = nullptr;
     }
+    if (mixed && fast_plane_supported(d, z.M, z.N, nc)) {
+      o = take(nc * z.Mt * sizeof(float));
+      if (pb) pb->coefp[k] = (float*)ptr(o);
+    } else if (pb) {
+      pb->coefp[k] = nullptr;
+    }
     o = take(nc * (size_t)z.S * sizeof(Cx<double>));
     if (pb) pb->ahat_half[k] = (Cx<double>*)ptr(o);
   }
@@ -478,6 +485,7 @@ Geo make_geo(const hom_problem* pb, int dual, int L, bool fp32, int P_override =
     const int G = fast_row_pairs(z.M[2], z.N[2], z.d, L, g.rowG);
     if (G > 0) g.nbF = g.nbL = (z.Q + G - 1) / G;
     g.pmaj = (z.d == 2 && G > 0 && z.M[0] == 2 * z.N[0] - 1 && fast_apply_supported(z.M[0], z.d, g.P, z.nc)) ? 1 : 0;
+    g.plane = (pb->coefp[dual] && fast_plane_supported(z.d, z.M, z.N, z.nc)) ? 1 : 0;
   }
   const size_t cs = fp32 ? sizeof(Cx<float>) : sizeof(Cx<double>);
   const int npts = z.M[1] * z.M[2];
@@ -516,6 +524,7 @@ Geo make_geo_gani(const hom_problem* pb, int dual, int L, bool fp32, int P_overr
   }
   g.rowG = g.rowThreads = g.apTP = g.apHX = g.apAll = 0;
   g.pmaj = 0;
+  g.plane = 0;
   g.nbF = g.nbL = z.Q;
   const size_t cs = fp32 ? sizeof(Cx<float>) : sizeof(Cx<double>);
   const int npts = g.M[1] * g.M[2];
@@ -537,13 +546,13 @@ hipError_t enqueue_matvec_passes(const Geo& g, const UnitDev* u, int nu, int fir
   const bool cg = first_mode == FIRST_CG;
   hipError_t e = launch_first<R>(g, u, nu, first_mode, jstep, iter_base, st);
   if (e != hipSuccess) return e;
-  if (g.d == 3) {
+  if (g.d == 3 && !g.plane) {
     e = launch_mid<R>(g, u, nu, 1 | (cg ? MID_CG : 0), st);
     if (e != hipSuccess) return e;
   }
   e = launch_apply<R>(g, u, nu, cg ? APPLY_COEF_CG : APPLY_COEF, st);
   if (e != hipSuccess) return e;
-  if (g.d == 3) {
+  if (g.d == 3 && !g.plane) {
     e = launch_mid<R>(g, u, nu, cg ? MID_CG : 0, st);
     if (e != hipSuccess) return e;
   }
@@ -558,13 +567,13 @@ template <typename R>
 hipError_t enqueue_cross_passes(const Geo& gin, const Geo& gout, const UnitDev* u, hipStream_t st) {
   hipError_t e = launch_first<R>(gin, u, 1, FIRST_BOUNDS, 0, nullptr, st);
   if (e != hipSuccess) return e;
-  if (gin.d == 3) {
+  if (gin.d == 3 && !gin.plane) {
     e = launch_mid<R>(gin, u, 1, 1, st);
     if (e != hipSuccess) return e;
   }
   e = launch_apply<R>(gin, u, 1, APPLY_COEF, st);
   if (e != hipSuccess) return e;
-  if (gin.d == 3) {
+  if (gin.d == 3 && !gin.plane) {
     e = launch_mid<R>(gin, u, 1, 0, st);
     if (e != hipSuccess) return e;
   }
@@ -588,6 +597,7 @@ void fill_unit(hom_problem* pb, int k, int L, const double* E, double* const* x,
     hu->ahat = gn.ahat[k];
   } else {
     hu->coef = mixed ? (const void*)pb->coef32[k] : (const void*)pb->coef64[k];
+    hu->coefp = mixed ? pb->coefp[k] : nullptr;
     hu->ahat = pb->ahat_half[k];
   }
   for (int l = 0; l < L; ++l) {
@@ -683,13 +693,15 @@ struct SolveRun {
   long long* tcnt = nullptr;           // [5] launches per pass type
 };
 
-// Pass types in launch order within one operator application.
-static int pass_types(int d, int* types) {
+// Pass types in launch order within one operator application (a plane pass
+// counts as the column pass).
+static int pass_types(const Geo& g, int* types) {
+  const bool mid = g.d == 3 && !g.plane;
   int n = 0;
   types[n++] = 0;
-  if (d == 3) types[n++] = 1;
+  if (mid) types[n++] = 1;
   types[n++] = 2;
-  if (d == 3) types[n++] = 3;
+  if (mid) types[n++] = 3;
   types[n++] = 4;
   return n;
 }
@@ -709,7 +721,7 @@ static hipError_t enqueue_timed_passes(const Geo& g, const UnitDev* u, int nu, i
   hipError_t e;
   arm();
   e = launch_first<R>(g, u, nu, FIRST_CG, jstep, iter_base, st);
-  if (e == hipSuccess && g.d == 3) {
+  if (e == hipSuccess && g.d == 3 && !g.plane) {
     arm();
     e = launch_mid<R>(g, u, nu, 1 | MID_CG, st);
   }
@@ -717,7 +729,7 @@ static hipError_t enqueue_timed_passes(const Geo& g, const UnitDev* u, int nu, i
     arm();
     e = launch_apply<R>(g, u, nu, APPLY_COEF_CG, st);
   }
-  if (e == hipSuccess && g.d == 3) {
+  if (e == hipSuccess && g.d == 3 && !g.plane) {
     arm();
     e = launch_mid<R>(g, u, nu, MID_CG, st);
   }
@@ -733,7 +745,7 @@ static hipError_t enqueue_timed_passes(const Geo& g, const UnitDev* u, int nu, i
 hipError_t enqueue_chunk(SolveRun& R) {
   const Geo& g = R.g;
   hipStream_t st = R.st;
-  const int npass = pass_types(g.d, R.types);
+  const int npass = pass_types(g, R.types);
   for (int j = 0; j < R.chunk; ++j) {
     hipError_t e;
     if (R.events) {
@@ -777,7 +789,7 @@ hom_status start_run(SolveRun& R, int nload, double tol, int maxit, bool have_x0
   }
   // events recorded inside a captured graph cannot be timed, so timing runs launch directly
   R.use_graph = st != nullptr && env_int("HOM_NO_GRAPH", 0) == 0 && R.events == nullptr;
-  const int npass = pass_types(g.d, R.types);
+  const int npass = pass_types(g, R.types);
   if (R.events && R.events->empty()) {
     R.events->resize((size_t)R.chunk * 2 * npass);
     for (auto& ev : *R.events) HIPCHK(hipEventCreate(&ev));
@@ -849,7 +861,7 @@ hom_status loop_runs(SolveRun* const* runs, int nr, int maxit, const int* partne
 // Per-kernel event times of the chunk just completed, into the run's sums.
 hom_status collect_events(SolveRun& R) {
   if (!R.events) return HOM_OK;
-  const int npass = pass_types(R.g.d, R.types);
+  const int npass = pass_types(R.g, R.types);
   for (int j = 0; j < R.chunk; ++j) {
     hipEvent_t* ev = R.events->data() + (size_t)j * 2 * npass;
     for (int p = 0; p < npass; ++p) {
@@ -1127,6 +1139,7 @@ hom_status setup_coefficients(hom_problem* pb, const void* Ahat, const void* Bha
       HIPCHK(launch_line_fft<double>(pb->scratch, nc * z.M[0], z.M[1], z.M[2], pb->plan[1], pb->tw64[1], 1, st));
     HIPCHK(launch_line_fft<double>(pb->scratch, nc * z.M[0] * z.M[1], z.M[2], 1, pb->plan[2], pb->tw64[2], 1, st));
     HIPCHK(launch_coef_real(pb->scratch, pb->coef64[k], pb->coef32[k], (long)(nc * z.Mt), st));
+    if (pb->coefp[k]) HIPCHK(launch_coef_planes(pb->coef32[k], pb->coefp[k], nc, z.M, st));
   }
   return HOM_OK;
 }
@@ -1941,10 +1954,12 @@ static hom_status profile_units(const Geo& g, const UnitDev* units, int n, bool 
       if (which == 0)
         e = fp32 ? launch_first<float>(g, units, n, FIRST_FIELD, 0, nullptr, st)
                  : launch_first<double>(g, units, n, FIRST_FIELD, 0, nullptr, st);
-      if (which == 1 && g.d == 3) e = fp32 ? launch_mid<float>(g, units, n, 1, st) : launch_mid<double>(g, units, n, 1, st);
+      if (which == 1 && g.d == 3 && !g.plane)
+        e = fp32 ? launch_mid<float>(g, units, n, 1, st) : launch_mid<double>(g, units, n, 1, st);
       if (which == 2)
         e = fp32 ? launch_apply<float>(g, units, n, APPLY_COEF, st) : launch_apply<double>(g, units, n, APPLY_COEF, st);
-      if (which == 3 && g.d == 3) e = fp32 ? launch_mid<float>(g, units, n, 0, st) : launch_mid<double>(g, units, n, 0, st);
+      if (which == 3 && g.d == 3 && !g.plane)
+        e = fp32 ? launch_mid<float>(g, units, n, 0, st) : launch_mid<double>(g, units, n, 0, st);
       if (which == 4)
         e = fp32 ? launch_last<float>(g, units, n, LAST_MATVEC, 0, nullptr, st)
                  : launch_last<double>(g, units, n, LAST_MATVEC, 0, nullptr, st);
@@ -1961,7 +1976,7 @@ static hom_status profile_units(const Geo& g, const UnitDev* units, int n, bool 
   for (int w = 0; w < 5 && rc == HOM_OK; ++w) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, ev[w], ev[w + 1]) != hipSuccess) rc = HOM_E_DEVICE;
-    const bool skipped = (w == 1 || w == 3) && g.d != 3;
+    const bool skipped = (w == 1 || w == 3) && (g.d != 3 || g.plane);
     ms_out[w] = skipped ? 0.0 : (double)ms / reps;
   }
   for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);

@@ -71,6 +71,32 @@ __device__ __forceinline__ void gstc(void* base, unsigned boff, Cx<float> v) {
   gst<unsigned long long>(base, boff, __builtin_bit_cast(unsigned long long, v));
 }
 
+// Element i of a buffer through a global (address space 1) pointer.  FLAT
+// instructions (the default for pointers read from the unit table) count
+// against the LDS counter as well, so every barrier after them waits until
+// they complete; global instructions leave barriers to LDS traffic and let
+// stores drain in the background.
+typedef double gdbl2 __attribute__((ext_vector_type(2)));
+typedef float gflt2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ Cx<double> gload(const Cx<double>* p, size_t i) {
+  return __builtin_bit_cast(Cx<double>, ((const __attribute__((address_space(1))) gdbl2*)p)[i]);
+}
+__device__ __forceinline__ void gstore(Cx<double>* p, size_t i, Cx<double> v) {
+  ((__attribute__((address_space(1))) gdbl2*)p)[i] = __builtin_bit_cast(gdbl2, v);
+}
+__device__ __forceinline__ Cx<float> gload(const Cx<float>* p, size_t i) {
+  return __builtin_bit_cast(Cx<float>, ((const __attribute__((address_space(1))) gflt2*)p)[i]);
+}
+__device__ __forceinline__ void gstore(Cx<float>* p, size_t i, Cx<float> v) {
+  ((__attribute__((address_space(1))) gflt2*)p)[i] = __builtin_bit_cast(gflt2, v);
+}
+__device__ __forceinline__ float gload(const float* p, size_t i) {
+  return ((const __attribute__((address_space(1))) float*)p)[i];
+}
+__device__ __forceinline__ void gstore(double* p, size_t i, double v) {
+  ((__attribute__((address_space(1))) double*)p)[i] = v;
+}
+
 // rows whose positions B n1 + q lie in Z_N for every q < B
 template <int M>
 constexpr bool full_row(int n1) {
@@ -1051,7 +1077,7 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
 #pragma unroll
     for (int n2 = 0; n2 < B; ++n2)
 #pragma unroll
-      for (int pk = 0; pk < P; ++pk) v[pk][n2] = in[(((size_t)i0 * N1 + i1) * M + (q + A * n2)) * lstr + (po + pk) * pstr];
+      for (int pk = 0; pk < P; ++pk) v[pk][n2] = gload(in, (((size_t)i0 * N1 + i1) * M + (q + A * n2)) * lstr + (po + pk) * pstr);
   }
 #pragma unroll
   for (int pk = 0; pk < P; ++pk) {
@@ -1102,13 +1128,13 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
       for (int c = 0; c < m; ++c) {
         const size_t idx = ((size_t)(c * g.H0 + kk0) * N1 + ii1) * N2 + i2;
         if (cgm) {
-          rv[c] = U.r[lo + l][idx];
+          rv[c] = gload(U.r[lo + l], idx);
           if (it > 0) {
-            pv[c] = U.p[lo + l][idx];
-            sv[c] = U.s[lo + l][idx];
+            pv[c] = gload(U.p[lo + l], idx);
+            sv[c] = gload(U.s[lo + l], idx);
           }
         } else if (mode == LAST_RESID) {
-          bv[c] = U.b[lo + l][idx];
+          bv[c] = gload(U.b[lo + l], idx);
         }
       }
       Cx<double> wv[D];
@@ -1132,19 +1158,19 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
         if (cgm) {
           const double b = s_beta[l];
           if (it == 0) {
-            U.p[lo + l][idx] = rv[c];
-            U.s[lo + l][idx] = w;
+            gstore(U.p[lo + l], idx, rv[c]);
+            gstore(U.s[lo + l], idx, w);
           } else {
-            U.p[lo + l][idx] = rv[c] + pv[c] * b;
-            U.s[lo + l][idx] = w + sv[c] * b;
+            gstore(U.p[lo + l], idx, rv[c] + pv[c] * b);
+            gstore(U.s[lo + l], idx, w + sv[c] * b);
           }
           e = wt * (rv[c].x * w.x + rv[c].y * w.y);
         } else if (mode == LAST_RESID) {
           const Cx<double> rn = bv[c] - w;
-          U.r[lo + l][idx] = rn;
+          gstore(U.r[lo + l], idx, rn);
           e = wt * (rn.x * rn.x + rn.y * rn.y);
         } else {
-          U.s[lo + l][idx] = w;
+          gstore(U.s[lo + l], idx, w);
           e = wt * (w.x * w.x + w.y * w.y);
         }
         if (l == 0) dp0 += e;
@@ -1162,7 +1188,7 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
     if (tid == 0) {
       double s = 0.0;
       for (int i = 0; i < (nthr + 63) / 64; ++i) s += s_red[i];
-      U.part_d[(size_t)(lo + l) * g.nbL + blockIdx.x] = s;
+      gstore(U.part_d, (size_t)(lo + l) * g.nbL + blockIdx.x, s);
     }
     __syncthreads();
   }
@@ -1337,6 +1363,232 @@ bool fast_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t s
   HOM_AP(81, 3, 2, 6) HOM_AP(81, 3, 3, 6) HOM_AP(81, 3, 5, 6)
 #undef HOM_AP
   return false;
+}
+
+// ============================================================== plane pass (3D)
+// The middle and column passes of a 3D operator application in one kernel.  A
+// block takes one plane m2 of a unit's row-pass buffer ([N0][N1][M2][P]) and,
+// one pack at a time, runs the zero-padded inverse transform along axis 1, the
+// inverse transform along axis 0, the product with the coefficient on the
+// doubled grid (Sec. 4, the quadrature of the Ga scheme), the forward
+// transform along axis 0 and the truncated forward transform along axis 1;
+// the result replaces the plane in place, where the last pass reads it.
+// Every transform is the one of the separate passes operation for operation,
+// so both routes give the same bits; the intermediate N0 x M1 plane stays in
+// LDS instead of making two round trips through HBM.  The coefficient comes
+// from its copy in plane order [M2][nc][M0][M1].
+//
+// Each four-step transform belongs to T = 9 lanes of one wave (seven groups
+// per wave, lane 63 idle), so its exchange needs no block barrier: a line's
+// exchange runs in its own column of the plane, a column's in its wave's
+// exchange area.  Block barriers only separate the line and column steps
+// (two per pack).  Workgroup x runs on XCD x % 8: each XCD takes a run of
+// consecutive planes, whose rows share cache lines of the row-pass buffer in
+// that XCD's L2.
+constexpr int kPlaneThreads = 384;
+
+template <int M>
+struct PlaneShape {
+  static constexpr int T = Cfg<M>::T, N = Cfg<M>::N;
+  static constexpr int GW = 64 / T;                     // thread groups per wave
+  static constexpr int NW = kPlaneThreads / 64;         // waves per block
+  static constexpr int NG = GW * NW;                    // thread groups per block
+  static constexpr int R = (M + NG - 1) / NG;           // rounds of the column step
+  static constexpr size_t lds = (2 * (size_t)M + (size_t)M * N + (size_t)NW * GW * M) * sizeof(Cx<float>);
+};
+
+// Order of the LDS accesses of one wave (lanes exchange through LDS without a block barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int M, int P>
+__global__ __launch_bounds__(kPlaneThreads) void k_plane_fast(Geo g, const UnitDev* __restrict__ units, int cg) {
+  using S = PlaneShape<M>;
+  constexpr int A = Cfg<M>::A, B = Cfg<M>::B, T = S::T, N = S::N, GW = S::GW, NG = S::NG;
+  constexpr int PPX = (M + 7) / 8;  // planes per XCD
+  static_assert(A == T && B == T, "square four-step split");
+  static_assert(N <= NG, "one thread group per line of the plane");
+  extern __shared__ __align__(16) unsigned char smem[];
+  Cx<float>* tw0 = reinterpret_cast<Cx<float>*>(smem);  // [M] axis 0
+  Cx<float>* tw1 = tw0 + M;                             // [M] axis 1
+  Cx<float>* Y = tw1 + M;                               // [M1][N0] the plane after the axis-1 transform
+  const UnitDev& U = units[blockIdx.z];
+  if (cg && !any_active(U, g.L)) return;
+  const int m2 = (int)(blockIdx.x & 7) * PPX + (int)(blockIdx.x >> 3);
+  if (m2 >= M) return;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int gi = lane / T, q = lane - gi * T;
+  const int grp = wave * GW + gi;                       // line i0 / first column of this thread group
+  const bool gv = gi < GW;                              // lane 63 (and beyond 7 T) idle
+  Cx<float>* ex = Y + (size_t)M * N + (size_t)wave * GW * M;  // this wave's exchange area [M][GW]
+  {
+    const Cx<float>* t0 = reinterpret_cast<const Cx<float>*>(g.tw[0]);
+    const Cx<float>* t1 = reinterpret_cast<const Cx<float>*>(g.tw[1]);
+    for (int i = tid; i < M; i += kPlaneThreads) {
+      tw0[i] = t0[i];
+      tw1[i] = t1[i];
+    }
+  }
+  Cx<float>* buf = reinterpret_cast<Cx<float>*>(U.bufA);
+  const size_t W = (size_t)M * P;                  // elements per (i0, i1) row of the buffer
+  const int fields = g.L * g.d;                    // fields past the last load's are padding
+  const bool lt = gv && grp < N;                   // this group owns line i0 = grp
+  // the plane's inputs for every pack: row i1 = kept(B n1 + q) of line i0
+  Cx<float> in[A][P];
+#pragma unroll
+  for (int n1 = 0; n1 < A; ++n1) {
+    const int i1 = (lt && !dead_row<M>(n1)) ? kept<M>(B * n1 + q) : -1;
+#pragma unroll
+    for (int pk = 0; pk < P; ++pk)
+      in[n1][pk] = i1 >= 0 ? gload(buf, ((size_t)grp * N + i1) * W + (size_t)m2 * P + pk) : rf::mk<float>(0, 0);
+  }
+  // the coefficient at the spatial points m0 = q + A k2 of this group's columns (nc = 1)
+  const float* cp = U.coefp + (size_t)m2 * M * M;  // [M0][M1] of this plane
+  float a[S::R][B];
+#pragma unroll
+  for (int r = 0; r < S::R; ++r) {
+    const int m1 = grp + r * NG;
+#pragma unroll
+    for (int k2 = 0; k2 < B; ++k2) a[r][k2] = (gv && m1 < M) ? gload(cp, (size_t)(q + A * k2) * M + m1) : 0.f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int pk = 0; pk < P; ++pk) {
+    Cx<float> v[T];
+    // (1) axis 1, inverse, zero-padded N1 -> M1 (the middle pass, INV); exchange in column i0 of Y
+    if (lt) {
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) v[n1] = in[n1][pk];
+      rf::Dft<float, A, 1>::template run_z<dead_mask<M>()>(v);
+#pragma unroll
+      for (int k1 = 0; k1 < A; ++k1) {
+        Cx<float> w = tw1[q * k1];
+        w.y = -w.y;
+        Y[(q * A + k1) * N + grp] = rf::mul(v[k1], w);
+      }
+    }
+    wave_sync();
+    if (lt) {
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) v[n2] = Y[(n2 * A + q) * N + grp];
+    }
+    wave_sync();
+    if (lt) {
+      rf::Dft<float, B, 1>::run(v);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) Y[(q + A * k2) * N + grp] = v[k2];
+    }
+    __syncthreads();
+    // (2) axis 0 on the columns m1 of the plane: inverse, coefficient, forward (the column pass)
+    const bool f0 = 2 * pk < fields, f1 = 2 * pk + 1 < fields;
+#pragma unroll
+    for (int r = 0; r < S::R; ++r) {
+      const int m1 = grp + r * NG;
+      const bool ok = gv && m1 < M;
+      if (ok) {
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) {
+          const int i0 = !dead_row<M>(n1) ? kept<M>(B * n1 + q) : -1;
+          v[n1] = i0 >= 0 ? Y[m1 * N + i0] : rf::mk<float>(0, 0);
+        }
+        rf::Dft<float, A, 1>::template run_z<dead_mask<M>()>(v);
+#pragma unroll
+        for (int k1 = 0; k1 < A; ++k1) {
+          Cx<float> w = tw0[q * k1];
+          w.y = -w.y;
+          ex[(q * A + k1) * GW + gi] = rf::mul(v[k1], w);
+        }
+      }
+      wave_sync();
+      if (ok) {
+#pragma unroll
+        for (int n2 = 0; n2 < B; ++n2) v[n2] = ex[(n2 * A + q) * GW + gi];
+        rf::Dft<float, B, 1>::run(v);
+        // spatial values at m0 = q + A k2
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) v[k2] = rf::mk<float>(f0 ? a[r][k2] * v[k2].x : 0.f, f1 ? a[r][k2] * v[k2].y : 0.f);
+        rf::Dft<float, B, -1>::run(v);
+      }
+      wave_sync();
+      if (ok) {
+#pragma unroll
+        for (int mm = 0; mm < B; ++mm) ex[(q * B + mm) * GW + gi] = rf::mul(v[mm], tw0[q * mm]);
+      }
+      wave_sync();
+      if (ok) {
+#pragma unroll
+        for (int n1 = 0; n1 < A; ++n1) v[n1] = ex[(n1 * B + q) * GW + gi];
+        rf::Dft<float, A, -1>::run(v);
+#pragma unroll
+        for (int mm = 0; mm < A; ++mm) {
+          if (dead_row<M>(mm)) continue;
+          const int i0 = kept<M>(q + B * mm);
+          if (i0 >= 0) Y[m1 * N + i0] = v[mm];
+        }
+      }
+      wave_sync();
+    }
+    __syncthreads();
+    // (3) axis 1, forward, truncated M1 -> N1 (the middle pass, forward), into the buffer
+    if (lt) {
+#pragma unroll
+      for (int n2 = 0; n2 < B; ++n2) v[n2] = Y[(q + A * n2) * N + grp];
+    }
+    wave_sync();
+    if (lt) {
+      rf::Dft<float, B, -1>::run(v);
+#pragma unroll
+      for (int mm = 0; mm < B; ++mm) Y[(q * B + mm) * N + grp] = rf::mul(v[mm], tw1[q * mm]);
+    }
+    wave_sync();
+    if (lt) {
+#pragma unroll
+      for (int n1 = 0; n1 < A; ++n1) v[n1] = Y[(n1 * B + q) * N + grp];
+      rf::Dft<float, A, -1>::run(v);
+#pragma unroll
+      for (int mm = 0; mm < A; ++mm) {
+        if (dead_row<M>(mm)) continue;
+        const int i1 = kept<M>(q + B * mm);
+        if (i1 >= 0) gstore(buf, ((size_t)grp * N + i1) * W + (size_t)m2 * P + pk, v[mm]);
+      }
+    }
+    wave_sync();
+  }
+}
+
+template <int M, int P>
+static hipError_t run_plane(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st) {
+  constexpr size_t lds = PlaneShape<M>::lds;
+  auto kern = k_plane_fast<M, P>;
+  hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const dim3 grid(8 * ((M + 7) / 8), 1, n);
+  if (g_ext_timing.on)
+    hipExtLaunchKernelGGL(kern, grid, dim3(kPlaneThreads), lds, st, g_ext_timing.start, g_ext_timing.stop, 0, g, units,
+                          cg);
+  else
+    hipLaunchKernelGGL(kern, grid, dim3(kPlaneThreads), lds, st, g, units, cg);
+  return hipGetLastError();
+}
+
+bool fast_plane_supported(int d, const int* Mz, const int* Nz, int nc) {
+  if (std::getenv("HOM_NO_FAST") || std::getenv("HOM_NO_PLANE")) return false;
+  return d == 3 && nc == 1 && Mz[0] == 81 && Mz[1] == 81 && Mz[2] == 81 && Nz[0] == 41 && Nz[1] == 41 && Nz[2] == 41;
+}
+
+// The middle, column and middle passes of a 3D application as one plane pass
+// (g.plane set); false when the geometry has no plane pass.
+bool fast_plane(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st, hipError_t* err) {
+  if (!g.plane || !fast_plane_supported(g.d, g.M, g.N, g.nc) || n < 1 || n > 65535) return false;
+  switch (g.P) {
+    case 2: *err = run_plane<81, 2>(g, units, n, cg, st); return true;
+    case 3: *err = run_plane<81, 3>(g, units, n, cg, st); return true;
+    case 5: *err = run_plane<81, 5>(g, units, n, cg, st); return true;
+    default: return false;
+  }
 }
 
 template <int M>

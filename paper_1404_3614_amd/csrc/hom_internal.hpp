@@ -91,6 +91,7 @@ struct UnitDev {
   double E[kMaxLoads][3];            // loads (physical components)
   CgScal* partner_sc;                // [L] CG scalars of the partner solve (gap rule), or null
   float* grid;                       // real fields on the doubled grid [L*d][M^d] (grid transfers)
+  const float* coefp;                // FP32 coefficient in plane order [M2][nc][M0][M1] (plane pass), or null
 };
 
 // Shape information shared by every unit of a launch (passed by value).
@@ -115,6 +116,7 @@ struct Geo {
   int apAll;           // 2D column pass: all packs of a point block in one block
   int pmaj;            // 2D, both specialised passes: row-pass buffer pack-major [P][N0][M2]
                        // (otherwise [N0][N1][M2][P], packs interleaved)
+  int plane;           // 3D: the coefficient product runs as one plane pass (fast_plane), no middle passes
   int phys_axis[3];
   double iY[3];        // 1 / Y_a (internal axes)
   double invM;         // 1 / (M0 M1 M2)
@@ -190,6 +192,8 @@ hipError_t launch_net_input_jobs(const NetJob* jobs, int n, int nc, int d, long 
 hipError_t launch_net_input(const double* coef64, int nc, int d, long Mt, const Cx<double>* ahat0, long S, float* out,
                             int weight_only, hipStream_t st);
 hipError_t launch_coef_real(const Cx<double>* full, double* c64, float* c32, long n, hipStream_t st);
+// FP32 coefficient [nc][M0][M1][M2] copied into plane order [M2][nc][M0][M1] (the 3D plane pass).
+hipError_t launch_coef_planes(const float* c32, float* cp, int nc, const int* Mz, hipStream_t st);
 hipError_t launch_extract_half(const Geo& g, const Cx<double>* full, Cx<double>* half, int nc, hipStream_t st);
 hipError_t launch_coef_incl(int d, const int* Mint, const double* iY, int nc, const double* A0c, int n_incl,
                             const void* dev_incl, Cx<double>* out, hipStream_t st);
@@ -216,6 +220,11 @@ int fast_row_pairs(int M, int N, int D, int L, int requested);
 bool fast_apply_supported(int M, int D, int P, int NC);
 // 3D middle pass (axis 1) for M1 in {25, 81, 125}; flags as launch_mid.
 bool fast_mid(const Geo& g, const UnitDev* units, int n, int flags, hipStream_t st, hipError_t* err);
+// 3D plane pass (middle, column and middle passes in one kernel) for M = 81 on
+// every axis and an isotropic coefficient; *_supported is the host-side test
+// (workspace layout, geometry flag), fast_plane the launch (g.plane set).
+bool fast_plane_supported(int d, const int* Mz, const int* Nz, int nc);
+bool fast_plane(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t st, hipError_t* err);
 bool fast_apply_shape_ok(int M, int D, int tp, int hx, int all);
 // Both coefficients on the doubled grid (FP64 and, when given, FP32 copies) for
 // 2D problems with equal doubled-grid lengths 25, 81, 125 or 625.

@@ -1266,6 +1266,9 @@ template <typename R>
 hipError_t launch_apply(const Geo& g, const UnitDev* units, int nunits, int mode, hipStream_t st) {
   if constexpr (sizeof(R) == 4) {
     hipError_t e;
+    // a plane geometry has skipped the middle passes: only the plane pass fits its buffers
+    if (g.plane && (mode == APPLY_COEF || mode == APPLY_COEF_CG))
+      return fast_plane(g, units, nunits, mode == APPLY_COEF_CG ? 1 : 0, st, &e) ? e : hipErrorNotSupported;
     if (mode != APPLY_QUAD && fast_apply(g, units, nunits, mode == APPLY_COEF_CG ? 1 : 0, st, &e)) return e;
   }
   const int nl = g.tileA * g.P;
@@ -1458,6 +1461,25 @@ hipError_t launch_net_input(const double* coef64, int nc, int d, long Mt, const 
                             int weight_only, hipStream_t st) {
   hipLaunchKernelGGL(k_net_input, dim3(grid_for(Mt)), dim3(kBlock), 0, st, coef64, nc, d, Mt, ahat0, S, out,
                      weight_only);
+  return hipGetLastError();
+}
+
+__global__ void k_coef_planes(const float* __restrict__ c32, float* __restrict__ cp, int nc, int M0, int M1, int M2) {
+  const size_t total = (size_t)nc * M0 * M1 * M2;
+  for (size_t t = blockIdx.x * (size_t)blockDim.x + threadIdx.x; t < total; t += (size_t)gridDim.x * blockDim.x) {
+    // t = ((m2 nc + c) M0 + m0) M1 + m1
+    const size_t m1 = t % M1;
+    size_t r = t / M1;
+    const size_t m0 = r % M0;
+    r /= M0;
+    const size_t c = r % nc, m2 = r / nc;
+    cp[t] = c32[((c * M0 + m0) * M1 + m1) * M2 + m2];
+  }
+}
+
+hipError_t launch_coef_planes(const float* c32, float* cp, int nc, const int* Mz, hipStream_t st) {
+  const size_t total = (size_t)nc * Mz[0] * Mz[1] * Mz[2];
+  hipLaunchKernelGGL(k_coef_planes, dim3(grid_for(total)), dim3(kBlock), 0, st, c32, cp, nc, Mz[0], Mz[1], Mz[2]);
   return hipGetLastError();
 }
 

@@ -58,6 +58,8 @@ CASES_OP = [
     ("n3", lambda: homgen.square_inclusion_cell(rho_in=4.0), (3, 3)),
     ("sph3d", lambda: homgen.sphere_cell(seed=3, n=4, anisotropic=True), (5, 13, 5)),
     ("sph3d_iso", lambda: homgen.sphere_cell(seed=9, n=6, anisotropic=False), (13, 13, 13)),
+    # M = 81 on every axis, isotropic: the mixed operator runs the 3D plane pass
+    ("sph3d_41", lambda: homgen.sphere_cell(seed=12, n=10, anisotropic=False, rho=10.0), (41, 41, 41)),
 ]
 
 
@@ -215,6 +217,52 @@ def test_deterministic_and_graph_equals_eager(monkeypatch):
     c, _ = pb.solve(True, tol=1e-8)
     for u, v, w in zip(a, b, c):
         assert bool((u == v).all()) and bool((u == w).all())
+
+
+def test_plane_pass_is_bitwise_the_separate_passes(monkeypatch):
+    """3D, N = 41 on every axis (M = 81), isotropic, mixed precision: the plane
+    pass (middle, column and middle passes in one kernel, HOM_NO_PLANE unset)
+    runs the FP32 operations of the three separate passes in their order, so
+    operator applications, iteration counts, fields and bounds are the same to
+    the bit; the per-pass profile shows no middle pass."""
+    H = _H()
+    import torch
+    from layout import field_from_spectrum
+    N = (41, 41, 41)
+    cells = [homgen.sphere_cell(seed=60 + i, n=6 + 6 * i, anisotropic=False, rho=10.0 ** (1 + i)) for i in range(3)]
+    rng = np.random.default_rng(29)
+    x = torch.tensor(field_from_spectrum(rand_field(3, N, cells[0].Y, False, rng), 3, N, cells[0].Y, False),
+                     dtype=torch.complex128, device="cuda")
+
+    def run():
+        st = torch.cuda.Stream()
+        probs = [H.problem_from_cell(c, N, precision="mixed", stream=st) for c in cells]
+        batch = H.Batch(probs)
+        fp, ip, fd, idl = batch.solve_pair(tol=1e-6)
+        out = batch.bounds(fp, fd)
+        for i, r in enumerate(out):
+            r.update(info_primal=ip[i], info_dual=idl[i], fields_primal=[t.cpu() for t in fp[i]],
+                     fields_dual=[t.cpu() for t in fd[i]])
+        y = probs[0].apply(x, False)
+        prof = batch.profile_passes(False, 3, reps=2)
+        torch.cuda.synchronize()
+        return out, y.cpu(), prof
+
+    monkeypatch.delenv("HOM_NO_PLANE", raising=False)
+    a, ya, pa = run()
+    monkeypatch.setenv("HOM_NO_PLANE", "1")
+    b, yb, pb_ = run()
+    print(f"[plane] profile plane {pa} separate {pb_}", flush=True)
+    assert pa["mid_inv"] == 0 and pa["mid_fwd"] == 0 and pa["apply"] > 0
+    assert pb_["mid_inv"] > 0 and pb_["mid_fwd"] > 0
+    assert torch.equal(ya, yb)
+    for ra, rb in zip(a, b):
+        for key in ("info_primal", "info_dual"):
+            assert [i["iters"] for i in ra[key]] == [i["iters"] for i in rb[key]]
+        for key in ("fields_primal", "fields_dual"):
+            for u, v in zip(ra[key], rb[key]):
+                assert torch.equal(u, v)
+        assert np.array_equal(ra["A_up"], rb["A_up"]) and np.array_equal(ra["A_low"], rb["A_low"])
 
 
 def _voxels(P, seed):
