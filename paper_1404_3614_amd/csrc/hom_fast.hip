@@ -97,6 +97,16 @@ __device__ __forceinline__ void gstore(double* p, size_t i, double v) {
   ((__attribute__((address_space(1))) double*)p)[i] = v;
 }
 
+// Element i through a global pointer (G) or the default flat one: the row
+// passes measure faster with flat loads in 2D and global loads in 3D.
+template <bool G, typename T>
+__device__ __forceinline__ T pick_load(const T* p, size_t i) {
+  if constexpr (G)
+    return gload(p, i);
+  else
+    return p[i];
+}
+
 // rows whose positions B n1 + q lie in Z_N for every q < B
 template <int M>
 constexpr bool full_row(int n1) {
@@ -884,8 +894,8 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_first_fast(Geo g, const
             const double a = s_alpha[l];
             const Cx<double> xv = U.x[lo + l][idx], pv = U.p[lo + l][idx], sv = U.s[lo + l][idx];
             v = v - sv * a;
-            U.x[lo + l][idx] = xv + pv * a;
-            U.r[lo + l][idx] = v;
+            gstore(U.x[lo + l], idx, xv + pv * a);
+            gstore(U.r[lo + l], idx, v);
           }
           const double e = wt * (v.x * v.x + v.y * v.y);
           if (l == 0) gp0 += e;
@@ -973,7 +983,7 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_first_fast(Geo g, const
       for (int n2 = 0; n2 < B; ++n2) v[n2] = sp[n2 * A + q];
       rf::Dft<R, B, 1>::run(v);
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) out[(((size_t)i0 * N1 + i1) * M + (q + A * k2)) * lstr + (po + pk) * pstr] = v[k2];
+      for (int k2 = 0; k2 < B; ++k2) gstore(out, (((size_t)i0 * N1 + i1) * M + (q + A * k2)) * lstr + (po + pk) * pstr, v[k2]);
     }
   }
   (void)H2;
@@ -1077,7 +1087,8 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
 #pragma unroll
     for (int n2 = 0; n2 < B; ++n2)
 #pragma unroll
-      for (int pk = 0; pk < P; ++pk) v[pk][n2] = gload(in, (((size_t)i0 * N1 + i1) * M + (q + A * n2)) * lstr + (po + pk) * pstr);
+      for (int pk = 0; pk < P; ++pk)
+        v[pk][n2] = pick_load<D == 3>(in, (((size_t)i0 * N1 + i1) * M + (q + A * n2)) * lstr + (po + pk) * pstr);
   }
 #pragma unroll
   for (int pk = 0; pk < P; ++pk) {
@@ -1128,13 +1139,13 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_last_fast(Geo g, const 
       for (int c = 0; c < m; ++c) {
         const size_t idx = ((size_t)(c * g.H0 + kk0) * N1 + ii1) * N2 + i2;
         if (cgm) {
-          rv[c] = gload(U.r[lo + l], idx);
+          rv[c] = pick_load<D == 3>((const Cx<double>*)U.r[lo + l], idx);
           if (it > 0) {
-            pv[c] = gload(U.p[lo + l], idx);
-            sv[c] = gload(U.s[lo + l], idx);
+            pv[c] = pick_load<D == 3>((const Cx<double>*)U.p[lo + l], idx);
+            sv[c] = pick_load<D == 3>((const Cx<double>*)U.s[lo + l], idx);
           }
         } else if (mode == LAST_RESID) {
-          bv[c] = gload(U.b[lo + l], idx);
+          bv[c] = pick_load<D == 3>((const Cx<double>*)U.b[lo + l], idx);
         }
       }
       Cx<double> wv[D];
