@@ -333,6 +333,16 @@ def apply_flops(pb, nload):
     return lines * P * (column_line_flops(M[0])[0] + coef * M[0])
 
 
+def plane_flops(pb, nload):
+    """FP32 flops per unit of the 3D plane pass as executed: per plane m2 and
+    pack, N0 lines along axis 1 and M1 columns along axis 0, each a pruned
+    inverse and forward length-M transform (the column pass's line), and the
+    isotropic coefficient product (2 flops per complex value) on M0 x M1 points."""
+    M = [2 * n - 1 for n in pb.N]
+    P = (nload * pb.d + 1) // 2
+    return M[2] * P * ((pb.N[0] + M[1]) * column_line_flops(M[0])[0] + 2 * M[0] * M[1])
+
+
 # FP32 vector peak of the chip: 256 CUs x 4 SIMD x 16 lanes x 2 (FMA) x 2 (packed FP32) x 2.4 GHz =
 # 157.3 TFLOP/s; without packed FP32 instructions (this build emits none) half of it
 VALU_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2 * 2.4e9 / 1e12
@@ -690,6 +700,9 @@ def _c3_variant(args, anisotropic):
             b = unit_launches * pbytes[k] / launches[k]
             per_pass[k] = dict(ms_per_launch=round(avg_ms[k], 5), bytes_per_launch=int(b),
                                gbs=round(b / (avg_ms[k] * 1e-3) / 1e9, 1), launches=launches[k])
+    if plane and "apply" in per_pass:
+        fl = unit_launches * plane_flops(probs[0], 3) / launches["apply"]
+        per_pass["apply"].update(flops_per_launch=int(fl), tflops=round(fl / (avg_ms["apply"] * 1e-3) / 1e12, 2))
     dom = max(per_pass, key=lambda k: per_pass[k]["ms_per_launch"] * per_pass[k]["launches"])
     iters = [[i["iters"] for i in cell["info_primal"] + cell["info_dual"]] for cell in res]
     ref = golden(name)
@@ -724,9 +737,18 @@ def run_c3(args):
                  apply="k_plane_fast (plane pass: axes 1 and 0 inverse, coefficient, axes 0 and 1 forward)"
                  if a["plane_pass"] else "k_apply_fast (column pass: inverse FFT, coefficient, forward FFT)",
                  mid_fwd="k_mid_fast (middle axis, forward)", last="k_last_fast (row pass of the last axis)")
-    line["roofline"] = dict(bound="hbm", achieved=pp["gbs"], peak=HBM_PEAK_GBS, unit="GB/s",
-                            frac=round(pp["gbs"] / HBM_PEAK_GBS, 4), bytes_per_launch=pp["bytes_per_launch"],
-                            traffic=None, kernel=f"{names[dom]} of C3a", ms_per_launch=pp["ms_per_launch"],
+    hbm = dict(achieved=pp["gbs"], peak=HBM_PEAK_GBS, unit="GB/s", frac=round(pp["gbs"] / HBM_PEAK_GBS, 4),
+               bytes_per_launch=pp["bytes_per_launch"])
+    if "tflops" in pp:
+        # the plane pass moves 12.9 MB per cell but executes its FFTs from LDS: bound by vector issue
+        tf = pp["tflops"]
+        roof = dict(bound="alu", achieved=tf, peak=round(VALU_PEAK_TFLOPS, 1), unit="TFLOP/s",
+                    frac=round(tf / VALU_PEAK_TFLOPS, 4), peak_unpacked=round(VALU_UNPACKED_TFLOPS, 1),
+                    frac_of_unpacked=round(tf / VALU_UNPACKED_TFLOPS, 4), hbm=hbm,
+                    flops_model="plane_flops() in bench.py (pruned line transforms as executed)")
+    else:
+        roof = dict(bound="hbm", **hbm)
+    line["roofline"] = dict(**roof, traffic=None, kernel=f"{names[dom]} of C3a", ms_per_launch=pp["ms_per_launch"],
                             per_pass=a["per_pass"],
                             bytes_model="pass_bytes() in bench.py; units per launch = active cells of the batch",
                             timed_region="a second run of the same solves, kernels launched directly by "
@@ -823,8 +845,8 @@ def mixed_roofline(args, ms, groups, n_total):
             b = units * pbytes[p] / c
             row = dict(cls=f"{d}D N={key[1][0]}", kernel_pass=p, ms_per_launch=round(avg[p], 5), launches=c,
                        total_ms=round(tot, 2), bytes_per_launch=int(b), gbs=round(b / (avg[p] * 1e-3) / 1e9, 1))
-            if p == "apply" and args.precision == "mixed" and 2 * key[1][0] - 1 in SPLIT and not plane:
-                fl = units * apply_flops(pb, d) / c
+            if p == "apply" and args.precision == "mixed" and 2 * key[1][0] - 1 in SPLIT:
+                fl = units * (plane_flops(pb, d) if plane else apply_flops(pb, d)) / c
                 row.update(flops_per_launch=int(fl), tflops=round(fl / (avg[p] * 1e-3) / 1e12, 2))
             rows.append(row)
             if best is None or tot > best["total_ms"]:

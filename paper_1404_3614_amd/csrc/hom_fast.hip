@@ -982,8 +982,35 @@ __global__ __launch_bounds__(256, D == 2 ? 6 : 1) void k_first_fast(Geo g, const
 #pragma unroll
       for (int n2 = 0; n2 < B; ++n2) v[n2] = sp[n2 * A + q];
       rf::Dft<R, B, 1>::run(v);
+      if constexpr (D == 2) {
 #pragma unroll
-      for (int k2 = 0; k2 < B; ++k2) gstore(out, (((size_t)i0 * N1 + i1) * M + (q + A * k2)) * lstr + (po + pk) * pstr, v[k2]);
+        for (int k2 = 0; k2 < B; ++k2)
+          gstore(out, (((size_t)i0 * N1 + i1) * M + (q + A * k2)) * lstr + (po + pk) * pstr, v[k2]);
+      }
+    }
+    if constexpr (D == 3) {
+      // the exchange of this pack has been read: its slots take the results, in position order
+      __syncthreads();
+      if (live && q < A) {
+#pragma unroll
+        for (int k2 = 0; k2 < B; ++k2) sp[q + A * k2] = v[k2];
+      }
+    }
+  }
+  if constexpr (D == 3) {
+    // 3D buffers interleave the packs of a position ([N0][N1][M2][P]): a block writes each line's
+    // positions with all their packs back to back, so every cache line is filled at once (pack by
+    // pack, the partial lines were evicted between the packs and written about 1.6 times)
+    __syncthreads();
+    for (int t = tid; t < 2 * G * M; t += nthr) {
+      const int ln = t / M, pos = t - ln * M;
+      const RowInfo& rr = s_row[ln >> 1];
+      const int lb = ln & 1;
+      if (!rr.valid || (lb == 1 && rr.self)) continue;
+      const int a0 = lb ? rr.i0B : rr.h0, a1 = lb ? rr.i1B : rr.i1A;
+      const size_t base = (((size_t)a0 * N1 + a1) * M + pos) * lstr + po * pstr;
+#pragma unroll
+      for (int pk = 0; pk < P; ++pk) gstore(out, base + pk * pstr, stage[((size_t)ln * P + pk) * M + pos]);
     }
   }
   (void)H2;
@@ -1559,14 +1586,23 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_fast(Geo g, const UnitD
 #pragma unroll
       for (int n1 = 0; n1 < A; ++n1) v[n1] = Y[(n1 * B + q) * N + grp];
       rf::Dft<float, A, -1>::run(v);
+      // the result of position q + B mm takes the register of the consumed input of position B n1 + q
 #pragma unroll
-      for (int mm = 0; mm < A; ++mm) {
-        if (dead_row<M>(mm)) continue;
-        const int i1 = kept<M>(q + B * mm);
-        if (i1 >= 0) gstore(buf, ((size_t)grp * N + i1) * W + (size_t)m2 * P + pk, v[mm]);
-      }
+      for (int mm = 0; mm < A; ++mm) in[mm][pk] = v[mm];
     }
     wave_sync();
+  }
+  // every pack of an element in one run (the buffer interleaves the packs of a position)
+  if (lt) {
+#pragma unroll
+    for (int mm = 0; mm < A; ++mm) {
+      if (dead_row<M>(mm)) continue;
+      const int i1 = kept<M>(q + B * mm);
+      if (i1 >= 0) {
+#pragma unroll
+        for (int pk = 0; pk < P; ++pk) gstore(buf, ((size_t)grp * N + i1) * W + (size_t)m2 * P + pk, in[mm][pk]);
+      }
+    }
   }
 }
 
