@@ -66,6 +66,8 @@ def parse():
                     help="energy rules: remaining energy decrease / energy of the iterate")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "e1", "e2", "e3"])
     ap.add_argument("--c3-cells", type=int, default=64, help="c3: cells per batch (C3a and C3b each)")
+    ap.add_argument("--c3-variant", default="both", choices=["both", "a", "b"],
+                    help="c3: isotropic C3a, anisotropic C3b or both (the value is C3a's whenever it runs)")
     ap.add_argument("--c4-mode", default="streams", choices=["graph", "streams", "threads"],
                     help="c4: one captured graph for all classes per chunk, every solve's own graph from one "
                          "host loop, or a host thread per class")
@@ -164,9 +166,10 @@ def apply_bytes(pb, nload):
     return 2 * N0 * plane * P * cs + pb.ncoef * Mt * rs
 
 
-def pass_bytes(pb, nload, plane=False):
+def pass_bytes(pb, nload, plane=False, m=1):
     """Algorithmic bytes per unit (one cell, nload loads) of each pass of one
-    CG iteration (primal, m = 1 component per load):
+    CG iteration (m components of the unknown per load: 1 primal and 2D dual,
+    2 for the 3D dual):
       first  : CG vectors x, p, r, s read and x, r written (FP64 complex on the
                stored half of Z_N) + the row-transformed intermediate written
                (N0 x N1 x M2 per pack; 2D: N0 x M1);
@@ -186,7 +189,7 @@ def pass_bytes(pb, nload, plane=False):
         S *= n
     P = (nload * d + 1) // 2
     cs = 8 if pb.precision == "mixed" else 16
-    vec = nload * 1 * S * 16
+    vec = nload * m * S * 16
     inner = 1
     for n in N[1:-1]:
         inner *= n
@@ -690,14 +693,16 @@ def _c3_variant(args, anisotropic):
     torch.cuda.synchronize()
     avg_ms, launches = batch.get_timing()
     batch.set_timing(False)
-    unit_launches = args.steps * sum(max(i["iters"] for i in cell[key]) + 1
-                                     for cell in res for key in ("info_primal", "info_dual"))
+    # unit-launches per side (the 3D dual moves two components per load in the row passes)
+    ul = {key: args.steps * sum(max(i["iters"] for i in cell[key]) + 1 for cell in res)
+          for key in ("info_primal", "info_dual")}
+    unit_launches = ul["info_primal"] + ul["info_dual"]
     plane = launches["mid_inv"] == 0        # the plane pass ran in place of the middle and column passes
-    pbytes = pass_bytes(probs[0], 3, plane)
+    pb_p, pb_d = pass_bytes(probs[0], 3, plane, 1), pass_bytes(probs[0], 3, plane, 2)
     per_pass = {}
     for k in ("first", "mid_inv", "apply", "mid_fwd", "last"):
         if launches[k]:
-            b = unit_launches * pbytes[k] / launches[k]
+            b = (ul["info_primal"] * pb_p[k] + ul["info_dual"] * pb_d[k]) / launches[k]
             per_pass[k] = dict(ms_per_launch=round(avg_ms[k], 5), bytes_per_launch=int(b),
                                gbs=round(b / (avg_ms[k] * 1e-3) / 1e9, 1), launches=launches[k])
     if plane and "apply" in per_pass:
@@ -721,17 +726,19 @@ def run_c3(args):
     roofline of the dominant pass of C3a (HBM-bound: every 3D pass streams the
     doubled-grid intermediate)."""
     out = {}
-    for aniso in (False, True):
+    for aniso in {"both": (False, True), "a": (False,), "b": (True,)}[args.c3_variant]:
         r = _c3_variant(args, aniso)
         out[r["variant"]] = r
         print(f"[c3] {r['variant']}: {r['bound_pairs_per_s']} bound pairs/s, iterations of cell 0 {r['cg_iters_cell0']}, "
               f"bound error vs oracle {r['bound_error_vs_oracle']}", file=sys.stderr, flush=True)
-    a = out["C3a"]
+    a = out.get("C3a") or out["C3b"]
     dom = a["dominant"]
     pp = a["per_pass"][dom]
     line = _line(args, a["bound_pairs_per_s"], a["ms_per_step"] * 1e-3 * args.steps, args.steps,
                  "C3: 3D N=41 (doubled grid 81^3), 20 random spheres, 3 loads, primal+dual, lockstep batch of "
-                 f"{args.c3_cells} cells (C3a 10 I inclusions, the value; C3b anisotropic SPD beside it)",
+                 f"{args.c3_cells} cells (" + {"both": "C3a 10 I inclusions, the value; C3b anisotropic SPD beside it",
+                                              "a": "C3a 10 I inclusions",
+                                              "b": "C3b anisotropic SPD inclusions"}[args.c3_variant] + ")",
                  dict(variants=out))
     names = dict(first="k_first_fast (row pass of the last axis)", mid_inv="k_mid_fast (middle axis, inverse)",
                  apply="k_plane_fast (plane pass: axes 1 and 0 inverse, coefficient, axes 0 and 1 forward)"
@@ -748,9 +755,10 @@ def run_c3(args):
                     flops_model="plane_flops() in bench.py (pruned line transforms as executed)")
     else:
         roof = dict(bound="hbm", **hbm)
-    line["roofline"] = dict(**roof, traffic=None, kernel=f"{names[dom]} of C3a", ms_per_launch=pp["ms_per_launch"],
+    line["roofline"] = dict(**roof, traffic=None, kernel=f"{names[dom]} of {a['variant']}", ms_per_launch=pp["ms_per_launch"],
                             per_pass=a["per_pass"],
-                            bytes_model="pass_bytes() in bench.py; units per launch = active cells of the batch",
+                            bytes_model="pass_bytes() in bench.py (primal and dual launches each with their own "
+                                        "components per load); units per launch = active cells of the batch",
                             timed_region="a second run of the same solves, kernels launched directly by "
                                          "hipExtLaunchKernelGGL with start/stop HIP events on the library stream")
     print(json.dumps(line), flush=True)
@@ -835,14 +843,16 @@ def mixed_roofline(args, ms, groups, n_total):
         pb = ms.classes[key]["probs"][0]
         d = key[0]
         # a cell takes part in the launches of a solve until all its loads stopped
-        units = sum(max(i["iters"] for i in res[j][k]) + 1 for j, _, _ in items for k in ("info_primal", "info_dual"))
+        uside = {k: sum(max(i["iters"] for i in res[j][k]) + 1 for j, _, _ in items)
+                 for k in ("info_primal", "info_dual")}
+        units = uside["info_primal"] + uside["info_dual"]
         plane = d == 3 and cnt.get("mid_inv", 0) == 0
-        pbytes = pass_bytes(pb, d, plane)
+        pb_p, pb_d = pass_bytes(pb, d, plane, 1), pass_bytes(pb, d, plane, d - 1)
         for p, c in cnt.items():
             if not c:
                 continue
             tot = avg[p] * c
-            b = units * pbytes[p] / c
+            b = (uside["info_primal"] * pb_p[p] + uside["info_dual"] * pb_d[p]) / c
             row = dict(cls=f"{d}D N={key[1][0]}", kernel_pass=p, ms_per_launch=round(avg[p], 5), launches=c,
                        total_ms=round(tot, 2), bytes_per_launch=int(b), gbs=round(b / (avg[p] * 1e-3) / 1e9, 1))
             if p == "apply" and args.precision == "mixed" and 2 * key[1][0] - 1 in SPLIT:
