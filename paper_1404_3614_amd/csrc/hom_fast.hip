@@ -1244,24 +1244,28 @@ template <int M>
 struct Cands;
 template <>
 struct Cands<625> {
+  static constexpr int NG = 3;
   static constexpr int G[3] = {2, 1, 4};
   static constexpr int TP[2] = {8, 4};
   static constexpr ApC AP2[6] = {{8, 0, 0}, {10, 1, 0}, {20, 1, 0}, {5, 1, 0}, {10, 1, 1}, {5, 1, 1}};
 };
 template <>
 struct Cands<125> {
+  static constexpr int NG = 3;
   static constexpr int G[3] = {4, 2, 1};
   static constexpr int TP[2] = {10, 5};
   static constexpr ApC AP2[6] = {{10, 0, 0}, {5, 0, 0}, {10, 1, 0}, {5, 1, 0}, {5, 0, 1}, {5, 1, 1}};
 };
 template <>
 struct Cands<81> {
-  static constexpr int G[3] = {14, 7, 4};
+  static constexpr int NG = 4;
+  static constexpr int G[4] = {14, 7, 4, 2};
   static constexpr int TP[2] = {28, 14};
   static constexpr ApC AP2[6] = {{28, 0, 0}, {14, 0, 0}, {28, 1, 0}, {14, 1, 0}, {14, 0, 1}, {14, 1, 1}};
 };
 template <>
 struct Cands<25> {
+  static constexpr int NG = 3;
   static constexpr int G[3] = {25, 12, 6};
   static constexpr int TP[2] = {51, 25};
   static constexpr ApC AP2[6] = {{51, 0, 0}, {25, 0, 0}, {51, 1, 0}, {25, 1, 0}, {25, 0, 1}, {25, 1, 1}};
@@ -1640,7 +1644,7 @@ bool fast_plane(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t s
 
 template <int M>
 static int row_pairs_for(int requested) {
-  return pick<M>(Cands<M>::G, 3, requested);
+  return pick<M>(Cands<M>::G, Cands<M>::NG, requested);
 }
 
 // Row pairs per block of the specialised row passes, or 0 when no
@@ -1684,6 +1688,10 @@ static hipError_t run_row(bool first, const Geo& g, const UnitDev* units, int n,
   const int G = row_pairs_for<M>(g.rowG);
   if (G == G1) return run_row_g<M, D, L, DUAL, G1>(first, g, units, n, mode, jstep, iter_base, st);
   if (G == G2) return run_row_g<M, D, L, DUAL, G2>(first, g, units, n, mode, jstep, iter_base, st);
+  if constexpr (Cands<M>::NG > 3) {
+    constexpr int G3 = Cands<M>::G[Cands<M>::NG > 3 ? 3 : 0];
+    if (G == G3) return run_row_g<M, D, L, DUAL, G3>(first, g, units, n, mode, jstep, iter_base, st);
+  }
   return run_row_g<M, D, L, DUAL, G0>(first, g, units, n, mode, jstep, iter_base, st);
 }
 
@@ -1746,7 +1754,7 @@ static hipError_t tune_m(const Geo& g0, const UnitDev* units, int n, hipStream_t
   hipError_t e = hipSuccess;
   if (row_supported(M, g0.d, g0.L)) {
     double bms = 1e30;
-    for (int gi = 0; gi < 3 && e == hipSuccess; ++gi) {
+    for (int gi = 0; gi < Cands<M>::NG && e == hipSuccess; ++gi) {
       const int G = Cands<M>::G[gi];
       const int base = round64(2 * G * T);
       for (int thr = base; thr <= 256 && e == hipSuccess; thr = (thr == 256 ? 512 : 256)) {
