@@ -243,10 +243,11 @@ def test_plane_pass_is_bitwise_the_separate_passes(monkeypatch):
         for i, r in enumerate(out):
             r.update(info_primal=ip[i], info_dual=idl[i], fields_primal=[t.cpu() for t in fp[i]],
                      fields_dual=[t.cpu() for t in fd[i]])
-        y = probs[0].apply(x, False)
+        y = probs[0].apply(x, False)                                    # one load: two packs
+        x2, i2 = probs[1].solve(True, E=np.array([[1.0, 0.0, 0.0], [0.0, 0.0, 1.0]]), tol=1e-6)  # three packs
         prof = batch.profile_passes(False, 3, reps=2)
         torch.cuda.synchronize()
-        return out, y.cpu(), prof
+        return out, (y.cpu(), [t.cpu() for t in x2], [i["iters"] for i in i2]), prof
 
     monkeypatch.delenv("HOM_NO_PLANE", raising=False)
     a, ya, pa = run()
@@ -255,7 +256,9 @@ def test_plane_pass_is_bitwise_the_separate_passes(monkeypatch):
     print(f"[plane] profile plane {pa} separate {pb_}", flush=True)
     assert pa["mid_inv"] == 0 and pa["mid_fwd"] == 0 and pa["apply"] > 0
     assert pb_["mid_inv"] > 0 and pb_["mid_fwd"] > 0
-    assert torch.equal(ya, yb)
+    assert torch.equal(ya[0], yb[0]) and ya[2] == yb[2]
+    for u, v in zip(ya[1], yb[1]):
+        assert torch.equal(u, v)
     for ra, rb in zip(a, b):
         for key in ("info_primal", "info_dual"):
             assert [i["iters"] for i in ra[key]] == [i["iters"] for i in rb[key]]
