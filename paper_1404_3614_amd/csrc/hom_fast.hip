@@ -1436,7 +1436,11 @@ struct PlaneShape {
   static constexpr int NW = kPlaneThreads / 64;         // waves per block
   static constexpr int NG = GW * NW;                    // thread groups per block
   static constexpr int R = (M + NG - 1) / NG;           // rounds of the column step
-  static constexpr size_t lds = (2 * (size_t)M + (size_t)M * N + (size_t)NW * GW * M) * sizeof(Cx<float>);
+  // slots per exchange row: GW groups, padded so that the writes of a half-wave (slot 9 q + k of
+  // group g at 8-byte address EX (9 q + k) + g) fall on distinct banks but for pairs (EX = 7 gave
+  // four-way conflicts)
+  static constexpr int EX = GW + 2;
+  static constexpr size_t lds = (2 * (size_t)M + (size_t)M * N + (size_t)NW * EX * M) * sizeof(Cx<float>);
 };
 
 // Order of the LDS accesses of one wave (lanes exchange through LDS without a block barrier).
@@ -1465,7 +1469,8 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_fast(Geo g, const UnitD
   const int gi = lane / T, q = lane - gi * T;
   const int grp = wave * GW + gi;                       // line i0 / first column of this thread group
   const bool gv = gi < GW;                              // lane 63 (and beyond 7 T) idle
-  Cx<float>* ex = Y + (size_t)M * N + (size_t)wave * GW * M;  // this wave's exchange area [M][GW]
+  constexpr int EX = S::EX;
+  Cx<float>* ex = Y + (size_t)M * N + (size_t)wave * EX * M;  // this wave's exchange area [M][EX]
   {
     const Cx<float>* t0 = reinterpret_cast<const Cx<float>*>(g.tw[0]);
     const Cx<float>* t1 = reinterpret_cast<const Cx<float>*>(g.tw[1]);
@@ -1541,13 +1546,13 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_fast(Geo g, const UnitD
         for (int k1 = 0; k1 < A; ++k1) {
           Cx<float> w = tw0[q * k1];
           w.y = -w.y;
-          ex[(q * A + k1) * GW + gi] = rf::mul(v[k1], w);
+          ex[(q * A + k1) * EX + gi] = rf::mul(v[k1], w);
         }
       }
       wave_sync();
       if (ok) {
 #pragma unroll
-        for (int n2 = 0; n2 < B; ++n2) v[n2] = ex[(n2 * A + q) * GW + gi];
+        for (int n2 = 0; n2 < B; ++n2) v[n2] = ex[(n2 * A + q) * EX + gi];
         rf::Dft<float, B, 1>::run(v);
         // spatial values at m0 = q + A k2
 #pragma unroll
@@ -1557,12 +1562,12 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_fast(Geo g, const UnitD
       wave_sync();
       if (ok) {
 #pragma unroll
-        for (int mm = 0; mm < B; ++mm) ex[(q * B + mm) * GW + gi] = rf::mul(v[mm], tw0[q * mm]);
+        for (int mm = 0; mm < B; ++mm) ex[(q * B + mm) * EX + gi] = rf::mul(v[mm], tw0[q * mm]);
       }
       wave_sync();
       if (ok) {
 #pragma unroll
-        for (int n1 = 0; n1 < A; ++n1) v[n1] = ex[(n1 * B + q) * GW + gi];
+        for (int n1 = 0; n1 < A; ++n1) v[n1] = ex[(n1 * B + q) * EX + gi];
         rf::Dft<float, A, -1>::run(v);
 #pragma unroll
         for (int mm = 0; mm < A; ++mm) {
