@@ -401,6 +401,22 @@ hom_status hom_batch_update_coefficients(hom_batch* b, const void* const* Ahat, 
  * NULL; out: host array of n results. */
 hom_status hom_batch_bounds(hom_batch* b, const double* const* primal, const double* const* dual, hom_result* out);
 
+/* Primal and dual solves of the unit loads e_1..e_d for every problem
+ * (eq. linear_system_primal and eq. linear_system_dual, as
+ * hom_batch_solve_pair with nload = d and E = I) followed by their guaranteed
+ * bounds (Def. upper_lower_bounds, as hom_batch_bounds on the returned
+ * fields).  The bound passes of a side are enqueued on its stream as soon as
+ * that side has stopped, so they run beside the other side's remaining
+ * iterations (without per-kernel timing and outside the gap rule; otherwise
+ * after both have stopped).  The fields, infos and results are those of
+ * hom_batch_solve_pair followed by hom_batch_bounds.  x0_primal, x0_dual,
+ * x_primal, x_dual: as in hom_batch_solve_pair with nload = d; out: host array
+ * of n results.  HOM_E_INVALID if the problems hold fewer than d loads.
+ * Synchronises as hom_batch_solve_pair; returns its status. */
+hom_status hom_batch_solve_bounds(hom_batch* b, const double* const* x0_primal, const double* const* x0_dual,
+                                  double tol, int32_t maxit, double* const* x_primal, double* const* x_dual,
+                                  hom_info* info_primal, hom_info* info_dual, hom_result* out);
+
 /* As hom_profile_passes, for the launch configuration of the batch (every
  * launch covers all n problems). */
 hom_status hom_batch_profile_passes(hom_batch* b, int32_t dual, int32_t nload, int32_t reps, double* ms_out);
@@ -442,6 +458,16 @@ hom_status hom_group_create(hom_batch* const* batches, int32_t n, hom_group** ou
  * (as hom_solve_primal). */
 hom_status hom_group_solve_pair(hom_group* g, double tol, int32_t maxit, double* const* x_primal,
                                 double* const* x_dual, hom_info* info_primal, hom_info* info_dual);
+/* hom_group_solve_pair followed by the guaranteed bounds of every problem
+ * (Def. upper_lower_bounds, as hom_batch_bounds on each batch's returned
+ * fields), in one call.  In launch mode 1 the bound passes of a solve are
+ * enqueued on its stream as soon as it has stopped (outside the gap rule),
+ * beside the solves still iterating; otherwise after all have stopped.  Same
+ * fields, infos and results as the two calls.  out: host array of the total
+ * problem count, batch-major. */
+hom_status hom_group_solve_bounds(hom_group* g, double tol, int32_t maxit, double* const* x_primal,
+                                  double* const* x_dual, hom_info* info_primal, hom_info* info_dual,
+                                  hom_result* out);
 /* Launch mode of later hom_group_solve_pair calls: 0 (default) one captured
  * graph advances every solve by a chunk per launch, as above; 1 each solve
  * replays its own captured chunk graph on its own stream and one host loop

@@ -50,6 +50,8 @@ EXPORTS = {
     "hom_group_create": (C.c_int32, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(C.c_void_p)]),
     "hom_group_solve_pair": (C.c_int32, [C.c_void_p, C.c_double, C.c_int32, C.POINTER(C.c_void_p),
                                          C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p]),
+    "hom_group_solve_bounds": (C.c_int32, [C.c_void_p, C.c_double, C.c_int32, C.POINTER(C.c_void_p),
+                                           C.POINTER(C.c_void_p), C.c_void_p, C.c_void_p, C.POINTER(Result)]),
     "hom_group_destroy": (None, [C.c_void_p]),
     "hom_group_set_launch": (C.c_int32, [C.c_void_p, C.c_int32]),
     "hom_batch_field_to_grid": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_void_p), C.c_void_p,
@@ -135,6 +137,9 @@ EXPORTS = {
     "hom_batch_solve_pair": (C.c_int32, [C.c_void_p, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_void_p),
                                          C.POINTER(C.c_void_p), C.c_double, C.c_int32, C.POINTER(C.c_void_p),
                                          C.POINTER(C.c_void_p), C.POINTER(Info), C.POINTER(Info)]),
+    "hom_batch_solve_bounds": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), C.c_double,
+                                           C.c_int32, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                           C.POINTER(Info), C.POINTER(Info), C.POINTER(Result)]),
     "hom_batch_update_coefficients": (C.c_int32, [C.c_void_p, C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]),
     "hom_problem_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Tuning)]),
     "hom_batch_tuning": (C.c_int32, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(Tuning)]),

@@ -704,13 +704,24 @@ class Batch:
         """Primal and dual solves of the unit loads (side by side, optionally from starting
         fields) and the bounds of every problem.  The fields live in buffers owned by the
         batch and are overwritten by the next call."""
-        d = self.d
-        xp, ip, xd, idl = self.solve_pair(tol=tol, maxit=maxit, out_primal=self._fields(False, d),
-                                          out_dual=self._fields(True, d), allow_not_converged=allow_not_converged,
-                                          x0_primal=x0_primal, x0_dual=x0_dual)
-        out = self.bounds(xp, xd)
-        for i, b in enumerate(out):
-            b.update(info_primal=ip[i], info_dual=idl[i])
+        d, n = self.d, len(self.problems)
+        fp, fd = self._fields(False, d), self._fields(True, d)
+        ip, idl = (L.Info * (n * d))(), (L.Info * (n * d))()
+        res = (L.Result * n)()
+        self.stream.wait_stream(torch.cuda.current_stream())
+        x0p = _dptrs([t for ts in x0_primal for t in ts]) if x0_primal is not None else None
+        x0d = _dptrs([t for ts in x0_dual for t in ts]) if x0_dual is not None else None
+        st = L.load().hom_batch_solve_bounds(self.h, x0p, x0d, float(tol), int(maxit),
+                                             _dptrs([t for ts in fp for t in ts]), _dptrs([t for ts in fd for t in ts]),
+                                             ip, idl, res)
+        L.check(st, "hom_batch_solve_bounds", allow_not_converged)
+        conv = lambda infos, i: [dict(iters=infos[i * d + l].iters, status=infos[i * d + l].status,
+                                      rel_res_recur=infos[i * d + l].rel_res_recur,
+                                      rel_res_true=infos[i * d + l].rel_res_true,
+                                      energy=infos[i * d + l].energy) for l in range(d)]
+        out = [_result_dict(res[i], d) for i in range(n)]
+        for i, r in enumerate(out):
+            r.update(info_primal=conv(ip, i), info_dual=conv(idl, i))
         return out
 
 
@@ -739,8 +750,10 @@ class Group:
         solve replays its own chunk graph, one host loop polls them all (hom_group_set_launch)."""
         L.check(L.load().hom_group_set_launch(self.h, {"graph": 0, "streams": 1}[mode]), "hom_group_set_launch")
 
-    def solve_bounds(self, tol=1e-6, maxit=10000, allow_not_converged=False):
-        """Bounds of every problem of every batch (a list per batch), fields in the batches' buffers."""
+    def solve_bounds(self, tol=1e-6, maxit=10000, allow_not_converged=False, fused=True):
+        """Bounds of every problem of every batch (a list per batch), fields in the batches' buffers.
+        fused: one call (hom_group_solve_bounds: each side's bound passes start when that side
+        stops); else hom_group_solve_pair followed by hom_batch_bounds per batch (same results)."""
         fp, fd, counts = [], [], []
         for b in self.batches:
             xp, xd = b._fields(False, b.d), b._fields(True, b.d)
@@ -751,10 +764,16 @@ class Group:
         ip, idl = (L.Info * n)(), (L.Info * n)()
         for b in self.batches:
             b.stream.wait_stream(torch.cuda.current_stream())
-        st = L.load().hom_group_solve_pair(self.h, float(tol), int(maxit), _dptrs(fp), _dptrs(fd),
-                                           C.cast(ip, C.c_void_p), C.cast(idl, C.c_void_p))
-        L.check(st, "hom_group_solve_pair", allow_not_converged)
-        out, off = [], 0
+        if fused:
+            res_all = (L.Result * sum(len(b.problems) for b in self.batches))()
+            st = L.load().hom_group_solve_bounds(self.h, float(tol), int(maxit), _dptrs(fp), _dptrs(fd),
+                                                 C.cast(ip, C.c_void_p), C.cast(idl, C.c_void_p), res_all)
+            L.check(st, "hom_group_solve_bounds", allow_not_converged)
+        else:
+            st = L.load().hom_group_solve_pair(self.h, float(tol), int(maxit), _dptrs(fp), _dptrs(fd),
+                                               C.cast(ip, C.c_void_p), C.cast(idl, C.c_void_p))
+            L.check(st, "hom_group_solve_pair", allow_not_converged)
+        out, off, roff = [], 0, 0
         for b, cnt in zip(self.batches, counts):
             d = b.d
             conv = lambda infos: [[dict(iters=infos[off + i * d + l].iters, status=infos[off + i * d + l].status,
@@ -762,11 +781,15 @@ class Group:
                                         rel_res_true=infos[off + i * d + l].rel_res_true,
                                         energy=infos[off + i * d + l].energy) for l in range(d)]
                                   for i in range(len(b.problems))]
-            res = b.bounds(b._fields(False, d), b._fields(True, d))
+            if fused:
+                res = [_result_dict(res_all[roff + i], d) for i in range(len(b.problems))]
+            else:
+                res = b.bounds(b._fields(False, d), b._fields(True, d))
             for r, a, c in zip(res, conv(ip), conv(idl)):
                 r.update(info_primal=a, info_dual=c)
             out.append(res)
             off += cnt
+            roff += len(b.problems)
         return out
 
 

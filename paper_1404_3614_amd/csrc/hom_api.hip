@@ -253,6 +253,8 @@ struct hom_problem {
   // bounds (FP64, L = d)
   void* bbufA;
   void* bbufB;
+  void* bbufA2;         // the dual side's bound buffers (batched bounds run both sides at once)
+  void* bbufB2;
   double* bpart_q[2];
   UnitDev* bunit[2];
   UnitDev host_unit[2];
@@ -437,6 +439,8 @@ size_t carve(const hom_desc* desc, int max_loads, const Sizes& z, hom_problem* p
     const int P = packs(std::max(d, L), d);
     void* a = ptr(take((size_t)z.N[0] * z.N[1] * z.M[2] * P * sizeof(Cx<double>)));
     void* b = d == 3 ? ptr(take((size_t)z.N[0] * z.M[1] * z.M[2] * P * sizeof(Cx<double>))) : nullptr;
+    void* a2 = ptr(take((size_t)z.N[0] * z.N[1] * z.M[2] * P * sizeof(Cx<double>)));
+    void* b2 = d == 3 ? ptr(take((size_t)z.N[0] * z.M[1] * z.M[2] * P * sizeof(Cx<double>))) : nullptr;
     double* q0 = (double*)ptr(take(npts * 9 * sizeof(double)));
     double* q1 = (double*)ptr(take(npts * 9 * sizeof(double)));
     UnitDev* u0 = (UnitDev*)ptr(take(sizeof(UnitDev)));
@@ -444,6 +448,8 @@ size_t carve(const hom_desc* desc, int max_loads, const Sizes& z, hom_problem* p
     if (pb) {
       pb->bbufA = a;
       pb->bbufB = b;
+      pb->bbufA2 = a2;
+      pb->bbufB2 = b2;
       pb->bpart_q[0] = q0;
       pb->bpart_q[1] = q1;
       pb->bunit[0] = u0;
@@ -816,8 +822,14 @@ hom_status start_run(SolveRun& R, int nload, double tol, int maxit, bool have_x0
 // run starts after chunk c - 1 of its partner has ended (the partner's last
 // chunk once it has stopped), so under the gap rule each reads the other's
 // state at the end of the previous chunk, never a chunk being written.
-hom_status loop_runs(SolveRun* const* runs, int nr, int maxit, const int* partner = nullptr) {
+// on_fin (optional; not for a run with a partner): called with ctx and the
+// run's index as soon as the host sees the run stop, to enqueue its closing
+// work on its stream while the other runs still iterate.
+typedef hom_status (*RunFinHook)(void* ctx, int r);
+hom_status loop_runs(SolveRun* const* runs, int nr, int maxit, const int* partner = nullptr,
+                     RunFinHook on_fin = nullptr, void* ctx = nullptr) {
   std::vector<hipEvent_t> ev((size_t)2 * nr, nullptr);
+  hom_status hs = HOM_OK;
   std::vector<int> it(nr, 0), done(nr, 0), fin(nr, 0), launched(nr, 0);
   hipError_t e = hipSuccess;
   for (size_t i = 0; i < ev.size() && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
@@ -849,13 +861,19 @@ hom_status loop_runs(SolveRun* const* runs, int nr, int maxit, const int* partne
       if (*runs[r]->pinned_active == 0 || done[r] > maxit + runs[r]->chunk) {
         fin[r] = 1;
         --left;
+        if (on_fin && !(partner && partner[r] >= 0)) {
+          hs = on_fin(ctx, r);
+          if (hs != HOM_OK) break;
+        }
       }
     }
+    if (hs != HOM_OK) break;
   }
   for (int r = 0; r < nr && e == hipSuccess; ++r) e = hipStreamSynchronize(runs[r]->st);
   for (auto x : ev)
     if (x) (void)hipEventDestroy(x);
-  return e == hipSuccess ? HOM_OK : HOM_E_DEVICE;
+  if (e != hipSuccess) return HOM_E_DEVICE;
+  return hs;
 }
 
 // Per-kernel event times of the chunk just completed, into the run's sums.
@@ -899,19 +917,35 @@ hom_status loop_direct(SolveRun* const* runs, int nr, int maxit) {
 }
 
 // Stage 3: true residual b - C x of the returned iterates (in the precision
-// mode of the solve) and the per-load summaries.
-hom_status finish_run(SolveRun& R, int nload, int maxit, hom_info* info) {
+// mode of the solve) and the per-load summaries.  finish_enqueue puts the
+// residual passes (and, with a summary workspace, its collection and copy to
+// the host) on the run's stream; finish_run waits for them and reads.  Runs on
+// different streams enqueue first and read afterwards, so their residual
+// passes overlap.
+static hom_status finish_enqueue(SolveRun& R, int nload) {
   hipStream_t st = R.st;
   const Geo& g = R.g;
   HIPCHK(enqueue_passes(R.fp32, g, R.units, FIRST_FIELD, LAST_RESID, 0, nullptr, st, R.n));
+  if (R.collect_dev) {
+    HIPCHK(launch_collect_solve(R.units, R.n, nload, g.nbL, R.collect_dev, st));
+    HIPCHK(hipMemcpyAsync(R.collect_host, R.collect_dev, (size_t)R.n * nload * sizeof(SolveOut),
+                          hipMemcpyDeviceToHost, st));
+  }
+  return HOM_OK;
+}
+
+hom_status finish_run(SolveRun& R, int nload, int maxit, hom_info* info, bool enqueued = false) {
+  if (!enqueued) {
+    hom_status s = finish_enqueue(R, nload);
+    if (s != HOM_OK) return s;
+  }
+  hipStream_t st = R.st;
+  const Geo& g = R.g;
   // partial sums of the residual pass ([load][nbL] per unit) and the CG scalars
   const size_t nbl = (size_t)g.nbL;
   std::vector<double> rres((size_t)R.n * nload);
   std::vector<CgScal> sc((size_t)R.n * nload);
   if (R.collect_dev) {
-    HIPCHK(launch_collect_solve(R.units, R.n, nload, g.nbL, R.collect_dev, st));
-    HIPCHK(hipMemcpyAsync(R.collect_host, R.collect_dev, (size_t)R.n * nload * sizeof(SolveOut),
-                          hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     for (size_t ul = 0; ul < (size_t)R.n * nload; ++ul) {
       rres[ul] = R.collect_host[ul].rres;
@@ -2264,9 +2298,50 @@ hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const doub
   return solve_units(R, nload, tol, maxit, have_x0, info);
 }
 
-hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, const double* const* x0_primal,
-                                const double* const* x0_dual, double tol, int32_t maxit, double* const* x_primal,
-                                double* const* x_dual, hom_info* info_primal, hom_info* info_dual) {
+// The batch's second library stream (the dual side's) and the event that
+// orders it against the first, created on first use.
+static bool side_stream(hom_batch* b) {
+  if (!b->stream2 && hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess) {
+    b->stream2 = nullptr;
+    return false;
+  }
+  if (!b->order_ev && hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming) != hipSuccess) {
+    b->order_ev = nullptr;
+    return false;
+  }
+  return true;
+}
+
+static hom_status upload_batch_bounds(hom_batch* b, int k, const double* const* f, hipStream_t st);
+static hom_status launch_batch_bounds(hom_batch* b, int k, hipStream_t st);
+static hom_status read_batch_bounds(hom_batch* b, const bool have[2], hom_result* out);
+
+// Closing work of one side of a pair solve: the residual passes and, when
+// bounds are asked for, the side's FP64 bound passes on its fields (their
+// unit tables are uploaded before the iterations start).
+struct PairClose {
+  hom_batch* b;
+  SolveRun* R;
+  int nload;
+  bool bounds;
+  bool queued[2];
+};
+
+static hom_status pair_close(void* ctx, int k) {
+  PairClose& c = *static_cast<PairClose*>(ctx);
+  if (c.queued[k]) return HOM_OK;
+  hom_status s = finish_enqueue(c.R[k], c.nload);
+  if (s == HOM_OK && c.bounds) s = launch_batch_bounds(c.b, k, c.R[k].st);
+  if (s == HOM_OK) c.queued[k] = true;
+  return s;
+}
+
+// Primal and dual solves side by side; with bounds (unit loads only) each
+// side's bound passes start as soon as that side has stopped, beside the
+// other side's remaining iterations.
+static hom_status solve_pair(hom_batch* b, int32_t nload, const double* E, const double* const* x0_primal,
+                             const double* const* x0_dual, double tol, int32_t maxit, double* const* x_primal,
+                             double* const* x_dual, hom_info* info_primal, hom_info* info_dual, hom_result* bounds) {
   if (!b || !info_primal || !info_dual || !x_primal || !x_dual) return HOM_E_INVALID;
   if (batch_has_gani(b)) return HOM_E_INVALID;
   const int n = b->n;
@@ -2278,12 +2353,7 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, co
   hom_problem* p0 = b->pbs[0];
   const bool gap_rule = b->stop.rule == 3;
   const bool fp32 = p0->desc.precision == HOM_MIXED;
-  if (!b->stream2) {
-    if (hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess) {
-      b->stream2 = nullptr;
-      return HOM_E_DEVICE;
-    }
-  }
+  if (!side_stream(b)) return HOM_E_DEVICE;
   hipStream_t st[2] = {b->stream, b->stream2};
   for (int k = 0; k < 2; ++k)
     if (!b->tuned[k][nload]) {
@@ -2360,29 +2430,54 @@ hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, co
     }
   }
   // the second stream starts after everything the caller's stream holds (coefficient setup, unit tables)
-  if (!b->order_ev && hipEventCreateWithFlags(&b->order_ev, hipEventDisableTiming) != hipSuccess) {
-    b->order_ev = nullptr;
-    return HOM_E_DEVICE;
-  }
   HIPCHK(hipEventRecord(b->order_ev, b->stream));
   HIPCHK(hipStreamWaitEvent(b->stream2, b->order_ev, 0));
   hom_status s = HOM_OK;
+  for (int k = 0; k < 2 && s == HOM_OK && bounds; ++k)
+    s = upload_batch_bounds(b, k, k == 0 ? x_primal : x_dual, st[k]);
   for (int k = 0; k < 2 && s == HOM_OK; ++k) s = start_run(R[k], nload, tol, maxit, have_x0[k]);
   if (s != HOM_OK) return s;
   SolveRun* runs[2] = {&R[0], &R[1]};
   const int partners[2] = {1, 0};
+  PairClose close{b, R, nload, bounds != nullptr, {false, false}};
   if (R[0].use_graph && R[1].use_graph)
-    s = loop_runs(runs, 2, maxit, gap_rule ? partners : nullptr);
+    s = loop_runs(runs, 2, maxit, gap_rule ? partners : nullptr, pair_close, &close);
   else
     s = loop_direct(runs, 2, maxit);
   if (s != HOM_OK) return s;
-  hom_status s0 = finish_run(R[0], nload, maxit, info_primal);
-  hom_status s1 = finish_run(R[1], nload, maxit, info_dual);
+  for (int k = 0; k < 2; ++k) {
+    s = pair_close(&close, k);
+    if (s != HOM_OK) return s;
+  }
+  hom_status s0 = finish_run(R[0], nload, maxit, info_primal, true);
+  hom_status s1 = finish_run(R[1], nload, maxit, info_dual, true);
   // later work on the caller's stream comes after the second stream's
   HIPCHK(hipStreamSynchronize(b->stream2));
+  if (bounds) {
+    const bool have[2] = {true, true};
+    s = read_batch_bounds(b, have, bounds);
+    if (s != HOM_OK) return s;
+  }
   if (s0 < 0) return s0;
   if (s1 < 0) return s1;
   return s0 != HOM_OK ? s0 : s1;
+}
+
+hom_status hom_batch_solve_pair(hom_batch* b, int32_t nload, const double* E, const double* const* x0_primal,
+                                const double* const* x0_dual, double tol, int32_t maxit, double* const* x_primal,
+                                double* const* x_dual, hom_info* info_primal, hom_info* info_dual) {
+  return solve_pair(b, nload, E, x0_primal, x0_dual, tol, maxit, x_primal, x_dual, info_primal, info_dual, nullptr);
+}
+
+hom_status hom_batch_solve_bounds(hom_batch* b, const double* const* x0_primal, const double* const* x0_dual,
+                                  double tol, int32_t maxit, double* const* x_primal, double* const* x_dual,
+                                  hom_info* info_primal, hom_info* info_dual, hom_result* out) {
+  if (!b || !out) return HOM_E_INVALID;
+  const int d = b->pbs[0]->desc.d;
+  if (b->pbs[0]->max_loads < d) return HOM_E_INVALID;
+  double E[9] = {};
+  for (int l = 0; l < d; ++l) E[l * d + l] = 1.0;
+  return solve_pair(b, d, E, x0_primal, x0_dual, tol, maxit, x_primal, x_dual, info_primal, info_dual, out);
 }
 
 // ---- grid transfers and network inputs of every problem of a batch (one launch per pass)
@@ -2582,8 +2677,28 @@ hom_status hom_group_create(hom_batch* const* batches, int32_t n, hom_group** ou
   return HOM_OK;
 }
 
-hom_status hom_group_solve_pair(hom_group* grp, double tol, int32_t maxit, double* const* x_primal,
-                                double* const* x_dual, hom_info* info_primal, hom_info* info_dual) {
+// Closing work of the runs of a group (run 2 bi + k: side k of batch bi), as
+// for a pair solve.
+struct GroupClose {
+  hom_group* grp;
+  std::vector<SolveRun>* runs;
+  bool bounds;
+  std::vector<char> queued;
+};
+
+static hom_status group_close(void* ctx, int r) {
+  GroupClose& c = *static_cast<GroupClose*>(ctx);
+  if (c.queued[r]) return HOM_OK;
+  hom_batch* b = c.grp->bs[r / 2];
+  SolveRun& R = (*c.runs)[r];
+  hom_status s = finish_enqueue(R, b->pbs[0]->desc.d);
+  if (s == HOM_OK && c.bounds) s = launch_batch_bounds(b, r & 1, R.st);
+  if (s == HOM_OK) c.queued[r] = 1;
+  return s;
+}
+
+static hom_status group_solve(hom_group* grp, double tol, int32_t maxit, double* const* x_primal,
+                              double* const* x_dual, hom_info* info_primal, hom_info* info_dual, hom_result* bounds) {
   if (!grp || !x_primal || !x_dual || !info_primal || !info_dual) return HOM_E_INVALID;
   const int nb = (int)grp->bs.size();
   // validation of every batch before anything is launched
@@ -2607,10 +2722,7 @@ hom_status hom_group_solve_pair(hom_group* grp, double tol, int32_t maxit, doubl
   for (int bi = 0; bi < nb; ++bi) {
     hom_batch* b = grp->bs[bi];
     const int d = b->pbs[0]->desc.d;
-    if (!b->stream2 && hipStreamCreateWithFlags(&b->stream2, hipStreamNonBlocking) != hipSuccess) {
-      b->stream2 = nullptr;
-      return HOM_E_DEVICE;
-    }
+    if (!side_stream(b)) return HOM_E_DEVICE;
     for (int k = 0; k < 2; ++k)
       if (!b->tuned[k][d]) {
         hom_status s = solve_tuning(b->pbs.data(), b->n, k, d, b->units[k], b->stream, &b->tune[k][d]);
@@ -2632,12 +2744,23 @@ hom_status hom_group_solve_pair(hom_group* grp, double tol, int32_t maxit, doubl
       for (hipStream_t st : {b->stream, b->stream2})
         if (bj != bi || st != b->stream) HIPCHK(hipStreamWaitEvent(st, grp->evs[1 + 2 * nb + bj], 0));
   }
+  // bound-pass unit tables of both sides of every batch, on the sides' streams
+  off = 0;
+  for (int bi = 0; bi < nb && bounds; ++bi) {
+    hom_batch* b = grp->bs[bi];
+    for (int k = 0; k < 2; ++k) {
+      hom_status s = upload_batch_bounds(b, k, (k == 0 ? x_primal : x_dual) + off, runs[2 * bi + k].st);
+      if (s != HOM_OK) return s;
+    }
+    off += (size_t)b->n * b->pbs[0]->desc.d;
+  }
   for (auto& R : runs) {
     R.capture = grp->launch == 1;      // launch mode 1 replays each solve's own chunk graph
     hom_status s = start_run(R, R.g.L, tol, maxit, false);
     if (s != HOM_OK) return s;
   }
   hom_status s = HOM_OK;
+  GroupClose close{grp, &runs, bounds != nullptr, std::vector<char>(runs.size(), 0)};
   const bool graphs = !timing && std::all_of(runs.begin(), runs.end(), [](const SolveRun& R) { return R.use_graph; });
   if (graphs && grp->launch == 1) {
     // every solve's chunk graph on its own stream, one host loop over all of them; the
@@ -2648,7 +2771,7 @@ hom_status hom_group_solve_pair(hom_group* grp, double tol, int32_t maxit, doubl
       rp.push_back(&runs[r]);
       if (grp->bs[r / 2]->stop.rule == 3) partner[r] = (int)(r ^ 1);
     }
-    s = loop_runs(rp.data(), (int)rp.size(), maxit, partner.data());
+    s = loop_runs(rp.data(), (int)rp.size(), maxit, partner.data(), group_close, &close);
     if (s != HOM_OK) return s;
   } else if (graphs) {
     // the captured graph holds the geometry (tile shapes) and the stopping rule of every run
@@ -2714,21 +2837,46 @@ hom_status hom_group_solve_pair(hom_group* grp, double tol, int32_t maxit, doubl
     s = loop_direct(rp.data(), (int)rp.size(), maxit);
     if (s != HOM_OK) return s;
   }
-  // per-run residual checks and summaries, worst status over the group
+  // per-run residual checks and summaries, worst status over the group (every
+  // run's residual passes are enqueued before the first is read)
+  for (size_t r = 0; r < runs.size(); ++r) {
+    s = group_close(&close, (int)r);
+    if (s != HOM_OK) return s;
+  }
   hom_status worst = HOM_OK;
   off = 0;
   for (int bi = 0; bi < nb; ++bi) {
     const int d = grp->bs[bi]->pbs[0]->desc.d;
     for (int k = 0; k < 2; ++k) {
       hom_info* info = (k == 0 ? info_primal : info_dual) + off;
-      hom_status r = finish_run(runs[2 * bi + k], d, maxit, info);
+      hom_status r = finish_run(runs[2 * bi + k], d, maxit, info, true);
       if (r < 0 && (worst >= 0 || r < worst)) worst = r;
       else if (r == HOM_NOT_CONVERGED && worst == HOM_OK) worst = r;
     }
     off += (size_t)grp->bs[bi]->n * d;
   }
   for (hom_batch* b : grp->bs) HIPCHK(hipStreamSynchronize(b->stream2));
+  if (bounds) {
+    const bool have[2] = {true, true};
+    for (hom_batch* b : grp->bs) {
+      s = read_batch_bounds(b, have, bounds);
+      if (s != HOM_OK) return s;
+      bounds += b->n;
+    }
+  }
   return worst;
+}
+
+hom_status hom_group_solve_pair(hom_group* grp, double tol, int32_t maxit, double* const* x_primal,
+                                double* const* x_dual, hom_info* info_primal, hom_info* info_dual) {
+  return group_solve(grp, tol, maxit, x_primal, x_dual, info_primal, info_dual, nullptr);
+}
+
+hom_status hom_group_solve_bounds(hom_group* grp, double tol, int32_t maxit, double* const* x_primal,
+                                  double* const* x_dual, hom_info* info_primal, hom_info* info_dual,
+                                  hom_result* out) {
+  if (!out) return HOM_E_INVALID;
+  return group_solve(grp, tol, maxit, x_primal, x_dual, info_primal, info_dual, out);
 }
 
 hom_status hom_group_set_launch(hom_group* grp, int32_t mode) {
@@ -2783,49 +2931,56 @@ hom_status hom_batch_update_coefficients(hom_batch* b, const void* const* Ahat, 
   return HOM_OK;
 }
 
-hom_status hom_batch_bounds(hom_batch* b, const double* const* primal, const double* const* dual, hom_result* out) {
-  if (!b || !out) return HOM_E_INVALID;
+// FP64 bound passes of one side (k = 0 primal, 1 dual) of every problem of a
+// batch, enqueued on st: the side's own bound buffers (so the two sides may
+// run on different streams at once) and its quadrature sums in the batch
+// workspace.  upload_batch_bounds copies the side's unit table (f: n * d
+// device pointers, problem-major, unit loads); launch_batch_bounds enqueues
+// the passes that read it.
+static hom_status upload_batch_bounds(hom_batch* b, int k, const double* const* f, hipStream_t st) {
+  const int n = b->n;
+  const int d = b->pbs[0]->desc.d;
+  for (int i = 0; i < n; ++i) {
+    hom_problem* pb = b->pbs[i];
+    UnitDev* hu = &b->host_bunits[k][i];
+    std::memset(hu, 0, sizeof(*hu));
+    hu->coef = pb->coef64[k];
+    hu->ahat = pb->ahat_half[k];
+    for (int l = 0; l < d; ++l) {
+      hu->x[l] = reinterpret_cast<Cx<double>*>(const_cast<double*>(f[(size_t)i * d + l]));
+      hu->E[l][l] = 1.0;
+    }
+    hu->bufA = k == 0 ? pb->bbufA : pb->bbufA2;
+    hu->bufB = k == 0 ? pb->bbufB : pb->bbufB2;
+    hu->part_q = pb->bpart_q[k];
+  }
+  HIPCHK(hipMemcpyAsync(b->bunits[k], b->host_bunits[k].data(), (size_t)n * sizeof(UnitDev), hipMemcpyHostToDevice,
+                        st));
+  return HOM_OK;
+}
+
+static hom_status launch_batch_bounds(hom_batch* b, int k, hipStream_t st) {
   const int n = b->n;
   hom_problem* p0 = b->pbs[0];
   const int d = p0->desc.d;
-  for (int k = 0; k < 2; ++k) {
-    const double* const* f = k == 0 ? primal : dual;
-    if (f)
-      for (int i = 0; i < n * d; ++i)
-        if (!f[i]) return HOM_E_INVALID;
-  }
-  hipStream_t st = b->stream;
-  const int P = packs(d, d);
-  bool have[2] = {primal != nullptr, dual != nullptr};
-  Geo g[2];
-  for (int k = 0; k < 2; ++k) {
-    if (!have[k]) continue;
-    const double* const* f = k == 0 ? primal : dual;
-    g[k] = make_geo(p0, k, d, false, P);
-    for (int i = 0; i < n; ++i) {
-      hom_problem* pb = b->pbs[i];
-      UnitDev* hu = &b->host_bunits[k][i];
-      std::memset(hu, 0, sizeof(*hu));
-      hu->coef = pb->coef64[k];
-      hu->ahat = pb->ahat_half[k];
-      for (int l = 0; l < d; ++l) {
-        hu->x[l] = reinterpret_cast<Cx<double>*>(const_cast<double*>(f[(size_t)i * d + l]));
-        hu->E[l][l] = 1.0;
-      }
-      hu->bufA = pb->bbufA;
-      hu->bufB = pb->bbufB;
-      hu->part_q = pb->bpart_q[k];
-    }
-    HIPCHK(hipMemcpyAsync(b->bunits[k], b->host_bunits[k].data(), (size_t)n * sizeof(UnitDev), hipMemcpyHostToDevice,
-                          st));
-    HIPCHK(launch_first<double>(g[k], b->bunits[k], n, FIRST_BOUNDS, 0, nullptr, st));
-    if (d == 3) HIPCHK(launch_mid<double>(g[k], b->bunits[k], n, 1, st));
-    HIPCHK(launch_apply<double>(g[k], b->bunits[k], n, APPLY_QUAD, st));
-    HIPCHK(launch_collect_bounds(b->bunits[k], n, g[k].nbA, b->bcollect_dev + (size_t)k * n * 9, st));
-  }
+  const Geo g = make_geo(p0, k, d, false, packs(d, d));
+  HIPCHK(launch_first<double>(g, b->bunits[k], n, FIRST_BOUNDS, 0, nullptr, st));
+  if (d == 3) HIPCHK(launch_mid<double>(g, b->bunits[k], n, 1, st));
+  HIPCHK(launch_apply<double>(g, b->bunits[k], n, APPLY_QUAD, st));
+  HIPCHK(launch_collect_bounds(b->bunits[k], n, g.nbA, b->bcollect_dev + (size_t)k * n * 9, st));
+  return HOM_OK;
+}
+
+// Copies both sides' quadrature sums to the host on the batch stream (after
+// the work on it), waits, and fills the results (sides not in have: NaN).
+static hom_status read_batch_bounds(hom_batch* b, const bool have[2], hom_result* out) {
+  const int n = b->n;
+  hom_problem* p0 = b->pbs[0];
+  const int d = p0->desc.d;
   HIPCHK(hipMemcpyAsync(b->bcollect_host, b->bcollect_dev, (size_t)2 * n * 9 * sizeof(double), hipMemcpyDeviceToHost,
-                        st));
-  HIPCHK(hipStreamSynchronize(st));
+                        b->stream));
+  HIPCHK(hipStreamSynchronize(b->stream));
+  const double invM = make_geo(p0, 0, d, false, packs(d, d)).invM;
   for (int i = 0; i < n; ++i) {
     double Ebar[2][9];
     for (int k = 0; k < 2; ++k) {
@@ -2833,11 +2988,44 @@ hom_status hom_batch_bounds(hom_batch* b, const double* const* primal, const dou
       if (!have[k]) continue;
       const double* sums = b->bcollect_host + ((size_t)k * n + i) * 9;
       for (int a = 0; a < d; ++a)
-        for (int c = 0; c < d; ++c) Ebar[k][a * d + c] = sums[a * kMaxLoads + c] * g[k].invM;
+        for (int c = 0; c < d; ++c) Ebar[k][a * d + c] = sums[a * kMaxLoads + c] * invM;
     }
     fill_result(d, Ebar, have, &out[i]);
   }
   return HOM_OK;
+}
+
+hom_status hom_batch_bounds(hom_batch* b, const double* const* primal, const double* const* dual, hom_result* out) {
+  if (!b || !out) return HOM_E_INVALID;
+  const int n = b->n;
+  const int d = b->pbs[0]->desc.d;
+  for (int k = 0; k < 2; ++k) {
+    const double* const* f = k == 0 ? primal : dual;
+    if (f)
+      for (int i = 0; i < n * d; ++i)
+        if (!f[i]) return HOM_E_INVALID;
+  }
+  const bool have[2] = {primal != nullptr, dual != nullptr};
+  // with both sides the dual's passes run on the second stream, beside the
+  // primal's, and the batch stream waits for them before the copy
+  hipStream_t sts[2] = {b->stream, b->stream};
+  if (have[0] && have[1]) {
+    if (!side_stream(b)) return HOM_E_DEVICE;
+    HIPCHK(hipEventRecord(b->order_ev, b->stream));
+    HIPCHK(hipStreamWaitEvent(b->stream2, b->order_ev, 0));
+    sts[1] = b->stream2;
+  }
+  for (int k = 0; k < 2; ++k) {
+    if (!have[k]) continue;
+    hom_status s = upload_batch_bounds(b, k, k == 0 ? primal : dual, sts[k]);
+    if (s == HOM_OK) s = launch_batch_bounds(b, k, sts[k]);
+    if (s != HOM_OK) return s;
+  }
+  if (sts[1] != b->stream) {
+    HIPCHK(hipEventRecord(b->order_ev, b->stream2));
+    HIPCHK(hipStreamWaitEvent(b->stream, b->order_ev, 0));
+  }
+  return read_batch_bounds(b, have, out);
 }
 
 hom_status hom_batch_profile_passes(hom_batch* b, int32_t dual, int32_t nload, int32_t reps, double* ms_out) {
