@@ -1424,10 +1424,15 @@ bool fast_apply(const Geo& g, const UnitDev* units, int n, int cg, hipStream_t s
 // per wave, lane 63 idle), so its exchange needs no block barrier: a line's
 // exchange runs in its own column of the plane, a column's in its wave's
 // exchange area.  Block barriers only separate the line and column steps
-// (two per pack).  Workgroup x runs on XCD x % 8: each XCD takes a run of
+// (two per pack).  Twelve waves give 84 groups, one per column of the plane
+// in a single round (the 41 lines take the first six waves); at 96.6 KB of
+// LDS one block fills a CU (twelve waves, three per SIMD).  With six waves
+// two blocks would fit the LDS, but a second one was never resident beside
+// the first: the twelve-wave block is the same occupancy with half the
+// column rounds.  Workgroup x runs on XCD x % 8: each XCD takes a run of
 // consecutive planes, whose rows share cache lines of the row-pass buffer in
 // that XCD's L2.
-constexpr int kPlaneThreads = 384;
+constexpr int kPlaneThreads = 768;
 
 template <int M>
 struct PlaneShape {
@@ -1440,7 +1445,7 @@ struct PlaneShape {
   // group g at 8-byte address EX (9 q + k) + g) fall on distinct banks but for pairs (EX = 7 gave
   // four-way conflicts)
   static constexpr int EX = GW + 2;
-  static constexpr size_t lds = (2 * (size_t)M + (size_t)M * N + (size_t)NW * EX * M) * sizeof(Cx<float>);
+  static constexpr size_t lds = ((size_t)M * N + (size_t)NW * EX * M) * sizeof(Cx<float>);
 };
 
 // Order of the LDS accesses of one wave (lanes exchange through LDS without a block barrier).
@@ -1458,9 +1463,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_fast(Geo g, const UnitD
   static_assert(A == T && B == T, "square four-step split");
   static_assert(N <= NG, "one thread group per line of the plane");
   extern __shared__ __align__(16) unsigned char smem[];
-  Cx<float>* tw0 = reinterpret_cast<Cx<float>*>(smem);  // [M] axis 0
-  Cx<float>* tw1 = tw0 + M;                             // [M] axis 1
-  Cx<float>* Y = tw1 + M;                               // [M1][N0] the plane after the axis-1 transform
+  Cx<float>* Y = reinterpret_cast<Cx<float>*>(smem);    // [M1][N0] the plane after the axis-1 transform
   const UnitDev& U = units[blockIdx.z];
   if (cg && !any_active(U, g.L)) return;
   const int m2 = (int)(blockIdx.x & 7) * PPX + (int)(blockIdx.x >> 3);
@@ -1471,13 +1474,13 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_fast(Geo g, const UnitD
   const bool gv = gi < GW;                              // lane 63 (and beyond 7 T) idle
   constexpr int EX = S::EX;
   Cx<float>* ex = Y + (size_t)M * N + (size_t)wave * EX * M;  // this wave's exchange area [M][EX]
+  // the twiddles omega_M^(q k) of every four-step transform of this lane, k < T, in registers: both
+  // axes have the same length, hence the same table (the separate passes read the same values)
+  Cx<float> tw[T];
   {
     const Cx<float>* t0 = reinterpret_cast<const Cx<float>*>(g.tw[0]);
-    const Cx<float>* t1 = reinterpret_cast<const Cx<float>*>(g.tw[1]);
-    for (int i = tid; i < M; i += kPlaneThreads) {
-      tw0[i] = t0[i];
-      tw1[i] = t1[i];
-    }
+#pragma unroll
+    for (int k = 0; k < T; ++k) tw[k] = gload(t0, (size_t)(gv ? q * k : 0));
   }
   Cx<float>* buf = reinterpret_cast<Cx<float>*>(U.bufA);
   const size_t W = (size_t)M * P;                  // elements per (i0, i1) row of the buffer
@@ -1512,7 +1515,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_fast(Geo g, const UnitD
       rf::Dft<float, A, 1>::template run_z<dead_mask<M>()>(v);
 #pragma unroll
       for (int k1 = 0; k1 < A; ++k1) {
-        Cx<float> w = tw1[q * k1];
+        Cx<float> w = tw[k1];
         w.y = -w.y;
         Y[(q * A + k1) * N + grp] = rf::mul(v[k1], w);
       }
@@ -1544,7 +1547,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_fast(Geo g, const UnitD
         rf::Dft<float, A, 1>::template run_z<dead_mask<M>()>(v);
 #pragma unroll
         for (int k1 = 0; k1 < A; ++k1) {
-          Cx<float> w = tw0[q * k1];
+          Cx<float> w = tw[k1];
           w.y = -w.y;
           ex[(q * A + k1) * EX + gi] = rf::mul(v[k1], w);
         }
@@ -1562,7 +1565,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_fast(Geo g, const UnitD
       wave_sync();
       if (ok) {
 #pragma unroll
-        for (int mm = 0; mm < B; ++mm) ex[(q * B + mm) * EX + gi] = rf::mul(v[mm], tw0[q * mm]);
+        for (int mm = 0; mm < B; ++mm) ex[(q * B + mm) * EX + gi] = rf::mul(v[mm], tw[mm]);
       }
       wave_sync();
       if (ok) {
@@ -1588,7 +1591,7 @@ __global__ __launch_bounds__(kPlaneThreads) void k_plane_fast(Geo g, const UnitD
     if (lt) {
       rf::Dft<float, B, -1>::run(v);
 #pragma unroll
-      for (int mm = 0; mm < B; ++mm) Y[(q * B + mm) * N + grp] = rf::mul(v[mm], tw1[q * mm]);
+      for (int mm = 0; mm < B; ++mm) Y[(q * B + mm) * N + grp] = rf::mul(v[mm], tw[mm]);
     }
     wave_sync();
     if (lt) {
