@@ -796,9 +796,11 @@ hom_status start_run(SolveRun& R, int nload, double tol, int maxit, bool have_x0
   // events recorded inside a captured graph cannot be timed, so timing runs launch directly
   R.use_graph = st != nullptr && env_int("HOM_NO_GRAPH", 0) == 0 && R.events == nullptr;
   const int npass = pass_types(g, R.types);
-  if (R.events && R.events->empty()) {
-    R.events->resize((size_t)R.chunk * 2 * npass);
-    for (auto& ev : *R.events) HIPCHK(hipEventCreate(&ev));
+  // event pairs for every pass of a chunk (a batch's chunk is longer in a group's single graph)
+  if (R.events && R.events->size() < (size_t)R.chunk * 2 * npass) {
+    const size_t have = R.events->size();
+    R.events->resize((size_t)R.chunk * 2 * npass, nullptr);
+    for (size_t i = have; i < R.events->size(); ++i) HIPCHK(hipEventCreate(&(*R.events)[i]));
   }
   hipGraphExec_t& gx = *R.graph;
   if (R.use_graph && R.capture && !gx) {
@@ -1239,7 +1241,10 @@ hom_status hom_setup(const hom_desc* desc, int32_t max_loads, const void* Ahat, 
   pb->ws_bytes = ws_bytes;
   pb->z = z;
   for (int a = 0; a < 3; ++a) pb->plan[a] = pl[a];
-  pb->graph_chunk = env_int("HOM_CHUNK", 8);
+  // iterations per captured chunk: a 3D iteration is long enough (about a millisecond on a batch) that
+  // the host can poll every second one, so a solve that stops is seen sooner and its closing work
+  // starts sooner; 2D iterations are far shorter
+  pb->graph_chunk = env_int("HOM_CHUNK", z.d == 3 ? 2 : 8);
   carve(desc, max_loads, z, pb);
   if (hipHostMalloc((void**)&pb->pinned_active, sizeof(int), hipHostMallocDefault) != hipSuccess) {
     delete pb;
@@ -2754,8 +2759,19 @@ static hom_status group_solve(hom_group* grp, double tol, int32_t maxit, double*
     }
     off += (size_t)b->n * b->pbs[0]->desc.d;
   }
+  // one graph launch advances every solve by its chunk and waits for the slowest, so in launch
+  // mode 0 every solve takes the longest chunk of the group (a 3D batch's short chunks would
+  // multiply the launches of the whole graph); not under the gap rule, whose stops depend on the
+  // chunk boundaries, so that every launch mode stops where the batch's own solves do
+  int chunk_max = 1;
+  bool any_gap = false;
+  for (auto& R : runs) {
+    chunk_max = std::max(chunk_max, R.chunk);
+    any_gap = any_gap || R.stop.rule == 3;
+  }
   for (auto& R : runs) {
     R.capture = grp->launch == 1;      // launch mode 1 replays each solve's own chunk graph
+    if (grp->launch == 0 && !any_gap) R.chunk = chunk_max;
     hom_status s = start_run(R, R.g.L, tol, maxit, false);
     if (s != HOM_OK) return s;
   }
@@ -2813,7 +2829,10 @@ static hom_status group_solve(hom_group* grp, double tol, int32_t maxit, double*
     hipError_t e = hipSuccess;
     for (int i = 0; i < 2 && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
     int it = 0, done = 0;
-    const int chunk = runs[0].chunk * grp->graph_chunks;
+    // the iteration guard counts the shortest chunk (runs of 2D and 3D batches differ)
+    int chunk = runs[0].chunk;
+    for (auto& R : runs) chunk = std::min(chunk, R.chunk);
+    chunk *= grp->graph_chunks;
     if (e == hipSuccess) e = hipGraphLaunch(grp->graph, root);
     if (e == hipSuccess) e = hipEventRecord(ev[0], root);
     while (e == hipSuccess) {
