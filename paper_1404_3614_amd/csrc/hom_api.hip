@@ -2242,6 +2242,17 @@ static bool batch_has_gani(const hom_batch* b) {
   return false;
 }
 
+// Iterations per chunk of a batch's solve.  Per-kernel timing launches every
+// pass directly and waits for each chunk, so it takes chunks of at least 8
+// iterations (the host waits, between which the GPU idles, would otherwise
+// lengthen the measured kernels); not under the gap rule, whose stops depend
+// on the chunk boundaries.
+static int batch_chunk(const hom_batch* b, const hom_problem* p0) {
+  int c = p0->graph_chunk;
+  if (b->timing && b->stop.rule != 3) c = std::max(c, 8);
+  return c;
+}
+
 hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const double* E, const double* const* x0,
                            double tol, int32_t maxit, double* const* x_out, hom_info* info) {
   if (!b || !info || (dual != 0 && dual != 1)) return HOM_E_INVALID;
@@ -2287,7 +2298,7 @@ hom_status hom_batch_solve(hom_batch* b, int32_t dual, int32_t nload, const doub
   R.active = b->active[k];
   R.pinned_active = b->pinned + k;
   R.graph = &b->graph[k][nload];
-  R.chunk = p0->graph_chunk;
+  R.chunk = batch_chunk(b, p0);
   R.stop = b->stop;
   if (b->timing) {
     R.events = &b->tevents[k][nload];
@@ -2419,7 +2430,7 @@ static hom_status solve_pair(hom_batch* b, int32_t nload, const double* E, const
     R[k].active = b->active[k];
     R[k].pinned_active = b->pinned + k;
     R[k].graph = &b->graph[k][nload];
-    R[k].chunk = p0->graph_chunk;
+    R[k].chunk = batch_chunk(b, p0);
     R[k].stop = b->stop;
     for (int i = 0; i < n; ++i) {
       R[k].part_d.push_back(b->pbs[i]->slot[k].part_d);
@@ -2612,7 +2623,7 @@ void group_run(hom_batch* b, int k, SolveRun& R) {
   R.pinned_active = b->pinned + k;
   R.graph = &b->graph[k][d];
   R.capture = false;
-  R.chunk = p0->graph_chunk;
+  R.chunk = batch_chunk(b, p0);
   R.stop = b->stop;
   for (int i = 0; i < n; ++i) {
     R.part_d.push_back(b->pbs[i]->slot[k].part_d);
